@@ -1,0 +1,222 @@
+"""A plan executed on oracle ciphertexts (test infrastructure only).
+
+The words produced here are the bit-exact target for the GPU library.
+
+Scale and level schedule (reading of Sec. 2.1's "each multiplication consumes
+a level" with 50-bit primes and Delta = 2^40; the paper leaves it to its
+library).  The scale is a double tracked through this exact sequence of IEEE
+operations, starting from s = 2^log_scale at the top level L-1:
+  Inter-CA layer at level l : P_k encoded at sP = q_l, weights at sW = q_{l-1};
+                              s = (s * sP) * sW; s = s / q_l; s = s / q_{l-1}; l -= 2
+  SpIntra-CA layer at level l, input not squared:
+                              weights at sW = (q_l * Delta) / s;
+                              s = s * sW; s = s / q_l; l -= 1
+  SpIntra-CA layer at level l, input squared by the previous activation:
+                              weights at sW = ((q_l * q_{l-1}) * Delta) / s;
+                              s = s * sW; s = s / q_l; s = s / q_{l-1}; l -= 2
+  then (SpIntra-CA)          masks at sM = q_l; s = s * sM; s = s / q_l; l -= 1
+  x^2 activation at level l : s = s * s (the rescale is deferred to the next
+                              combination, or never for the model output, so
+                              that no rounding happens below scale Delta)
+Weights become integers c = round_half_even(w * sW); plaintexts are encoded
+with round_half_even of the scaled inverse embedding.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Dict, List
+
+import numpy as np
+
+from . import ckks
+from . import encoding as enc
+from . import simulate as sim
+from .params import Params
+from .planner import Plan
+
+
+def schedule(prm: Params, plan: Plan) -> List[dict]:
+    s = float(2 ** prm.log_scale)
+    delta = float(2 ** prm.log_scale)
+    lv = prm.L - 1
+    pending = False
+    out = []
+    for lp in plan.layers:
+        st = dict(level_in=lv, scale_in=s)
+        if lp.kind == "inter":
+            if lv < 2:
+                raise ValueError("not enough levels")
+            st["sP"] = float(prm.q[lv])
+            st["sW"] = float(prm.q[lv - 1])
+            s = s * st["sP"]
+            s = s * st["sW"]
+            s = s / float(prm.q[lv])
+            s = s / float(prm.q[lv - 1])
+            lv -= 2
+        else:
+            st["n_rescale_comb"] = 2 if pending else 1
+            if lv < st["n_rescale_comb"] + 1:
+                raise ValueError("not enough levels")
+            if pending:
+                st["sW"] = ((float(prm.q[lv]) * float(prm.q[lv - 1])) * delta) / s
+                s = s * st["sW"]
+                s = s / float(prm.q[lv])
+                s = s / float(prm.q[lv - 1])
+                lv -= 2
+            else:
+                st["sW"] = (float(prm.q[lv]) * delta) / s
+                s = s * st["sW"]
+                s = s / float(prm.q[lv])
+                lv -= 1
+            st["level_agg"] = lv
+            st["scale_agg"] = s
+            st["sM"] = float(prm.q[lv])
+            s = s * st["sM"]
+            s = s / float(prm.q[lv])
+            lv -= 1
+        st["level_pre_act"] = lv
+        st["scale_pre_act"] = s
+        pending = False
+        if lp.activation:
+            s = s * s
+            pending = True
+        st["squared_out"] = pending
+        st["level_out"] = lv
+        st["scale_out"] = s
+        out.append(st)
+    return out
+
+
+def weight_ints(w: np.ndarray, sW: float) -> np.ndarray:
+    return np.rint(np.asarray(w, dtype=np.float64) * np.float64(sW)).astype(np.int64)
+
+
+def mask_vectors(plan: Plan, li: int) -> List[Dict[int, np.ndarray]]:
+    """Per packed ciphertext g: slot vector per shift as the aggregation
+    multiplies it (family 2 masks are pre-rotated by -g*G)."""
+    lp = plan.layers[li]
+    out = []
+    for g in range(-(-lp.f_out // lp.t)):
+        n_cols = min(lp.t, lp.f_out - g * lp.t)
+        mk = sim.masks(plan, lp, n_cols)
+        if lp.family == 2:
+            mk = {d: sim.rot(v, -(d // lp.G) * lp.G) for d, v in mk.items()}
+        out.append(mk)
+    return out
+
+
+def encode_operands(prm: Params, plan: Plan, weights, sched=None) -> List[dict]:
+    """Plaintext operands of every layer (the FP64 encoding step)."""
+    sched = sched or schedule(prm, plan)
+    ops = []
+    for li, (lp, w, st) in enumerate(zip(plan.layers, weights, sched)):
+        d = dict(W=weight_ints(w, st["sW"]))
+        if lp.kind == "inter":
+            lv = st["level_in"]
+            d["P"] = [enc.encode(prm, p, st["sP"], lv) for p in sim.inter_plaintexts(plan, lp)]
+        else:
+            lv = st["level_agg"]
+            d["masks"] = [{dd: enc.encode(prm, v, st["sM"], lv) for dd, v in mk.items()}
+                          for mk in mask_vectors(plan, li)]
+        ops.append(d)
+    return ops
+
+
+def client_encrypt(prm: Params, plan: Plan, x: np.ndarray, keys: ckks.Keys, seed: int) -> List[ckks.Ciphertext]:
+    """The client's input ciphertexts, ct id = k * F + f (copy k, column f)."""
+    lp = plan.layers[0]
+    copies = sim.client_layout(plan, x, lp)
+    cts = []
+    for k, vecs in enumerate(copies):
+        for f, v in enumerate(vecs):
+            pt = enc.encode(prm, v, prm.scale, prm.L - 1)
+            cts.append(ckks.encrypt(prm, seed, k * lp.f_in + f, keys.s, pt))
+    return cts
+
+
+def _zero(prm, level, scale):
+    return ckks.zero_ct(prm, level, scale)
+
+
+def run_layer(prm: Params, plan: Plan, li: int, keys: ckks.Keys, cts: List[ckks.Ciphertext],
+              ops: dict, st: dict) -> List[ckks.Ciphertext]:
+    lp = plan.layers[li]
+    if lp.kind == "inter":
+        lv = st["level_in"]
+        F = lp.f_in
+        Z = []
+        for f in range(F):
+            acc = _zero(prm, lv, st["scale_in"] * st["sP"])
+            Z.append(ckks.pt_mul_acc(prm, acc, [cts[k * F + f] for k in range(lp.K)], ops["P"]))
+        outs = []
+        for l in range(lp.f_out):
+            acc = _zero(prm, lv, st["scale_in"] * st["sP"] * st["sW"])
+            h = ckks.scalar_mul_acc(prm, acc, Z, [int(ops["W"][f, l]) for f in range(F)])
+            outs.append(ckks.rescale(prm, ckks.rescale(prm, h)))
+    else:
+        lv = st["level_in"]
+        cols = []
+        for l in range(lp.f_out):
+            acc = _zero(prm, lv, st["scale_in"] * st["sW"])
+            h = ckks.scalar_mul_acc(prm, acc, cts, [int(ops["W"][f, l]) for f in range(lp.f_in)])
+            for _ in range(st["n_rescale_comb"]):
+                h = ckks.rescale(prm, h)
+            cols.append(h)
+        outs = []
+        for g in range(-(-lp.f_out // lp.t)):
+            y = None
+            for l in range(g * lp.t, min(lp.f_out, (g + 1) * lp.t)):
+                c = l % lp.t
+                term = cols[l] if c == 0 else ckks.rotate(prm, keys, cols[l], -c * lp.B)
+                y = term if y is None else ckks.add(prm, y, term)
+            outs.append(aggregate(prm, plan, li, keys, y, ops["masks"][g], st))
+    if lp.activation:
+        outs = [ckks.ct_mul_relin(prm, keys, c, c) for c in outs]
+    return outs
+
+
+def aggregate(prm: Params, plan: Plan, li: int, keys, y: ckks.Ciphertext, masks: dict, st: dict):
+    lp = plan.layers[li]
+    acc = _zero(prm, y.level, y.scale * st["sM"])
+    if lp.family == 1:
+        steps = [d for d in lp.shifts if d != 0]
+        rots = dict(zip(steps, ckks.rotate_hoisted(prm, keys, y, steps)))
+        rots[0] = y
+        acc = ckks.pt_mul_acc(prm, acc, [rots[d] for d in lp.shifts], [masks[d] for d in lp.shifts])
+    else:
+        G = lp.G
+        babies = sorted({d % G for d in lp.shifts} - {0})
+        rb = dict(zip(babies, ckks.rotate_hoisted(prm, keys, y, babies)))
+        rb[0] = y
+        giants = {}
+        for d in lp.shifts:
+            giants.setdefault(d // G, []).append(d)
+        for g in sorted(giants):
+            ds = giants[g]
+            inner = ckks.pt_mul_acc(prm, _zero(prm, y.level, y.scale * st["sM"]),
+                                    [rb[d % G] for d in ds], [masks[d] for d in ds])
+            if g != 0:
+                inner = ckks.rotate(prm, keys, inner, g * G)
+            acc = ckks.add(prm, acc, inner)
+    return ckks.rescale(prm, acc)
+
+
+def run(prm: Params, plan: Plan, keys: ckks.Keys, cts: List[ckks.Ciphertext], ops: List[dict],
+        sched=None, upto: int = None) -> List[List[ckks.Ciphertext]]:
+    """Outputs of every layer (list per layer)."""
+    sched = sched or schedule(prm, plan)
+    outs = []
+    cur = cts
+    for li in range(len(plan.layers) if upto is None else upto):
+        cur = run_layer(prm, plan, li, keys, cur, ops[li], sched[li])
+        outs.append(cur)
+    return outs
+
+
+def decrypt_output(prm: Params, plan: Plan, keys: ckks.Keys, cts: List[ckks.Ciphertext], li: int = None) -> np.ndarray:
+    li = len(plan.layers) - 1 if li is None else li
+    lp = plan.layers[li]
+    slots = [np.real(enc.decode(prm, ckks.decrypt(prm, keys.s, c))) for c in cts]
+    if lp.kind == "inter":
+        return sim.read_output_layer(plan, lp, slots, ("cols",))
+    return sim.read_output_layer(plan, lp, slots, ("packed", lp.t, lp.B))

@@ -1,0 +1,413 @@
+"""Plan construction for the encrypted GCN (test infrastructure only).
+
+What a plan fixes, following the paper:
+  * packing (Sec. 3.2, App. B): t feature columns per ciphertext, column-major:
+    column c of a ciphertext sits in slots [c*B, (c+1)*B), B = M/t, node v at
+    slot c*B + pi(v);
+  * aggregation mode per layer (Sec. 3.3.2): the first layer is Inter-CA over
+    client-provided neighbour copies; later layers use SpIntra-CA;
+  * SpIntra-CA routing (Sec. 3.3): every nonzero A_vu is a demand moving u's
+    value by the shift delta = pi(u) - pi(v) onto v's slot; demands that share a
+    shift share one rotation and one mask (the diagonal form), or one baby and
+    one giant rotation (the baby-step/giant-step form);
+  * node order pi (Sec. 3.4, Alg. 1): sibling-BFS regions capped at TH nodes,
+    interleaved region by region, then a greedy conflict-least placement;
+  * AOO (Sec. 3.3.1): with one column per ciphertext (t = 1) a shift is taken
+    mod M in (-M/2, M/2], the shorter way round the ring.
+
+Readings of points the paper leaves open (each also listed in the design notes):
+  * the region loop of Alg. 1 (stage 1) runs while the region has fewer than
+    TH nodes and the sibling BFS is not exhausted; when
+    the sibling BFS runs dry before TH, it restarts inside the same region
+    from the highest-degree node not yet in any region.
+  * degree(v) = number of u != v with A_vu != 0 or A_uv != 0; ties -> smaller id.
+  * sibling of x: w != x with A_vx != 0 and A_vw != 0 for some v (diagonal
+    included), enqueued in ascending id.
+  * interleave: round-robin over regions; an exhausted region's turn takes a
+    blank slot while blanks remain, else it is skipped.
+  * greedy placement (Alg. 1, stage 3): nodes of a region in BFS order, the
+    first at the region's first slot; every later node goes to the free slot
+    of its region that adds the fewest shifts not yet in the plan's shift set
+    (ties -> lowest slot).  For the diagonal form every distinct shift is one
+    rotation, so "conflicts" are counted as new distinct shifts.
+"""
+from __future__ import annotations
+
+import math
+from collections import deque
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+
+# ----------------------------------------------------------------------------
+# the paper's analytic cost formulas (Sec. 3.2, Sec. 3.3.2, App. B)
+# ----------------------------------------------------------------------------
+def ceil_div(a: int, b: int) -> int:
+    return -(-a // b)
+
+
+def clog2(x: int) -> int:
+    return 0 if x <= 1 else int(math.ceil(math.log2(x)))
+
+
+def j_objective(t: int, F: int, n: int) -> int:
+    """Case M > N F': J(t; F, n) = 2 ceil(F n / t) + 20 ceil(log t)."""
+    return 2 * ceil_div(F * n, t) + 20 * clog2(t)
+
+
+def case2_pmults(t: int, F: int, n: int, n_nodes: int, F_out: int, M: int) -> int:
+    """Case M <= N F': #PMult = #Add = ceil(F n / t) * ceil(N F' / ceil(M / t))."""
+    return ceil_div(F * n, t) * ceil_div(n_nodes * F_out, ceil_div(M, t))
+
+
+def paper_packing_t(F: int, n: int, n_nodes: int, F_out: int, M: int) -> int:
+    """t from the paper's rule: t = 1 when M <= N F'; otherwise the argmin of J
+    over powers of two with t N F' <= M (ties -> smaller t)."""
+    if M <= n_nodes * F_out:
+        return 1
+    best, best_j = 1, j_objective(1, F, n)
+    t = 2
+    while t * n_nodes * F_out <= M:
+        j = j_objective(t, F, n)
+        if j < best_j:
+            best, best_j = t, j
+        t *= 2
+    return best
+
+
+def paper_agg_mode(F: int, n: int, t: int, n_nodes: int, c: float) -> str:
+    """argmin{ Inter-CA: 2 ceil(F n / t), SpIntra-CA: 10 c n log^2 N } (Sec. 3.3.2)."""
+    inter = 2 * ceil_div(F * n, t)
+    spintra = 10.0 * c * n * math.log2(n_nodes) ** 2
+    return "inter" if inter <= spintra else "spintra"
+
+
+def spintra_worst_case_rots(n: int, n_nodes: int) -> int:
+    """Worst case of Sec. 3.3.1: (n - 1) log^2 N rotations."""
+    return (n - 1) * clog2(n_nodes) ** 2
+
+
+# ----------------------------------------------------------------------------
+# graph helpers
+# ----------------------------------------------------------------------------
+def support(rows) -> List[set]:
+    """Undirected support of A_hat without the diagonal."""
+    n = len(rows)
+    s = [set() for _ in range(n)]
+    for v, row in enumerate(rows):
+        for u, _ in row:
+            if u != v:
+                s[v].add(u)
+                s[u].add(v)
+    return s
+
+
+def siblings(rows) -> List[List[int]]:
+    """sib[x] = sorted w != x sharing a row of A_hat (diagonal included) with x."""
+    n = len(rows)
+    sib = [set() for _ in range(n)]
+    for row in rows:
+        us = [u for u, _ in row]
+        for a in us:
+            sib[a].update(us)
+    return [sorted(x - {i}) for i, x in enumerate(sib)]
+
+
+def reduce_shift(delta: int, M: int, wrap: bool) -> int:
+    """AOO: with wrap, the representative of delta mod M in (-M/2, M/2]."""
+    if not wrap:
+        return delta
+    r = delta % M
+    return r - M if r > M // 2 else r
+
+
+# ----------------------------------------------------------------------------
+# node order optimisation (Alg. 1)
+# ----------------------------------------------------------------------------
+def noo_regions(rows, TH: int) -> List[List[int]]:
+    """Stage 1 of Alg. 1 (detection): sibling-BFS regions of at most TH nodes."""
+    n = len(rows)
+    deg = [len(x) for x in support(rows)]
+    sib = siblings(rows)
+    order = sorted(range(n), key=lambda v: (-deg[v], v))   # highest degree first
+    remaining = [True] * n
+    regions = []
+    ptr = 0
+    n_left = n
+    while n_left > 0:
+        region = []
+        visited = set()
+        while len(region) < TH and n_left > 0:
+            while not remaining[order[ptr]]:
+                ptr += 1
+            start = order[ptr]
+            queue = deque([start])
+            visited.add(start)
+            while queue and len(region) < TH:
+                x = queue.popleft()
+                region.append(x)
+                remaining[x] = False
+                n_left -= 1
+                for w in sib[x]:
+                    if remaining[w] and w not in visited:
+                        visited.add(w)
+                        queue.append(w)
+        regions.append(region)
+    return regions
+
+
+def interleave_slots(sizes: Sequence[int], B: int) -> List[List[int]]:
+    """Stage 2 of Alg. 1 (interleaved arrangement): slots of each region in the interleaved
+    arrangement ABCABC... over [0, B)."""
+    R = len(sizes)
+    left = list(sizes)
+    blanks = B - sum(sizes)
+    if blanks < 0:
+        raise ValueError("graph does not fit the block")
+    slots = [[] for _ in range(R)]
+    j = 0
+    while any(x > 0 for x in left):
+        for r in range(R):
+            if left[r] > 0:
+                slots[r].append(j)
+                left[r] -= 1
+                j += 1
+            elif blanks > 0:
+                blanks -= 1
+                j += 1
+    return slots
+
+
+def noo_place(rows, regions, slots, M: int, wrap: bool) -> np.ndarray:
+    """Stage 3 of Alg. 1 (conflict-least search): greedy placement minimising new shifts."""
+    n = len(rows)
+    out_nb = [[u for u, _ in row if u != v] for v, row in enumerate(rows)]   # v needs u
+    in_nb = [[] for _ in range(n)]                                           # v needs x: x's in
+    for v in range(n):
+        for u in out_nb[v]:
+            in_nb[u].append(v)
+    pi = np.full(n, -1, dtype=np.int64)
+    shiftset = set()
+
+    def add_shifts(x):
+        for u in out_nb[x]:
+            if pi[u] >= 0:
+                shiftset.add(reduce_shift(int(pi[u] - pi[x]), M, wrap))
+        for v in in_nb[x]:
+            if pi[v] >= 0:
+                shiftset.add(reduce_shift(int(pi[x] - pi[v]), M, wrap))
+
+    for region, sl in zip(regions, slots):
+        free = np.array(sl, dtype=np.int64)
+        taken = np.zeros(len(free), dtype=bool)
+        first = region[0]
+        pi[first] = free[0]
+        taken[0] = True
+        add_shifts(first)
+        for x in region[1:]:
+            cand = np.nonzero(~taken)[0]
+            pos = free[cand]
+            rows_d = []
+            for u in out_nb[x]:
+                if pi[u] >= 0:
+                    rows_d.append(pi[u] - pos)
+            for v in in_nb[x]:
+                if pi[v] >= 0:
+                    rows_d.append(pos - pi[v])
+            if rows_d:
+                D = np.stack(rows_d)
+                if wrap:
+                    D = D % M
+                    D = np.where(D > M // 2, D - M, D)
+                D = np.sort(D, axis=0)
+                known = np.isin(D, np.fromiter(shiftset, dtype=np.int64, count=len(shiftset)))
+                first_of_run = np.ones_like(known)
+                first_of_run[1:] = D[1:] != D[:-1]
+                cost = np.sum(~known & first_of_run, axis=0)
+                k = int(np.argmin(cost))          # lowest slot among minima
+            else:
+                k = 0
+            pi[x] = pos[k]
+            taken[cand[k]] = True
+            add_shifts(x)
+    return pi
+
+
+def noo(rows, B: int, M: int, TH: int) -> tuple:
+    regions = noo_regions(rows, TH)
+    slots = interleave_slots([len(r) for r in regions], B)
+    pi = noo_place(rows, regions, slots, M, wrap=(B == M))
+    return pi, regions
+
+
+# ----------------------------------------------------------------------------
+# plans
+# ----------------------------------------------------------------------------
+@dataclass
+class LayerPlan:
+    kind: str                 # "inter" | "spintra"
+    f_in: int
+    f_out: int
+    activation: bool
+    # inter
+    K: int = 0
+    copy_src: Optional[np.ndarray] = None     # (K, n_v) source node, -1 = none
+    copy_val: Optional[np.ndarray] = None     # (K, n_v) A_hat value
+    # spintra
+    t: int = 1                # columns per packed ciphertext
+    B: int = 0                # block = M / t
+    shifts: List[int] = field(default_factory=list)      # sorted distinct shifts
+    family: int = 1           # 1 = diagonal, 2 = baby-step/giant-step
+    G: int = 1                # baby-step count of the family-2 split
+    # shifts per (ciphertext) of the pack step: -l*B for l = 1..t-1
+    pack_steps: List[int] = field(default_factory=list)
+
+
+@dataclass
+class Plan:
+    n_v: int
+    M: int
+    B_pi: int
+    pi: np.ndarray
+    rows: list
+    layers: List[LayerPlan]
+    regions: List[List[int]] = field(default_factory=list)
+
+    @property
+    def n_out_cts(self) -> int:
+        last = self.layers[-1]
+        return last.f_out if last.kind == "inter" else ceil_div(last.f_out, last.t)
+
+    def rot_steps(self, M: int) -> List[int]:
+        steps = set()
+        for lp in self.layers:
+            if lp.kind != "spintra":
+                continue
+            steps.update(s % M for s in lp.pack_steps)
+            for s in rotation_steps_of(lp):
+                steps.add(s % M)
+        steps.discard(0)
+        return sorted(steps)
+
+
+def next_pow2(x: int) -> int:
+    p = 1
+    while p < x:
+        p *= 2
+    return p
+
+
+def bsgs_split(shifts: Sequence[int], B: int):
+    """Baby-step count G (a power of two <= B) minimising distinct nonzero
+    babies + giants for delta = g*G + b, b in [0, G); ties -> smaller G."""
+    best = None
+    G = 1
+    while G <= max(B, 1):
+        babies = {d % G for d in shifts} - {0}
+        giants = {d // G for d in shifts} - {0}
+        c = len(babies) + len(giants)
+        if best is None or c < best[0]:
+            best = (c, G)
+        G *= 2
+    return best[1], best[0]
+
+
+def rotation_steps_of(lp: LayerPlan) -> List[int]:
+    """Rotation steps the aggregation uses (nonzero)."""
+    if lp.family == 1:
+        return sorted(set(lp.shifts) - {0})
+    babies = {d % lp.G for d in lp.shifts} - {0}
+    giants = {(d // lp.G) * lp.G for d in lp.shifts} - {0}
+    return sorted(babies | giants)
+
+
+def build_plan(n_v: int, rows, dims: Sequence[int], activation: bool, M: int,
+               use_noo: bool = True, TH: Optional[int] = None, family: Optional[int] = None,
+               first_mode: str = "inter") -> Plan:
+    """The executable plan: layer 1 by `first_mode` ("inter" per the paper's
+    first-layer rule, or "spintra"), later layers SpIntra-CA; SpIntra layers
+    combine first (F -> F' at one column per ciphertext), pack t = min(pow2(F'),
+    M / pow2(n_v)) columns per ciphertext, then aggregate on the packed layout."""
+    n_layers = len(dims) - 1
+    if first_mode == "spintra" and n_layers > 1:
+        raise ValueError("a SpIntra-CA layer leaves packed ciphertexts; only the last layer may be SpIntra-CA "
+                         "when it is also the first")
+    # packing of the SpIntra layers fixes the block the node order must fit
+    spin_f = [dims[i + 1] for i in range(n_layers) if i > 0 or first_mode == "spintra"]
+    t_pack = min([next_pow2(f) for f in spin_f] + [M // next_pow2(n_v)]) if spin_f else 1
+    B = M // t_pack
+    if TH is None:
+        TH = 1024 if n_v < 10000 else 4096
+    if use_noo:
+        pi, regions = noo(rows, B, M, TH)
+    else:
+        pi, regions = np.arange(n_v, dtype=np.int64), [list(range(n_v))]
+    layers = []
+    for li in range(n_layers):
+        f_in, f_out = dims[li], dims[li + 1]
+        kind = first_mode if li == 0 else "spintra"
+        if kind == "inter":
+            K = 1 + max(sum(1 for u, _ in row if u != v) for v, row in enumerate(rows))
+            src = np.full((K, n_v), -1, dtype=np.int64)
+            val = np.zeros((K, n_v))
+            for v, row in enumerate(rows):
+                k = 1
+                for u, a in row:
+                    if u == v:
+                        src[0, v], val[0, v] = v, a
+                    else:
+                        src[k, v], val[k, v] = u, a
+                        k += 1
+            layers.append(LayerPlan("inter", f_in, f_out, activation, K=K, copy_src=src, copy_val=val))
+        else:
+            t = min(next_pow2(f_out), M // next_pow2(n_v))
+            Bl = M // t
+            wrap = Bl == M
+            shifts = sorted({reduce_shift(int(pi[u] - pi[v]), M, wrap) for v, row in enumerate(rows)
+                             for u, _ in row})
+            G, c2 = bsgs_split(shifts, Bl)
+            c1 = len(set(shifts) - {0})
+            fam = family if family is not None else (2 if c2 < c1 else 1)
+            pack = [-(l % t) * Bl for l in range(f_out) if l % t != 0]
+            layers.append(LayerPlan("spintra", f_in, f_out, activation, t=t, B=Bl, shifts=shifts,
+                                    family=fam, G=G, pack_steps=sorted(set(pack))))
+    return Plan(n_v=n_v, M=M, B_pi=B, pi=pi, rows=rows, layers=layers, regions=regions)
+
+
+# ----------------------------------------------------------------------------
+# operation counts of a plan (HE operation counts, Table 1)
+# ----------------------------------------------------------------------------
+def op_counts(plan: Plan) -> dict:
+    c = dict(rot=0, pmult=0, cmult=0, smult=0, add=0, rescale=0, keyswitch=0)
+    n_cts = None
+    for li, lp in enumerate(plan.layers):
+        if lp.kind == "inter":
+            c["pmult"] += lp.K * lp.f_in
+            c["add"] += lp.K * lp.f_in
+            c["smult"] += lp.f_in * lp.f_out
+            c["rescale"] += 2 * lp.f_out
+            n_cts = lp.f_out
+        else:
+            n_in = lp.f_in
+            c["smult"] += n_in * lp.f_out
+            c["rescale"] += lp.f_out
+            n_packed = ceil_div(lp.f_out, lp.t)
+            c["rot"] += lp.f_out - n_packed
+            steps = rotation_steps_of(lp)
+            if lp.family == 1:
+                c["rot"] += n_packed * len(steps)
+            else:
+                babies = {d % lp.G for d in lp.shifts} - {0}
+                giants = {d // lp.G for d in lp.shifts} - {0}
+                c["rot"] += n_packed * (len(babies) + len(giants))
+            c["pmult"] += n_packed * len(lp.shifts)
+            c["add"] += n_packed * len(lp.shifts)
+            c["rescale"] += n_packed
+            n_cts = n_packed
+        if lp.activation:
+            c["cmult"] += n_cts
+            c["rescale"] += n_cts
+    c["keyswitch"] = c["rot"] + c["cmult"]
+    return c

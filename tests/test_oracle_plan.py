@@ -1,0 +1,214 @@
+"""Pins of the oracle's planner, slot simulator and encrypted executor: the
+paper's cost formulas at hand-computed values, structural invariants of the
+node-order optimisation, brute force over small placements, and the FP64 GCN."""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import gcn, planner, simulate as sim, execute as ex, ckks
+from oracle.params import Params
+from workload import make_workload, Graph
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(name, **kw):
+    w = make_workload(name, **kw)
+    return w, gcn.normalized_rows(w.graph.n, w.neighbors, w.norm)
+
+
+def test_j_objective_hand_values():
+    with open(os.path.join(GOLD, "j_objective_cfg_tiny.txt")) as f:
+        pairs = [tuple(map(int, l.split())) for l in f if l.strip() and not l.startswith("#")]
+    for t, j in pairs:
+        assert planner.j_objective(t, 32, 4) == j
+    # feasible argmin for the tiny configuration (t N F' <= M: t <= 2)
+    assert planner.paper_packing_t(32, 4, 128, 16, 4096) == 2
+    # citation-graph shape: M <= N F' -> t = 1 (Sec. 3.2 case 2)
+    assert planner.paper_packing_t(1433, 4, 2708, 16, 32768) == 1
+
+
+def test_packing_ciphertext_counts_match_printed_table():
+    with open(os.path.join(GOLD, "packing_ciphertext_counts.txt")) as f:
+        rows = [list(map(int, l.split())) for l in f if l.strip() and not l.startswith("#")]
+    for t, *counts in rows:
+        assert [planner.ceil_div(F, t) for F in (1433, 32, 16)] == counts
+
+
+def test_case2_count_and_mode_rule():
+    # ceil(Fn/t) * ceil(N F' / ceil(M/t)) at t = 1 for the citation-graph shape
+    assert planner.case2_pmults(1, 1433, 4, 2708, 16, 32768) == 1433 * 4 * 2
+    # Inter-CA: 2 ceil(F n / t) vs SpIntra-CA: 10 c n log^2 N
+    assert planner.paper_agg_mode(16, 4, 1, 2708, 0.01) == "spintra"
+    assert planner.paper_agg_mode(16, 4, 1, 2708, 1.0) == "inter"
+    assert planner.spintra_worst_case_rots(4, 1024) == 3 * 100
+
+
+def test_sibling_definition():
+    rows = [[(0, 1.0), (1, 1.0)], [(1, 1.0), (2, 1.0)], [(2, 1.0)], [(3, 1.0), (2, 1.0)]]
+    sib = planner.siblings(rows)
+    assert sib[0] == [1] and sib[1] == [0, 2] and sib[2] == [1, 3] and sib[3] == [2]
+
+
+def test_noo_structure_invariants():
+    w, rows = _rows("cora", n_nodes=600, dims=[8, 4, 3])
+    B = 1024
+    for TH in (64, 200, 1024):
+        regions = planner.noo_regions(rows, TH)
+        assert sorted(v for r in regions for v in r) == list(range(600))
+        assert all(len(r) <= TH for r in regions)
+        assert all(len(r) == TH for r in regions[:-1])
+        slots = planner.interleave_slots([len(r) for r in regions], B)
+        flat = sorted(s for sl in slots for s in sl)
+        assert len(set(flat)) == 600 and flat[-1] < B
+        pi = planner.noo_place(rows, regions, slots, 32768, wrap=False)
+        assert len(set(pi.tolist())) == 600 and pi.min() >= 0 and pi.max() < B
+        # every node sits on one of its region's interleaved slots
+        for r, sl in zip(regions, slots):
+            assert sorted(pi[r].tolist()) == sorted(sl)
+    # the region's first node is the highest-degree node left
+    deg = [len(s) for s in planner.support(rows)]
+    regions = planner.noo_regions(rows, 200)
+    assert deg[regions[0][0]] == max(deg)
+
+
+def test_interleave_round_robin_with_blanks():
+    assert planner.interleave_slots([2, 2, 1], 6) == [[0, 3], [1, 4], [2]]
+    # region 2 exhausted after one round: its turn takes the blank (slot 5)
+    assert planner.interleave_slots([3, 3, 1], 8) == [[0, 3, 6], [1, 4, 7], [2]]
+    # blanks exhausted: exhausted region skipped
+    assert planner.interleave_slots([3, 3, 1], 7) == [[0, 3, 5], [1, 4, 6], [2]]
+
+
+def test_greedy_step_is_argmin_by_brute_force():
+    """Each greedy placement equals the brute-force argmin of its objective
+    (number of new distinct shifts, lowest slot on ties)."""
+    w, rows = _rows("tiny", n_nodes=8, dims=[4, 2])
+    regions = planner.noo_regions(rows, 8)
+    slots = planner.interleave_slots([len(r) for r in regions], 8)
+    pi = planner.noo_place(rows, regions, slots, 4096, wrap=False)
+    placed = {}
+    shifts = set()
+    order = regions[0]
+    for idx, x in enumerate(order):
+        free = [s for s in slots[0] if s not in placed.values()]
+        if idx == 0:
+            best = free[0]
+        else:
+            def cost(pos):
+                new = set()
+                for u, _ in rows[x]:
+                    if u != x and u in placed:
+                        new.add(placed[u] - pos)
+                for v, row in enumerate(rows):
+                    if v != x and v in placed and any(u == x for u, _ in row):
+                        new.add(pos - placed[v])
+                return len(new - shifts)
+            best = min(free, key=lambda p: (cost(p), p))
+        assert pi[x] == best
+        placed[x] = best
+        for u, _ in rows[x]:
+            if u != x and u in placed:
+                shifts.add(placed[u] - best)
+        for v, row in enumerate(rows):
+            if v != x and v in placed and any(u == x for u, _ in row):
+                shifts.add(best - placed[v])
+
+
+def test_circulant_graph_routes_with_one_rotation():
+    """A directed cycle v -> v+1 (identity order, one column): the only shifts
+    are 0 and +1, i.e. one rotation (diagonal form)."""
+    n = 64
+    rows = [[(v, 0.5), ((v + 1) % n, 0.5)] for v in range(n)]
+    plan = planner.build_plan(n, rows, [1, 1], False, 64, use_noo=False, family=1, first_mode="spintra")
+    lp = plan.layers[0]
+    assert lp.t == 1 and lp.B == 64
+    # the wrap-around demand (n-1 -> 0) reduces to +1 with AOO
+    assert lp.shifts == [0, 1] and planner.rotation_steps_of(lp) == [1]
+
+
+def test_aoo_reduces_to_shortest_direction():
+    assert planner.reduce_shift(4095, 4096, True) == -1
+    assert planner.reduce_shift(2048, 4096, True) == 2048
+    assert planner.reduce_shift(-2049, 4096, True) == 2047
+    assert planner.reduce_shift(4095, 4096, False) == 4095
+
+
+def test_bsgs_split_covers_every_shift():
+    shifts = [-300, -17, 0, 3, 64, 65, 129, 511]
+    G, c = planner.bsgs_split(shifts, 512)
+    babies = {d % G for d in shifts}
+    giants = {d // G for d in shifts}
+    for d in shifts:
+        assert (d // G) * G + d % G == d
+    assert c == len(babies - {0}) + len(giants - {0})
+
+
+@pytest.mark.parametrize("name,mode,noo,fam", [
+    ("tiny", "inter", True, None), ("tiny", "spintra", True, 1), ("tiny", "spintra", False, 2),
+    ("tiny2", "inter", True, 1), ("tiny2", "inter", False, 2)])
+def test_slot_simulator_equals_fp64_gcn(name, mode, noo, fam):
+    w, rows = _rows(name)
+    ref = gcn.gcn_forward(rows, w.x, w.weights, w.activation)[-1]
+    M = 2 ** (w.params["log_n"] - 1)
+    plan = planner.build_plan(w.graph.n, rows, w.meta["dims"], w.activation, M, use_noo=noo,
+                              family=fam, first_mode=mode)
+    counts = dict(rot=0, pmult=0, smult=0, cmult=0)
+    out = sim.run(plan, w.x, w.weights, counts)
+    assert gcn.max_rel_error(out, ref) < 1e-12
+    oc = planner.op_counts(plan)
+    assert oc["rot"] == counts["rot"] and oc["pmult"] == counts["pmult"]
+    assert oc["smult"] == counts["smult"] and oc["cmult"] == counts["cmult"]
+    if mode == "inter":
+        lp = plan.layers[0]
+        # Inter-CA: PMult = Add = K F with K = n + 1 copies (Sec. 3.2, Table 1), no rotation
+        assert oc["pmult"] >= lp.K * lp.f_in
+        assert planner.op_counts(planner.Plan(plan.n_v, M, plan.B_pi, plan.pi, rows, [lp]))["rot"] == 0
+
+
+def test_spintra_first_layer_of_deep_model_rejected():
+    w, rows = _rows("tiny2")
+    with pytest.raises(ValueError):
+        planner.build_plan(w.graph.n, rows, w.meta["dims"], True, 4096, first_mode="spintra")
+
+
+def test_mask_nonzeros_equal_adjacency_nonzeros():
+    w, rows = _rows("tiny2")
+    M = 2 ** (w.params["log_n"] - 1)
+    plan = planner.build_plan(w.graph.n, rows, w.meta["dims"], w.activation, M)
+    lp = plan.layers[1]
+    mk = sim.masks(plan, lp, lp.f_out)
+    nnz = sum(len(r) for r in rows)
+    assert sum(int(np.count_nonzero(v)) for v in mk.values()) == nnz * lp.f_out
+
+
+def test_gcn_normalisations():
+    n = 4
+    nb = [np.array([1]), np.array([0, 2]), np.array([1]), np.array([], dtype=np.int64)]
+    rows = gcn.normalized_rows(n, nb, "sym")
+    a = gcn.dense_adjacency(n, rows)
+    A = np.array([[0, 1, 0, 0], [1, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 0]], float) + np.eye(4)
+    d = A.sum(1)
+    assert np.allclose(a, A / np.sqrt(np.outer(d, d)))
+    rows = gcn.normalized_rows(n, nb, "mean")
+    a = gcn.dense_adjacency(n, rows)
+    assert np.allclose(a.sum(1), 1.0) and a[1, 0] == pytest.approx(1 / 3)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,mode", [("tiny", "inter"), ("tiny", "spintra"), ("tiny2", "inter")])
+def test_encrypted_plan_decrypts_to_fp64_gcn(name, mode):
+    w, rows = _rows(name)
+    prm = Params.from_dict(w.params)
+    ref = gcn.gcn_forward(rows, w.x, w.weights, w.activation)[-1]
+    plan = planner.build_plan(w.graph.n, rows, w.meta["dims"], w.activation, prm.M, first_mode=mode)
+    keys = ckks.keygen(prm, 11, plan.rot_steps(prm.M), relin=w.activation)
+    sched = ex.schedule(prm, plan)
+    ops = ex.encode_operands(prm, plan, w.weights, sched)
+    cts = ex.client_encrypt(prm, plan, w.x, keys, 12)
+    outs = ex.run(prm, plan, keys, cts, ops, sched)
+    y = ex.decrypt_output(prm, plan, keys, outs[-1])
+    assert gcn.max_rel_error(y, ref) < 1e-3
