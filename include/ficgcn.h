@@ -1,0 +1,220 @@
+/*
+ * ficgcn.h -- C ABI of the MI355X library for the encrypted GCN layer
+ * X' = A_hat X W under RNS-CKKS (FicGCN, arXiv 2506.10399).
+ *
+ * Threat model (paper Sec. 2.4): the server holds A_hat and W in plaintext,
+ * the client holds the secret key and sends X encrypted; the server computes
+ * on ciphertexts and returns ciphertexts.  Calls marked [client] use the
+ * secret key; [server] calls take only evaluation keys.
+ *
+ * Conventions shared by every entry point
+ *  - Return value: ficgcn_status (0 = OK).  On failure nothing was enqueued
+ *    unless the code is FICGCN_EDEVICE; ficgcn_last_error() gives a message
+ *    (thread-local, valid until the next failing call on that thread).
+ *  - Device buffers are caller-owned (e.g. torch tensors); the library never
+ *    frees them.  Contexts, key sets and plans are library-owned handles,
+ *    released with their *_destroy call.
+ *  - Every device operation is enqueued on the context's HIP stream
+ *    (ckks_ctx_set_stream; default: the null stream) and is asynchronous
+ *    unless stated otherwise.  Host buffers passed to a call may be reused
+ *    when the call returns.
+ *  - Layout: a polynomial at level l is l+1 limbs of N uint64 words, limb i
+ *    holding residues modulo q_i; a ciphertext is [2][l+1][N] (c0 limbs then
+ *    c1 limbs), a plaintext [l+1][N].  Device ciphertexts and plaintexts are
+ *    in the library's evaluation (NTT) representation; "coefficient form"
+ *    host arrays hold the residues of the polynomial's coefficients.
+ *  - Levels: q_0 > q_1 > ... > q_{L-1}; a rescale drops q_l.
+ *  - Rotation by k maps slots (v_0..v_{M-1}) to (v_k..v_{M-1}, v_0..v_{k-1})
+ *    (paper Sec. 2.1); negative k rotates right.
+ */
+#ifndef FICGCN_H
+#define FICGCN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FICGCN_OK = 0,
+  FICGCN_EINVAL = -1,  /* bad argument (null pointer, size, unsupported parameter) */
+  FICGCN_ELEVEL = -2,  /* level out of range or mismatched operands */
+  FICGCN_ESCALE = -3,  /* scale or encoded value out of range */
+  FICGCN_ENOKEY = -4,  /* a needed rotation / relinearisation key is missing */
+  FICGCN_ENOMEM = -5,  /* device allocation failed */
+  FICGCN_EDEVICE = -6, /* HIP runtime error */
+  FICGCN_EPLAN = -7    /* plan cannot be built or does not match the call */
+} ficgcn_status;
+
+typedef struct ckks_ctx ckks_ctx;
+typedef struct ckks_keys ckks_keys;
+typedef struct ficgcn_plan ficgcn_plan;
+
+/* CKKS parameters (paper Sec. 2.1; the sizes follow the workload table).
+ * N = 2^log_n (2^9..2^17), M = N/2 slots; n_q primes of q_bits bits form Q,
+ * n_p special primes of p_bits bits form P (hybrid key switching with
+ * digits of n_p consecutive Q primes); scale = 2^log_scale. */
+typedef struct {
+  uint32_t log_n, n_q, q_bits, n_p, p_bits, log_scale;
+} ckks_params;
+
+const char* ficgcn_last_error(void);
+
+/* ---------------------------------------------------------------- context */
+/* Builds the prime chain (the n_q largest primes below 2^q_bits congruent to
+ * 1 mod 2N, descending, then the n_p largest below 2^p_bits), NTT tables
+ * and base-conversion constants on the current HIP device.  Synchronous. */
+ficgcn_status ckks_context_create(const ckks_params* p, ckks_ctx** out);
+void ckks_ctx_destroy(ckks_ctx* ctx);
+/* stream: a hipStream_t (NULL = default stream). */
+ficgcn_status ckks_ctx_set_stream(ckks_ctx* ctx, void* stream);
+/* moduli_out[n_q + n_p]: Q primes then P primes. */
+ficgcn_status ckks_ctx_moduli(const ckks_ctx* ctx, uint64_t* moduli_out);
+/* Galois element 5^(step mod M) mod 2N of a slot rotation. */
+ficgcn_status ckks_galois_element(const ckks_ctx* ctx, int64_t step, uint64_t* g_out);
+/* Waits for all work enqueued on the context's stream. */
+ficgcn_status ckks_sync(ckks_ctx* ctx);
+
+/* ------------------------------------------------------------------ keys */
+/* [client] Samples the ternary secret and the switching keys (rotation keys
+ * for every step in rot_steps, the relinearisation key if with_relin) from
+ * the ChaCha20 streams of `seed`.  *client_keys holds the secret and can
+ * decrypt; *eval_keys holds only switching keys (what the server receives).
+ * Either output pointer may be NULL if that object is not wanted. */
+ficgcn_status ckks_keygen(ckks_ctx* ctx, uint64_t seed, const int64_t* rot_steps, size_t n_steps, int with_relin,
+                          ckks_keys** client_keys, ckks_keys** eval_keys);
+/* Number of switching keys held and their tags (Galois element; 0 = relin). */
+ficgcn_status ckks_keys_tags(const ckks_keys* keys, uint64_t* tags_out, size_t cap, size_t* n_out);
+/* Copies one switching key to the host in coefficient form,
+ * [beta][2][n_q + n_p][N] (b then a per digit).  Synchronous. */
+ficgcn_status ckks_keys_export(ckks_ctx* ctx, const ckks_keys* keys, uint64_t tag, uint64_t* host_out);
+/* Installs a switching key given in coefficient form (layout as export). */
+ficgcn_status ckks_keys_import(ckks_ctx* ctx, ckks_keys* keys, uint64_t tag, const uint64_t* host_in);
+/* An empty evaluation key set, to be filled with ckks_keys_import. */
+ficgcn_status ckks_keys_create_empty(ckks_ctx* ctx, ckks_keys** out);
+void ckks_keys_destroy(ckks_keys* keys);
+
+/* ------------------------------------------------- encode / encrypt [client] */
+/* Encodes n <= M complex slots (im may be NULL) at `scale` into a device
+ * plaintext [level+1][N]: round-half-even of the scaled inverse canonical
+ * embedding (FP64 FFT on the host), then residues and NTT. */
+ficgcn_status ckks_encode(ckks_ctx* ctx, const double* re, const double* im, size_t n, double scale, uint32_t level,
+                          uint64_t* pt_dev);
+/* Batch form: `count` slot vectors of n doubles each (real parts only,
+ * row-major), encoded on host threads into pt_dev[count][level+1][N]. */
+ficgcn_status ckks_encode_batch(ckks_ctx* ctx, const double* re, size_t count, size_t n, double scale, uint32_t level,
+                                uint64_t* pt_dev);
+/* Uploads a plaintext given as coefficient-form residues [level+1][N]. */
+ficgcn_status ckks_pt_load(ckks_ctx* ctx, const uint64_t* host_coeffs, uint32_t level, uint64_t* pt_dev);
+/* ct = (-a s + e + m, a) mod Q_level with a, e from the streams of (seed, ct_id). */
+ficgcn_status ckks_encrypt(ckks_ctx* ctx, const ckks_keys* client_keys, const uint64_t* pt_dev, uint32_t level,
+                           uint64_t seed, uint32_t ct_id, uint64_t* ct_dev);
+/* Decrypts and decodes n_slots slots (im may be NULL) at `scale`.  Synchronous. */
+ficgcn_status ckks_decrypt(ckks_ctx* ctx, const ckks_keys* client_keys, const uint64_t* ct_dev, uint32_t level,
+                           double scale, double* re, double* im, size_t n_slots);
+
+/* -------------------------------------------------- transfers (either side) */
+/* Uploads a ciphertext given in coefficient form [2][level+1][N]. */
+ficgcn_status ckks_ct_load(ckks_ctx* ctx, const uint64_t* host_coeffs, uint32_t level, uint64_t* ct_dev);
+/* Downloads a ciphertext (or, with n_polys = 1, a plaintext) in coefficient
+ * form [n_polys][level+1][N].  Synchronous. */
+ficgcn_status ckks_poly_store(ckks_ctx* ctx, const uint64_t* dev, uint32_t level, uint32_t n_polys,
+                              uint64_t* host_coeffs);
+/* Forward (inverse = 0) or inverse NTT in place on n_limbs limbs starting at
+ * modulus index first_mod (Q primes 0..n_q-1, then P primes). */
+ficgcn_status ckks_ntt(ckks_ctx* ctx, uint64_t* dev, uint32_t n_limbs, uint32_t first_mod, int inverse);
+
+/* ------------------------------------------------------ evaluation [server] */
+/* Rotations of one ciphertext by each of steps[0..k): one ModUp of c1 is
+ * shared by all k (hoisting).  Each rotation is computed as ModUp, then the
+ * Galois automorphism on every extended digit, the key inner product and a
+ * rounding ModDown (words equal to k single rotations).  outs[i] are k
+ * device buffers [2][level+1][N]; a zero step copies the input.  ENOKEY if
+ * a step's key is missing (nothing enqueued). */
+ficgcn_status ckks_rotate_hoisted(ckks_ctx* ctx, const ckks_keys* eval_keys, const uint64_t* ct_dev, uint32_t level,
+                                  const int64_t* steps, size_t k, uint64_t* const* outs);
+/* acc += sum_i pts[i] (.) cts[i]  (plaintext-ciphertext multiply-accumulate
+ * of Sec. 3.3's masks and Inter-CA copies); no rescale. */
+ficgcn_status ckks_pt_mul_acc(ckks_ctx* ctx, uint64_t* acc_dev, uint32_t level, const uint64_t* const* cts,
+                              const uint64_t* const* pts, size_t k);
+/* acc += sum_i consts[i] * cts[i] for signed integer constants (a weight w
+ * encoded at scale s is round_half_even(w * s)); no rescale. */
+ficgcn_status ckks_scalar_mul_acc(ckks_ctx* ctx, uint64_t* acc_dev, uint32_t level, const uint64_t* const* cts,
+                                  const int64_t* consts, size_t k);
+/* acc += in (ciphertexts at the same level). */
+ficgcn_status ckks_add(ckks_ctx* ctx, uint64_t* acc_dev, const uint64_t* in_dev, uint32_t level);
+/* In place: round(c / q_level) on both components; the result is the
+ * ciphertext at level-1, packed as [2][level][N] at the start of the buffer. */
+ficgcn_status ckks_rescale(ckks_ctx* ctx, uint64_t* ct_dev, uint32_t level);
+/* out = x * y relinearised (tensor, then the relin key switches the a1 a2
+ * term); no rescale.  out may not alias x or y. */
+ficgcn_status ckks_mul_relin(ckks_ctx* ctx, const ckks_keys* eval_keys, const uint64_t* x_dev, const uint64_t* y_dev,
+                             uint32_t level, uint64_t* out_dev);
+
+/* ------------------------------------------------------------ plan [server] */
+/* Plan options. */
+typedef struct {
+  int32_t first_mode;   /* 0: Inter-CA first layer (paper's rule), 1: SpIntra-CA (one-layer models only) */
+  int32_t use_noo;      /* node order optimisation (Alg. 1) on/off */
+  int32_t family;       /* SpIntra-CA routing: 0 = cheaper of the two, 1 = diagonal, 2 = baby-step/giant-step */
+  int32_t TH;           /* region size cap; 0 = 1024 below 10000 nodes, else 4096 */
+  int32_t activation;   /* x^2 after every layer */
+} ficgcn_plan_opts;
+
+/* Builds the plan of an n_layers-layer GCN over the normalised adjacency
+ * A_hat given as CSR (row v: columns col[rowptr[v]..rowptr[v+1]) with values
+ * val, the diagonal included): node order, per-layer aggregation mode,
+ * packing, shift routing, scale schedule and integer weights.  weights[l]
+ * is the dims[l] x dims[l+1] row-major FP64 matrix of layer l.  The
+ * plaintext operands (Inter-CA copies' adjacency plaintexts, masks) are
+ * encoded by ficgcn_plan_encode or loaded with ficgcn_plan_load_operand. */
+ficgcn_status ficgcn_plan_create(ckks_ctx* ctx, const int32_t* rowptr, const int32_t* col, const double* val,
+                                 uint32_t n_v, const uint32_t* dims, uint32_t n_layers, const double* const* weights,
+                                 const ficgcn_plan_opts* opts, ficgcn_plan** out);
+void ficgcn_plan_destroy(ficgcn_plan* plan);
+/* The node order: pi_out[v] = slot of node v inside a column block (the
+ * client packs its inputs in this order, paper App. B). */
+ficgcn_status ficgcn_plan_node_order(const ficgcn_plan* plan, int32_t* pi_out);
+/* Inter-CA copy structure of layer `layer` (the client builds its encrypted
+ * copies from it, paper Sec. 3.3.2): src_out[k * n_v + v] = the node whose
+ * features copy k holds at node v's slot, -1 for none; copy 0 is the node
+ * itself.  K = info "K". */
+ficgcn_status ficgcn_plan_copy_sources(const ficgcn_plan* plan, uint32_t layer, int32_t* src_out);
+/* Rotation steps whose keys the client must generate (sorted, in [1, M)). */
+ficgcn_status ficgcn_plan_rot_steps(const ficgcn_plan* plan, int64_t* steps_out, size_t cap, size_t* n_out);
+/* Plan description: per layer {kind, f_in, f_out, K, t, B, family, G,
+ * n_shifts, level_in, level_out, n_in_cts, n_out_cts} as int64, 13 per layer,
+ * then 3 doubles per layer in scales_out {scale_in, scale_out, weight scale}. */
+ficgcn_status ficgcn_plan_info(const ficgcn_plan* plan, int64_t* info_out, double* scales_out, uint32_t* n_layers);
+/* Shifts of layer `layer` (SpIntra-CA), sorted. */
+ficgcn_status ficgcn_plan_shifts(const ficgcn_plan* plan, uint32_t layer, int64_t* out, size_t cap, size_t* n_out);
+/* Integer weights of a layer as the plan encodes them (round_half_even(w * sW)). */
+ficgcn_status ficgcn_plan_weights_int(const ficgcn_plan* plan, uint32_t layer, int64_t* out);
+/* Number of plaintext operands of a layer and the slot vector of operand i
+ * (M doubles): Inter-CA adjacency plaintext of copy i, or SpIntra-CA mask i
+ * (packed ciphertext i / n_shifts, shift index i % n_shifts). */
+ficgcn_status ficgcn_plan_operand_count(const ficgcn_plan* plan, uint32_t layer, size_t* n_out);
+ficgcn_status ficgcn_plan_operand_slots(const ficgcn_plan* plan, uint32_t layer, size_t i, double* slots_out);
+/* Encodes every operand with the library's encoder.  Synchronous. */
+ficgcn_status ficgcn_plan_encode(ckks_ctx* ctx, ficgcn_plan* plan);
+/* Installs operand i of a layer from coefficient-form residues [level+1][N]
+ * at the operand's level (for operands encoded elsewhere). */
+ficgcn_status ficgcn_plan_load_operand(ckks_ctx* ctx, ficgcn_plan* plan, uint32_t layer, size_t i,
+                                       const uint64_t* host_coeffs);
+
+/* Runs layer `layer` of the plan (combination, packing, aggregation,
+ * rescales and the x^2 activation as the plan schedules them).
+ * Inputs: Inter-CA first layer: K*F client ciphertexts, copy k of column f at
+ * index k*F + f; later / SpIntra-CA layers: the previous layer's outputs.
+ * mode 0 = one library operation at a time ("plain"), mode 1 = fused,
+ * batched launches ("batched"); both produce the same words. */
+ficgcn_status ficgcn_gcn_layer(ckks_ctx* ctx, const ckks_keys* eval_keys, const ficgcn_plan* plan, uint32_t layer,
+                               const uint64_t* const* in_cts, size_t n_in, uint64_t* const* out_cts, size_t n_out,
+                               int32_t mode);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

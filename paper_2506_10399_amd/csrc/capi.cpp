@@ -1,0 +1,510 @@
+// extern "C" entry points: argument validation, then the device routines.
+// No exception crosses the boundary; failures return a status and leave a
+// thread-local message.
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/ficgcn.h"
+#include "internal.h"
+
+namespace ficgcn {
+void encode_coeffs(int N, const double* re, const double* im, size_t n, double scale, std::vector<int64_t>& out);
+void decode_values(int N, const std::vector<double>& m, double scale, double* re, double* im, size_t n);
+void crt_center(const std::vector<uint64_t>& mods, const uint64_t* res, int N, std::vector<double>& out);
+
+static thread_local std::string g_err;
+void set_error(const std::string& m) { g_err = m; }
+
+template <typename F>
+static ficgcn_status guard(F&& f) {
+  try {
+    f();
+    return FICGCN_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return (ficgcn_status)e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return FICGCN_ENOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return FICGCN_EINVAL;
+  }
+}
+
+#define REQUIRE(cond, code, msg) \
+  do {                           \
+    if (!(cond)) FICGCN_THROW(code, msg); \
+  } while (0)
+
+static void check_level(const ckks_ctx* c, uint32_t level) {
+  REQUIRE(c != nullptr, EINVAL_, "null context");
+  REQUIRE((int)level < c->L, ELEVEL_, "level " + std::to_string(level) + " >= number of Q primes");
+}
+
+// residues of signed coefficients into [k][N] over the first k Q primes
+static void to_residues(const ckks_ctx* c, const std::vector<int64_t>& m, int k, std::vector<uint64_t>& out) {
+  const size_t N = c->N;
+  out.resize((size_t)k * N);
+  for (int i = 0; i < k; ++i) {
+    uint64_t q = c->mod[i];
+    for (size_t j = 0; j < N; ++j) {
+      int64_t v = m[j];
+      uint64_t a = v >= 0 ? (uint64_t)v % q : (q - (uint64_t)(-(v + 1)) % q - 1) % q;
+      out[i * N + j] = a;
+    }
+  }
+}
+
+static void upload_ntt(ckks_ctx* c, const uint64_t* host, int n_limbs, uint64_t* dev, int n_polys) {
+  const size_t bytes = (size_t)n_polys * n_limbs * c->N * 8;
+  HIPCHECK(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, c->stream));
+  ntt_fwd(c, dev, n_limbs, lm_q(n_limbs), n_polys, (size_t)n_limbs * c->N);
+  HIPCHECK(hipStreamSynchronize(c->stream));   // host buffer may be released on return
+}
+
+static const uint64_t* need_key(const ckks_keys* k, uint64_t tag) {
+  REQUIRE(k != nullptr, EINVAL_, "null key set");
+  auto it = k->swk.find(tag);
+  REQUIRE(it != k->swk.end(), ENOKEY_, "missing switching key for tag " + std::to_string(tag));
+  return it->second;
+}
+
+}  // namespace ficgcn
+
+using namespace ficgcn;
+
+extern "C" {
+
+const char* ficgcn_last_error(void) { return g_err.c_str(); }
+
+ficgcn_status ckks_context_create(const ckks_params* p, ckks_ctx** out) {
+  return guard([&] {
+    REQUIRE(p && out, EINVAL_, "null argument");
+    REQUIRE(p->log_n >= 9 && p->log_n <= 17, EINVAL_, "log_n must be in [9, 17]");
+    REQUIRE(p->n_q >= 1 && p->n_q <= 60 && p->n_p >= 1 && p->n_p <= 8, EINVAL_, "n_q in [1, 60], n_p in [1, 8]");
+    std::unique_ptr<ckks_ctx> c(new ckks_ctx());
+    c->log_n = (int)p->log_n;
+    c->L = (int)p->n_q;
+    c->alpha = (int)p->n_p;
+    c->q_bits = (int)p->q_bits;
+    c->p_bits = (int)p->p_bits;
+    c->log_scale = (int)p->log_scale;
+    build_context(c.get());
+    *out = c.release();
+  });
+}
+
+void ckks_ctx_destroy(ckks_ctx* ctx) { delete ctx; }
+
+ficgcn_status ckks_ctx_set_stream(ckks_ctx* ctx, void* stream) {
+  return guard([&] {
+    REQUIRE(ctx, EINVAL_, "null context");
+    ctx->stream = (hipStream_t)stream;
+  });
+}
+
+ficgcn_status ckks_ctx_moduli(const ckks_ctx* ctx, uint64_t* out) {
+  return guard([&] {
+    REQUIRE(ctx && out, EINVAL_, "null argument");
+    std::memcpy(out, ctx->mod.data(), ctx->mod.size() * 8);
+  });
+}
+
+ficgcn_status ckks_galois_element(const ckks_ctx* ctx, int64_t step, uint64_t* g_out) {
+  return guard([&] {
+    REQUIRE(ctx && g_out, EINVAL_, "null argument");
+    *g_out = galois_elt(const_cast<ckks_ctx*>(ctx), step);
+  });
+}
+
+ficgcn_status ckks_sync(ckks_ctx* ctx) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    REQUIRE(ctx, EINVAL_, "null context");
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+// ---------------------------------------------------------------- keys
+static uint64_t* alloc_swk(ckks_ctx* c) {
+  uint64_t* p = nullptr;
+  size_t bytes = (size_t)c->beta() * 2 * c->n_mod() * c->N * 8;
+  if (hipMalloc(&p, bytes) != hipSuccess) FICGCN_THROW(ENOMEM_, "key allocation failed");
+  return p;
+}
+
+ficgcn_status ckks_keygen(ckks_ctx* ctx, uint64_t seed, const int64_t* rot_steps, size_t n_steps, int with_relin,
+                          ckks_keys** client_keys, ckks_keys** eval_keys) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    REQUIRE(ctx, EINVAL_, "null context");
+    REQUIRE(n_steps == 0 || rot_steps, EINVAL_, "null rot_steps");
+    const size_t N = ctx->N;
+    const int nm = ctx->n_mod();
+    std::unique_ptr<ckks_keys> cl(new ckks_keys()), ev(new ckks_keys());
+    cl->ctx = ev->ctx = ctx;
+    cl->has_secret = true;
+    HIPCHECK(hipMalloc(&cl->s_ntt, (size_t)nm * N * 8));
+    sample_small_rns(ctx, cl->s_ntt, seed, 1, 0, 0, 0, nm, lm_q(nm));
+    ntt_fwd(ctx, cl->s_ntt, nm, lm_q(nm), 1, 0);
+    uint64_t* sp = (uint64_t*)ctx->buf(11, (size_t)nm * N * 8);
+    auto make = [&](uint64_t tag) {
+      if (ev->swk.count(tag)) return;
+      if (tag == 0)
+        ew_mul(ctx, sp, cl->s_ntt, cl->s_ntt, nm, lm_q(nm));
+      else
+        automorph_ntt(ctx, sp, cl->s_ntt, tag, nm, 1);
+      uint64_t* k = alloc_swk(ctx);
+      ev->swk[tag] = k;
+      keygen_swk(ctx, seed, cl->s_ntt, sp, tag, k);
+    };
+    for (size_t i = 0; i < n_steps; ++i) {
+      uint64_t g = galois_elt(ctx, rot_steps[i]);
+      if (g != 1) make(g);
+    }
+    if (with_relin) make(0);
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+    if (client_keys) {
+      // the client object also carries the switching keys (copies)
+      for (auto& kv : ev->swk) {
+        uint64_t* k = alloc_swk(ctx);
+        HIPCHECK(hipMemcpyAsync(k, kv.second, (size_t)ctx->beta() * 2 * nm * N * 8, hipMemcpyDeviceToDevice,
+                                ctx->stream));
+        cl->swk[kv.first] = k;
+      }
+      HIPCHECK(hipStreamSynchronize(ctx->stream));
+      *client_keys = cl.release();
+    }
+    if (eval_keys) *eval_keys = ev.release();
+  });
+}
+
+ficgcn_status ckks_keys_tags(const ckks_keys* keys, uint64_t* tags_out, size_t cap, size_t* n_out) {
+  return guard([&] {
+    REQUIRE(keys && n_out, EINVAL_, "null argument");
+    *n_out = keys->swk.size();
+    size_t i = 0;
+    for (auto& kv : keys->swk) {
+      if (tags_out && i < cap) tags_out[i] = kv.first;
+      ++i;
+    }
+  });
+}
+
+ficgcn_status ckks_keys_export(ckks_ctx* ctx, const ckks_keys* keys, uint64_t tag, uint64_t* host_out) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    REQUIRE(ctx && host_out, EINVAL_, "null argument");
+    const uint64_t* k = need_key(keys, tag);
+    const size_t N = ctx->N;
+    const int nm = ctx->n_mod();
+    const size_t words = (size_t)ctx->beta() * 2 * nm * N;
+    uint64_t* tmp = (uint64_t*)ctx->buf(12, words * 8);
+    HIPCHECK(hipMemcpyAsync(tmp, k, words * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    ntt_inv(ctx, tmp, nm, lm_q(nm), ctx->beta() * 2, (size_t)nm * N);
+    HIPCHECK(hipMemcpyAsync(host_out, tmp, words * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+ficgcn_status ckks_keys_import(ckks_ctx* ctx, ckks_keys* keys, uint64_t tag, const uint64_t* host_in) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    REQUIRE(ctx && keys && host_in, EINVAL_, "null argument");
+    const size_t N = ctx->N;
+    const int nm = ctx->n_mod();
+    const size_t words = (size_t)ctx->beta() * 2 * nm * N;
+    uint64_t* k;
+    auto it = keys->swk.find(tag);
+    if (it == keys->swk.end()) {
+      k = alloc_swk(ctx);
+      keys->swk[tag] = k;
+    } else {
+      k = it->second;
+    }
+    HIPCHECK(hipMemcpyAsync(k, host_in, words * 8, hipMemcpyHostToDevice, ctx->stream));
+    ntt_fwd(ctx, k, nm, lm_q(nm), ctx->beta() * 2, (size_t)nm * N);
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+ficgcn_status ckks_keys_create_empty(ckks_ctx* ctx, ckks_keys** out) {
+  return guard([&] {
+    REQUIRE(ctx && out, EINVAL_, "null argument");
+    ckks_keys* k = new ckks_keys();
+    k->ctx = ctx;
+    *out = k;
+  });
+}
+
+void ckks_keys_destroy(ckks_keys* keys) { delete keys; }
+
+// ---------------------------------------------------------------- encode / encrypt
+ficgcn_status ckks_encode(ckks_ctx* ctx, const double* re, const double* im, size_t n, double scale, uint32_t level,
+                          uint64_t* pt_dev) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    check_level(ctx, level);
+    REQUIRE(pt_dev && (re || n == 0), EINVAL_, "null argument");
+    REQUIRE(n <= (size_t)ctx->N / 2, EINVAL_, "more values than slots");
+    std::vector<int64_t> m;
+    encode_coeffs(ctx->N, re, im, n, scale, m);
+    std::vector<uint64_t> r;
+    to_residues(ctx, m, level + 1, r);
+    upload_ntt(ctx, r.data(), level + 1, pt_dev, 1);
+  });
+}
+
+ficgcn_status ckks_encode_batch(ckks_ctx* ctx, const double* re, size_t count, size_t n, double scale, uint32_t level,
+                                uint64_t* pt_dev) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    check_level(ctx, level);
+    REQUIRE(pt_dev && re, EINVAL_, "null argument");
+    REQUIRE(n <= (size_t)ctx->N / 2, EINVAL_, "more values than slots");
+    const size_t N = ctx->N;
+    const int l1 = level + 1;
+    const size_t per = (size_t)l1 * N;
+    const size_t chunk = 64;
+    std::vector<uint64_t> host(chunk * per);
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    for (size_t b0 = 0; b0 < count; b0 += chunk) {
+      size_t nb = std::min(chunk, count - b0);
+      std::vector<std::thread> th;
+      std::vector<std::string> errs(nt);
+      for (unsigned t = 0; t < nt; ++t)
+        th.emplace_back([&, t] {
+          try {
+            std::vector<int64_t> m;
+            std::vector<uint64_t> r;
+            for (size_t b = t; b < nb; b += nt) {
+              encode_coeffs(ctx->N, re + (b0 + b) * n, nullptr, n, scale, m);
+              to_residues(ctx, m, l1, r);
+              std::memcpy(host.data() + b * per, r.data(), per * 8);
+            }
+          } catch (const Error& e) {
+            errs[t] = e.msg;
+          }
+        });
+      for (auto& x : th) x.join();
+      for (auto& e : errs) REQUIRE(e.empty(), ESCALE_, e);
+      upload_ntt(ctx, host.data(), l1, pt_dev + b0 * per, (int)nb);
+    }
+  });
+}
+
+ficgcn_status ckks_pt_load(ckks_ctx* ctx, const uint64_t* host_coeffs, uint32_t level, uint64_t* pt_dev) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    check_level(ctx, level);
+    REQUIRE(host_coeffs && pt_dev, EINVAL_, "null argument");
+    upload_ntt(ctx, host_coeffs, level + 1, pt_dev, 1);
+  });
+}
+
+ficgcn_status ckks_encrypt(ckks_ctx* ctx, const ckks_keys* client_keys, const uint64_t* pt_dev, uint32_t level,
+                           uint64_t seed, uint32_t ct_id, uint64_t* ct_dev) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    check_level(ctx, level);
+    REQUIRE(client_keys && client_keys->has_secret, EINVAL_, "encryption needs the client key set");
+    REQUIRE(pt_dev && ct_dev, EINVAL_, "null argument");
+    encrypt_sym(ctx, client_keys->s_ntt, pt_dev, level, seed, ct_id, ct_dev);
+  });
+}
+
+ficgcn_status ckks_decrypt(ckks_ctx* ctx, const ckks_keys* client_keys, const uint64_t* ct_dev, uint32_t level,
+                           double scale, double* re, double* im, size_t n_slots) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    check_level(ctx, level);
+    REQUIRE(client_keys && client_keys->has_secret, EINVAL_, "decryption needs the client key set");
+    REQUIRE(ct_dev && (re || im), EINVAL_, "null argument");
+    const size_t N = ctx->N;
+    const int l1 = level + 1;
+    uint64_t* m = (uint64_t*)ctx->buf(13, (size_t)l1 * N * 8);
+    decrypt_core(ctx, ct_dev, client_keys->s_ntt, level, m);
+    ntt_inv(ctx, m, l1, lm_q(l1), 1, 0);
+    std::vector<uint64_t> host((size_t)l1 * N);
+    HIPCHECK(hipMemcpyAsync(host.data(), m, host.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+    std::vector<uint64_t> mods(ctx->mod.begin(), ctx->mod.begin() + l1);
+    std::vector<double> coef;
+    crt_center(mods, host.data(), (int)N, coef);
+    decode_values((int)N, coef, scale, re, im, n_slots);
+  });
+}
+
+// ---------------------------------------------------------------- transfers
+ficgcn_status ckks_ct_load(ckks_ctx* ctx, const uint64_t* host_coeffs, uint32_t level, uint64_t* ct_dev) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    check_level(ctx, level);
+    REQUIRE(host_coeffs && ct_dev, EINVAL_, "null argument");
+    upload_ntt(ctx, host_coeffs, level + 1, ct_dev, 2);
+  });
+}
+
+ficgcn_status ckks_poly_store(ckks_ctx* ctx, const uint64_t* dev, uint32_t level, uint32_t n_polys,
+                              uint64_t* host_coeffs) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    check_level(ctx, level);
+    REQUIRE(dev && host_coeffs && n_polys >= 1, EINVAL_, "bad argument");
+    const size_t N = ctx->N;
+    const int l1 = level + 1;
+    const size_t words = (size_t)n_polys * l1 * N;
+    uint64_t* tmp = (uint64_t*)ctx->buf(14, words * 8);
+    HIPCHECK(hipMemcpyAsync(tmp, dev, words * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    ntt_inv(ctx, tmp, l1, lm_q(l1), (int)n_polys, (size_t)l1 * N);
+    HIPCHECK(hipMemcpyAsync(host_coeffs, tmp, words * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+ficgcn_status ckks_ntt(ckks_ctx* ctx, uint64_t* dev, uint32_t n_limbs, uint32_t first_mod, int inverse) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    REQUIRE(ctx && dev, EINVAL_, "null argument");
+    REQUIRE(first_mod + n_limbs <= (uint32_t)ctx->n_mod(), EINVAL_, "limb range outside the modulus chain");
+    LimbMap map{(int)first_mod, 1 << 30, 0};
+    if (inverse)
+      ntt_inv(ctx, dev, (int)n_limbs, map, 1, 0);
+    else
+      ntt_fwd(ctx, dev, (int)n_limbs, map, 1, 0);
+  });
+}
+
+// ---------------------------------------------------------------- evaluation
+ficgcn_status ckks_rotate_hoisted(ckks_ctx* ctx, const ckks_keys* eval_keys, const uint64_t* ct_dev, uint32_t level,
+                                  const int64_t* steps, size_t k, uint64_t* const* outs) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    check_level(ctx, level);
+    REQUIRE(ct_dev && (k == 0 || (steps && outs)), EINVAL_, "null argument");
+    const size_t N = ctx->N;
+    const int l1 = level + 1, ext = l1 + ctx->alpha;
+    const int nd = (l1 + ctx->alpha - 1) / ctx->alpha;
+    std::vector<uint64_t> gs(k);
+    std::vector<const uint64_t*> keys(k, nullptr);
+    bool any = false;
+    for (size_t i = 0; i < k; ++i) {
+      REQUIRE(outs[i] && outs[i] != ct_dev, EINVAL_, "output buffer missing or aliases the input");
+      gs[i] = galois_elt(ctx, steps[i]);
+      if (gs[i] != 1) {
+        keys[i] = need_key(eval_keys, gs[i]);
+        any = true;
+      }
+    }
+    uint64_t* D = nullptr;
+    uint64_t* acc = nullptr;
+    if (any) {
+      D = (uint64_t*)ctx->buf(20, (size_t)nd * ext * N * 8);
+      acc = (uint64_t*)ctx->buf(21, (size_t)2 * ext * N * 8);
+      modup(ctx, ct_dev + (size_t)l1 * N, level, D);
+    }
+    for (size_t i = 0; i < k; ++i) {
+      if (gs[i] == 1) {
+        copy_d2d(ctx, outs[i], ct_dev, (size_t)2 * l1 * N * 8);
+        continue;
+      }
+      keymac(ctx, acc, D, keys[i], level, gs[i]);
+      moddown(ctx, acc, level, outs[i], ct_dev, gs[i], nullptr);
+    }
+  });
+}
+
+ficgcn_status ckks_pt_mul_acc(ckks_ctx* ctx, uint64_t* acc_dev, uint32_t level, const uint64_t* const* cts,
+                              const uint64_t* const* pts, size_t k) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    check_level(ctx, level);
+    REQUIRE(acc_dev && (k == 0 || (cts && pts)), EINVAL_, "null argument");
+    for (size_t b = 0; b < k; b += PtrList::MAX) {
+      PtrList c{}, p{};
+      int n = (int)std::min<size_t>(PtrList::MAX, k - b);
+      for (int i = 0; i < n; ++i) {
+        REQUIRE(cts[b + i] && pts[b + i], EINVAL_, "null operand");
+        c.p[i] = cts[b + i];
+        p.p[i] = pts[b + i];
+      }
+      pmul_acc(ctx, acc_dev, c, p, n, level + 1);
+    }
+  });
+}
+
+ficgcn_status ckks_scalar_mul_acc(ckks_ctx* ctx, uint64_t* acc_dev, uint32_t level, const uint64_t* const* cts,
+                                  const int64_t* consts, size_t k) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    check_level(ctx, level);
+    REQUIRE(acc_dev && (k == 0 || (cts && consts)), EINVAL_, "null argument");
+    const int l1 = level + 1;
+    std::vector<uint64_t> host(k * l1 * 2);
+    for (size_t t = 0; t < k; ++t)
+      for (int i = 0; i < l1; ++i) {
+        uint64_t q = ctx->mod[i];
+        int64_t v = consts[t];
+        uint64_t r = v >= 0 ? (uint64_t)v % q : (q - (uint64_t)(-(v + 1)) % q - 1) % q;
+        host[(t * l1 + i) * 2] = r;
+        host[(t * l1 + i) * 2 + 1] = shoup(r, q);
+      }
+    uint64_t* dev = (uint64_t*)ctx->buf(15, std::max<size_t>(8, host.size() * 8));
+    HIPCHECK(hipMemcpyAsync(dev, host.data(), host.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+    for (size_t b = 0; b < k; b += PtrList::MAX) {
+      PtrList c{};
+      int n = (int)std::min<size_t>(PtrList::MAX, k - b);
+      for (int i = 0; i < n; ++i) {
+        REQUIRE(cts[b + i], EINVAL_, "null operand");
+        c.p[i] = cts[b + i];
+      }
+      smul_acc(ctx, acc_dev, c, dev + b * l1 * 2, n, l1);
+    }
+    HIPCHECK(hipStreamSynchronize(ctx->stream));   // host constants must outlive the copy
+  });
+}
+
+ficgcn_status ckks_add(ckks_ctx* ctx, uint64_t* acc_dev, const uint64_t* in_dev, uint32_t level) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    check_level(ctx, level);
+    REQUIRE(acc_dev && in_dev, EINVAL_, "null argument");
+    add_inplace(ctx, acc_dev, in_dev, level + 1, 2);
+  });
+}
+
+ficgcn_status ckks_rescale(ckks_ctx* ctx, uint64_t* ct_dev, uint32_t level) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    check_level(ctx, level);
+    REQUIRE(ct_dev, EINVAL_, "null argument");
+    REQUIRE(level >= 1, ELEVEL_, "rescale at level 0");
+    rescale_inplace(ctx, ct_dev, (int)level);
+  });
+}
+
+ficgcn_status ckks_mul_relin(ckks_ctx* ctx, const ckks_keys* eval_keys, const uint64_t* x_dev, const uint64_t* y_dev,
+                             uint32_t level, uint64_t* out_dev) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    check_level(ctx, level);
+    REQUIRE(x_dev && y_dev && out_dev, EINVAL_, "null argument");
+    REQUIRE(out_dev != x_dev && out_dev != y_dev, EINVAL_, "output aliases an input");
+    const uint64_t* rk = need_key(eval_keys, 0);
+    const size_t N = ctx->N;
+    const int l1 = level + 1, ext = l1 + ctx->alpha;
+    const int nd = (l1 + ctx->alpha - 1) / ctx->alpha;
+    uint64_t* d = (uint64_t*)ctx->buf(22, (size_t)3 * l1 * N * 8);
+    tensor(ctx, x_dev, y_dev, d, level);
+    uint64_t* D = (uint64_t*)ctx->buf(20, (size_t)nd * ext * N * 8);
+    uint64_t* acc = (uint64_t*)ctx->buf(21, (size_t)2 * ext * N * 8);
+    modup(ctx, d + (size_t)2 * l1 * N, level, D);
+    keymac(ctx, acc, D, rk, level, 1);
+    moddown(ctx, acc, level, out_dev, d, 1, d + (size_t)l1 * N);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,542 @@
+// GCN layer executor and the plan entry points.
+//
+// A layer runs in one of two forms that produce identical words:
+//  plain   (mode 0): one HE operation per library call -- PMult/Add per
+//          Inter-CA copy, scalar MAC per weight, one key switch (ModUp,
+//          inner product, ModDown) per rotation, one rescale per ciphertext;
+//  batched (mode 1): the Inter-CA aggregation and the combination fused in
+//          one pass over the inputs, every rotation of a source hoisted on
+//          one ModUp, constants resident on the device.
+// Words agree because every step is exact modular arithmetic and a rotation
+// is defined as ModUp, automorphism, inner product, ModDown in both forms.
+#include <algorithm>
+#include <cstring>
+#include <set>
+
+#include "../../include/ficgcn.h"
+#include "plan.h"
+
+namespace ficgcn {
+
+void comb_fused(ckks_ctx* c, uint64_t* const* out_dev_ptrs, const uint64_t* const* in_dev_ptrs,
+                const uint64_t* const* pt_dev_ptrs, int K, int F, int F_out, int level, const uint64_t* w_dev);
+void zero_fill(ckks_ctx* c, uint64_t* p, size_t words);
+void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_layers, const double* const* weights,
+                const ficgcn_plan_opts& o);
+std::vector<int64_t> layer_rotation_steps(const LayerPlan& lp);
+
+static int64_t fdiv(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+  return q;
+}
+static int64_t fmodp(int64_t a, int64_t b) { return a - fdiv(a, b) * b; }
+
+static uint64_t residue(int64_t v, uint64_t q) {
+  return v >= 0 ? (uint64_t)v % q : (q - (uint64_t)(-(v + 1)) % q - 1) % q;
+}
+
+// weights as [F'][F][l1][2] (residue, Shoup) at the combination level
+static void ensure_weights(ckks_ctx* c, LayerPlan& lp) {
+  if (lp.w_dev) return;
+  const int l1 = lp.level_in + 1;
+  std::vector<uint64_t> h((size_t)lp.f_out * lp.f_in * l1 * 2);
+  for (int l = 0; l < lp.f_out; ++l)
+    for (int f = 0; f < lp.f_in; ++f)
+      for (int i = 0; i < l1; ++i) {
+        uint64_t q = c->mod[i];
+        uint64_t r = residue(lp.w_int[(size_t)f * lp.f_out + l], q);
+        size_t o = (((size_t)l * lp.f_in + f) * l1 + i) * 2;
+        h[o] = r;
+        h[o + 1] = shoup(r, q);
+      }
+  HIPCHECK(hipMalloc(&lp.w_dev, h.size() * 8));
+  HIPCHECK(hipMemcpy(lp.w_dev, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+}
+
+// residue-only copy [F'][F][l1] for the fused kernel
+static uint64_t* weights_residues(ckks_ctx* c, LayerPlan& lp, int slot) {
+  const int l1 = lp.level_in + 1;
+  const size_t n = (size_t)lp.f_out * lp.f_in * l1;
+  std::vector<uint64_t> h(n);
+  for (int l = 0; l < lp.f_out; ++l)
+    for (int f = 0; f < lp.f_in; ++f)
+      for (int i = 0; i < l1; ++i)
+        h[((size_t)l * lp.f_in + f) * l1 + i] = residue(lp.w_int[(size_t)f * lp.f_out + l], c->mod[i]);
+  uint64_t* d = (uint64_t*)c->buf(slot, n * 8);
+  HIPCHECK(hipMemcpyAsync(d, h.data(), n * 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHECK(hipStreamSynchronize(c->stream));
+  return d;
+}
+
+template <typename T>
+static T* upload_ptrs(ckks_ctx* c, const std::vector<T>& v, int slot) {
+  T* d = (T*)c->buf(slot, std::max<size_t>(8, v.size() * sizeof(T)));
+  HIPCHECK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  HIPCHECK(hipStreamSynchronize(c->stream));
+  return d;
+}
+
+// one key switch of a whole ciphertext (non-hoisted), out != in
+static void rotate_one(ckks_ctx* c, const ckks_keys* ek, const uint64_t* in, int level, int64_t step, uint64_t* out) {
+  const size_t N = c->N;
+  const int l1 = level + 1, ext = l1 + c->alpha;
+  const int nd = (l1 + c->alpha - 1) / c->alpha;
+  uint64_t g = galois_elt(c, step);
+  if (g == 1) {
+    copy_d2d(c, out, in, (size_t)2 * l1 * N * 8);
+    return;
+  }
+  auto it = ek->swk.find(g);
+  if (it == ek->swk.end()) FICGCN_THROW(ENOKEY_, "missing rotation key for step " + std::to_string(step));
+  uint64_t* D = (uint64_t*)c->buf(40, (size_t)nd * ext * N * 8);
+  uint64_t* acc = (uint64_t*)c->buf(41, (size_t)2 * ext * N * 8);
+  modup(c, in + (size_t)l1 * N, level, D);
+  keymac(c, acc, D, it->second, level, g);
+  moddown(c, acc, level, out, in, g, nullptr);
+}
+
+struct Hoisted {
+  ckks_ctx* c;
+  const ckks_keys* ek;
+  const uint64_t* in;
+  int level;
+  uint64_t* D;
+  void init(ckks_ctx* cc, const ckks_keys* k, const uint64_t* x, int lv, int slot) {
+    c = cc;
+    ek = k;
+    in = x;
+    level = lv;
+    const int l1 = lv + 1, ext = l1 + c->alpha, nd = (l1 + c->alpha - 1) / c->alpha;
+    D = (uint64_t*)c->buf(slot, (size_t)nd * ext * c->N * 8);
+    modup(c, x + (size_t)l1 * c->N, lv, D);
+  }
+  void rotate(int64_t step, uint64_t* out) {
+    const int l1 = level + 1, ext = l1 + c->alpha;
+    uint64_t g = galois_elt(c, step);
+    if (g == 1) {
+      copy_d2d(c, out, in, (size_t)2 * l1 * c->N * 8);
+      return;
+    }
+    auto it = ek->swk.find(g);
+    if (it == ek->swk.end()) FICGCN_THROW(ENOKEY_, "missing rotation key for step " + std::to_string(step));
+    uint64_t* acc = (uint64_t*)c->buf(43, (size_t)2 * ext * c->N * 8);
+    keymac(c, acc, D, it->second, level, g);
+    moddown(c, acc, level, out, in, g, nullptr);
+  }
+};
+
+static void aggregate(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, LayerPlan& lp, int g, const uint64_t* y,
+                      uint64_t* out, int mode) {
+  const size_t N = c->N;
+  const int lv = lp.level_agg, l1 = lv + 1;
+  const size_t ct_words = (size_t)2 * l1 * N;
+  const size_t ns = lp.shifts.size();
+  uint64_t* rt = (uint64_t*)c->buf(44, ct_words * 8);
+  zero_fill(c, out, ct_words);
+  auto mask = [&](size_t si) { return (const uint64_t*)lp.ops[(size_t)g * ns + si]; };
+  auto mac = [&](const uint64_t* ct, const uint64_t* pt) {
+    PtrList a{}, b{};
+    a.p[0] = ct;
+    b.p[0] = pt;
+    pmul_acc(c, out, a, b, 1, l1);
+  };
+  Hoisted h;
+  if (lp.family == 1) {
+    if (mode == 1) h.init(c, ek, y, lv, 42);
+    for (size_t si = 0; si < ns; ++si) {
+      int64_t d = lp.shifts[si];
+      if (d == 0) {
+        mac(y, mask(si));
+        continue;
+      }
+      if (mode == 1)
+        h.rotate(d, rt);
+      else
+        rotate_one(c, ek, y, lv, d, rt);
+      mac(rt, mask(si));
+    }
+  } else {
+    const int64_t G = lp.G;
+    std::set<int64_t> babies;
+    std::map<int64_t, std::vector<size_t>> giants;
+    for (size_t si = 0; si < ns; ++si) {
+      int64_t d = lp.shifts[si];
+      if (fmodp(d, G)) babies.insert(fmodp(d, G));
+      giants[fdiv(d, G)].push_back(si);
+    }
+    // baby rotations of y, kept for every giant step
+    std::map<int64_t, uint64_t*> rb;
+    uint64_t* bb = (uint64_t*)c->buf(45, std::max<size_t>(1, babies.size()) * ct_words * 8);
+    if (mode == 1 && !babies.empty()) h.init(c, ek, y, lv, 42);
+    size_t bi = 0;
+    for (int64_t b : babies) {
+      uint64_t* dst = bb + (bi++) * ct_words;
+      if (mode == 1)
+        h.rotate(b, dst);
+      else
+        rotate_one(c, ek, y, lv, b, dst);
+      rb[b] = dst;
+    }
+    uint64_t* inner = (uint64_t*)c->buf(46, ct_words * 8);
+    for (auto& kv : giants) {
+      int64_t gi = kv.first;
+      zero_fill(c, inner, ct_words);
+      for (size_t si : kv.second) {
+        int64_t b = fmodp(lp.shifts[si], G);
+        PtrList a{}, m{};
+        a.p[0] = b ? rb[b] : y;
+        m.p[0] = mask(si);
+        pmul_acc(c, inner, a, m, 1, l1);
+      }
+      if (gi != 0) {
+        rotate_one(c, ek, inner, lv, gi * G, rt);
+        add_inplace(c, out, rt, l1, 2);
+      } else {
+        add_inplace(c, out, inner, l1, 2);
+      }
+    }
+  }
+  rescale_inplace(c, out, lv);
+}
+
+void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const uint64_t* const* in, size_t n_in,
+               uint64_t* const* out, size_t n_out, int mode) {
+  LayerPlan& lp = p->layers[li];
+  const size_t N = c->N;
+  if ((int)n_in != lp.n_in_cts()) FICGCN_THROW(EPLAN_, "wrong number of input ciphertexts");
+  if ((int)n_out != lp.n_packed()) FICGCN_THROW(EPLAN_, "wrong number of output ciphertexts");
+  for (size_t i = 0; i < n_in; ++i)
+    if (!in[i]) FICGCN_THROW(EINVAL_, "null input ciphertext");
+  for (size_t i = 0; i < n_out; ++i)
+    if (!out[i]) FICGCN_THROW(EINVAL_, "null output ciphertext");
+  for (uint64_t* o : lp.ops)
+    if (!o) FICGCN_THROW(EPLAN_, "plan operands not encoded or loaded");
+  ensure_weights(c, lp);
+  const int lv = lp.level_in, l1 = lv + 1;
+  const size_t ct_words = (size_t)2 * l1 * N;
+  if (lp.act && !ek->swk.count(0)) FICGCN_THROW(ENOKEY_, "missing relinearisation key");
+  // layer result before the activation goes to `pre` (the outputs when no activation)
+  std::vector<uint64_t*> pre(n_out);
+  uint64_t* pre_block = nullptr;
+  if (lp.act) {
+    pre_block = (uint64_t*)c->buf(47, n_out * ct_words * 8);
+    for (size_t i = 0; i < n_out; ++i) pre[i] = pre_block + i * ct_words;
+  } else {
+    for (size_t i = 0; i < n_out; ++i) pre[i] = out[i];
+  }
+  if (lp.kind == 0) {
+    const int F = lp.f_in, K = lp.K;
+    if (mode == 1) {
+      std::vector<const uint64_t*> ins(in, in + n_in);
+      std::vector<const uint64_t*> pts(lp.ops.begin(), lp.ops.end());
+      uint64_t* const* od = upload_ptrs(c, pre, 30);
+      const uint64_t* const* idv = upload_ptrs(c, ins, 31);
+      const uint64_t* const* pdv = upload_ptrs(c, pts, 32);
+      uint64_t* wres = weights_residues(c, lp, 33);
+      comb_fused(c, od, idv, pdv, K, F, lp.f_out, lv, wres);
+    } else {
+      const int CH = 64;
+      uint64_t* Z = (uint64_t*)c->buf(34, (size_t)CH * ct_words * 8);
+      for (int l = 0; l < lp.f_out; ++l) zero_fill(c, pre[l], ct_words);
+      for (int f0 = 0; f0 < F; f0 += CH) {
+        int nf = std::min(CH, F - f0);
+        for (int f = 0; f < nf; ++f) {
+          uint64_t* z = Z + (size_t)f * ct_words;
+          zero_fill(c, z, ct_words);
+          for (int k0 = 0; k0 < K; k0 += PtrList::MAX) {
+            PtrList a{}, b{};
+            int nk = std::min((int)PtrList::MAX, K - k0);
+            for (int k = 0; k < nk; ++k) {
+              a.p[k] = in[(size_t)(k0 + k) * F + f0 + f];
+              b.p[k] = lp.ops[k0 + k];
+            }
+            pmul_acc(c, z, a, b, nk, l1);
+          }
+        }
+        for (int l = 0; l < lp.f_out; ++l)
+          for (int t0 = 0; t0 < nf; t0 += PtrList::MAX) {
+            PtrList a{};
+            int nt = std::min((int)PtrList::MAX, nf - t0);
+            for (int t = 0; t < nt; ++t) a.p[t] = Z + (size_t)(t0 + t) * ct_words;
+            smul_acc(c, pre[l], a, lp.w_dev + (((size_t)l * F + f0 + t0) * l1) * 2, nt, l1);
+          }
+      }
+    }
+    for (int l = 0; l < lp.f_out; ++l) {
+      rescale_inplace(c, pre[l], lv);
+      rescale_inplace(c, pre[l], lv - 1);
+    }
+  } else {
+    // combination at one column per ciphertext
+    const int F = lp.f_in;
+    uint64_t* cols = (uint64_t*)c->buf(35, (size_t)lp.f_out * ct_words * 8);
+    std::vector<uint64_t*> colp(lp.f_out);
+    for (int l = 0; l < lp.f_out; ++l) colp[l] = cols + (size_t)l * ct_words;
+    if (mode == 1) {
+      std::vector<const uint64_t*> ins(in, in + n_in);
+      uint64_t* const* od = upload_ptrs(c, colp, 30);
+      const uint64_t* const* idv = upload_ptrs(c, ins, 31);
+      uint64_t* wres = weights_residues(c, lp, 33);
+      comb_fused(c, od, idv, nullptr, 0, F, lp.f_out, lv, wres);
+    } else {
+      for (int l = 0; l < lp.f_out; ++l) {
+        zero_fill(c, colp[l], ct_words);
+        for (int t0 = 0; t0 < F; t0 += PtrList::MAX) {
+          PtrList a{};
+          int nt = std::min((int)PtrList::MAX, F - t0);
+          for (int t = 0; t < nt; ++t) a.p[t] = in[t0 + t];
+          smul_acc(c, colp[l], a, lp.w_dev + (((size_t)l * F + t0) * l1) * 2, nt, l1);
+        }
+      }
+    }
+    int lvc = lv;
+    for (int r = 0; r < lp.n_rescale_comb; ++r) {
+      for (int l = 0; l < lp.f_out; ++l) rescale_inplace(c, colp[l], lvc);
+      --lvc;
+    }
+    if (lvc != lp.level_agg) FICGCN_THROW(EPLAN_, "inconsistent schedule");
+    const size_t agg_words = (size_t)2 * (lvc + 1) * N;
+    uint64_t* y = (uint64_t*)c->buf(36, agg_words * 8);
+    uint64_t* rt = (uint64_t*)c->buf(37, agg_words * 8);
+    for (int g = 0; g < lp.n_packed(); ++g) {
+      copy_d2d(c, y, colp[(size_t)g * lp.t], agg_words * 8);
+      for (int l = g * lp.t + 1; l < std::min(lp.f_out, (g + 1) * lp.t); ++l) {
+        rotate_one(c, ek, colp[l], lvc, -(int64_t)(l % lp.t) * lp.B, rt);
+        add_inplace(c, y, rt, lvc + 1, 2);
+      }
+      aggregate(c, ek, p, lp, g, y, pre[g], mode);
+    }
+  }
+  if (lp.act) {
+    const int lo = lp.level_out;
+    for (size_t i = 0; i < n_out; ++i) {
+      // out = pre^2 with relinearisation at the layer's output level
+      const size_t l1o = lo + 1, ext = l1o + c->alpha;
+      const int nd = (int)((l1o + c->alpha - 1) / c->alpha);
+      uint64_t* d = (uint64_t*)c->buf(48, 3 * l1o * N * 8);
+      tensor(c, pre[i], pre[i], d, lo);
+      uint64_t* D = (uint64_t*)c->buf(40, (size_t)nd * ext * N * 8);
+      uint64_t* acc = (uint64_t*)c->buf(41, 2 * ext * N * 8);
+      modup(c, d + 2 * l1o * N, lo, D);
+      keymac(c, acc, D, ek->swk.at(0), lo, 1);
+      moddown(c, acc, lo, out[i], d, 1, d + l1o * N);
+    }
+  }
+}
+
+}  // namespace ficgcn
+
+using namespace ficgcn;
+
+static ficgcn_status plan_guard_status(const Error& e) {
+  set_error(e.msg);
+  return (ficgcn_status)e.code;
+}
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                   \
+  return FICGCN_OK;                                 \
+  }                                                 \
+  catch (const Error& e) { return plan_guard_status(e); } \
+  catch (const std::exception& e) {                 \
+    set_error(e.what());                            \
+    return FICGCN_EINVAL;                           \
+  }
+
+extern "C" {
+
+ficgcn_status ficgcn_plan_create(ckks_ctx* ctx, const int32_t* rowptr, const int32_t* col, const double* val,
+                                 uint32_t n_v, const uint32_t* dims, uint32_t n_layers, const double* const* weights,
+                                 const ficgcn_plan_opts* opts, ficgcn_plan** out) {
+  GUARD_BEGIN
+  if (!ctx || !rowptr || !col || !val || !dims || !weights || !opts || !out || n_v == 0 || n_layers == 0)
+    FICGCN_THROW(EINVAL_, "null or empty argument");
+  for (uint32_t l = 0; l < n_layers; ++l)
+    if (!weights[l] || dims[l] == 0 || dims[l + 1] == 0) FICGCN_THROW(EINVAL_, "bad layer dimensions or weights");
+  std::unique_ptr<ficgcn_plan> p(new ficgcn_plan());
+  p->ctx = ctx;
+  p->n_v = (int)n_v;
+  p->rowptr.assign(rowptr, rowptr + n_v + 1);
+  if (p->rowptr[0] != 0) FICGCN_THROW(EINVAL_, "rowptr[0] must be 0");
+  for (uint32_t v = 0; v < n_v; ++v)
+    if (p->rowptr[v + 1] < p->rowptr[v]) FICGCN_THROW(EINVAL_, "rowptr not monotone");
+  const int nnz = p->rowptr[n_v];
+  p->col.assign(col, col + nnz);
+  p->val.assign(val, val + nnz);
+  for (uint32_t v = 0; v < n_v; ++v) {
+    // rows sorted by column, as the routing and copy order read them
+    std::vector<std::pair<int32_t, double>> r;
+    for (int e = p->rowptr[v]; e < p->rowptr[v + 1]; ++e) {
+      if (p->col[e] < 0 || p->col[e] >= (int32_t)n_v) FICGCN_THROW(EINVAL_, "column index out of range");
+      r.push_back({p->col[e], p->val[e]});
+    }
+    std::sort(r.begin(), r.end());
+    for (size_t i = 0; i + 1 < r.size(); ++i)
+      if (r[i].first == r[i + 1].first) FICGCN_THROW(EINVAL_, "duplicate column in a row");
+    for (size_t i = 0; i < r.size(); ++i) {
+      p->col[p->rowptr[v] + i] = r[i].first;
+      p->val[p->rowptr[v] + i] = r[i].second;
+    }
+  }
+  build_plan(ctx, p.get(), dims, n_layers, weights, *opts);
+  for (auto& lp : p->layers) lp.ops.assign(plan_operand_count(p.get(), (int)(&lp - &p->layers[0])), nullptr);
+  *out = p.release();
+  GUARD_END
+}
+
+void ficgcn_plan_destroy(ficgcn_plan* plan) { delete plan; }
+
+ficgcn_status ficgcn_plan_node_order(const ficgcn_plan* plan, int32_t* pi_out) {
+  GUARD_BEGIN
+  if (!plan || !pi_out) FICGCN_THROW(EINVAL_, "null argument");
+  std::memcpy(pi_out, plan->pi.data(), plan->pi.size() * 4);
+  GUARD_END
+}
+
+ficgcn_status ficgcn_plan_copy_sources(const ficgcn_plan* plan, uint32_t layer, int32_t* src_out) {
+  GUARD_BEGIN
+  if (!plan || !src_out || layer >= plan->layers.size()) FICGCN_THROW(EINVAL_, "bad argument");
+  const LayerPlan& lp = plan->layers[layer];
+  if (lp.kind != 0) FICGCN_THROW(EPLAN_, "not an Inter-CA layer");
+  std::memcpy(src_out, lp.copy_src.data(), lp.copy_src.size() * 4);
+  GUARD_END
+}
+
+ficgcn_status ficgcn_plan_rot_steps(const ficgcn_plan* plan, int64_t* steps_out, size_t cap, size_t* n_out) {
+  GUARD_BEGIN
+  if (!plan || !n_out) FICGCN_THROW(EINVAL_, "null argument");
+  *n_out = plan->rot_steps.size();
+  for (size_t i = 0; i < plan->rot_steps.size() && i < cap && steps_out; ++i) steps_out[i] = plan->rot_steps[i];
+  GUARD_END
+}
+
+ficgcn_status ficgcn_plan_info(const ficgcn_plan* plan, int64_t* info_out, double* scales_out, uint32_t* n_layers) {
+  GUARD_BEGIN
+  if (!plan || !n_layers) FICGCN_THROW(EINVAL_, "null argument");
+  *n_layers = (uint32_t)plan->layers.size();
+  for (size_t li = 0; li < plan->layers.size(); ++li) {
+    const LayerPlan& lp = plan->layers[li];
+    if (info_out) {
+      int64_t* o = info_out + li * 13;
+      o[0] = lp.kind;
+      o[1] = lp.f_in;
+      o[2] = lp.f_out;
+      o[3] = lp.K;
+      o[4] = lp.t;
+      o[5] = lp.B;
+      o[6] = lp.family;
+      o[7] = lp.G;
+      o[8] = (int64_t)lp.shifts.size();
+      o[9] = lp.level_in;
+      o[10] = lp.level_out;
+      o[11] = lp.n_in_cts();
+      o[12] = lp.n_packed();
+    }
+    if (scales_out) {
+      scales_out[li * 3] = lp.scale_in;
+      scales_out[li * 3 + 1] = lp.scale_out;
+      scales_out[li * 3 + 2] = lp.sW;
+    }
+  }
+  GUARD_END
+}
+
+ficgcn_status ficgcn_plan_shifts(const ficgcn_plan* plan, uint32_t layer, int64_t* out, size_t cap, size_t* n_out) {
+  GUARD_BEGIN
+  if (!plan || !n_out || layer >= plan->layers.size()) FICGCN_THROW(EINVAL_, "bad argument");
+  const auto& s = plan->layers[layer].shifts;
+  *n_out = s.size();
+  for (size_t i = 0; i < s.size() && i < cap && out; ++i) out[i] = s[i];
+  GUARD_END
+}
+
+ficgcn_status ficgcn_plan_weights_int(const ficgcn_plan* plan, uint32_t layer, int64_t* out) {
+  GUARD_BEGIN
+  if (!plan || !out || layer >= plan->layers.size()) FICGCN_THROW(EINVAL_, "bad argument");
+  const auto& w = plan->layers[layer].w_int;
+  std::memcpy(out, w.data(), w.size() * 8);
+  GUARD_END
+}
+
+ficgcn_status ficgcn_plan_operand_count(const ficgcn_plan* plan, uint32_t layer, size_t* n_out) {
+  GUARD_BEGIN
+  if (!plan || !n_out || layer >= plan->layers.size()) FICGCN_THROW(EINVAL_, "bad argument");
+  *n_out = plan_operand_count(plan, (int)layer);
+  GUARD_END
+}
+
+ficgcn_status ficgcn_plan_operand_slots(const ficgcn_plan* plan, uint32_t layer, size_t i, double* slots_out) {
+  GUARD_BEGIN
+  if (!plan || !slots_out || layer >= plan->layers.size() || i >= plan_operand_count(plan, (int)layer))
+    FICGCN_THROW(EINVAL_, "bad argument");
+  std::vector<double> v;
+  plan_operand_slots(plan, (int)layer, i, v);
+  std::memcpy(slots_out, v.data(), v.size() * 8);
+  GUARD_END
+}
+
+static void ensure_ops_block(ckks_ctx* ctx, LayerPlan& lp) {
+  if (lp.ops_block) return;
+  const size_t per = (size_t)(lp.op_level + 1) * ctx->N;
+  if (hipMalloc(&lp.ops_block, std::max<size_t>(1, lp.ops.size()) * per * 8) != hipSuccess)
+    FICGCN_THROW(ENOMEM_, "operand allocation failed");
+}
+
+ficgcn_status ficgcn_plan_encode(ckks_ctx* ctx, ficgcn_plan* plan) {
+  GUARD_BEGIN
+  if (!ctx || !plan) FICGCN_THROW(EINVAL_, "null argument");
+  ensure_device(ctx);
+  for (size_t li = 0; li < plan->layers.size(); ++li) {
+    LayerPlan& lp = plan->layers[li];
+    ensure_ops_block(ctx, lp);
+    const size_t n = lp.ops.size();
+    const size_t per = (size_t)(lp.op_level + 1) * ctx->N;
+    const size_t chunk = 256;
+    std::vector<double> all;
+    for (size_t b0 = 0; b0 < n; b0 += chunk) {
+      size_t nb = std::min(chunk, n - b0);
+      all.assign(nb * plan->M, 0.0);
+      std::vector<double> v;
+      for (size_t b = 0; b < nb; ++b) {
+        plan_operand_slots(plan, (int)li, b0 + b, v);
+        std::memcpy(all.data() + b * plan->M, v.data(), plan->M * 8);
+      }
+      ficgcn_status st = ckks_encode_batch(ctx, all.data(), nb, plan->M, lp.op_scale, lp.op_level,
+                                           lp.ops_block + b0 * per);
+      if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
+      for (size_t b = 0; b < nb; ++b) lp.ops[b0 + b] = lp.ops_block + (b0 + b) * per;
+    }
+  }
+  GUARD_END
+}
+
+ficgcn_status ficgcn_plan_load_operand(ckks_ctx* ctx, ficgcn_plan* plan, uint32_t layer, size_t i,
+                                       const uint64_t* host_coeffs) {
+  GUARD_BEGIN
+  if (!ctx || !plan || !host_coeffs || layer >= plan->layers.size()) FICGCN_THROW(EINVAL_, "bad argument");
+  ensure_device(ctx);
+  LayerPlan& lp = plan->layers[layer];
+  if (i >= lp.ops.size()) FICGCN_THROW(EINVAL_, "operand index out of range");
+  ensure_ops_block(ctx, lp);
+  const size_t per = (size_t)(lp.op_level + 1) * ctx->N;
+  uint64_t* dst = lp.ops_block + i * per;
+  ficgcn_status st = ckks_pt_load(ctx, host_coeffs, lp.op_level, dst);
+  if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
+  lp.ops[i] = dst;
+  GUARD_END
+}
+
+ficgcn_status ficgcn_gcn_layer(ckks_ctx* ctx, const ckks_keys* eval_keys, const ficgcn_plan* plan, uint32_t layer,
+                               const uint64_t* const* in_cts, size_t n_in, uint64_t* const* out_cts, size_t n_out,
+                               int32_t mode) {
+  GUARD_BEGIN
+  if (!ctx || !eval_keys || !plan || !in_cts || !out_cts) FICGCN_THROW(EINVAL_, "null argument");
+  if (layer >= plan->layers.size()) FICGCN_THROW(EINVAL_, "layer index out of range");
+  if (mode != 0 && mode != 1) FICGCN_THROW(EINVAL_, "mode must be 0 (plain) or 1 (batched)");
+  ensure_device(ctx);
+  run_layer(ctx, eval_keys, const_cast<ficgcn_plan*>(plan), (int)layer, in_cts, n_in, out_cts, n_out, mode);
+  GUARD_END
+}
+
+}  // extern "C"

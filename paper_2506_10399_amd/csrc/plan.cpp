@@ -1,0 +1,456 @@
+// Planner of the encrypted GCN (host C++).
+//
+// Packing (paper Sec. 3.2, App. B): t feature columns per ciphertext, column
+// c of a ciphertext in slots [c*B, (c+1)*B), B = M/t, node v at c*B + pi(v).
+// Aggregation mode (Sec. 3.3.2): the first layer is Inter-CA over the
+// client's neighbour copies; later layers are SpIntra-CA: combination first
+// (one column per ciphertext), packing of t = min(pow2(F'), M / pow2(n_v))
+// columns, then routing of every nonzero A_vu by its shift pi(u) - pi(v) in
+// the diagonal form (one rotation + mask per distinct shift, all rotations
+// hoisted on one ModUp) or the baby-step/giant-step form.
+// Node order (Sec. 3.4, Alg. 1): sibling-BFS regions of at most TH nodes
+// (highest degree first; when the BFS runs dry the region continues from the
+// highest-degree node left), interleaved round-robin (an exhausted region's
+// turn takes a blank while blanks last), then greedy placement in BFS order
+// where each node takes the free slot of its region adding the fewest shifts
+// not yet used (lowest slot on ties).  With t = 1 shifts are taken mod M in
+// (-M/2, M/2] (AOO, Sec. 3.3.1).
+// Scale schedule: the scale is a double tracked through a fixed sequence of
+// IEEE operations (first layer: sP = q_l, sW = q_{l-1}, two rescales; later
+// layers: sW = (q_l [* q_{l-1}] * Delta) / s with one [two] rescale(s),
+// masks at sM = q_l, one rescale; x^2 leaves its rescale to the consumer).
+#include <algorithm>
+#include <cmath>
+#include <deque>
+#include <set>
+
+#include "../../include/ficgcn.h"
+#include "plan.h"
+
+namespace ficgcn {
+
+static int64_t fdiv(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+  return q;
+}
+static int64_t fmod_(int64_t a, int64_t b) { return a - fdiv(a, b) * b; }
+
+static int next_pow2(int x) {
+  int p = 1;
+  while (p < x) p *= 2;
+  return p;
+}
+
+static int64_t reduce_shift(int64_t d, int64_t M, bool wrap) {
+  if (!wrap) return d;
+  int64_t r = fmod_(d, M);
+  return r > M / 2 ? r - M : r;
+}
+
+struct Rows {
+  int n;
+  const std::vector<int32_t>& rp;
+  const std::vector<int32_t>& col;
+};
+
+static std::vector<std::vector<int>> regions_of(const ficgcn_plan* p, int TH) {
+  const int n = p->n_v;
+  std::vector<std::set<int>> sup(n), sib(n);
+  for (int v = 0; v < n; ++v) {
+    for (int e = p->rowptr[v]; e < p->rowptr[v + 1]; ++e) {
+      int u = p->col[e];
+      if (u != v) {
+        sup[v].insert(u);
+        sup[u].insert(v);
+      }
+      for (int e2 = p->rowptr[v]; e2 < p->rowptr[v + 1]; ++e2) sib[u].insert(p->col[e2]);
+    }
+  }
+  std::vector<std::vector<int>> sibv(n);
+  for (int x = 0; x < n; ++x) {
+    sib[x].erase(x);
+    sibv[x].assign(sib[x].begin(), sib[x].end());
+  }
+  std::vector<int> order(n);
+  for (int v = 0; v < n; ++v) order[v] = v;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (sup[a].size() != sup[b].size()) return sup[a].size() > sup[b].size();
+    return a < b;
+  });
+  std::vector<char> remaining(n, 1);
+  std::vector<std::vector<int>> regions;
+  size_t ptr = 0;
+  int n_left = n;
+  while (n_left > 0) {
+    std::vector<int> region;
+    std::set<int> visited;
+    while ((int)region.size() < TH && n_left > 0) {
+      while (!remaining[order[ptr]]) ++ptr;
+      int start = order[ptr];
+      std::deque<int> q{start};
+      visited.insert(start);
+      while (!q.empty() && (int)region.size() < TH) {
+        int x = q.front();
+        q.pop_front();
+        region.push_back(x);
+        remaining[x] = 0;
+        --n_left;
+        for (int w : sibv[x])
+          if (remaining[w] && !visited.count(w)) {
+            visited.insert(w);
+            q.push_back(w);
+          }
+      }
+    }
+    regions.push_back(region);
+  }
+  return regions;
+}
+
+static std::vector<std::vector<int>> interleave(const std::vector<int>& sizes, int B) {
+  const int R = (int)sizes.size();
+  std::vector<int> left(sizes);
+  int total = 0;
+  for (int s : sizes) total += s;
+  int blanks = B - total;
+  if (blanks < 0) FICGCN_THROW(EPLAN_, "graph does not fit the column block");
+  std::vector<std::vector<int>> slots(R);
+  int j = 0;
+  auto any = [&] {
+    for (int x : left)
+      if (x > 0) return true;
+    return false;
+  };
+  while (any()) {
+    for (int r = 0; r < R; ++r) {
+      if (left[r] > 0) {
+        slots[r].push_back(j++);
+        --left[r];
+      } else if (blanks > 0) {
+        --blanks;
+        ++j;
+      }
+    }
+  }
+  return slots;
+}
+
+static void place(ficgcn_plan* p, const std::vector<std::vector<int>>& regions,
+                  const std::vector<std::vector<int>>& slots, bool wrap) {
+  const int n = p->n_v;
+  const int64_t M = p->M;
+  std::vector<std::vector<int>> out_nb(n), in_nb(n);
+  for (int v = 0; v < n; ++v)
+    for (int e = p->rowptr[v]; e < p->rowptr[v + 1]; ++e) {
+      int u = p->col[e];
+      if (u != v) {
+        out_nb[v].push_back(u);
+        in_nb[u].push_back(v);
+      }
+    }
+  p->pi.assign(n, -1);
+  // shifts lie in (-M, M): index d + M
+  std::vector<char> used(2 * M + 1, 0);
+  std::vector<int> stamp(2 * M + 1, -1);
+  auto red = [&](int64_t d) { return reduce_shift(d, M, wrap); };
+  auto add_shifts = [&](int x) {
+    for (int u : out_nb[x])
+      if (p->pi[u] >= 0) used[red((int64_t)p->pi[u] - p->pi[x]) + M] = 1;
+    for (int v : in_nb[x])
+      if (p->pi[v] >= 0) used[red((int64_t)p->pi[x] - p->pi[v]) + M] = 1;
+  };
+  int stamp_id = 0;
+  for (size_t r = 0; r < regions.size(); ++r) {
+    const std::vector<int>& reg = regions[r];
+    const std::vector<int>& sl = slots[r];
+    std::vector<char> taken(sl.size(), 0);
+    p->pi[reg[0]] = sl[0];
+    taken[0] = 1;
+    add_shifts(reg[0]);
+    for (size_t idx = 1; idx < reg.size(); ++idx) {
+      int x = reg[idx];
+      std::vector<int> pu, pv;
+      for (int u : out_nb[x])
+        if (p->pi[u] >= 0) pu.push_back(p->pi[u]);
+      for (int v : in_nb[x])
+        if (p->pi[v] >= 0) pv.push_back(p->pi[v]);
+      int best = -1;
+      long best_cost = -1;
+      for (size_t k = 0; k < sl.size(); ++k) {
+        if (taken[k]) continue;
+        int64_t pos = sl[k];
+        long cost = 0;
+        if (!pu.empty() || !pv.empty()) {
+          ++stamp_id;
+          for (int a : pu) {
+            int64_t d = red(a - pos) + M;
+            if (!used[d] && stamp[d] != stamp_id) {
+              stamp[d] = stamp_id;
+              ++cost;
+            }
+          }
+          for (int b : pv) {
+            int64_t d = red(pos - b) + M;
+            if (!used[d] && stamp[d] != stamp_id) {
+              stamp[d] = stamp_id;
+              ++cost;
+            }
+          }
+        }
+        if (best < 0 || cost < best_cost) {
+          best = (int)k;
+          best_cost = cost;
+          if (cost == 0) break;   // lowest free slot with zero cost
+        }
+      }
+      p->pi[x] = sl[best];
+      taken[best] = 1;
+      add_shifts(x);
+    }
+  }
+}
+
+static void bsgs_split(const std::vector<int64_t>& shifts, int B, int& G_out, int& c_out) {
+  int bestc = -1, bestG = 1;
+  for (int64_t G = 1; G <= std::max(B, 1); G *= 2) {
+    std::set<int64_t> babies, giants;
+    for (int64_t d : shifts) {
+      int64_t b = fmod_(d, G), g = fdiv(d, G);
+      if (b) babies.insert(b);
+      if (g) giants.insert(g);
+    }
+    int c = (int)(babies.size() + giants.size());
+    if (bestc < 0 || c < bestc) {
+      bestc = c;
+      bestG = (int)G;
+    }
+  }
+  G_out = bestG;
+  c_out = bestc;
+}
+
+static std::vector<int64_t> rotation_steps_of(const LayerPlan& lp) {
+  std::set<int64_t> s;
+  if (lp.family == 1) {
+    for (int64_t d : lp.shifts)
+      if (d) s.insert(d);
+  } else {
+    for (int64_t d : lp.shifts) {
+      int64_t b = fmod_(d, lp.G), g = fdiv(d, lp.G) * lp.G;
+      if (b) s.insert(b);
+      if (g) s.insert(g);
+    }
+  }
+  return std::vector<int64_t>(s.begin(), s.end());
+}
+
+static void schedule(ckks_ctx* c, ficgcn_plan* p) {
+  const double delta = std::ldexp(1.0, c->log_scale);
+  double s = delta;
+  int lv = c->L - 1;
+  bool pending = false;
+  for (LayerPlan& lp : p->layers) {
+    lp.level_in = lv;
+    lp.scale_in = s;
+    if (lp.kind == 0) {
+      if (lv < 2) FICGCN_THROW(EPLAN_, "not enough levels for the Inter-CA layer");
+      lp.sP = (double)c->mod[lv];
+      lp.sW = (double)c->mod[lv - 1];
+      s = s * lp.sP;
+      s = s * lp.sW;
+      s = s / (double)c->mod[lv];
+      s = s / (double)c->mod[lv - 1];
+      lv -= 2;
+      lp.op_level = lp.level_in;
+      lp.op_scale = lp.sP;
+    } else {
+      lp.n_rescale_comb = pending ? 2 : 1;
+      if (lv < lp.n_rescale_comb + 1) FICGCN_THROW(EPLAN_, "not enough levels for the SpIntra-CA layer");
+      if (pending) {
+        lp.sW = (((double)c->mod[lv] * (double)c->mod[lv - 1]) * delta) / s;
+        s = s * lp.sW;
+        s = s / (double)c->mod[lv];
+        s = s / (double)c->mod[lv - 1];
+        lv -= 2;
+      } else {
+        lp.sW = ((double)c->mod[lv] * delta) / s;
+        s = s * lp.sW;
+        s = s / (double)c->mod[lv];
+        lv -= 1;
+      }
+      lp.level_agg = lv;
+      lp.scale_agg = s;
+      lp.sM = (double)c->mod[lv];
+      s = s * lp.sM;
+      s = s / (double)c->mod[lv];
+      lv -= 1;
+      lp.op_level = lp.level_agg;
+      lp.op_scale = lp.sM;
+    }
+    pending = false;
+    if (lp.act) {
+      s = s * s;
+      pending = true;
+    }
+    lp.squared_out = pending;
+    lp.level_out = lv;
+    lp.scale_out = s;
+  }
+}
+
+size_t plan_operand_count(const ficgcn_plan* p, int li) {
+  const LayerPlan& lp = p->layers[li];
+  return lp.kind == 0 ? (size_t)lp.K : (size_t)lp.n_packed() * lp.shifts.size();
+}
+
+void plan_operand_slots(const ficgcn_plan* p, int li, size_t i, std::vector<double>& out) {
+  const LayerPlan& lp = p->layers[li];
+  const int M = p->M, n = p->n_v;
+  out.assign(M, 0.0);
+  if (lp.kind == 0) {
+    for (int v = 0; v < n; ++v)
+      if (lp.copy_src[i * n + v] >= 0) out[p->pi[v]] = lp.copy_val[i * n + v];
+    return;
+  }
+  const size_t ns = lp.shifts.size();
+  const int g = (int)(i / ns);
+  const int64_t delta = lp.shifts[i % ns];
+  const int n_cols = std::min(lp.t, lp.f_out - g * lp.t);
+  const bool wrap = lp.B == M;
+  std::vector<double> mask(M, 0.0);
+  for (int v = 0; v < n; ++v)
+    for (int e = p->rowptr[v]; e < p->rowptr[v + 1]; ++e) {
+      int u = p->col[e];
+      if (reduce_shift((int64_t)p->pi[u] - p->pi[v], M, wrap) != delta) continue;
+      for (int cc = 0; cc < n_cols; ++cc) mask[(size_t)cc * lp.B + p->pi[v]] = p->val[e];
+    }
+  if (lp.family == 2) {
+    // pre-rotated by -g*G: out[i] = mask[(i - gG) mod M]
+    int64_t gG = fdiv(delta, lp.G) * lp.G;
+    for (int64_t k = 0; k < M; ++k) out[k] = mask[fmod_(k - gG, M)];
+  } else {
+    out = mask;
+  }
+}
+
+}  // namespace ficgcn
+
+using namespace ficgcn;
+
+ficgcn_plan::~ficgcn_plan() {
+  if (ctx && ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  for (auto& lp : layers) {
+    if (lp.ops_block) (void)hipFree(lp.ops_block);
+    if (lp.w_dev) (void)hipFree(lp.w_dev);
+  }
+}
+
+namespace ficgcn {
+
+void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_layers, const double* const* weights,
+                const ficgcn_plan_opts& o) {
+  const int n = p->n_v;
+  const int M = c->N / 2;
+  p->M = M;
+  if (o.first_mode == 1 && n_layers > 1)
+    FICGCN_THROW(EPLAN_, "a SpIntra-CA first layer is only supported for one-layer models");
+  std::vector<int> spin_f;
+  for (uint32_t i = 0; i < n_layers; ++i)
+    if (i > 0 || o.first_mode == 1) spin_f.push_back((int)dims[i + 1]);
+  int t_pack = 1;
+  if (!spin_f.empty()) {
+    t_pack = M / next_pow2(n);
+    for (int f : spin_f) t_pack = std::min(t_pack, next_pow2(f));
+  }
+  if (t_pack < 1) FICGCN_THROW(EPLAN_, "graph larger than the slot count");
+  const int B = M / t_pack;
+  p->B_pi = B;
+  const int TH = o.TH > 0 ? o.TH : (n < 10000 ? 1024 : 4096);
+  if (o.use_noo) {
+    p->regions = regions_of(p, TH);
+    std::vector<int> sizes;
+    for (auto& r : p->regions) sizes.push_back((int)r.size());
+    auto slots = interleave(sizes, B);
+    place(p, p->regions, slots, B == M);
+  } else {
+    if (n > B) FICGCN_THROW(EPLAN_, "graph does not fit the column block");
+    p->pi.resize(n);
+    for (int v = 0; v < n; ++v) p->pi[v] = v;
+    p->regions = {std::vector<int>()};
+    for (int v = 0; v < n; ++v) p->regions[0].push_back(v);
+  }
+  p->layers.clear();
+  for (uint32_t li = 0; li < n_layers; ++li) {
+    LayerPlan lp;
+    lp.f_in = (int)dims[li];
+    lp.f_out = (int)dims[li + 1];
+    lp.act = o.activation != 0;
+    lp.kind = (li == 0 && o.first_mode == 0) ? 0 : 1;
+    if (lp.kind == 0) {
+      int K = 0;
+      for (int v = 0; v < n; ++v) {
+        int off = 0;
+        for (int e = p->rowptr[v]; e < p->rowptr[v + 1]; ++e) off += p->col[e] != v;
+        K = std::max(K, off);
+      }
+      lp.K = K + 1;
+      lp.copy_src.assign((size_t)lp.K * n, -1);
+      lp.copy_val.assign((size_t)lp.K * n, 0.0);
+      for (int v = 0; v < n; ++v) {
+        int k = 1;
+        for (int e = p->rowptr[v]; e < p->rowptr[v + 1]; ++e) {
+          int u = p->col[e];
+          if (u == v) {
+            lp.copy_src[v] = v;
+            lp.copy_val[v] = p->val[e];
+          } else {
+            lp.copy_src[(size_t)k * n + v] = u;
+            lp.copy_val[(size_t)k * n + v] = p->val[e];
+            ++k;
+          }
+        }
+      }
+    } else {
+      lp.t = std::min(next_pow2(lp.f_out), M / next_pow2(n));
+      lp.B = M / lp.t;
+      const bool wrap = lp.B == M;
+      std::set<int64_t> sh;
+      for (int v = 0; v < n; ++v)
+        for (int e = p->rowptr[v]; e < p->rowptr[v + 1]; ++e)
+          sh.insert(reduce_shift((int64_t)p->pi[p->col[e]] - p->pi[v], M, wrap));
+      lp.shifts.assign(sh.begin(), sh.end());
+      int c2;
+      bsgs_split(lp.shifts, lp.B, lp.G, c2);
+      int c1 = (int)lp.shifts.size() - (sh.count(0) ? 1 : 0);
+      lp.family = o.family == 1 ? 1 : o.family == 2 ? 2 : (c2 < c1 ? 2 : 1);
+      std::set<int64_t> pk;
+      for (int l = 0; l < lp.f_out; ++l)
+        if (l % lp.t) pk.insert(-(int64_t)(l % lp.t) * lp.B);
+      lp.pack_steps.assign(pk.begin(), pk.end());
+    }
+    p->layers.push_back(lp);
+  }
+  schedule(c, p);
+  for (uint32_t li = 0; li < n_layers; ++li) {
+    LayerPlan& lp = p->layers[li];
+    lp.w_int.resize((size_t)lp.f_in * lp.f_out);
+    for (size_t i = 0; i < lp.w_int.size(); ++i) {
+      double x = weights[li][i] * lp.sW;
+      if (!(std::fabs(x) < 9.2e18)) FICGCN_THROW(ESCALE_, "weight times scale exceeds 63 bits");
+      lp.w_int[i] = (int64_t)std::nearbyint(x);
+    }
+  }
+  std::set<int64_t> steps;
+  for (auto& lp : p->layers) {
+    if (lp.kind != 1) continue;
+    for (int64_t s : lp.pack_steps) steps.insert(fmod_(s, M));
+    for (int64_t s : rotation_steps_of(lp)) steps.insert(fmod_(s, M));
+  }
+  steps.erase(0);
+  p->rot_steps.assign(steps.begin(), steps.end());
+}
+
+std::vector<int64_t> layer_rotation_steps(const LayerPlan& lp) { return rotation_steps_of(lp); }
+
+}  // namespace ficgcn

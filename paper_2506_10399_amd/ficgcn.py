@@ -1,0 +1,396 @@
+"""Python binding of libficgcn.so (the C ABI of include/ficgcn.h).
+
+Argument marshalling only: every step runs in the HIP library.  Device
+buffers are torch tensors (int64 storage holding uint64 words); host arrays
+are numpy arrays.  Importing this module does not load the library; the
+first call does, and raises FicgcnError if libficgcn.so is missing -- there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("FICGCN_LIB", os.path.join(HERE, "libficgcn.so"))
+
+_lib = None
+
+c_u64p = ctypes.POINTER(ctypes.c_uint64)
+c_vp = ctypes.c_void_p
+
+
+class FicgcnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("ficgcn status %d: %s" % (status, msg))
+        self.status = status
+
+
+class CkksParams(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("q_bits", ctypes.c_uint32),
+                ("n_p", ctypes.c_uint32), ("p_bits", ctypes.c_uint32), ("log_scale", ctypes.c_uint32)]
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("first_mode", ctypes.c_int32), ("use_noo", ctypes.c_int32), ("family", ctypes.c_int32),
+                ("TH", ctypes.c_int32), ("activation", ctypes.c_int32)]
+
+
+# name -> (restype, argtypes); every status-returning call returns c_int
+_SIGS = {
+    "ficgcn_last_error": (ctypes.c_char_p, []),
+    "ckks_context_create": (ctypes.c_int, [ctypes.POINTER(CkksParams), ctypes.POINTER(c_vp)]),
+    "ckks_ctx_destroy": (None, [c_vp]),
+    "ckks_ctx_set_stream": (ctypes.c_int, [c_vp, c_vp]),
+    "ckks_ctx_moduli": (ctypes.c_int, [c_vp, c_vp]),
+    "ckks_galois_element": (ctypes.c_int, [c_vp, ctypes.c_int64, c_u64p]),
+    "ckks_sync": (ctypes.c_int, [c_vp]),
+    "ckks_keygen": (ctypes.c_int, [c_vp, ctypes.c_uint64, c_vp, ctypes.c_size_t, ctypes.c_int,
+                                   ctypes.POINTER(c_vp), ctypes.POINTER(c_vp)]),
+    "ckks_keys_tags": (ctypes.c_int, [c_vp, c_vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    "ckks_keys_export": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint64, c_vp]),
+    "ckks_keys_import": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint64, c_vp]),
+    "ckks_keys_create_empty": (ctypes.c_int, [c_vp, ctypes.POINTER(c_vp)]),
+    "ckks_keys_destroy": (None, [c_vp]),
+    "ckks_encode": (ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_size_t, ctypes.c_double, ctypes.c_uint32, c_vp]),
+    "ckks_encode_batch": (ctypes.c_int, [c_vp, c_vp, ctypes.c_size_t, ctypes.c_size_t, ctypes.c_double,
+                                         ctypes.c_uint32, c_vp]),
+    "ckks_pt_load": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, c_vp]),
+    "ckks_encrypt": (ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, c_vp]),
+    "ckks_decrypt": (ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_uint32, ctypes.c_double, c_vp, c_vp,
+                                    ctypes.c_size_t]),
+    "ckks_ct_load": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, c_vp]),
+    "ckks_poly_store": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, ctypes.c_uint32, c_vp]),
+    "ckks_ntt": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]),
+    "ckks_rotate_hoisted": (ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_uint32, c_vp, ctypes.c_size_t, c_vp]),
+    "ckks_pt_mul_acc": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, c_vp, c_vp, ctypes.c_size_t]),
+    "ckks_scalar_mul_acc": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, c_vp, c_vp, ctypes.c_size_t]),
+    "ckks_add": (ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_uint32]),
+    "ckks_rescale": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32]),
+    "ckks_mul_relin": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.c_uint32, c_vp]),
+    "ficgcn_plan_create": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.c_uint32, c_vp, ctypes.c_uint32, c_vp,
+                                          ctypes.POINTER(PlanOpts), ctypes.POINTER(c_vp)]),
+    "ficgcn_plan_destroy": (None, [c_vp]),
+    "ficgcn_plan_node_order": (ctypes.c_int, [c_vp, c_vp]),
+    "ficgcn_plan_copy_sources": (ctypes.c_int, [c_vp, ctypes.c_uint32, c_vp]),
+    "ficgcn_plan_rot_steps": (ctypes.c_int, [c_vp, c_vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    "ficgcn_plan_info": (ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.POINTER(ctypes.c_uint32)]),
+    "ficgcn_plan_shifts": (ctypes.c_int, [c_vp, ctypes.c_uint32, c_vp, ctypes.c_size_t,
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "ficgcn_plan_weights_int": (ctypes.c_int, [c_vp, ctypes.c_uint32, c_vp]),
+    "ficgcn_plan_operand_count": (ctypes.c_int, [c_vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]),
+    "ficgcn_plan_operand_slots": (ctypes.c_int, [c_vp, ctypes.c_uint32, ctypes.c_size_t, c_vp]),
+    "ficgcn_plan_encode": (ctypes.c_int, [c_vp, c_vp]),
+    "ficgcn_plan_load_operand": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, ctypes.c_size_t, c_vp]),
+    "ficgcn_gcn_layer": (ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_uint32, c_vp, ctypes.c_size_t, c_vp,
+                                        ctypes.c_size_t, ctypes.c_int32]),
+}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FicgcnError(-6, "HIP library %s is not built (run __graft_entry__.build())" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> List[str]:
+    return list(_SIGS)
+
+
+def _check(st: int):
+    if st != 0:
+        raise FicgcnError(st, lib().ficgcn_last_error().decode())
+
+
+def _ptr(x) -> int:
+    """Address of a torch tensor, numpy array or raw integer."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        assert x.flags["C_CONTIGUOUS"]
+        return x.ctypes.data
+    raise TypeError(type(x))
+
+
+def _ptr_array(xs) -> ctypes.Array:
+    arr = (c_vp * max(1, len(xs)))()
+    for i, x in enumerate(xs):
+        arr[i] = _ptr(x)
+    return arr
+
+
+class Context:
+    """A CKKS context on the current HIP device, bound to torch's current stream."""
+
+    def __init__(self, log_n: int, n_q: int, q_bits: int, n_p: int, p_bits: int, log_scale: int = 40,
+                 stream=None):
+        self.params = CkksParams(log_n, n_q, q_bits, n_p, p_bits, log_scale)
+        h = c_vp()
+        _check(lib().ckks_context_create(ctypes.byref(self.params), ctypes.byref(h)))
+        self.h = h
+        self.N = 1 << log_n
+        self.M = self.N // 2
+        self.L, self.alpha, self.log_scale = n_q, n_p, log_scale
+        self.beta = -(-n_q // n_p)
+        if stream is None:
+            import torch
+            # host-only use (planning) needs no device; device tables upload on first device call
+            stream = torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else 0
+        self.ckks_ctx_set_stream(stream)
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "Context":
+        return cls(d["log_n"], d["n_q"], d["q_bits"], d["n_p"], d["p_bits"], d.get("log_scale", 40))
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ckks_ctx_destroy(self.h)
+            self.h = None
+
+    # ---- context
+    def ckks_ctx_set_stream(self, stream):
+        _check(lib().ckks_ctx_set_stream(self.h, stream))
+
+    def ckks_ctx_moduli(self) -> List[int]:
+        out = np.zeros(self.L + self.alpha, dtype=np.uint64)
+        _check(lib().ckks_ctx_moduli(self.h, _ptr(out)))
+        return [int(x) for x in out]
+
+    def ckks_galois_element(self, step: int) -> int:
+        g = ctypes.c_uint64()
+        _check(lib().ckks_galois_element(self.h, step, ctypes.byref(g)))
+        return g.value
+
+    def ckks_sync(self):
+        _check(lib().ckks_sync(self.h))
+
+    # ---- buffers
+    def ct_buffer(self, level: int, count: Optional[int] = None):
+        import torch
+        shape = (2, level + 1, self.N) if count is None else (count, 2, level + 1, self.N)
+        return torch.empty(shape, dtype=torch.int64, device="cuda")
+
+    def pt_buffer(self, level: int, count: Optional[int] = None):
+        import torch
+        shape = (level + 1, self.N) if count is None else (count, level + 1, self.N)
+        return torch.empty(shape, dtype=torch.int64, device="cuda")
+
+    # ---- keys
+    def ckks_keygen(self, seed: int, rot_steps: Sequence[int] = (), with_relin: bool = True):
+        steps = np.ascontiguousarray(np.array(list(rot_steps), dtype=np.int64))
+        cl, ev = c_vp(), c_vp()
+        _check(lib().ckks_keygen(self.h, seed, _ptr(steps) if len(steps) else None, len(steps), int(with_relin),
+                                 ctypes.byref(cl), ctypes.byref(ev)))
+        return Keys(self, cl), Keys(self, ev)
+
+    def ckks_keys_create_empty(self):
+        k = c_vp()
+        _check(lib().ckks_keys_create_empty(self.h, ctypes.byref(k)))
+        return Keys(self, k)
+
+    # ---- encode / encrypt / decrypt
+    def ckks_encode(self, z, scale: float, level: int, out=None):
+        out = self.pt_buffer(level) if out is None else out
+        z = np.asarray(z)
+        re = np.ascontiguousarray(np.real(z), dtype=np.float64)
+        im = np.ascontiguousarray(np.imag(z), dtype=np.float64) if np.iscomplexobj(z) else None
+        _check(lib().ckks_encode(self.h, _ptr(re), _ptr(im), len(re), scale, level, _ptr(out)))
+        return out
+
+    def ckks_encode_batch(self, rows: np.ndarray, scale: float, level: int, out=None):
+        rows = np.ascontiguousarray(rows, dtype=np.float64)
+        out = self.pt_buffer(level, rows.shape[0]) if out is None else out
+        _check(lib().ckks_encode_batch(self.h, _ptr(rows), rows.shape[0], rows.shape[1], scale, level, _ptr(out)))
+        return out
+
+    def ckks_pt_load(self, coeffs: np.ndarray, level: int, out=None):
+        out = self.pt_buffer(level) if out is None else out
+        coeffs = np.ascontiguousarray(coeffs, dtype=np.uint64)
+        _check(lib().ckks_pt_load(self.h, _ptr(coeffs), level, _ptr(out)))
+        return out
+
+    def ckks_encrypt(self, client_keys: "Keys", pt, level: int, seed: int, ct_id: int, out=None):
+        out = self.ct_buffer(level) if out is None else out
+        _check(lib().ckks_encrypt(self.h, client_keys.h, _ptr(pt), level, seed, ct_id, _ptr(out)))
+        return out
+
+    def ckks_decrypt(self, client_keys: "Keys", ct, level: int, scale: float, n_slots: int) -> np.ndarray:
+        re = np.zeros(n_slots, dtype=np.float64)
+        im = np.zeros(n_slots, dtype=np.float64)
+        _check(lib().ckks_decrypt(self.h, client_keys.h, _ptr(ct), level, scale, _ptr(re), _ptr(im), n_slots))
+        return re + 1j * im
+
+    # ---- transfers
+    def ckks_ct_load(self, coeffs: np.ndarray, level: int, out=None):
+        out = self.ct_buffer(level) if out is None else out
+        coeffs = np.ascontiguousarray(coeffs, dtype=np.uint64)
+        _check(lib().ckks_ct_load(self.h, _ptr(coeffs), level, _ptr(out)))
+        return out
+
+    def ckks_poly_store(self, dev, level: int, n_polys: int) -> np.ndarray:
+        out = np.zeros((n_polys, level + 1, self.N), dtype=np.uint64)
+        _check(lib().ckks_poly_store(self.h, _ptr(dev), level, n_polys, _ptr(out)))
+        return out
+
+    def ckks_ntt(self, dev, n_limbs: int, first_mod: int, inverse: bool):
+        _check(lib().ckks_ntt(self.h, _ptr(dev), n_limbs, first_mod, int(inverse)))
+
+    # ---- evaluation
+    def ckks_rotate_hoisted(self, eval_keys: "Keys", ct, level: int, steps: Sequence[int], outs=None):
+        steps = np.ascontiguousarray(np.array(list(steps), dtype=np.int64))
+        outs = [self.ct_buffer(level) for _ in steps] if outs is None else outs
+        _check(lib().ckks_rotate_hoisted(self.h, eval_keys.h, _ptr(ct), level, _ptr(steps), len(steps),
+                                         _ptr_array(outs)))
+        return outs
+
+    def ckks_pt_mul_acc(self, acc, level: int, cts, pts):
+        _check(lib().ckks_pt_mul_acc(self.h, _ptr(acc), level, _ptr_array(cts), _ptr_array(pts), len(cts)))
+
+    def ckks_scalar_mul_acc(self, acc, level: int, cts, consts):
+        c = np.ascontiguousarray(np.array(list(consts), dtype=np.int64))
+        _check(lib().ckks_scalar_mul_acc(self.h, _ptr(acc), level, _ptr_array(cts), _ptr(c), len(cts)))
+
+    def ckks_add(self, acc, x, level: int):
+        _check(lib().ckks_add(self.h, _ptr(acc), _ptr(x), level))
+
+    def ckks_rescale(self, ct, level: int):
+        _check(lib().ckks_rescale(self.h, _ptr(ct), level))
+
+    def ckks_mul_relin(self, eval_keys: "Keys", x, y, level: int, out=None):
+        out = self.ct_buffer(level) if out is None else out
+        _check(lib().ckks_mul_relin(self.h, eval_keys.h, _ptr(x), _ptr(y), level, _ptr(out)))
+        return out
+
+
+class Keys:
+    def __init__(self, ctx: Context, h):
+        self.ctx, self.h = ctx, h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ckks_keys_destroy(self.h)
+            self.h = None
+
+    def ckks_keys_tags(self) -> List[int]:
+        n = ctypes.c_size_t()
+        _check(lib().ckks_keys_tags(self.h, None, 0, ctypes.byref(n)))
+        out = np.zeros(max(1, n.value), dtype=np.uint64)
+        _check(lib().ckks_keys_tags(self.h, _ptr(out), n.value, ctypes.byref(n)))
+        return [int(x) for x in out[: n.value]]
+
+    def ckks_keys_export(self, tag: int) -> np.ndarray:
+        c = self.ctx
+        out = np.zeros((c.beta, 2, c.L + c.alpha, c.N), dtype=np.uint64)
+        _check(lib().ckks_keys_export(c.h, self.h, tag, _ptr(out)))
+        return out
+
+    def ckks_keys_import(self, tag: int, coeffs: np.ndarray):
+        coeffs = np.ascontiguousarray(coeffs, dtype=np.uint64)
+        _check(lib().ckks_keys_import(self.ctx.h, self.h, tag, _ptr(coeffs)))
+
+
+class Plan:
+    """ficgcn_plan: node order, per-layer routing and schedule, operands."""
+
+    def __init__(self, ctx: Context, rowptr, col, val, n_v: int, dims: Sequence[int], weights,
+                 first_mode: int = 0, use_noo: bool = True, family: int = 0, TH: int = 0, activation: bool = False):
+        self.ctx = ctx
+        self._rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+        self._col = np.ascontiguousarray(col, dtype=np.int32)
+        self._val = np.ascontiguousarray(val, dtype=np.float64)
+        self._dims = np.ascontiguousarray(dims, dtype=np.uint32)
+        self._w = [np.ascontiguousarray(w, dtype=np.float64) for w in weights]
+        wp = _ptr_array(self._w)
+        opts = PlanOpts(first_mode, int(use_noo), family, TH, int(activation))
+        h = c_vp()
+        _check(lib().ficgcn_plan_create(ctx.h, _ptr(self._rowptr), _ptr(self._col), _ptr(self._val), n_v,
+                                        _ptr(self._dims), len(self._w), wp, ctypes.byref(opts), ctypes.byref(h)))
+        self.h = h
+        self.n_v = n_v
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ficgcn_plan_destroy(self.h)
+            self.h = None
+
+    def ficgcn_plan_node_order(self) -> np.ndarray:
+        out = np.zeros(self.n_v, dtype=np.int32)
+        _check(lib().ficgcn_plan_node_order(self.h, _ptr(out)))
+        return out
+
+    def ficgcn_plan_copy_sources(self, layer: int) -> np.ndarray:
+        K = self.ficgcn_plan_info()[layer]["K"]
+        out = np.zeros((K, self.n_v), dtype=np.int32)
+        _check(lib().ficgcn_plan_copy_sources(self.h, layer, _ptr(out)))
+        return out
+
+    def ficgcn_plan_rot_steps(self) -> List[int]:
+        n = ctypes.c_size_t()
+        _check(lib().ficgcn_plan_rot_steps(self.h, None, 0, ctypes.byref(n)))
+        out = np.zeros(max(1, n.value), dtype=np.int64)
+        _check(lib().ficgcn_plan_rot_steps(self.h, _ptr(out), n.value, ctypes.byref(n)))
+        return [int(x) for x in out[: n.value]]
+
+    def ficgcn_plan_info(self) -> List[dict]:
+        n = ctypes.c_uint32()
+        _check(lib().ficgcn_plan_info(self.h, None, None, ctypes.byref(n)))
+        info = np.zeros(13 * n.value, dtype=np.int64)
+        sc = np.zeros(3 * n.value, dtype=np.float64)
+        _check(lib().ficgcn_plan_info(self.h, _ptr(info), _ptr(sc), ctypes.byref(n)))
+        keys = ["kind", "f_in", "f_out", "K", "t", "B", "family", "G", "n_shifts", "level_in", "level_out",
+                "n_in_cts", "n_out_cts"]
+        out = []
+        for li in range(n.value):
+            d = {k: int(info[13 * li + i]) for i, k in enumerate(keys)}
+            d.update(scale_in=float(sc[3 * li]), scale_out=float(sc[3 * li + 1]), sW=float(sc[3 * li + 2]))
+            out.append(d)
+        return out
+
+    def ficgcn_plan_shifts(self, layer: int) -> List[int]:
+        n = ctypes.c_size_t()
+        _check(lib().ficgcn_plan_shifts(self.h, layer, None, 0, ctypes.byref(n)))
+        out = np.zeros(max(1, n.value), dtype=np.int64)
+        _check(lib().ficgcn_plan_shifts(self.h, layer, _ptr(out), n.value, ctypes.byref(n)))
+        return [int(x) for x in out[: n.value]]
+
+    def ficgcn_plan_weights_int(self, layer: int) -> np.ndarray:
+        info = self.ficgcn_plan_info()[layer]
+        out = np.zeros((info["f_in"], info["f_out"]), dtype=np.int64)
+        _check(lib().ficgcn_plan_weights_int(self.h, layer, _ptr(out)))
+        return out
+
+    def ficgcn_plan_operand_count(self, layer: int) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().ficgcn_plan_operand_count(self.h, layer, ctypes.byref(n)))
+        return n.value
+
+    def ficgcn_plan_operand_slots(self, layer: int, i: int) -> np.ndarray:
+        out = np.zeros(self.ctx.M, dtype=np.float64)
+        _check(lib().ficgcn_plan_operand_slots(self.h, layer, i, _ptr(out)))
+        return out
+
+    def ficgcn_plan_encode(self):
+        _check(lib().ficgcn_plan_encode(self.ctx.h, self.h))
+
+    def ficgcn_plan_load_operand(self, layer: int, i: int, coeffs: np.ndarray):
+        coeffs = np.ascontiguousarray(coeffs, dtype=np.uint64)
+        _check(lib().ficgcn_plan_load_operand(self.ctx.h, self.h, layer, i, _ptr(coeffs)))
+
+    def ficgcn_gcn_layer(self, eval_keys: Keys, layer: int, in_cts, out_cts, mode: int = 1):
+        _check(lib().ficgcn_gcn_layer(self.ctx.h, eval_keys.h, self.h, layer, _ptr_array(in_cts), len(in_cts),
+                                      _ptr_array(out_cts), len(out_cts), mode))

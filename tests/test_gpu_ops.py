@@ -1,0 +1,173 @@
+"""GPU parity of every CKKS operation against the oracle, through the C ABI.
+
+Inputs (ciphertexts, plaintexts, keys) come from the oracle; the GPU result is
+read back in coefficient form and compared word for word.  Runs at the tiny
+parameters (N = 2^13, 4 + 1 primes) and at the citation-graph parameters
+(N = 2^16, 8 + 2 primes), i.e. in the launch shapes the benchmark uses."""
+import numpy as np
+import pytest
+
+from oracle import ckks, encoding as enc
+from oracle.params import Params
+
+pytestmark = pytest.mark.gpu
+
+PARAMS = {
+    "tiny": dict(log_n=13, n_q=4, q_bits=50, n_p=1, p_bits=60, log_scale=40),
+    "cora": dict(log_n=16, n_q=8, q_bits=50, n_p=2, p_bits=60, log_scale=40),
+}
+STEPS = [1, 3, -5, 100]
+SEED = 4242
+
+
+def _ct(c: ckks.Ciphertext) -> np.ndarray:
+    return np.stack([c.c0, c.c1])
+
+
+@pytest.fixture(scope="module", params=["tiny", "cora"])
+def env(request):
+    import torch
+    from paper_2506_10399_amd import ficgcn as fg
+    assert torch.cuda.is_available()
+    d = PARAMS[request.param]
+    prm = Params.from_dict(d)
+    ctx = fg.Context.from_dict(d)
+    steps = STEPS if request.param == "tiny" else STEPS[:2]
+    okeys = ckks.keygen(prm, SEED, steps, relin=True)
+    cl, ev = ctx.ckks_keygen(SEED, steps, with_relin=True)
+    rng = np.random.default_rng(11)
+    return dict(name=request.param, prm=prm, ctx=ctx, okeys=okeys, cl=cl, ev=ev, steps=steps, rng=rng, fg=fg)
+
+
+def _rand_ct(e, level, ct_id):
+    prm = e["prm"]
+    z = e["rng"].uniform(-1, 1, prm.M)
+    return z, ckks.encrypt(prm, 77, ct_id, e["okeys"].s, enc.encode(prm, z, prm.scale, level))
+
+
+def test_prime_chain(env):
+    assert env["ctx"].ckks_ctx_moduli() == env["prm"].q + env["prm"].p
+
+
+def test_ntt_roundtrip_and_ring_product(env):
+    prm, ctx = env["prm"], env["ctx"]
+    lv = prm.L - 1
+    mods = prm.q_level(lv)
+    a = np.stack([np.stack([env["rng"].integers(0, q, prm.N, dtype=np.uint64) for q in mods]) for _ in range(2)])
+    b = np.stack([env["rng"].integers(0, q, prm.N, dtype=np.uint64) for q in mods])
+    da = ctx.ckks_ct_load(a, lv)
+    assert np.array_equal(ctx.ckks_poly_store(da, lv, 2), a)
+    db = ctx.ckks_pt_load(b, lv)
+    acc = ctx.ct_buffer(lv)
+    acc.zero_()
+    ctx.ckks_pt_mul_acc(acc, lv, [da], [db])
+    got = ctx.ckks_poly_store(acc, lv, 2)
+    for c in range(2):
+        assert np.array_equal(got[c], ckks.poly_mul(b, a[c], mods, prm))
+
+
+def test_keygen_matches_oracle(env):
+    prm, ctx = env["prm"], env["ctx"]
+    tags = env["ev"].ckks_keys_tags()
+    assert sorted(tags) == sorted([0] + list(env["okeys"].rot))
+    for tag in tags:
+        ok = env["okeys"].relin if tag == 0 else env["okeys"].rot[tag]
+        got = env["ev"].ckks_keys_export(tag)
+        for j in range(prm.beta):
+            assert np.array_equal(got[j, 0], ok.b[j]), ("b", tag, j)
+            assert np.array_equal(got[j, 1], ok.a[j]), ("a", tag, j)
+
+
+def test_encrypt_matches_oracle(env):
+    prm, ctx = env["prm"], env["ctx"]
+    for lv in (prm.L - 1, 1):
+        z = env["rng"].uniform(-1, 1, prm.M)
+        pt = enc.encode(prm, z, prm.scale, lv)
+        want = ckks.encrypt(prm, SEED, 9 + lv, env["okeys"].s, pt)
+        dpt = ctx.ckks_pt_load(pt.m, lv)
+        ct = ctx.ckks_encrypt(env["cl"], dpt, lv, SEED, 9 + lv)
+        assert np.array_equal(ctx.ckks_poly_store(ct, lv, 2), _ct(want))
+        # decrypt + decode on the GPU path
+        got = ctx.ckks_decrypt(env["cl"], ct, lv, prm.scale, prm.M)
+        assert np.abs(got - z).max() < 1e-6
+
+
+def test_rotate_hoisted_matches_oracle(env):
+    prm, ctx = env["prm"], env["ctx"]
+    for lv in (prm.L - 1, 2):
+        z, oct_ = _rand_ct(env, lv, 1 + lv)
+        want = ckks.rotate_hoisted(prm, env["okeys"], oct_, env["steps"])
+        dct = ctx.ckks_ct_load(_ct(oct_), lv)
+        outs = ctx.ckks_rotate_hoisted(env["ev"], dct, lv, env["steps"])
+        for k, o, wnt in zip(env["steps"], outs, want):
+            assert np.array_equal(ctx.ckks_poly_store(o, lv, 2), _ct(wnt)), (lv, k)
+        # a single rotation gives the same words (canonical rotation)
+        one = ctx.ckks_rotate_hoisted(env["ev"], dct, lv, env["steps"][1:2])[0]
+        assert np.array_equal(ctx.ckks_poly_store(one, lv, 2), _ct(want[1]))
+
+
+def test_rotate_missing_key_is_enokey(env):
+    ctx = env["ctx"]
+    lv = 1
+    dct = ctx.ct_buffer(lv)
+    dct.zero_()
+    with pytest.raises(env["fg"].FicgcnError) as e:
+        ctx.ckks_rotate_hoisted(env["ev"], dct, lv, [7])
+    assert e.value.status == -4
+
+
+def test_pt_and_scalar_mac_and_add_match_oracle(env):
+    prm, ctx = env["prm"], env["ctx"]
+    lv = prm.L - 1
+    cts = [_rand_ct(env, lv, 20 + i)[1] for i in range(3)]
+    pts = [enc.encode(prm, env["rng"].uniform(-1, 1, prm.M), float(prm.q[lv]), lv) for _ in range(3)]
+    consts = [123456789012, -987654321098, 5]
+    acc0 = ckks.zero_ct(prm, lv, 1.0)
+    want = ckks.pt_mul_acc(prm, acc0, cts, pts)
+    want = ckks.scalar_mul_acc(prm, want, cts, consts)
+    want = ckks.add(prm, want, cts[0])
+    dcts = [ctx.ckks_ct_load(_ct(c), lv) for c in cts]
+    dpts = [ctx.ckks_pt_load(p.m, lv) for p in pts]
+    acc = ctx.ct_buffer(lv)
+    acc.zero_()
+    ctx.ckks_pt_mul_acc(acc, lv, dcts, dpts)
+    ctx.ckks_scalar_mul_acc(acc, lv, dcts, consts)
+    ctx.ckks_add(acc, dcts[0], lv)
+    assert np.array_equal(ctx.ckks_poly_store(acc, lv, 2), _ct(want))
+
+
+def test_rescale_matches_oracle(env):
+    prm, ctx = env["prm"], env["ctx"]
+    for lv in (prm.L - 1, 1):
+        _, c = _rand_ct(env, lv, 30 + lv)
+        want = ckks.rescale(prm, c)
+        d = ctx.ckks_ct_load(_ct(c), lv)
+        ctx.ckks_rescale(d, lv)
+        got = ctx.ckks_poly_store(d, lv - 1, 2)
+        assert np.array_equal(got, _ct(want))
+
+
+def test_mul_relin_matches_oracle(env):
+    prm, ctx = env["prm"], env["ctx"]
+    lv = prm.L - 2
+    z1, c1 = _rand_ct(env, lv, 40)
+    z2, c2 = _rand_ct(env, lv, 41)
+    want = ckks.ct_mul_relin(prm, env["okeys"], c1, c2)
+    d1, d2 = ctx.ckks_ct_load(_ct(c1), lv), ctx.ckks_ct_load(_ct(c2), lv)
+    out = ctx.ckks_mul_relin(env["ev"], d1, d2, lv)
+    assert np.array_equal(ctx.ckks_poly_store(out, lv, 2), _ct(want))
+    got = ctx.ckks_decrypt(env["cl"], out, lv, prm.scale ** 2, prm.M)
+    assert np.abs(got - z1 * z2).max() < 1e-6
+
+
+def test_encoder_decodes_within_precision(env):
+    prm, ctx = env["prm"], env["ctx"]
+    lv = prm.L - 1
+    z = env["rng"].uniform(-1, 1, prm.M)
+    d = ctx.ckks_encode(z, prm.scale, lv)
+    m = ctx.ckks_poly_store(d, lv, 1)[0]
+    want = enc.encode(prm, z, prm.scale, lv).m
+    # independent FP64 FFTs may round a handful of coefficients differently
+    assert np.mean(m != want) < 1e-3
+    back = enc.decode(prm, ckks.Plaintext(m=m, level=lv, scale=prm.scale))
+    assert np.abs(back - z).max() < 1e-9
