@@ -1,0 +1,305 @@
+#!/usr/bin/env python3
+"""Encrypted 2-layer GCN on one MI355X: the citation-graph-shape workload.
+
+Workload (synthetic, seeded): power-law graph of 2708 nodes (average degree
+3.9, 4 sampled neighbours + self, mean aggregation), binary bag-of-words X of
+2708 x 1433 at 1.3% density, W1 1433 x 16, W2 16 x 7 ~ N(0, 0.1^2), x^2 after
+both layers; CKKS N = 2^16, 8 x 50-bit primes + 2 x 60-bit special primes,
+scale 2^40.  Layer 1 is Inter-CA over the client's 5 neighbour copies of
+each of the 1433 columns (7165 input ciphertexts, 56 GiB resident in HBM
+before timing), layer 2 is SpIntra-CA on the packed hidden layer.
+
+A step is one whole encrypted inference (both layers, every rotation,
+rescale and relinearisation) in the batched form.  The plain per-operation
+form of the same plan is timed once for the speedup; both forms' output
+words are compared.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "enc. GCN latency: batched+planned vs plain (same GPU); key-switch/s; HBM %"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def fp64_gcn(rp, col, val, x, weights):
+    """The plaintext model the encrypted path computes: (A (A X W1)^2 W2)^2."""
+    import scipy.sparse as sp
+    n = len(rp) - 1
+    A = sp.csr_matrix((val, col, rp), shape=(n, n))
+    h = x
+    for w in weights:
+        h = A @ (h @ w)
+        h = h * h
+    return h
+
+
+def cpu_baseline(params, plan_info, op_counts, sample_features=2):
+    """The CPU oracle on a bounded sample of the same workload, scaled to one
+    inference by the plan's operation counts."""
+    from oracle import ckks, encoding as enc
+    from oracle.params import Params
+    prm = Params.from_dict(params)
+    rng = np.random.default_rng(0)
+    t_total = 0.0
+    timings = {}
+    keys = ckks.keygen(prm, 1, [1], relin=True)
+    lv = prm.L - 1
+
+    def ct_at(level, cid):
+        z = rng.uniform(-1, 1, prm.M)
+        return ckks.encrypt(prm, 2, cid, keys.s, enc.encode(prm, z, prm.scale, level))
+
+    K = plan_info[0]["K"]
+    F_out = plan_info[0]["f_out"]
+    cts = [ct_at(lv, i) for i in range(K)]
+    pts = [enc.encode(prm, rng.uniform(0, 1, prm.M), float(prm.q[lv]), lv) for _ in range(K)]
+    t0 = time.perf_counter()
+    for _ in range(sample_features):
+        z = ckks.pt_mul_acc(prm, ckks.zero_ct(prm, lv, 1.0), cts, pts)
+        acc = ckks.zero_ct(prm, lv, 1.0)
+        for l in range(F_out):
+            acc = ckks.scalar_mul_acc(prm, acc, [z], [12345 + l])
+    timings["inter_feature"] = (time.perf_counter() - t0) / sample_features
+    la = plan_info[1]["level_in"] - 2   # aggregation level of layer 2
+    y = ct_at(la, 99)
+    keys3 = ckks.keygen(prm, 1, [3], relin=False)
+    t0 = time.perf_counter()
+    ckks.rotate(prm, keys3, y, 3)
+    timings["rotation_agg_level"] = time.perf_counter() - t0
+    mask = enc.encode(prm, rng.uniform(0, 1, prm.M), float(prm.q[la]), la)
+    t0 = time.perf_counter()
+    ckks.pt_mul_acc(prm, ckks.zero_ct(prm, la, 1.0), [y], [mask])
+    timings["mask_mac"] = time.perf_counter() - t0
+    lr = plan_info[0]["level_out"]
+    h = ct_at(lr, 98)
+    t0 = time.perf_counter()
+    ckks.ct_mul_relin(prm, keys, h, h)
+    timings["relin"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ckks.rescale(prm, h)
+    timings["rescale"] = time.perf_counter() - t0
+    sample_s = sum(timings.values())
+    F = plan_info[0]["f_in"]
+    est = (timings["inter_feature"] * F + timings["rotation_agg_level"] * op_counts["rot"]
+           + timings["mask_mac"] * op_counts["mask_pmult"] + timings["relin"] * op_counts["cmult"]
+           + timings["rescale"] * op_counts["rescale"])
+    return dict(value=est * 1e3, unit="ms", cores=1, kind="oracle",
+                sample=("oracle on this host, single thread: %d of %d layer-1 feature columns (Inter-CA "
+                        "PMult over %d copies + %d scalar MACs), one rotation and one mask PMult at the "
+                        "aggregation level, one relinearised square, one rescale; scaled by the plan's "
+                        "counts (%d rotations, %d mask PMults, %d squares, %d rescales); sample %.1f s"
+                        % (sample_features, F, K, F_out, op_counts["rot"], op_counts["mask_pmult"],
+                           op_counts["cmult"], op_counts["rescale"], sample_s * sample_features)),
+                per_op_s=timings)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="cora")
+    ap.add_argument("--features", type=int, default=None, help="shrink F (quick runs only)")
+    ap.add_argument("--skip-plain", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-ks", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (scale reference for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2506_10399_amd import ficgcn as fg, graph
+    from workload import make_workload
+
+    torch.cuda.set_device(0)
+    t_setup = time.perf_counter()
+    kw = {}
+    if args.features:
+        from workload.configs import CONFIGS
+        d = list(CONFIGS[args.config]["dims"])
+        d[0] = args.features
+        kw["dims"] = d
+    w = make_workload(args.config, **kw)
+    dims = w.meta["dims"]
+    rp, col, val = graph.normalize(w.graph.n, w.neighbors, w.norm)
+    ctx = fg.Context.from_dict(w.params)
+    prm = w.params
+    N = 1 << prm["log_n"]
+    M = N // 2
+    L = prm["n_q"]
+    plan = fg.Plan(ctx, rp, col, val, w.graph.n, dims, w.weights, activation=w.activation)
+    info = plan.ficgcn_plan_info()
+    steps_needed = plan.ficgcn_plan_rot_steps()
+    log("plan: %s ; %d rotation keys" % (info, len(steps_needed)))
+    cl, ev = ctx.ckks_keygen(7, steps_needed, with_relin=True)
+    plan.ficgcn_plan_encode()
+    pi = plan.ficgcn_plan_node_order()
+    src = plan.ficgcn_plan_copy_sources(0)
+    K, F = info[0]["K"], info[0]["f_in"]
+    lv0 = L - 1
+    n_in = K * F
+    inputs = torch.empty((n_in, 2, lv0 + 1, N), dtype=torch.int64, device="cuda")
+    log("encrypting %d client ciphertexts (%.1f GiB)" % (n_in, inputs.numel() * 8 / 2 ** 30))
+    CH = 256
+    for k in range(K):
+        have = src[k] >= 0
+        for f0 in range(0, F, CH):
+            nf = min(CH, F - f0)
+            rows = np.zeros((nf, M))
+            rows[:, pi[have]] = w.x[src[k][have], f0:f0 + nf].T
+            pts = ctx.ckks_encode_batch(rows, 2.0 ** prm["log_scale"], lv0)
+            for i in range(nf):
+                ctx.ckks_encrypt(cl, pts[i], lv0, 1234, k * F + f0 + i, out=inputs[k * F + f0 + i])
+        log("  copy %d done" % k)
+    ctx.ckks_sync()
+    in_list = [inputs[i] for i in range(n_in)]
+    outs = [[ctx.ct_buffer(d["level_in"]) for _ in range(d["n_out_cts"])] for d in info]
+    log("setup %.1f s" % (time.perf_counter() - t_setup))
+
+    if args.calibrate_copy:
+        a = torch.ones(1 << 27, dtype=torch.int64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    def step(mode):
+        cur = in_list
+        for li in range(len(info)):
+            plan.ficgcn_gcn_layer(ev, li, cur, outs[li], mode=mode)
+            cur = outs[li]
+
+    for _ in range(args.warmup):
+        step(1)
+    torch.cuda.synchronize()
+    ctx.ficgcn_profile_enable(True)
+    for k in ("inter_fused", "comb_fused", "keymac", "moddown", "modup", "ntt"):
+        ctx.ficgcn_profile_read(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.ficgcn_profile_enable(False)
+    prof = {k: ctx.ficgcn_profile_read(k) for k in ("inter_fused", "comb_fused", "keymac", "moddown", "modup", "ntt")}
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    log("batched: %.2f ms per inference; kernel event totals %s" % (ms_step, prof))
+    last = info[-1]
+    batched_words = [ctx.ckks_poly_store(x, last["level_out"], 2) for x in outs[-1]]
+    slots = [np.real(ctx.ckks_decrypt(cl, x, last["level_out"], last["scale_out"], M)) for x in outs[-1]]
+    y = graph.read_output(pi, slots, last["f_out"], last["t"], last["B"], last["kind"] == 1)
+    ref = fp64_gcn(rp, col, val, w.x, w.weights)
+    err = float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
+    log("max rel err vs FP64 GCN: %.3e" % err)
+
+    plain_ms = None
+    same = None
+    if not args.skip_plain:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step(0)
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - t0) * 1e3
+        plain_words = [ctx.ckks_poly_store(x, last["level_out"], 2) for x in outs[-1]]
+        same = all(np.array_equal(a, b) for a, b in zip(plain_words, batched_words))
+        log("plain: %.2f ms, words equal to batched: %s" % (plain_ms, same))
+
+    ks = {}
+    if not args.skip_ks:
+        nrot = 16
+        rsteps = [s for s in steps_needed[:nrot]]
+        for lv in (lv0, info[1]["level_in"] - 2):
+            x = ctx.ct_buffer(lv)
+            x.copy_(inputs[0][:, : lv + 1, :])
+            outs_ks = [ctx.ct_buffer(lv) for _ in rsteps]
+            ctx.ckks_rotate_hoisted(ev, x, lv, rsteps, outs_ks)
+            torch.cuda.synchronize()
+            reps = 5
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.ckks_rotate_hoisted(ev, x, lv, rsteps, outs_ks)
+            torch.cuda.synchronize()
+            hoisted = reps * len(rsteps) / (time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                for s, o in zip(rsteps, outs_ks):
+                    ctx.ckks_rotate_hoisted(ev, x, lv, [s], [o])
+            torch.cuda.synchronize()
+            single = reps * len(rsteps) / (time.perf_counter() - t0)
+            ks["level_%d" % lv] = dict(hoisted_per_s=round(hoisted, 1), single_per_s=round(single, 1))
+        log("key-switch/s: %s" % ks)
+
+    # roofline of the dominant kernel: the fused Inter-CA + combination pass
+    F_out = info[0]["f_out"]
+    l1 = lv0 + 1
+    alg_bytes = 8.0 * N * l1 * (2 * K * F + K + 2 * F_out) + 8.0 * l1 * F * F_out
+    ms_k, n_k = prof["inter_fused"]
+    per_step_ms = ms_k / args.steps       # one fused pass (F' <= 16 outputs per launch) per inference
+    achieved = alg_bytes / (per_step_ms * 1e-3) / 1e9
+    roofline = dict(kernel="k_comb_fused (Inter-CA aggregation + combination)", bound="hbm",
+                    achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    alg_bytes_per_launch=alg_bytes, avg_launch_ms=per_step_ms, launches=n_k,
+                    share_of_step=round(ms_k / args.steps / ms_step, 3))
+
+    cpu = None
+    if not args.skip_cpu:
+        counts = dict(rot=plan_rot_count(plan, info),
+                      mask_pmult=info[1]["n_shifts"] * info[1]["n_out_cts"],
+                      cmult=info[0]["n_out_cts"] + info[1]["n_out_cts"],
+                      rescale=2 * info[0]["n_out_cts"] + 2 * info[1]["f_out"] + info[1]["n_out_cts"])
+        log("cpu baseline (oracle sample)...")
+        cpu = cpu_baseline(prm, info, counts)
+        log("cpu baseline: %.0f ms extrapolated" % cpu["value"])
+
+    out = dict(metric=METRIC, value=round(ms_step, 3), unit="ms", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=round(ms_step, 3), higher_is_better=False, scaling="weak", vs_baseline=None,
+               dtype="u64", data="synthetic",
+               config=dict(workload="%s-shape 2-layer x^2 GCN: %d nodes, %s, K=%d copies, CKKS N=2^%d, "
+                           "%d+%d primes, %d input cts resident" % (args.config, w.graph.n, "-".join(map(str, dims)),
+                                                                     K, prm["log_n"], L, prm["n_p"], n_in),
+                           form="batched (fused Inter-CA pass, hoisted rotations)"),
+               plain_ms=None if plain_ms is None else round(plain_ms, 3),
+               speedup_vs_plain=None if plain_ms is None else round(plain_ms / ms_step, 3),
+               plain_equals_batched=same, max_rel_err=err, keyswitch=ks, roofline=roofline,
+               kernel_ms_per_step={k: round(v[0] / args.steps, 3) for k, v in prof.items()},
+               cpu_baseline=cpu)
+    print(json.dumps(out), flush=True)
+
+
+def plan_rot_count(plan, info) -> int:
+    """Key switches for rotations in one inference (packing + aggregation)."""
+    d = info[1]
+    shifts = plan.ficgcn_plan_shifts(1)
+    n_packed = d["n_out_cts"]
+    pack = d["f_out"] - n_packed
+    if d["family"] == 1:
+        agg = sum(1 for s in shifts if s != 0)
+    else:
+        G = d["G"]
+        agg = len({s % G for s in shifts} - {0}) + len({s // G for s in shifts} - {0})
+    return pack + n_packed * agg
+
+
+if __name__ == "__main__":
+    main()

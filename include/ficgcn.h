@@ -76,6 +76,15 @@ ficgcn_status ckks_ctx_moduli(const ckks_ctx* ctx, uint64_t* moduli_out);
 ficgcn_status ckks_galois_element(const ckks_ctx* ctx, int64_t step, uint64_t* g_out);
 /* Waits for all work enqueued on the context's stream. */
 ficgcn_status ckks_sync(ckks_ctx* ctx);
+/* Kernel timing: while enabled, HIP events are recorded on the context's
+ * stream around every launch of the instrumented kernels ("inter_fused":
+ * the fused Inter-CA + combination pass, "comb_fused": the fused
+ * combination of a SpIntra-CA layer,
+ * "keymac", "moddown", "modup", "ntt").  profile_read synchronises the
+ * stream, returns the summed event time and launch count of `kernel` since
+ * the last read, and clears that kernel's record. */
+ficgcn_status ficgcn_profile_enable(ckks_ctx* ctx, int on);
+ficgcn_status ficgcn_profile_read(ckks_ctx* ctx, const char* kernel, double* ms_total, uint64_t* launches);
 
 /* ------------------------------------------------------------------ keys */
 /* [client] Samples the ternary secret and the switching keys (rotation keys

@@ -167,17 +167,7 @@ ficgcn_status ckks_keygen(ckks_ctx* ctx, uint64_t seed, const int64_t* rot_steps
     }
     if (with_relin) make(0);
     HIPCHECK(hipStreamSynchronize(ctx->stream));
-    if (client_keys) {
-      // the client object also carries the switching keys (copies)
-      for (auto& kv : ev->swk) {
-        uint64_t* k = alloc_swk(ctx);
-        HIPCHECK(hipMemcpyAsync(k, kv.second, (size_t)ctx->beta() * 2 * nm * N * 8, hipMemcpyDeviceToDevice,
-                                ctx->stream));
-        cl->swk[kv.first] = k;
-      }
-      HIPCHECK(hipStreamSynchronize(ctx->stream));
-      *client_keys = cl.release();
-    }
+    if (client_keys) *client_keys = cl.release();
     if (eval_keys) *eval_keys = ev.release();
   });
 }
@@ -483,6 +473,36 @@ ficgcn_status ckks_rescale(ckks_ctx* ctx, uint64_t* ct_dev, uint32_t level) {
     REQUIRE(ct_dev, EINVAL_, "null argument");
     REQUIRE(level >= 1, ELEVEL_, "rescale at level 0");
     rescale_inplace(ctx, ct_dev, (int)level);
+  });
+}
+
+ficgcn_status ficgcn_profile_enable(ckks_ctx* ctx, int on) {
+  return guard([&] {
+    REQUIRE(ctx, EINVAL_, "null context");
+    ctx->profiling = on != 0;
+  });
+}
+
+ficgcn_status ficgcn_profile_read(ckks_ctx* ctx, const char* kernel, double* ms_total, uint64_t* launches) {
+  return guard([&] {
+    REQUIRE(ctx && kernel && ms_total && launches, EINVAL_, "null argument");
+    HIPCHECK(hipStreamSynchronize(ctx->stream));
+    double tot = 0;
+    uint64_t n = 0;
+    auto it = ctx->prof.find(kernel);
+    if (it != ctx->prof.end()) {
+      for (auto& ev : it->second) {
+        float ms = 0;
+        HIPCHECK(hipEventElapsedTime(&ms, ev.first, ev.second));
+        tot += ms;
+        ++n;
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+      }
+      ctx->prof.erase(it);
+    }
+    *ms_total = tot;
+    *launches = n;
   });
 }
 

@@ -19,7 +19,8 @@
 namespace ficgcn {
 
 void comb_fused(ckks_ctx* c, uint64_t* const* out_dev_ptrs, const uint64_t* const* in_dev_ptrs,
-                const uint64_t* const* pt_dev_ptrs, int K, int F, int F_out, int level, const uint64_t* w_dev);
+                const uint64_t* const* pt_dev_ptrs, int K, int F, int F_out, int level, const uint64_t* w_dev,
+                const char* prof_name);
 void zero_fill(ckks_ctx* c, uint64_t* p, size_t words);
 void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_layers, const double* const* weights,
                 const ficgcn_plan_opts& o);
@@ -234,7 +235,7 @@ void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const u
       const uint64_t* const* idv = upload_ptrs(c, ins, 31);
       const uint64_t* const* pdv = upload_ptrs(c, pts, 32);
       uint64_t* wres = weights_residues(c, lp, 33);
-      comb_fused(c, od, idv, pdv, K, F, lp.f_out, lv, wres);
+      comb_fused(c, od, idv, pdv, K, F, lp.f_out, lv, wres, "inter_fused");
     } else {
       const int CH = 64;
       uint64_t* Z = (uint64_t*)c->buf(34, (size_t)CH * ct_words * 8);
@@ -278,7 +279,7 @@ void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const u
       uint64_t* const* od = upload_ptrs(c, colp, 30);
       const uint64_t* const* idv = upload_ptrs(c, ins, 31);
       uint64_t* wres = weights_residues(c, lp, 33);
-      comb_fused(c, od, idv, nullptr, 0, F, lp.f_out, lv, wres);
+      comb_fused(c, od, idv, nullptr, 0, F, lp.f_out, lv, wres, "comb_fused");
     } else {
       for (int l = 0; l < lp.f_out; ++l) {
         zero_fill(c, colp[l], ct_words);

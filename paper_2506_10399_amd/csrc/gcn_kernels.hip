@@ -54,7 +54,9 @@ __global__ __launch_bounds__(FB) void k_comb_fused(uint64_t* const* __restrict__
 }
 
 void comb_fused(ckks_ctx* c, uint64_t* const* out_dev_ptrs, const uint64_t* const* in_dev_ptrs,
-                const uint64_t* const* pt_dev_ptrs, int K, int F, int F_out, int level, const uint64_t* w_dev) {
+                const uint64_t* const* pt_dev_ptrs, int K, int F, int F_out, int level, const uint64_t* w_dev,
+                const char* prof_name) {
+  ProfScope ps(c, prof_name);
   if (K > 16) FICGCN_THROW(EPLAN_, "more than 16 Inter-CA copies per fused launch");
   const int l1 = level + 1;
   for (int l0 = 0; l0 < F_out; l0 += 16) {

@@ -76,6 +76,9 @@ struct ckks_ctx {
   std::map<int, ficgcn::BConv> moddown;                  // level
   // grow-only scratch buffers
   std::vector<std::pair<void*, size_t>> scratch;
+  // kernel timing (HIP events on `stream`), see ficgcn_profile_enable
+  bool profiling = false;
+  std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof;
   int beta() const { return (L + alpha - 1) / alpha; }
   int n_mod() const { return L + alpha; }
   void* buf(int slot, size_t bytes);
@@ -91,6 +94,24 @@ struct ckks_keys {
 };
 
 namespace ficgcn {
+
+// Records a start/stop event pair around the enclosed launches when the
+// context is profiling.
+struct ProfScope {
+  ckks_ctx* c;
+  const char* name;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(ckks_ctx* cc, const char* n) : c(cc), name(n) {
+    if (!c->profiling) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+    (void)hipEventRecord(a, c->stream);
+  }
+  ~ProfScope() {
+    if (!c->profiling || !a || !b) return;
+    (void)hipEventRecord(b, c->stream);
+    c->prof[name].push_back({a, b});
+  }
+};
 
 uint64_t powmod(uint64_t a, uint64_t e, uint64_t q);
 uint64_t invmod(uint64_t a, uint64_t q);

@@ -167,6 +167,7 @@ static void split(int log_n, int& l1, int& l2) {
 
 void ntt_fwd(ckks_ctx* c, uint64_t* base, int n_limbs, LimbMap map, int n_polys, size_t poly_stride, int skip_alpha,
              int skip_q) {
+  ProfScope ps(c, "ntt");
   if (n_limbs <= 0 || n_polys <= 0) return;
   int l1, l2;
   split(c->log_n, l1, l2);
@@ -180,6 +181,7 @@ void ntt_fwd(ckks_ctx* c, uint64_t* base, int n_limbs, LimbMap map, int n_polys,
 }
 
 void ntt_inv(ckks_ctx* c, uint64_t* base, int n_limbs, LimbMap map, int n_polys, size_t poly_stride) {
+  ProfScope ps(c, "ntt");
   if (n_limbs <= 0 || n_polys <= 0) return;
   int l1, l2;
   split(c->log_n, l1, l2);

@@ -130,6 +130,7 @@ static BConvDev bconv_indices(ckks_ctx*, const BConv& bc, int) { return BConvDev
 enum { S_MODUP_TMP = 1, S_IDX_A = 2, S_IDX_B = 3, S_MD_TMP = 4, S_RS_TMP = 5, S_RS_D = 6 };
 
 void modup(ckks_ctx* c, const uint64_t* a_ntt, int level, uint64_t* D) {
+  ProfScope ps(c, "modup");
   const size_t N = c->N;
   const int l1 = level + 1, ext = l1 + c->alpha;
   const int nd = (l1 + c->alpha - 1) / c->alpha;
@@ -165,6 +166,7 @@ __global__ void k_keymac(uint64_t* __restrict__ acc, const uint64_t* __restrict_
 }
 
 void keymac(ckks_ctx* c, uint64_t* acc, const uint64_t* D, const uint64_t* key, int level, uint64_t g) {
+  ProfScope ps(c, "keymac");
   const int l1 = level + 1, ext = l1 + c->alpha;
   const int nd = (l1 + c->alpha - 1) / c->alpha;
   hipLaunchKernelGGL(k_keymac, dim3(c->N / EW, ext, 2), dim3(EW), 0, c->stream, acc, D, key, nd, ext, l1, c->L,
@@ -241,6 +243,7 @@ static MDConst md_const(ckks_ctx* c, int level) {
 
 void moddown(ckks_ctx* c, uint64_t* acc, int level, uint64_t* out, const uint64_t* add0, uint64_t g_add0,
              const uint64_t* add1) {
+  ProfScope ps(c, "moddown");
   const size_t N = c->N;
   const int l1 = level + 1, ext = l1 + c->alpha;
   // P limbs back to coefficient form

@@ -48,6 +48,9 @@ _SIGS = {
     "ckks_ctx_moduli": (ctypes.c_int, [c_vp, c_vp]),
     "ckks_galois_element": (ctypes.c_int, [c_vp, ctypes.c_int64, c_u64p]),
     "ckks_sync": (ctypes.c_int, [c_vp]),
+    "ficgcn_profile_enable": (ctypes.c_int, [c_vp, ctypes.c_int]),
+    "ficgcn_profile_read": (ctypes.c_int, [c_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_uint64)]),
     "ckks_keygen": (ctypes.c_int, [c_vp, ctypes.c_uint64, c_vp, ctypes.c_size_t, ctypes.c_int,
                                    ctypes.POINTER(c_vp), ctypes.POINTER(c_vp)]),
     "ckks_keys_tags": (ctypes.c_int, [c_vp, c_vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
@@ -178,6 +181,14 @@ class Context:
 
     def ckks_sync(self):
         _check(lib().ckks_sync(self.h))
+
+    def ficgcn_profile_enable(self, on: bool):
+        _check(lib().ficgcn_profile_enable(self.h, int(on)))
+
+    def ficgcn_profile_read(self, kernel: str):
+        ms, n = ctypes.c_double(), ctypes.c_uint64()
+        _check(lib().ficgcn_profile_read(self.h, kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     # ---- buffers
     def ct_buffer(self, level: int, count: Optional[int] = None):
