@@ -145,6 +145,8 @@ def main():
     N = 1 << prm["log_n"]
     M = N // 2
     L = prm["n_q"]
+    ntt_cols = ctx.ckks_ntt_autotune(L + prm["n_p"])
+    log("NTT autotune (column, row workgroup widths): %s" % (ntt_cols,))
     plan = fg.Plan(ctx, rp, col, val, w.graph.n, dims, w.weights, activation=w.activation)
     info = plan.ficgcn_plan_info()
     steps_needed = plan.ficgcn_plan_rot_steps()
@@ -278,7 +280,7 @@ def main():
                config=dict(workload="%s-shape 2-layer x^2 GCN: %d nodes, %s, K=%d copies, CKKS N=2^%d, "
                            "%d+%d primes, %d input cts resident" % (args.config, w.graph.n, "-".join(map(str, dims)),
                                                                      K, prm["log_n"], L, prm["n_p"], n_in),
-                           form="batched (fused Inter-CA pass, hoisted rotations)"),
+                           form="batched (fused Inter-CA pass, hoisted rotations)", ntt_tiles=list(ntt_cols)),
                plain_ms=None if plain_ms is None else round(plain_ms, 3),
                speedup_vs_plain=None if plain_ms is None else round(plain_ms / ms_step, 3),
                plain_equals_batched=same, max_rel_err=err, keyswitch=ks, roofline=roofline,

@@ -476,6 +476,54 @@ ficgcn_status ckks_rescale(ckks_ctx* ctx, uint64_t* ct_dev, uint32_t level) {
   });
 }
 
+ficgcn_status ckks_ntt_autotune(ckks_ctx* ctx, uint32_t n_limbs, int32_t* cols_out) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    REQUIRE(ctx && n_limbs >= 1 && n_limbs <= (uint32_t)ctx->n_mod(), EINVAL_, "bad argument");
+    const size_t words = (size_t)n_limbs * ctx->N;
+    uint64_t* d = (uint64_t*)ctx->buf(16, words * 8);
+    HIPCHECK(hipMemsetAsync(d, 0, words * 8, ctx->stream));
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    const int saved[2] = {ctx->ntt_cols[0], ctx->ntt_cols[1]};
+    const bool prof = ctx->profiling;
+    ctx->profiling = false;
+    float best = 1e30f;
+    int bc[2] = {saved[0], saved[1]};
+    for (int c0 : {4, 8, 16})
+      for (int c1 : {2, 4, 8, 16}) {
+        ctx->ntt_cols[0] = c0;
+        ctx->ntt_cols[1] = c1;
+        ntt_fwd(ctx, d, (int)n_limbs, lm_q((int)n_limbs), 1, 0);   // warm-up
+        ntt_inv(ctx, d, (int)n_limbs, lm_q((int)n_limbs), 1, 0);
+        HIPCHECK(hipEventRecord(e0, ctx->stream));
+        for (int r = 0; r < 5; ++r) {
+          ntt_fwd(ctx, d, (int)n_limbs, lm_q((int)n_limbs), 1, 0);
+          ntt_inv(ctx, d, (int)n_limbs, lm_q((int)n_limbs), 1, 0);
+        }
+        HIPCHECK(hipEventRecord(e1, ctx->stream));
+        HIPCHECK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          bc[0] = c0;
+          bc[1] = c1;
+        }
+      }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->profiling = prof;
+    ctx->ntt_cols[0] = bc[0];
+    ctx->ntt_cols[1] = bc[1];
+    if (cols_out) {
+      cols_out[0] = bc[0];
+      cols_out[1] = bc[1];
+    }
+  });
+}
+
 ficgcn_status ficgcn_profile_enable(ckks_ctx* ctx, int on) {
   return guard([&] {
     REQUIRE(ctx, EINVAL_, "null context");

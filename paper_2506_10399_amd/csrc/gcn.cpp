@@ -18,9 +18,9 @@
 
 namespace ficgcn {
 
-void comb_fused(ckks_ctx* c, uint64_t* const* out_dev_ptrs, const uint64_t* const* in_dev_ptrs,
-                const uint64_t* const* pt_dev_ptrs, int K, int F, int F_out, int level, const uint64_t* w_dev,
-                const char* prof_name);
+void comb_fused(ckks_ctx* c, const std::vector<uint64_t*>& outs, const uint64_t* in_base, size_t in_stride,
+                const uint64_t* const* in_dev_ptrs, const PtrList& pts, int K, int F, int F_out, int level,
+                const void* w_dev, bool split, const char* prof_name);
 void zero_fill(ckks_ctx* c, uint64_t* p, size_t words);
 void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_layers, const double* const* weights,
                 const ficgcn_plan_opts& o);
@@ -55,19 +55,50 @@ static void ensure_weights(ckks_ctx* c, LayerPlan& lp) {
   HIPCHECK(hipMemcpy(lp.w_dev, h.data(), h.size() * 8, hipMemcpyHostToDevice));
 }
 
-// residue-only copy [F'][F][l1] for the fused kernel
-static uint64_t* weights_residues(ckks_ctx* c, LayerPlan& lp, int slot) {
+// weights of the fused pass, [l1][F][F'] in the form the kernel reads:
+// 26-bit halves (uint32 pairs) when every active prime is below 2^52, else residues
+static void ensure_fused_weights(ckks_ctx* c, LayerPlan& lp) {
+  if (lp.wf_dev) return;
   const int l1 = lp.level_in + 1;
-  const size_t n = (size_t)lp.f_out * lp.f_in * l1;
-  std::vector<uint64_t> h(n);
-  for (int l = 0; l < lp.f_out; ++l)
-    for (int f = 0; f < lp.f_in; ++f)
-      for (int i = 0; i < l1; ++i)
-        h[((size_t)l * lp.f_in + f) * l1 + i] = residue(lp.w_int[(size_t)f * lp.f_out + l], c->mod[i]);
-  uint64_t* d = (uint64_t*)c->buf(slot, n * 8);
-  HIPCHECK(hipMemcpyAsync(d, h.data(), n * 8, hipMemcpyHostToDevice, c->stream));
-  HIPCHECK(hipStreamSynchronize(c->stream));
-  return d;
+  lp.wf_split = c->mod[0] < (1ull << 52);
+  const size_t n = (size_t)l1 * lp.f_in * lp.f_out;
+  if (lp.wf_split) {
+    const int F_pad = (lp.f_out + 15) / 16 * 16;   // zero columns up to the kernel's unroll width
+    std::vector<uint32_t> h((size_t)2 * l1 * lp.f_in * F_pad, 0u);
+    for (int i = 0; i < l1; ++i)
+      for (int f = 0; f < lp.f_in; ++f)
+        for (int l = 0; l < lp.f_out; ++l) {
+          uint64_t r = residue(lp.w_int[(size_t)f * lp.f_out + l], c->mod[i]);
+          size_t o = (((size_t)i * lp.f_in + f) * F_pad + l) * 2;
+          h[o] = (uint32_t)(r & ((1u << 26) - 1));
+          h[o + 1] = (uint32_t)(r >> 26);
+        }
+    HIPCHECK(hipMalloc(&lp.wf_dev, h.size() * 4));
+    HIPCHECK(hipMemcpy(lp.wf_dev, h.data(), h.size() * 4, hipMemcpyHostToDevice));
+  } else {
+    std::vector<uint64_t> h(n);
+    for (int i = 0; i < l1; ++i)
+      for (int f = 0; f < lp.f_in; ++f)
+        for (int l = 0; l < lp.f_out; ++l)
+          h[((size_t)i * lp.f_in + f) * lp.f_out + l] = residue(lp.w_int[(size_t)f * lp.f_out + l], c->mod[i]);
+    HIPCHECK(hipMalloc(&lp.wf_dev, h.size() * 8));
+    HIPCHECK(hipMemcpy(lp.wf_dev, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+  }
+}
+
+// A batch of equally spaced buffers is read by base + stride (no pointer table).
+static bool strided(const uint64_t* const* p, size_t n, size_t min_words, const uint64_t*& base, size_t& stride) {
+  base = p[0];
+  if (n == 1) {
+    stride = min_words;
+    return true;
+  }
+  if (p[1] <= p[0]) return false;
+  stride = (size_t)(p[1] - p[0]);
+  if (stride < min_words) return false;
+  for (size_t i = 2; i < n; ++i)
+    if (p[i] != p[0] + i * stride) return false;
+  return true;
 }
 
 template <typename T>
@@ -229,13 +260,19 @@ void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const u
   if (lp.kind == 0) {
     const int F = lp.f_in, K = lp.K;
     if (mode == 1) {
-      std::vector<const uint64_t*> ins(in, in + n_in);
-      std::vector<const uint64_t*> pts(lp.ops.begin(), lp.ops.end());
-      uint64_t* const* od = upload_ptrs(c, pre, 30);
-      const uint64_t* const* idv = upload_ptrs(c, ins, 31);
-      const uint64_t* const* pdv = upload_ptrs(c, pts, 32);
-      uint64_t* wres = weights_residues(c, lp, 33);
-      comb_fused(c, od, idv, pdv, K, F, lp.f_out, lv, wres, "inter_fused");
+      ensure_fused_weights(c, lp);
+      if (K > PtrList::MAX) FICGCN_THROW(EPLAN_, "batched form supports at most 16 Inter-CA copies");
+      PtrList pts{};
+      for (int k = 0; k < K; ++k) pts.p[k] = lp.ops[k];
+      const uint64_t* base = nullptr;
+      size_t stride = 0;
+      const uint64_t* const* idv = nullptr;
+      if (!strided(in, n_in, ct_words, base, stride)) {
+        std::vector<const uint64_t*> ins(in, in + n_in);
+        idv = upload_ptrs(c, ins, 31);
+        base = nullptr;
+      }
+      comb_fused(c, pre, base, stride, idv, pts, K, F, lp.f_out, lv, lp.wf_dev, lp.wf_split, "inter_fused");
     } else {
       const int CH = 64;
       uint64_t* Z = (uint64_t*)c->buf(34, (size_t)CH * ct_words * 8);
@@ -275,11 +312,16 @@ void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const u
     std::vector<uint64_t*> colp(lp.f_out);
     for (int l = 0; l < lp.f_out; ++l) colp[l] = cols + (size_t)l * ct_words;
     if (mode == 1) {
-      std::vector<const uint64_t*> ins(in, in + n_in);
-      uint64_t* const* od = upload_ptrs(c, colp, 30);
-      const uint64_t* const* idv = upload_ptrs(c, ins, 31);
-      uint64_t* wres = weights_residues(c, lp, 33);
-      comb_fused(c, od, idv, nullptr, 0, F, lp.f_out, lv, wres, "comb_fused");
+      ensure_fused_weights(c, lp);
+      const uint64_t* base = nullptr;
+      size_t stride = 0;
+      const uint64_t* const* idv = nullptr;
+      if (!strided(in, n_in, ct_words, base, stride)) {
+        std::vector<const uint64_t*> ins(in, in + n_in);
+        idv = upload_ptrs(c, ins, 31);
+        base = nullptr;
+      }
+      comb_fused(c, colp, base, stride, idv, PtrList{}, 0, F, lp.f_out, lv, lp.wf_dev, lp.wf_split, "comb_fused");
     } else {
       for (int l = 0; l < lp.f_out; ++l) {
         zero_fill(c, colp[l], ct_words);

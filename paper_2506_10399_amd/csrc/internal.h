@@ -70,6 +70,7 @@ struct ckks_ctx {
   std::vector<uint64_t> h_psi, h_psi_s, h_ipsi, h_ipsi_s, h_ninv, h_ninv_s;   // host tables
   std::vector<ficgcn::Mod> h_mods;
   bool on_device = false;
+  int ntt_cols[2] = {16, 4};          // NTT workgroup width (column pass, row pass); autotuned
   hipStream_t stream = nullptr;
   int device = 0;
   std::map<std::pair<int, int>, ficgcn::BConv> modup;   // (level, digit)
@@ -135,6 +136,10 @@ void ntt_inv(ckks_ctx* c, uint64_t* base, int n_limbs, LimbMap map, int n_polys,
 struct PtrList {
   enum { MAX = 16 };
   const uint64_t* p[MAX];
+};
+struct OutList {
+  enum { MAX = 16 };
+  uint64_t* p[MAX];
 };
 void pmul_acc(ckks_ctx* c, uint64_t* acc, const PtrList& cts, const PtrList& pts, int k, int n_limbs);
 void smul_acc(ckks_ctx* c, uint64_t* acc, const PtrList& cts, const uint64_t* consts_dev, int k, int n_limbs);

@@ -5,158 +5,265 @@
 // powers psi^{2 brev(k) + 1} in bit-reversed order k.  Inverse: the
 // Gentleman-Sande mirror, then a multiply by N^{-1}.
 //
-// A limb of N = 2^16 words (512 KiB) exceeds the 160 KiB LDS, so each
-// transform runs as two passes of N = N1 * N2:
-//   column pass : the stages m < N1 touch only elements j0 + k*N2 (k < N1) of
-//                 one column j0; a workgroup stages 16 adjacent columns
-//                 (128-byte rows, coalesced) in LDS and runs those stages;
-//   row pass    : the stages m >= N1 stay inside contiguous chunks of N2
-//                 words; a workgroup stages 16 chunks.
-// Each pass reads and writes the limb once, so a transform moves 4 N words.
+// A limb of N = 2^16 words (512 KiB) exceeds the LDS, so each transform runs
+// as two passes of N = N1 * N2:
+//   column pass: the stages m < N1 touch only the N1 elements j0 + k*N2 of one
+//                column j0 (a C = N1-point sub-transform);
+//   row pass   : the stages m >= N1 stay inside one contiguous chunk of C = N2
+//                words.
+// Inside a pass, TPC = 2^floor(log C / 2) threads share one sub-transform and
+// each holds EPT = C / TPC elements in registers:
+//   strided layout     thread r holds elements r + TPC*u  (u < EPT): the
+//                      stages with butterfly distance t >= TPC are local;
+//   contiguous layout  thread r holds elements r*EPT + v (v < EPT): the stages
+//                      with t < TPC are local.
+// One LDS transpose switches layouts (a second one in the row pass keeps the
+// global loads and stores coalesced).  Every twiddle a thread needs is read
+// before its stages run.  A workgroup handles COLS columns (column pass) or
+// chunks (row pass); COLS is picked per ring degree by the autotuner.
 #include "internal.h"
 
 namespace ficgcn {
-
-constexpr int NTT_THREADS = 256;
-constexpr int NTT_TILE = 16;   // columns (column pass) or chunks (row pass) per workgroup
 
 __device__ __forceinline__ bool skip_limb(int limb, int poly, int skip_alpha, int skip_q) {
   return skip_alpha > 0 && limb < skip_q && limb / skip_alpha == poly;
 }
 
-template <int LOGC, bool INV>
-__global__ __launch_bounds__(NTT_THREADS) void k_ntt_cols(uint64_t* __restrict__ base, int log_n, LimbMap map,
-                                                        size_t poly_stride, const uint64_t* __restrict__ tw,
-                                                        const uint64_t* __restrict__ tws, const Mod* __restrict__ mods,
-                                                        const uint64_t* __restrict__ ninv,
-                                                        const uint64_t* __restrict__ ninv_s, int skip_alpha,
-                                                        int skip_q) {
+// forward CT butterfly / inverse GS butterfly on residues in [0, q)
+__device__ __forceinline__ void bf_fwd(uint64_t& x, uint64_t& y, uint64_t w, uint64_t ws, uint64_t q) {
+  uint64_t v = mul_shoup(y, w, ws, q);
+  y = sub_mod(x, v, q);
+  x = add_mod(x, v, q);
+}
+__device__ __forceinline__ void bf_inv(uint64_t& x, uint64_t& y, uint64_t w, uint64_t ws, uint64_t q) {
+  uint64_t d = sub_mod(x, y, q);
+  x = add_mod(x, y, q);
+  y = mul_shoup(d, w, ws, q);
+}
+
+// ROW: row pass (sub-transform = contiguous chunk), else column pass.
+template <int LOGC, int COLS, bool INV, bool ROW>
+__global__ __launch_bounds__((1 << (LOGC / 2)) * COLS) void k_ntt_pass(
+    uint64_t* __restrict__ base, int log_n, LimbMap map, size_t poly_stride, const uint64_t* __restrict__ tw,
+    const uint64_t* __restrict__ tws, const Mod* __restrict__ mods, const uint64_t* __restrict__ ninv,
+    const uint64_t* __restrict__ ninv_s, int skip_alpha, int skip_q) {
   constexpr int C = 1 << LOGC;
-  __shared__ uint64_t s[C * NTT_TILE];
+  constexpr int LT = LOGC / 2;
+  constexpr int TPC = 1 << LT;
+  constexpr int LE = LOGC - LT;
+  constexpr int EPT = 1 << LE;
+  // one pad word per EPT elements (row pass) or one group width per EPT rows
+  // (column pass) keeps the contiguous-layout accesses off a single bank set
+  __shared__ uint64_t s[COLS * (C + TPC)];
   const int limb = blockIdx.y, poly = blockIdx.z;
   if (skip_limb(limb, poly, skip_alpha, skip_q)) return;
   const int N = 1 << log_n;
-  const int stride = N >> LOGC;
   const int mi = lm_mod(map, limb);
   const uint64_t q = mods[mi].q;
   uint64_t* a = base + poly * poly_stride + (size_t)limb * N;
   const uint64_t* W = tw + (size_t)mi * N;
   const uint64_t* Ws = tws + (size_t)mi * N;
-  const int col0 = blockIdx.x * NTT_TILE;
-  for (int e = threadIdx.x; e < C * NTT_TILE; e += NTT_THREADS) {
-    int r = e / NTT_TILE, cc = e % NTT_TILE;
-    s[e] = a[(size_t)r * stride + col0 + cc];
-  }
-  __syncthreads();
-#pragma unroll 1
-  for (int it = 0; it < LOGC; ++it) {
-    const int st = INV ? (LOGC - 1 - it) : it;
-    const int m = 1 << st;
-    const int t = C >> (st + 1);
-    for (int b = threadIdx.x; b < (C / 2) * NTT_TILE; b += NTT_THREADS) {
-      int cc = b % NTT_TILE, k = b / NTT_TILE;
-      int i = k / t, r = k % t;
-      int j = i * 2 * t + r;
-      uint64_t w = W[m + i], ws = Ws[m + i];
-      uint64_t* x = &s[j * NTT_TILE + cc];
-      uint64_t* y = &s[(j + t) * NTT_TILE + cc];
-      uint64_t U = *x, V = *y;
-      if (!INV) {
-        V = mul_shoup(V, w, ws, q);
-        *x = add_mod(U, V, q);
-        *y = sub_mod(U, V, q);
-      } else {
-        *x = add_mod(U, V, q);
-        *y = mul_shoup(sub_mod(U, V, q), w, ws, q);
+  const int tid = threadIdx.x;
+  // column pass: consecutive threads = consecutive columns (coalesced rows);
+  // row pass: consecutive threads = consecutive elements of one chunk
+  const int col = ROW ? tid / TPC : tid % COLS;
+  const int r = ROW ? tid % TPC : tid / COLS;
+  const int unit = blockIdx.x * COLS + col;           // column index j0 or chunk index
+  const int stride = ROW ? 1 : (N >> LOGC);           // element step inside the sub-transform
+  uint64_t* g = ROW ? a + (size_t)unit * C : a + unit;
+  // global twiddle index of group i at local stage st
+  auto twi = [&](int st, int i) { return ROW ? ((N >> LOGC) << st) + unit * (1 << st) + i : (1 << st) + i; };
+  // LDS element index of element e of this unit
+  auto sidx = [&](int e) { return ROW ? col * (C + TPC) + e + e / EPT : e * COLS + col + (e / EPT) * COLS; };
+  uint64_t x[EPT];
+
+  if (!INV) {
+    // ---- load strided: x[u] = element r + TPC u
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) x[u] = g[(size_t)(r + TPC * u) * stride];
+    // ---- stages 0..LE-1 (t >= TPC) in registers
+    {
+      uint64_t w[EPT], ws[EPT];
+#pragma unroll
+      for (int st = 0; st < LE; ++st)
+#pragma unroll
+        for (int i = 0; i < (1 << st); ++i) {
+          int k = twi(st, i);
+          w[(1 << st) + i - 1] = W[k];
+          ws[(1 << st) + i - 1] = Ws[k];
+        }
+#pragma unroll
+      for (int st = 0; st < LE; ++st) {
+        const int tu = EPT >> (st + 1);
+#pragma unroll
+        for (int u = 0; u < EPT; ++u)
+          if ((u & tu) == 0) {
+            const int i = u / (2 * tu);
+            bf_fwd(x[u], x[u + tu], w[(1 << st) + i - 1], ws[(1 << st) + i - 1], q);
+          }
       }
     }
+    // ---- transpose to the contiguous layout
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) s[sidx(r + TPC * u)] = x[u];
     __syncthreads();
-  }
-  const uint64_t ni = INV ? ninv[mi] : 0, nis = INV ? ninv_s[mi] : 0;
-  for (int e = threadIdx.x; e < C * NTT_TILE; e += NTT_THREADS) {
-    int r = e / NTT_TILE, cc = e % NTT_TILE;
-    uint64_t v = s[e];
-    if (INV) v = mul_shoup(v, ni, nis, q);
-    a[(size_t)r * stride + col0 + cc] = v;
+#pragma unroll
+    for (int v = 0; v < EPT; ++v) x[v] = s[sidx(r * EPT + v)];
+    // ---- stages LE..LOGC-1 (t < TPC), element r*EPT + v
+    {
+      uint64_t w[EPT], ws[EPT];   // at most EPT - 1 twiddles in these stages
+      int pos = 0;
+#pragma unroll
+      for (int st = LE; st < LOGC; ++st) {
+        const int t = C >> (st + 1);
+        const int ng = EPT / (2 * t) > 0 ? EPT / (2 * t) : 1;   // groups touched by this thread
+#pragma unroll
+        for (int gi = 0; gi < ng; ++gi) {
+          int i = (r * EPT) / (2 * t) + gi;
+          int k = twi(st, i);
+          w[pos] = W[k];
+          ws[pos] = Ws[k];
+          ++pos;
+        }
+      }
+      pos = 0;
+#pragma unroll
+      for (int st = LE; st < LOGC; ++st) {
+        const int t = C >> (st + 1);
+        const int ng = EPT / (2 * t) > 0 ? EPT / (2 * t) : 1;
+#pragma unroll
+        for (int v = 0; v < EPT; ++v)
+          if ((v & t) == 0) {
+            const int gi = v / (2 * t);
+            bf_fwd(x[v], x[v + t], w[pos + gi], ws[pos + gi], q);
+          }
+        pos += ng;
+      }
+    }
+    if (ROW) {
+      // back to the strided layout for a coalesced store
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < EPT; ++v) s[sidx(r * EPT + v)] = x[v];
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) g[(size_t)(r + TPC * u) * stride] = s[sidx(r + TPC * u)];
+    } else {
+#pragma unroll
+      for (int v = 0; v < EPT; ++v) g[(size_t)(r * EPT + v) * stride] = x[v];
+    }
+  } else {
+    // ---- inverse: load in the contiguous layout
+    if (ROW) {
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) s[sidx(r + TPC * u)] = g[(size_t)(r + TPC * u) * stride];
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < EPT; ++v) x[v] = s[sidx(r * EPT + v)];
+      __syncthreads();
+    } else {
+#pragma unroll
+      for (int v = 0; v < EPT; ++v) x[v] = g[(size_t)(r * EPT + v) * stride];
+    }
+    // ---- stages LOGC-1..LE (t < TPC) in registers
+    {
+      uint64_t w[EPT], ws[EPT];   // at most EPT - 1 twiddles in these stages
+      int pos = 0;
+#pragma unroll
+      for (int st = LOGC - 1; st >= LE; --st) {
+        const int t = C >> (st + 1);
+        const int ng = EPT / (2 * t) > 0 ? EPT / (2 * t) : 1;
+#pragma unroll
+        for (int gi = 0; gi < ng; ++gi) {
+          int i = (r * EPT) / (2 * t) + gi;
+          int k = twi(st, i);
+          w[pos] = W[k];
+          ws[pos] = Ws[k];
+          ++pos;
+        }
+      }
+      pos = 0;
+#pragma unroll
+      for (int st = LOGC - 1; st >= LE; --st) {
+        const int t = C >> (st + 1);
+        const int ng = EPT / (2 * t) > 0 ? EPT / (2 * t) : 1;
+#pragma unroll
+        for (int v = 0; v < EPT; ++v)
+          if ((v & t) == 0) {
+            const int gi = v / (2 * t);
+            bf_inv(x[v], x[v + t], w[pos + gi], ws[pos + gi], q);
+          }
+        pos += ng;
+      }
+    }
+    // ---- transpose to the strided layout
+#pragma unroll
+    for (int v = 0; v < EPT; ++v) s[sidx(r * EPT + v)] = x[v];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) x[u] = s[sidx(r + TPC * u)];
+    // ---- stages LE-1..0 (t >= TPC)
+    {
+      uint64_t w[EPT], ws[EPT];
+#pragma unroll
+      for (int st = 0; st < LE; ++st)
+#pragma unroll
+        for (int i = 0; i < (1 << st); ++i) {
+          int k = twi(st, i);
+          w[(1 << st) + i - 1] = W[k];
+          ws[(1 << st) + i - 1] = Ws[k];
+        }
+#pragma unroll
+      for (int st = LE - 1; st >= 0; --st) {
+        const int tu = EPT >> (st + 1);
+#pragma unroll
+        for (int u = 0; u < EPT; ++u)
+          if ((u & tu) == 0) {
+            const int i = u / (2 * tu);
+            bf_inv(x[u], x[u + tu], w[(1 << st) + i - 1], ws[(1 << st) + i - 1], q);
+          }
+      }
+    }
+    if (!ROW) {
+      const uint64_t ni = ninv[mi], nis = ninv_s[mi];
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) x[u] = mul_shoup(x[u], ni, nis, q);
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) g[(size_t)(r + TPC * u) * stride] = x[u];
   }
 }
 
-template <int LOGC, bool INV>
-__global__ __launch_bounds__(NTT_THREADS) void k_ntt_rows(uint64_t* __restrict__ base, int log_n, LimbMap map,
-                                                        size_t poly_stride, const uint64_t* __restrict__ tw,
-                                                        const uint64_t* __restrict__ tws, const Mod* __restrict__ mods,
-                                                        int skip_alpha, int skip_q) {
-  constexpr int C = 1 << LOGC;
-  __shared__ uint64_t s[C * NTT_TILE];
-  const int limb = blockIdx.y, poly = blockIdx.z;
-  if (skip_limb(limb, poly, skip_alpha, skip_q)) return;
-  const int N = 1 << log_n;
-  const int N1 = N >> LOGC;   // number of chunks = first-pass length
-  const int mi = lm_mod(map, limb);
-  const uint64_t q = mods[mi].q;
-  uint64_t* a = base + poly * poly_stride + (size_t)limb * N;
-  const uint64_t* W = tw + (size_t)mi * N;
-  const uint64_t* Ws = tws + (size_t)mi * N;
-  const int ch0 = blockIdx.x * NTT_TILE;
-  uint64_t* g = a + (size_t)ch0 * C;
-  for (int e = threadIdx.x; e < C * NTT_TILE; e += NTT_THREADS) s[e] = g[e];
-  __syncthreads();
-#pragma unroll 1
-  for (int it = 0; it < LOGC; ++it) {
-    const int st = INV ? (LOGC - 1 - it) : it;
-    const int m = N1 << st;   // global stage
-    const int t = C >> (st + 1);
-    for (int b = threadIdx.x; b < (C / 2) * NTT_TILE; b += NTT_THREADS) {
-      int cc = b / (C / 2), k = b % (C / 2);
-      int il = k / t, r = k % t;
-      int j = il * 2 * t + r;
-      int ti = m + (ch0 + cc) * (1 << st) + il;
-      uint64_t w = W[ti], ws = Ws[ti];
-      uint64_t* x = &s[cc * C + j];
-      uint64_t* y = x + t;
-      uint64_t U = *x, V = *y;
-      if (!INV) {
-        V = mul_shoup(V, w, ws, q);
-        *x = add_mod(U, V, q);
-        *y = sub_mod(U, V, q);
-      } else {
-        *x = add_mod(U, V, q);
-        *y = mul_shoup(sub_mod(U, V, q), w, ws, q);
-      }
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < C * NTT_TILE; e += NTT_THREADS) g[e] = s[e];
-}
-
-template <bool INV>
-static void launch_cols(int logc, dim3 grid, hipStream_t st, uint64_t* base, int log_n, LimbMap map, size_t ps,
-                        const uint64_t* tw, const uint64_t* tws, const Mod* mods, const uint64_t* ni,
-                        const uint64_t* nis, int sa, int sq) {
+// ---- launch selection --------------------------------------------------------
+template <bool INV, bool ROW, int COLS>
+static void launch_c(int logc, dim3 grid, hipStream_t st, uint64_t* base, int log_n, LimbMap map, size_t ps,
+                     const Tables& t, int sa, int sq) {
+  const uint64_t* tw = INV ? t.ipsi : t.psi;
+  const uint64_t* tws = INV ? t.ipsi_s : t.psi_s;
   switch (logc) {
-#define CASE(L)                                                                                                \
-  case L:                                                                                                      \
-    hipLaunchKernelGGL((k_ntt_cols<L, INV>), grid, dim3(NTT_THREADS), 0, st, base, log_n, map, ps, tw, tws, mods, \
-                       ni, nis, sa, sq);                                                                       \
+#define CASE(L)                                                                                                   \
+  case L:                                                                                                         \
+    hipLaunchKernelGGL((k_ntt_pass<L, COLS, INV, ROW>), grid, dim3((1 << (L / 2)) * COLS), 0, st, base, log_n, map, \
+                       ps, tw, tws, t.mods, t.ninv, t.ninv_s, sa, sq);                                            \
     break;
-    CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+    CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9)
 #undef CASE
     default: FICGCN_THROW(EINVAL_, "unsupported ring degree");
   }
 }
 
-template <bool INV>
-static void launch_rows(int logc, dim3 grid, hipStream_t st, uint64_t* base, int log_n, LimbMap map, size_t ps,
-                        const uint64_t* tw, const uint64_t* tws, const Mod* mods, int sa, int sq) {
-  switch (logc) {
-#define CASE(L)                                                                                                 \
-  case L:                                                                                                       \
-    hipLaunchKernelGGL((k_ntt_rows<L, INV>), grid, dim3(NTT_THREADS), 0, st, base, log_n, map, ps, tw, tws, mods, \
-                       sa, sq);                                                                                 \
-    break;
-    CASE(5) CASE(6) CASE(7) CASE(8) CASE(9)
-#undef CASE
-    default: FICGCN_THROW(EINVAL_, "unsupported ring degree");
+template <bool INV, bool ROW>
+static void launch(ckks_ctx* c, int logc, int cols, uint64_t* base, int n_limbs, LimbMap map, int n_polys,
+                   size_t ps, int sa, int sq) {
+  const int units = c->N >> logc;   // columns (column pass) or chunks (row pass)
+  if (units % cols) cols = 1;
+  dim3 grid(units / cols, n_limbs, n_polys);
+  switch (cols) {
+    case 1: launch_c<INV, ROW, 1>(logc, grid, c->stream, base, c->log_n, map, ps, c->t, sa, sq); break;
+    case 2: launch_c<INV, ROW, 2>(logc, grid, c->stream, base, c->log_n, map, ps, c->t, sa, sq); break;
+    case 4: launch_c<INV, ROW, 4>(logc, grid, c->stream, base, c->log_n, map, ps, c->t, sa, sq); break;
+    case 8: launch_c<INV, ROW, 8>(logc, grid, c->stream, base, c->log_n, map, ps, c->t, sa, sq); break;
+    default: launch_c<INV, ROW, 16>(logc, grid, c->stream, base, c->log_n, map, ps, c->t, sa, sq); break;
   }
 }
 
@@ -171,12 +278,8 @@ void ntt_fwd(ckks_ctx* c, uint64_t* base, int n_limbs, LimbMap map, int n_polys,
   if (n_limbs <= 0 || n_polys <= 0) return;
   int l1, l2;
   split(c->log_n, l1, l2);
-  dim3 g1((c->N >> l1) / NTT_TILE, n_limbs, n_polys);
-  launch_cols<false>(l1, g1, c->stream, base, c->log_n, map, poly_stride, c->t.psi, c->t.psi_s, c->t.mods, nullptr,
-                     nullptr, skip_alpha, skip_q);
-  dim3 g2((c->N >> l2) / NTT_TILE, n_limbs, n_polys);
-  launch_rows<false>(l2, g2, c->stream, base, c->log_n, map, poly_stride, c->t.psi, c->t.psi_s, c->t.mods, skip_alpha,
-                     skip_q);
+  launch<false, false>(c, l1, c->ntt_cols[0], base, n_limbs, map, n_polys, poly_stride, skip_alpha, skip_q);
+  launch<false, true>(c, l2, c->ntt_cols[1], base, n_limbs, map, n_polys, poly_stride, skip_alpha, skip_q);
   HIPCHECK(hipGetLastError());
 }
 
@@ -185,11 +288,8 @@ void ntt_inv(ckks_ctx* c, uint64_t* base, int n_limbs, LimbMap map, int n_polys,
   if (n_limbs <= 0 || n_polys <= 0) return;
   int l1, l2;
   split(c->log_n, l1, l2);
-  dim3 g2((c->N >> l2) / NTT_TILE, n_limbs, n_polys);
-  launch_rows<true>(l2, g2, c->stream, base, c->log_n, map, poly_stride, c->t.ipsi, c->t.ipsi_s, c->t.mods, 0, 0);
-  dim3 g1((c->N >> l1) / NTT_TILE, n_limbs, n_polys);
-  launch_cols<true>(l1, g1, c->stream, base, c->log_n, map, poly_stride, c->t.ipsi, c->t.ipsi_s, c->t.mods,
-                    c->t.ninv, c->t.ninv_s, 0, 0);
+  launch<true, true>(c, l2, c->ntt_cols[1], base, n_limbs, map, n_polys, poly_stride, 0, 0);
+  launch<true, false>(c, l1, c->ntt_cols[0], base, n_limbs, map, n_polys, poly_stride, 0, 0);
   HIPCHECK(hipGetLastError());
 }
 

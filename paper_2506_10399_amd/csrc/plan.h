@@ -31,7 +31,9 @@ struct LayerPlan {
   std::vector<uint64_t*> ops;
   uint64_t* ops_block = nullptr;   // one allocation for all operands
   // device constants for the fused kernels (built on first use)
-  uint64_t* w_dev = nullptr;       // [f_in][f_out][level+1][2] residues + Shoup
+  uint64_t* w_dev = nullptr;       // [f_out][f_in][level+1][2] residues + Shoup (per-operation form)
+  void* wf_dev = nullptr;          // fused-pass weights [level+1][f_in][f_out] (split halves or residues)
+  bool wf_split = false;
   int n_packed() const { return kind == 0 ? f_out : (f_out + t - 1) / t; }
   int n_in_cts() const { return kind == 0 ? K * f_in : f_in; }
 };

@@ -48,6 +48,7 @@ _SIGS = {
     "ckks_ctx_moduli": (ctypes.c_int, [c_vp, c_vp]),
     "ckks_galois_element": (ctypes.c_int, [c_vp, ctypes.c_int64, c_u64p]),
     "ckks_sync": (ctypes.c_int, [c_vp]),
+    "ckks_ntt_autotune": (ctypes.c_int, [c_vp, ctypes.c_uint32, c_vp]),
     "ficgcn_profile_enable": (ctypes.c_int, [c_vp, ctypes.c_int]),
     "ficgcn_profile_read": (ctypes.c_int, [c_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_uint64)]),
@@ -181,6 +182,11 @@ class Context:
 
     def ckks_sync(self):
         _check(lib().ckks_sync(self.h))
+
+    def ckks_ntt_autotune(self, n_limbs: int):
+        out = np.zeros(2, dtype=np.int32)
+        _check(lib().ckks_ntt_autotune(self.h, n_limbs, _ptr(out)))
+        return int(out[0]), int(out[1])
 
     def ficgcn_profile_enable(self, on: bool):
         _check(lib().ficgcn_profile_enable(self.h, int(on)))
