@@ -5,8 +5,11 @@
 //          Inter-CA copy, scalar MAC per weight, one key switch (ModUp,
 //          inner product, ModDown) per rotation, one rescale per ciphertext;
 //  batched (mode 1): the Inter-CA aggregation and the combination fused in
-//          one pass over the inputs, every rotation of a source hoisted on
-//          one ModUp, constants resident on the device.
+//          one pass over the inputs; the rotations of each stage (packing,
+//          baby steps, giant steps, the diagonal shifts) and the
+//          relinearisations of a layer run as one key-switch batch, the
+//          rotations of a source hoisted on one ModUp and the masked sums
+//          folded into the batch's final ModDown step; rescales batched.
 // Words agree because every step is exact modular arithmetic and a rotation
 // is defined as ModUp, automorphism, inner product, ModDown in both forms.
 #include <algorithm>
@@ -14,6 +17,7 @@
 #include <set>
 
 #include "../../include/ficgcn.h"
+#include "ks_batch.h"
 #include "plan.h"
 
 namespace ficgcn {
@@ -128,38 +132,8 @@ static void rotate_one(ckks_ctx* c, const ckks_keys* ek, const uint64_t* in, int
   moddown(c, acc, level, out, in, g, nullptr);
 }
 
-struct Hoisted {
-  ckks_ctx* c;
-  const ckks_keys* ek;
-  const uint64_t* in;
-  int level;
-  uint64_t* D;
-  void init(ckks_ctx* cc, const ckks_keys* k, const uint64_t* x, int lv, int slot) {
-    c = cc;
-    ek = k;
-    in = x;
-    level = lv;
-    const int l1 = lv + 1, ext = l1 + c->alpha, nd = (l1 + c->alpha - 1) / c->alpha;
-    D = (uint64_t*)c->buf(slot, (size_t)nd * ext * c->N * 8);
-    modup(c, x + (size_t)l1 * c->N, lv, D);
-  }
-  void rotate(int64_t step, uint64_t* out) {
-    const int l1 = level + 1, ext = l1 + c->alpha;
-    uint64_t g = galois_elt(c, step);
-    if (g == 1) {
-      copy_d2d(c, out, in, (size_t)2 * l1 * c->N * 8);
-      return;
-    }
-    auto it = ek->swk.find(g);
-    if (it == ek->swk.end()) FICGCN_THROW(ENOKEY_, "missing rotation key for step " + std::to_string(step));
-    uint64_t* acc = (uint64_t*)c->buf(43, (size_t)2 * ext * c->N * 8);
-    keymac(c, acc, D, it->second, level, g);
-    moddown(c, acc, level, out, in, g, nullptr);
-  }
-};
-
-static void aggregate(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, LayerPlan& lp, int g, const uint64_t* y,
-                      uint64_t* out, int mode) {
+// SpIntra-CA of one packed ciphertext, one operation per call (plain form)
+static void aggregate(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, int g, const uint64_t* y, uint64_t* out) {
   const size_t N = c->N;
   const int lv = lp.level_agg, l1 = lv + 1;
   const size_t ct_words = (size_t)2 * l1 * N;
@@ -173,19 +147,14 @@ static void aggregate(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, LayerPla
     b.p[0] = pt;
     pmul_acc(c, out, a, b, 1, l1);
   };
-  Hoisted h;
   if (lp.family == 1) {
-    if (mode == 1) h.init(c, ek, y, lv, 42);
     for (size_t si = 0; si < ns; ++si) {
       int64_t d = lp.shifts[si];
       if (d == 0) {
         mac(y, mask(si));
         continue;
       }
-      if (mode == 1)
-        h.rotate(d, rt);
-      else
-        rotate_one(c, ek, y, lv, d, rt);
+      rotate_one(c, ek, y, lv, d, rt);
       mac(rt, mask(si));
     }
   } else {
@@ -200,14 +169,10 @@ static void aggregate(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, LayerPla
     // baby rotations of y, kept for every giant step
     std::map<int64_t, uint64_t*> rb;
     uint64_t* bb = (uint64_t*)c->buf(45, std::max<size_t>(1, babies.size()) * ct_words * 8);
-    if (mode == 1 && !babies.empty()) h.init(c, ek, y, lv, 42);
     size_t bi = 0;
     for (int64_t b : babies) {
       uint64_t* dst = bb + (bi++) * ct_words;
-      if (mode == 1)
-        h.rotate(b, dst);
-      else
-        rotate_one(c, ek, y, lv, b, dst);
+      rotate_one(c, ek, y, lv, b, dst);
       rb[b] = dst;
     }
     uint64_t* inner = (uint64_t*)c->buf(46, ct_words * 8);
@@ -230,6 +195,140 @@ static void aggregate(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, LayerPla
     }
   }
   rescale_inplace(c, out, lv);
+}
+
+// Galois element and switching key of a rotation step; null key for the identity
+static const uint64_t* rot_key(ckks_ctx* c, const ckks_keys* ek, int64_t step, uint64_t& g) {
+  g = galois_elt(c, step);
+  if (g == 1) return nullptr;
+  auto it = ek->swk.find(g);
+  if (it == ek->swk.end()) FICGCN_THROW(ENOKEY_, "missing rotation key for step " + std::to_string(step));
+  return it->second;
+}
+
+// SpIntra-CA of every packed ciphertext Y[g] into outs[g] (batched form)
+static void aggregate_batched(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, const std::vector<uint64_t*>& Y,
+                              const std::vector<uint64_t*>& outs) {
+  const size_t N = c->N;
+  const int lv = lp.level_agg, l1 = lv + 1;
+  const size_t ct_words = (size_t)2 * l1 * N;
+  const size_t ns = lp.shifts.size();
+  const int np = (int)Y.size();
+  auto mask = [&](int g, size_t si) { return (const uint64_t*)lp.ops[(size_t)g * ns + si]; };
+  std::vector<const uint64_t*> ysrc(np);
+  for (int g = 0; g < np; ++g) ysrc[g] = Y[g] + (size_t)l1 * N;
+  if (lp.family == 1) {
+    // out_g = sum_delta Rot_delta(Y_g) (.) mask_delta: identity terms first,
+    // every rotation (hoisted on Y_g's ModUp) accumulated in the final ModDown step
+    std::vector<std::vector<MacTerm>> init(np);
+    std::vector<KSJob> jobs;
+    for (int g = 0; g < np; ++g)
+      for (size_t si = 0; si < ns; ++si) {
+        uint64_t gal;
+        const uint64_t* key = rot_key(c, ek, lp.shifts[si], gal);
+        if (!key)
+          init[g].push_back(MacTerm{Y[g], mask(g, si)});
+        else
+          jobs.push_back(KSJob{key, Y[g], nullptr, mask(g, si), gal, g, g});
+      }
+    group_mac(c, lv, init, outs, false);
+    keyswitch_batch(c, lv, ysrc, jobs, outs, true);
+  } else {
+    // baby-step giant-step: Rot_{gi G}( sum_b Rot_b(Y_g) (.) mask'_{gi,b} )
+    const int64_t G = lp.G;
+    std::set<int64_t> babies;
+    std::map<int64_t, std::vector<size_t>> giants;
+    for (size_t si = 0; si < ns; ++si) {
+      const int64_t d = lp.shifts[si];
+      if (fmodp(d, G)) babies.insert(fmodp(d, G));
+      giants[fdiv(d, G)].push_back(si);
+    }
+    const int nb = (int)babies.size();
+    std::map<int64_t, int> bpos;
+    for (int64_t b : babies) bpos.emplace(b, (int)bpos.size());
+    // baby rotations of every packed ciphertext, hoisted on its ModUp
+    uint64_t* bb = (uint64_t*)c->buf(70, std::max<size_t>(1, (size_t)np * nb) * ct_words * 8);
+    auto baby = [&](int g, int64_t b) { return bb + ((size_t)g * nb + bpos.at(b)) * ct_words; };
+    {
+      std::vector<KSJob> jobs;
+      std::vector<uint64_t*> bouts;
+      for (int g = 0; g < np; ++g)
+        for (int64_t b : babies) {
+          uint64_t gal;
+          const uint64_t* key = rot_key(c, ek, b, gal);
+          if (!key) {
+            copy_d2d(c, baby(g, b), Y[g], ct_words * 8);
+            continue;
+          }
+          jobs.push_back(KSJob{key, Y[g], nullptr, nullptr, gal, g, (int)bouts.size()});
+          bouts.push_back(baby(g, b));
+        }
+      keyswitch_batch(c, lv, ysrc, jobs, bouts, false);
+    }
+    // inner sums: giant 0 straight into the output, the others into buffers
+    int n_inner = 0;
+    for (auto& kv : giants) n_inner += kv.first != 0;
+    uint64_t* ib = (uint64_t*)c->buf(71, std::max<size_t>(1, (size_t)np * n_inner) * ct_words * 8);
+    std::vector<std::vector<MacTerm>> groups;
+    std::vector<uint64_t*> gouts;
+    std::vector<const uint64_t*> isrc;
+    std::vector<std::vector<MacTerm>> ident(np);
+    std::vector<KSJob> jobs;
+    for (int g = 0; g < np; ++g) {
+      if (!giants.count(0)) {
+        groups.emplace_back();   // an empty group clears the output
+        gouts.push_back(outs[g]);
+      }
+      for (auto& kv : giants) {
+        std::vector<MacTerm> terms;
+        for (size_t si : kv.second) {
+          const int64_t b = fmodp(lp.shifts[si], G);
+          terms.push_back(MacTerm{b ? baby(g, b) : Y[g], mask(g, si)});
+        }
+        if (kv.first == 0) {
+          groups.push_back(terms);
+          gouts.push_back(outs[g]);
+          continue;
+        }
+        uint64_t* inner = ib + isrc.size() * ct_words;
+        groups.push_back(terms);
+        gouts.push_back(inner);
+        uint64_t gal;
+        const uint64_t* key = rot_key(c, ek, kv.first * G, gal);
+        if (!key) {
+          ident[g].push_back(MacTerm{inner, nullptr});
+        } else {
+          jobs.push_back(KSJob{key, inner, nullptr, nullptr, gal, (int)isrc.size(), g});
+        }
+        isrc.push_back(inner + (size_t)l1 * N);
+      }
+    }
+    group_mac(c, lv, groups, gouts, false);
+    // giant rotations summed into the outputs by the final ModDown step
+    keyswitch_batch(c, lv, isrc, jobs, outs, true);
+    group_mac(c, lv, ident, outs, true);
+  }
+  rescale_batch(c, lv, outs);
+}
+
+// Layer outputs squared and relinearised (batched form): out_i = Relin(pre_i (x) pre_i)
+static void activation_batched(ckks_ctx* c, const ckks_keys* ek, int lo, const std::vector<uint64_t*>& pre,
+                               uint64_t* const* out) {
+  const size_t N = c->N, l1 = lo + 1;
+  const size_t n = pre.size();
+  uint64_t* d = (uint64_t*)c->buf(48, n * 3 * l1 * N * 8);
+  std::vector<TensorJob> tj(n);
+  std::vector<const uint64_t*> srcs(n);
+  std::vector<KSJob> jobs(n);
+  std::vector<uint64_t*> outs(out, out + n);
+  for (size_t i = 0; i < n; ++i) {
+    uint64_t* di = d + i * 3 * l1 * N;
+    tj[i] = TensorJob{pre[i], pre[i], di};
+    srcs[i] = di + 2 * l1 * N;
+    jobs[i] = KSJob{ek->swk.at(0), di, di + l1 * N, nullptr, 1, (int)i, (int)i};
+  }
+  tensor_batch(c, lo, tj);
+  keyswitch_batch(c, lo, srcs, jobs, outs, false);
 }
 
 void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const uint64_t* const* in, size_t n_in,
@@ -301,9 +400,14 @@ void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const u
           }
       }
     }
-    for (int l = 0; l < lp.f_out; ++l) {
-      rescale_inplace(c, pre[l], lv);
-      rescale_inplace(c, pre[l], lv - 1);
+    if (mode == 1) {
+      rescale_batch(c, lv, pre);
+      rescale_batch(c, lv - 1, pre);
+    } else {
+      for (int l = 0; l < lp.f_out; ++l) {
+        rescale_inplace(c, pre[l], lv);
+        rescale_inplace(c, pre[l], lv - 1);
+      }
     }
   } else {
     // combination at one column per ciphertext
@@ -335,23 +439,55 @@ void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const u
     }
     int lvc = lv;
     for (int r = 0; r < lp.n_rescale_comb; ++r) {
-      for (int l = 0; l < lp.f_out; ++l) rescale_inplace(c, colp[l], lvc);
+      if (mode == 1)
+        rescale_batch(c, lvc, colp);
+      else
+        for (int l = 0; l < lp.f_out; ++l) rescale_inplace(c, colp[l], lvc);
       --lvc;
     }
     if (lvc != lp.level_agg) FICGCN_THROW(EPLAN_, "inconsistent schedule");
     const size_t agg_words = (size_t)2 * (lvc + 1) * N;
-    uint64_t* y = (uint64_t*)c->buf(36, agg_words * 8);
-    uint64_t* rt = (uint64_t*)c->buf(37, agg_words * 8);
-    for (int g = 0; g < lp.n_packed(); ++g) {
-      copy_d2d(c, y, colp[(size_t)g * lp.t], agg_words * 8);
-      for (int l = g * lp.t + 1; l < std::min(lp.f_out, (g + 1) * lp.t); ++l) {
-        rotate_one(c, ek, colp[l], lvc, -(int64_t)(l % lp.t) * lp.B, rt);
-        add_inplace(c, y, rt, lvc + 1, 2);
+    const int np = lp.n_packed();
+    if (mode == 1) {
+      // pack t columns per ciphertext: Y_g = col_{gt} + sum_l Rot_{-(l mod t) B}(col_l)
+      uint64_t* yb = (uint64_t*)c->buf(36, (size_t)np * agg_words * 8);
+      std::vector<uint64_t*> Y(np);
+      std::vector<std::vector<MacTerm>> init(np);
+      std::vector<const uint64_t*> srcs;
+      std::vector<KSJob> jobs;
+      for (int g = 0; g < np; ++g) {
+        Y[g] = yb + (size_t)g * agg_words;
+        init[g].push_back(MacTerm{colp[(size_t)g * lp.t], nullptr});
+        for (int l = g * lp.t + 1; l < std::min(lp.f_out, (g + 1) * lp.t); ++l) {
+          uint64_t gal;
+          const uint64_t* key = rot_key(c, ek, -(int64_t)(l % lp.t) * lp.B, gal);
+          if (!key) {
+            init[g].push_back(MacTerm{colp[l], nullptr});
+            continue;
+          }
+          jobs.push_back(KSJob{key, colp[l], nullptr, nullptr, gal, (int)srcs.size(), g});
+          srcs.push_back(colp[l] + (size_t)(lvc + 1) * N);
+        }
       }
-      aggregate(c, ek, p, lp, g, y, pre[g], mode);
+      group_mac(c, lvc, init, Y, false);
+      keyswitch_batch(c, lvc, srcs, jobs, Y, true);
+      aggregate_batched(c, ek, lp, Y, pre);
+    } else {
+      uint64_t* y = (uint64_t*)c->buf(36, agg_words * 8);
+      uint64_t* rt = (uint64_t*)c->buf(37, agg_words * 8);
+      for (int g = 0; g < np; ++g) {
+        copy_d2d(c, y, colp[(size_t)g * lp.t], agg_words * 8);
+        for (int l = g * lp.t + 1; l < std::min(lp.f_out, (g + 1) * lp.t); ++l) {
+          rotate_one(c, ek, colp[l], lvc, -(int64_t)(l % lp.t) * lp.B, rt);
+          add_inplace(c, y, rt, lvc + 1, 2);
+        }
+        aggregate(c, ek, lp, g, y, pre[g]);
+      }
     }
   }
-  if (lp.act) {
+  if (lp.act && mode == 1) {
+    activation_batched(c, ek, lp.level_out, pre, out);
+  } else if (lp.act) {
     const int lo = lp.level_out;
     for (size_t i = 0; i < n_out; ++i) {
       // out = pre^2 with relinearisation at the layer's output level

@@ -75,7 +75,8 @@ struct ckks_ctx {
   int device = 0;
   std::map<std::pair<int, int>, ficgcn::BConv> modup;   // (level, digit)
   std::map<int, ficgcn::BConv> moddown;                  // level
-  // grow-only scratch buffers
+  // grow-only scratch buffers by slot: ops.hip 1-9, sample/capi 10-29, gcn.cpp 30-49 and 70-79,
+  // ks_batch.hip 50-69 (a slot's memory moves when it grows, so one user per slot)
   std::vector<std::pair<void*, size_t>> scratch;
   // kernel timing (HIP events on `stream`), see ficgcn_profile_enable
   bool profiling = false;
@@ -127,7 +128,8 @@ uint64_t galois_elt(ckks_ctx* c, int64_t step);
 // ---- NTT (ntt.hip) ----
 // n_polys polynomials, each n_limbs limbs of N words; limb i of poly p at
 // base + p*poly_stride + i*N, modulus lm_mod(map, i).  Limbs with
-// (skip_alpha > 0 && i < skip_q && i / skip_alpha == p) are left untouched.
+// (skip_alpha > 0 && i < skip_q && i / skip_alpha == p mod ceil(skip_q / skip_alpha))
+// are left untouched (the digits' own limbs of one or more ModUp outputs).
 void ntt_fwd(ckks_ctx* c, uint64_t* base, int n_limbs, LimbMap map, int n_polys, size_t poly_stride,
              int skip_alpha = 0, int skip_q = 0);
 void ntt_inv(ckks_ctx* c, uint64_t* base, int n_limbs, LimbMap map, int n_polys, size_t poly_stride);

@@ -1,0 +1,465 @@
+// Batched hybrid key switching and batched ciphertext kernels.
+//
+// A batch holds R key switches at one level whose inputs come from U
+// distinct source polynomials (U = 1 when every rotation of one ciphertext
+// is hoisted on its ModUp; U = R when each ciphertext is switched once, as
+// for relinearising a layer).  Each stage is one launch over the batch:
+//   ModUp  : inverse NTT of the U sources, fast base conversion of every
+//            digit of every source, forward NTT of the extended limbs;
+//   inner  : acc_r = sum_d sigma_{g_r}(D_{src(r),d}) * key_{r,d}   (both components);
+//   ModDown: inverse NTT of the P limbs of every acc_r, rounded conversion
+//            to Q_l, forward NTT, then the grouped final step
+//            out_grp (+)= sum_r ((acc_r - conv_r) * P^-1 + add_r) [(.) pt_r].
+// Every switch is the same exact modular computation as a single key
+// switch (ModUp, automorphism on the digits, inner product, ModDown with
+// rounding), so the words equal those of R separate switches.  The
+// grouped final step replaces "write R switched ciphertexts, read them
+// back for a masked sum" by one read of acc and conv per switch.
+#include <algorithm>
+
+#include "internal.h"
+#include "ks_batch.h"
+
+namespace ficgcn {
+
+void zero_fill(ckks_ctx* c, uint64_t* p, size_t words);
+
+constexpr int KB = 256;
+
+__device__ __forceinline__ uint32_t auto_idx(uint32_t k, uint64_t g, int log_n) {
+  // evaluation index k holds A(psi^(2 brev(k) + 1)); sigma_g reads the index of psi^(g (2 brev(k) + 1))
+  uint32_t N2 = 2u << log_n;
+  uint32_t e = 2u * bitrev(k, log_n) + 1u;
+  uint32_t ge = (uint32_t)(((uint64_t)e * g) & (N2 - 1));
+  return bitrev((ge - 1u) >> 1, log_n);
+}
+
+// tmp[u] = sources[u] (l1 limbs)
+__global__ void k_gather(uint64_t* __restrict__ tmp, const uint64_t* const* __restrict__ src, int l1, int log_n) {
+  const size_t N = (size_t)1 << log_n;
+  const size_t j = blockIdx.x * (size_t)KB + threadIdx.x;
+  const int i = blockIdx.y, u = blockIdx.z;
+  tmp[((size_t)u * l1 + i) * N + j] = src[u][(size_t)i * N + j];
+}
+
+struct DigitTables {
+  enum { MAX = 32 };
+  const uint64_t* tab[MAX];   // [n_src] hat_inv, [n_src] Shoup, [n_dst][n_src] hat mod dst
+  const int* idx[MAX];        // [n_src] source moduli, then [n_dst] destination moduli
+  int n_src[MAX];
+  int n_dst[MAX];
+};
+
+// Digit d of source u: the digit's residues (coefficient form, in tmp)
+// converted to every other prime of Q_l and P; the digit's own limbs are
+// the source limbs in evaluation form.
+__global__ void k_modup_conv(const uint64_t* __restrict__ tmp, const uint64_t* const* __restrict__ src,
+                             uint64_t* __restrict__ D, DigitTables dt, int alpha, int l1, int ext, int nd, int L,
+                             int log_n, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << log_n;
+  const size_t j = blockIdx.x * (size_t)KB + threadIdx.x;
+  const int d = blockIdx.y, u = blockIdx.z;
+  const uint64_t* tab = dt.tab[d];
+  const int* idx = dt.idx[d];
+  const int ns = dt.n_src[d], ndst = dt.n_dst[d];
+  const uint64_t* s = tmp + ((size_t)u * l1 + (size_t)d * alpha) * N;
+  const uint64_t* own = src[u] + (size_t)d * alpha * N;
+  uint64_t* Dd = D + ((size_t)u * nd + d) * ext * N;
+  uint64_t y[8];
+  for (int t = 0; t < ns; ++t) {
+    const uint64_t b = mods[idx[t]].q;
+    y[t] = mul_shoup(s[t * N + j], tab[t], tab[ns + t], b);
+    Dd[((size_t)d * alpha + t) * N + j] = own[t * N + j];
+  }
+  const uint64_t* hm = tab + 2 * ns;
+  for (int k = 0; k < ndst; ++k) {
+    const int m = idx[ns + k];
+    const Mod md = mods[m];
+    u128 acc = 0;
+    for (int t = 0; t < ns; ++t) acc += (u128)y[t] * hm[k * ns + t];
+    const int pos = m < L ? m : m - L + l1;
+    Dd[(size_t)pos * N + j] = reduce128(acc, md);
+  }
+}
+
+// acc[r][c][i] = sum_d D_{src(r),d}[i][sigma_g(j)] * key_r[d][c][m(i)][j]
+__global__ void k_keymac_batch(uint64_t* __restrict__ acc, const uint64_t* __restrict__ D,
+                               const KSJob* __restrict__ jobs, int nd, int ext, int l1, int L, int n_mod, int log_n,
+                               const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << log_n;
+  const uint32_t j = blockIdx.x * KB + threadIdx.x;
+  const int i = blockIdx.y, r = blockIdx.z;
+  const KSJob jb = jobs[r];
+  const int m = i < l1 ? i : i - l1 + L;
+  const uint32_t jj = jb.g == 1 ? j : auto_idx(j, jb.g, log_n);
+  const uint64_t* Du = D + (size_t)jb.src * nd * ext * N;
+  u128 s0 = 0, s1 = 0;
+  for (int d = 0; d < nd; ++d) {
+    const u128 x = Du[((size_t)d * ext + i) * N + jj];
+    s0 += x * jb.key[(((size_t)d * 2 + 0) * n_mod + m) * N + j];
+    s1 += x * jb.key[(((size_t)d * 2 + 1) * n_mod + m) * N + j];
+  }
+  const Mod md = mods[m];
+  acc[(((size_t)r * 2 + 0) * ext + i) * N + j] = reduce128(s0, md);
+  acc[(((size_t)r * 2 + 1) * ext + i) * N + j] = reduce128(s1, md);
+}
+
+struct MDK {
+  uint64_t hP[8];                 // floor(P/2) mod p_t
+  uint64_t hQ[64];                // floor(P/2) mod q_i
+  uint64_t pinv[64], pinv_s[64];  // P^-1 mod q_i, Shoup
+};
+
+// conv[z][i] = FastBConv_{P -> q_i}([acc_P + floor(P/2)]) - floor(P/2)   (coefficient form)
+__global__ void k_moddown_conv_batch(const uint64_t* __restrict__ acc, int ext, int l1, const int* __restrict__ src_mod,
+                                     const int* __restrict__ dst_mod, int ns, const uint64_t* __restrict__ table,
+                                     MDK k, uint64_t* __restrict__ conv, int log_n, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << log_n;
+  const size_t j = blockIdx.x * (size_t)KB + threadIdx.x;
+  const int z = blockIdx.y;   // r * 2 + component
+  const uint64_t* ap = acc + ((size_t)z * ext + l1) * N;
+  uint64_t y[8];
+  for (int t = 0; t < ns; ++t) {
+    const uint64_t b = mods[src_mod[t]].q;
+    const uint64_t x = add_mod(ap[t * N + j], k.hP[t], b);
+    y[t] = mul_shoup(x, table[t], table[ns + t], b);
+  }
+  const uint64_t* hm = table + 2 * ns;
+  for (int d = 0; d < l1; ++d) {
+    const Mod md = mods[dst_mod[d]];
+    u128 a = 0;
+    for (int t = 0; t < ns; ++t) a += (u128)y[t] * hm[d * ns + t];
+    conv[((size_t)z * l1 + d) * N + j] = sub_mod(reduce128(a, md), k.hQ[d], md.q);
+  }
+}
+
+struct GroupDesc {
+  uint64_t* out;   // [2][l+1][N]
+  int start, end;  // job range within the chunk
+  int accumulate;
+  int pad;
+};
+
+__global__ void k_ks_final(const uint64_t* __restrict__ acc, const uint64_t* __restrict__ conv, int ext, int l1, MDK k,
+                           const KSJob* __restrict__ jobs, const GroupDesc* __restrict__ groups, int log_n,
+                           const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << log_n;
+  const uint32_t j = blockIdx.x * KB + threadIdx.x;
+  const int i = blockIdx.y;
+  const int comp = blockIdx.z & 1;
+  const GroupDesc gd = groups[blockIdx.z >> 1];
+  const Mod md = mods[i];
+  const uint64_t q = md.q;
+  const size_t o = ((size_t)comp * l1 + i) * N + j;
+  uint64_t a = gd.accumulate ? gd.out[o] : 0;
+  u128 s = 0;
+  int cnt = 0;
+  for (int r = gd.start; r < gd.end; ++r) {
+    const KSJob jb = jobs[r];
+    uint64_t v = sub_mod(acc[(((size_t)r * 2 + comp) * ext + i) * N + j],
+                         conv[(((size_t)r * 2 + comp) * l1 + i) * N + j], q);
+    v = mul_shoup(v, k.pinv[i], k.pinv_s[i], q);
+    if (comp == 0 && jb.add0) v = add_mod(v, jb.add0[(size_t)i * N + (jb.g == 1 ? j : auto_idx(j, jb.g, log_n))], q);
+    if (comp == 1 && jb.add1) v = add_mod(v, jb.add1[(size_t)i * N + j], q);
+    if (jb.pt) {
+      s += (u128)v * jb.pt[(size_t)i * N + j];
+      if (++cnt == 8) {
+        a = add_mod(a, reduce128(s, md), q);
+        s = 0;
+        cnt = 0;
+      }
+    } else {
+      a = add_mod(a, v, q);
+    }
+  }
+  gd.out[o] = add_mod(a, reduce128(s, md), q);
+}
+
+static MDK mdk(ckks_ctx* c, int level) {
+  MDK k{};
+  for (int t = 0; t < c->alpha; ++t) {
+    const uint64_t pm = c->mod[c->L + t];
+    uint64_t P_mod = 1;
+    for (int u = 0; u < c->alpha; ++u) P_mod = (uint64_t)((u128)P_mod * (c->mod[c->L + u] % pm) % pm);
+    k.hP[t] = (uint64_t)((u128)sub_mod(P_mod, 1, pm) * invmod(2, pm) % pm);
+  }
+  for (int i = 0; i <= level; ++i) {
+    const uint64_t q = c->mod[i];
+    uint64_t P_mod = 1;
+    for (int u = 0; u < c->alpha; ++u) P_mod = (uint64_t)((u128)P_mod * (c->mod[c->L + u] % q) % q);
+    k.hQ[i] = (uint64_t)((u128)sub_mod(P_mod, 1, q) * invmod(2, q) % q);
+    k.pinv[i] = invmod(P_mod, q);
+    k.pinv_s[i] = shoup(k.pinv[i], q);
+  }
+  return k;
+}
+
+enum { S_KB_TMP = 50, S_KB_D, S_KB_ACC, S_KB_CONV, S_KB_JOBS, S_KB_SRC, S_KB_GRP, S_TB_JOBS, S_RS_PTR, S_RS_LAST,
+       S_RS_D, S_GM_TERMS, S_GM_START, S_GM_OUT };
+
+template <typename T>
+static T* upload(ckks_ctx* c, int slot, const std::vector<T>& v) {
+  T* d = (T*)c->buf(slot, std::max<size_t>(16, v.size() * sizeof(T)));
+  if (!v.empty()) HIPCHECK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  return d;
+}
+
+// scratch bound of one chunk of a key-switch batch
+static constexpr size_t KS_BUDGET = (size_t)3 << 30;
+
+void keyswitch_batch(ckks_ctx* c, int level, const std::vector<const uint64_t*>& sources,
+                     const std::vector<KSJob>& jobs, const std::vector<uint64_t*>& outs, bool accumulate) {
+  const size_t N = c->N;
+  const int l1 = level + 1, ext = l1 + c->alpha;
+  const int nd = (l1 + c->alpha - 1) / c->alpha;
+  const int n_grp = (int)outs.size();
+  if (c->alpha > 8 || l1 > 64 || nd > DigitTables::MAX) FICGCN_THROW(EINVAL_, "too many primes");
+  for (size_t r = 0; r < jobs.size(); ++r) {
+    const KSJob& jb = jobs[r];
+    if (jb.src < 0 || jb.src >= (int)sources.size() || !sources[jb.src] || !jb.key || jb.grp < 0 || jb.grp >= n_grp ||
+        !outs[jb.grp] || (r && jobs[r - 1].grp > jb.grp))
+      FICGCN_THROW(EINVAL_, "bad key-switch job");
+  }
+  ProfScope ps(c, "ks_batch");
+  const size_t per_job = (size_t)2 * (ext + l1) * N * 8;
+  const size_t per_src = (size_t)(nd * ext + l1) * N * 8;
+  std::vector<char> touched(n_grp, 0);
+  const MDK k = mdk(c, level);
+  DigitTables dt{};
+  for (int d = 0; d < nd; ++d) {
+    const BConv& bc = get_modup(c, level, d);
+    dt.tab[d] = bc.dev;
+    dt.idx[d] = bc.idx;
+    dt.n_src[d] = bc.n_src;
+    dt.n_dst[d] = bc.n_dst;
+  }
+  const BConv& md = get_moddown(c, level);
+  size_t a = 0;
+  while (a < jobs.size()) {
+    // chunk [a, b): sources remapped to a dense local list
+    std::vector<int> local(sources.size(), -1);
+    std::vector<const uint64_t*> srcs;
+    std::vector<KSJob> cj;
+    size_t b = a, bytes = 0;
+    while (b < jobs.size()) {
+      const bool new_src = local[jobs[b].src] < 0;
+      const size_t add = per_job + (new_src ? per_src : 0);
+      if (b > a && bytes + add > KS_BUDGET) break;
+      bytes += add;
+      if (new_src) {
+        local[jobs[b].src] = (int)srcs.size();
+        srcs.push_back(sources[jobs[b].src]);
+      }
+      KSJob j = jobs[b];
+      j.src = local[j.src];
+      cj.push_back(j);
+      ++b;
+    }
+    // groups of the chunk (contiguous since jobs are sorted by group)
+    std::vector<GroupDesc> gds;
+    for (size_t r = 0; r < cj.size(); ++r) {
+      const int g = cj[r].grp;
+      if (gds.empty() || r == 0 || cj[r - 1].grp != g) {
+        gds.push_back(GroupDesc{outs[g], (int)r, (int)r + 1, (accumulate || touched[g]) ? 1 : 0, 0});
+        touched[g] = 1;
+      } else {
+        gds.back().end = (int)r + 1;
+      }
+    }
+    const int U = (int)srcs.size(), R = (int)cj.size();
+    KSJob* jd = upload(c, S_KB_JOBS, cj);
+    const uint64_t* const* sd = upload(c, S_KB_SRC, srcs);
+    GroupDesc* gd = upload(c, S_KB_GRP, gds);
+    uint64_t* tmp = (uint64_t*)c->buf(S_KB_TMP, (size_t)U * l1 * N * 8);
+    uint64_t* D = (uint64_t*)c->buf(S_KB_D, (size_t)U * nd * ext * N * 8);
+    uint64_t* acc = (uint64_t*)c->buf(S_KB_ACC, (size_t)R * 2 * ext * N * 8);
+    uint64_t* conv = (uint64_t*)c->buf(S_KB_CONV, (size_t)R * 2 * l1 * N * 8);
+    {
+      ProfScope pm(c, "modup");
+      hipLaunchKernelGGL(k_gather, dim3(N / KB, l1, U), dim3(KB), 0, c->stream, tmp, sd, l1, c->log_n);
+      HIPCHECK(hipGetLastError());
+      ntt_inv(c, tmp, l1, lm_q(l1), U, (size_t)l1 * N);
+      hipLaunchKernelGGL(k_modup_conv, dim3(N / KB, nd, U), dim3(KB), 0, c->stream, tmp, sd, D, dt, c->alpha, l1, ext,
+                         nd, c->L, c->log_n, c->t.mods);
+      HIPCHECK(hipGetLastError());
+      // every extended limb to evaluation form except each digit's own limbs
+      ntt_fwd(c, D, ext, lm_ext(level, c->L), U * nd, (size_t)ext * N, c->alpha, l1);
+    }
+    {
+      ProfScope pk(c, "keymac");
+      hipLaunchKernelGGL(k_keymac_batch, dim3(N / KB, ext, R), dim3(KB), 0, c->stream, acc, D, jd, nd, ext, l1, c->L,
+                         c->n_mod(), c->log_n, c->t.mods);
+      HIPCHECK(hipGetLastError());
+    }
+    {
+      ProfScope pd(c, "moddown");
+      ntt_inv(c, acc + (size_t)l1 * N, c->alpha, LimbMap{c->L, 1 << 30, 0}, 2 * R, (size_t)ext * N);
+      hipLaunchKernelGGL(k_moddown_conv_batch, dim3(N / KB, 2 * R), dim3(KB), 0, c->stream, acc, ext, l1, md.idx,
+                         md.idx + md.n_src, md.n_src, (const uint64_t*)md.dev, k, conv, c->log_n, c->t.mods);
+      HIPCHECK(hipGetLastError());
+      ntt_fwd(c, conv, l1, lm_q(l1), 2 * R, (size_t)l1 * N);
+      hipLaunchKernelGGL(k_ks_final, dim3(N / KB, l1, 2 * gds.size()), dim3(KB), 0, c->stream, acc, conv, ext, l1, k,
+                         jd, gd, c->log_n, c->t.mods);
+      HIPCHECK(hipGetLastError());
+    }
+    // the host lists of this chunk are released below and the device lists reused
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    a = b;
+  }
+  if (!accumulate)
+    for (int g = 0; g < n_grp; ++g)
+      if (!touched[g]) zero_fill(c, outs[g], (size_t)2 * l1 * N);
+}
+
+// ---- batched ciphertext kernels --------------------------------------------------
+
+// d = (x0 y0, x0 y1 + x1 y0, x1 y1) per job, [3][l1][N]
+__global__ void k_tensor_batch(const TensorJob* __restrict__ jobs, int l1, int log_n, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << log_n;
+  const size_t j = blockIdx.x * (size_t)KB + threadIdx.x;
+  const int i = blockIdx.y;
+  const TensorJob jb = jobs[blockIdx.z];
+  const Mod m = mods[i];
+  const size_t o0 = i * N + j, o1 = (l1 + i) * N + j;
+  const uint64_t x0 = jb.x[o0], x1 = jb.x[o1], y0 = jb.y[o0], y1 = jb.y[o1];
+  jb.d[o0] = reduce128((u128)x0 * y0, m);
+  jb.d[o1] = reduce128((u128)x0 * y1 + (u128)x1 * y0, m);
+  jb.d[(2 * l1 + i) * N + j] = reduce128((u128)x1 * y1, m);
+}
+
+void tensor_batch(ckks_ctx* c, int level, const std::vector<TensorJob>& jobs) {
+  if (jobs.empty()) return;
+  TensorJob* jd = upload(c, S_TB_JOBS, jobs);
+  hipLaunchKernelGGL(k_tensor_batch, dim3(c->N / KB, level + 1, jobs.size()), dim3(KB), 0, c->stream, jd, level + 1,
+                     c->log_n, c->t.mods);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(c->stream));
+}
+
+struct RSK {
+  uint64_t h[64];               // floor(q_l / 2) mod q_i
+  uint64_t inv[64], inv_s[64];  // q_l^-1 mod q_i, Shoup
+};
+
+__global__ void k_rs_gather(uint64_t* __restrict__ last, uint64_t* const* __restrict__ cts, int lvl, int log_n) {
+  const size_t N = (size_t)1 << log_n;
+  const size_t j = blockIdx.x * (size_t)KB + threadIdx.x;
+  const int z = blockIdx.y;   // ct * 2 + component
+  last[(size_t)z * N + j] = cts[z >> 1][((size_t)(z & 1) * (lvl + 1) + lvl) * N + j];
+}
+
+// d[z][i] = (h - ((x + h) mod q_l)) mod q_i for the last limb x in coefficient form
+__global__ void k_rs_prep(const uint64_t* __restrict__ last, uint64_t* __restrict__ d, int lvl, uint64_t hl, RSK k,
+                          int log_n, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << log_n;
+  const size_t j = blockIdx.x * (size_t)KB + threadIdx.x;
+  const int i = blockIdx.y, z = blockIdx.z;
+  const uint64_t ql = mods[lvl].q, q = mods[i].q;
+  const uint64_t y = add_mod(last[(size_t)z * N + j], hl, ql);   // < q_l < q_i (descending chain)
+  d[((size_t)z * lvl + i) * N + j] = sub_mod(k.h[i], y, q);
+}
+
+// c'_i = (c_i + d_i) q_l^-1, compacted in place from [2][l+1][N] to [2][l][N].
+// One thread walks the limbs of one component upwards, so a limb is read
+// before the write of the next-lower position reaches it; the two
+// components write disjoint ranges.
+__global__ void k_rs_final(uint64_t* const* __restrict__ cts, const uint64_t* __restrict__ d, int lvl, RSK k, int log_n,
+                           const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << log_n;
+  const size_t j = blockIdx.x * (size_t)KB + threadIdx.x;
+  const int z = blockIdx.y;
+  const int comp = z & 1;
+  uint64_t* ct = cts[z >> 1];
+  for (int i = 0; i < lvl; ++i) {
+    const uint64_t q = mods[i].q;
+    const uint64_t v = add_mod(ct[((size_t)comp * (lvl + 1) + i) * N + j], d[((size_t)z * lvl + i) * N + j], q);
+    ct[((size_t)comp * lvl + i) * N + j] = mul_shoup(v, k.inv[i], k.inv_s[i], q);
+  }
+}
+
+void rescale_batch(ckks_ctx* c, int level, const std::vector<uint64_t*>& cts) {
+  if (cts.empty()) return;
+  if (level < 1) FICGCN_THROW(ELEVEL_, "rescale at level 0");
+  if (level > 63) FICGCN_THROW(EINVAL_, "too many primes");
+  ProfScope ps(c, "rescale");
+  const size_t N = c->N;
+  const int n = (int)cts.size();
+  uint64_t* const* cd = upload(c, S_RS_PTR, cts);
+  uint64_t* last = (uint64_t*)c->buf(S_RS_LAST, (size_t)2 * n * N * 8);
+  uint64_t* d = (uint64_t*)c->buf(S_RS_D, (size_t)2 * n * level * N * 8);
+  hipLaunchKernelGGL(k_rs_gather, dim3(N / KB, 2 * n), dim3(KB), 0, c->stream, last, cd, level, c->log_n);
+  HIPCHECK(hipGetLastError());
+  ntt_inv(c, last, 1, LimbMap{level, 1 << 30, 0}, 2 * n, N);
+  RSK k{};
+  const uint64_t ql = c->mod[level], hl = ql / 2;
+  for (int i = 0; i < level; ++i) {
+    const uint64_t q = c->mod[i];
+    k.h[i] = hl % q;
+    k.inv[i] = invmod(ql % q, q);
+    k.inv_s[i] = shoup(k.inv[i], q);
+  }
+  hipLaunchKernelGGL(k_rs_prep, dim3(N / KB, level, 2 * n), dim3(KB), 0, c->stream, last, d, level, hl, k, c->log_n,
+                     c->t.mods);
+  HIPCHECK(hipGetLastError());
+  ntt_fwd(c, d, level, lm_q(level), 2 * n, (size_t)level * N);
+  hipLaunchKernelGGL(k_rs_final, dim3(N / KB, 2 * n), dim3(KB), 0, c->stream, cd, d, level, k, c->log_n, c->t.mods);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(c->stream));
+}
+
+// outs[g] (+)= sum over the terms of group g of ct (.) pt, or ct when pt is null
+__global__ void k_group_mac(const MacTerm* __restrict__ terms, const int* __restrict__ group_start,
+                            uint64_t* const* __restrict__ outs, int l1, int accumulate, int log_n,
+                            const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << log_n;
+  const size_t j = blockIdx.x * (size_t)KB + threadIdx.x;
+  const int i = blockIdx.y;
+  const int g = blockIdx.z >> 1, comp = blockIdx.z & 1;
+  const Mod m = mods[i];
+  const size_t o = ((size_t)comp * l1 + i) * N + j;
+  uint64_t* out = outs[g];
+  uint64_t a = accumulate ? out[o] : 0;
+  u128 s = 0;
+  int cnt = 0;
+  for (int t = group_start[g]; t < group_start[g + 1]; ++t) {
+    const MacTerm tm = terms[t];
+    const uint64_t x = tm.ct[o];
+    if (tm.pt) {
+      s += (u128)x * tm.pt[(size_t)i * N + j];
+      if (++cnt == 8) {
+        a = add_mod(a, reduce128(s, m), m.q);
+        s = 0;
+        cnt = 0;
+      }
+    } else {
+      a = add_mod(a, x, m.q);
+    }
+  }
+  out[o] = add_mod(a, reduce128(s, m), m.q);
+}
+
+void group_mac(ckks_ctx* c, int level, const std::vector<std::vector<MacTerm>>& groups,
+               const std::vector<uint64_t*>& outs, bool accumulate) {
+  if (groups.empty()) return;
+  if (groups.size() != outs.size()) FICGCN_THROW(EINVAL_, "group/output count mismatch");
+  ProfScope ps(c, "group_mac");
+  std::vector<MacTerm> flat;
+  std::vector<int> start{0};
+  for (const auto& g : groups) {
+    for (const MacTerm& t : g)
+      if (!t.ct) FICGCN_THROW(EINVAL_, "null term");
+    flat.insert(flat.end(), g.begin(), g.end());
+    start.push_back((int)flat.size());
+  }
+  for (uint64_t* o : outs)
+    if (!o) FICGCN_THROW(EINVAL_, "null output");
+  MacTerm* td = upload(c, S_GM_TERMS, flat);
+  int* sd = upload(c, S_GM_START, start);
+  uint64_t* const* od = upload(c, S_GM_OUT, outs);
+  hipLaunchKernelGGL(k_group_mac, dim3(c->N / KB, level + 1, 2 * groups.size()), dim3(KB), 0, c->stream, td, sd, od,
+                     level + 1, accumulate ? 1 : 0, c->log_n, c->t.mods);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(c->stream));
+}
+
+}  // namespace ficgcn

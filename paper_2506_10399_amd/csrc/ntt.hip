@@ -25,8 +25,10 @@
 
 namespace ficgcn {
 
+// ModUp output: digit d of a source owns limbs d*alpha .. d*alpha+alpha-1, which
+// hold evaluation-form input already; polys run digit-fastest over sources
 __device__ __forceinline__ bool skip_limb(int limb, int poly, int skip_alpha, int skip_q) {
-  return skip_alpha > 0 && limb < skip_q && limb / skip_alpha == poly;
+  return skip_alpha > 0 && limb < skip_q && limb / skip_alpha == poly % ((skip_q + skip_alpha - 1) / skip_alpha);
 }
 
 // forward CT butterfly / inverse GS butterfly on residues in [0, q)
