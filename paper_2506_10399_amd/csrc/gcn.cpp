@@ -26,6 +26,13 @@ void comb_fused(ckks_ctx* c, const std::vector<uint64_t*>& outs, const uint64_t*
                 const uint64_t* const* in_dev_ptrs, const PtrList& pts, int K, int F, int F_out, int level,
                 const void* w_dev, bool split, const char* prof_name);
 void zero_fill(ckks_ctx* c, uint64_t* p, size_t words);
+bool mfma_supported(ckks_ctx* c, int K, int F, int F_out);
+bool mfma_weight_planes(const std::vector<int64_t>& w_int, int F, int F_out, int l0, std::vector<uint8_t>& planes,
+                        int& n_fb);
+void mfma_pow256(ckks_ctx* c, int l1, std::vector<uint64_t>& out);
+void comb_mfma(ckks_ctx* c, const std::vector<uint64_t*>& outs, const uint64_t* in_base, size_t in_stride,
+               const uint64_t* const* in_dev_ptrs, const PtrList& pts, int K, int F, int level, const void* wd,
+               const uint64_t* pw, const char* prof_name);
 void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_layers, const double* const* weights,
                 const ficgcn_plan_opts& o);
 std::vector<int64_t> layer_rotation_steps(const LayerPlan& lp);
@@ -88,6 +95,46 @@ static void ensure_fused_weights(ckks_ctx* c, LayerPlan& lp) {
     HIPCHECK(hipMalloc(&lp.wf_dev, h.size() * 8));
     HIPCHECK(hipMemcpy(lp.wf_dev, h.data(), h.size() * 8, hipMemcpyHostToDevice));
   }
+}
+
+// Digit planes of the weights for the matrix-core pass; false when the
+// layer's shape or weights are outside it (the split pass runs instead).
+static bool ensure_mfma_weights(ckks_ctx* c, LayerPlan& lp, int K) {
+  if (lp.wm_state) return lp.wm_state > 0;
+  lp.wm_state = -1;
+  if (!mfma_supported(c, K, lp.f_in, std::min(lp.f_out, 16))) return false;
+  const int groups = (lp.f_out + 15) / 16;
+  std::vector<uint8_t> all, one;
+  int n_fb = 0;
+  for (int gi = 0; gi < groups; ++gi) {
+    if (!mfma_weight_planes(lp.w_int, lp.f_in, lp.f_out, gi * 16, one, n_fb)) return false;
+    all.insert(all.end(), one.begin(), one.end());
+  }
+  lp.wm_group_bytes = one.size();
+  std::vector<uint64_t> pw;
+  mfma_pow256(c, lp.level_in + 1, pw);
+  HIPCHECK(hipMalloc(&lp.wm_dev, all.size()));
+  HIPCHECK(hipMemcpy(lp.wm_dev, all.data(), all.size(), hipMemcpyHostToDevice));
+  HIPCHECK(hipMalloc(&lp.pw_dev, pw.size() * 8));
+  HIPCHECK(hipMemcpy(lp.pw_dev, pw.data(), pw.size() * 8, hipMemcpyHostToDevice));
+  lp.wm_state = 1;
+  return true;
+}
+
+// Fused pass of one layer: matrix-core form where it applies, else the split form
+static void fused_pass(ckks_ctx* c, LayerPlan& lp, const std::vector<uint64_t*>& outs, const uint64_t* base,
+                       size_t stride, const uint64_t* const* idv, const PtrList& pts, int K, const char* name) {
+  // buffer loads address a 64-ciphertext span with 31-bit offsets
+  if (ensure_mfma_weights(c, lp, K) && (!base || stride < ((size_t)1 << 22))) {
+    for (int l0 = 0; l0 < lp.f_out; l0 += 16) {
+      std::vector<uint64_t*> o(outs.begin() + l0, outs.begin() + std::min(lp.f_out, l0 + 16));
+      comb_mfma(c, o, base, stride, idv, pts, K, lp.f_in, lp.level_in, lp.wm_dev + (size_t)(l0 / 16) * lp.wm_group_bytes,
+                lp.pw_dev, name);
+    }
+    return;
+  }
+  ensure_fused_weights(c, lp);
+  comb_fused(c, outs, base, stride, idv, pts, K, lp.f_in, lp.f_out, lp.level_in, lp.wf_dev, lp.wf_split, name);
 }
 
 // A batch of equally spaced buffers is read by base + stride (no pointer table).
@@ -359,7 +406,6 @@ void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const u
   if (lp.kind == 0) {
     const int F = lp.f_in, K = lp.K;
     if (mode == 1) {
-      ensure_fused_weights(c, lp);
       if (K > PtrList::MAX) FICGCN_THROW(EPLAN_, "batched form supports at most 16 Inter-CA copies");
       PtrList pts{};
       for (int k = 0; k < K; ++k) pts.p[k] = lp.ops[k];
@@ -371,7 +417,7 @@ void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const u
         idv = upload_ptrs(c, ins, 31);
         base = nullptr;
       }
-      comb_fused(c, pre, base, stride, idv, pts, K, F, lp.f_out, lv, lp.wf_dev, lp.wf_split, "inter_fused");
+      fused_pass(c, lp, pre, base, stride, idv, pts, K, "inter_fused");
     } else {
       const int CH = 64;
       uint64_t* Z = (uint64_t*)c->buf(34, (size_t)CH * ct_words * 8);
@@ -416,7 +462,6 @@ void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const u
     std::vector<uint64_t*> colp(lp.f_out);
     for (int l = 0; l < lp.f_out; ++l) colp[l] = cols + (size_t)l * ct_words;
     if (mode == 1) {
-      ensure_fused_weights(c, lp);
       const uint64_t* base = nullptr;
       size_t stride = 0;
       const uint64_t* const* idv = nullptr;
@@ -425,7 +470,7 @@ void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const u
         idv = upload_ptrs(c, ins, 31);
         base = nullptr;
       }
-      comb_fused(c, colp, base, stride, idv, PtrList{}, 0, F, lp.f_out, lv, lp.wf_dev, lp.wf_split, "comb_fused");
+      fused_pass(c, lp, colp, base, stride, idv, PtrList{}, 0, "comb_fused");
     } else {
       for (int l = 0; l < lp.f_out; ++l) {
         zero_fill(c, colp[l], ct_words);

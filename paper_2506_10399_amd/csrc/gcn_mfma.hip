@@ -1,0 +1,223 @@
+// Fused Inter-CA aggregation + combination with the contraction on the
+// int8 matrix cores.
+//
+// For one output group (F' <= 16 columns) the pass computes
+//   H_l = sum_k P_k (.) T_{k,l},   T_{k,l} = sum_f w_{f,l} X_{k*F + f}   (Inter-CA, K > 0)
+//   H_l = sum_f w_{f,l} X_f                                              (combination, K = 0)
+// in one read of the inputs: the Inter-CA aggregation of Sec. 3.3.2 fused
+// with the one-column-per-ciphertext combination of App. B.  Modular
+// arithmetic is a ring, so applying P_k after the contraction gives the same
+// residues as sum_f w_{f,l} (sum_k P_k (.) X_{k,f}).
+//
+// The contraction over f is, per wave, a dense [16 coefficients x F] x
+// [F x 16 columns] product computed exactly in integers: an input residue
+// x (< 2^50) and a signed integer weight w (|w| < 2^55) are written in
+// balanced base-256 digits in [-128, 127],
+//   x = sum_{a<7} x_a 256^a,   w = sum_{b<7} w_b 256^b,
+// so sum_f x_f w_f = sum_{s<13} 256^s D_s with D_s = sum_{a+b=s} sum_f x_{a,f} w_{b,f}.
+// Each digit pair (a, b) is one v_mfma_i32_16x16x64_i8 over 64 features into
+// the i32 accumulator of diagonal s = a + b; |D_s| <= 7 * 2^14 * F stays below
+// 2^31 for F <= 16384.  After the features of one copy the diagonals are
+// folded to residues, T = sum_s [D_s]_q [256^s]_q mod q, and P_k (.) T is
+// added to the output residues.
+//
+// Wave layout: one wave owns 16 consecutive coefficients j of one limb of one
+// component and loops over the copies k and 64-feature blocks.  Lane
+// (r = lane % 16, g = lane / 16) reads coefficient j0 + r of features
+// 16g .. 16g+15 of each block; the digit planes of those 16 words are its A
+// operands.  The B operands (weight digit planes) are laid out per block on
+// the host in the same lane order.  The output tile lands as lane
+// (n = lane % 16, g): column n, coefficients j0 + 4g .. j0 + 4g + 3.
+#include "internal.h"
+
+namespace ficgcn {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int MW = 256;   // 4 waves per workgroup
+constexpr uint64_t DIG_C = 0x0080808080808080ull;   // 128 in each of bytes 0..6
+
+// balanced base-256 digits of x (requires x + DIG_C in [0, 2^56)):
+// byte a of the result is digit a as an int8, byte 7 is zero
+__device__ __forceinline__ uint64_t bal_digits(uint64_t x) { return (x + DIG_C) ^ DIG_C; }
+
+// 16 words -> 7 digit planes: plane a, dword w holds digit a of words 4w..4w+3
+__device__ __forceinline__ void digit_planes(const uint64_t (&x)[16], v4i (&A)[7]) {
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    uint32_t lo[4], hi[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint64_t d = bal_digits(x[4 * w + u]);
+      lo[u] = (uint32_t)d;
+      hi[u] = (uint32_t)(d >> 32);
+    }
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      const uint32_t* src = a < 4 ? lo : hi;
+      const int sh = (a & 3) * 8;
+      A[a][w] = (int)(((src[0] >> sh) & 0xffu) | (((src[1] >> sh) & 0xffu) << 8) | (((src[2] >> sh) & 0xffu) << 16) |
+                      (((src[3] >> sh) & 0xffu) << 24));
+    }
+  }
+}
+
+template <bool STRIDED>
+__global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_fused_mfma(OutList out, int n_out, const uint64_t* __restrict__ in_base,
+                                                   size_t in_stride, const uint64_t* const* __restrict__ in_ptrs,
+                                                   PtrList pts, int K, int F, int n_fb, int l1,
+                                                   const v4i* __restrict__ wd, const uint64_t* __restrict__ pow256,
+                                                   int log_n, const Mod* __restrict__ mods) {
+  const int lane = threadIdx.x & 63;
+  const size_t N = (size_t)1 << log_n;
+  const size_t tiles = N >> 4;
+  const size_t wave = (size_t)blockIdx.x * (MW / 64) + (threadIdx.x >> 6);
+  const size_t tile = wave % tiles;
+  const int rest = (int)(wave / tiles);
+  const int i = rest % l1, comp = rest / l1;
+  const int r = lane & 15, g = lane >> 4;
+  const size_t limb_off = ((size_t)comp * l1 + i) * N;
+  const size_t off = limb_off + tile * 16 + r;
+  const Mod m = mods[i];
+  const int KK = K > 0 ? K : 1;
+  const int n_steps = KK * n_fb;   // (copy, block) steps, block-fastest
+  // Strided inputs are read with buffer loads: a wave-uniform resource per
+  // (copy, feature of lane group 0) in scalar registers and one 32-bit
+  // per-lane byte offset (lane group g, coefficient).  The resource's range
+  // ends after the lane groups whose features exist, so lanes past F read 0.
+  const int lane_bytes = STRIDED ? (int)(((size_t)g * 16 * in_stride + off) * 8) : 0;
+  const size_t grp_bytes = (size_t)16 * in_stride * 8;
+  auto load_block = [&](uint64_t (&x)[16], int step) {
+    const int k = step / n_fb, fb = step - k * n_fb;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int fu = fb * 64 + e;   // feature of lane group 0
+      if (STRIDED) {
+        const int left = F - fu;    // features fu, fu+16, ... below F
+        const int n_grp = left <= 0 ? 0 : (left + 15) / 16 > 4 ? 4 : (left + 15) / 16;
+        const char* b = (const char*)in_base + ((size_t)k * F + fu) * in_stride * 8;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void*)b, 0, (int)(n_grp * grp_bytes), 0x00020000);
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, lane_bytes, 0, 0);
+        x[e] = ((uint64_t)w[1] << 32) | w[0];
+      } else {
+        const int f = fu + g * 16;
+        x[e] = f < F ? in_ptrs[(size_t)k * F + f][off] : 0;
+      }
+    }
+  };
+  const uint64_t* pw = pow256 + (size_t)i * 13;
+  uint64_t h[4] = {0, 0, 0, 0};   // output residues: column lane % 16, coefficients j0 + 4g + rr
+  v4i acc[13];
+#pragma unroll
+  for (int s = 0; s < 13; ++s) acc[s] = v4i{0, 0, 0, 0};
+  uint64_t xa[16], xb[16];
+  load_block(xa, 0);
+  for (int step = 0; step < n_steps; step += 2) {
+    // two steps per iteration so the register buffers alternate statically
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int st = step + half;
+      if (st >= n_steps) break;
+      uint64_t (&cur)[16] = half ? xb : xa;
+      uint64_t (&nxt)[16] = half ? xa : xb;
+      if (st + 1 < n_steps) load_block(nxt, st + 1);
+      v4i A[7];
+      digit_planes(cur, A);
+      const int k = st / n_fb, fb = st - k * n_fb;
+#pragma unroll
+      for (int b = 0; b < 7; ++b) {
+        const v4i B = wd[((size_t)fb * 7 + b) * 64 + lane];
+#pragma unroll
+        for (int a = 0; a < 7; ++a) acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[a], B, acc[a + b], 0, 0, 0);
+      }
+      if (fb == n_fb - 1) {
+        // copy k done: fold the diagonals and add P_k (.) T
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          u128 sum = 0;
+#pragma unroll
+          for (int d = 0; d < 13; ++d) {
+            const int v = acc[d][rr];
+            const uint64_t res = v >= 0 ? (uint64_t)v : m.q - (uint64_t)(-(int64_t)v);
+            sum += (u128)res * pw[d];
+          }
+          uint64_t t = reduce128(sum, m);
+          if (K > 0) t = reduce128((u128)t * pts.p[k][(size_t)i * N + tile * 16 + 4 * g + rr], m);
+          h[rr] = add_mod(h[rr], t, m.q);
+        }
+#pragma unroll
+        for (int s = 0; s < 13; ++s) acc[s] = v4i{0, 0, 0, 0};
+      }
+    }
+  }
+  const int n = lane & 15;
+  if (n >= n_out) return;
+  uint64_t* o = out.p[n] + limb_off + tile * 16 + 4 * g;
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) o[rr] = h[rr];
+}
+
+// Weight digit planes of one 16-column group: [n_fb][7][64 lanes] x 16 bytes;
+// lane (n, g), byte e holds digit b of w[f = 64 fb + 16 g + e][l0 + n] (zero
+// outside F x F').  Returns false when a weight is outside the digit range.
+bool mfma_weight_planes(const std::vector<int64_t>& w_int, int F, int F_out, int l0, std::vector<uint8_t>& planes,
+                        int& n_fb) {
+  n_fb = (F + 63) / 64;
+  planes.assign((size_t)n_fb * 7 * 64 * 16, 0);
+  for (int f = 0; f < F; ++f)
+    for (int n = 0; n < 16 && l0 + n < F_out; ++n) {
+      const int64_t w = w_int[(size_t)f * F_out + l0 + n];
+      const int64_t lim = (int64_t)DIG_C;
+      if (w < -lim || w >= (int64_t)(1ull << 56) - lim) return false;
+      const uint64_t d = ((uint64_t)w + DIG_C) ^ DIG_C;
+      const int fb = f / 64, g = (f % 64) / 16, e = f % 16;
+      const int lane = g * 16 + n;
+      for (int b = 0; b < 7; ++b) planes[(((size_t)fb * 7 + b) * 64 + lane) * 16 + e] = (uint8_t)(d >> (8 * b));
+    }
+  return true;
+}
+
+// 256^s mod q_i, s < 13, for the limbs of one level: [l1][13]
+void mfma_pow256(ckks_ctx* c, int l1, std::vector<uint64_t>& out) {
+  out.resize((size_t)l1 * 13);
+  for (int i = 0; i < l1; ++i) {
+    const uint64_t q = c->mod[i];
+    uint64_t v = 1;
+    for (int s = 0; s < 13; ++s) {
+      out[(size_t)i * 13 + s] = v;
+      v = (uint64_t)((u128)v * 256 % q);
+    }
+  }
+}
+
+constexpr int MFMA_MAX_K = PtrList::MAX;
+
+bool mfma_supported(ckks_ctx* c, int K, int F, int F_out) {
+  return c->mod[0] < (1ull << 52) && K <= MFMA_MAX_K && F <= 16384 && F_out <= 16 && c->log_n >= 6;
+}
+
+// outs: F' <= 16 buffers [2][l+1][N]; wd: digit planes of this group; pw: [l1][13] on the device
+void comb_mfma(ckks_ctx* c, const std::vector<uint64_t*>& outs, const uint64_t* in_base, size_t in_stride,
+               const uint64_t* const* in_dev_ptrs, const PtrList& pts, int K, int F, int level, const void* wd,
+               const uint64_t* pw, const char* prof_name) {
+  ProfScope ps(c, prof_name);
+  const int n_out = (int)outs.size();
+  if (n_out > 16 || K > MFMA_MAX_K || F > 16384 || (in_base && in_stride >= ((size_t)1 << 22)))
+    FICGCN_THROW(EINVAL_, "shape outside the matrix-core pass");
+  const int l1 = level + 1;
+  OutList o{};
+  for (int l = 0; l < n_out; ++l) o.p[l] = outs[l];
+  const int n_fb = (F + 63) / 64;
+  const size_t waves = ((size_t)c->N >> 4) * l1 * 2;
+  dim3 grid((unsigned)(waves / (MW / 64)));
+  if (in_base)
+    hipLaunchKernelGGL(k_fused_mfma<true>, grid, dim3(MW), 0, c->stream, o, n_out, in_base, in_stride, in_dev_ptrs, pts,
+                       K, F, n_fb, l1, (const v4i*)wd, pw, c->log_n, c->t.mods);
+  else
+    hipLaunchKernelGGL(k_fused_mfma<false>, grid, dim3(MW), 0, c->stream, o, n_out, in_base, in_stride, in_dev_ptrs,
+                       pts, K, F, n_fb, l1, (const v4i*)wd, pw, c->log_n, c->t.mods);
+  HIPCHECK(hipGetLastError());
+}
+
+}  // namespace ficgcn

@@ -343,6 +343,9 @@ ficgcn_plan::~ficgcn_plan() {
   for (auto& lp : layers) {
     if (lp.ops_block) (void)hipFree(lp.ops_block);
     if (lp.w_dev) (void)hipFree(lp.w_dev);
+    if (lp.wf_dev) (void)hipFree(lp.wf_dev);
+    if (lp.wm_dev) (void)hipFree(lp.wm_dev);
+    if (lp.pw_dev) (void)hipFree(lp.pw_dev);
   }
 }
 

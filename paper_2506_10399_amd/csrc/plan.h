@@ -34,6 +34,11 @@ struct LayerPlan {
   uint64_t* w_dev = nullptr;       // [f_out][f_in][level+1][2] residues + Shoup (per-operation form)
   void* wf_dev = nullptr;          // fused-pass weights [level+1][f_in][f_out] (split halves or residues)
   bool wf_split = false;
+  // matrix-core pass: weight digit planes per 16-column group, 256^s mod q_i
+  int wm_state = 0;                // 0 not built, 1 built, -1 shape or weights outside the pass
+  uint8_t* wm_dev = nullptr;       // [groups][n_fb][7][64][16]
+  size_t wm_group_bytes = 0;
+  uint64_t* pw_dev = nullptr;      // [level+1][13]
   int n_packed() const { return kind == 0 ? f_out : (f_out + t - 1) / t; }
   int n_in_cts() const { return kind == 0 ? K * f_in : f_in; }
 };
