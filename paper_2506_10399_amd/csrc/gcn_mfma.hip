@@ -71,7 +71,8 @@ __global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   const int lane = threadIdx.x & 63;
   const size_t N = (size_t)1 << log_n;
   const size_t tiles = N >> 4;
-  const size_t wave = (size_t)blockIdx.x * (MW / 64) + (threadIdx.x >> 6);
+  // wave-uniform indices (scalar registers): the wave's number within the grid
+  const size_t wave = (size_t)blockIdx.x * (MW / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const size_t tile = wave % tiles;
   const int rest = (int)(wave / tiles);
   const int i = rest % l1, comp = rest / l1;
@@ -87,13 +88,16 @@ __global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   // ends after the lane groups whose features exist, so lanes past F read 0.
   const int lane_bytes = STRIDED ? (int)(((size_t)g * 16 * in_stride + off) * 8) : 0;
   const size_t grp_bytes = (size_t)16 * in_stride * 8;
+  // A step past the end loads nothing (empty range / no active lane), so the
+  // prefetch is issued unconditionally and the wait counts stay static.
   auto load_block = [&](uint64_t (&x)[16], int step) {
-    const int k = step / n_fb, fb = step - k * n_fb;
+    const bool live = step < n_steps;
+    const int k = live ? step / n_fb : 0, fb = live ? step - k * n_fb : 0;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int fu = fb * 64 + e;   // feature of lane group 0
       if (STRIDED) {
-        const int left = F - fu;    // features fu, fu+16, ... below F
+        const int left = live ? F - fu : 0;   // features fu, fu+16, ... below F
         const int n_grp = left <= 0 ? 0 : (left + 15) / 16 > 4 ? 4 : (left + 15) / 16;
         const char* b = (const char*)in_base + ((size_t)k * F + fu) * in_stride * 8;
         const __amdgpu_buffer_rsrc_t rs =
@@ -102,7 +106,7 @@ __global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         x[e] = ((uint64_t)w[1] << 32) | w[0];
       } else {
         const int f = fu + g * 16;
-        x[e] = f < F ? in_ptrs[(size_t)k * F + f][off] : 0;
+        x[e] = live && f < F ? in_ptrs[(size_t)k * F + f][off] : 0;
       }
     }
   };
@@ -121,17 +125,30 @@ __global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void
       if (st >= n_steps) break;
       uint64_t (&cur)[16] = half ? xb : xa;
       uint64_t (&nxt)[16] = half ? xa : xb;
-      if (st + 1 < n_steps) load_block(nxt, st + 1);
+      const int k = st / n_fb, fb = st - k * n_fb;
+      const bool last = fb == n_fb - 1;
+      // this step's weight planes (and the copy's plaintext words on its last
+      // block) are requested before the next block: loads retire in order, so
+      // waiting for them leaves the prefetch in flight
+      v4i B[7];
+#pragma unroll
+      for (int b = 0; b < 7; ++b) B[b] = wd[((size_t)fb * 7 + b) * 64 + lane];
+      uint64_t pk[4] = {1, 1, 1, 1};
+      if (K > 0 && last) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) pk[rr] = pts.p[k][(size_t)i * N + tile * 16 + 4 * g + rr];
+      }
+      // keep the order: these loads, then the prefetch, then the arithmetic
+      __builtin_amdgcn_sched_barrier(0);
+      load_block(nxt, st + 1);
+      __builtin_amdgcn_sched_barrier(0);
       v4i A[7];
       digit_planes(cur, A);
-      const int k = st / n_fb, fb = st - k * n_fb;
 #pragma unroll
-      for (int b = 0; b < 7; ++b) {
-        const v4i B = wd[((size_t)fb * 7 + b) * 64 + lane];
+      for (int b = 0; b < 7; ++b)
 #pragma unroll
-        for (int a = 0; a < 7; ++a) acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[a], B, acc[a + b], 0, 0, 0);
-      }
-      if (fb == n_fb - 1) {
+        for (int a = 0; a < 7; ++a) acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[a], B[b], acc[a + b], 0, 0, 0);
+      if (last) {
         // copy k done: fold the diagonals and add P_k (.) T
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
@@ -143,7 +160,7 @@ __global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void
             sum += (u128)res * pw[d];
           }
           uint64_t t = reduce128(sum, m);
-          if (K > 0) t = reduce128((u128)t * pts.p[k][(size_t)i * N + tile * 16 + 4 * g + rr], m);
+          if (K > 0) t = reduce128((u128)t * pk[rr], m);
           h[rr] = add_mod(h[rr], t, m.q);
         }
 #pragma unroll
