@@ -150,6 +150,13 @@ ficgcn_status ckks_ntt(ckks_ctx* ctx, uint64_t* dev, uint32_t n_limbs, uint32_t 
  * a step's key is missing (nothing enqueued). */
 ficgcn_status ckks_rotate_hoisted(ckks_ctx* ctx, const ckks_keys* eval_keys, const uint64_t* ct_dev, uint32_t level,
                                   const int64_t* steps, size_t k, uint64_t* const* outs);
+/* n rotations Rot(cts[i], steps[i]) -> outs[i] at one level, run as one
+ * key-switch batch (one ModUp per distinct input pointer, one inner-product
+ * launch and one ModDown sequence for all n).  Words equal n single
+ * rotations.  Outputs may not alias each other or any input; ENOKEY if a
+ * step's key is missing (nothing enqueued). */
+ficgcn_status ckks_rotate_batch(ckks_ctx* ctx, const ckks_keys* eval_keys, const uint64_t* const* cts, uint32_t level,
+                                const int64_t* steps, size_t n, uint64_t* const* outs);
 /* acc += sum_i pts[i] (.) cts[i]  (plaintext-ciphertext multiply-accumulate
  * of Sec. 3.3's masks and Inter-CA copies); no rescale. */
 ficgcn_status ckks_pt_mul_acc(ckks_ctx* ctx, uint64_t* acc_dev, uint32_t level, const uint64_t* const* cts,

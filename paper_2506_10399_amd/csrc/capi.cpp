@@ -8,6 +8,7 @@
 
 #include "../../include/ficgcn.h"
 #include "internal.h"
+#include "ks_batch.h"
 
 namespace ficgcn {
 void encode_coeffs(int N, const double* re, const double* im, size_t n, double scale, std::vector<int64_t>& out);
@@ -75,6 +76,39 @@ static const uint64_t* need_key(const ckks_keys* k, uint64_t tag) {
 }  // namespace ficgcn
 
 using namespace ficgcn;
+
+// n rotations (cts[i] by steps[i] into outs[i]) as one key-switch batch:
+// inputs given by the same pointer share one ModUp (hoisting)
+static void rotate_batch(ckks_ctx* ctx, const ckks_keys* ek, const uint64_t* const* cts, uint32_t level,
+                         const int64_t* steps, size_t n, uint64_t* const* outs) {
+  const size_t N = ctx->N;
+  const int l1 = level + 1;
+  std::vector<const uint64_t*> srcs;
+  std::map<const uint64_t*, int> src_of;
+  std::vector<KSJob> jobs;
+  std::vector<uint64_t*> gouts;
+  std::vector<std::pair<uint64_t*, const uint64_t*>> copies;
+  for (size_t i = 0; i < n; ++i) {
+    REQUIRE(cts[i] && outs[i], EINVAL_, "null ciphertext");
+    for (size_t j = 0; j < n; ++j)
+      REQUIRE(outs[i] != cts[j] && (i == j || outs[i] != outs[j]), EINVAL_, "output buffers alias");
+    const uint64_t g = galois_elt(ctx, steps[i]);
+    if (g == 1) {
+      copies.push_back({outs[i], cts[i]});
+      continue;
+    }
+    const uint64_t* key = need_key(ek, g);
+    auto it = src_of.find(cts[i]);
+    if (it == src_of.end()) {
+      it = src_of.emplace(cts[i], (int)srcs.size()).first;
+      srcs.push_back(cts[i] + (size_t)l1 * N);
+    }
+    jobs.push_back(KSJob{key, cts[i], nullptr, nullptr, g, it->second, (int)gouts.size()});
+    gouts.push_back(outs[i]);
+  }
+  for (auto& cp : copies) copy_d2d(ctx, cp.first, cp.second, (size_t)2 * l1 * N * 8);
+  keyswitch_batch(ctx, (int)level, srcs, jobs, gouts, false);
+}
 
 extern "C" {
 
@@ -375,35 +409,18 @@ ficgcn_status ckks_rotate_hoisted(ckks_ctx* ctx, const ckks_keys* eval_keys, con
     if (ctx) ensure_device(ctx);
     check_level(ctx, level);
     REQUIRE(ct_dev && (k == 0 || (steps && outs)), EINVAL_, "null argument");
-    const size_t N = ctx->N;
-    const int l1 = level + 1, ext = l1 + ctx->alpha;
-    const int nd = (l1 + ctx->alpha - 1) / ctx->alpha;
-    std::vector<uint64_t> gs(k);
-    std::vector<const uint64_t*> keys(k, nullptr);
-    bool any = false;
-    for (size_t i = 0; i < k; ++i) {
-      REQUIRE(outs[i] && outs[i] != ct_dev, EINVAL_, "output buffer missing or aliases the input");
-      gs[i] = galois_elt(ctx, steps[i]);
-      if (gs[i] != 1) {
-        keys[i] = need_key(eval_keys, gs[i]);
-        any = true;
-      }
-    }
-    uint64_t* D = nullptr;
-    uint64_t* acc = nullptr;
-    if (any) {
-      D = (uint64_t*)ctx->buf(20, (size_t)nd * ext * N * 8);
-      acc = (uint64_t*)ctx->buf(21, (size_t)2 * ext * N * 8);
-      modup(ctx, ct_dev + (size_t)l1 * N, level, D);
-    }
-    for (size_t i = 0; i < k; ++i) {
-      if (gs[i] == 1) {
-        copy_d2d(ctx, outs[i], ct_dev, (size_t)2 * l1 * N * 8);
-        continue;
-      }
-      keymac(ctx, acc, D, keys[i], level, gs[i]);
-      moddown(ctx, acc, level, outs[i], ct_dev, gs[i], nullptr);
-    }
+    std::vector<const uint64_t*> cts(k, ct_dev);
+    rotate_batch(ctx, eval_keys, cts.data(), level, steps, k, outs);
+  });
+}
+
+ficgcn_status ckks_rotate_batch(ckks_ctx* ctx, const ckks_keys* eval_keys, const uint64_t* const* cts, uint32_t level,
+                                const int64_t* steps, size_t n, uint64_t* const* outs) {
+  return guard([&] {
+    if (ctx) ensure_device(ctx);
+    check_level(ctx, level);
+    REQUIRE(n == 0 || (cts && steps && outs), EINVAL_, "null argument");
+    rotate_batch(ctx, eval_keys, cts, level, steps, n, outs);
   });
 }
 

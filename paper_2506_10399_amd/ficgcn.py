@@ -70,6 +70,7 @@ _SIGS = {
     "ckks_poly_store": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, ctypes.c_uint32, c_vp]),
     "ckks_ntt": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]),
     "ckks_rotate_hoisted": (ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_uint32, c_vp, ctypes.c_size_t, c_vp]),
+    "ckks_rotate_batch": (ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_uint32, c_vp, ctypes.c_size_t, c_vp]),
     "ckks_pt_mul_acc": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, c_vp, c_vp, ctypes.c_size_t]),
     "ckks_scalar_mul_acc": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, c_vp, c_vp, ctypes.c_size_t]),
     "ckks_add": (ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_uint32]),
@@ -273,6 +274,15 @@ class Context:
         outs = [self.ct_buffer(level) for _ in steps] if outs is None else outs
         _check(lib().ckks_rotate_hoisted(self.h, eval_keys.h, _ptr(ct), level, _ptr(steps), len(steps),
                                          _ptr_array(outs)))
+        return outs
+
+    def ckks_rotate_batch(self, eval_keys: "Keys", cts, level: int, steps: Sequence[int], outs=None):
+        steps = np.ascontiguousarray(np.array(list(steps), dtype=np.int64))
+        if len(cts) != len(steps):
+            raise ValueError("one step per ciphertext")
+        outs = [self.ct_buffer(level) for _ in steps] if outs is None else outs
+        _check(lib().ckks_rotate_batch(self.h, eval_keys.h, _ptr_array(cts), level, _ptr(steps), len(steps),
+                                       _ptr_array(outs)))
         return outs
 
     def ckks_pt_mul_acc(self, acc, level: int, cts, pts):

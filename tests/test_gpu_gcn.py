@@ -57,10 +57,15 @@ def _load_operands(e):
             p.ficgcn_plan_load_operand(li, i, pt.m)
 
 
-def _run_gpu(e, mode):
+def _run_gpu(e, mode, contiguous=False):
     ctx, p, info = e["ctx"], e["p"], e["p"].ficgcn_plan_info()
     lv0 = e["prm"].L - 1
     cur = [ctx.ckks_ct_load(_ct(c), lv0) for c in e["cts"]]
+    if contiguous:
+        # the inputs as equally spaced views of one block (the strided read path)
+        import torch
+        block = torch.stack(cur)
+        cur = [block[i] for i in range(len(cur))]
     per_layer = []
     for li, d in enumerate(info):
         outs = [ctx.ct_buffer(d["level_in"]) for _ in range(d["n_out_cts"])]
@@ -78,8 +83,8 @@ def test_layers_bit_exact_both_forms(name, mode, family):
     e = _setup(name, mode, family)
     _load_operands(e)
     words = {}
-    for m in (0, 1):
-        res = _run_gpu(e, m)
+    for m, contiguous in ((0, False), (1, False), (1, True)):
+        res = _run_gpu(e, m, contiguous)
         for li, ((outs, lvo), want) in enumerate(zip(res, e["outs"])):
             got = [e["ctx"].ckks_poly_store(x, lvo, 2) for x in outs]
             for g, (a, b) in enumerate(zip(got, want)):

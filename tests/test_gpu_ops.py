@@ -106,6 +106,21 @@ def test_rotate_hoisted_matches_oracle(env):
         assert np.array_equal(ctx.ckks_poly_store(one, lv, 2), _ct(want[1]))
 
 
+def test_rotate_batch_matches_oracle(env):
+    """Several ciphertexts and steps in one key-switch batch (shared sources
+    hoisted, zero step copied) give the oracle's single-rotation words."""
+    prm, ctx = env["prm"], env["ctx"]
+    lv = prm.L - 1
+    cts = [_rand_ct(env, lv, 40 + i)[1] for i in range(3)]
+    dcts = [ctx.ckks_ct_load(_ct(c), lv) for c in cts]
+    st = env["steps"]
+    pairs = [(0, st[0]), (1, st[1]), (0, st[-1]), (2, 0), (2, st[0]), (1, st[0])]
+    outs = ctx.ckks_rotate_batch(env["ev"], [dcts[i] for i, _ in pairs], lv, [k for _, k in pairs])
+    for (i, k), o in zip(pairs, outs):
+        want = cts[i] if k == 0 else ckks.rotate(prm, env["okeys"], cts[i], k)
+        assert np.array_equal(ctx.ckks_poly_store(o, lv, 2), _ct(want)), (i, k)
+
+
 def test_rotate_missing_key_is_enokey(env):
     ctx = env["ctx"]
     lv = 1
