@@ -9,10 +9,16 @@ scale 2^40.  Layer 1 is Inter-CA over the client's 5 neighbour copies of
 each of the 1433 columns (7165 input ciphertexts, 56 GiB resident in HBM
 before timing), layer 2 is SpIntra-CA on the packed hidden layer.
 
+Plans: the paper's rule (packing t, NOO with the default region cap, the
+cheaper routing family) and the learned search (a cost model trained here on
+measured SpIntra-CA latencies of small synthetic graphs keeps 4 candidates,
+the analytic judge picks among them).
+
 A step is one whole encrypted inference (both layers, every rotation,
-rescale and relinearisation) in the batched form.  The plain per-operation
-form of the same plan is timed once for the speedup; both forms' output
-words are compared.  Prints one JSON line.
+rescale and relinearisation) of the learned plan in the batched form.  The
+plain per-operation form is timed once on the paper-rule plan (the
+baseline) and once on the learned plan (its words must equal the batched
+form's).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -134,6 +140,7 @@ def main():
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-ks", action="store_true")
+    ap.add_argument("--rule-plan", action="store_true", help="batched form on the paper-rule plan (no learned search)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -143,7 +150,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2506_10399_amd import ficgcn as fg, graph
+    from paper_2506_10399_amd import ficgcn as fg, graph, costmodel as cm
     from workload import make_workload
 
     torch.cuda.set_device(0)
@@ -164,32 +171,65 @@ def main():
     L = prm["n_q"]
     ntt_cols = ctx.ckks_ntt_autotune(L + prm["n_p"])
     log("NTT autotune (column, row workgroup widths): %s" % (ntt_cols,))
-    plan = fg.Plan(ctx, rp, col, val, w.graph.n, dims, w.weights, activation=w.activation)
+
+    # plan choice: the paper's rule, and the learned search (cost model trained
+    # on SpIntra-CA layer latencies measured here on small synthetic graphs)
+    base = fg.PlanOpts(0, 1, 0, 0, int(w.activation), 0)
+    rule_plan = fg.Plan(ctx, rp, col, val, w.graph.n, dims, w.weights, activation=w.activation)
+    learned = None
+    plan = rule_plan
+    if not args.rule_plan:
+        t0 = time.perf_counter()
+        ctx_m = fg.Context.from_dict(dict(log_n=13, n_q=8, q_bits=50, n_p=2, p_bits=60, log_scale=40))
+        Xs, ys = [], []
+        for c in cm.synthetic_cases(8, 100, n_range=(128, 1400)):
+            _, F, ms = cm.measure_case(ctx_m, c, base)
+            Xs.append(F)
+            ys.append(ms)
+        net, losses = cm.train(ctx_m, np.concatenate(Xs), np.concatenate(ys), epochs=300)
+        t_train = time.perf_counter() - t0
+        best_l, st_l = fg.ficgcn_plan_search(ctx, rp, col, val, w.graph.n, dims, w.weights, base, model=net, keep=4)
+        best_x, st_x = fg.ficgcn_plan_search(ctx, rp, col, val, w.graph.n, dims, w.weights, base)
+        plan = fg.Plan(ctx, rp, col, val, w.graph.n, dims, w.weights, opts=best_l)
+        learned = dict(samples=int(sum(len(x) for x in Xs)), train_loss=[round(losses[0], 4), round(losses[-1], 5)],
+                       measure_and_train_s=round(t_train, 1),
+                       chosen=dict(t=best_l.t, use_noo=best_l.use_noo, TH=best_l.TH, family=best_l.family),
+                       built=[st_l.n_built, st_x.n_built], search_s=[round(st_l.build_seconds, 3),
+                                                                    round(st_x.build_seconds, 3)],
+                       judge_bytes=dict(learned=st_l.best_cost, exhaustive=st_x.best_cost,
+                                        paper_rule=rule_plan.ficgcn_plan_cost()),
+                       within_5pct=bool(st_l.best_cost <= 1.05 * st_x.best_cost))
+        log("learned plan search: %s" % learned)
     info = plan.ficgcn_plan_info()
-    steps_needed = plan.ficgcn_plan_rot_steps()
+    steps_needed = sorted(set(plan.ficgcn_plan_rot_steps()) | set(rule_plan.ficgcn_plan_rot_steps()))
     log("plan: %s ; %d rotation keys" % (info, len(steps_needed)))
     cl, ev = ctx.ckks_keygen(7, steps_needed, with_relin=True)
-    plan.ficgcn_plan_encode()
-    pi = plan.ficgcn_plan_node_order()
-    src = plan.ficgcn_plan_copy_sources(0)
     K, F = info[0]["K"], info[0]["f_in"]
     lv0 = L - 1
     n_in = K * F
     inputs = torch.empty((n_in, 2, lv0 + 1, N), dtype=torch.int64, device="cuda")
-    log("encrypting %d client ciphertexts (%.1f GiB)" % (n_in, inputs.numel() * 8 / 2 ** 30))
-    CH = 256
-    for k in range(K):
-        have = src[k] >= 0
-        for f0 in range(0, F, CH):
-            nf = min(CH, F - f0)
-            rows = np.zeros((nf, M))
-            rows[:, pi[have]] = w.x[src[k][have], f0:f0 + nf].T
-            pts = ctx.ckks_encode_batch(rows, 2.0 ** prm["log_scale"], lv0)
-            for i in range(nf):
-                ctx.ckks_encrypt(cl, pts[i], lv0, 1234, k * F + f0 + i, out=inputs[k * F + f0 + i])
-        log("  copy %d done" % k)
-    ctx.ckks_sync()
     in_list = [inputs[i] for i in range(n_in)]
+
+    def encrypt_for(p):
+        """The client's ciphertexts for plan p: copy k of column f in p's slot order."""
+        pi = p.ficgcn_plan_node_order()
+        src = p.ficgcn_plan_copy_sources(0)
+        CH = 256
+        for k in range(K):
+            have = src[k] >= 0
+            for f0 in range(0, F, CH):
+                nf = min(CH, F - f0)
+                rows = np.zeros((nf, M))
+                rows[:, pi[have]] = w.x[src[k][have], f0:f0 + nf].T
+                pts = ctx.ckks_encode_batch(rows, 2.0 ** prm["log_scale"], lv0)
+                for i in range(nf):
+                    ctx.ckks_encrypt(cl, pts[i], lv0, 1234, k * F + f0 + i, out=inputs[k * F + f0 + i])
+        ctx.ckks_sync()
+        return pi
+
+    log("encrypting %d client ciphertexts (%.1f GiB)" % (n_in, inputs.numel() * 8 / 2 ** 30))
+    plan.ficgcn_plan_encode()
+    pi = encrypt_for(plan)
     outs = [[ctx.ct_buffer(d["level_in"]) for _ in range(d["n_out_cts"])] for d in info]
     log("setup %.1f s" % (time.perf_counter() - t_setup))
 
@@ -201,14 +241,21 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    def step(mode):
+    def step(p, mode, outs_):
         cur = in_list
-        for li in range(len(info)):
-            plan.ficgcn_gcn_layer(ev, li, cur, outs[li], mode=mode)
-            cur = outs[li]
+        for li in range(len(outs_)):
+            p.ficgcn_gcn_layer(ev, li, cur, outs_[li], mode=mode)
+            cur = outs_[li]
 
+    def decrypt_err(p, outs_):
+        d = p.ficgcn_plan_info()[-1]
+        slots = [np.real(ctx.ckks_decrypt(cl, x, d["level_out"], d["scale_out"], M)) for x in outs_[-1]]
+        y = graph.read_output(p.ficgcn_plan_node_order(), slots, d["f_out"], d["t"], d["B"], d["kind"] == 1)
+        return float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
+
+    ref = fp64_gcn(rp, col, val, w.x, w.weights)
     for _ in range(args.warmup):
-        step(1)
+        step(plan, 1, outs)
     torch.cuda.synchronize()
     ctx.ficgcn_profile_enable(True)
     for k in ("inter_fused", "comb_fused", "keymac", "moddown", "modup", "ntt"):
@@ -216,7 +263,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step(1)
+        step(plan, 1, outs)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.ficgcn_profile_enable(False)
@@ -225,23 +272,37 @@ def main():
     log("batched: %.2f ms per inference; kernel event totals %s" % (ms_step, prof))
     last = info[-1]
     batched_words = [ctx.ckks_poly_store(x, last["level_out"], 2) for x in outs[-1]]
-    slots = [np.real(ctx.ckks_decrypt(cl, x, last["level_out"], last["scale_out"], M)) for x in outs[-1]]
-    y = graph.read_output(pi, slots, last["f_out"], last["t"], last["B"], last["kind"] == 1)
-    ref = fp64_gcn(rp, col, val, w.x, w.weights)
-    err = float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
+    err = decrypt_err(plan, outs)
     log("max rel err vs FP64 GCN: %.3e" % err)
 
-    plain_ms = None
+    plain_ms = plain_same_ms = None
     same = None
+    err_plain = None
     if not args.skip_plain:
+        # the same plan op by op: identical words
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        step(0)
+        step(plan, 0, outs)
         torch.cuda.synchronize()
-        plain_ms = (time.perf_counter() - t0) * 1e3
+        plain_same_ms = (time.perf_counter() - t0) * 1e3
         plain_words = [ctx.ckks_poly_store(x, last["level_out"], 2) for x in outs[-1]]
         same = all(np.array_equal(a, b) for a, b in zip(plain_words, batched_words))
-        log("plain: %.2f ms, words equal to batched: %s" % (plain_ms, same))
+        log("plain, same plan: %.2f ms, words equal to batched: %s" % (plain_same_ms, same))
+        if plan is rule_plan:
+            plain_ms, err_plain = plain_same_ms, err
+        else:
+            # the paper's rule plan op by op: the plain baseline
+            rule_plan.ficgcn_plan_encode()
+            encrypt_for(rule_plan)
+            r_info = rule_plan.ficgcn_plan_info()
+            outs_r = [[ctx.ct_buffer(d["level_in"]) for _ in range(d["n_out_cts"])] for d in r_info]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            step(rule_plan, 0, outs_r)
+            torch.cuda.synchronize()
+            plain_ms = (time.perf_counter() - t0) * 1e3
+            err_plain = decrypt_err(rule_plan, outs_r)
+        log("plain, paper-rule plan: %.2f ms, max rel err %.3e" % (plain_ms, err_plain))
 
     ks = {}
     if not args.skip_ks:
@@ -312,7 +373,9 @@ def main():
                            form="batched (fused Inter-CA pass, hoisted rotations)", ntt_tiles=list(ntt_cols)),
                plain_ms=None if plain_ms is None else round(plain_ms, 3),
                speedup_vs_plain=None if plain_ms is None else round(plain_ms / ms_step, 3),
-               plain_equals_batched=same, max_rel_err=err, keyswitch=ks, roofline=roofline,
+               plain_same_plan_ms=None if plain_same_ms is None else round(plain_same_ms, 3),
+               plain_equals_batched=same, max_rel_err=err, max_rel_err_plain=err_plain,
+               learned_planner=learned, keyswitch=ks, roofline=roofline,
                kernel_ms_per_step={k: round(v[0] / args.steps, 3) for k, v in prof.items()},
                cpu_baseline=cpu)
     print(json.dumps(out), flush=True)

@@ -183,6 +183,8 @@ typedef struct {
   int32_t family;       /* SpIntra-CA routing: 0 = cheaper of the two, 1 = diagonal, 2 = baby-step/giant-step */
   int32_t TH;           /* region size cap; 0 = 1024 below 10000 nodes, else 4096 */
   int32_t activation;   /* x^2 after every layer */
+  int32_t t;            /* SpIntra-CA packing: columns per ciphertext, a power of two no larger than
+                           next_pow2(F') and M / next_pow2(n_v); 0 = the paper's rule (Sec. 3.2, App. B) */
 } ficgcn_plan_opts;
 
 /* Builds the plan of an n_layers-layer GCN over the normalised adjacency
@@ -226,6 +228,12 @@ ficgcn_status ficgcn_plan_encode(ckks_ctx* ctx, ficgcn_plan* plan);
 ficgcn_status ficgcn_plan_load_operand(ckks_ctx* ctx, ficgcn_plan* plan, uint32_t layer, size_t i,
                                        const uint64_t* host_coeffs);
 
+/* Fills every operand of the plan with uniform residues drawn on the device
+ * (ChaCha20 stream (6, layer * 2^20 + operand, limb) of `seed`, one the
+ * scheme never uses).  For latency measurement only: the layer runs exactly
+ * as with encoded operands, but its words mean nothing. */
+ficgcn_status ficgcn_plan_fill_operands(ckks_ctx* ctx, ficgcn_plan* plan, uint64_t seed);
+
 /* Runs layer `layer` of the plan (combination, packing, aggregation,
  * rescales and the x^2 activation as the plan schedules them).
  * Inputs: Inter-CA first layer: K*F client ciphertexts, copy k of column f at
@@ -235,6 +243,81 @@ ficgcn_status ficgcn_plan_load_operand(ckks_ctx* ctx, ficgcn_plan* plan, uint32_
 ficgcn_status ficgcn_gcn_layer(ckks_ctx* ctx, const ckks_keys* eval_keys, const ficgcn_plan* plan, uint32_t layer,
                                const uint64_t* const* in_cts, size_t n_in, uint64_t* const* out_cts, size_t n_out,
                                int32_t mode);
+
+/* ------------------------------------------------------ plan search [server]
+ * The packing and node-order choice as a search over candidate plans
+ * (packing t of Sec. 3.2, NOO on/off and its region cap TH of Sec. 3.4, the
+ * SpIntra-CA routing family).  The analytic judge scores a built plan by the
+ * algorithmic HBM bytes of its batched execution; a learned cost model
+ * (below) may prune the candidates before any plan is built. */
+
+/* Number of floats ficgcn_candidate_features writes. */
+#define FICGCN_N_FEATURES 24
+
+/* Enumerates the candidate options for this graph size and model: every
+ * feasible t, NOO off (when the graph fits one column block) or on with TH
+ * in {64, 256, 1024, 4096} below n_v (plus TH = n_v), family 1 and 2; the
+ * other fields are copied from base.  Writes up to cap entries, *n_out =
+ * the full count.  Host only. */
+ficgcn_status ficgcn_plan_candidates(uint32_t n_v, const uint32_t* dims, uint32_t n_layers, uint32_t log_n,
+                                     const ficgcn_plan_opts* base, ficgcn_plan_opts* out, size_t cap,
+                                     size_t* n_out);
+/* Local-adjacency features of one candidate, computed from the CSR graph
+ * (as ficgcn_plan_create takes it) without building the plan: degree
+ * statistics, locality of the given node order, shift counts of the
+ * identity order, and the candidate's t, B, TH, family.  Host only; out
+ * holds FICGCN_N_FEATURES floats. */
+ficgcn_status ficgcn_candidate_features(const int32_t* rowptr, const int32_t* col, uint32_t n_v, const uint32_t* dims,
+                                        uint32_t n_layers, uint32_t log_n, const ficgcn_plan_opts* opts, float* out);
+/* Analytic judge: algorithmic HBM bytes of one batched inference of the
+ * plan (inputs, keys, masks and outputs of every operation, per the key
+ * switching, MAC and rescale byte counts), as a double.  Host only. */
+ficgcn_status ficgcn_plan_cost(const ficgcn_plan* plan, double* bytes_out);
+
+typedef struct ficgcn_mlp ficgcn_mlp;
+
+typedef struct {
+  uint32_t n_candidates;   /* candidates enumerated */
+  uint32_t n_built;        /* plans built and judged */
+  double best_cost;        /* judge's bytes of the chosen plan */
+  double build_seconds;    /* host time spent building candidate plans */
+} ficgcn_search_stats;
+
+/* Picks the options of the plan to build.  model == NULL: exhaustive
+ * analytic search (every candidate built and judged).  Otherwise the model
+ * predicts each candidate's latency from its features, the `keep` fastest
+ * predictions are built and judged, and the judge's best of those wins
+ * (every candidate is the fallback when none of the kept builds).  The
+ * model runs on the context's device. */
+ficgcn_status ficgcn_plan_search(ckks_ctx* ctx, const int32_t* rowptr, const int32_t* col, const double* val,
+                                 uint32_t n_v, const uint32_t* dims, uint32_t n_layers, const double* const* weights,
+                                 const ficgcn_plan_opts* base, ficgcn_mlp* model, uint32_t keep,
+                                 ficgcn_plan_opts* best_out, ficgcn_search_stats* stats_out);
+
+/* ------------------------------------------------ learned cost model [server]
+ * A fully connected network widths[0] -> ... -> widths[n-1] with ReLU after
+ * every layer but the last, fp32, trained by mean squared error with Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8).  Parameters are packed layer by layer
+ * as W_j [widths[j+1]][widths[j]] then b_j [widths[j+1]]; the caller
+ * supplies the initial values (host).  Forward, backward and Adam run in the
+ * library's kernels on the context's stream; x and y are device buffers
+ * [n][widths[0]] and [n][widths[n-1]]. */
+ficgcn_status ficgcn_mlp_create(ckks_ctx* ctx, const uint32_t* widths, uint32_t n_widths, const float* params,
+                                ficgcn_mlp** out);
+void ficgcn_mlp_destroy(ficgcn_mlp* mlp);
+ficgcn_status ficgcn_mlp_param_count(const ficgcn_mlp* mlp, size_t* n_out);
+/* Copies the parameters to host memory (n_params floats). */
+ficgcn_status ficgcn_mlp_get_params(const ficgcn_mlp* mlp, float* params_out);
+/* y = network(x) for n rows. */
+ficgcn_status ficgcn_mlp_forward(ficgcn_mlp* mlp, const float* x_dev, uint32_t n, float* y_dev);
+/* Loss mean((network(x) - y)^2) and its gradient (n_params floats), both to
+ * host memory; parameters unchanged. */
+ficgcn_status ficgcn_mlp_gradient(ficgcn_mlp* mlp, const float* x_dev, const float* y_dev, uint32_t n,
+                                  float* loss_out, float* grad_out);
+/* One Adam step on the batch (x, y) with learning rate lr; *loss_out gets the
+ * batch loss before the step. */
+ficgcn_status ficgcn_mlp_train_step(ficgcn_mlp* mlp, const float* x_dev, const float* y_dev, uint32_t n, float lr,
+                                    float* loss_out);
 
 #ifdef __cplusplus
 }

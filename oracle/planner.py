@@ -325,11 +325,13 @@ def rotation_steps_of(lp: LayerPlan) -> List[int]:
 
 def build_plan(n_v: int, rows, dims: Sequence[int], activation: bool, M: int,
                use_noo: bool = True, TH: Optional[int] = None, family: Optional[int] = None,
-               first_mode: str = "inter") -> Plan:
+               first_mode: str = "inter", t: Optional[int] = None) -> Plan:
     """The executable plan: layer 1 by `first_mode` ("inter" per the paper's
     first-layer rule, or "spintra"), later layers SpIntra-CA; SpIntra layers
     combine first (F -> F' at one column per ciphertext), pack t = min(pow2(F'),
-    M / pow2(n_v)) columns per ciphertext, then aggregate on the packed layout."""
+    M / pow2(n_v)) columns per ciphertext, then aggregate on the packed layout.
+    A given t (a power of two no larger than pow2(F') of every SpIntra layer
+    and M / pow2(n_v)) replaces that rule for every SpIntra layer."""
     n_layers = len(dims) - 1
     if first_mode == "spintra" and n_layers > 1:
         raise ValueError("a SpIntra-CA layer leaves packed ciphertexts; only the last layer may be SpIntra-CA "
@@ -337,6 +339,10 @@ def build_plan(n_v: int, rows, dims: Sequence[int], activation: bool, M: int,
     # packing of the SpIntra layers fixes the block the node order must fit
     spin_f = [dims[i + 1] for i in range(n_layers) if i > 0 or first_mode == "spintra"]
     t_pack = min([next_pow2(f) for f in spin_f] + [M // next_pow2(n_v)]) if spin_f else 1
+    if t is not None and spin_f:
+        if t < 1 or t & (t - 1) or t > t_pack:
+            raise ValueError("packing t must be a power of two no larger than %d" % t_pack)
+        t_pack = t
     B = M // t_pack
     if TH is None:
         TH = 1024 if n_v < 10000 else 4096
@@ -362,16 +368,16 @@ def build_plan(n_v: int, rows, dims: Sequence[int], activation: bool, M: int,
                         k += 1
             layers.append(LayerPlan("inter", f_in, f_out, activation, K=K, copy_src=src, copy_val=val))
         else:
-            t = min(next_pow2(f_out), M // next_pow2(n_v))
-            Bl = M // t
+            t_l = t_pack if t is not None else min(next_pow2(f_out), M // next_pow2(n_v))
+            Bl = M // t_l
             wrap = Bl == M
             shifts = sorted({reduce_shift(int(pi[u] - pi[v]), M, wrap) for v, row in enumerate(rows)
                              for u, _ in row})
             G, c2 = bsgs_split(shifts, Bl)
             c1 = len(set(shifts) - {0})
             fam = family if family is not None else (2 if c2 < c1 else 1)
-            pack = [-(l % t) * Bl for l in range(f_out) if l % t != 0]
-            layers.append(LayerPlan("spintra", f_in, f_out, activation, t=t, B=Bl, shifts=shifts,
+            pack = [-(l % t_l) * Bl for l in range(f_out) if l % t_l != 0]
+            layers.append(LayerPlan("spintra", f_in, f_out, activation, t=t_l, B=Bl, shifts=shifts,
                                     family=fam, G=G, pack_steps=sorted(set(pack))))
     return Plan(n_v=n_v, M=M, B_pi=B, pi=pi, rows=rows, layers=layers, regions=regions)
 

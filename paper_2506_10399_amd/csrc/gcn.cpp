@@ -751,6 +751,25 @@ ficgcn_status ficgcn_plan_load_operand(ckks_ctx* ctx, ficgcn_plan* plan, uint32_
   GUARD_END
 }
 
+ficgcn_status ficgcn_plan_fill_operands(ckks_ctx* ctx, ficgcn_plan* plan, uint64_t seed) {
+  GUARD_BEGIN
+  if (!ctx || !plan) FICGCN_THROW(EINVAL_, "null argument");
+  ensure_device(ctx);
+  for (size_t li = 0; li < plan->layers.size(); ++li) {
+    LayerPlan& lp = plan->layers[li];
+    ensure_ops_block(ctx, lp);
+    const size_t per = (size_t)(lp.op_level + 1) * ctx->N;
+    for (size_t i = 0; i < lp.ops.size(); ++i) {
+      uint64_t* dst = lp.ops_block + i * per;
+      // stream (6, layer * 2^20 + i, limb): a stream the scheme itself never draws
+      sample_uniform(ctx, dst, seed, 6, (uint32_t)(li << 20 | i), 0, lp.op_level + 1, lm_q(lp.op_level + 1), 1);
+      lp.ops[i] = dst;
+    }
+  }
+  HIPCHECK(hipStreamSynchronize(ctx->stream));
+  GUARD_END
+}
+
 ficgcn_status ficgcn_gcn_layer(ckks_ctx* ctx, const ckks_keys* eval_keys, const ficgcn_plan* plan, uint32_t layer,
                                const uint64_t* const* in_cts, size_t n_in, uint64_t* const* out_cts, size_t n_out,
                                int32_t mode) {

@@ -367,6 +367,11 @@ void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_la
     for (int f : spin_f) t_pack = std::min(t_pack, next_pow2(f));
   }
   if (t_pack < 1) FICGCN_THROW(EPLAN_, "graph larger than the slot count");
+  if (o.t != 0 && !spin_f.empty()) {
+    if (o.t < 1 || (o.t & (o.t - 1)) || o.t > t_pack)
+      FICGCN_THROW(EPLAN_, "packing t must be a power of two no larger than " + std::to_string(t_pack));
+    t_pack = o.t;
+  }
   const int B = M / t_pack;
   p->B_pi = B;
   const int TH = o.TH > 0 ? o.TH : (n < 10000 ? 1024 : 4096);
@@ -415,7 +420,7 @@ void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_la
         }
       }
     } else {
-      lp.t = std::min(next_pow2(lp.f_out), M / next_pow2(n));
+      lp.t = o.t != 0 ? t_pack : std::min(next_pow2(lp.f_out), M / next_pow2(n));
       lp.B = M / lp.t;
       const bool wrap = lp.B == M;
       std::set<int64_t> sh;

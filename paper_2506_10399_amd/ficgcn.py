@@ -36,8 +36,15 @@ class CkksParams(ctypes.Structure):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("first_mode", ctypes.c_int32), ("use_noo", ctypes.c_int32), ("family", ctypes.c_int32),
-                ("TH", ctypes.c_int32), ("activation", ctypes.c_int32)]
+                ("TH", ctypes.c_int32), ("activation", ctypes.c_int32), ("t", ctypes.c_int32)]
 
+
+class SearchStats(ctypes.Structure):
+    _fields_ = [("n_candidates", ctypes.c_uint32), ("n_built", ctypes.c_uint32), ("best_cost", ctypes.c_double),
+                ("build_seconds", ctypes.c_double)]
+
+
+N_FEATURES = 24
 
 # name -> (restype, argtypes); every status-returning call returns c_int
 _SIGS = {
@@ -92,6 +99,24 @@ _SIGS = {
     "ficgcn_plan_load_operand": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, ctypes.c_size_t, c_vp]),
     "ficgcn_gcn_layer": (ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_uint32, c_vp, ctypes.c_size_t, c_vp,
                                         ctypes.c_size_t, ctypes.c_int32]),
+    "ficgcn_plan_fill_operands": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint64]),
+    "ficgcn_plan_candidates": (ctypes.c_int, [ctypes.c_uint32, c_vp, ctypes.c_uint32, ctypes.c_uint32,
+                                              ctypes.POINTER(PlanOpts), c_vp, ctypes.c_size_t,
+                                              ctypes.POINTER(ctypes.c_size_t)]),
+    "ficgcn_candidate_features": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, c_vp, ctypes.c_uint32,
+                                                 ctypes.c_uint32, ctypes.POINTER(PlanOpts), c_vp]),
+    "ficgcn_plan_cost": (ctypes.c_int, [c_vp, ctypes.POINTER(ctypes.c_double)]),
+    "ficgcn_plan_search": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.c_uint32, c_vp, ctypes.c_uint32, c_vp,
+                                          ctypes.POINTER(PlanOpts), c_vp, ctypes.c_uint32,
+                                          ctypes.POINTER(PlanOpts), ctypes.POINTER(SearchStats)]),
+    "ficgcn_mlp_create": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, c_vp, ctypes.POINTER(c_vp)]),
+    "ficgcn_mlp_destroy": (None, [c_vp]),
+    "ficgcn_mlp_param_count": (ctypes.c_int, [c_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "ficgcn_mlp_get_params": (ctypes.c_int, [c_vp, c_vp]),
+    "ficgcn_mlp_forward": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, c_vp]),
+    "ficgcn_mlp_gradient": (ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_float), c_vp]),
+    "ficgcn_mlp_train_step": (ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_uint32, ctypes.c_float,
+                                             ctypes.POINTER(ctypes.c_float)]),
 }
 
 
@@ -148,6 +173,7 @@ class Context:
         h = c_vp()
         _check(lib().ckks_context_create(ctypes.byref(self.params), ctypes.byref(h)))
         self.h = h
+        self.log_n = log_n
         self.N = 1 << log_n
         self.M = self.N // 2
         self.L, self.alpha, self.log_scale = n_q, n_p, log_scale
@@ -335,7 +361,8 @@ class Plan:
     """ficgcn_plan: node order, per-layer routing and schedule, operands."""
 
     def __init__(self, ctx: Context, rowptr, col, val, n_v: int, dims: Sequence[int], weights,
-                 first_mode: int = 0, use_noo: bool = True, family: int = 0, TH: int = 0, activation: bool = False):
+                 first_mode: int = 0, use_noo: bool = True, family: int = 0, TH: int = 0, activation: bool = False,
+                 t: int = 0, opts: "PlanOpts" = None):
         self.ctx = ctx
         self._rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
         self._col = np.ascontiguousarray(col, dtype=np.int32)
@@ -343,7 +370,9 @@ class Plan:
         self._dims = np.ascontiguousarray(dims, dtype=np.uint32)
         self._w = [np.ascontiguousarray(w, dtype=np.float64) for w in weights]
         wp = _ptr_array(self._w)
-        opts = PlanOpts(first_mode, int(use_noo), family, TH, int(activation))
+        if opts is None:
+            opts = PlanOpts(first_mode, int(use_noo), family, TH, int(activation), t)
+        self.opts = opts
         h = c_vp()
         _check(lib().ficgcn_plan_create(ctx.h, _ptr(self._rowptr), _ptr(self._col), _ptr(self._val), n_v,
                                         _ptr(self._dims), len(self._w), wp, ctypes.byref(opts), ctypes.byref(h)))
@@ -372,6 +401,14 @@ class Plan:
         out = np.zeros(max(1, n.value), dtype=np.int64)
         _check(lib().ficgcn_plan_rot_steps(self.h, _ptr(out), n.value, ctypes.byref(n)))
         return [int(x) for x in out[: n.value]]
+
+    def ficgcn_plan_fill_operands(self, seed: int):
+        _check(lib().ficgcn_plan_fill_operands(self.ctx.h, self.h, seed))
+
+    def ficgcn_plan_cost(self) -> float:
+        c = ctypes.c_double()
+        _check(lib().ficgcn_plan_cost(self.h, ctypes.byref(c)))
+        return c.value
 
     def ficgcn_plan_info(self) -> List[dict]:
         n = ctypes.c_uint32()
@@ -421,3 +458,87 @@ class Plan:
     def ficgcn_gcn_layer(self, eval_keys: Keys, layer: int, in_cts, out_cts, mode: int = 1):
         _check(lib().ficgcn_gcn_layer(self.ctx.h, eval_keys.h, self.h, layer, _ptr_array(in_cts), len(in_cts),
                                       _ptr_array(out_cts), len(out_cts), mode))
+
+
+# ------------------------------------------------------------------ plan search
+def ficgcn_plan_candidates(n_v: int, dims: Sequence[int], log_n: int, base: PlanOpts) -> List[PlanOpts]:
+    d = np.ascontiguousarray(dims, dtype=np.uint32)
+    n = ctypes.c_size_t()
+    _check(lib().ficgcn_plan_candidates(n_v, _ptr(d), len(d) - 1, log_n, ctypes.byref(base), None, 0,
+                                        ctypes.byref(n)))
+    arr = (PlanOpts * n.value)()
+    _check(lib().ficgcn_plan_candidates(n_v, _ptr(d), len(d) - 1, log_n, ctypes.byref(base), arr, n.value,
+                                        ctypes.byref(n)))
+    return list(arr)
+
+
+def ficgcn_candidate_features(rowptr, col, n_v: int, dims: Sequence[int], log_n: int, opts: PlanOpts) -> np.ndarray:
+    rp = np.ascontiguousarray(rowptr, dtype=np.int32)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    d = np.ascontiguousarray(dims, dtype=np.uint32)
+    out = np.zeros(N_FEATURES, dtype=np.float32)
+    _check(lib().ficgcn_candidate_features(_ptr(rp), _ptr(cl), n_v, _ptr(d), len(d) - 1, log_n,
+                                           ctypes.byref(opts), _ptr(out)))
+    return out
+
+
+def ficgcn_plan_search(ctx: Context, rowptr, col, val, n_v: int, dims: Sequence[int], weights, base: PlanOpts,
+                       model: "Mlp" = None, keep: int = 0):
+    rp = np.ascontiguousarray(rowptr, dtype=np.int32)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    vl = np.ascontiguousarray(val, dtype=np.float64)
+    d = np.ascontiguousarray(dims, dtype=np.uint32)
+    ws = [np.ascontiguousarray(w, dtype=np.float64) for w in weights]
+    best = PlanOpts()
+    stats = SearchStats()
+    _check(lib().ficgcn_plan_search(ctx.h, _ptr(rp), _ptr(cl), _ptr(vl), n_v, _ptr(d), len(ws), _ptr_array(ws),
+                                    ctypes.byref(base), model.h if model is not None else None, keep,
+                                    ctypes.byref(best), ctypes.byref(stats)))
+    return best, stats
+
+
+class Mlp:
+    """ficgcn_mlp: the learned cost model (fp32 network, trained on the GPU)."""
+
+    def __init__(self, ctx: Context, widths: Sequence[int], params: np.ndarray):
+        self.ctx = ctx
+        w = np.ascontiguousarray(widths, dtype=np.uint32)
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        h = c_vp()
+        _check(lib().ficgcn_mlp_create(ctx.h, _ptr(w), len(w), _ptr(p), ctypes.byref(h)))
+        self.h = h
+        n = ctypes.c_size_t()
+        _check(lib().ficgcn_mlp_param_count(self.h, ctypes.byref(n)))
+        self.n_params = n.value
+        self.widths = list(widths)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ficgcn_mlp_destroy(self.h)
+            self.h = None
+
+    def ficgcn_mlp_get_params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().ficgcn_mlp_get_params(self.h, _ptr(out)))
+        return out
+
+    def ficgcn_mlp_forward(self, x, y=None):
+        y = self._buf(x.shape[0], self.widths[-1]) if y is None else y
+        _check(lib().ficgcn_mlp_forward(self.h, _ptr(x), x.shape[0], _ptr(y)))
+        return y
+
+    def ficgcn_mlp_gradient(self, x, y):
+        loss = ctypes.c_float()
+        g = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().ficgcn_mlp_gradient(self.h, _ptr(x), _ptr(y), x.shape[0], ctypes.byref(loss), _ptr(g)))
+        return float(loss.value), g
+
+    def ficgcn_mlp_train_step(self, x, y, lr: float) -> float:
+        loss = ctypes.c_float()
+        _check(lib().ficgcn_mlp_train_step(self.h, _ptr(x), _ptr(y), x.shape[0], lr, ctypes.byref(loss)))
+        return float(loss.value)
+
+    @staticmethod
+    def _buf(rows, cols):
+        import torch
+        return torch.empty((rows, cols), dtype=torch.float32, device="cuda")
