@@ -319,6 +319,55 @@ ficgcn_status ficgcn_mlp_gradient(ficgcn_mlp* mlp, const float* x_dev, const flo
 ficgcn_status ficgcn_mlp_train_step(ficgcn_mlp* mlp, const float* x_dev, const float* y_dev, uint32_t n, float lr,
                                     float* loss_out);
 
+/* ----------------------------------------------------------- serving [server]
+ * Continuous batching of encrypted GCN inferences on one GPU.  The server
+ * runs up to n_slots requests at once, each on its own context and stream
+ * (so their kernels overlap on the device), admits waiting requests in FIFO
+ * order as slots and device memory free up (a later request that fits may
+ * pass the head until the head has been passed 16 times), and keeps every
+ * client's evaluation keys resident (the caller's ckks_keys objects).  A
+ * request's footprint = its input ciphertexts + every layer's outputs + its
+ * encoded plan operands; it must fit under hbm_budget_bytes next to the
+ * running requests (per-slot scratch is outside the budget). */
+typedef struct ficgcn_server ficgcn_server;
+
+typedef struct {
+  const ficgcn_plan* plan;         /* the graph's plan (server side); serves one request at a time */
+  const ckks_keys* eval_keys;      /* the client's keys, resident on the device */
+  const uint64_t* inputs_host;     /* n_in client ciphertexts [n_in][2][level_in+1][N] in host memory
+                                      (pinned for an asynchronous upload); read while the request runs */
+  size_t n_in;
+  uint64_t* output_host;           /* the last layer's n_out ciphertexts [n_out][2][level_out+1][N] */
+  size_t n_out;
+} ficgcn_request;
+
+typedef struct {
+  int32_t status;                  /* the request's ficgcn_status */
+  double queue_ms, run_ms, latency_ms;   /* submission to admission, admission to completion, total */
+  uint64_t footprint_bytes;
+} ficgcn_request_result;
+
+typedef struct {
+  uint32_t completed, failed;
+  double p50_ms, p99_ms, mean_ms;  /* latency (submission to completion), nearest-rank percentiles */
+  double throughput_per_s;         /* completed requests / (last completion - first submission) */
+  uint64_t peak_bytes;             /* largest admitted footprint sum */
+  uint32_t max_concurrent;         /* most requests running at once */
+} ficgcn_server_summary;
+
+/* Creates the slots (contexts for params on the current device, one stream
+ * each, at the default priority) and their worker threads. */
+ficgcn_status ficgcn_server_create(const ckks_params* params, uint32_t n_slots, uint64_t hbm_budget_bytes,
+                                   ficgcn_server** out);
+/* Stops the workers after their running requests; waiting requests are dropped. */
+void ficgcn_server_destroy(ficgcn_server* server);
+/* Queues a request; ENOMEM if it can never fit the budget, EINVAL if its plan
+ * has other parameters or another request of the same plan is pending. */
+ficgcn_status ficgcn_server_submit(ficgcn_server* server, const ficgcn_request* req, uint64_t* id_out);
+/* Blocks until the request completes; returns its status. */
+ficgcn_status ficgcn_server_wait(ficgcn_server* server, uint64_t id, ficgcn_request_result* out);
+ficgcn_status ficgcn_server_stats(ficgcn_server* server, ficgcn_server_summary* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -340,14 +340,30 @@ using namespace ficgcn;
 
 ficgcn_plan::~ficgcn_plan() {
   if (ctx && ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  for (auto& lp : layers) {
-    if (lp.ops_block) (void)hipFree(lp.ops_block);
-    if (lp.w_dev) (void)hipFree(lp.w_dev);
-    if (lp.wf_dev) (void)hipFree(lp.wf_dev);
-    if (lp.wm_dev) (void)hipFree(lp.wm_dev);
-    if (lp.pw_dev) (void)hipFree(lp.pw_dev);
+  ficgcn::release_plan_device(this);
+}
+
+namespace ficgcn {
+
+void release_plan_device(ficgcn_plan* p) {
+  for (auto& lp : p->layers) {
+    for (void** q : {(void**)&lp.ops_block, (void**)&lp.w_dev, &lp.wf_dev, (void**)&lp.wm_dev, (void**)&lp.pw_dev})
+      if (*q) {
+        (void)hipFree(*q);
+        *q = nullptr;
+      }
+    for (auto& o : lp.ops) o = nullptr;
+    lp.wm_state = 0;
   }
 }
+
+size_t plan_operand_bytes(const ficgcn_plan* p) {
+  size_t b = 0;
+  for (const auto& lp : p->layers) b += lp.ops.size() * (size_t)(lp.op_level + 1) * p->ctx->N * 8;
+  return b;
+}
+
+}  // namespace ficgcn
 
 namespace ficgcn {
 

@@ -63,4 +63,8 @@ void plan_operand_slots(const ficgcn_plan* p, int li, size_t i, std::vector<doub
 size_t plan_operand_count(const ficgcn_plan* p, int li);
 void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const uint64_t* const* in, size_t n_in,
                uint64_t* const* out, size_t n_out, int mode);
+// frees the plan's device memory (operands and layer constants); the plan can be encoded again
+void release_plan_device(ficgcn_plan* p);
+// device bytes the plan's operands take once encoded
+size_t plan_operand_bytes(const ficgcn_plan* p);
 }  // namespace ficgcn

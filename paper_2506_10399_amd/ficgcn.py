@@ -46,6 +46,22 @@ class SearchStats(ctypes.Structure):
 
 N_FEATURES = 24
 
+
+class Request(ctypes.Structure):
+    _fields_ = [("plan", c_vp), ("eval_keys", c_vp), ("inputs_host", c_vp), ("n_in", ctypes.c_size_t),
+                ("output_host", c_vp), ("n_out", ctypes.c_size_t)]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
+                ("latency_ms", ctypes.c_double), ("footprint_bytes", ctypes.c_uint64)]
+
+
+class ServerSummary(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint32), ("failed", ctypes.c_uint32), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double), ("throughput_per_s", ctypes.c_double),
+                ("peak_bytes", ctypes.c_uint64), ("max_concurrent", ctypes.c_uint32)]
+
 # name -> (restype, argtypes); every status-returning call returns c_int
 _SIGS = {
     "ficgcn_last_error": (ctypes.c_char_p, []),
@@ -109,6 +125,12 @@ _SIGS = {
     "ficgcn_plan_search": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.c_uint32, c_vp, ctypes.c_uint32, c_vp,
                                           ctypes.POINTER(PlanOpts), c_vp, ctypes.c_uint32,
                                           ctypes.POINTER(PlanOpts), ctypes.POINTER(SearchStats)]),
+    "ficgcn_server_create": (ctypes.c_int, [ctypes.POINTER(CkksParams), ctypes.c_uint32, ctypes.c_uint64,
+                                            ctypes.POINTER(c_vp)]),
+    "ficgcn_server_destroy": (None, [c_vp]),
+    "ficgcn_server_submit": (ctypes.c_int, [c_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+    "ficgcn_server_wait": (ctypes.c_int, [c_vp, ctypes.c_uint64, ctypes.POINTER(RequestResult)]),
+    "ficgcn_server_stats": (ctypes.c_int, [c_vp, ctypes.POINTER(ServerSummary)]),
     "ficgcn_mlp_create": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, c_vp, ctypes.POINTER(c_vp)]),
     "ficgcn_mlp_destroy": (None, [c_vp]),
     "ficgcn_mlp_param_count": (ctypes.c_int, [c_vp, ctypes.POINTER(ctypes.c_size_t)]),
@@ -542,3 +564,45 @@ class Mlp:
     def _buf(rows, cols):
         import torch
         return torch.empty((rows, cols), dtype=torch.float32, device="cuda")
+
+
+class Server:
+    """ficgcn_server: continuous batching of encrypted inferences on one GPU."""
+
+    def __init__(self, params: dict, n_slots: int, hbm_budget_bytes: int):
+        p = CkksParams(params["log_n"], params["n_q"], params["q_bits"], params["n_p"], params["p_bits"],
+                       params.get("log_scale", 40))
+        h = c_vp()
+        _check(lib().ficgcn_server_create(ctypes.byref(p), n_slots, hbm_budget_bytes, ctypes.byref(h)))
+        self.h = h
+        self._held = {}
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ficgcn_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def ficgcn_server_submit(self, plan: "Plan", eval_keys: "Keys", inputs_host, n_in: int, output_host,
+                             n_out: int) -> int:
+        r = Request(plan.h, eval_keys.h, _ptr(inputs_host), n_in, _ptr(output_host), n_out)
+        rid = ctypes.c_uint64()
+        _check(lib().ficgcn_server_submit(self.h, ctypes.byref(r), ctypes.byref(rid)))
+        self._held[rid.value] = (plan, eval_keys, inputs_host, output_host)   # alive until waited for
+        return rid.value
+
+    def ficgcn_server_wait(self, rid: int) -> dict:
+        res = RequestResult()
+        st = lib().ficgcn_server_wait(self.h, rid, ctypes.byref(res))
+        self._held.pop(rid, None)
+        out = {f: getattr(res, f) for f, _ in RequestResult._fields_}
+        if st != 0:
+            raise FicgcnError(st, lib().ficgcn_last_error().decode())
+        return out
+
+    def ficgcn_server_stats(self) -> dict:
+        s = ServerSummary()
+        _check(lib().ficgcn_server_stats(self.h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerSummary._fields_}
