@@ -143,11 +143,17 @@ def main():
     ap.add_argument("--rule-plan", action="store_true", help="batched form on the paper-rule plan (no learned search)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (scale reference for HBM counters)")
+    ap.add_argument("--serving", action="store_true",
+                    help="instead: a Poisson stream of encrypted GCN requests through the server (rate sweep)")
+    ap.add_argument("--requests", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.serving:
+        serving_bench(args)
+        return
 
     import torch
     from paper_2506_10399_amd import ficgcn as fg, graph, costmodel as cm
@@ -378,6 +384,61 @@ def main():
                learned_planner=learned, keyswitch=ks, roofline=roofline,
                kernel_ms_per_step={k: round(v[0] / args.steps, 3) for k, v in prof.items()},
                cpu_baseline=cpu)
+    print(json.dumps(out), flush=True)
+
+
+def serving_bench(args):
+    """Encrypted 2-layer GCN requests on power-law graphs of log-uniform size
+    (500-4000 nodes) and feature width (64-160), hidden 16, 2-10 classes,
+    CKKS N = 2^16 with 8 + 2 primes; one client's keys resident; plans by the
+    learned search.  The server (4 slots, 64 GB budget) first takes every
+    request at once (its saturated throughput), then Poisson streams at 25%,
+    50% and 90% of that rate."""
+    import torch
+    from paper_2506_10399_amd import ficgcn as fg, costmodel as cm, serving as sv
+    torch.cuda.set_device(0)
+    params = dict(log_n=16, n_q=8, q_bits=50, n_p=2, p_bits=60, log_scale=40)
+    t0 = time.perf_counter()
+    ctx_m = fg.Context.from_dict(dict(log_n=13, n_q=8, q_bits=50, n_p=2, p_bits=60, log_scale=40))
+    base = fg.PlanOpts(0, 1, 0, 0, 1, 0)
+    Xs, ys = [], []
+    for c in cm.synthetic_cases(8, 100, n_range=(128, 1400)):
+        _, F, ms = cm.measure_case(ctx_m, c, base)
+        Xs.append(F)
+        ys.append(ms)
+    net, _ = cm.train(ctx_m, np.concatenate(Xs), np.concatenate(ys), epochs=300)
+    ctx = fg.Context.from_dict(params)
+    ctx.ckks_ntt_autotune(params["n_q"] + params["n_p"])
+    reqs = sv.make_requests(ctx, args.requests, 505, n_range=(500, 4000), f_range=(64, 160), model=net)
+    cl, ev = sv.client_keys(ctx, reqs, 88)
+    for i, q in enumerate(reqs):
+        sv.encrypt_inputs(ctx, cl, q, 2000 + i)
+    log("serving setup %.1f s: %s" % (time.perf_counter() - t0, [q.name for q in reqs]))
+    runs = []
+    budget = 64 << 30
+
+    def one(rate, seed):
+        srv = fg.Server(params, 4, budget)
+        st = sv.run_stream(srv, reqs, ev, rate, seed)
+        srv.close()
+        st = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+        st["offered_per_s"] = rate if rate > 0 else None
+        log("rate %s: %s" % (rate, st))
+        return st
+
+    sat = one(0.0, 1)
+    runs.append(sat)
+    for frac in (0.25, 0.5, 0.9):
+        runs.append(one(frac * sat["throughput_per_s"], 2))
+    err = max(sv.decrypt_error(ctx, cl, q) for q in reqs)
+    out = dict(metric="serving: p50/p99 latency and throughput vs offered load", unit="ms",
+               value=runs[2]["p99_ms"], higher_is_better=False, n_gpus=1, dtype="u64", data="synthetic",
+               config=dict(workload="Poisson stream of %d encrypted 2-layer x^2 GCN requests, power-law graphs "
+                           "500-4000 nodes, F 64-160, hidden 16, 2-10 classes, CKKS N=2^16 8+2 primes" % len(reqs),
+                           slots=4, budget_bytes=budget, planner="learned"),
+               runs=runs, max_rel_err=err,
+               requests=[dict(name=q.name, latency_ms=round(q.result["latency_ms"], 2),
+                              footprint_gb=round(q.result["footprint_bytes"] / 1e9, 2)) for q in reqs])
     print(json.dumps(out), flush=True)
 
 
