@@ -239,7 +239,12 @@ ficgcn_status ficgcn_plan_fill_operands(ckks_ctx* ctx, ficgcn_plan* plan, uint64
  * Inputs: Inter-CA first layer: K*F client ciphertexts, copy k of column f at
  * index k*F + f; later / SpIntra-CA layers: the previous layer's outputs.
  * mode 0 = one library operation at a time ("plain"), mode 1 = fused,
- * batched launches ("batched"); both produce the same words. */
+ * batched launches ("batched"), mode 2 = the batched launch sequence
+ * captured in a HIP graph: the first call for a given set of input and
+ * output buffers and keys runs mode 1 while recording its device tables,
+ * then captures; later calls with the same buffers replay the graph (the
+ * plan keeps one graph per layer; new buffers recapture).  All three
+ * produce the same words. */
 ficgcn_status ficgcn_gcn_layer(ckks_ctx* ctx, const ckks_keys* eval_keys, const ficgcn_plan* plan, uint32_t layer,
                                const uint64_t* const* in_cts, size_t n_in, uint64_t* const* out_cts, size_t n_out,
                                int32_t mode);

@@ -219,6 +219,49 @@ uint64_t galois_elt(ckks_ctx* c, int64_t step) {
 
 }  // namespace ficgcn
 
+namespace ficgcn {
+
+Recorder::~Recorder() {
+  for (auto& b : bufs)
+    if (b.first) (void)hipFree(b.first);
+}
+
+static void* recorded(ckks_ctx* c, size_t bytes, const void* host) {
+  Recorder* r = c->rec;
+  if (r->mode == Recorder::RECORD) {
+    void* d = nullptr;
+    HIPCHECK(hipMalloc(&d, std::max<size_t>(16, bytes)));
+    r->bufs.push_back({d, bytes});
+    if (host && bytes) {
+      HIPCHECK(hipStreamSynchronize(c->stream));
+      HIPCHECK(hipMemcpy(d, host, bytes, hipMemcpyHostToDevice));
+    }
+    return d;
+  }
+  if (r->cursor >= r->bufs.size() || r->bufs[r->cursor].second != bytes)
+    FICGCN_THROW(EPLAN_, "replayed launch sequence differs from the recorded one");
+  return r->bufs[r->cursor++].first;
+}
+
+void* dev_scratch(ckks_ctx* c, int slot, size_t bytes) {
+  if (c->rec) return recorded(c, bytes, nullptr);
+  return c->buf(slot, bytes);
+}
+
+void* dev_table(ckks_ctx* c, int slot, const void* host, size_t bytes) {
+  if (c->rec) return recorded(c, bytes, host);
+  void* d = c->buf(slot, std::max<size_t>(16, bytes));
+  if (bytes) HIPCHECK(hipMemcpyAsync(d, host, bytes, hipMemcpyHostToDevice, c->stream));
+  return d;
+}
+
+void stream_sync(ckks_ctx* c) {
+  if (c->rec && c->rec->mode == Recorder::REPLAY) return;
+  HIPCHECK(hipStreamSynchronize(c->stream));
+}
+
+}  // namespace ficgcn
+
 void* ckks_ctx::buf(int slot, size_t bytes) {
   if ((int)scratch.size() <= slot) scratch.resize(slot + 1, {nullptr, 0});
   auto& s = scratch[slot];

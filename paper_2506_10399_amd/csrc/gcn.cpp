@@ -154,9 +154,8 @@ static bool strided(const uint64_t* const* p, size_t n, size_t min_words, const 
 
 template <typename T>
 static T* upload_ptrs(ckks_ctx* c, const std::vector<T>& v, int slot) {
-  T* d = (T*)c->buf(slot, std::max<size_t>(8, v.size() * sizeof(T)));
-  HIPCHECK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
-  HIPCHECK(hipStreamSynchronize(c->stream));
+  T* d = (T*)dev_table(c, slot, v.data(), v.size() * sizeof(T));
+  stream_sync(c);
   return d;
 }
 
@@ -294,7 +293,7 @@ static void aggregate_batched(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, c
     std::map<int64_t, int> bpos;
     for (int64_t b : babies) bpos.emplace(b, (int)bpos.size());
     // baby rotations of every packed ciphertext, hoisted on its ModUp
-    uint64_t* bb = (uint64_t*)c->buf(70, std::max<size_t>(1, (size_t)np * nb) * ct_words * 8);
+    uint64_t* bb = (uint64_t*)dev_scratch(c, 70, std::max<size_t>(1, (size_t)np * nb) * ct_words * 8);
     auto baby = [&](int g, int64_t b) { return bb + ((size_t)g * nb + bpos.at(b)) * ct_words; };
     {
       std::vector<KSJob> jobs;
@@ -315,7 +314,7 @@ static void aggregate_batched(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, c
     // inner sums: giant 0 straight into the output, the others into buffers
     int n_inner = 0;
     for (auto& kv : giants) n_inner += kv.first != 0;
-    uint64_t* ib = (uint64_t*)c->buf(71, std::max<size_t>(1, (size_t)np * n_inner) * ct_words * 8);
+    uint64_t* ib = (uint64_t*)dev_scratch(c, 71, std::max<size_t>(1, (size_t)np * n_inner) * ct_words * 8);
     std::vector<std::vector<MacTerm>> groups;
     std::vector<uint64_t*> gouts;
     std::vector<const uint64_t*> isrc;
@@ -363,7 +362,7 @@ static void activation_batched(ckks_ctx* c, const ckks_keys* ek, int lo, const s
                                uint64_t* const* out) {
   const size_t N = c->N, l1 = lo + 1;
   const size_t n = pre.size();
-  uint64_t* d = (uint64_t*)c->buf(48, n * 3 * l1 * N * 8);
+  uint64_t* d = (uint64_t*)dev_scratch(c, 48, n * 3 * l1 * N * 8);
   std::vector<TensorJob> tj(n);
   std::vector<const uint64_t*> srcs(n);
   std::vector<KSJob> jobs(n);
@@ -378,8 +377,89 @@ static void activation_batched(ckks_ctx* c, const ckks_keys* ek, int lo, const s
   keyswitch_batch(c, lo, srcs, jobs, outs, false);
 }
 
+static void run_layer_eager(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const uint64_t* const* in,
+                            size_t n_in, uint64_t* const* out, size_t n_out, int mode);
+
+// Graph form: the first call for a set of buffers runs the batched form
+// eagerly while recording its device tables and scratch, then captures the
+// same launch sequence (recorded buffers, no uploads, no host waits) into a
+// HIP graph; later calls with the same buffers and keys replay the graph.
+static void run_layer_graph(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const uint64_t* const* in,
+                            size_t n_in, uint64_t* const* out, size_t n_out) {
+  if (p->graphs.size() < p->layers.size()) p->graphs.resize(p->layers.size());
+  auto& g = p->graphs[li];
+  const std::vector<const uint64_t*> vin(in, in + n_in);
+  const std::vector<uint64_t*> vout(out, out + n_out);
+  if (g && !g->failed && g->exec && g->in == vin && g->out == vout && g->keys == ek && g->ctx == c) {
+    HIPCHECK(hipGraphLaunch(g->exec, c->stream));
+    return;
+  }
+  if (g && g->failed && g->in == vin && g->out == vout && g->keys == ek && g->ctx == c) {
+    run_layer_eager(c, ek, p, li, in, n_in, out, n_out, 1);
+    return;
+  }
+  HIPCHECK(hipStreamSynchronize(c->stream));
+  g.reset(new LayerGraph());
+  g->in = vin;
+  g->out = vout;
+  g->keys = ek;
+  g->ctx = c;
+  // 1. eager run, recording every table and scratch buffer in call order
+  g->rec.mode = Recorder::RECORD;
+  c->rec = &g->rec;
+  try {
+    run_layer_eager(c, ek, p, li, in, n_in, out, n_out, 1);
+  } catch (...) {
+    c->rec = nullptr;
+    g.reset();
+    throw;
+  }
+  c->rec = nullptr;
+  HIPCHECK(hipStreamSynchronize(c->stream));
+  // 2. capture the same sequence on a stream of its own (the context's may be the null stream)
+  hipStream_t cap = nullptr, saved = c->stream;
+  HIPCHECK(hipStreamCreate(&cap));
+  g->rec.mode = Recorder::REPLAY;
+  g->rec.cursor = 0;
+  c->rec = &g->rec;
+  c->stream = cap;
+  bool ok = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    try {
+      run_layer_eager(c, ek, p, li, in, n_in, out, n_out, 1);
+    } catch (...) {
+      ok = false;
+    }
+    hipGraph_t graph = nullptr;
+    ok = (hipStreamEndCapture(cap, &graph) == hipSuccess) && ok && graph;
+    if (ok) {
+      g->graph = graph;
+      ok = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) == hipSuccess;
+    } else if (graph) {
+      (void)hipGraphDestroy(graph);
+    }
+    ok = ok && g->rec.cursor == g->rec.bufs.size();
+  }
+  c->stream = saved;
+  c->rec = nullptr;
+  (void)hipGetLastError();
+  (void)hipStreamDestroy(cap);
+  if (!ok) g->failed = true;
+}
+
 void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const uint64_t* const* in, size_t n_in,
                uint64_t* const* out, size_t n_out, int mode) {
+  if (mode == 2) {
+    LayerPlan& lp = p->layers[li];
+    if ((int)n_in != lp.n_in_cts() || (int)n_out != lp.n_packed()) FICGCN_THROW(EPLAN_, "wrong ciphertext count");
+    run_layer_graph(c, ek, p, li, in, n_in, out, n_out);
+    return;
+  }
+  run_layer_eager(c, ek, p, li, in, n_in, out, n_out, mode);
+}
+
+static void run_layer_eager(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const uint64_t* const* in,
+                            size_t n_in, uint64_t* const* out, size_t n_out, int mode) {
   LayerPlan& lp = p->layers[li];
   const size_t N = c->N;
   if ((int)n_in != lp.n_in_cts()) FICGCN_THROW(EPLAN_, "wrong number of input ciphertexts");
@@ -398,7 +478,7 @@ void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const u
   std::vector<uint64_t*> pre(n_out);
   uint64_t* pre_block = nullptr;
   if (lp.act) {
-    pre_block = (uint64_t*)c->buf(47, n_out * ct_words * 8);
+    pre_block = (uint64_t*)dev_scratch(c, 47, n_out * ct_words * 8);
     for (size_t i = 0; i < n_out; ++i) pre[i] = pre_block + i * ct_words;
   } else {
     for (size_t i = 0; i < n_out; ++i) pre[i] = out[i];
@@ -458,7 +538,7 @@ void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const u
   } else {
     // combination at one column per ciphertext
     const int F = lp.f_in;
-    uint64_t* cols = (uint64_t*)c->buf(35, (size_t)lp.f_out * ct_words * 8);
+    uint64_t* cols = (uint64_t*)dev_scratch(c, 35, (size_t)lp.f_out * ct_words * 8);
     std::vector<uint64_t*> colp(lp.f_out);
     for (int l = 0; l < lp.f_out; ++l) colp[l] = cols + (size_t)l * ct_words;
     if (mode == 1) {
@@ -495,7 +575,7 @@ void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const u
     const int np = lp.n_packed();
     if (mode == 1) {
       // pack t columns per ciphertext: Y_g = col_{gt} + sum_l Rot_{-(l mod t) B}(col_l)
-      uint64_t* yb = (uint64_t*)c->buf(36, (size_t)np * agg_words * 8);
+      uint64_t* yb = (uint64_t*)dev_scratch(c, 36, (size_t)np * agg_words * 8);
       std::vector<uint64_t*> Y(np);
       std::vector<std::vector<MacTerm>> init(np);
       std::vector<const uint64_t*> srcs;
@@ -538,7 +618,7 @@ void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const u
       // out = pre^2 with relinearisation at the layer's output level
       const size_t l1o = lo + 1, ext = l1o + c->alpha;
       const int nd = (int)((l1o + c->alpha - 1) / c->alpha);
-      uint64_t* d = (uint64_t*)c->buf(48, 3 * l1o * N * 8);
+      uint64_t* d = (uint64_t*)dev_scratch(c, 48, 3 * l1o * N * 8);
       tensor(c, pre[i], pre[i], d, lo);
       uint64_t* D = (uint64_t*)c->buf(40, (size_t)nd * ext * N * 8);
       uint64_t* acc = (uint64_t*)c->buf(41, 2 * ext * N * 8);
@@ -776,7 +856,7 @@ ficgcn_status ficgcn_gcn_layer(ckks_ctx* ctx, const ckks_keys* eval_keys, const 
   GUARD_BEGIN
   if (!ctx || !eval_keys || !plan || !in_cts || !out_cts) FICGCN_THROW(EINVAL_, "null argument");
   if (layer >= plan->layers.size()) FICGCN_THROW(EINVAL_, "layer index out of range");
-  if (mode != 0 && mode != 1) FICGCN_THROW(EINVAL_, "mode must be 0 (plain) or 1 (batched)");
+  if (mode < 0 || mode > 2) FICGCN_THROW(EINVAL_, "mode must be 0 (plain), 1 (batched) or 2 (batched, graph)");
   ensure_device(ctx);
   run_layer(ctx, eval_keys, const_cast<ficgcn_plan*>(plan), (int)layer, in_cts, n_in, out_cts, n_out, mode);
   GUARD_END

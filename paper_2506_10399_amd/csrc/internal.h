@@ -62,8 +62,23 @@ struct BConv {
 
 }  // namespace ficgcn
 
+namespace ficgcn {
+// Device buffers of one recorded launch sequence (a layer captured in a HIP
+// graph).  RECORD: every table upload and scratch request gets a buffer of
+// its own, kept in call order; REPLAY: the same calls get the same buffers
+// back in the same order, with no upload and no host synchronisation, so
+// the sequence can be captured.
+struct Recorder {
+  enum Mode { RECORD, REPLAY } mode = RECORD;
+  std::vector<std::pair<void*, size_t>> bufs;
+  size_t cursor = 0;
+  ~Recorder();
+};
+}  // namespace ficgcn
+
 struct ckks_ctx {
   int log_n = 0, N = 0, L = 0, alpha = 0, log_scale = 40, q_bits = 0, p_bits = 0;
+  ficgcn::Recorder* rec = nullptr;   // set while a layer is recorded or captured
   std::vector<uint64_t> mod;         // Q primes (descending) then P primes
   std::vector<uint64_t> psi;         // primitive 2N-th root per modulus
   ficgcn::Tables t;                  // device copies, uploaded on first device use
@@ -104,16 +119,23 @@ struct ProfScope {
   const char* name;
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(ckks_ctx* cc, const char* n) : c(cc), name(n) {
-    if (!c->profiling) return;
+    if (!c->profiling || c->rec) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
     (void)hipEventRecord(a, c->stream);
   }
   ~ProfScope() {
-    if (!c->profiling || !a || !b) return;
+    if (!c->profiling || c->rec || !a || !b) return;
     (void)hipEventRecord(b, c->stream);
     c->prof[name].push_back({a, b});
   }
 };
+
+// Scratch of `bytes` (context slot, or the recorder's buffer), a device copy
+// of a host table (slot + asynchronous copy, or the recorder's buffer), and
+// a stream synchronisation that a replay being captured skips.
+void* dev_scratch(ckks_ctx* c, int slot, size_t bytes);
+void* dev_table(ckks_ctx* c, int slot, const void* host, size_t bytes);
+void stream_sync(ckks_ctx* c);
 
 uint64_t powmod(uint64_t a, uint64_t e, uint64_t q);
 uint64_t invmod(uint64_t a, uint64_t q);

@@ -199,9 +199,7 @@ enum { S_KB_TMP = 50, S_KB_D, S_KB_ACC, S_KB_CONV, S_KB_JOBS, S_KB_SRC, S_KB_GRP
 
 template <typename T>
 static T* upload(ckks_ctx* c, int slot, const std::vector<T>& v) {
-  T* d = (T*)c->buf(slot, std::max<size_t>(16, v.size() * sizeof(T)));
-  if (!v.empty()) HIPCHECK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
-  return d;
+  return (T*)dev_table(c, slot, v.data(), v.size() * sizeof(T));
 }
 
 // scratch bound of one chunk of a key-switch batch
@@ -270,10 +268,10 @@ void keyswitch_batch(ckks_ctx* c, int level, const std::vector<const uint64_t*>&
     KSJob* jd = upload(c, S_KB_JOBS, cj);
     const uint64_t* const* sd = upload(c, S_KB_SRC, srcs);
     GroupDesc* gd = upload(c, S_KB_GRP, gds);
-    uint64_t* tmp = (uint64_t*)c->buf(S_KB_TMP, (size_t)U * l1 * N * 8);
-    uint64_t* D = (uint64_t*)c->buf(S_KB_D, (size_t)U * nd * ext * N * 8);
-    uint64_t* acc = (uint64_t*)c->buf(S_KB_ACC, (size_t)R * 2 * ext * N * 8);
-    uint64_t* conv = (uint64_t*)c->buf(S_KB_CONV, (size_t)R * 2 * l1 * N * 8);
+    uint64_t* tmp = (uint64_t*)dev_scratch(c, S_KB_TMP, (size_t)U * l1 * N * 8);
+    uint64_t* D = (uint64_t*)dev_scratch(c, S_KB_D, (size_t)U * nd * ext * N * 8);
+    uint64_t* acc = (uint64_t*)dev_scratch(c, S_KB_ACC, (size_t)R * 2 * ext * N * 8);
+    uint64_t* conv = (uint64_t*)dev_scratch(c, S_KB_CONV, (size_t)R * 2 * l1 * N * 8);
     {
       ProfScope pm(c, "modup");
       hipLaunchKernelGGL(k_gather, dim3(N / KB, l1, U), dim3(KB), 0, c->stream, tmp, sd, l1, c->log_n);
@@ -303,7 +301,7 @@ void keyswitch_batch(ckks_ctx* c, int level, const std::vector<const uint64_t*>&
       HIPCHECK(hipGetLastError());
     }
     // the host lists of this chunk are released below and the device lists reused
-    HIPCHECK(hipStreamSynchronize(c->stream));
+    stream_sync(c);
     a = b;
   }
   if (!accumulate)
@@ -333,7 +331,7 @@ void tensor_batch(ckks_ctx* c, int level, const std::vector<TensorJob>& jobs) {
   hipLaunchKernelGGL(k_tensor_batch, dim3(c->N / KB, level + 1, jobs.size()), dim3(KB), 0, c->stream, jd, level + 1,
                      c->log_n, c->t.mods);
   HIPCHECK(hipGetLastError());
-  HIPCHECK(hipStreamSynchronize(c->stream));
+  stream_sync(c);
 }
 
 struct RSK {
@@ -385,8 +383,8 @@ void rescale_batch(ckks_ctx* c, int level, const std::vector<uint64_t*>& cts) {
   const size_t N = c->N;
   const int n = (int)cts.size();
   uint64_t* const* cd = upload(c, S_RS_PTR, cts);
-  uint64_t* last = (uint64_t*)c->buf(S_RS_LAST, (size_t)2 * n * N * 8);
-  uint64_t* d = (uint64_t*)c->buf(S_RS_D, (size_t)2 * n * level * N * 8);
+  uint64_t* last = (uint64_t*)dev_scratch(c, S_RS_LAST, (size_t)2 * n * N * 8);
+  uint64_t* d = (uint64_t*)dev_scratch(c, S_RS_D, (size_t)2 * n * level * N * 8);
   hipLaunchKernelGGL(k_rs_gather, dim3(N / KB, 2 * n), dim3(KB), 0, c->stream, last, cd, level, c->log_n);
   HIPCHECK(hipGetLastError());
   ntt_inv(c, last, 1, LimbMap{level, 1 << 30, 0}, 2 * n, N);
@@ -404,7 +402,7 @@ void rescale_batch(ckks_ctx* c, int level, const std::vector<uint64_t*>& cts) {
   ntt_fwd(c, d, level, lm_q(level), 2 * n, (size_t)level * N);
   hipLaunchKernelGGL(k_rs_final, dim3(N / KB, 2 * n), dim3(KB), 0, c->stream, cd, d, level, k, c->log_n, c->t.mods);
   HIPCHECK(hipGetLastError());
-  HIPCHECK(hipStreamSynchronize(c->stream));
+  stream_sync(c);
 }
 
 // outs[g] (+)= sum over the terms of group g of ct (.) pt, or ct when pt is null
@@ -459,7 +457,7 @@ void group_mac(ckks_ctx* c, int level, const std::vector<std::vector<MacTerm>>& 
   hipLaunchKernelGGL(k_group_mac, dim3(c->N / KB, level + 1, 2 * groups.size()), dim3(KB), 0, c->stream, td, sd, od,
                      level + 1, accumulate ? 1 : 0, c->log_n, c->t.mods);
   HIPCHECK(hipGetLastError());
-  HIPCHECK(hipStreamSynchronize(c->stream));
+  stream_sync(c);
 }
 
 }  // namespace ficgcn

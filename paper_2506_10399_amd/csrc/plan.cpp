@@ -345,7 +345,13 @@ ficgcn_plan::~ficgcn_plan() {
 
 namespace ficgcn {
 
+LayerGraph::~LayerGraph() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+}
+
 void release_plan_device(ficgcn_plan* p) {
+  p->graphs.clear();
   for (auto& lp : p->layers) {
     for (void** q : {(void**)&lp.ops_block, (void**)&lp.w_dev, &lp.wf_dev, (void**)&lp.wm_dev, (void**)&lp.pw_dev})
       if (*q) {

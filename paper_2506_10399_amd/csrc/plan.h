@@ -45,8 +45,25 @@ struct LayerPlan {
 
 }  // namespace ficgcn
 
+namespace ficgcn {
+// One layer's batched launch sequence captured in a HIP graph, for fixed
+// input and output buffers.
+struct LayerGraph {
+  std::vector<const uint64_t*> in;
+  std::vector<uint64_t*> out;
+  const ckks_keys* keys = nullptr;
+  ckks_ctx* ctx = nullptr;
+  Recorder rec;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool failed = false;   // capture not possible: the layer runs eagerly
+  ~LayerGraph();
+};
+}  // namespace ficgcn
+
 struct ficgcn_plan {
   ckks_ctx* ctx = nullptr;
+  std::vector<std::unique_ptr<ficgcn::LayerGraph>> graphs;   // per layer, built on first graph-mode call
   int n_v = 0, M = 0, B_pi = 0;
   std::vector<int32_t> pi;
   std::vector<int32_t> rowptr, col;

@@ -147,6 +147,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise FicgcnError(-6, "HIP library %s is not built (run __graft_entry__.build())" % LIB_PATH)
+        # PyTorch's HIP runtime is loaded first, so the library binds to the
+        # same runtime as the tensors it is handed (one runtime per process)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)

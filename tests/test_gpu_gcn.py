@@ -101,6 +101,35 @@ def test_layers_bit_exact_both_forms(name, mode, family):
     assert gcn.max_rel_error(y, e["ref"][-1]) < 1e-3
 
 
+@pytest.mark.parametrize("name,mode,family", CASES)
+def test_graph_replays_equal_batched(name, mode, family):
+    """Mode 2 (HIP graph) on fixed buffers: the capturing call and three
+    replays, with eager work and synchronisations between them, each give
+    the batched form's words."""
+    import torch
+    e = _setup(name, mode, family)
+    _load_operands(e)
+    want = [[e["ctx"].ckks_poly_store(x, lvo, 2) for x in outs] for outs, lvo in _run_gpu(e, 1)]
+    ctx, p, info = e["ctx"], e["p"], e["p"].ficgcn_plan_info()
+    lv0 = e["prm"].L - 1
+    ins = [ctx.ckks_ct_load(_ct(c), lv0) for c in e["cts"]]
+    outs = [[ctx.ct_buffer(d["level_in"]) for _ in range(d["n_out_cts"])] for d in info]
+    for rep in range(4):
+        cur = ins
+        for li in range(len(info)):
+            p.ficgcn_gcn_layer(e["ev"], li, cur, outs[li], mode=2)
+            cur = outs[li]
+        got = [[ctx.ckks_poly_store(x, d["level_out"], 2) for x in o] for o, d in zip(outs, info)]
+        for li, (g, w) in enumerate(zip(got, want)):
+            for k, (a, b) in enumerate(zip(g, w)):
+                assert np.array_equal(a, b), (name, mode, family, "replay", rep, "layer", li, "ct", k)
+        for o in outs:            # eager work between replays
+            for x in o:
+                x.zero_()
+        _run_gpu(e, 1)
+        torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("name,mode", [("tiny", "inter"), ("tiny2", "inter")])
 def test_library_encoder_end_to_end(name, mode):
     """Operands encoded by the library, inputs encrypted by the library."""
