@@ -43,28 +43,74 @@ __device__ __forceinline__ void bf_inv(uint64_t& x, uint64_t& y, uint64_t w, uin
   y = mul_shoup(d, w, ws, q);
 }
 
-// ROW: row pass (sub-transform = contiguous chunk), else column pass.
-template <int LOGC, int COLS, bool INV, bool ROW>
-__global__ __launch_bounds__((1 << (LOGC / 2)) * COLS) void k_ntt_pass(
-    uint64_t* __restrict__ base, int log_n, LimbMap map, size_t poly_stride, const uint64_t* __restrict__ tw,
-    const uint64_t* __restrict__ tws, const Mod* __restrict__ mods, const uint64_t* __restrict__ ninv,
-    const uint64_t* __restrict__ ninv_s, int skip_alpha, int skip_q) {
+// Residue arithmetic in fp64 for 2^49 < q < 2^50 (every Q prime of the chain).
+// a, b < q are exact doubles; a*b = hi + lo exactly (fma error term); the
+// quotient estimate rint(hi * fl(1/q)) is within 1 of a*b/q (its error is
+// below hi/q * 2^-52 + 1/2 + |lo|/q < 1/4 + 1/2 + 1/4), so
+// r = (hi - qt*q) + lo, computed exactly by one fma and one add of integers
+// below 2^52, lies in (-q, q) and one correction makes it the residue.  The
+// fp64 FMA runs at full rate, where a 64-bit integer Shoup multiply takes
+// about ten quarter-rate 32-bit multiplies; the results are the same words.
+// Values travel as the bit patterns of the doubles in the uint64 registers
+// and LDS words of the pass.
+__device__ __forceinline__ uint64_t f2b(double d) { return (uint64_t)__double_as_longlong(d); }
+__device__ __forceinline__ double b2f(uint64_t b) { return __longlong_as_double((long long)b); }
+__device__ __forceinline__ uint64_t to_fbits(uint64_t v) { return f2b((double)v); }
+__device__ __forceinline__ uint64_t from_fbits(uint64_t b) { return (uint64_t)b2f(b); }
+
+__device__ __forceinline__ double fmulmod(double a, double b, double q, double qinv) {
+  const double hi = a * b;
+  const double lo = fma(a, b, -hi);
+  const double qt = rint(hi * qinv);
+  double r = fma(-qt, q, hi) + lo;
+  r = r < 0.0 ? r + q : r;
+  return r >= q ? r - q : r;
+}
+
+template <bool FP>
+__device__ __forceinline__ void bfly_fwd(uint64_t& x, uint64_t& y, uint64_t w, uint64_t ws, uint64_t q, double qd,
+                                         double qinv) {
+  if (FP) {
+    const double xd = b2f(x), v = fmulmod(b2f(y), b2f(w), qd, qinv);
+    double yn = xd - v, xn = xd + v;
+    yn = yn < 0.0 ? yn + qd : yn;
+    xn = xn >= qd ? xn - qd : xn;
+    x = f2b(xn);
+    y = f2b(yn);
+  } else {
+    bf_fwd(x, y, w, ws, q);
+  }
+}
+
+template <bool FP>
+__device__ __forceinline__ void bfly_inv(uint64_t& x, uint64_t& y, uint64_t w, uint64_t ws, uint64_t q, double qd,
+                                         double qinv) {
+  if (FP) {
+    const double xd = b2f(x), yd = b2f(y);
+    double d = xd - yd, xn = xd + yd;
+    d = d < 0.0 ? d + qd : d;
+    xn = xn >= qd ? xn - qd : xn;
+    x = f2b(xn);
+    y = f2b(fmulmod(d, b2f(w), qd, qinv));
+  } else {
+    bf_inv(x, y, w, ws, q);
+  }
+}
+
+// One pass over one sub-transform set of a limb; FP selects the fp64 residue arithmetic.
+template <int LOGC, int COLS, bool INV, bool ROW, bool FP>
+__device__ __forceinline__ void ntt_pass_body(uint64_t* s, uint64_t* a, const uint64_t* __restrict__ W,
+                                              const uint64_t* __restrict__ Ws, uint64_t q, int N, int mi,
+                                              const uint64_t* __restrict__ ninv,
+                                              const uint64_t* __restrict__ ninv_s) {
   constexpr int C = 1 << LOGC;
   constexpr int LT = LOGC / 2;
   constexpr int TPC = 1 << LT;
   constexpr int LE = LOGC - LT;
   constexpr int EPT = 1 << LE;
-  // one pad word per EPT elements (row pass) or one group width per EPT rows
-  // (column pass) keeps the contiguous-layout accesses off a single bank set
-  __shared__ uint64_t s[COLS * (C + TPC)];
-  const int limb = blockIdx.y, poly = blockIdx.z;
-  if (skip_limb(limb, poly, skip_alpha, skip_q)) return;
-  const int N = 1 << log_n;
-  const int mi = lm_mod(map, limb);
-  const uint64_t q = mods[mi].q;
-  uint64_t* a = base + poly * poly_stride + (size_t)limb * N;
-  const uint64_t* W = tw + (size_t)mi * N;
-  const uint64_t* Ws = tws + (size_t)mi * N;
+  const double qd = (double)q, qinv = 1.0 / qd;
+  auto twv = [&](int k) { return FP ? to_fbits(W[k]) : W[k]; };
+  auto tws = [&](int k) { return FP ? (uint64_t)0 : Ws[k]; };
   const int tid = threadIdx.x;
   // column pass: consecutive threads = consecutive columns (coalesced rows);
   // row pass: consecutive threads = consecutive elements of one chunk
@@ -82,7 +128,7 @@ __global__ __launch_bounds__((1 << (LOGC / 2)) * COLS) void k_ntt_pass(
   if (!INV) {
     // ---- load strided: x[u] = element r + TPC u
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) x[u] = g[(size_t)(r + TPC * u) * stride];
+    for (int u = 0; u < EPT; ++u) x[u] = FP ? to_fbits(g[(size_t)(r + TPC * u) * stride]) : g[(size_t)(r + TPC * u) * stride];
     // ---- stages 0..LE-1 (t >= TPC) in registers
     {
       uint64_t w[EPT], ws[EPT];
@@ -91,8 +137,8 @@ __global__ __launch_bounds__((1 << (LOGC / 2)) * COLS) void k_ntt_pass(
 #pragma unroll
         for (int i = 0; i < (1 << st); ++i) {
           int k = twi(st, i);
-          w[(1 << st) + i - 1] = W[k];
-          ws[(1 << st) + i - 1] = Ws[k];
+          w[(1 << st) + i - 1] = twv(k);
+          ws[(1 << st) + i - 1] = tws(k);
         }
 #pragma unroll
       for (int st = 0; st < LE; ++st) {
@@ -101,7 +147,7 @@ __global__ __launch_bounds__((1 << (LOGC / 2)) * COLS) void k_ntt_pass(
         for (int u = 0; u < EPT; ++u)
           if ((u & tu) == 0) {
             const int i = u / (2 * tu);
-            bf_fwd(x[u], x[u + tu], w[(1 << st) + i - 1], ws[(1 << st) + i - 1], q);
+            bfly_fwd<FP>(x[u], x[u + tu], w[(1 << st) + i - 1], ws[(1 << st) + i - 1], q, qd, qinv);
           }
       }
     }
@@ -123,8 +169,8 @@ __global__ __launch_bounds__((1 << (LOGC / 2)) * COLS) void k_ntt_pass(
         for (int gi = 0; gi < ng; ++gi) {
           int i = (r * EPT) / (2 * t) + gi;
           int k = twi(st, i);
-          w[pos] = W[k];
-          ws[pos] = Ws[k];
+          w[pos] = twv(k);
+          ws[pos] = tws(k);
           ++pos;
         }
       }
@@ -137,10 +183,14 @@ __global__ __launch_bounds__((1 << (LOGC / 2)) * COLS) void k_ntt_pass(
         for (int v = 0; v < EPT; ++v)
           if ((v & t) == 0) {
             const int gi = v / (2 * t);
-            bf_fwd(x[v], x[v + t], w[pos + gi], ws[pos + gi], q);
+            bfly_fwd<FP>(x[v], x[v + t], w[pos + gi], ws[pos + gi], q, qd, qinv);
           }
         pos += ng;
       }
+    }
+    if (FP) {
+#pragma unroll
+      for (int v = 0; v < EPT; ++v) x[v] = from_fbits(x[v]);
     }
     if (ROW) {
       // back to the strided layout for a coalesced store
@@ -167,6 +217,10 @@ __global__ __launch_bounds__((1 << (LOGC / 2)) * COLS) void k_ntt_pass(
 #pragma unroll
       for (int v = 0; v < EPT; ++v) x[v] = g[(size_t)(r * EPT + v) * stride];
     }
+    if (FP) {
+#pragma unroll
+      for (int v = 0; v < EPT; ++v) x[v] = to_fbits(x[v]);
+    }
     // ---- stages LOGC-1..LE (t < TPC) in registers
     {
       uint64_t w[EPT], ws[EPT];   // at most EPT - 1 twiddles in these stages
@@ -179,8 +233,8 @@ __global__ __launch_bounds__((1 << (LOGC / 2)) * COLS) void k_ntt_pass(
         for (int gi = 0; gi < ng; ++gi) {
           int i = (r * EPT) / (2 * t) + gi;
           int k = twi(st, i);
-          w[pos] = W[k];
-          ws[pos] = Ws[k];
+          w[pos] = twv(k);
+          ws[pos] = tws(k);
           ++pos;
         }
       }
@@ -193,7 +247,7 @@ __global__ __launch_bounds__((1 << (LOGC / 2)) * COLS) void k_ntt_pass(
         for (int v = 0; v < EPT; ++v)
           if ((v & t) == 0) {
             const int gi = v / (2 * t);
-            bf_inv(x[v], x[v + t], w[pos + gi], ws[pos + gi], q);
+            bfly_inv<FP>(x[v], x[v + t], w[pos + gi], ws[pos + gi], q, qd, qinv);
           }
         pos += ng;
       }
@@ -212,8 +266,8 @@ __global__ __launch_bounds__((1 << (LOGC / 2)) * COLS) void k_ntt_pass(
 #pragma unroll
         for (int i = 0; i < (1 << st); ++i) {
           int k = twi(st, i);
-          w[(1 << st) + i - 1] = W[k];
-          ws[(1 << st) + i - 1] = Ws[k];
+          w[(1 << st) + i - 1] = twv(k);
+          ws[(1 << st) + i - 1] = tws(k);
         }
 #pragma unroll
       for (int st = LE - 1; st >= 0; --st) {
@@ -222,18 +276,48 @@ __global__ __launch_bounds__((1 << (LOGC / 2)) * COLS) void k_ntt_pass(
         for (int u = 0; u < EPT; ++u)
           if ((u & tu) == 0) {
             const int i = u / (2 * tu);
-            bf_inv(x[u], x[u + tu], w[(1 << st) + i - 1], ws[(1 << st) + i - 1], q);
+            bfly_inv<FP>(x[u], x[u + tu], w[(1 << st) + i - 1], ws[(1 << st) + i - 1], q, qd, qinv);
           }
       }
     }
     if (!ROW) {
       const uint64_t ni = ninv[mi], nis = ninv_s[mi];
+      const double nid = (double)ni;
 #pragma unroll
-      for (int u = 0; u < EPT; ++u) x[u] = mul_shoup(x[u], ni, nis, q);
+      for (int u = 0; u < EPT; ++u) x[u] = FP ? f2b(fmulmod(b2f(x[u]), nid, qd, qinv)) : mul_shoup(x[u], ni, nis, q);
+    }
+    if (FP) {
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) x[u] = from_fbits(x[u]);
     }
 #pragma unroll
     for (int u = 0; u < EPT; ++u) g[(size_t)(r + TPC * u) * stride] = x[u];
   }
+}
+
+// ROW: row pass (sub-transform = contiguous chunk), else column pass.
+template <int LOGC, int COLS, bool INV, bool ROW>
+__global__ __launch_bounds__((1 << (LOGC / 2)) * COLS) void k_ntt_pass(
+    uint64_t* __restrict__ base, int log_n, LimbMap map, size_t poly_stride, const uint64_t* __restrict__ tw,
+    const uint64_t* __restrict__ tws, const Mod* __restrict__ mods, const uint64_t* __restrict__ ninv,
+    const uint64_t* __restrict__ ninv_s, int skip_alpha, int skip_q) {
+  constexpr int C = 1 << LOGC;
+  constexpr int TPC = 1 << (LOGC / 2);
+  // one pad word per EPT elements (row pass) or one group width per EPT rows
+  // (column pass) keeps the contiguous-layout accesses off a single bank set
+  __shared__ uint64_t s[COLS * (C + TPC)];
+  const int limb = blockIdx.y, poly = blockIdx.z;
+  if (skip_limb(limb, poly, skip_alpha, skip_q)) return;
+  const int N = 1 << log_n;
+  const int mi = lm_mod(map, limb);
+  const uint64_t q = mods[mi].q;
+  uint64_t* a = base + poly * poly_stride + (size_t)limb * N;
+  const uint64_t* W = tw + (size_t)mi * N;
+  const uint64_t* Ws = tws + (size_t)mi * N;
+  if (q > (1ull << 49) && q < (1ull << 50))
+    ntt_pass_body<LOGC, COLS, INV, ROW, true>(s, a, W, Ws, q, N, mi, ninv, ninv_s);
+  else
+    ntt_pass_body<LOGC, COLS, INV, ROW, false>(s, a, W, Ws, q, N, mi, ninv, ninv_s);
 }
 
 // ---- launch selection --------------------------------------------------------
