@@ -411,8 +411,10 @@ __global__ void k_group_mac(const MacTerm* __restrict__ terms, const int* __rest
                             const Mod* __restrict__ mods) {
   const size_t N = (size_t)1 << log_n;
   const size_t j = blockIdx.x * (size_t)KB + threadIdx.x;
-  const int i = blockIdx.y;
-  const int g = blockIdx.z >> 1, comp = blockIdx.z & 1;
+  // limb slowest: one limb of every group's terms is in flight at a time, so
+  // ciphertexts shared by many groups (baby steps) are re-read from cache
+  const int i = blockIdx.z;
+  const int g = blockIdx.y >> 1, comp = blockIdx.y & 1;
   const Mod m = mods[i];
   const size_t o = ((size_t)comp * l1 + i) * N + j;
   uint64_t* out = outs[g];
@@ -454,7 +456,8 @@ void group_mac(ckks_ctx* c, int level, const std::vector<std::vector<MacTerm>>& 
   MacTerm* td = upload(c, S_GM_TERMS, flat);
   int* sd = upload(c, S_GM_START, start);
   uint64_t* const* od = upload(c, S_GM_OUT, outs);
-  hipLaunchKernelGGL(k_group_mac, dim3(c->N / KB, level + 1, 2 * groups.size()), dim3(KB), 0, c->stream, td, sd, od,
+  if (2 * groups.size() > 65535) FICGCN_THROW(EINVAL_, "too many groups in one launch");
+  hipLaunchKernelGGL(k_group_mac, dim3(c->N / KB, 2 * groups.size(), level + 1), dim3(KB), 0, c->stream, td, sd, od,
                      level + 1, accumulate ? 1 : 0, c->log_n, c->t.mods);
   HIPCHECK(hipGetLastError());
   stream_sync(c);
