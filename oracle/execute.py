@@ -15,6 +15,9 @@ operations, starting from s = 2^log_scale at the top level L-1:
                               weights at sW = ((q_l * q_{l-1}) * Delta) / s;
                               s = s * sW; s = s / q_l; s = s / q_{l-1}; l -= 2
   then (SpIntra-CA)          masks at sM = q_l; s = s * sM; s = s / q_l; l -= 1
+  (radix-2 routing, D steps)  the masks of a step at level l are encoded at
+                              q_l and the step rescales by q_l, so every
+                              result term keeps the scale s exactly; l -= D
   x^2 activation at level l : s = s * s (the rescale is deferred to the next
                               combination, or never for the model output, so
                               that no rounding happens below scale Delta)
@@ -30,6 +33,7 @@ import numpy as np
 
 from . import ckks
 from . import encoding as enc
+from . import radix2
 from . import simulate as sim
 from .params import Params
 from .planner import Plan
@@ -71,9 +75,15 @@ def schedule(prm: Params, plan: Plan) -> List[dict]:
             st["level_agg"] = lv
             st["scale_agg"] = s
             st["sM"] = float(prm.q[lv])
-            s = s * st["sM"]
-            s = s / float(prm.q[lv])
-            lv -= 1
+            if lp.family == 3:
+                depth = lp.program.depth
+                if lv < depth:
+                    raise ValueError("not enough levels for the radix-2 aggregation")
+                lv -= depth
+            else:
+                s = s * st["sM"]
+                s = s / float(prm.q[lv])
+                lv -= 1
         st["level_pre_act"] = lv
         st["scale_pre_act"] = s
         pending = False
@@ -105,6 +115,18 @@ def mask_vectors(plan: Plan, li: int) -> List[Dict[int, np.ndarray]]:
     return out
 
 
+def radix2_mask_vectors(plan: Plan, li: int):
+    """Family 3: per packed ciphertext g, the program's masks in operand order
+    as (depth, slot vector)."""
+    lp = plan.layers[li]
+    out = []
+    for g in range(-(-lp.f_out // lp.t)):
+        n_cols = min(lp.t, lp.f_out - g * lp.t)
+        out.append([(dep, radix2.mask_vector(e, plan.M, lp.B, n_cols))
+                    for dep, e in radix2.operand_list(lp.program)])
+    return out
+
+
 def encode_operands(prm: Params, plan: Plan, weights, sched=None) -> List[dict]:
     """Plaintext operands of every layer (the FP64 encoding step)."""
     sched = sched or schedule(prm, plan)
@@ -114,6 +136,10 @@ def encode_operands(prm: Params, plan: Plan, weights, sched=None) -> List[dict]:
         if lp.kind == "inter":
             lv = st["level_in"]
             d["P"] = [enc.encode(prm, p, st["sP"], lv) for p in sim.inter_plaintexts(plan, lp)]
+        elif lp.family == 3:
+            lv = st["level_agg"]
+            d["masks"] = [[enc.encode(prm, v, float(prm.q[lv - dep]), lv - dep) for dep, v in per_g]
+                          for per_g in radix2_mask_vectors(plan, li)]
         else:
             lv = st["level_agg"]
             d["masks"] = [{dd: enc.encode(prm, v, st["sM"], lv) for dd, v in mk.items()}
@@ -175,8 +201,55 @@ def run_layer(prm: Params, plan: Plan, li: int, keys: ckks.Keys, cts: List[ckks.
     return outs
 
 
-def aggregate(prm: Params, plan: Plan, li: int, keys, y: ckks.Ciphertext, masks: dict, st: dict):
+def aggregate_radix2(prm: Params, lp, keys, y: ckks.Ciphertext, masks: list, st: dict) -> ckks.Ciphertext:
+    """The radix-2 program on one packed ciphertext (Sec. 3.3): every step's
+    rotations hoisted on its register, Keep/Move masks summed into the next
+    registers (rescaled once complete), Fin masks into the result term of
+    the step's level; the result terms rescaled, dropped to the output level
+    and summed."""
+    prog = lp.program
+    lv = y.level
+    q = lambda dep: float(prm.q[lv - dep])
+    it = iter(masks)
+    regs = {0: y}
+    pending = {}
+    rots = {}
+
+    def reg(r):
+        if r in pending:
+            regs[r] = ckks.rescale(prm, pending.pop(r))
+        return regs[r]
+
+    O = {0: ckks.pt_mul_acc(prm, _zero(prm, lv, y.scale * q(0)), [y], [next(it)])}
+    for op in prog.ops:
+        src = reg(op.src)
+        need = [m for m in prog.amounts_of(op) if m != 0 and (op.src, m) not in rots]
+        for m, c in zip(need, ckks.rotate_hoisted(prm, keys, src, need)):
+            rots[(op.src, m)] = c
+        rot = lambda m: src if m == 0 else rots[(op.src, m)]
+        for t in sorted(op.keep):
+            ms = sorted(op.keep[t])
+            pts = [next(it) for _ in ms]
+            acc = pending.get(t) or _zero(prm, src.level, src.scale * q(op.depth))
+            pending[t] = ckks.pt_mul_acc(prm, acc, [rot(m) for m in ms], pts)
+        fms = sorted(op.fin)
+        if fms:
+            pts = [next(it) for _ in fms]
+            acc = O.get(op.depth) or _zero(prm, src.level, y.scale * q(op.depth))
+            O[op.depth] = ckks.pt_mul_acc(prm, acc, [rot(m) for m in fms], pts)
+    lo = lv - prog.depth
+    out = None
+    for dep in sorted(O):
+        term = ckks.drop_to(ckks.rescale(prm, O[dep]), lo)
+        out = term if out is None else ckks.add(prm, out, term)
+    out.scale = y.scale
+    return out
+
+
+def aggregate(prm: Params, plan: Plan, li: int, keys, y: ckks.Ciphertext, masks, st: dict):
     lp = plan.layers[li]
+    if lp.family == 3:
+        return aggregate_radix2(prm, lp, keys, y, masks, st)
     acc = _zero(prm, y.level, y.scale * st["sM"])
     if lp.family == 1:
         steps = [d for d in lp.shifts if d != 0]

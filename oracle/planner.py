@@ -9,7 +9,8 @@ What a plan fixes, following the paper:
   * SpIntra-CA routing (Sec. 3.3): every nonzero A_vu is a demand moving u's
     value by the shift delta = pi(u) - pi(v) onto v's slot; demands that share a
     shift share one rotation and one mask (the diagonal form), or one baby and
-    one giant rotation (the baby-step/giant-step form);
+    one giant rotation (the baby-step/giant-step form), or travel bit by bit
+    through per-round masks (the paper's radix-2 form, oracle.radix2);
   * node order pi (Sec. 3.4, Alg. 1): sibling-BFS regions capped at TH nodes,
     interleaved region by region, then a greedy conflict-least placement;
   * AOO (Sec. 3.3.1): with one column per ciphertext (t = 1) a shift is taken
@@ -39,6 +40,8 @@ from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
 import numpy as np
+
+from . import radix2
 
 
 # ----------------------------------------------------------------------------
@@ -259,8 +262,10 @@ class LayerPlan:
     t: int = 1                # columns per packed ciphertext
     B: int = 0                # block = M / t
     shifts: List[int] = field(default_factory=list)      # sorted distinct shifts
-    family: int = 1           # 1 = diagonal, 2 = baby-step/giant-step
+    family: int = 1           # 1 = diagonal, 2 = baby-step/giant-step, 3 = radix-2 per-round masks
     G: int = 1                # baby-step count of the family-2 split
+    program: object = None    # family 3: the radix-2 program (oracle.radix2.Program)
+    cpoo: Optional[float] = None   # family 3: CPOO sparsity threshold (None = off)
     # shifts per (ciphertext) of the pack step: -l*B for l = 1..t-1
     pack_steps: List[int] = field(default_factory=list)
 
@@ -316,6 +321,8 @@ def bsgs_split(shifts: Sequence[int], B: int):
 
 def rotation_steps_of(lp: LayerPlan) -> List[int]:
     """Rotation steps the aggregation uses (nonzero)."""
+    if lp.family == 3:
+        return lp.program.amounts()
     if lp.family == 1:
         return sorted(set(lp.shifts) - {0})
     babies = {d % lp.G for d in lp.shifts} - {0}
@@ -325,13 +332,15 @@ def rotation_steps_of(lp: LayerPlan) -> List[int]:
 
 def build_plan(n_v: int, rows, dims: Sequence[int], activation: bool, M: int,
                use_noo: bool = True, TH: Optional[int] = None, family: Optional[int] = None,
-               first_mode: str = "inter", t: Optional[int] = None) -> Plan:
+               first_mode: str = "inter", t: Optional[int] = None, cpoo: Optional[float] = None) -> Plan:
     """The executable plan: layer 1 by `first_mode` ("inter" per the paper's
     first-layer rule, or "spintra"), later layers SpIntra-CA; SpIntra layers
     combine first (F -> F' at one column per ciphertext), pack t = min(pow2(F'),
     M / pow2(n_v)) columns per ciphertext, then aggregate on the packed layout.
     A given t (a power of two no larger than pow2(F') of every SpIntra layer
-    and M / pow2(n_v)) replaces that rule for every SpIntra layer."""
+    and M / pow2(n_v)) replaces that rule for every SpIntra layer.
+    family: None = the cheaper of 1 and 2 by rotation count; 3 = the paper's
+    radix-2 routing (Sec. 3.3), with CPOO at threshold `cpoo` when given."""
     n_layers = len(dims) - 1
     if first_mode == "spintra" and n_layers > 1:
         raise ValueError("a SpIntra-CA layer leaves packed ciphertexts; only the last layer may be SpIntra-CA "
@@ -376,9 +385,11 @@ def build_plan(n_v: int, rows, dims: Sequence[int], activation: bool, M: int,
             G, c2 = bsgs_split(shifts, Bl)
             c1 = len(set(shifts) - {0})
             fam = family if family is not None else (2 if c2 < c1 else 1)
+            prog = radix2.build_program(pi, rows, M, Bl, wrap, cpoo) if fam == 3 else None
             pack = [-(l % t_l) * Bl for l in range(f_out) if l % t_l != 0]
             layers.append(LayerPlan("spintra", f_in, f_out, activation, t=t_l, B=Bl, shifts=shifts,
-                                    family=fam, G=G, pack_steps=sorted(set(pack))))
+                                    family=fam, G=G, pack_steps=sorted(set(pack)), program=prog,
+                                    cpoo=cpoo if fam == 3 else None))
     return Plan(n_v=n_v, M=M, B_pi=B, pi=pi, rows=rows, layers=layers, regions=regions)
 
 
@@ -402,6 +413,17 @@ def op_counts(plan: Plan) -> dict:
             n_packed = ceil_div(lp.f_out, lp.t)
             c["rot"] += lp.f_out - n_packed
             steps = rotation_steps_of(lp)
+            if lp.family == 3:
+                c["rot"] += n_packed * len(lp.program.rotations())
+                n_ops = len(radix2.operand_list(lp.program))
+                c["pmult"] += n_packed * n_ops
+                c["add"] += n_packed * n_ops
+                c["rescale"] += n_packed * lp.program.n_rescales()
+                n_cts = n_packed
+                if lp.activation:
+                    c["cmult"] += n_cts
+                    c["rescale"] += n_cts
+                continue
             if lp.family == 1:
                 c["rot"] += n_packed * len(steps)
             else:

@@ -12,6 +12,7 @@ from typing import List
 
 import numpy as np
 
+from . import radix2
 from .planner import LayerPlan, Plan, reduce_shift
 
 
@@ -73,6 +74,8 @@ def masks(plan: Plan, lp: LayerPlan, n_cols: int) -> dict:
 
 
 def aggregate_packed(plan: Plan, lp: LayerPlan, y: np.ndarray, n_cols: int, counts: dict) -> np.ndarray:
+    if lp.family == 3:
+        return radix2.run_slots(lp.program, y, lp.B, n_cols, counts)
     mk = masks(plan, lp, n_cols)
     out = np.zeros(plan.M)
     if lp.family == 1:

@@ -27,6 +27,19 @@ CONFIGS: Dict[str, dict] = {
     "tiny2": dict(id=6, log_n=13, n_q=8, q_bits=50, n_p=2, p_bits=60, log_scale=40,
                   graph=("chung_lu", 200, 3.9), norm="mean", n_sample=4,
                   features=("binary", 48, 0.05), dims=[48, 16, 7], activation=True),
+    # Deep chains for the radix-2 aggregation (one level per routing round):
+    # the shapes of "tiny" and "tiny2" with enough primes for every round.
+    "tiny_deep": dict(id=7, log_n=13, n_q=10, q_bits=50, n_p=2, p_bits=60, log_scale=40,
+                      graph=("er", 128, 4.0), norm="sym", n_sample=None,
+                      features=("uniform", 32), dims=[32, 16], activation=False),
+    "tiny2_deep": dict(id=8, log_n=13, n_q=14, q_bits=50, n_p=2, p_bits=60, log_scale=40,
+                       graph=("chung_lu", 200, 3.9), norm="mean", n_sample=4,
+                       features=("binary", 48, 0.05), dims=[48, 16, 7], activation=True),
+    # Citation-graph shape with the primes a radix-2 second layer needs
+    # (log QP = 18 * 50 + 2 * 60 = 1020 bits at N = 2^16).
+    "cora_deep": dict(id=9, log_n=16, n_q=18, q_bits=50, n_p=2, p_bits=60, log_scale=40,
+                      graph=("chung_lu", 2708, 3.9), norm="mean", n_sample=4,
+                      features=("binary", 1433, 0.013), dims=[1433, 16, 7], activation=True),
     # Citation-graph shape: 2708 nodes, 1433 binary features, 2-layer x^2 GCN.
     "cora": dict(id=2, log_n=16, n_q=8, q_bits=50, n_p=2, p_bits=60, log_scale=40,
                  graph=("chung_lu", 2708, 3.9), norm="mean", n_sample=4,
