@@ -180,11 +180,15 @@ ficgcn_status ckks_mul_relin(ckks_ctx* ctx, const ckks_keys* eval_keys, const ui
 typedef struct {
   int32_t first_mode;   /* 0: Inter-CA first layer (paper's rule), 1: SpIntra-CA (one-layer models only) */
   int32_t use_noo;      /* node order optimisation (Alg. 1) on/off */
-  int32_t family;       /* SpIntra-CA routing: 0 = cheaper of the two, 1 = diagonal, 2 = baby-step/giant-step */
+  int32_t family;       /* SpIntra-CA routing: 0 = cheaper of 1 and 2, 1 = diagonal, 2 = baby-step/giant-step,
+                           3 = the paper's radix-2 routing with per-round masks (Sec. 3.3): one level per
+                           round in which something moves, so the chain needs that many spare primes */
   int32_t TH;           /* region size cap; 0 = 1024 below 10000 nodes, else 4096 */
   int32_t activation;   /* x^2 after every layer */
   int32_t t;            /* SpIntra-CA packing: columns per ciphertext, a power of two no larger than
                            next_pow2(F') and M / next_pow2(n_v); 0 = the paper's rule (Sec. 3.2, App. B) */
+  double cpoo;          /* family 3: CPOO sparsity threshold in [0, 1] (Sec. 3.3.1; the paper's ablation,
+                           Sec. 4.2.2, finds 0.2-0.3 best); 0 = CPOO off */
 } ficgcn_plan_opts;
 
 /* Builds the plan of an n_layers-layer GCN over the normalised adjacency
@@ -218,13 +222,29 @@ ficgcn_status ficgcn_plan_shifts(const ficgcn_plan* plan, uint32_t layer, int64_
 ficgcn_status ficgcn_plan_weights_int(const ficgcn_plan* plan, uint32_t layer, int64_t* out);
 /* Number of plaintext operands of a layer and the slot vector of operand i
  * (M doubles): Inter-CA adjacency plaintext of copy i, or SpIntra-CA mask i
- * (packed ciphertext i / n_shifts, shift index i % n_shifts). */
+ * (families 1 and 2: packed ciphertext i / n_shifts, shift index
+ * i % n_shifts; family 3: see ficgcn_plan_radix2_stats). */
 ficgcn_status ficgcn_plan_operand_count(const ficgcn_plan* plan, uint32_t layer, size_t* n_out);
 ficgcn_status ficgcn_plan_operand_slots(const ficgcn_plan* plan, uint32_t layer, size_t i, double* slots_out);
+/* Level and encoding scale of operand i (the Inter-CA plaintexts sit at the
+ * layer's input level, the masks of families 1 and 2 at the aggregation
+ * level; a radix-2 mask sits at the level of the step that multiplies it and
+ * is encoded at that level's prime, which the step's rescale drops). */
+ficgcn_status ficgcn_plan_operand_level(const ficgcn_plan* plan, uint32_t layer, size_t i, uint32_t* level_out,
+                                        double* scale_out);
+/* Radix-2 aggregation program of a family-3 layer (Sec. 3.3 with CPOO of
+ * Sec. 3.3.1), 8 int64: {working ciphertexts created by the first-fit
+ * assignment, steps, distinct (ciphertext, amount) rotations, distinct
+ * rotation amounts, levels consumed, masks per packed ciphertext, demands
+ * moved by CPOO merging, intermediate ciphertexts}.  Operand i of the layer
+ * is mask i % (masks per packed ciphertext) of packed ciphertext
+ * i / (masks per packed ciphertext).  EPLAN for other layers. */
+ficgcn_status ficgcn_plan_radix2_stats(const ficgcn_plan* plan, uint32_t layer, int64_t* out);
 /* Encodes every operand with the library's encoder.  Synchronous. */
 ficgcn_status ficgcn_plan_encode(ckks_ctx* ctx, ficgcn_plan* plan);
 /* Installs operand i of a layer from coefficient-form residues [level+1][N]
- * at the operand's level (for operands encoded elsewhere). */
+ * at the operand's level (ficgcn_plan_operand_level), for operands encoded
+ * elsewhere. */
 ficgcn_status ficgcn_plan_load_operand(ckks_ctx* ctx, ficgcn_plan* plan, uint32_t layer, size_t i,
                                        const uint64_t* host_coeffs);
 

@@ -14,6 +14,7 @@
 // is defined as ModUp, automorphism, inner product, ModDown in both forms.
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <set>
 
 #include "../../include/ficgcn.h"
@@ -178,8 +179,88 @@ static void rotate_one(ckks_ctx* c, const ckks_keys* ek, const uint64_t* in, int
   moddown(c, acc, level, out, in, g, nullptr);
 }
 
+// Radix-2 program (family 3) of one packed ciphertext, one operation per
+// call: per step and rotation amount one key switch, then the masks of that
+// amount into the next registers and the result terms.  Registers are
+// accumulated at their step's level and rescaled when first read; result
+// terms (one per level) are rescaled, dropped to the output level and summed.
+static void aggregate_r2_plain(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, int g, const uint64_t* y,
+                               uint64_t* out) {
+  const size_t N = c->N;
+  const R2Program& pr = lp.r2;
+  const int la = lp.level_agg, D = pr.depth, lo = la - D;
+  const size_t nops = pr.ops.size();
+  auto mask = [&](size_t j) { return (const uint64_t*)lp.ops[(size_t)g * nops + j]; };
+  auto ctw = [&](int level) { return (size_t)2 * (level + 1) * N; };
+  const int nreg = (int)pr.reg_depth.size();
+  std::vector<size_t> roff(nreg, 0), ooff(D, 0);
+  size_t rtot = 0, otot = 0;
+  for (int r = 1; r < nreg; ++r) {
+    roff[r] = rtot;
+    rtot += ctw(la - pr.reg_depth[r] + 1);
+  }
+  for (int d = 0; d < D; ++d) {
+    ooff[d] = otot;
+    otot += ctw(la - d);
+  }
+  uint64_t* regs = (uint64_t*)c->buf(75, std::max<size_t>(1, rtot) * 8);
+  uint64_t* obuf = (uint64_t*)c->buf(76, otot * 8);
+  uint64_t* rt = (uint64_t*)c->buf(77, ctw(la) * 8);
+  if (rtot) zero_fill(c, regs, rtot);
+  zero_fill(c, obuf, otot);
+  std::vector<char> ready(nreg, 0);
+  ready[0] = 1;
+  auto reg = [&](int r) -> const uint64_t* {
+    if (r == 0) return y;
+    if (!ready[r]) {
+      rescale_inplace(c, regs + roff[r], la - pr.reg_depth[r] + 1);
+      ready[r] = 1;
+    }
+    return regs + roff[r];
+  };
+  auto mac = [&](uint64_t* acc, const uint64_t* ct, const uint64_t* pt, int l1) {
+    PtrList a{}, b{};
+    a.p[0] = ct;
+    b.p[0] = pt;
+    pmul_acc(c, acc, a, b, 1, l1);
+  };
+  mac(obuf + ooff[0], y, mask(0), la + 1);
+  size_t j0 = 1;
+  for (const R2Step& st : pr.steps) {
+    const int level = la - st.depth, l1 = level + 1;
+    const uint64_t* src = reg(st.src);
+    std::set<int64_t> ms;
+    for (const R2Term& t : st.keep) ms.insert(t.m);
+    for (const R2Term& t : st.fin) ms.insert(t.m);
+    const size_t nk = st.keep.size();
+    for (int64_t m : ms) {
+      const uint64_t* rm = src;
+      if (m != 0) {
+        rotate_one(c, ek, src, level, m, rt);
+        rm = rt;
+      }
+      for (size_t t = 0; t < nk; ++t)
+        if (st.keep[t].m == m) mac(regs + roff[st.keep[t].dst], rm, mask(j0 + t), l1);
+      for (size_t t = 0; t < st.fin.size(); ++t)
+        if (st.fin[t].m == m) mac(obuf + ooff[st.depth], rm, mask(j0 + nk + t), l1);
+    }
+    j0 += nk + st.fin.size();
+  }
+  zero_fill(c, out, ctw(lo));
+  for (int d = 0; d < D; ++d) {
+    uint64_t* o = obuf + ooff[d];
+    rescale_inplace(c, o, la - d);                   // now [2][la - d][N]
+    add_inplace(c, out, o, lo + 1, 1);
+    add_inplace(c, out + (size_t)(lo + 1) * N, o + (size_t)(la - d) * N, lo + 1, 1);
+  }
+}
+
 // SpIntra-CA of one packed ciphertext, one operation per call (plain form)
 static void aggregate(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, int g, const uint64_t* y, uint64_t* out) {
+  if (lp.family == 3) {
+    aggregate_r2_plain(c, ek, lp, g, y, out);
+    return;
+  }
   const size_t N = c->N;
   const int lv = lp.level_agg, l1 = lv + 1;
   const size_t ct_words = (size_t)2 * l1 * N;
@@ -252,6 +333,178 @@ static const uint64_t* rot_key(ckks_ctx* c, const ckks_keys* ek, int64_t step, u
   return it->second;
 }
 
+// Radix-2 program (family 3) of every packed ciphertext (batched form).
+// Steps are taken boundary by boundary (the rounds they start at) and, within
+// a boundary, level by level: one key-switch batch for the distinct
+// (register, amount) rotations of every packed ciphertext, one masked-sum
+// launch into the next registers, one into the result terms; the registers
+// written at a boundary are rescaled together.  The result terms are rescaled
+// and summed into the outputs at the output level.
+static void aggregate_r2_batched(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, const std::vector<uint64_t*>& Y,
+                                 const std::vector<uint64_t*>& outs) {
+  const size_t N = c->N;
+  const R2Program& pr = lp.r2;
+  const int la = lp.level_agg, D = pr.depth, lo = la - D;
+  const int np = (int)Y.size();
+  const size_t nops = pr.ops.size();
+  auto mask = [&](int g, size_t j) { return (const uint64_t*)lp.ops[(size_t)g * nops + j]; };
+  auto ctw = [&](int level) { return (size_t)2 * (level + 1) * N; };
+  const int nreg = (int)pr.reg_depth.size();
+  std::vector<size_t> roff(nreg, 0), ooff(D, 0);
+  size_t RB = 0, OB = 0;
+  for (int r = 1; r < nreg; ++r) {
+    roff[r] = RB;
+    RB += ctw(la - pr.reg_depth[r] + 1);
+  }
+  for (int d = 0; d < D; ++d) {
+    ooff[d] = OB;
+    OB += ctw(la - d);
+  }
+  // operand index of each step's first term
+  std::vector<size_t> first(pr.steps.size());
+  {
+    size_t j = 1;
+    for (size_t s = 0; s < pr.steps.size(); ++s) {
+      first[s] = j;
+      j += pr.steps[s].keep.size() + pr.steps[s].fin.size();
+    }
+  }
+  // (boundary, depth) groups in program order, and the largest rotation set
+  std::vector<std::pair<size_t, size_t>> runs;   // [begin, end) of equal r0
+  for (size_t s = 0; s < pr.steps.size();) {
+    size_t e = s;
+    while (e < pr.steps.size() && pr.steps[e].r0 == pr.steps[s].r0) ++e;
+    runs.push_back({s, e});
+    s = e;
+  }
+  size_t max_rot = 1;
+  for (auto& rn : runs) {
+    std::map<int, std::set<std::pair<int, int64_t>>> per_depth;
+    for (size_t s = rn.first; s < rn.second; ++s) {
+      const R2Step& st = pr.steps[s];
+      for (const auto* v : {&st.keep, &st.fin})
+        for (const R2Term& t : *v)
+          if (t.m) per_depth[st.depth].insert({st.src, t.m});
+    }
+    for (auto& kv : per_depth) max_rot = std::max(max_rot, kv.second.size());
+  }
+  uint64_t* regs = (uint64_t*)dev_scratch(c, 72, std::max<size_t>(1, (size_t)np * RB) * 8);
+  uint64_t* obuf = (uint64_t*)dev_scratch(c, 73, (size_t)np * OB * 8);
+  uint64_t* rbuf = (uint64_t*)dev_scratch(c, 74, (size_t)np * max_rot * ctw(la) * 8);
+  zero_fill(c, obuf, (size_t)np * OB);
+  auto reg = [&](int g, int r) -> uint64_t* { return r == 0 ? Y[g] : regs + (size_t)g * RB + roff[r]; };
+  auto oterm = [&](int g, int d) { return obuf + (size_t)g * OB + ooff[d]; };
+  {
+    std::vector<std::vector<MacTerm>> grp(np);
+    std::vector<uint64_t*> go(np);
+    for (int g = 0; g < np; ++g) {
+      grp[g].push_back(MacTerm{Y[g], mask(g, 0)});
+      go[g] = oterm(g, 0);
+    }
+    group_mac(c, la, grp, go, true);
+  }
+  for (auto& rn : runs) {
+    std::map<int, std::vector<size_t>> by_depth;
+    for (size_t s = rn.first; s < rn.second; ++s) by_depth[pr.steps[s].depth].push_back(s);
+    std::map<int, std::vector<int>> written;          // depth -> registers written at this boundary
+    for (auto& kv : by_depth) {
+      const int d = kv.first, level = la - d;
+      const size_t w = ctw(level);
+      // distinct rotations of this level's steps
+      // numbered in (register, amount) order, so the key-switch jobs come sorted by output
+      std::map<std::pair<int, int64_t>, int> rix;
+      std::map<int, int> six;
+      for (size_t s : kv.second) {
+        const R2Step& st = pr.steps[s];
+        for (const auto* v : {&st.keep, &st.fin})
+          for (const R2Term& t : *v)
+            if (t.m) rix.emplace(std::make_pair(st.src, t.m), 0);
+      }
+      {
+        int k = 0;
+        for (auto& kv2 : rix) {
+          kv2.second = k++;
+          if (!six.count(kv2.first.first)) six.emplace(kv2.first.first, (int)six.size());
+        }
+      }
+      const int nr = (int)rix.size(), ns = (int)six.size();
+      auto rot = [&](int g, int src, int64_t m) -> const uint64_t* {
+        if (m == 0) return reg(g, src);
+        return rbuf + ((size_t)g * nr + rix.at({src, m})) * w;
+      };
+      if (nr) {
+        std::vector<const uint64_t*> sources((size_t)np * ns);
+        for (int g = 0; g < np; ++g)
+          for (auto& sv : six) sources[(size_t)g * ns + sv.second] = reg(g, sv.first) + (size_t)(level + 1) * N;
+        std::vector<KSJob> jobs;
+        std::vector<uint64_t*> routs((size_t)np * nr);
+        for (int g = 0; g < np; ++g)
+          for (auto& kv2 : rix) {
+            uint64_t gal;
+            const uint64_t* key = rot_key(c, ek, kv2.first.second, gal);
+            const int k = g * nr + kv2.second;
+            routs[k] = rbuf + (size_t)k * w;
+            jobs.push_back(KSJob{key, reg(g, kv2.first.first), nullptr, nullptr, gal,
+                                 g * ns + six.at(kv2.first.first), k});
+          }
+        keyswitch_batch(c, level, sources, jobs, routs, false);
+      }
+      // masked sums: next registers, then this level's result term
+      std::map<int, std::vector<std::pair<size_t, size_t>>> into;   // register -> (step, term)
+      std::vector<std::pair<size_t, size_t>> fins;
+      for (size_t s : kv.second) {
+        const R2Step& st = pr.steps[s];
+        for (size_t t = 0; t < st.keep.size(); ++t) into[st.keep[t].dst].push_back({s, t});
+        for (size_t t = 0; t < st.fin.size(); ++t) fins.push_back({s, t});
+      }
+      if (!into.empty()) {
+        std::vector<std::vector<MacTerm>> grp;
+        std::vector<uint64_t*> go;
+        for (int g = 0; g < np; ++g)
+          for (auto& kv3 : into) {
+            std::vector<MacTerm> terms;
+            for (auto& st_t : kv3.second) {
+              const R2Step& st = pr.steps[st_t.first];
+              const R2Term& tm = st.keep[st_t.second];
+              terms.push_back(MacTerm{rot(g, st.src, tm.m), mask(g, first[st_t.first] + st_t.second)});
+            }
+            grp.push_back(std::move(terms));
+            go.push_back(reg(g, kv3.first));
+          }
+        group_mac(c, level, grp, go, false);
+        for (auto& kv3 : into) written[d].push_back(kv3.first);
+      }
+      if (!fins.empty()) {
+        std::vector<std::vector<MacTerm>> grp(np);
+        std::vector<uint64_t*> go(np);
+        for (int g = 0; g < np; ++g) {
+          for (auto& st_t : fins) {
+            const R2Step& st = pr.steps[st_t.first];
+            const R2Term& tm = st.fin[st_t.second];
+            grp[g].push_back(MacTerm{rot(g, st.src, tm.m), mask(g, first[st_t.first] + st.keep.size() + st_t.second)});
+          }
+          go[g] = oterm(g, d);
+        }
+        group_mac(c, level, grp, go, true);
+      }
+    }
+    for (auto& kv : written) {
+      std::vector<uint64_t*> cts;
+      for (int g = 0; g < np; ++g)
+        for (int r : kv.second) cts.push_back(reg(g, r));
+      rescale_batch(c, la - kv.first, cts);
+    }
+  }
+  std::vector<std::vector<MacTerm>> grp(np);
+  for (int d = 0; d < D; ++d) {
+    std::vector<uint64_t*> cts(np);
+    for (int g = 0; g < np; ++g) cts[g] = oterm(g, d);
+    rescale_batch(c, la - d, cts);
+    for (int g = 0; g < np; ++g) grp[g].push_back(MacTerm{oterm(g, d), nullptr, la - d});
+  }
+  group_mac(c, lo, grp, outs, false);
+}
+
 // SpIntra-CA of every packed ciphertext Y[g] into outs[g] (batched form)
 static void aggregate_batched(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, const std::vector<uint64_t*>& Y,
                               const std::vector<uint64_t*>& outs) {
@@ -260,6 +513,10 @@ static void aggregate_batched(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, c
   const size_t ct_words = (size_t)2 * l1 * N;
   const size_t ns = lp.shifts.size();
   const int np = (int)Y.size();
+  if (lp.family == 3) {
+    aggregate_r2_batched(c, ek, lp, Y, outs);
+    return;
+  }
   auto mask = [&](int g, size_t si) { return (const uint64_t*)lp.ops[(size_t)g * ns + si]; };
   std::vector<const uint64_t*> ysrc(np);
   for (int g = 0; g < np; ++g) ysrc[g] = Y[g] + (size_t)l1 * N;
@@ -656,6 +913,7 @@ ficgcn_status ficgcn_plan_create(ckks_ctx* ctx, const int32_t* rowptr, const int
   GUARD_BEGIN
   if (!ctx || !rowptr || !col || !val || !dims || !weights || !opts || !out || n_v == 0 || n_layers == 0)
     FICGCN_THROW(EINVAL_, "null or empty argument");
+  if (opts->family < 0 || opts->family > 3) FICGCN_THROW(EINVAL_, "family must be 0, 1, 2 or 3");
   for (uint32_t l = 0; l < n_layers; ++l)
     if (!weights[l] || dims[l] == 0 || dims[l + 1] == 0) FICGCN_THROW(EINVAL_, "bad layer dimensions or weights");
   std::unique_ptr<ficgcn_plan> p(new ficgcn_plan());
@@ -782,9 +1040,45 @@ ficgcn_status ficgcn_plan_operand_slots(const ficgcn_plan* plan, uint32_t layer,
 
 static void ensure_ops_block(ckks_ctx* ctx, LayerPlan& lp) {
   if (lp.ops_block) return;
-  const size_t per = (size_t)(lp.op_level + 1) * ctx->N;
-  if (hipMalloc(&lp.ops_block, std::max<size_t>(1, lp.ops.size()) * per * 8) != hipSuccess)
+  if (hipMalloc(&lp.ops_block, std::max<size_t>(1, lp.op_words) * 8) != hipSuccess)
     FICGCN_THROW(ENOMEM_, "operand allocation failed");
+}
+
+ficgcn_status ficgcn_plan_operand_level(const ficgcn_plan* plan, uint32_t layer, size_t i, uint32_t* level_out,
+                                        double* scale_out) {
+  GUARD_BEGIN
+  if (!plan || !level_out || layer >= plan->layers.size() || i >= plan_operand_count(plan, (int)layer))
+    FICGCN_THROW(EINVAL_, "bad argument");
+  *level_out = (uint32_t)plan_operand_level(plan, (int)layer, i);
+  if (scale_out) *scale_out = plan_operand_scale(plan, (int)layer, i);
+  GUARD_END
+}
+
+ficgcn_status ficgcn_plan_radix2_stats(const ficgcn_plan* plan, uint32_t layer, int64_t* out) {
+  GUARD_BEGIN
+  if (!plan || !out || layer >= plan->layers.size()) FICGCN_THROW(EINVAL_, "bad argument");
+  const LayerPlan& lp = plan->layers[layer];
+  if (lp.kind != 1 || lp.family != 3) FICGCN_THROW(EPLAN_, "not a radix-2 SpIntra-CA layer");
+  const R2Program& r = lp.r2;
+  std::set<std::pair<int, int64_t>> rots;
+  std::set<int64_t> amounts;
+  for (const R2Step& st : r.steps) {
+    for (const auto* v : {&st.keep, &st.fin})
+      for (const R2Term& t : *v)
+        if (t.m) {
+          rots.insert({st.src, t.m});
+          amounts.insert(t.m);
+        }
+  }
+  out[0] = r.n_lanes;
+  out[1] = (int64_t)r.steps.size();
+  out[2] = (int64_t)rots.size();
+  out[3] = (int64_t)amounts.size();
+  out[4] = r.depth;
+  out[5] = (int64_t)r.ops.size();
+  out[6] = r.n_moved;
+  out[7] = (int64_t)r.reg_depth.size() - 1;
+  GUARD_END
 }
 
 ficgcn_status ficgcn_plan_encode(ckks_ctx* ctx, ficgcn_plan* plan) {
@@ -795,21 +1089,23 @@ ficgcn_status ficgcn_plan_encode(ckks_ctx* ctx, ficgcn_plan* plan) {
     LayerPlan& lp = plan->layers[li];
     ensure_ops_block(ctx, lp);
     const size_t n = lp.ops.size();
-    const size_t per = (size_t)(lp.op_level + 1) * ctx->N;
     const size_t chunk = 256;
     std::vector<double> all;
-    for (size_t b0 = 0; b0 < n; b0 += chunk) {
-      size_t nb = std::min(chunk, n - b0);
+    std::vector<double> v;
+    // runs of operands with one level (all of them, except for the radix-2 masks)
+    for (size_t b0 = 0; b0 < n;) {
+      size_t nb = 1;
+      while (b0 + nb < n && nb < chunk && lp.op_lv[b0 + nb] == lp.op_lv[b0]) ++nb;
       all.assign(nb * plan->M, 0.0);
-      std::vector<double> v;
       for (size_t b = 0; b < nb; ++b) {
         plan_operand_slots(plan, (int)li, b0 + b, v);
         std::memcpy(all.data() + b * plan->M, v.data(), plan->M * 8);
       }
-      ficgcn_status st = ckks_encode_batch(ctx, all.data(), nb, plan->M, lp.op_scale, lp.op_level,
-                                           lp.ops_block + b0 * per);
+      ficgcn_status st = ckks_encode_batch(ctx, all.data(), nb, plan->M, plan_operand_scale(plan, (int)li, b0),
+                                           lp.op_lv[b0], lp.ops_block + lp.op_off[b0]);
       if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
-      for (size_t b = 0; b < nb; ++b) lp.ops[b0 + b] = lp.ops_block + (b0 + b) * per;
+      for (size_t b = 0; b < nb; ++b) lp.ops[b0 + b] = lp.ops_block + lp.op_off[b0 + b];
+      b0 += nb;
     }
   }
   GUARD_END
@@ -823,9 +1119,8 @@ ficgcn_status ficgcn_plan_load_operand(ckks_ctx* ctx, ficgcn_plan* plan, uint32_
   LayerPlan& lp = plan->layers[layer];
   if (i >= lp.ops.size()) FICGCN_THROW(EINVAL_, "operand index out of range");
   ensure_ops_block(ctx, lp);
-  const size_t per = (size_t)(lp.op_level + 1) * ctx->N;
-  uint64_t* dst = lp.ops_block + i * per;
-  ficgcn_status st = ckks_pt_load(ctx, host_coeffs, lp.op_level, dst);
+  uint64_t* dst = lp.ops_block + lp.op_off[i];
+  ficgcn_status st = ckks_pt_load(ctx, host_coeffs, lp.op_lv[i], dst);
   if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
   lp.ops[i] = dst;
   GUARD_END
@@ -838,11 +1133,11 @@ ficgcn_status ficgcn_plan_fill_operands(ckks_ctx* ctx, ficgcn_plan* plan, uint64
   for (size_t li = 0; li < plan->layers.size(); ++li) {
     LayerPlan& lp = plan->layers[li];
     ensure_ops_block(ctx, lp);
-    const size_t per = (size_t)(lp.op_level + 1) * ctx->N;
     for (size_t i = 0; i < lp.ops.size(); ++i) {
-      uint64_t* dst = lp.ops_block + i * per;
+      uint64_t* dst = lp.ops_block + lp.op_off[i];
+      const int l1 = lp.op_lv[i] + 1;
       // stream (6, layer * 2^20 + i, limb): a stream the scheme itself never draws
-      sample_uniform(ctx, dst, seed, 6, (uint32_t)(li << 20 | i), 0, lp.op_level + 1, lm_q(lp.op_level + 1), 1);
+      sample_uniform(ctx, dst, seed, 6, (uint32_t)(li << 20 | i), 0, l1, lm_q(l1), 1);
       lp.ops[i] = dst;
     }
   }

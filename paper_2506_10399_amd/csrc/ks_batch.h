@@ -28,8 +28,9 @@ struct TensorJob {
 };
 
 struct MacTerm {
-  const uint64_t* ct;     // [2][l+1][N]
+  const uint64_t* ct;     // [2][l+1][N], or [2][l1][N] when l1 is set
   const uint64_t* pt;     // [l+1][N], null = plain addition
+  int64_t l1 = 0;         // limbs per component of ct (0: l+1); a larger value reads ct dropped to level l
 };
 
 // sources: polynomials [l+1][N] in evaluation form (a ciphertext's c1 or a

@@ -423,7 +423,7 @@ __global__ void k_group_mac(const MacTerm* __restrict__ terms, const int* __rest
   int cnt = 0;
   for (int t = group_start[g]; t < group_start[g + 1]; ++t) {
     const MacTerm tm = terms[t];
-    const uint64_t x = tm.ct[o];
+    const uint64_t x = tm.ct[tm.l1 ? ((size_t)comp * tm.l1 + i) * N + j : o];
     if (tm.pt) {
       s += (u128)x * tm.pt[(size_t)i * N + j];
       if (++cnt == 8) {

@@ -7,7 +7,8 @@
 // (one column per ciphertext), packing of t = min(pow2(F'), M / pow2(n_v))
 // columns, then routing of every nonzero A_vu by its shift pi(u) - pi(v) in
 // the diagonal form (one rotation + mask per distinct shift, all rotations
-// hoisted on one ModUp) or the baby-step/giant-step form.
+// hoisted on one ModUp), the baby-step/giant-step form, or the paper's
+// radix-2 form with per-round masks (radix2.cpp).
 // Node order (Sec. 3.4, Alg. 1): sibling-BFS regions of at most TH nodes
 // (highest degree first; when the BFS runs dry the region continues from the
 // highest-degree node left), interleaved round-robin (an exhausted region's
@@ -232,7 +233,14 @@ static void bsgs_split(const std::vector<int64_t>& shifts, int B, int& G_out, in
 
 static std::vector<int64_t> rotation_steps_of(const LayerPlan& lp) {
   std::set<int64_t> s;
-  if (lp.family == 1) {
+  if (lp.family == 3) {
+    for (const R2Step& st : lp.r2.steps) {
+      for (const R2Term& t : st.keep)
+        if (t.m) s.insert(t.m);
+      for (const R2Term& t : st.fin)
+        if (t.m) s.insert(t.m);
+    }
+  } else if (lp.family == 1) {
     for (int64_t d : lp.shifts)
       if (d) s.insert(d);
   } else {
@@ -282,9 +290,16 @@ static void schedule(ckks_ctx* c, ficgcn_plan* p) {
       lp.level_agg = lv;
       lp.scale_agg = s;
       lp.sM = (double)c->mod[lv];
-      s = s * lp.sM;
-      s = s / (double)c->mod[lv];
-      lv -= 1;
+      if (lp.family == 3) {
+        // every step's masks are encoded at the prime its rescale drops: the
+        // result keeps the scale exactly; one level per step on the deepest chain
+        if (lv < lp.r2.depth) FICGCN_THROW(EPLAN_, "not enough levels for the radix-2 aggregation");
+        lv -= lp.r2.depth;
+      } else {
+        s = s * lp.sM;
+        s = s / (double)c->mod[lv];
+        lv -= 1;
+      }
       lp.op_level = lp.level_agg;
       lp.op_scale = lp.sM;
     }
@@ -301,7 +316,38 @@ static void schedule(ckks_ctx* c, ficgcn_plan* p) {
 
 size_t plan_operand_count(const ficgcn_plan* p, int li) {
   const LayerPlan& lp = p->layers[li];
-  return lp.kind == 0 ? (size_t)lp.K : (size_t)lp.n_packed() * lp.shifts.size();
+  if (lp.kind == 0) return (size_t)lp.K;
+  if (lp.family == 3) return (size_t)lp.n_packed() * lp.r2.ops.size();
+  return (size_t)lp.n_packed() * lp.shifts.size();
+}
+
+int plan_operand_level(const ficgcn_plan* p, int li, size_t i) {
+  const LayerPlan& lp = p->layers[li];
+  if (lp.kind == 1 && lp.family == 3) return lp.level_agg - lp.r2.ops[i % lp.r2.ops.size()].depth;
+  return lp.op_level;
+}
+
+double plan_operand_scale(const ficgcn_plan* p, int li, size_t i) {
+  const LayerPlan& lp = p->layers[li];
+  if (lp.kind == 1 && lp.family == 3) return (double)p->ctx->mod[plan_operand_level(p, li, i)];
+  return lp.op_scale;
+}
+
+static void layout_operands(ficgcn_plan* p) {
+  const size_t N = p->ctx->N;
+  for (size_t li = 0; li < p->layers.size(); ++li) {
+    LayerPlan& lp = p->layers[li];
+    const size_t n = plan_operand_count(p, (int)li);
+    lp.op_lv.resize(n);
+    lp.op_off.resize(n);
+    size_t off = 0;
+    for (size_t i = 0; i < n; ++i) {
+      lp.op_lv[i] = plan_operand_level(p, (int)li, i);
+      lp.op_off[i] = off;
+      off += (size_t)(lp.op_lv[i] + 1) * N;
+    }
+    lp.op_words = off;
+  }
 }
 
 void plan_operand_slots(const ficgcn_plan* p, int li, size_t i, std::vector<double>& out) {
@@ -311,6 +357,20 @@ void plan_operand_slots(const ficgcn_plan* p, int li, size_t i, std::vector<doub
   if (lp.kind == 0) {
     for (int v = 0; v < n; ++v)
       if (lp.copy_src[i * n + v] >= 0) out[p->pi[v]] = lp.copy_val[i * n + v];
+    return;
+  }
+  if (lp.family == 3) {
+    const size_t nops = lp.r2.ops.size();
+    const int g = (int)(i / nops);
+    const int n_cols = std::min(lp.t, lp.f_out - g * lp.t);
+    const R2Program::Ref& ref = lp.r2.ops[i % nops];
+    const R2Term* t = &lp.r2.self;
+    if (ref.step >= 0) {
+      const R2Step& st = lp.r2.steps[ref.step];
+      t = ref.term < (int)st.keep.size() ? &st.keep[ref.term] : &st.fin[ref.term - st.keep.size()];
+    }
+    for (size_t k = 0; k < t->slot.size(); ++k)
+      for (int cc = 0; cc < n_cols; ++cc) out[(size_t)cc * lp.B + t->slot[k]] = t->val[k];
     return;
   }
   const size_t ns = lp.shifts.size();
@@ -365,7 +425,7 @@ void release_plan_device(ficgcn_plan* p) {
 
 size_t plan_operand_bytes(const ficgcn_plan* p) {
   size_t b = 0;
-  for (const auto& lp : p->layers) b += lp.ops.size() * (size_t)(lp.op_level + 1) * p->ctx->N * 8;
+  for (const auto& lp : p->layers) b += lp.op_words * 8;
   return b;
 }
 
@@ -453,7 +513,12 @@ void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_la
       int c2;
       bsgs_split(lp.shifts, lp.B, lp.G, c2);
       int c1 = (int)lp.shifts.size() - (sh.count(0) ? 1 : 0);
-      lp.family = o.family == 1 ? 1 : o.family == 2 ? 2 : (c2 < c1 ? 2 : 1);
+      lp.family = o.family == 1 ? 1 : o.family == 2 ? 2 : o.family == 3 ? 3 : (c2 < c1 ? 2 : 1);
+      if (lp.family == 3) {
+        if (!(o.cpoo >= 0.0 && o.cpoo <= 1.0)) FICGCN_THROW(EPLAN_, "CPOO threshold must lie in [0, 1]");
+        lp.cpoo = o.cpoo;
+        build_radix2(p->pi, p->rowptr, p->col, p->val, M, lp.B, wrap, o.cpoo, lp.r2);
+      }
       std::set<int64_t> pk;
       for (int l = 0; l < lp.f_out; ++l)
         if (l % lp.t) pk.insert(-(int64_t)(l % lp.t) * lp.B);
@@ -462,6 +527,7 @@ void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_la
     p->layers.push_back(lp);
   }
   schedule(c, p);
+  layout_operands(p);
   for (uint32_t li = 0; li < n_layers; ++li) {
     LayerPlan& lp = p->layers[li];
     lp.w_int.resize((size_t)lp.f_in * lp.f_out);

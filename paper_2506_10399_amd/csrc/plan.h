@@ -6,6 +6,38 @@
 
 namespace ficgcn {
 
+// Radix-2 SpIntra-CA program (paper Sec. 3.3, CPOO of Sec. 3.3.1): working
+// ciphertexts ("registers") stepped round by round through masks.
+struct R2Term {
+  int dst = -1;                    // Keep/Move term: register written; Fin term: -1
+  int64_t m = 0;                   // rotation amount of the source register (0: none)
+  std::vector<int32_t> slot;       // block-local slots, ascending
+  std::vector<double> val;         // mask values at those slots
+};
+struct R2Step {
+  int lane = 0, r0 = 0, r1 = 0;    // rounds [r0, r1)
+  int depth = 0;                   // levels below the aggregation level of the source register
+  int src = 0;                     // register read (0 = the packed input)
+  std::vector<R2Term> keep;        // by (dst, m)
+  std::vector<R2Term> fin;         // by m
+};
+struct R2Program {
+  R2Term self;                     // the self terms, multiplied into the input
+  std::vector<R2Step> steps;
+  std::vector<int> reg_depth;      // per register
+  int depth = 1;                   // levels the aggregation consumes
+  int n_lanes = 0;
+  int64_t n_moved = 0;
+  // operand j: step (-1 = self), term index (keep first, then fin), depth
+  struct Ref { int step, term, depth; };
+  std::vector<Ref> ops;
+};
+// The program of one packed layout: node order pi, CSR adjacency (diagonal
+// included), M slots, column block B (wrap: t = 1, shifts AOO-reduced),
+// CPOO threshold theta (0 = off).
+void build_radix2(const std::vector<int32_t>& pi, const std::vector<int32_t>& rowptr, const std::vector<int32_t>& col,
+                  const std::vector<double>& val, int M, int B, bool wrap, double theta, R2Program& out);
+
 struct LayerPlan {
   int kind = 0;              // 0 = Inter-CA (client copies), 1 = SpIntra-CA
   int f_in = 0, f_out = 0;
@@ -19,6 +51,8 @@ struct LayerPlan {
   std::vector<int64_t> shifts;     // sorted distinct
   int family = 1, G = 1;
   std::vector<int64_t> pack_steps; // sorted distinct, negative
+  R2Program r2;                    // family 3
+  double cpoo = 0;                 // family 3: CPOO threshold (0 = off)
   // schedule
   int level_in = 0, level_agg = 0, level_out = 0, n_rescale_comb = 0;
   double scale_in = 0, sP = 0, sW = 0, sM = 0, scale_agg = 0, scale_out = 0;
@@ -28,6 +62,9 @@ struct LayerPlan {
   // SpIntra-CA: n_packed * n_shifts masks at level_agg
   int op_level = 0;
   double op_scale = 0;
+  std::vector<int32_t> op_lv;      // level of each operand
+  std::vector<size_t> op_off;      // word offset of each operand in ops_block
+  size_t op_words = 0;
   std::vector<uint64_t*> ops;
   uint64_t* ops_block = nullptr;   // one allocation for all operands
   // device constants for the fused kernels (built on first use)
@@ -78,6 +115,9 @@ namespace ficgcn {
 // operand slot vector i of layer li (M doubles)
 void plan_operand_slots(const ficgcn_plan* p, int li, size_t i, std::vector<double>& out);
 size_t plan_operand_count(const ficgcn_plan* p, int li);
+// level and encoding scale of operand i of layer li
+int plan_operand_level(const ficgcn_plan* p, int li, size_t i);
+double plan_operand_scale(const ficgcn_plan* p, int li, size_t i);
 void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const uint64_t* const* in, size_t n_in,
                uint64_t* const* out, size_t n_out, int mode);
 // frees the plan's device memory (operands and layer constants); the plan can be encoded again

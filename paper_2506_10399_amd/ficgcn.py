@@ -36,7 +36,8 @@ class CkksParams(ctypes.Structure):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("first_mode", ctypes.c_int32), ("use_noo", ctypes.c_int32), ("family", ctypes.c_int32),
-                ("TH", ctypes.c_int32), ("activation", ctypes.c_int32), ("t", ctypes.c_int32)]
+                ("TH", ctypes.c_int32), ("activation", ctypes.c_int32), ("t", ctypes.c_int32),
+                ("cpoo", ctypes.c_double)]
 
 
 class SearchStats(ctypes.Structure):
@@ -111,6 +112,9 @@ _SIGS = {
     "ficgcn_plan_weights_int": (ctypes.c_int, [c_vp, ctypes.c_uint32, c_vp]),
     "ficgcn_plan_operand_count": (ctypes.c_int, [c_vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_size_t)]),
     "ficgcn_plan_operand_slots": (ctypes.c_int, [c_vp, ctypes.c_uint32, ctypes.c_size_t, c_vp]),
+    "ficgcn_plan_operand_level": (ctypes.c_int, [c_vp, ctypes.c_uint32, ctypes.c_size_t,
+                                                 ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_double)]),
+    "ficgcn_plan_radix2_stats": (ctypes.c_int, [c_vp, ctypes.c_uint32, c_vp]),
     "ficgcn_plan_encode": (ctypes.c_int, [c_vp, c_vp]),
     "ficgcn_plan_load_operand": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, ctypes.c_size_t, c_vp]),
     "ficgcn_gcn_layer": (ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_uint32, c_vp, ctypes.c_size_t, c_vp,
@@ -387,7 +391,7 @@ class Plan:
 
     def __init__(self, ctx: Context, rowptr, col, val, n_v: int, dims: Sequence[int], weights,
                  first_mode: int = 0, use_noo: bool = True, family: int = 0, TH: int = 0, activation: bool = False,
-                 t: int = 0, opts: "PlanOpts" = None):
+                 t: int = 0, cpoo: float = 0.0, opts: "PlanOpts" = None):
         self.ctx = ctx
         self._rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
         self._col = np.ascontiguousarray(col, dtype=np.int32)
@@ -396,7 +400,7 @@ class Plan:
         self._w = [np.ascontiguousarray(w, dtype=np.float64) for w in weights]
         wp = _ptr_array(self._w)
         if opts is None:
-            opts = PlanOpts(first_mode, int(use_noo), family, TH, int(activation), t)
+            opts = PlanOpts(first_mode, int(use_noo), family, TH, int(activation), t, cpoo)
         self.opts = opts
         h = c_vp()
         _check(lib().ficgcn_plan_create(ctx.h, _ptr(self._rowptr), _ptr(self._col), _ptr(self._val), n_v,
@@ -472,6 +476,18 @@ class Plan:
         out = np.zeros(self.ctx.M, dtype=np.float64)
         _check(lib().ficgcn_plan_operand_slots(self.h, layer, i, _ptr(out)))
         return out
+
+    def ficgcn_plan_operand_level(self, layer: int, i: int):
+        lv = ctypes.c_uint32()
+        sc = ctypes.c_double()
+        _check(lib().ficgcn_plan_operand_level(self.h, layer, i, ctypes.byref(lv), ctypes.byref(sc)))
+        return lv.value, sc.value
+
+    def ficgcn_plan_radix2_stats(self, layer: int) -> dict:
+        out = np.zeros(8, dtype=np.int64)
+        _check(lib().ficgcn_plan_radix2_stats(self.h, layer, _ptr(out)))
+        keys = ["lanes", "steps", "rotations", "amounts", "depth", "masks", "moved", "registers"]
+        return {k: int(v) for k, v in zip(keys, out)}
 
     def ficgcn_plan_encode(self):
         _check(lib().ficgcn_plan_encode(self.ctx.h, self.h))

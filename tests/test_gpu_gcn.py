@@ -23,13 +23,14 @@ def _ct(c):
     return np.stack([c.c0, c.c1])
 
 
-def _setup(name, mode, family=None, **kw):
+def _setup(name, mode, family=None, cpoo=None, **kw):
     from paper_2506_10399_amd import ficgcn as fg, graph
     w = make_workload(name, **kw)
     prm = Params.from_dict(w.params)
     rows = gcn.normalized_rows(w.graph.n, w.neighbors, w.norm)
     ref = gcn.gcn_forward(rows, w.x, w.weights, w.activation)
-    o = planner.build_plan(w.graph.n, rows, w.meta["dims"], w.activation, prm.M, family=family, first_mode=mode)
+    o = planner.build_plan(w.graph.n, rows, w.meta["dims"], w.activation, prm.M, family=family, first_mode=mode,
+                           cpoo=cpoo)
     okeys = ckks.keygen(prm, KEY_SEED, o.rot_steps(prm.M), relin=w.activation)
     sched = ex.schedule(prm, o)
     ops = ex.encode_operands(prm, o, w.weights, sched)
@@ -38,7 +39,7 @@ def _setup(name, mode, family=None, **kw):
     ctx = fg.Context.from_dict(w.params)
     rp, col, val = graph.normalize(w.graph.n, w.neighbors, w.norm)
     p = fg.Plan(ctx, rp, col, val, w.graph.n, w.meta["dims"], w.weights, first_mode=0 if mode == "inter" else 1,
-                family=family or 0, activation=w.activation)
+                family=family or 0, activation=w.activation, cpoo=cpoo or 0.0)
     assert np.array_equal(p.ficgcn_plan_node_order(), o.pi)
     cl, ev = ctx.ckks_keygen(KEY_SEED, p.ficgcn_plan_rot_steps(), with_relin=w.activation)
     return dict(w=w, prm=prm, rows=rows, ref=ref, o=o, okeys=okeys, sched=sched, ops=ops, cts=cts, outs=outs,
@@ -50,6 +51,8 @@ def _load_operands(e):
     for li, (lp, d) in enumerate(zip(o.layers, e["ops"])):
         if lp.kind == "inter":
             flat = d["P"]
+        elif lp.family == 3:
+            flat = [pt for per_g in d["masks"] for pt in per_g]
         else:
             flat = [d["masks"][g][s] for g in range(len(d["masks"])) for s in lp.shifts]
         assert len(flat) == p.ficgcn_plan_operand_count(li)
@@ -149,4 +152,47 @@ def test_library_encoder_end_to_end(name, mode):
     lp = e["o"].layers[-1]
     slots = [np.real(ctx.ckks_decrypt(e["cl"], x, info[-1]["level_out"], info[-1]["scale_out"], prm.M)) for x in cur]
     y = e["graph"].read_output(p.ficgcn_plan_node_order(), slots, lp.f_out, lp.t, lp.B, lp.kind == "spintra")
+    assert gcn.max_rel_error(y, e["ref"][-1]) < 1e-3
+
+
+R2_CASES = [("tiny_deep", "spintra", 0.25), ("tiny_deep", "spintra", None), ("tiny2_deep", "inter", 0.25)]
+
+
+@pytest.mark.parametrize("name,mode,cpoo", R2_CASES)
+def test_radix2_layers_bit_exact_all_forms(name, mode, cpoo):
+    """The paper's radix-2 SpIntra-CA (per-round masks, CPOO on or off) on a
+    deep prime chain: plain, batched and graph forms (capture and a replay)
+    give the oracle's words; the decrypted output is within 1e-3 of FP64."""
+    e = _setup(name, mode, 3, cpoo)
+    _load_operands(e)
+    for m in (0, 1, 2, 2):
+        res = _run_gpu(e, m)
+        for li, ((outs, lvo), want) in enumerate(zip(res, e["outs"])):
+            for g, (x, b) in enumerate(zip(outs, want)):
+                assert b.level == lvo
+                got = e["ctx"].ckks_poly_store(x, lvo, 2)
+                assert np.array_equal(got, _ct(b)), (name, cpoo, "form", m, "layer", li, "ct", g)
+    lp = e["o"].layers[-1]
+    info = e["p"].ficgcn_plan_info()[-1]
+    slots = [np.real(e["ctx"].ckks_decrypt(e["cl"], x, info["level_out"], info["scale_out"], e["prm"].M))
+             for x in res[-1][0]]
+    y = e["graph"].read_output(e["o"].pi, slots, lp.f_out, lp.t, lp.B, True)
+    assert gcn.max_rel_error(y, e["ref"][-1]) < 1e-3
+
+
+def test_radix2_library_encoder_end_to_end():
+    """Radix-2 masks encoded by the library at their own levels and scales."""
+    e = _setup("tiny_deep", "spintra", 3, 0.25)
+    ctx, p, prm, w = e["ctx"], e["p"], e["prm"], e["w"]
+    p.ficgcn_plan_encode()
+    lv0 = prm.L - 1
+    rows = e["graph"].client_slots(p.ficgcn_plan_node_order(), w.x, prm.M, None)
+    pts = ctx.ckks_encode_batch(rows, prm.scale, lv0)
+    cur = [ctx.ckks_encrypt(e["cl"], pts[i], lv0, ENC_SEED, i) for i in range(rows.shape[0])]
+    d = p.ficgcn_plan_info()[0]
+    outs = [ctx.ct_buffer(d["level_in"]) for _ in range(d["n_out_cts"])]
+    p.ficgcn_gcn_layer(e["ev"], 0, cur, outs, mode=1)
+    lp = e["o"].layers[-1]
+    slots = [np.real(ctx.ckks_decrypt(e["cl"], x, d["level_out"], d["scale_out"], prm.M)) for x in outs]
+    y = e["graph"].read_output(p.ficgcn_plan_node_order(), slots, lp.f_out, lp.t, lp.B, True)
     assert gcn.max_rel_error(y, e["ref"][-1]) < 1e-3

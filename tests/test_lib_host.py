@@ -200,3 +200,47 @@ def test_exhaustive_search_no_worse_than_paper_rule(fg, name):
     c = fg.ficgcn_plan_candidates(w.graph.n, w.meta["dims"], w.params["log_n"], base)
     costs = [fg.Plan(ctx, rp, col, val, w.graph.n, w.meta["dims"], w.weights, opts=o).ficgcn_plan_cost() for o in c]
     assert st.best_cost == min(costs)
+
+
+@pytest.mark.parametrize("name,mode,cpoo,kw", [
+    ("tiny_deep", "spintra", None, {}), ("tiny_deep", "spintra", 0.25, {}), ("tiny_deep", "spintra", 0.3, {"t": 1}),
+    ("tiny2_deep", "inter", None, {}), ("tiny2_deep", "inter", 0.25, {}),
+    ("cora_deep", "inter", 0.25, {"dims": [24, 16, 7]}),
+])
+def test_radix2_plan_matches_oracle(fg, name, mode, cpoo, kw):
+    """The library's radix-2 program (family 3) equals the oracle's: step and
+    rotation counts, levels, every mask's slots, level and scale, the keys."""
+    from paper_2506_10399_amd import graph
+    from oracle import radix2
+    t = kw.get("t")
+    w = make_workload(name, **{k: v for k, v in kw.items() if k != "t"})
+    prm = Params.from_dict(w.params)
+    rows = gcn.normalized_rows(w.graph.n, w.neighbors, w.norm)
+    o = planner.build_plan(w.graph.n, rows, w.meta["dims"], w.activation, prm.M, family=3, first_mode=mode,
+                           cpoo=cpoo, t=t)
+    rp, col, val = graph.normalize(w.graph.n, w.neighbors, w.norm)
+    ctx = fg.Context.from_dict(w.params)
+    p = fg.Plan(ctx, rp, col, val, w.graph.n, w.meta["dims"], w.weights, first_mode=0 if mode == "inter" else 1,
+                family=3, activation=w.activation, t=t or 0, cpoo=cpoo or 0.0)
+    assert np.array_equal(p.ficgcn_plan_node_order(), o.pi.astype(np.int32))
+    sched = ex.schedule(prm, o)
+    info = p.ficgcn_plan_info()
+    for li, (lp, d, st) in enumerate(zip(o.layers, info, sched)):
+        assert d["level_out"] == st["level_out"] and d["scale_out"] == st["scale_out"] and d["sW"] == st["sW"]
+        if lp.kind == "inter":
+            continue
+        prog = lp.program
+        assert d["family"] == 3
+        assert p.ficgcn_plan_radix2_stats(li) == dict(
+            lanes=prog.n_lanes, steps=prog.n_steps(), rotations=len(prog.rotations()), amounts=len(prog.amounts()),
+            depth=prog.depth, masks=len(radix2.operand_list(prog)), moved=prog.n_moved,
+            registers=len(prog.reg_depth) - 1)
+        flat = [x for per_g in ex.radix2_mask_vectors(o, li) for x in per_g]
+        assert p.ficgcn_plan_operand_count(li) == len(flat)
+        stride = max(1, len(flat) // 97)
+        for i in list(range(0, len(flat), stride)) + [len(flat) - 1]:
+            dep, v = flat[i]
+            lvl = st["level_agg"] - dep
+            assert p.ficgcn_plan_operand_level(li, i) == (lvl, float(prm.q[lvl]))
+            assert np.array_equal(p.ficgcn_plan_operand_slots(li, i), v)
+    assert p.ficgcn_plan_rot_steps() == o.rot_steps(prm.M)
