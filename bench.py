@@ -146,6 +146,10 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="instead: a Poisson stream of encrypted GCN requests through the server (rate sweep)")
     ap.add_argument("--requests", type=int, default=10)
+    ap.add_argument("--radix2", action="store_true",
+                    help="instead: the paper's radix-2 SpIntra-CA (per-round masks, CPOO, AOO): rotation/level "
+                         "ablation on synthetic graphs and the second layer of the citation-graph shape on a deep "
+                         "prime chain, timed against the baby-step/giant-step form")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU path "
@@ -153,6 +157,9 @@ def main():
         sys.exit(2)
     if args.serving:
         serving_bench(args)
+        return
+    if args.radix2:
+        radix2_bench(args)
         return
 
     import torch
@@ -452,6 +459,156 @@ def serving_bench(args):
                runs=runs, max_rel_err=err,
                requests=[dict(name=q.name, latency_ms=round(q.result["latency_ms"], 2),
                               footprint_gb=round(q.result["footprint_bytes"] / 1e9, 2)) for q in reqs])
+    print(json.dumps(out), flush=True)
+
+
+def agg_rotations(plan, layer) -> int:
+    """Aggregation key switches per packed ciphertext of a SpIntra-CA layer."""
+    d = plan.ficgcn_plan_info()[layer]
+    if d["family"] == 3:
+        return plan.ficgcn_plan_radix2_stats(layer)["rotations"]
+    shifts = plan.ficgcn_plan_shifts(layer)
+    if d["family"] == 1:
+        return sum(1 for s in shifts if s != 0)
+    G = d["G"]
+    return len({s % G for s in shifts} - {0}) + len({s // G for s in shifts} - {0})
+
+
+def radix2_bench(args):
+    """The paper's radix-2 SpIntra-CA (Sec. 3.3) with AOO and CPOO (Sec. 3.3.1).
+
+    Ablation (host, library planner): the second layer of the citation-graph,
+    larger citation-graph and clustered-graph shapes (3 seeded replicates
+    each) at the paper's packing, with CPOO thresholds 0-0.5, and at one
+    column per ciphertext with AOO on and off.  Counts: aggregation key
+    switches per packed ciphertext, levels, masks.  The diagonal and
+    baby-step/giant-step forms are listed beside them.
+
+    Timing (GPU): the second layer (combination, packing, aggregation, x^2) of
+    the citation-graph shape on a chain of 18 + 2 primes (N = 2^16), its 16
+    input ciphertexts resident (squared encryptions of uniform values, as the
+    first layer leaves them), in the baby-step/giant-step form and the
+    radix-2 form without and with CPOO (0.25), each as HIP-graph replays; the
+    plain form's words must equal the batched form's, and the decoded output
+    is checked against the FP64 layer."""
+    import torch
+    from paper_2506_10399_amd import ficgcn as fg, graph
+    from workload import make_workload
+    torch.cuda.set_device(0)
+    t_all = time.perf_counter()
+    ablation = []
+    thetas = (0.0, 0.1, 0.2, 0.25, 0.3, 0.5)
+    for name in ("cora", "citeseer", "pubmed"):
+        for rep in range(3):
+            w = make_workload(name, replicate=rep)
+            rp, col, val = graph.normalize(w.graph.n, w.neighbors, w.norm)
+            # planning only: a chain deep enough for any routing depth here
+            ctx = fg.Context.from_dict(dict(w.params, n_q=26))
+            row = dict(graph=name, replicate=rep, n_v=w.graph.n)
+            for fam in (1, 2):
+                p = fg.Plan(ctx, rp, col, val, w.graph.n, w.meta["dims"], w.weights, family=fam, activation=True)
+                row["t"] = p.ficgcn_plan_info()[1]["t"]
+                row["family%d_rot" % fam] = agg_rotations(p, 1)
+            for th in thetas:
+                p = fg.Plan(ctx, rp, col, val, w.graph.n, w.meta["dims"], w.weights, family=3, activation=True,
+                            cpoo=th)
+                st = p.ficgcn_plan_radix2_stats(1)
+                row["radix2_cpoo%s" % th] = dict(rot=st["rotations"], depth=st["depth"], masks=st["masks"],
+                                                 moved=st["moved"])
+            for aoo in (True, False):
+                for th in (0.0, 0.25):
+                    p = fg.Plan(ctx, rp, col, val, w.graph.n, w.meta["dims"], w.weights, family=3,
+                                activation=True, t=1, cpoo=th, aoo=aoo)
+                    st = p.ficgcn_plan_radix2_stats(1)
+                    row["t1_aoo%d_cpoo%s" % (aoo, th)] = dict(rot=st["rotations"], depth=st["depth"])
+            ablation.append(row)
+            log("ablation %s/%d: %s" % (name, rep, row))
+    summary = {}
+    for name in ("cora", "citeseer", "pubmed"):
+        rows = [r for r in ablation if r["graph"] == name]
+        base = np.mean([r["radix2_cpoo0.0"]["rot"] for r in rows])
+        summary[name] = dict(
+            radix2_rot=round(float(base), 1),
+            cpoo_rot_pruned={str(th): round(1.0 - float(np.mean([r["radix2_cpoo%s" % th]["rot"] for r in rows])) / base, 3)
+                             for th in thetas[1:]},
+            depth={str(th): round(float(np.mean([r["radix2_cpoo%s" % th]["depth"] for r in rows])), 2)
+                   for th in thetas},
+            aoo_rot_pruned_t1=round(1 - float(np.mean([r["t1_aoo1_cpoo0.0"]["rot"] for r in rows])) /
+                                    float(np.mean([r["t1_aoo0_cpoo0.0"]["rot"] for r in rows])), 3),
+            family1_rot=round(float(np.mean([r["family1_rot"] for r in rows])), 1),
+            family2_rot=round(float(np.mean([r["family2_rot"] for r in rows])), 1))
+    log("ablation summary: %s" % summary)
+
+    # timing on the GPU: layer 2 of the citation-graph shape on a deep chain
+    w = make_workload("cora_deep")
+    rp, col, val = graph.normalize(w.graph.n, w.neighbors, w.norm)
+    ctx = fg.Context.from_dict(w.params)
+    prm = w.params
+    N = 1 << prm["log_n"]
+    ctx.ckks_ntt_autotune(prm["n_q"] + prm["n_p"])
+    forms = [("bsgs", dict(family=2)), ("radix2", dict(family=3)), ("radix2_cpoo0.25", dict(family=3, cpoo=0.25))]
+    plans = {k: fg.Plan(ctx, rp, col, val, w.graph.n, w.meta["dims"], w.weights, activation=True, **kw)
+             for k, kw in forms}
+    steps = sorted(set().union(*[set(p.ficgcn_plan_rot_steps()) for p in plans.values()]))
+    t0 = time.perf_counter()
+    cl, ev = ctx.ckks_keygen(7, steps, with_relin=True)
+    torch.cuda.synchronize()
+    log("%d rotation keys generated in %.1f s" % (len(steps), time.perf_counter() - t0))
+    d1 = plans["bsgs"].ficgcn_plan_info()[1]
+    lv_in = d1["level_in"]
+    # the layer's inputs as the first layer leaves them: squared (scale Delta^2,
+    # rescale pending), one column per ciphertext in the plan's node order
+    rng = np.random.default_rng(3)
+    pi = plans["bsgs"].ficgcn_plan_node_order()
+    for p in plans.values():
+        assert np.array_equal(p.ficgcn_plan_node_order(), pi)
+    z = rng.uniform(-1, 1, (w.graph.n, d1["f_in"]))
+    rows = np.zeros((d1["f_in"], N // 2))
+    rows[:, pi] = z.T
+    pts = ctx.ckks_encode_batch(rows, 2.0 ** prm["log_scale"], lv_in)
+    ins = []
+    for i in range(d1["f_in"]):
+        c = ctx.ckks_encrypt(cl, pts[i], lv_in, 99, i)
+        ins.append(ctx.ckks_mul_relin(ev, c, c, lv_in))
+    ref = fp64_gcn(rp, col, val, z * z, [w.weights[1]])
+    res = {}
+    for k, p in plans.items():
+        d = p.ficgcn_plan_info()[1]
+        p.ficgcn_plan_encode()
+        outs = [ctx.ct_buffer(lv_in) for _ in range(d["n_out_cts"])]
+        p.ficgcn_gcn_layer(ev, 1, ins, outs, mode=2)
+        for _ in range(args.warmup):
+            p.ficgcn_gcn_layer(ev, 1, ins, outs, mode=2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            p.ficgcn_gcn_layer(ev, 1, ins, outs, mode=2)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        words = [ctx.ckks_poly_store(x, d["level_out"], 2) for x in outs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.ficgcn_gcn_layer(ev, 1, ins, outs, mode=0)
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - t0) * 1e3
+        same = all(np.array_equal(a, ctx.ckks_poly_store(x, d["level_out"], 2)) for a, x in zip(words, outs))
+        slots = [np.real(ctx.ckks_decrypt(cl, x, d["level_out"], d["scale_out"], N // 2)) for x in outs]
+        y = graph.read_output(pi, slots, d["f_out"], d["t"], d["B"], True)
+        res[k] = dict(ms=round(ms, 3), plain_ms=round(plain_ms, 3), plain_equals_batched=same,
+                      rotations=agg_rotations(p, 1), level_in=lv_in, level_out=d["level_out"],
+                      masks=p.ficgcn_plan_operand_count(1), keys=len(p.ficgcn_plan_rot_steps()),
+                      max_rel_err=float(np.max(np.abs(y - ref)) / np.max(np.abs(ref))))
+        log("%s: %.2f ms per layer (graph replay), plain %.1f ms, words equal %s, %d rotations, levels %d->%d"
+            % (k, ms, plain_ms, same, res[k]["rotations"], lv_in, d["level_out"]))
+        log("%s: max rel err vs FP64 %.3e" % (k, res[k]["max_rel_err"]))
+    out = dict(metric="radix-2 SpIntra-CA (per-round masks, CPOO, AOO): layer latency, rotations, levels",
+               unit="ms", value=res["radix2_cpoo0.25"]["ms"], higher_is_better=False, n_gpus=1, steps=args.steps,
+               warmup=args.warmup, dtype="u64", data="synthetic",
+               config=dict(workload="second layer (16 -> 7, x^2) of the citation-graph shape (2708 nodes, "
+                           "4 sampled neighbours + self, NOO, t=8) on CKKS N=2^16 with 18+2 primes, 16 input "
+                           "ciphertexts resident", form="batched, HIP-graph replay"),
+               layer2=res, ablation_summary=summary, ablation=ablation,
+               seconds=round(time.perf_counter() - t_all, 1))
     print(json.dumps(out), flush=True)
 
 

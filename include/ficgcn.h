@@ -187,6 +187,8 @@ typedef struct {
   int32_t activation;   /* x^2 after every layer */
   int32_t t;            /* SpIntra-CA packing: columns per ciphertext, a power of two no larger than
                            next_pow2(F') and M / next_pow2(n_v); 0 = the paper's rule (Sec. 3.2, App. B) */
+  int32_t aoo_off;      /* family 3 with t = 1: route each shift pi(u) - pi(v) as it is instead of the
+                           shorter way round the ring (AOO, Sec. 3.3.1, off: for its ablation) */
   double cpoo;          /* family 3: CPOO sparsity threshold in [0, 1] (Sec. 3.3.1; the paper's ablation,
                            Sec. 4.2.2, finds 0.2-0.3 best); 0 = CPOO off */
 } ficgcn_plan_opts;

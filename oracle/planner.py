@@ -332,7 +332,8 @@ def rotation_steps_of(lp: LayerPlan) -> List[int]:
 
 def build_plan(n_v: int, rows, dims: Sequence[int], activation: bool, M: int,
                use_noo: bool = True, TH: Optional[int] = None, family: Optional[int] = None,
-               first_mode: str = "inter", t: Optional[int] = None, cpoo: Optional[float] = None) -> Plan:
+               first_mode: str = "inter", t: Optional[int] = None, cpoo: Optional[float] = None,
+               aoo: bool = True) -> Plan:
     """The executable plan: layer 1 by `first_mode` ("inter" per the paper's
     first-layer rule, or "spintra"), later layers SpIntra-CA; SpIntra layers
     combine first (F -> F' at one column per ciphertext), pack t = min(pow2(F'),
@@ -340,7 +341,8 @@ def build_plan(n_v: int, rows, dims: Sequence[int], activation: bool, M: int,
     A given t (a power of two no larger than pow2(F') of every SpIntra layer
     and M / pow2(n_v)) replaces that rule for every SpIntra layer.
     family: None = the cheaper of 1 and 2 by rotation count; 3 = the paper's
-    radix-2 routing (Sec. 3.3), with CPOO at threshold `cpoo` when given."""
+    radix-2 routing (Sec. 3.3), with CPOO at threshold `cpoo` when given;
+    aoo=False takes its shifts unreduced around the ring (the AOO ablation)."""
     n_layers = len(dims) - 1
     if first_mode == "spintra" and n_layers > 1:
         raise ValueError("a SpIntra-CA layer leaves packed ciphertexts; only the last layer may be SpIntra-CA "
@@ -385,7 +387,7 @@ def build_plan(n_v: int, rows, dims: Sequence[int], activation: bool, M: int,
             G, c2 = bsgs_split(shifts, Bl)
             c1 = len(set(shifts) - {0})
             fam = family if family is not None else (2 if c2 < c1 else 1)
-            prog = radix2.build_program(pi, rows, M, Bl, wrap, cpoo) if fam == 3 else None
+            prog = radix2.build_program(pi, rows, M, Bl, wrap and aoo, cpoo) if fam == 3 else None
             pack = [-(l % t_l) * Bl for l in range(f_out) if l % t_l != 0]
             layers.append(LayerPlan("spintra", f_in, f_out, activation, t=t_l, B=Bl, shifts=shifts,
                                     family=fam, G=G, pack_steps=sorted(set(pack)), program=prog,

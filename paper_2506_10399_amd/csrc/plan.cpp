@@ -517,7 +517,7 @@ void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_la
       if (lp.family == 3) {
         if (!(o.cpoo >= 0.0 && o.cpoo <= 1.0)) FICGCN_THROW(EPLAN_, "CPOO threshold must lie in [0, 1]");
         lp.cpoo = o.cpoo;
-        build_radix2(p->pi, p->rowptr, p->col, p->val, M, lp.B, wrap, o.cpoo, lp.r2);
+        build_radix2(p->pi, p->rowptr, p->col, p->val, M, lp.B, wrap && !o.aoo_off, o.cpoo, lp.r2);
       }
       std::set<int64_t> pk;
       for (int l = 0; l < lp.f_out; ++l)

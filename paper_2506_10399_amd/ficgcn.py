@@ -37,7 +37,7 @@ class CkksParams(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("first_mode", ctypes.c_int32), ("use_noo", ctypes.c_int32), ("family", ctypes.c_int32),
                 ("TH", ctypes.c_int32), ("activation", ctypes.c_int32), ("t", ctypes.c_int32),
-                ("cpoo", ctypes.c_double)]
+                ("aoo_off", ctypes.c_int32), ("cpoo", ctypes.c_double)]
 
 
 class SearchStats(ctypes.Structure):
@@ -391,7 +391,7 @@ class Plan:
 
     def __init__(self, ctx: Context, rowptr, col, val, n_v: int, dims: Sequence[int], weights,
                  first_mode: int = 0, use_noo: bool = True, family: int = 0, TH: int = 0, activation: bool = False,
-                 t: int = 0, cpoo: float = 0.0, opts: "PlanOpts" = None):
+                 t: int = 0, cpoo: float = 0.0, aoo: bool = True, opts: "PlanOpts" = None):
         self.ctx = ctx
         self._rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
         self._col = np.ascontiguousarray(col, dtype=np.int32)
@@ -400,7 +400,8 @@ class Plan:
         self._w = [np.ascontiguousarray(w, dtype=np.float64) for w in weights]
         wp = _ptr_array(self._w)
         if opts is None:
-            opts = PlanOpts(first_mode, int(use_noo), family, TH, int(activation), t, cpoo)
+            opts = PlanOpts(first_mode=first_mode, use_noo=int(use_noo), family=family, TH=TH,
+                            activation=int(activation), t=t, aoo_off=int(not aoo), cpoo=cpoo)
         self.opts = opts
         h = c_vp()
         _check(lib().ficgcn_plan_create(ctx.h, _ptr(self._rowptr), _ptr(self._col), _ptr(self._val), n_v,

@@ -204,6 +204,9 @@ def test_exhaustive_search_no_worse_than_paper_rule(fg, name):
 
 @pytest.mark.parametrize("name,mode,cpoo,kw", [
     ("tiny_deep", "spintra", None, {}), ("tiny_deep", "spintra", 0.25, {}), ("tiny_deep", "spintra", 0.3, {"t": 1}),
+    # nodes filling most of the ring (t = 1): AOO changes the routing
+    ("tiny_deep", "spintra", 0.25, {"t": 1, "aoo": False, "n_nodes": 3000, "n_q": 20}),
+    ("tiny_deep", "spintra", None, {"t": 1, "n_nodes": 3000, "n_q": 20}),
     ("tiny2_deep", "inter", None, {}), ("tiny2_deep", "inter", 0.25, {}),
     ("cora_deep", "inter", 0.25, {"dims": [24, 16, 7]}),
 ])
@@ -212,16 +215,17 @@ def test_radix2_plan_matches_oracle(fg, name, mode, cpoo, kw):
     rotation counts, levels, every mask's slots, level and scale, the keys."""
     from paper_2506_10399_amd import graph
     from oracle import radix2
-    t = kw.get("t")
-    w = make_workload(name, **{k: v for k, v in kw.items() if k != "t"})
-    prm = Params.from_dict(w.params)
+    t, aoo = kw.get("t"), kw.get("aoo", True)
+    w = make_workload(name, **{k: v for k, v in kw.items() if k not in ("t", "aoo", "n_q")})
+    params = dict(w.params, n_q=kw.get("n_q", w.params["n_q"]))
+    prm = Params.from_dict(params)
     rows = gcn.normalized_rows(w.graph.n, w.neighbors, w.norm)
     o = planner.build_plan(w.graph.n, rows, w.meta["dims"], w.activation, prm.M, family=3, first_mode=mode,
-                           cpoo=cpoo, t=t)
+                           cpoo=cpoo, t=t, aoo=aoo)
     rp, col, val = graph.normalize(w.graph.n, w.neighbors, w.norm)
-    ctx = fg.Context.from_dict(w.params)
+    ctx = fg.Context.from_dict(params)
     p = fg.Plan(ctx, rp, col, val, w.graph.n, w.meta["dims"], w.weights, first_mode=0 if mode == "inter" else 1,
-                family=3, activation=w.activation, t=t or 0, cpoo=cpoo or 0.0)
+                family=3, activation=w.activation, t=t or 0, cpoo=cpoo or 0.0, aoo=aoo)
     assert np.array_equal(p.ficgcn_plan_node_order(), o.pi.astype(np.int32))
     sched = ex.schedule(prm, o)
     info = p.ficgcn_plan_info()
