@@ -146,6 +146,9 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="instead: a Poisson stream of encrypted GCN requests through the server (rate sweep)")
     ap.add_argument("--requests", type=int, default=10)
+    ap.add_argument("--ntu", action="store_true",
+                    help="instead: the 3-layer x^2 GCN (3-64-128-128) on the multi-frame skeleton shape "
+                         "(25 joints x 256 frames, N=2^14)")
     ap.add_argument("--radix2", action="store_true",
                     help="instead: the paper's radix-2 SpIntra-CA (per-round masks, CPOO, AOO): rotation/level "
                          "ablation on synthetic graphs and the second layer of the citation-graph shape on a deep "
@@ -160,6 +163,9 @@ def main():
         return
     if args.radix2:
         radix2_bench(args)
+        return
+    if args.ntu:
+        ntu_bench(args)
         return
 
     import torch
@@ -459,6 +465,92 @@ def serving_bench(args):
                runs=runs, max_rel_err=err,
                requests=[dict(name=q.name, latency_ms=round(q.result["latency_ms"], 2),
                               footprint_gb=round(q.result["footprint_bytes"] / 1e9, 2)) for q in reqs])
+    print(json.dumps(out), flush=True)
+
+
+def ntu_bench(args):
+    """The action-recognition shape of the paper's evaluation (Sec. 4.1): a
+    25-joint skeleton graph (seeded random tree, degree <= 4, symmetric
+    normalisation with self loops) over 256 frames as disjoint copies (6400
+    nodes), 3-dimensional joint features U[-1, 1], a 3-layer x^2 GCN
+    3-64-128-128 with N(0, 1/F) weights; CKKS N = 2^14, 10 x 50-bit + 2 x
+    60-bit primes.  Layer 1 is Inter-CA over the client's copies (K = 5),
+    layers 2 and 3 SpIntra-CA at one column per ciphertext (6400 nodes fill
+    the 8192 slots).  Two plans: the paper's rule (NOO) and the analytic
+    judge's exhaustive search.  A step is one whole inference (HIP-graph
+    replay of every layer); the plain form's words must equal it."""
+    import torch
+    from paper_2506_10399_amd import ficgcn as fg, graph
+    from workload import make_workload
+    torch.cuda.set_device(0)
+    w = make_workload("ntu")
+    dims = w.meta["dims"]
+    rp, col, val = graph.normalize(w.graph.n, w.neighbors, w.norm)
+    ctx = fg.Context.from_dict(w.params)
+    prm = w.params
+    N = 1 << prm["log_n"]
+    M = N // 2
+    lv0 = prm["n_q"] - 1
+    ctx.ckks_ntt_autotune(prm["n_q"] + prm["n_p"])
+    base = fg.PlanOpts(0, 1, 0, 0, 1, 0)
+    best, st = fg.ficgcn_plan_search(ctx, rp, col, val, w.graph.n, dims, w.weights, base)
+    plans = {"paper_rule": fg.Plan(ctx, rp, col, val, w.graph.n, dims, w.weights, activation=True),
+             "searched": fg.Plan(ctx, rp, col, val, w.graph.n, dims, w.weights, opts=best)}
+    steps = sorted(set().union(*[set(p.ficgcn_plan_rot_steps()) for p in plans.values()]))
+    cl, ev = ctx.ckks_keygen(7, steps, with_relin=True)
+    ref = fp64_gcn(rp, col, val, w.x, w.weights)
+    res = {}
+    for k, p in plans.items():
+        info = p.ficgcn_plan_info()
+        K, F = info[0]["K"], info[0]["f_in"]
+        pi = p.ficgcn_plan_node_order()
+        rows = graph.client_slots(pi, w.x, M, p.ficgcn_plan_copy_sources(0))
+        pts = ctx.ckks_encode_batch(rows, 2.0 ** prm["log_scale"], lv0)
+        ins = [ctx.ckks_encrypt(cl, pts[i], lv0, 1234, i) for i in range(K * F)]
+        p.ficgcn_plan_encode()
+        outs = [[ctx.ct_buffer(d["level_in"]) for _ in range(d["n_out_cts"])] for d in info]
+
+        def step(mode):
+            cur = ins
+            for li in range(len(info)):
+                p.ficgcn_gcn_layer(ev, li, cur, outs[li], mode=mode)
+                cur = outs[li]
+
+        step(2)
+        for _ in range(args.warmup):
+            step(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(2)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        d = info[-1]
+        words = [ctx.ckks_poly_store(x, d["level_out"], 2) for x in outs[-1]]
+        slots = [np.real(ctx.ckks_decrypt(cl, x, d["level_out"], d["scale_out"], M)) for x in outs[-1]]
+        y = graph.read_output(pi, slots, d["f_out"], d["t"], d["B"], True)
+        err = float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step(0)
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - t0) * 1e3
+        same = all(np.array_equal(a, ctx.ckks_poly_store(x, d["level_out"], 2)) for a, x in zip(words, outs[-1]))
+        rots = [0] + [agg_rotations(p, li) * info[li]["n_out_cts"] for li in range(1, len(info))]
+        n_ks = sum(rots) + sum(x["n_out_cts"] for x in info)
+        res[k] = dict(ms=round(ms, 3), plain_ms=round(plain_ms, 3), speedup_vs_plain=round(plain_ms / ms, 2),
+                      plain_equals_batched=same, max_rel_err=err, use_noo=int(p.opts.use_noo),
+                      family=[x["family"] for x in info], shifts=[x["n_shifts"] for x in info],
+                      rotations=rots, key_switches=n_ks, key_switches_per_s=round(n_ks / (ms * 1e-3), 1))
+        log("%s: %.2f ms per inference (graph replay), plain %.1f ms, words equal %s, err %.2e, %s"
+            % (k, ms, plain_ms, same, err, res[k]))
+    best_k = min(res, key=lambda k: res[k]["ms"])
+    out = dict(metric="encrypted 3-layer GCN latency, multi-frame skeleton shape", unit="ms",
+               value=res[best_k]["ms"], higher_is_better=False, n_gpus=1, steps=args.steps, warmup=args.warmup,
+               dtype="u64", data="synthetic",
+               config=dict(workload="25-joint skeleton x 256 frames (6400 nodes), 3-64-128-128 x^2 GCN, "
+                           "CKKS N=2^14 10+2 primes, 15 input cts resident", form="batched, HIP-graph replay"),
+               plans=res, judge_bytes=dict(searched=st.best_cost, paper_rule=plans["paper_rule"].ficgcn_plan_cost()))
     print(json.dumps(out), flush=True)
 
 

@@ -337,7 +337,8 @@ def build_plan(n_v: int, rows, dims: Sequence[int], activation: bool, M: int,
     """The executable plan: layer 1 by `first_mode` ("inter" per the paper's
     first-layer rule, or "spintra"), later layers SpIntra-CA; SpIntra layers
     combine first (F -> F' at one column per ciphertext), pack t = min(pow2(F'),
-    M / pow2(n_v)) columns per ciphertext, then aggregate on the packed layout.
+    M / pow2(n_v)) columns per ciphertext, then aggregate on the packed layout
+    (t = 1 for every SpIntra layer when one of them feeds another layer).
     A given t (a power of two no larger than pow2(F') of every SpIntra layer
     and M / pow2(n_v)) replaces that rule for every SpIntra layer.
     family: None = the cheaper of 1 and 2 by rotation count; 3 = the paper's
@@ -347,9 +348,14 @@ def build_plan(n_v: int, rows, dims: Sequence[int], activation: bool, M: int,
     if first_mode == "spintra" and n_layers > 1:
         raise ValueError("a SpIntra-CA layer leaves packed ciphertexts; only the last layer may be SpIntra-CA "
                          "when it is also the first")
-    # packing of the SpIntra layers fixes the block the node order must fit
-    spin_f = [dims[i + 1] for i in range(n_layers) if i > 0 or first_mode == "spintra"]
+    # packing of the SpIntra layers fixes the block the node order must fit; a
+    # SpIntra layer that feeds another layer leaves one column per ciphertext
+    # (the next combination reads columns), so then every SpIntra layer packs t = 1
+    spin = [i for i in range(n_layers) if i > 0 or first_mode == "spintra"]
+    spin_f = [dims[i + 1] for i in spin]
     t_pack = min([next_pow2(f) for f in spin_f] + [M // next_pow2(n_v)]) if spin_f else 1
+    if any(i < n_layers - 1 for i in spin):
+        t_pack = 1
     if t is not None and spin_f:
         if t < 1 or t & (t - 1) or t > t_pack:
             raise ValueError("packing t must be a power of two no larger than %d" % t_pack)
@@ -379,7 +385,7 @@ def build_plan(n_v: int, rows, dims: Sequence[int], activation: bool, M: int,
                         k += 1
             layers.append(LayerPlan("inter", f_in, f_out, activation, K=K, copy_src=src, copy_val=val))
         else:
-            t_l = t_pack if t is not None else min(next_pow2(f_out), M // next_pow2(n_v))
+            t_l = t_pack
             Bl = M // t_l
             wrap = Bl == M
             shifts = sorted({reduce_shift(int(pi[u] - pi[v]), M, wrap) for v, row in enumerate(rows)

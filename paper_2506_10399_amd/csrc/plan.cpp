@@ -5,7 +5,8 @@
 // Aggregation mode (Sec. 3.3.2): the first layer is Inter-CA over the
 // client's neighbour copies; later layers are SpIntra-CA: combination first
 // (one column per ciphertext), packing of t = min(pow2(F'), M / pow2(n_v))
-// columns, then routing of every nonzero A_vu by its shift pi(u) - pi(v) in
+// columns (t = 1 for every SpIntra-CA layer when one of them feeds another
+// layer), then routing of every nonzero A_vu by its shift pi(u) - pi(v) in
 // the diagonal form (one rotation + mask per distinct shift, all rotations
 // hoisted on one ModUp), the baby-step/giant-step form, or the paper's
 // radix-2 form with per-round masks (radix2.cpp).
@@ -441,13 +442,18 @@ void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_la
   if (o.first_mode == 1 && n_layers > 1)
     FICGCN_THROW(EPLAN_, "a SpIntra-CA first layer is only supported for one-layer models");
   std::vector<int> spin_f;
+  bool chained = false;     // a SpIntra-CA layer feeds another layer: its outputs stay one column each
   for (uint32_t i = 0; i < n_layers; ++i)
-    if (i > 0 || o.first_mode == 1) spin_f.push_back((int)dims[i + 1]);
+    if (i > 0 || o.first_mode == 1) {
+      spin_f.push_back((int)dims[i + 1]);
+      chained |= i + 1 < n_layers;
+    }
   int t_pack = 1;
   if (!spin_f.empty()) {
     t_pack = M / next_pow2(n);
     for (int f : spin_f) t_pack = std::min(t_pack, next_pow2(f));
   }
+  if (chained) t_pack = 1;
   if (t_pack < 1) FICGCN_THROW(EPLAN_, "graph larger than the slot count");
   if (o.t != 0 && !spin_f.empty()) {
     if (o.t < 1 || (o.t & (o.t - 1)) || o.t > t_pack)
@@ -502,7 +508,7 @@ void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_la
         }
       }
     } else {
-      lp.t = o.t != 0 ? t_pack : std::min(next_pow2(lp.f_out), M / next_pow2(n));
+      lp.t = t_pack;
       lp.B = M / lp.t;
       const bool wrap = lp.B == M;
       std::set<int64_t> sh;

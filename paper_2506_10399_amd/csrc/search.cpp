@@ -38,7 +38,10 @@ static int ilog2(int x) {
 static int t_max_of(uint32_t n_v, const uint32_t* dims, uint32_t n_layers, int M, int first_mode) {
   int t = 0;
   for (uint32_t i = 0; i < n_layers; ++i)
-    if (i > 0 || first_mode == 1) t = t == 0 ? next_pow2i((int)dims[i + 1]) : std::min(t, next_pow2i((int)dims[i + 1]));
+    if (i > 0 || first_mode == 1) {
+      if (i + 1 < n_layers) return 1;   // a SpIntra-CA layer feeding another keeps one column per ciphertext
+      t = t == 0 ? next_pow2i((int)dims[i + 1]) : std::min(t, next_pow2i((int)dims[i + 1]));
+    }
   if (t == 0) return 1;
   return std::min(t, M / next_pow2i((int)n_v));
 }
@@ -206,6 +209,32 @@ static double plan_bytes(const ficgcn_plan* p) {
       for (int g = 0; g < np; ++g) {
         const int cols = std::min(lp.f_out, (g + 1) * lp.t) - g * lp.t;
         bytes += (cols - 1) * ks_single(la);
+      }
+      if (lp.family == 3) {
+        // radix-2 program: every term one masked product at its step's level, every
+        // distinct (register, amount) one hoisted switch (one ModUp per register),
+        // a rescale per register and per result level, the result terms summed
+        const R2Program& r2 = lp.r2;
+        double per = mask(la);
+        std::set<std::pair<int, int64_t>> seen;
+        std::set<int> upped;
+        for (const R2Step& st : r2.steps) {
+          const int lv = la - st.depth;
+          for (const auto* v : {&st.keep, &st.fin})
+            for (const R2Term& t : *v) {
+              per += mask(lv);
+              if (t.m && seen.insert({st.src, t.m}).second) {
+                per += ks_extra(lv);
+                if (upped.insert(st.src).second) per += modup(lv);
+              }
+            }
+        }
+        for (size_t r = 1; r < r2.reg_depth.size(); ++r) per += rs(la - r2.reg_depth[r] + 1);
+        for (int d = 0; d < r2.depth; ++d) per += rs(la - d) + limb * 2.0 * (la - r2.depth + 1);
+        bytes += np * per;
+        n_out_cts = np;
+        if (lp.act) bytes += n_out_cts * (ks_single(lp.level_out) + limb * 5.0 * (lp.level_out + 1));
+        continue;
       }
       const size_t ns = lp.shifts.size();
       std::set<int64_t> babies, giants;

@@ -196,3 +196,25 @@ def test_radix2_library_encoder_end_to_end():
     slots = [np.real(ctx.ckks_decrypt(e["cl"], x, d["level_out"], d["scale_out"], prm.M)) for x in outs]
     y = e["graph"].read_output(p.ficgcn_plan_node_order(), slots, lp.f_out, lp.t, lp.B, True)
     assert gcn.max_rel_error(y, e["ref"][-1]) < 1e-3
+
+
+def test_three_layer_model_bit_exact_all_forms():
+    """A three-layer x^2 GCN (multi-frame skeleton shape, 3-16-16-8): the
+    SpIntra-CA layers chain one column per ciphertext; plain, batched and
+    graph forms give the oracle's words at every layer, and the decrypted
+    output is within 1e-3 of FP64."""
+    e = _setup("ntu_small", "inter")
+    _load_operands(e)
+    assert len(e["o"].layers) == 3
+    for m in (0, 1, 2, 2):
+        res = _run_gpu(e, m)
+        for li, ((outs, lvo), want) in enumerate(zip(res, e["outs"])):
+            for g, (x, b) in enumerate(zip(outs, want)):
+                got = e["ctx"].ckks_poly_store(x, lvo, 2)
+                assert np.array_equal(got, _ct(b)), ("form", m, "layer", li, "ct", g)
+    lp = e["o"].layers[-1]
+    info = e["p"].ficgcn_plan_info()[-1]
+    slots = [np.real(e["ctx"].ckks_decrypt(e["cl"], x, info["level_out"], info["scale_out"], e["prm"].M))
+             for x in res[-1][0]]
+    y = e["graph"].read_output(e["o"].pi, slots, lp.f_out, lp.t, lp.B, True)
+    assert gcn.max_rel_error(y, e["ref"][-1]) < 1e-3

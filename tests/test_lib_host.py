@@ -74,6 +74,8 @@ def _plans(fg, name, mode, noo, family, t=None, TH=None, **kw):
     ("tiny2", "inter", True, 2, {"t": 1}), ("tiny2", "inter", True, 1, {"t": 4, "TH": 64}),
     ("tiny", "spintra", False, 2, {"t": 2}),
     ("cora", "inter", True, 1, {"dims": [24, 16, 7], "t": 2, "TH": 256}),
+    # three layers: every SpIntra-CA layer packs one column per ciphertext
+    ("ntu_small", "inter", True, None, {}), ("ntu_small", "inter", False, 2, {}), ("ntu", "inter", False, None, {}),
 ])
 def test_plan_matches_oracle(fg, name, mode, noo, family, kw):
     w, prm, rows, o, p = _plans(fg, name, mode, noo, family, **kw)

@@ -12,7 +12,7 @@ from typing import Dict, List, Optional
 
 import numpy as np
 
-from .graphs import Graph, erdos_renyi, chung_lu, dc_sbm, sample_neighbors
+from .graphs import Graph, erdos_renyi, chung_lu, dc_sbm, sample_neighbors, skeleton_frames
 from .features import (binary_features, uniform_features, tfidf_features,
                        gaussian_weights)
 
@@ -40,6 +40,16 @@ CONFIGS: Dict[str, dict] = {
     "cora_deep": dict(id=9, log_n=16, n_q=18, q_bits=50, n_p=2, p_bits=60, log_scale=40,
                       graph=("chung_lu", 2708, 3.9), norm="mean", n_sample=4,
                       features=("binary", 1433, 0.013), dims=[1433, 16, 7], activation=True),
+    # Action-recognition shape: 25-joint skeleton over 256 frames (6400 nodes),
+    # 3-dimensional joint features, 3-layer x^2 GCN 3-64-128-128, N = 2^14.
+    # Weights N(0, 1/F) keep the three squared layers at magnitudes near 1.
+    "ntu": dict(id=10, log_n=14, n_q=10, q_bits=50, n_p=2, p_bits=60, log_scale=40,
+                graph=("skeleton", 25, 256), norm="sym", n_sample=None,
+                features=("uniform", 3), dims=[3, 64, 128, 128], activation=True, w_std="fan_in"),
+    # The same model on 8 frames at N = 2^13: the small case of the 3-layer path.
+    "ntu_small": dict(id=11, log_n=13, n_q=10, q_bits=50, n_p=2, p_bits=60, log_scale=40,
+                      graph=("skeleton", 25, 8), norm="sym", n_sample=None,
+                      features=("uniform", 3), dims=[3, 16, 16, 8], activation=True, w_std="fan_in"),
     # Citation-graph shape: 2708 nodes, 1433 binary features, 2-layer x^2 GCN.
     "cora": dict(id=2, log_n=16, n_q=8, q_bits=50, n_p=2, p_bits=60, log_scale=40,
                  graph=("chung_lu", 2708, 3.9), norm="mean", n_sample=4,
@@ -70,6 +80,8 @@ class Workload:
 
 def _graph(spec, seed: int) -> Graph:
     kind, n, deg = spec
+    if kind == "skeleton":
+        return skeleton_frames(n, int(deg), seed)
     if kind == "er":
         return erdos_renyi(n, deg, seed)
     if kind == "chung_lu":
@@ -103,7 +115,8 @@ def make_workload(name: str, replicate: int = 0, n_nodes: Optional[int] = None,
         x = tfidf_features(g.n, dims[0], fspec[2], base * 10 + 2)
     else:
         raise ValueError(fspec)
-    ws = [gaussian_weights(dims[i], dims[i + 1], base * 10 + 3 + i)
+    ws = [gaussian_weights(dims[i], dims[i + 1], base * 10 + 3 + i,
+                           std=dims[i] ** -0.5 if cfg.get("w_std") == "fan_in" else 0.1)
           for i in range(len(dims) - 1)]
     params = {k: cfg[k] for k in ("log_n", "n_q", "q_bits", "n_p", "p_bits", "log_scale")}
     return Workload(name=name, params=params, graph=g, neighbors=nbrs, norm=cfg["norm"],

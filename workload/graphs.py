@@ -135,3 +135,24 @@ def sample_neighbors(g: Graph, n_sample: int, seed: int) -> List[np.ndarray]:
             pick = rng.choice(len(a), size=n_sample, replace=False)
             out.append(np.sort(a[pick]))
     return out
+
+
+def skeleton_frames(n_joints: int, n_frames: int, seed: int, max_degree: int = 4) -> Graph:
+    """A multi-frame skeleton graph: one seeded random tree of n_joints joints
+    (each joint attached to a uniformly chosen earlier joint with fewer than
+    max_degree bones), repeated over n_frames frames as disjoint copies; node
+    f * n_joints + j is joint j of frame f.  The shape of the paper's
+    action-recognition workload (Sec. 4.1: 25 joints, 256 frames) without
+    any of its data."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    deg = np.zeros(n_joints, dtype=np.int64)
+    bones = []
+    for j in range(1, n_joints):
+        cand = [i for i in range(j) if deg[i] < max_degree]
+        i = int(cand[rng.integers(len(cand))])
+        bones.append((i, j))
+        deg[i] += 1
+        deg[j] += 1
+    edges = np.array([(f * n_joints + a, f * n_joints + b) for f in range(n_frames) for a, b in bones],
+                     dtype=np.int64).reshape(-1, 2)
+    return _from_edge_set(n_joints * n_frames, edges, rng, shuffle=False)
