@@ -41,25 +41,35 @@ constexpr uint64_t DIG_C = 0x0080808080808080ull;   // 128 in each of bytes 0..6
 // byte a of the result is digit a as an int8, byte 7 is zero
 __device__ __forceinline__ uint64_t bal_digits(uint64_t x) { return (x + DIG_C) ^ DIG_C; }
 
+// 4 x 4 byte transpose: out[a] byte u = byte a of s[u].  v_perm_b32 picks
+// bytes 0..3 from its second operand and 4..7 from its first.
+__device__ __forceinline__ void byte_transpose(const uint32_t (&s)[4], uint32_t (&o)[4], int n_out) {
+  const uint32_t t0 = __builtin_amdgcn_perm(s[1], s[0], 0x06020400u);   // s0.b0 s1.b0 s0.b2 s1.b2
+  const uint32_t t1 = __builtin_amdgcn_perm(s[1], s[0], 0x07030501u);   // s0.b1 s1.b1 s0.b3 s1.b3
+  const uint32_t t2 = __builtin_amdgcn_perm(s[3], s[2], 0x06020400u);
+  const uint32_t t3 = __builtin_amdgcn_perm(s[3], s[2], 0x07030501u);
+  o[0] = __builtin_amdgcn_perm(t2, t0, 0x05040100u);
+  o[1] = __builtin_amdgcn_perm(t3, t1, 0x05040100u);
+  o[2] = __builtin_amdgcn_perm(t2, t0, 0x07060302u);
+  if (n_out > 3) o[3] = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
+}
+
 // 16 words -> 7 digit planes: plane a, dword w holds digit a of words 4w..4w+3
-__device__ __forceinline__ void digit_planes(const uint64_t (&x)[16], v4i (&A)[7]) {
+// (byte u = word 4w+u); this fills dword w of every plane
+__device__ __forceinline__ void digit_planes_w(const uint64_t (&x)[16], v4i (&A)[7], int w) {
+  uint32_t lo[4], hi[4], o[4];
 #pragma unroll
-  for (int w = 0; w < 4; ++w) {
-    uint32_t lo[4], hi[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const uint64_t d = bal_digits(x[4 * w + u]);
-      lo[u] = (uint32_t)d;
-      hi[u] = (uint32_t)(d >> 32);
-    }
-#pragma unroll
-    for (int a = 0; a < 7; ++a) {
-      const uint32_t* src = a < 4 ? lo : hi;
-      const int sh = (a & 3) * 8;
-      A[a][w] = (int)(((src[0] >> sh) & 0xffu) | (((src[1] >> sh) & 0xffu) << 8) | (((src[2] >> sh) & 0xffu) << 16) |
-                      (((src[3] >> sh) & 0xffu) << 24));
-    }
+  for (int u = 0; u < 4; ++u) {
+    const uint64_t d = bal_digits(x[4 * w + u]);
+    lo[u] = (uint32_t)d;
+    hi[u] = (uint32_t)(d >> 32);
   }
+  byte_transpose(lo, o, 4);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) A[a][w] = (int)o[a];
+  byte_transpose(hi, o, 3);   // byte 7 of a digit word is zero: three planes
+#pragma unroll
+  for (int a = 0; a < 3; ++a) A[4 + a][w] = (int)o[a];
 }
 
 template <bool STRIDED>
@@ -82,30 +92,31 @@ __global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   const Mod m = mods[i];
   const int KK = K > 0 ? K : 1;
   const int n_steps = KK * n_fb;   // (copy, block) steps, block-fastest
-  // Strided inputs are read with buffer loads: a wave-uniform resource per
-  // (copy, feature of lane group 0) in scalar registers and one 32-bit
-  // per-lane byte offset (lane group g, coefficient).  The resource's range
-  // ends after the lane groups whose features exist, so lanes past F read 0.
-  const int lane_bytes = STRIDED ? (int)(((size_t)g * 16 * in_stride + off) * 8) : 0;
-  const size_t grp_bytes = (size_t)16 * in_stride * 8;
-  // A step past the end loads nothing (empty range / no active lane), so the
-  // prefetch is issued unconditionally and the wait counts stay static.
-  auto load_block = [&](uint64_t (&x)[16], int step) {
-    const bool live = step < n_steps;
-    const int k = live ? step / n_fb : 0, fb = live ? step - k * n_fb : 0;
+  // Strided inputs are read with buffer loads: one wave-uniform resource per
+  // step in scalar registers, based at the step's first feature (copy k,
+  // feature 64 fb) and ranging over the features of the block below F, and a
+  // fixed per-lane byte offset per load e: feature 16 g + e of the block,
+  // coefficient `off`.  Features past F, and steps past the end (empty
+  // range), read 0, so the prefetch is issued unconditionally and the wait
+  // counts stay static.
+  const size_t feat_bytes = in_stride * 8;
+  uint32_t voff[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int fu = fb * 64 + e;   // feature of lane group 0
+  for (int e = 0; e < 16; ++e) voff[e] = STRIDED ? (uint32_t)(((size_t)(g * 16 + e) * in_stride + off) * 8) : 0u;
+  auto block_rsrc = [&](int k, int fb, bool live) {
+    const int nf = live ? (F - fb * 64 < 64 ? F - fb * 64 : 64) : 0;
+    const char* b = (const char*)in_base + ((size_t)k * F + (size_t)fb * 64) * feat_bytes;
+    return __builtin_amdgcn_make_buffer_rsrc((void*)b, 0, (int)((size_t)nf * feat_bytes), 0x00020000);
+  };
+  // words e0 .. e0+n-1 of a block
+  auto load_words = [&](uint64_t (&x)[16], __amdgpu_buffer_rsrc_t rs, int k, int fb, bool live, int e0, int n) {
+#pragma unroll
+    for (int e = e0; e < e0 + n; ++e) {
       if (STRIDED) {
-        const int left = live ? F - fu : 0;   // features fu, fu+16, ... below F
-        const int n_grp = left <= 0 ? 0 : (left + 15) / 16 > 4 ? 4 : (left + 15) / 16;
-        const char* b = (const char*)in_base + ((size_t)k * F + fu) * in_stride * 8;
-        const __amdgpu_buffer_rsrc_t rs =
-            __builtin_amdgcn_make_buffer_rsrc((void*)b, 0, (int)(n_grp * grp_bytes), 0x00020000);
-        const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, lane_bytes, 0, 0);
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff[e], 0, 0);
         x[e] = ((uint64_t)w[1] << 32) | w[0];
       } else {
-        const int f = fu + g * 16;
+        const int f = fb * 64 + e + g * 16;
         x[e] = live && f < F ? in_ptrs[(size_t)k * F + f][off] : 0;
       }
     }
@@ -116,7 +127,12 @@ __global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 #pragma unroll
   for (int s = 0; s < 13; ++s) acc[s] = v4i{0, 0, 0, 0};
   uint64_t xa[16], xb[16];
-  load_block(xa, 0);
+  {
+    const auto rs0 = block_rsrc(0, 0, n_steps > 0);
+    load_words(xa, rs0, 0, 0, n_steps > 0, 0, 16);
+  }
+  // (copy, block) of the current step, advanced without divisions
+  int k = 0, fb = 0;
   for (int step = 0; step < n_steps; step += 2) {
     // two steps per iteration so the register buffers alternate statically
 #pragma unroll
@@ -125,8 +141,8 @@ __global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void
       if (st >= n_steps) break;
       uint64_t (&cur)[16] = half ? xb : xa;
       uint64_t (&nxt)[16] = half ? xa : xb;
-      const int k = st / n_fb, fb = st - k * n_fb;
       const bool last = fb == n_fb - 1;
+      const int kn = last ? k + 1 : k, fbn = last ? 0 : fb + 1;
       // this step's weight planes (and the copy's plaintext words on its last
       // block) are requested before the next block: loads retire in order, so
       // waiting for them leaves the prefetch in flight
@@ -138,16 +154,29 @@ __global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) pk[rr] = pts.p[k][(size_t)i * N + tile * 16 + 4 * g + rr];
       }
-      // keep the order: these loads, then the prefetch, then the arithmetic
+      // keep the order: these loads, then the prefetch spread over the digit
+      // planes of this block and the first matrix products (two words at a time)
       __builtin_amdgcn_sched_barrier(0);
-      load_block(nxt, st + 1);
-      __builtin_amdgcn_sched_barrier(0);
+      const bool nlive = st + 1 < n_steps;
+      const auto rs = block_rsrc(kn, fbn, nlive);
       v4i A[7];
-      digit_planes(cur, A);
 #pragma unroll
-      for (int b = 0; b < 7; ++b)
+      for (int w = 0; w < 4; ++w) {
+        load_words(nxt, rs, kn, fbn, nlive, 2 * w, 2);
+        __builtin_amdgcn_sched_barrier(0);
+        digit_planes_w(cur, A, w);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int b = 0; b < 7; ++b) {
 #pragma unroll
         for (int a = 0; a < 7; ++a) acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[a], B[b], acc[a + b], 0, 0, 0);
+        if (b < 4) {
+          __builtin_amdgcn_sched_barrier(0);
+          load_words(nxt, rs, kn, fbn, nlive, 8 + 2 * b, 2);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
       if (last) {
         // copy k done: fold the diagonals and add P_k (.) T
 #pragma unroll
@@ -166,6 +195,8 @@ __global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 #pragma unroll
         for (int s = 0; s < 13; ++s) acc[s] = v4i{0, 0, 0, 0};
       }
+      k = kn;
+      fb = fbn;
     }
   }
   const int n = lane & 15;
