@@ -300,6 +300,36 @@ def rotate(prm: Params, keys: Keys, ct: Ciphertext, k: int) -> Ciphertext:
     return rotate_hoisted(prm, keys, ct, [k])[0]
 
 
+def rotate_masked_sum(prm: Params, keys: Keys, ct: Ciphertext, steps: Sequence[int],
+                      masks_ext: Sequence[np.ndarray]) -> Ciphertext:
+    """sum_k Rot_k(ct) (.) m_k for nonzero steps k, with the mask products taken
+    on the key-switching basis before a single ModDown (double hoisting):
+    D_j = ModUp_j(c1);  A = sum_k KeyInner(sigma_gk(D)) * m_k  over Q_l and P;
+    out = (ModDown(A_0) + sum_k sigma_gk(c0) * m_k,  ModDown(A_1)).
+    masks_ext[k]: the mask's integer coefficients reduced over Q_l then P
+    (rows = ext_basis).  No rescale; scale = ct.scale * (mask scale)."""
+    lv = ct.level
+    qs = prm.q_level(lv)
+    basis = ext_basis(prm, lv)
+    D = [mod_up(prm, ct.c1, lv, dg) for dg in prm.digits(lv)]
+    a0_terms, a1_terms, c0_terms = [], [], []
+    for k, m in zip(steps, masks_ext):
+        if k % prm.M == 0:
+            raise ValueError("the identity shift is a plain mask product, not a key switch")
+        g = galois_element(k, prm)
+        if g not in keys.rot:
+            raise KeyError("no rotation key for step %d" % k)
+        Dg = [automorph(Dj, g, basis) for Dj in D]
+        acc0, acc1 = _key_inner(prm, Dg, keys.rot[g], lv)
+        a0_terms.append((acc0, m))
+        a1_terms.append((acc1, m))
+        c0_terms.append((automorph(ct.c0, g, qs), m[: lv + 1]))
+    A0 = poly_mul_sum(a0_terms, basis, prm)
+    A1 = poly_mul_sum(a1_terms, basis, prm)
+    c0 = poly_add(mod_down(prm, A0, lv), poly_mul_sum(c0_terms, qs, prm), qs)
+    return Ciphertext(c0=c0, c1=mod_down(prm, A1, lv), level=lv, scale=ct.scale)
+
+
 # ----------------------------------------------------------------------------
 # arithmetic
 # ----------------------------------------------------------------------------

@@ -88,6 +88,13 @@ def encode(prm: Params, z: Sequence[complex], scale: float, level: int) -> Plain
     return Plaintext(m=np.stack([_ffi.from_signed(m, q) for q in mods]), level=level, scale=scale)
 
 
+def encode_ext(prm: Params, z: Sequence[complex], scale: float, level: int) -> np.ndarray:
+    """The same integer coefficients as encode(), reduced over Q_l and then the
+    special primes P (the key-switching basis): rows level + 1 + alpha."""
+    m = round_coeffs(embed_inverse(z, prm.N) * scale)
+    return np.stack([_ffi.from_signed(m, q) for q in prm.q_level(level) + prm.p])
+
+
 def encode_int(prm: Params, m: np.ndarray, level: int, scale: float) -> Plaintext:
     mods = prm.q_level(level)
     return Plaintext(m=np.stack([_ffi.from_signed(np.asarray(m, dtype=np.int64), q) for q in mods]),

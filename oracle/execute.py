@@ -136,6 +136,10 @@ def encode_operands(prm: Params, plan: Plan, weights, sched=None) -> List[dict]:
         if lp.kind == "inter":
             lv = st["level_in"]
             d["P"] = [enc.encode(prm, p, st["sP"], lv) for p in sim.inter_plaintexts(plan, lp)]
+        elif lp.family == 4:
+            lv = st["level_agg"]
+            d["masks"] = [{dd: (enc.encode(prm, v, st["sM"], lv), enc.encode_ext(prm, v, st["sM"], lv))
+                           for dd, v in mk.items()} for mk in mask_vectors(plan, li)]
         elif lp.family == 3:
             lv = st["level_agg"]
             d["masks"] = [[enc.encode(prm, v, float(prm.q[lv - dep]), lv - dep) for dep, v in per_g]
@@ -251,6 +255,15 @@ def aggregate(prm: Params, plan: Plan, li: int, keys, y: ckks.Ciphertext, masks,
     if lp.family == 3:
         return aggregate_radix2(prm, lp, keys, y, masks, st)
     acc = _zero(prm, y.level, y.scale * st["sM"])
+    if lp.family == 4:
+        # Sum_delta Rot_delta(Y) (.) mask_delta with the products on the key
+        # basis and one ModDown; the identity shift is a plain mask product
+        steps = [d for d in lp.shifts if d != 0]
+        out = ckks.rotate_masked_sum(prm, keys, y, steps, [masks[d][1] for d in steps])
+        if 0 in lp.shifts:
+            out = ckks.pt_mul_acc(prm, out, [y], [masks[0][0]])
+        out.scale = y.scale * st["sM"]
+        return ckks.rescale(prm, out)
     if lp.family == 1:
         steps = [d for d in lp.shifts if d != 0]
         rots = dict(zip(steps, ckks.rotate_hoisted(prm, keys, y, steps)))

@@ -262,7 +262,8 @@ class LayerPlan:
     t: int = 1                # columns per packed ciphertext
     B: int = 0                # block = M / t
     shifts: List[int] = field(default_factory=list)      # sorted distinct shifts
-    family: int = 1           # 1 = diagonal, 2 = baby-step/giant-step, 3 = radix-2 per-round masks
+    family: int = 1           # 1 = diagonal, 2 = baby-step/giant-step, 3 = radix-2 per-round masks,
+                              # 4 = diagonal with the mask products before one ModDown (double hoisting)
     G: int = 1                # baby-step count of the family-2 split
     program: object = None    # family 3: the radix-2 program (oracle.radix2.Program)
     cpoo: Optional[float] = None   # family 3: CPOO sparsity threshold (None = off)
@@ -323,7 +324,7 @@ def rotation_steps_of(lp: LayerPlan) -> List[int]:
     """Rotation steps the aggregation uses (nonzero)."""
     if lp.family == 3:
         return lp.program.amounts()
-    if lp.family == 1:
+    if lp.family in (1, 4):
         return sorted(set(lp.shifts) - {0})
     babies = {d % lp.G for d in lp.shifts} - {0}
     giants = {(d // lp.G) * lp.G for d in lp.shifts} - {0}
@@ -432,7 +433,7 @@ def op_counts(plan: Plan) -> dict:
                     c["cmult"] += n_cts
                     c["rescale"] += n_cts
                 continue
-            if lp.family == 1:
+            if lp.family in (1, 4):
                 c["rot"] += n_packed * len(steps)
             else:
                 babies = {d % lp.G for d in lp.shifts} - {0}

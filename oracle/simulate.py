@@ -78,7 +78,7 @@ def aggregate_packed(plan: Plan, lp: LayerPlan, y: np.ndarray, n_cols: int, coun
         return radix2.run_slots(lp.program, y, lp.B, n_cols, counts)
     mk = masks(plan, lp, n_cols)
     out = np.zeros(plan.M)
-    if lp.family == 1:
+    if lp.family in (1, 4):
         for d in lp.shifts:
             out += rot(y, d) * mk[d]
             counts["pmult"] += 1

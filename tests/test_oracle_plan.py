@@ -149,7 +149,7 @@ def test_bsgs_split_covers_every_shift():
 
 @pytest.mark.parametrize("name,mode,noo,fam", [
     ("tiny", "inter", True, None), ("tiny", "spintra", True, 1), ("tiny", "spintra", False, 2),
-    ("tiny2", "inter", True, 1), ("tiny2", "inter", False, 2)])
+    ("tiny", "spintra", True, 4), ("tiny2", "inter", True, 1), ("tiny2", "inter", False, 2)])
 def test_slot_simulator_equals_fp64_gcn(name, mode, noo, fam):
     w, rows = _rows(name)
     ref = gcn.gcn_forward(rows, w.x, w.weights, w.activation)[-1]
@@ -199,12 +199,13 @@ def test_gcn_normalisations():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("name,mode", [("tiny", "inter"), ("tiny", "spintra"), ("tiny2", "inter")])
-def test_encrypted_plan_decrypts_to_fp64_gcn(name, mode):
+@pytest.mark.parametrize("name,mode,fam", [("tiny", "inter", None), ("tiny", "spintra", None), ("tiny", "spintra", 4),
+                                           ("tiny2", "inter", None)])
+def test_encrypted_plan_decrypts_to_fp64_gcn(name, mode, fam):
     w, rows = _rows(name)
     prm = Params.from_dict(w.params)
     ref = gcn.gcn_forward(rows, w.x, w.weights, w.activation)[-1]
-    plan = planner.build_plan(w.graph.n, rows, w.meta["dims"], w.activation, prm.M, first_mode=mode)
+    plan = planner.build_plan(w.graph.n, rows, w.meta["dims"], w.activation, prm.M, first_mode=mode, family=fam)
     keys = ckks.keygen(prm, 11, plan.rot_steps(prm.M), relin=w.activation)
     sched = ex.schedule(prm, plan)
     ops = ex.encode_operands(prm, plan, w.weights, sched)

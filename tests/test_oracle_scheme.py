@@ -148,3 +148,34 @@ def test_switching_key_decrypts_to_gadget(small):
             diff = [(int(a) - int(b)) % m for a, b in zip(lhs[i], want)]
             diff = [d - m if d > m // 2 else d for d in diff]
             assert max(abs(d) for d in diff) <= 21
+
+
+def test_masked_rotation_sum_slots_and_precision(small):
+    """Double hoisting: sum_k Rot_k(ct) (.) m_k with the mask products on the
+    key basis before one ModDown decodes to sum_k roll(z, -k) * m_k, at least
+    as precisely as the form with one ModDown per rotation."""
+    prm, keys = small
+    z = rng.uniform(-1, 1, prm.M)
+    lv = prm.L - 1
+    ct = ckks.encrypt(prm, 3, 0, keys.s, enc.encode(prm, z, prm.scale, lv))
+    steps = [1, 2, -7, 5]
+    ms = [rng.uniform(-1, 1, prm.M) for _ in steps]
+    sM = float(prm.q[lv])
+    out = ckks.rotate_masked_sum(prm, keys, ct, steps, [enc.encode_ext(prm, m, sM, lv) for m in ms])
+    assert out.c0.shape == (lv + 1, prm.N) and out.c1.shape == (lv + 1, prm.N)
+    out.scale = prm.scale * sM
+    got = np.real(enc.decode(prm, ckks.decrypt(prm, keys.s, ckks.rescale(prm, out))))
+    want = sum(np.roll(z, -k) * m for k, m in zip(steps, ms))
+    err = np.max(np.abs(got - want))
+    assert err < 1e-8
+    rots = ckks.rotate_hoisted(prm, keys, ct, steps)
+    acc = ckks.pt_mul_acc(prm, ckks.zero_ct(prm, lv, prm.scale * sM), rots,
+                          [enc.encode(prm, m, sM, lv) for m in ms])
+    got1 = np.real(enc.decode(prm, ckks.decrypt(prm, keys.s, ckks.rescale(prm, acc))))
+    assert err <= 2 * np.max(np.abs(got1 - want))
+    # the extended encoding reduces the same integers over Q_l and P
+    m_ext = enc.encode_ext(prm, ms[0], sM, lv)
+    m_q = enc.encode(prm, ms[0], sM, lv).m
+    assert np.array_equal(m_ext[: lv + 1], m_q) and m_ext.shape[0] == lv + 1 + prm.alpha
+    with pytest.raises(ValueError):
+        ckks.rotate_masked_sum(prm, keys, ct, [0], [m_ext])
