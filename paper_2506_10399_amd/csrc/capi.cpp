@@ -46,11 +46,14 @@ static void check_level(const ckks_ctx* c, uint32_t level) {
 }
 
 // residues of signed coefficients into [k][N] over the first k Q primes
-static void to_residues(const ckks_ctx* c, const std::vector<int64_t>& m, int k, std::vector<uint64_t>& out) {
+// residues of m for the first k moduli of the chain, or (ext_level >= 0) for
+// Q_0..Q_ext_level followed by the special primes
+static void to_residues(const ckks_ctx* c, const std::vector<int64_t>& m, int k, std::vector<uint64_t>& out,
+                        int ext_level = -1) {
   const size_t N = c->N;
   out.resize((size_t)k * N);
   for (int i = 0; i < k; ++i) {
-    uint64_t q = c->mod[i];
+    uint64_t q = c->mod[ext_level >= 0 && i > ext_level ? c->L + i - ext_level - 1 : i];
     for (size_t j = 0; j < N; ++j) {
       int64_t v = m[j];
       uint64_t a = v >= 0 ? (uint64_t)v % q : (q - (uint64_t)(-(v + 1)) % q - 1) % q;
@@ -59,11 +62,30 @@ static void to_residues(const ckks_ctx* c, const std::vector<int64_t>& m, int k,
   }
 }
 
-static void upload_ntt(ckks_ctx* c, const uint64_t* host, int n_limbs, uint64_t* dev, int n_polys) {
+static void upload_ntt(ckks_ctx* c, const uint64_t* host, int n_limbs, uint64_t* dev, int n_polys,
+                       int ext_level = -1) {
   const size_t bytes = (size_t)n_polys * n_limbs * c->N * 8;
   HIPCHECK(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, c->stream));
-  ntt_fwd(c, dev, n_limbs, lm_q(n_limbs), n_polys, (size_t)n_limbs * c->N);
+  ntt_fwd(c, dev, n_limbs, ext_level >= 0 ? lm_ext(ext_level, c->L) : lm_q(n_limbs), n_polys, (size_t)n_limbs * c->N);
   HIPCHECK(hipStreamSynchronize(c->stream));   // host buffer may be released on return
+}
+
+void encode_batch_ext(ckks_ctx* c, const double* re, size_t count, size_t n, double scale, int level,
+                      uint64_t* dev) {
+  const size_t N = c->N;
+  const int k = level + 1 + c->alpha;
+  const size_t per = (size_t)k * N;
+  std::vector<int64_t> m;
+  std::vector<uint64_t> r;
+  for (size_t b = 0; b < count; ++b) {
+    encode_coeffs(c->N, re + b * n, nullptr, n, scale, m);
+    to_residues(c, m, k, r, level);
+    upload_ntt(c, r.data(), k, dev + b * per, 1, level);
+  }
+}
+
+void pt_load_ext(ckks_ctx* c, const uint64_t* host, int level, uint64_t* dev) {
+  upload_ntt(c, host, level + 1 + c->alpha, dev, 1, level);
 }
 
 static const uint64_t* need_key(const ckks_keys* k, uint64_t tag) {

@@ -160,6 +160,8 @@ static T* upload_ptrs(ckks_ctx* c, const std::vector<T>& v, int slot) {
   return d;
 }
 
+static const uint64_t* rot_key(ckks_ctx* c, const ckks_keys* ek, int64_t step, uint64_t& g);
+
 // one key switch of a whole ciphertext (non-hoisted), out != in
 static void rotate_one(ckks_ctx* c, const ckks_keys* ek, const uint64_t* in, int level, int64_t step, uint64_t* out) {
   const size_t N = c->N;
@@ -256,9 +258,58 @@ static void aggregate_r2_plain(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, 
 }
 
 // SpIntra-CA of one packed ciphertext, one operation per call (plain form)
+// Double-hoisted diagonal form (family 4) of one packed ciphertext, one
+// operation per call: one ModUp of y's c1; per nonzero shift the key inner
+// product of the automorphed digits, multiplied by the mask on the key basis
+// and summed, and sigma(c0) (.) mask summed on Q_l; one ModDown of the sum;
+// the identity shift's plain mask product; rescale.
+static void aggregate_dh_plain(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, int g, const uint64_t* y,
+                               uint64_t* out) {
+  const size_t N = c->N;
+  const int lv = lp.level_agg, l1 = lv + 1, ext = l1 + c->alpha;
+  const int nd = (l1 + c->alpha - 1) / c->alpha;
+  const size_t ns = lp.shifts.size();
+  auto mask = [&](size_t si) { return (const uint64_t*)lp.ops[(size_t)g * ns + si]; };
+  uint64_t* D = (uint64_t*)c->buf(40, (size_t)nd * ext * N * 8);
+  uint64_t* acc = (uint64_t*)c->buf(41, (size_t)2 * ext * N * 8);
+  uint64_t* A = (uint64_t*)c->buf(78, (size_t)2 * ext * N * 8);
+  uint64_t* t = (uint64_t*)c->buf(79, (size_t)2 * l1 * N * 8);   // (sigma(c0), 0)
+  zero_fill(c, A, (size_t)2 * ext * N);
+  zero_fill(c, out, (size_t)2 * l1 * N);
+  zero_fill(c, t + (size_t)l1 * N, (size_t)l1 * N);
+  modup(c, y + (size_t)l1 * N, lv, D);
+  auto mac = [&](const uint64_t* ct, const uint64_t* pt) {
+    PtrList a{}, b{};
+    a.p[0] = ct;
+    b.p[0] = pt;
+    pmul_acc(c, out, a, b, 1, l1);
+  };
+  for (size_t si = 0; si < ns; ++si) {
+    const int64_t d = lp.shifts[si];
+    if (d == 0) {
+      mac(y, mask(si));
+      continue;
+    }
+    uint64_t gal;
+    const uint64_t* key = rot_key(c, ek, d, gal);
+    keymac(c, acc, D, key, lv, gal);
+    mac_ext(c, A, acc, mask(si), lv);
+    automorph_ntt(c, t, y, gal, l1, 1);
+    mac(t, mask(si));
+  }
+  uint64_t* md = (uint64_t*)c->buf(44, (size_t)2 * l1 * N * 8);
+  moddown(c, A, lv, md, nullptr, 1, nullptr);
+  add_inplace(c, out, md, l1, 2);
+  rescale_inplace(c, out, lv);
+}
+
 static void aggregate(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, int g, const uint64_t* y, uint64_t* out) {
   if (lp.family == 3) {
     aggregate_r2_plain(c, ek, lp, g, y, out);
+    return;
+  }
+  if (lp.family == 4) {
+    aggregate_dh_plain(c, ek, lp, g, y, out);
     return;
   }
   const size_t N = c->N;
@@ -520,6 +571,25 @@ static void aggregate_batched(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, c
   auto mask = [&](int g, size_t si) { return (const uint64_t*)lp.ops[(size_t)g * ns + si]; };
   std::vector<const uint64_t*> ysrc(np);
   for (int g = 0; g < np; ++g) ysrc[g] = Y[g] + (size_t)l1 * N;
+  if (lp.family == 4) {
+    // out_g = Y_g (.) mask_0 + ModDown(sum_delta KeyInner_delta (.) mask_delta) + sum_delta sigma(c0) (.) mask_delta:
+    // every rotation of Y_g on its one ModUp, one ModDown per packed ciphertext
+    std::vector<std::vector<MacTerm>> init(np);
+    std::vector<KSJob> jobs;
+    for (int g = 0; g < np; ++g)
+      for (size_t si = 0; si < ns; ++si) {
+        uint64_t gal;
+        const uint64_t* key = rot_key(c, ek, lp.shifts[si], gal);
+        if (!key)
+          init[g].push_back(MacTerm{Y[g], mask(g, si)});
+        else
+          jobs.push_back(KSJob{key, Y[g], nullptr, mask(g, si), gal, g, g});
+      }
+    group_mac(c, lv, init, outs, false);
+    keyswitch_masked_sum(c, lv, ysrc, jobs, outs, true);
+    rescale_batch(c, lv, outs);
+    return;
+  }
   if (lp.family == 1) {
     // out_g = sum_delta Rot_delta(Y_g) (.) mask_delta: identity terms first,
     // every rotation (hoisted on Y_g's ModUp) accumulated in the final ModDown step
@@ -913,7 +983,7 @@ ficgcn_status ficgcn_plan_create(ckks_ctx* ctx, const int32_t* rowptr, const int
   GUARD_BEGIN
   if (!ctx || !rowptr || !col || !val || !dims || !weights || !opts || !out || n_v == 0 || n_layers == 0)
     FICGCN_THROW(EINVAL_, "null or empty argument");
-  if (opts->family < 0 || opts->family > 3) FICGCN_THROW(EINVAL_, "family must be 0, 1, 2 or 3");
+  if (opts->family < 0 || opts->family > 4) FICGCN_THROW(EINVAL_, "family must be 0, 1, 2, 3 or 4");
   for (uint32_t l = 0; l < n_layers; ++l)
     if (!weights[l] || dims[l] == 0 || dims[l + 1] == 0) FICGCN_THROW(EINVAL_, "bad layer dimensions or weights");
   std::unique_ptr<ficgcn_plan> p(new ficgcn_plan());
@@ -1101,9 +1171,14 @@ ficgcn_status ficgcn_plan_encode(ckks_ctx* ctx, ficgcn_plan* plan) {
         plan_operand_slots(plan, (int)li, b0 + b, v);
         std::memcpy(all.data() + b * plan->M, v.data(), plan->M * 8);
       }
-      ficgcn_status st = ckks_encode_batch(ctx, all.data(), nb, plan->M, plan_operand_scale(plan, (int)li, b0),
-                                           lp.op_lv[b0], lp.ops_block + lp.op_off[b0]);
-      if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
+      if (lp.op_ext) {
+        encode_batch_ext(ctx, all.data(), nb, plan->M, plan_operand_scale(plan, (int)li, b0), lp.op_lv[b0],
+                         lp.ops_block + lp.op_off[b0]);
+      } else {
+        ficgcn_status st = ckks_encode_batch(ctx, all.data(), nb, plan->M, plan_operand_scale(plan, (int)li, b0),
+                                             lp.op_lv[b0], lp.ops_block + lp.op_off[b0]);
+        if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
+      }
       for (size_t b = 0; b < nb; ++b) lp.ops[b0 + b] = lp.ops_block + lp.op_off[b0 + b];
       b0 += nb;
     }
@@ -1120,8 +1195,12 @@ ficgcn_status ficgcn_plan_load_operand(ckks_ctx* ctx, ficgcn_plan* plan, uint32_
   if (i >= lp.ops.size()) FICGCN_THROW(EINVAL_, "operand index out of range");
   ensure_ops_block(ctx, lp);
   uint64_t* dst = lp.ops_block + lp.op_off[i];
-  ficgcn_status st = ckks_pt_load(ctx, host_coeffs, lp.op_lv[i], dst);
-  if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
+  if (lp.op_ext) {
+    pt_load_ext(ctx, host_coeffs, lp.op_lv[i], dst);
+  } else {
+    ficgcn_status st = ckks_pt_load(ctx, host_coeffs, lp.op_lv[i], dst);
+    if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
+  }
   lp.ops[i] = dst;
   GUARD_END
 }
@@ -1137,7 +1216,8 @@ ficgcn_status ficgcn_plan_fill_operands(ckks_ctx* ctx, ficgcn_plan* plan, uint64
       uint64_t* dst = lp.ops_block + lp.op_off[i];
       const int l1 = lp.op_lv[i] + 1;
       // stream (6, layer * 2^20 + i, limb): a stream the scheme itself never draws
-      sample_uniform(ctx, dst, seed, 6, (uint32_t)(li << 20 | i), 0, l1, lm_q(l1), 1);
+      sample_uniform(ctx, dst, seed, 6, (uint32_t)(li << 20 | i), 0, l1 + (lp.op_ext ? ctx->alpha : 0),
+                     lp.op_ext ? lm_ext(lp.op_lv[i], ctx->L) : lm_q(l1), 1);
       lp.ops[i] = dst;
     }
   }

@@ -91,7 +91,8 @@ struct ckks_ctx {
   std::map<std::pair<int, int>, ficgcn::BConv> modup;   // (level, digit)
   std::map<int, ficgcn::BConv> moddown;                  // level
   // grow-only scratch buffers by slot: ops.hip 1-9, sample/capi 10-29, gcn.cpp 30-49 and 70-79,
-  // ks_batch.hip 50-69 (a slot's memory moves when it grows, so one user per slot)
+  // ks_batch.hip 50-64 and 80-89, search.cpp 65-66 (a slot's memory moves when it grows, so one
+  // user per slot)
   std::vector<std::pair<void*, size_t>> scratch;
   // kernel timing (HIP events on `stream`), see ficgcn_profile_enable
   bool profiling = false;
@@ -178,6 +179,11 @@ void moddown(ckks_ctx* c, uint64_t* acc, int level, uint64_t* out, const uint64_
 void rescale_inplace(ckks_ctx* c, uint64_t* ct, int level);
 void tensor(ckks_ctx* c, const uint64_t* x, const uint64_t* y, uint64_t* d, int level);
 void copy_d2d(ckks_ctx* c, void* dst, const void* src, size_t bytes);
+// A[c][i] += acc[c][i] (.) pt[i] on the key basis (Q_l limbs then P), both components
+void mac_ext(ckks_ctx* c, uint64_t* A, const uint64_t* acc, const uint64_t* pt, int level);
+// plaintexts on the key basis: [level+1+alpha][N], Q_l limbs then P, evaluation form
+void encode_batch_ext(ckks_ctx* c, const double* re, size_t count, size_t n, double scale, int level, uint64_t* dev);
+void pt_load_ext(ckks_ctx* c, const uint64_t* host, int level, uint64_t* dev);
 
 // ---- sampling (sample.hip) ----
 void sample_uniform(ckks_ctx* c, uint64_t* out, uint64_t seed, uint32_t kind, uint32_t a, uint32_t b0,

@@ -39,6 +39,13 @@ struct MacTerm {
 // (or left as it is when accumulating).
 void keyswitch_batch(ckks_ctx* c, int level, const std::vector<const uint64_t*>& sources,
                      const std::vector<KSJob>& jobs, const std::vector<uint64_t*>& outs, bool accumulate);
+// Masked sums of key switches with one ModDown per output (double hoisting):
+// for every output group, A = sum over its jobs of acc_r (.) pt_r on the key
+// basis (pt_r: [l+1+alpha][N], Q_l limbs then P limbs), then
+//   out_grp (+)= ( ModDown(A_0) + sum_r sigma_g(add0_r) (.) pt_r,  ModDown(A_1) ).
+// Every job needs pt; add1 is ignored.
+void keyswitch_masked_sum(ckks_ctx* c, int level, const std::vector<const uint64_t*>& sources,
+                          const std::vector<KSJob>& jobs, const std::vector<uint64_t*>& outs, bool accumulate);
 void tensor_batch(ckks_ctx* c, int level, const std::vector<TensorJob>& jobs);
 // rounding rescale of each ciphertext in place ([2][l+1][N] -> [2][l][N])
 void rescale_batch(ckks_ctx* c, int level, const std::vector<uint64_t*>& cts);

@@ -309,6 +309,190 @@ void keyswitch_batch(ckks_ctx* c, int level, const std::vector<const uint64_t*>&
       if (!touched[g]) zero_fill(c, outs[g], (size_t)2 * l1 * N);
 }
 
+// ---- masked sums of key switches before one ModDown (double hoisting) ---------
+
+struct MaskGroup {
+  int start, end;   // job range (all jobs of the batch, sorted by group)
+};
+
+// A[grp][c][i] += sum_r acc_r[c][i] (.) pt_r[i] over the key basis (Q_l then P)
+__global__ void k_mask_sum_ext(const uint64_t* __restrict__ acc, const KSJob* __restrict__ jobs,
+                               const GroupDesc* __restrict__ groups, uint64_t* __restrict__ A, int ext, int l1, int L,
+                               int log_n, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << log_n;
+  const uint32_t j = blockIdx.x * KB + threadIdx.x;
+  const int i = blockIdx.y;
+  const int comp = blockIdx.z & 1;
+  const GroupDesc gd = groups[blockIdx.z >> 1];
+  const int m = i < l1 ? i : i - l1 + L;
+  const Mod md = mods[m];
+  uint64_t* a = gd.out + ((size_t)comp * ext + i) * N + j;   // gd.out: this group's A
+  u128 s = 0;
+  int cnt = 0;
+  uint64_t v = *a;
+  for (int r = gd.start; r < gd.end; ++r) {
+    s += (u128)acc[(((size_t)r * 2 + comp) * ext + i) * N + j] * jobs[r].pt[(size_t)i * N + j];
+    if (++cnt == 8) {
+      v = add_mod(v, reduce128(s, md), md.q);
+      s = 0;
+      cnt = 0;
+    }
+  }
+  *a = add_mod(v, reduce128(s, md), md.q);
+}
+
+// out_grp (+)= (A_Q - conv) P^-1  [+ sum_r sigma_g(add0_r) (.) pt_r on component 0]
+__global__ void k_masked_final(const uint64_t* __restrict__ A, const uint64_t* __restrict__ conv, int ext, int l1,
+                               MDK k, const KSJob* __restrict__ jobs, const MaskGroup* __restrict__ groups,
+                               uint64_t* const* __restrict__ outs, int accumulate, int log_n,
+                               const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << log_n;
+  const uint32_t j = blockIdx.x * KB + threadIdx.x;
+  const int i = blockIdx.y;
+  const int comp = blockIdx.z & 1, g = blockIdx.z >> 1;
+  const Mod md = mods[i];
+  const uint64_t q = md.q;
+  const size_t o = ((size_t)comp * l1 + i) * N + j;
+  uint64_t v = sub_mod(A[(((size_t)g * 2 + comp) * ext + i) * N + j], conv[(((size_t)g * 2 + comp) * l1 + i) * N + j], q);
+  v = mul_shoup(v, k.pinv[i], k.pinv_s[i], q);
+  if (comp == 0) {
+    const MaskGroup gr = groups[g];
+    u128 s = 0;
+    int cnt = 0;
+    for (int r = gr.start; r < gr.end; ++r) {
+      const KSJob jb = jobs[r];
+      if (!jb.add0) continue;
+      s += (u128)jb.add0[(size_t)i * N + (jb.g == 1 ? j : auto_idx(j, jb.g, log_n))] * jb.pt[(size_t)i * N + j];
+      if (++cnt == 8) {
+        v = add_mod(v, reduce128(s, md), q);
+        s = 0;
+        cnt = 0;
+      }
+    }
+    v = add_mod(v, reduce128(s, md), q);
+  }
+  uint64_t* out = outs[g];
+  out[o] = accumulate ? add_mod(out[o], v, q) : v;
+}
+
+enum { S_KM_A = 80, S_KM_CONV, S_KM_JOBS, S_KM_GRP, S_KM_OUT, S_KM_CGRP };
+
+void keyswitch_masked_sum(ckks_ctx* c, int level, const std::vector<const uint64_t*>& sources,
+                          const std::vector<KSJob>& jobs, const std::vector<uint64_t*>& outs, bool accumulate) {
+  const size_t N = c->N;
+  const int l1 = level + 1, ext = l1 + c->alpha;
+  const int nd = (l1 + c->alpha - 1) / c->alpha;
+  const int n_grp = (int)outs.size();
+  if (c->alpha > 8 || l1 > 64 || nd > DigitTables::MAX) FICGCN_THROW(EINVAL_, "too many primes");
+  if (n_grp == 0) return;
+  for (size_t r = 0; r < jobs.size(); ++r) {
+    const KSJob& jb = jobs[r];
+    if (jb.src < 0 || jb.src >= (int)sources.size() || !sources[jb.src] || !jb.key || !jb.pt || jb.grp < 0 ||
+        jb.grp >= n_grp || (r && jobs[r - 1].grp > jb.grp))
+      FICGCN_THROW(EINVAL_, "bad masked key-switch job");
+  }
+  for (uint64_t* o : outs)
+    if (!o) FICGCN_THROW(EINVAL_, "null output");
+  ProfScope ps(c, "ks_masked");
+  // one accumulator on the key basis per output, summed over every chunk
+  uint64_t* A = (uint64_t*)dev_scratch(c, S_KM_A, (size_t)n_grp * 2 * ext * N * 8);
+  zero_fill(c, A, (size_t)n_grp * 2 * ext * N);
+  const size_t per_job = (size_t)2 * ext * N * 8;
+  const size_t per_src = (size_t)(nd * ext + l1) * N * 8;
+  DigitTables dt{};
+  for (int d = 0; d < nd; ++d) {
+    const BConv& bc = get_modup(c, level, d);
+    dt.tab[d] = bc.dev;
+    dt.idx[d] = bc.idx;
+    dt.n_src[d] = bc.n_src;
+    dt.n_dst[d] = bc.n_dst;
+  }
+  size_t a = 0;
+  while (a < jobs.size()) {
+    std::vector<int> local(sources.size(), -1);
+    std::vector<const uint64_t*> srcs;
+    std::vector<KSJob> cj;
+    size_t b = a, bytes = 0;
+    while (b < jobs.size()) {
+      const bool new_src = local[jobs[b].src] < 0;
+      const size_t add = per_job + (new_src ? per_src : 0);
+      if (b > a && bytes + add > KS_BUDGET) break;
+      bytes += add;
+      if (new_src) {
+        local[jobs[b].src] = (int)srcs.size();
+        srcs.push_back(sources[jobs[b].src]);
+      }
+      KSJob jc = jobs[b];
+      jc.src = local[jc.src];
+      cj.push_back(jc);
+      ++b;
+    }
+    // this chunk's job ranges per output, each pointing at the output's accumulator
+    std::vector<GroupDesc> gds;
+    for (size_t r = 0; r < cj.size(); ++r) {
+      const int g = cj[r].grp;
+      if (r == 0 || cj[r - 1].grp != g)
+        gds.push_back(GroupDesc{A + (size_t)g * 2 * ext * N, (int)r, (int)r + 1, 1, 0});
+      else
+        gds.back().end = (int)r + 1;
+    }
+    const int U = (int)srcs.size(), R = (int)cj.size();
+    KSJob* jd = upload(c, S_KB_JOBS, cj);
+    const uint64_t* const* sd = upload(c, S_KB_SRC, srcs);
+    GroupDesc* gd = upload(c, S_KM_CGRP, gds);
+    uint64_t* tmp = (uint64_t*)dev_scratch(c, S_KB_TMP, (size_t)U * l1 * N * 8);
+    uint64_t* D = (uint64_t*)dev_scratch(c, S_KB_D, (size_t)U * nd * ext * N * 8);
+    uint64_t* acc = (uint64_t*)dev_scratch(c, S_KB_ACC, (size_t)R * 2 * ext * N * 8);
+    {
+      ProfScope pm(c, "modup");
+      hipLaunchKernelGGL(k_gather, dim3(N / KB, l1, U), dim3(KB), 0, c->stream, tmp, sd, l1, c->log_n);
+      HIPCHECK(hipGetLastError());
+      ntt_inv(c, tmp, l1, lm_q(l1), U, (size_t)l1 * N);
+      hipLaunchKernelGGL(k_modup_conv, dim3(N / KB, nd, U), dim3(KB), 0, c->stream, tmp, sd, D, dt, c->alpha, l1, ext,
+                         nd, c->L, c->log_n, c->t.mods);
+      HIPCHECK(hipGetLastError());
+      ntt_fwd(c, D, ext, lm_ext(level, c->L), U * nd, (size_t)ext * N, c->alpha, l1);
+    }
+    {
+      ProfScope pk(c, "keymac");
+      hipLaunchKernelGGL(k_keymac_batch, dim3(N / KB, ext, R), dim3(KB), 0, c->stream, acc, D, jd, nd, ext, l1, c->L,
+                         c->n_mod(), c->log_n, c->t.mods);
+      HIPCHECK(hipGetLastError());
+      hipLaunchKernelGGL(k_mask_sum_ext, dim3(N / KB, ext, 2 * gds.size()), dim3(KB), 0, c->stream, acc, jd, gd, A,
+                         ext, l1, c->L, c->log_n, c->t.mods);
+      HIPCHECK(hipGetLastError());
+    }
+    stream_sync(c);
+    a = b;
+  }
+  // one ModDown per output: P limbs to coefficient form, rounded conversion,
+  // forward NTT, then out (+)= (A_Q - conv) P^-1 + sum sigma(add0) (.) pt
+  {
+    ProfScope pd(c, "moddown");
+    const MDK k = mdk(c, level);
+    const BConv& md = get_moddown(c, level);
+    std::vector<MaskGroup> mg(n_grp, MaskGroup{0, 0});
+    for (size_t r = 0; r < jobs.size(); ++r) {
+      const int g = jobs[r].grp;
+      if (mg[g].end == 0) mg[g].start = (int)r;
+      mg[g].end = (int)r + 1;
+    }
+    KSJob* jall = upload(c, S_KM_JOBS, jobs);
+    MaskGroup* mgd = upload(c, S_KM_GRP, mg);
+    uint64_t* const* od = upload(c, S_KM_OUT, outs);
+    uint64_t* conv = (uint64_t*)dev_scratch(c, S_KM_CONV, (size_t)n_grp * 2 * l1 * N * 8);
+    ntt_inv(c, A + (size_t)l1 * N, c->alpha, LimbMap{c->L, 1 << 30, 0}, 2 * n_grp, (size_t)ext * N);
+    hipLaunchKernelGGL(k_moddown_conv_batch, dim3(N / KB, 2 * n_grp), dim3(KB), 0, c->stream, A, ext, l1, md.idx,
+                       md.idx + md.n_src, md.n_src, (const uint64_t*)md.dev, k, conv, c->log_n, c->t.mods);
+    HIPCHECK(hipGetLastError());
+    ntt_fwd(c, conv, l1, lm_q(l1), 2 * n_grp, (size_t)l1 * N);
+    hipLaunchKernelGGL(k_masked_final, dim3(N / KB, l1, 2 * n_grp), dim3(KB), 0, c->stream, A, conv, ext, l1, k, jall,
+                       mgd, od, accumulate ? 1 : 0, c->log_n, c->t.mods);
+    HIPCHECK(hipGetLastError());
+    stream_sync(c);
+  }
+}
+
 // ---- batched ciphertext kernels --------------------------------------------------
 
 // d = (x0 y0, x0 y1 + x1 y0, x1 y1) per job, [3][l1][N]

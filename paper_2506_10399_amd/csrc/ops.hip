@@ -337,6 +337,23 @@ void tensor(ckks_ctx* c, const uint64_t* x, const uint64_t* y, uint64_t* d, int 
   HIPCHECK(hipGetLastError());
 }
 
+__global__ void k_mac_ext(uint64_t* __restrict__ A, const uint64_t* __restrict__ acc, const uint64_t* __restrict__ pt,
+                          int ext, int l1, int L, int log_n, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << log_n;
+  const size_t j = blockIdx.x * (size_t)EW + threadIdx.x;
+  const int i = blockIdx.y, c = blockIdx.z;
+  const Mod m = mods[i < l1 ? i : i - l1 + L];
+  const size_t o = ((size_t)c * ext + i) * N + j;
+  A[o] = add_mod(A[o], reduce128((u128)acc[o] * pt[(size_t)i * N + j], m), m.q);
+}
+
+void mac_ext(ckks_ctx* c, uint64_t* A, const uint64_t* acc, const uint64_t* pt, int level) {
+  const int l1 = level + 1, ext = l1 + c->alpha;
+  hipLaunchKernelGGL(k_mac_ext, dim3(c->N / EW, ext, 2), dim3(EW), 0, c->stream, A, acc, pt, ext, l1, c->L, c->log_n,
+                     c->t.mods);
+  HIPCHECK(hipGetLastError());
+}
+
 void copy_d2d(ckks_ctx* c, void* dst, const void* src, size_t bytes) {
   HIPCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream));
 }

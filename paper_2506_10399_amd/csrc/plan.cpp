@@ -241,7 +241,7 @@ static std::vector<int64_t> rotation_steps_of(const LayerPlan& lp) {
       for (const R2Term& t : st.fin)
         if (t.m) s.insert(t.m);
     }
-  } else if (lp.family == 1) {
+  } else if (lp.family == 1 || lp.family == 4) {
     for (int64_t d : lp.shifts)
       if (d) s.insert(d);
   } else {
@@ -339,13 +339,14 @@ static void layout_operands(ficgcn_plan* p) {
   for (size_t li = 0; li < p->layers.size(); ++li) {
     LayerPlan& lp = p->layers[li];
     const size_t n = plan_operand_count(p, (int)li);
+    lp.op_ext = lp.kind == 1 && lp.family == 4;
     lp.op_lv.resize(n);
     lp.op_off.resize(n);
     size_t off = 0;
     for (size_t i = 0; i < n; ++i) {
       lp.op_lv[i] = plan_operand_level(p, (int)li, i);
       lp.op_off[i] = off;
-      off += (size_t)(lp.op_lv[i] + 1) * N;
+      off += (size_t)(lp.op_lv[i] + 1 + (lp.op_ext ? p->ctx->alpha : 0)) * N;
     }
     lp.op_words = off;
   }
@@ -519,7 +520,7 @@ void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_la
       int c2;
       bsgs_split(lp.shifts, lp.B, lp.G, c2);
       int c1 = (int)lp.shifts.size() - (sh.count(0) ? 1 : 0);
-      lp.family = o.family == 1 ? 1 : o.family == 2 ? 2 : o.family == 3 ? 3 : (c2 < c1 ? 2 : 1);
+      lp.family = (o.family >= 1 && o.family <= 4) ? o.family : (c2 < c1 ? 2 : 1);
       if (lp.family == 3) {
         if (!(o.cpoo >= 0.0 && o.cpoo <= 1.0)) FICGCN_THROW(EPLAN_, "CPOO threshold must lie in [0, 1]");
         lp.cpoo = o.cpoo;

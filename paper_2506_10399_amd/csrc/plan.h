@@ -62,6 +62,7 @@ struct LayerPlan {
   // SpIntra-CA: n_packed * n_shifts masks at level_agg
   int op_level = 0;
   double op_scale = 0;
+  bool op_ext = false;             // operands on the key basis (level+1+alpha limbs): family 4 masks
   std::vector<int32_t> op_lv;      // level of each operand
   std::vector<size_t> op_off;      // word offset of each operand in ops_block
   size_t op_words = 0;

@@ -247,6 +247,9 @@ static double plan_bytes(const ficgcn_plan* p) {
       double per = mask(la) * ns + limb * 2.0 * (la + 1);
       if (lp.family == 1)
         per += modup(la) + nz * ks_extra(la);
+      else if (lp.family == 4)   // inner products (key, digits, mask on the key basis), one ModDown
+        per += modup(la) + nz * limb * (2.0 * beta(la + 1) * (la + 1 + a) + 5.0 * (la + 1 + a)) +
+               limb * (2.0 * a + 4.0 * (la + 1));
       else
         per += (babies.empty() ? 0.0 : modup(la) + babies.size() * ks_extra(la)) + giants.size() * ks_single(la);
       bytes += np * (per + rs(la));

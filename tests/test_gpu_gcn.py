@@ -53,11 +53,14 @@ def _load_operands(e):
             flat = d["P"]
         elif lp.family == 3:
             flat = [pt for per_g in d["masks"] for pt in per_g]
+        elif lp.family == 4:
+            # (Q-level plaintext, residues on the key basis): the library takes the latter
+            flat = [d["masks"][g][s][1] for g in range(len(d["masks"])) for s in lp.shifts]
         else:
             flat = [d["masks"][g][s] for g in range(len(d["masks"])) for s in lp.shifts]
         assert len(flat) == p.ficgcn_plan_operand_count(li)
         for i, pt in enumerate(flat):
-            p.ficgcn_plan_load_operand(li, i, pt.m)
+            p.ficgcn_plan_load_operand(li, i, pt if isinstance(pt, np.ndarray) else pt.m)
 
 
 def _run_gpu(e, mode, contiguous=False):
@@ -78,7 +81,8 @@ def _run_gpu(e, mode, contiguous=False):
     return per_layer
 
 
-CASES = [("tiny", "inter", None), ("tiny", "spintra", 1), ("tiny", "spintra", 2), ("tiny2", "inter", None)]
+CASES = [("tiny", "inter", None), ("tiny", "spintra", 1), ("tiny", "spintra", 2), ("tiny", "spintra", 4),
+         ("tiny2", "inter", None), ("tiny2", "inter", 4)]
 
 
 @pytest.mark.parametrize("name,mode,family", CASES)
@@ -133,10 +137,11 @@ def test_graph_replays_equal_batched(name, mode, family):
         torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("name,mode", [("tiny", "inter"), ("tiny2", "inter")])
-def test_library_encoder_end_to_end(name, mode):
-    """Operands encoded by the library, inputs encrypted by the library."""
-    e = _setup(name, mode)
+@pytest.mark.parametrize("name,mode,family", [("tiny", "inter", None), ("tiny2", "inter", None), ("tiny", "spintra", 4)])
+def test_library_encoder_end_to_end(name, mode, family):
+    """Operands encoded by the library (family 4: on the key basis), inputs
+    encrypted by the library."""
+    e = _setup(name, mode, family)
     ctx, p, prm, w = e["ctx"], e["p"], e["prm"], e["w"]
     p.ficgcn_plan_encode()
     lv0 = prm.L - 1

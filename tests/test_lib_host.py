@@ -69,6 +69,8 @@ def _plans(fg, name, mode, noo, family, t=None, TH=None, **kw):
 @pytest.mark.parametrize("name,mode,noo,family,kw", [
     ("tiny", "inter", True, None, {}), ("tiny", "spintra", True, None, {}), ("tiny", "spintra", False, 1, {}),
     ("tiny2", "inter", True, None, {}), ("tiny2", "inter", False, 2, {}),
+    # the double-hoisted diagonal form: the diagonal routing, masks on the key basis
+    ("tiny", "spintra", True, 4, {}), ("tiny2", "inter", True, 4, {}),
     ("cora", "inter", True, None, {"dims": [24, 16, 7]}), ("citeseer", "inter", True, None, {"dims": [24, 16, 6]}),
     # candidates of the plan search: forced packing t and region cap TH
     ("tiny2", "inter", True, 2, {"t": 1}), ("tiny2", "inter", True, 1, {"t": 4, "TH": 64}),
@@ -103,6 +105,8 @@ def test_plan_matches_oracle(fg, name, mode, noo, family, kw):
             assert (d["t"], d["B"], d["family"], d["G"]) == (lp.t, lp.B, lp.family, lp.G)
             assert p.ficgcn_plan_shifts(li) == list(lp.shifts)
             n_ops = d["n_out_cts"] * len(lp.shifts)
+            if lp.family == 4:
+                assert p.ficgcn_plan_operand_level(li, n_ops - 1) == (st["level_agg"], st["sM"])
         assert p.ficgcn_plan_operand_count(li) == n_ops
     assert p.ficgcn_plan_rot_steps() == o.rot_steps(prm.M)
 
