@@ -182,7 +182,10 @@ typedef struct {
   int32_t use_noo;      /* node order optimisation (Alg. 1) on/off */
   int32_t family;       /* SpIntra-CA routing: 0 = cheaper of 1 and 2, 1 = diagonal, 2 = baby-step/giant-step,
                            3 = the paper's radix-2 routing with per-round masks (Sec. 3.3): one level per
-                           round in which something moves, so the chain needs that many spare primes */
+                           round in which something moves, so the chain needs that many spare primes;
+                           4 = diagonal with double hoisting: every rotation's key inner product is multiplied
+                           by its mask on the key basis (Q_l and P) and summed before one ModDown per output;
+                           its masks carry level + 1 + alpha limbs */
   int32_t TH;           /* region size cap; 0 = 1024 below 10000 nodes, else 4096 */
   int32_t activation;   /* x^2 after every layer */
   int32_t t;            /* SpIntra-CA packing: columns per ciphertext, a power of two no larger than
@@ -229,9 +232,11 @@ ficgcn_status ficgcn_plan_weights_int(const ficgcn_plan* plan, uint32_t layer, i
 ficgcn_status ficgcn_plan_operand_count(const ficgcn_plan* plan, uint32_t layer, size_t* n_out);
 ficgcn_status ficgcn_plan_operand_slots(const ficgcn_plan* plan, uint32_t layer, size_t i, double* slots_out);
 /* Level and encoding scale of operand i (the Inter-CA plaintexts sit at the
- * layer's input level, the masks of families 1 and 2 at the aggregation
+ * layer's input level, the masks of families 1, 2 and 4 at the aggregation
  * level; a radix-2 mask sits at the level of the step that multiplies it and
- * is encoded at that level's prime, which the step's rescale drops). */
+ * is encoded at that level's prime, which the step's rescale drops).  Family
+ * 4 masks hold level + 1 + alpha limbs: the Q_0..Q_level residues, then the
+ * special primes' (ficgcn_plan_load_operand takes them in that order). */
 ficgcn_status ficgcn_plan_operand_level(const ficgcn_plan* plan, uint32_t layer, size_t i, uint32_t* level_out,
                                         double* scale_out);
 /* Radix-2 aggregation program of a family-3 layer (Sec. 3.3 with CPOO of
@@ -283,8 +288,8 @@ ficgcn_status ficgcn_gcn_layer(ckks_ctx* ctx, const ckks_keys* eval_keys, const 
 
 /* Enumerates the candidate options for this graph size and model: every
  * feasible t, NOO off (when the graph fits one column block) or on with TH
- * in {64, 256, 1024, 4096} below n_v (plus TH = n_v), family 1 and 2; the
- * other fields are copied from base.  Writes up to cap entries, *n_out =
+ * in {64, 256, 1024, 4096} below n_v (plus TH = n_v), families 1, 2 and 4;
+ * the other fields are copied from base.  Writes up to cap entries, *n_out =
  * the full count.  Host only. */
 ficgcn_status ficgcn_plan_candidates(uint32_t n_v, const uint32_t* dims, uint32_t n_layers, uint32_t log_n,
                                      const ficgcn_plan_opts* base, ficgcn_plan_opts* out, size_t cap,

@@ -66,7 +66,7 @@ static std::vector<ficgcn_plan_opts> candidates(uint32_t n_v, const uint32_t* di
       if (!noo && (int)n_v > B) continue;
       const std::vector<int> th_list = noo ? ths : std::vector<int>{0};
       for (int th : th_list)
-        for (int fam = 1; fam <= 2; ++fam) {
+        for (int fam : {1, 2, 4}) {
           ficgcn_plan_opts o = base;
           o.t = t;
           o.use_noo = noo;
@@ -160,7 +160,7 @@ static void features(const int32_t* rowptr, const int32_t* col, uint32_t n_v, co
       (float)(std::log2((double)std::max(1, TH)) / 16.0),
       (float)(o.family == 1),
       (float)(o.family == 2),
-      (float)(o.family == 0),
+      (float)(o.family == 4),
       (float)(std::log2((double)f_in + 1.0) / 12.0),
       (float)(std::log2((double)f_out + 1.0) / 12.0),
       (float)(std::log2(n_packed + 1.0) / 6.0),
@@ -173,26 +173,31 @@ static void features(const int32_t* rowptr, const int32_t* col, uint32_t n_v, co
   std::memcpy(out, f, sizeof(f));
 }
 
-// algorithmic HBM bytes of one batched inference of the plan
+// HBM bytes of one batched inference of the plan, every pass of the batched
+// launch sequence counted (in limbs of N words): an NTT of n limbs moves 4n
+// (two passes, read and write); a ModUp at level l (L1 = l + 1 limbs, beta
+// digits, ext = L1 + alpha) moves 4 L1 + 5 beta ext (copy, inverse NTT,
+// conversion, forward NTT of the converted limbs); a key inner product
+// 3 beta ext + 2 ext (digits, key, accumulator); a ModDown with its final
+// step 10 alpha + 17 L1; a rescale 14 l + 16; a masked-sum term 3 L1.
 static double plan_bytes(const ficgcn_plan* p) {
   const ckks_ctx* c = p->ctx;
   const double limb = 8.0 * c->N;
   const int a = c->alpha;
   auto beta = [&](int L1) { return (double)((L1 + a - 1) / a); };
-  auto ks_single = [&](int l) {
-    const int L1 = l + 1;
-    return limb * (2.0 * L1 + 2.0 * beta(L1) * (L1 + a) + 2.0 * L1);
-  };
-  auto ks_extra = [&](int l) {
-    const int L1 = l + 1;
-    return limb * (2.0 * beta(L1) * (L1 + a) + 3.0 * L1);
-  };
   auto modup = [&](int l) {
-    const int L1 = l + 1;
-    return limb * (L1 + beta(L1) * (L1 + a));
+    const double L1 = l + 1, ext = L1 + a;
+    return limb * (4.0 * L1 + 5.0 * beta(l + 1) * ext);
   };
+  auto inner = [&](int l) {
+    const double ext = l + 1 + a;
+    return limb * (3.0 * beta(l + 1) * ext + 2.0 * ext);
+  };
+  auto moddown = [&](int l) { return limb * (10.0 * a + 17.0 * (l + 1)); };
+  auto ks_single = [&](int l) { return modup(l) + inner(l) + moddown(l); };
+  auto ks_extra = [&](int l) { return inner(l) + moddown(l); };
   auto mask = [&](int l) { return limb * 3.0 * (l + 1); };
-  auto rs = [&](int l) { return limb * (2.0 * (l + 1) + 2.0 * l); };
+  auto rs = [&](int l) { return limb * (14.0 * l + 16.0); };
   double bytes = 0;
   for (const LayerPlan& lp : p->layers) {
     const int l1 = lp.level_in + 1;
@@ -247,9 +252,9 @@ static double plan_bytes(const ficgcn_plan* p) {
       double per = mask(la) * ns + limb * 2.0 * (la + 1);
       if (lp.family == 1)
         per += modup(la) + nz * ks_extra(la);
-      else if (lp.family == 4)   // inner products (key, digits, mask on the key basis), one ModDown
-        per += modup(la) + nz * limb * (2.0 * beta(la + 1) * (la + 1 + a) + 5.0 * (la + 1 + a)) +
-               limb * (2.0 * a + 4.0 * (la + 1));
+      else if (lp.family == 4)   // inner products, their masked sum on the key basis, one ModDown
+        per += modup(la) + nz * (inner(la) + limb * (3.0 * (la + 1 + a) + 2.0 * (la + 1))) + moddown(la) +
+               limb * 4.0 * (la + 1 + a);
       else
         per += (babies.empty() ? 0.0 : modup(la) + babies.size() * ks_extra(la)) + giants.size() * ks_single(la);
       bytes += np * (per + rs(la));

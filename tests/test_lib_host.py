@@ -163,12 +163,13 @@ def test_candidates_cover_packing_order_and_family(fg):
     w, rp, col, val = _case("tiny2")
     base = fg.PlanOpts(0, 1, 0, 0, int(w.activation), 0)
     c = fg.ficgcn_plan_candidates(w.graph.n, w.meta["dims"], w.params["log_n"], base)
-    # t in {1, 2, 4, 8} (F' = 7, 200 nodes in 4096 slots), NOO off + TH in {64, 256... below n} + {n}, 2 families
+    # t in {1, 2, 4, 8} (F' = 7, 200 nodes in 4096 slots), NOO off + TH in {64, 256... below n} + {n},
+    # families 1, 2 and 4
     ts = sorted({o.t for o in c})
     assert ts == [1, 2, 4, 8]
     n_th = len([x for x in (64, 256, 1024, 4096) if x < w.graph.n]) + 1
-    assert len(c) == len(ts) * (1 + n_th) * 2
-    assert {(o.use_noo, o.family) for o in c} == {(0, 1), (0, 2), (1, 1), (1, 2)}
+    assert len(c) == len(ts) * (1 + n_th) * 3
+    assert {(o.use_noo, o.family) for o in c} == {(u, f) for u in (0, 1) for f in (1, 2, 4)}
     # every candidate builds
     ctx = fg.Context.from_dict(w.params)
     for o in c:
