@@ -146,6 +146,9 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="instead: a Poisson stream of encrypted GCN requests through the server (rate sweep)")
     ap.add_argument("--requests", type=int, default=10)
+    ap.add_argument("--keyswitch", action="store_true",
+                    help="instead: key switching alone at the citation-graph parameters (hoisted rotations of one "
+                         "ciphertext, rotations of distinct ciphertexts, relinearisations)")
     ap.add_argument("--ntu", action="store_true",
                     help="instead: the 3-layer x^2 GCN (3-64-128-128) on the multi-frame skeleton shape "
                          "(25 joints x 256 frames, N=2^14)")
@@ -166,6 +169,9 @@ def main():
         return
     if args.ntu:
         ntu_bench(args)
+        return
+    if args.keyswitch:
+        keyswitch_bench(args)
         return
 
     import torch
@@ -465,6 +471,71 @@ def serving_bench(args):
                runs=runs, max_rel_err=err,
                requests=[dict(name=q.name, latency_ms=round(q.result["latency_ms"], 2),
                               footprint_gb=round(q.result["footprint_bytes"] / 1e9, 2)) for q in reqs])
+    print(json.dumps(out), flush=True)
+
+
+def keyswitch_bench(args):
+    """Key switching alone: CKKS N = 2^16, 8 x 50-bit + 2 x 60-bit primes
+    (alpha = 2, four digits at the top level), fresh ciphertexts resident.
+    Three batched forms at the top level (7) and at level 3: 16 rotations of
+    one ciphertext hoisted on one ModUp, 16 rotations of 16 distinct
+    ciphertexts in one batch, and 16 relinearised squares, one call each.  Reported per form: key switches
+    per second, the algorithmic bytes per switch (source and output
+    ciphertexts, key; the hoisted form's shared ModUp input counted once)
+    and the bytes every pass of the launch sequence moves (NTT passes, base
+    conversions, inner products), as rates."""
+    import torch
+    from paper_2506_10399_amd import ficgcn as fg
+    torch.cuda.set_device(0)
+    prm = dict(log_n=16, n_q=8, q_bits=50, n_p=2, p_bits=60, log_scale=40)
+    ctx = fg.Context.from_dict(prm)
+    ctx.ckks_ntt_autotune(prm["n_q"] + prm["n_p"])
+    N, M, a = 1 << 16, 1 << 15, prm["n_p"]
+    steps = list(range(1, 17))
+    cl, ev = ctx.ckks_keygen(5, steps, with_relin=True)
+    rng = np.random.default_rng(9)
+    limb = 8.0 * N
+    res = {}
+    reps = max(3, args.steps)
+    for lv in (prm["n_q"] - 1, 3):
+        L1 = lv + 1
+        beta = -(-L1 // a)
+        ext = L1 + a
+        pts = ctx.ckks_encode_batch(rng.uniform(-1, 1, (17, M)), 2.0 ** prm["log_scale"], lv)
+        xs = [ctx.ckks_encrypt(cl, pts[i], lv, 3, i) for i in range(17)]
+        outs = [ctx.ct_buffer(lv) for _ in steps]
+        key_b = limb * 2 * beta * ext
+        alg = dict(hoisted=(key_b + 2 * L1 * limb) + 2 * L1 * limb / len(steps),   # key + output, source shared
+                   batch=key_b + 4 * L1 * limb, relin=key_b + 4 * L1 * limb)
+        modup = limb * (4 * L1 + 5 * beta * ext)
+        inner = limb * (3 * beta * ext + 2 * ext)
+        moddown = limb * (10 * a + 17 * L1)
+        passes = dict(hoisted=inner + moddown + modup / len(steps), batch=modup + inner + moddown,
+                      relin=modup + inner + moddown + limb * 7 * L1)
+        forms = dict(
+            hoisted=lambda: ctx.ckks_rotate_hoisted(ev, xs[0], lv, steps, outs),
+            batch=lambda: ctx.ckks_rotate_batch(ev, xs[1:], lv, steps, outs),
+            relin=lambda: [ctx.ckks_mul_relin(ev, xs[i + 1], xs[i + 1], lv, outs[i]) for i in range(len(steps))])
+        for name, fn in forms.items():
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / (reps * len(steps))
+            res["level%d_%s" % (lv, name)] = dict(
+                per_s=round(1.0 / dt, 1), us=round(dt * 1e6, 2),
+                alg_gbs=round(alg[name] / dt / 1e9, 1), alg_frac=round(alg[name] / dt / 1e9 / HBM_PEAK_GBS, 4),
+                pass_gbs=round(passes[name] / dt / 1e9, 1),
+                pass_frac=round(passes[name] / dt / 1e9 / HBM_PEAK_GBS, 4))
+            log("level %d %s: %s" % (lv, name, res["level%d_%s" % (lv, name)]))
+    best = max(res.values(), key=lambda r: r["per_s"])
+    out = dict(metric="key switches per second (batched hybrid key switching)", unit="key switches/s",
+               value=res["level%d_hoisted" % (prm["n_q"] - 1)]["per_s"], higher_is_better=True, n_gpus=1,
+               dtype="u64", data="synthetic",
+               config=dict(workload="CKKS N=2^16, 8+2 primes, alpha 2; 16 rotations per call", reps=reps),
+               forms=res)
     print(json.dumps(out), flush=True)
 
 
