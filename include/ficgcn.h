@@ -87,9 +87,9 @@ ficgcn_status ficgcn_profile_enable(ckks_ctx* ctx, int on);
 ficgcn_status ficgcn_profile_read(ckks_ctx* ctx, const char* kernel, double* ms_total, uint64_t* launches);
 
 /* NTT autotuner: times every workgroup width pair (column pass x row pass)
- * on n_limbs scratch limbs with HIP events on the context's stream and keeps
- * the fastest for this context.  cols_out[2] receives the choice (may be
- * NULL).  Synchronous. */
+ * on 16 scratch polynomials of n_limbs limbs (a key-switch batch's launch
+ * shape) with HIP events on the context's stream and keeps the fastest for
+ * this context.  cols_out[2] receives the choice (may be NULL).  Synchronous. */
 ficgcn_status ckks_ntt_autotune(ckks_ctx* ctx, uint32_t n_limbs, int32_t* cols_out);
 
 /* ------------------------------------------------------------------ keys */

@@ -519,9 +519,13 @@ ficgcn_status ckks_ntt_autotune(ckks_ctx* ctx, uint32_t n_limbs, int32_t* cols_o
   return guard([&] {
     if (ctx) ensure_device(ctx);
     REQUIRE(ctx && n_limbs >= 1 && n_limbs <= (uint32_t)ctx->n_mod(), EINVAL_, "bad argument");
-    const size_t words = (size_t)n_limbs * ctx->N;
+    // a key-switch batch's shape: 16 polynomials of n_limbs limbs in one launch
+    constexpr int NP = 16;
+    const size_t words = (size_t)NP * n_limbs * ctx->N;
+    const size_t ps = (size_t)n_limbs * ctx->N;
     uint64_t* d = (uint64_t*)ctx->buf(16, words * 8);
-    HIPCHECK(hipMemsetAsync(d, 0, words * 8, ctx->stream));
+    // residues spread over [0, q): the transform's timing depends on the data
+    for (int p = 0; p < NP; ++p) sample_uniform(ctx, d + p * ps, 0, 99, (uint32_t)p, 0, (int)n_limbs, lm_q((int)n_limbs), 0);
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
@@ -534,12 +538,12 @@ ficgcn_status ckks_ntt_autotune(ckks_ctx* ctx, uint32_t n_limbs, int32_t* cols_o
       for (int c1 : {2, 4, 8, 16}) {
         ctx->ntt_cols[0] = c0;
         ctx->ntt_cols[1] = c1;
-        ntt_fwd(ctx, d, (int)n_limbs, lm_q((int)n_limbs), 1, 0);   // warm-up
-        ntt_inv(ctx, d, (int)n_limbs, lm_q((int)n_limbs), 1, 0);
+        ntt_fwd(ctx, d, (int)n_limbs, lm_q((int)n_limbs), NP, ps);   // warm-up
+        ntt_inv(ctx, d, (int)n_limbs, lm_q((int)n_limbs), NP, ps);
         HIPCHECK(hipEventRecord(e0, ctx->stream));
         for (int r = 0; r < 5; ++r) {
-          ntt_fwd(ctx, d, (int)n_limbs, lm_q((int)n_limbs), 1, 0);
-          ntt_inv(ctx, d, (int)n_limbs, lm_q((int)n_limbs), 1, 0);
+          ntt_fwd(ctx, d, (int)n_limbs, lm_q((int)n_limbs), NP, ps);
+          ntt_inv(ctx, d, (int)n_limbs, lm_q((int)n_limbs), NP, ps);
         }
         HIPCHECK(hipEventRecord(e1, ctx->stream));
         HIPCHECK(hipEventSynchronize(e1));

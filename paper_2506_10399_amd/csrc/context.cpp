@@ -145,6 +145,14 @@ void ensure_device(ckks_ctx* c) {
   up(&c->t.psi_s, c->h_psi_s);
   up(&c->t.ipsi, c->h_ipsi);
   up(&c->t.ipsi_s, c->h_ipsi_s);
+  auto up_f = [&](double** dst, const std::vector<uint64_t>& v) {
+    std::vector<double> f(v.size());
+    for (size_t i = 0; i < v.size(); ++i) f[i] = (double)v[i];
+    HIPCHECK(hipMalloc(dst, f.size() * 8));
+    HIPCHECK(hipMemcpy(*dst, f.data(), f.size() * 8, hipMemcpyHostToDevice));
+  };
+  up_f(&c->t.psi_f, c->h_psi);
+  up_f(&c->t.ipsi_f, c->h_ipsi);
   up(&c->t.ninv, c->h_ninv);
   up(&c->t.ninv_s, c->h_ninv_s);
   HIPCHECK(hipMalloc(&c->t.mods, c->h_mods.size() * sizeof(Mod)));
@@ -282,6 +290,8 @@ ckks_ctx::~ckks_ctx() {
   for (auto& s : scratch)
     if (s.first) (void)hipFree(s.first);
   for (uint64_t* p : {t.psi, t.psi_s, t.ipsi, t.ipsi_s, t.ninv, t.ninv_s})
+    if (p) (void)hipFree(p);
+  for (double* p : {t.psi_f, t.ipsi_f})
     if (p) (void)hipFree(p);
   if (t.mods) (void)hipFree(t.mods);
   for (auto& kv : modup) { (void)hipFree(kv.second.dev); (void)hipFree(kv.second.idx); }

@@ -47,6 +47,8 @@ struct Tables {
   uint64_t* psi_s = nullptr;   // Shoup companions
   uint64_t* ipsi = nullptr;    // [n_mod][N] psi^{-brev(k)}
   uint64_t* ipsi_s = nullptr;
+  double* psi_f = nullptr;     // [n_mod][N] the same twiddles as doubles (exact below 2^53)
+  double* ipsi_f = nullptr;
   Mod* mods = nullptr;         // [n_mod]
   uint64_t* ninv = nullptr;    // [n_mod] N^{-1}
   uint64_t* ninv_s = nullptr;

@@ -21,6 +21,9 @@
 // global loads and stores coalesced).  Every twiddle a thread needs is read
 // before its stages run.  A workgroup handles COLS columns (column pass) or
 // chunks (row pass); COLS is picked per ring degree by the autotuner.
+// For the 50-bit Q primes (fp64 residue arithmetic below) the limb travels
+// between the two passes as the bit patterns of its doubles: the first pass
+// converts on load, the second on store.
 #include "internal.h"
 
 namespace ficgcn {
@@ -48,23 +51,28 @@ __device__ __forceinline__ void bf_inv(uint64_t& x, uint64_t& y, uint64_t w, uin
 // quotient estimate rint(hi * fl(1/q)) is within 1 of a*b/q (its error is
 // below hi/q * 2^-52 + 1/2 + |lo|/q < 1/4 + 1/2 + 1/4), so
 // r = (hi - qt*q) + lo, computed exactly by one fma and one add of integers
-// below 2^52, lies in (-q, q) and one correction makes it the residue.  The
+// below 2^52, lies in (-q, q) and one correction (r < 0: add q) makes it the
+// residue.  The
 // fp64 FMA runs at full rate, where a 64-bit integer Shoup multiply takes
 // about ten quarter-rate 32-bit multiplies; the results are the same words.
 // Values travel as the bit patterns of the doubles in the uint64 registers
 // and LDS words of the pass.
 __device__ __forceinline__ uint64_t f2b(double d) { return (uint64_t)__double_as_longlong(d); }
 __device__ __forceinline__ double b2f(uint64_t b) { return __longlong_as_double((long long)b); }
-__device__ __forceinline__ uint64_t to_fbits(uint64_t v) { return f2b((double)v); }
-__device__ __forceinline__ uint64_t from_fbits(uint64_t b) { return (uint64_t)b2f(b); }
+// Exact conversions for integers below 2^52: the double 2^52 + v has v as its
+// mantissa field, so the two directions are an OR / AND of the exponent bits
+// and one fp64 add (instead of the generic 64-bit conversion sequences).
+constexpr uint64_t TWO52_BITS = 0x4330000000000000ull;
+constexpr double TWO52 = 4503599627370496.0;
+__device__ __forceinline__ uint64_t to_fbits(uint64_t v) { return f2b(b2f(v | TWO52_BITS) - TWO52); }
+__device__ __forceinline__ uint64_t from_fbits(uint64_t b) { return f2b(b2f(b) + TWO52) & 0x000FFFFFFFFFFFFFull; }
 
 __device__ __forceinline__ double fmulmod(double a, double b, double q, double qinv) {
   const double hi = a * b;
   const double lo = fma(a, b, -hi);
   const double qt = rint(hi * qinv);
-  double r = fma(-qt, q, hi) + lo;
-  r = r < 0.0 ? r + q : r;
-  return r >= q ? r - q : r;
+  const double r = fma(-qt, q, hi) + lo;
+  return r < 0.0 ? r + q : r;
 }
 
 template <bool FP>
@@ -100,7 +108,8 @@ __device__ __forceinline__ void bfly_inv(uint64_t& x, uint64_t& y, uint64_t w, u
 // One pass over one sub-transform set of a limb; FP selects the fp64 residue arithmetic.
 template <int LOGC, int COLS, bool INV, bool ROW, bool FP>
 __device__ __forceinline__ void ntt_pass_body(uint64_t* s, uint64_t* a, const uint64_t* __restrict__ W,
-                                              const uint64_t* __restrict__ Ws, uint64_t q, int N, int mi,
+                                              const uint64_t* __restrict__ Ws, const double* __restrict__ Wf,
+                                              uint64_t q, int N, int mi,
                                               const uint64_t* __restrict__ ninv,
                                               const uint64_t* __restrict__ ninv_s) {
   constexpr int C = 1 << LOGC;
@@ -109,7 +118,7 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* s, uint64_t* a, const ui
   constexpr int LE = LOGC - LT;
   constexpr int EPT = 1 << LE;
   const double qd = (double)q, qinv = 1.0 / qd;
-  auto twv = [&](int k) { return FP ? to_fbits(W[k]) : W[k]; };
+  auto twv = [&](int k) { return FP ? f2b(Wf[k]) : W[k]; };
   auto tws = [&](int k) { return FP ? (uint64_t)0 : Ws[k]; };
   const int tid = threadIdx.x;
   // column pass: consecutive threads = consecutive columns (coalesced rows);
@@ -128,7 +137,7 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* s, uint64_t* a, const ui
   if (!INV) {
     // ---- load strided: x[u] = element r + TPC u
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) x[u] = FP ? to_fbits(g[(size_t)(r + TPC * u) * stride]) : g[(size_t)(r + TPC * u) * stride];
+    for (int u = 0; u < EPT; ++u) x[u] = FP && !ROW ? to_fbits(g[(size_t)(r + TPC * u) * stride]) : g[(size_t)(r + TPC * u) * stride];
     // ---- stages 0..LE-1 (t >= TPC) in registers
     {
       uint64_t w[EPT], ws[EPT];
@@ -188,7 +197,7 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* s, uint64_t* a, const ui
         pos += ng;
       }
     }
-    if (FP) {
+    if (FP && ROW) {
 #pragma unroll
       for (int v = 0; v < EPT; ++v) x[v] = from_fbits(x[v]);
     }
@@ -217,7 +226,7 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* s, uint64_t* a, const ui
 #pragma unroll
       for (int v = 0; v < EPT; ++v) x[v] = g[(size_t)(r * EPT + v) * stride];
     }
-    if (FP) {
+    if (FP && ROW) {
 #pragma unroll
       for (int v = 0; v < EPT; ++v) x[v] = to_fbits(x[v]);
     }
@@ -286,7 +295,7 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* s, uint64_t* a, const ui
 #pragma unroll
       for (int u = 0; u < EPT; ++u) x[u] = FP ? f2b(fmulmod(b2f(x[u]), nid, qd, qinv)) : mul_shoup(x[u], ni, nis, q);
     }
-    if (FP) {
+    if (FP && !ROW) {
 #pragma unroll
       for (int u = 0; u < EPT; ++u) x[u] = from_fbits(x[u]);
     }
@@ -299,8 +308,8 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* s, uint64_t* a, const ui
 template <int LOGC, int COLS, bool INV, bool ROW>
 __global__ __launch_bounds__((1 << (LOGC / 2)) * COLS) void k_ntt_pass(
     uint64_t* __restrict__ base, int log_n, LimbMap map, size_t poly_stride, const uint64_t* __restrict__ tw,
-    const uint64_t* __restrict__ tws, const Mod* __restrict__ mods, const uint64_t* __restrict__ ninv,
-    const uint64_t* __restrict__ ninv_s, int skip_alpha, int skip_q) {
+    const uint64_t* __restrict__ tws, const double* __restrict__ twf, const Mod* __restrict__ mods,
+    const uint64_t* __restrict__ ninv, const uint64_t* __restrict__ ninv_s, int skip_alpha, int skip_q) {
   constexpr int C = 1 << LOGC;
   constexpr int TPC = 1 << (LOGC / 2);
   // one pad word per EPT elements (row pass) or one group width per EPT rows
@@ -314,10 +323,11 @@ __global__ __launch_bounds__((1 << (LOGC / 2)) * COLS) void k_ntt_pass(
   uint64_t* a = base + poly * poly_stride + (size_t)limb * N;
   const uint64_t* W = tw + (size_t)mi * N;
   const uint64_t* Ws = tws + (size_t)mi * N;
+  const double* Wf = twf + (size_t)mi * N;
   if (q > (1ull << 49) && q < (1ull << 50))
-    ntt_pass_body<LOGC, COLS, INV, ROW, true>(s, a, W, Ws, q, N, mi, ninv, ninv_s);
+    ntt_pass_body<LOGC, COLS, INV, ROW, true>(s, a, W, Ws, Wf, q, N, mi, ninv, ninv_s);
   else
-    ntt_pass_body<LOGC, COLS, INV, ROW, false>(s, a, W, Ws, q, N, mi, ninv, ninv_s);
+    ntt_pass_body<LOGC, COLS, INV, ROW, false>(s, a, W, Ws, Wf, q, N, mi, ninv, ninv_s);
 }
 
 // ---- launch selection --------------------------------------------------------
@@ -326,11 +336,12 @@ static void launch_c(int logc, dim3 grid, hipStream_t st, uint64_t* base, int lo
                      const Tables& t, int sa, int sq) {
   const uint64_t* tw = INV ? t.ipsi : t.psi;
   const uint64_t* tws = INV ? t.ipsi_s : t.psi_s;
+  const double* twf = INV ? t.ipsi_f : t.psi_f;
   switch (logc) {
 #define CASE(L)                                                                                                   \
   case L:                                                                                                         \
     hipLaunchKernelGGL((k_ntt_pass<L, COLS, INV, ROW>), grid, dim3((1 << (L / 2)) * COLS), 0, st, base, log_n, map, \
-                       ps, tw, tws, t.mods, t.ninv, t.ninv_s, sa, sq);                                            \
+                       ps, tw, tws, twf, t.mods, t.ninv, t.ninv_s, sa, sq);                                       \
     break;
     CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9)
 #undef CASE
