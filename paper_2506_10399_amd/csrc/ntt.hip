@@ -57,6 +57,15 @@ __device__ __forceinline__ void bf_inv(uint64_t& x, uint64_t& y, uint64_t w, uin
 // about ten quarter-rate 32-bit multiplies; the results are the same words.
 // Values travel as the bit patterns of the doubles in the uint64 registers
 // and LDS words of the pass.
+//
+// Inside a transform the values are signed representatives in (-q, q):
+//   * the product of a in (-q, q) and a twiddle in [0, q) by the same steps
+//     without the correction stays in (-q, q) (|a*b| < q^2, so the estimate
+//     error is at most 1/4 + 1/2 + 1/8 of q);
+//   * a sum or difference t in (-2q, 2q) is brought back by t - q*rint(t/q),
+//     which lands in [-q/2 - 1, q/2 + 1] (t/q is known to 2^-51);
+// three fp64 operations each, in place of a compare, an add and two selects.
+// The last pass maps the values to [0, q) once.
 __device__ __forceinline__ uint64_t f2b(double d) { return (uint64_t)__double_as_longlong(d); }
 __device__ __forceinline__ double b2f(uint64_t b) { return __longlong_as_double((long long)b); }
 // Exact conversions for integers below 2^52: the double 2^52 + v has v as its
@@ -75,16 +84,25 @@ __device__ __forceinline__ double fmulmod(double a, double b, double q, double q
   return r < 0.0 ? r + q : r;
 }
 
+// signed product: a in (-q, q), b in [0, q) -> (-q, q)
+__device__ __forceinline__ double fmulmod_s(double a, double b, double q, double qinv) {
+  const double hi = a * b;
+  const double lo = fma(a, b, -hi);
+  const double qt = rint(hi * qinv);
+  return fma(-qt, q, hi) + lo;
+}
+// t in (-2q, 2q) -> (-q, q), congruent
+__device__ __forceinline__ double sred(double t, double q, double qinv) { return fma(-rint(t * qinv), q, t); }
+// (-q, q) -> [0, q)
+__device__ __forceinline__ double canon(double r, double q) { return r < 0.0 ? r + q : r; }
+
 template <bool FP>
 __device__ __forceinline__ void bfly_fwd(uint64_t& x, uint64_t& y, uint64_t w, uint64_t ws, uint64_t q, double qd,
                                          double qinv) {
   if (FP) {
-    const double xd = b2f(x), v = fmulmod(b2f(y), b2f(w), qd, qinv);
-    double yn = xd - v, xn = xd + v;
-    yn = yn < 0.0 ? yn + qd : yn;
-    xn = xn >= qd ? xn - qd : xn;
-    x = f2b(xn);
-    y = f2b(yn);
+    const double xd = b2f(x), v = fmulmod_s(b2f(y), b2f(w), qd, qinv);
+    x = f2b(sred(xd + v, qd, qinv));
+    y = f2b(sred(xd - v, qd, qinv));
   } else {
     bf_fwd(x, y, w, ws, q);
   }
@@ -95,11 +113,8 @@ __device__ __forceinline__ void bfly_inv(uint64_t& x, uint64_t& y, uint64_t w, u
                                          double qinv) {
   if (FP) {
     const double xd = b2f(x), yd = b2f(y);
-    double d = xd - yd, xn = xd + yd;
-    d = d < 0.0 ? d + qd : d;
-    xn = xn >= qd ? xn - qd : xn;
-    x = f2b(xn);
-    y = f2b(fmulmod(d, b2f(w), qd, qinv));
+    x = f2b(sred(xd + yd, qd, qinv));
+    y = f2b(fmulmod_s(sred(xd - yd, qd, qinv), b2f(w), qd, qinv));
   } else {
     bf_inv(x, y, w, ws, q);
   }
@@ -199,7 +214,7 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* s, uint64_t* a, const ui
     }
     if (FP && ROW) {
 #pragma unroll
-      for (int v = 0; v < EPT; ++v) x[v] = from_fbits(x[v]);
+      for (int v = 0; v < EPT; ++v) x[v] = from_fbits(f2b(canon(b2f(x[v]), qd)));
     }
     if (ROW) {
       // back to the strided layout for a coalesced store
