@@ -596,30 +596,40 @@ __global__ void k_group_mac(const MacTerm* __restrict__ terms, const int* __rest
   const size_t N = (size_t)1 << log_n;
   const size_t j = blockIdx.x * (size_t)KB + threadIdx.x;
   // limb slowest: one limb of every group's terms is in flight at a time, so
-  // ciphertexts shared by many groups (baby steps) are re-read from cache
+  // ciphertexts shared by many groups (baby steps) are re-read from cache.
+  // One thread takes both components of a coefficient: each plaintext word
+  // is read once for the two products.
   const int i = blockIdx.z;
-  const int g = blockIdx.y >> 1, comp = blockIdx.y & 1;
+  const int g = blockIdx.y;
   const Mod m = mods[i];
-  const size_t o = ((size_t)comp * l1 + i) * N + j;
+  const size_t o0 = (size_t)i * N + j, o1 = ((size_t)l1 + i) * N + j;
   uint64_t* out = outs[g];
-  uint64_t a = accumulate ? out[o] : 0;
-  u128 s = 0;
+  uint64_t a0 = accumulate ? out[o0] : 0, a1 = accumulate ? out[o1] : 0;
+  u128 s0 = 0, s1 = 0;
   int cnt = 0;
   for (int t = group_start[g]; t < group_start[g + 1]; ++t) {
     const MacTerm tm = terms[t];
-    const uint64_t x = tm.ct[tm.l1 ? ((size_t)comp * tm.l1 + i) * N + j : o];
+    const size_t c0 = tm.l1 ? (size_t)i * N + j : o0;
+    const size_t c1 = tm.l1 ? ((size_t)tm.l1 + i) * N + j : o1;
+    const uint64_t x0 = tm.ct[c0], x1 = tm.ct[c1];
     if (tm.pt) {
-      s += (u128)x * tm.pt[(size_t)i * N + j];
+      const uint64_t p = tm.pt[(size_t)i * N + j];
+      s0 += (u128)x0 * p;
+      s1 += (u128)x1 * p;
       if (++cnt == 8) {
-        a = add_mod(a, reduce128(s, m), m.q);
-        s = 0;
+        a0 = add_mod(a0, reduce128(s0, m), m.q);
+        a1 = add_mod(a1, reduce128(s1, m), m.q);
+        s0 = 0;
+        s1 = 0;
         cnt = 0;
       }
     } else {
-      a = add_mod(a, x, m.q);
+      a0 = add_mod(a0, x0, m.q);
+      a1 = add_mod(a1, x1, m.q);
     }
   }
-  out[o] = add_mod(a, reduce128(s, m), m.q);
+  out[o0] = add_mod(a0, reduce128(s0, m), m.q);
+  out[o1] = add_mod(a1, reduce128(s1, m), m.q);
 }
 
 void group_mac(ckks_ctx* c, int level, const std::vector<std::vector<MacTerm>>& groups,
@@ -640,8 +650,8 @@ void group_mac(ckks_ctx* c, int level, const std::vector<std::vector<MacTerm>>& 
   MacTerm* td = upload(c, S_GM_TERMS, flat);
   int* sd = upload(c, S_GM_START, start);
   uint64_t* const* od = upload(c, S_GM_OUT, outs);
-  if (2 * groups.size() > 65535) FICGCN_THROW(EINVAL_, "too many groups in one launch");
-  hipLaunchKernelGGL(k_group_mac, dim3(c->N / KB, 2 * groups.size(), level + 1), dim3(KB), 0, c->stream, td, sd, od,
+  if (groups.size() > 65535) FICGCN_THROW(EINVAL_, "too many groups in one launch");
+  hipLaunchKernelGGL(k_group_mac, dim3(c->N / KB, groups.size(), level + 1), dim3(KB), 0, c->stream, td, sd, od,
                      level + 1, accumulate ? 1 : 0, c->log_n, c->t.mods);
   HIPCHECK(hipGetLastError());
   stream_sync(c);
