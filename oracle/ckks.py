@@ -330,6 +330,38 @@ def rotate_masked_sum(prm: Params, keys: Keys, ct: Ciphertext, steps: Sequence[i
     return Ciphertext(c0=c0, c1=mod_down(prm, A1, lv), level=lv, scale=ct.scale)
 
 
+def rotate_sum(prm: Params, keys: Keys, cts: Sequence[Ciphertext], steps: Sequence[int]) -> Ciphertext:
+    """sum_g Rot_{k_g}(ct_g) over distinct ciphertexts with one ModDown (the
+    giant-step sum of the baby-step/giant-step SpIntra-CA form):
+    A = sum_g KeyInner(sigma_g(ModUp(c1_g))) over Q_l and P;
+    out = (ModDown(A_0) + sum_g sigma_g(c0_g),  ModDown(A_1)).
+    With one term this is rotate() word for word.  All inputs share level and
+    scale; every step is a nonzero rotation."""
+    if not cts or len(cts) != len(steps):
+        raise ValueError("one step per ciphertext, at least one")
+    lv = cts[0].level
+    qs = prm.q_level(lv)
+    basis = ext_basis(prm, lv)
+    A0 = np.zeros((len(basis), prm.N), dtype=np.uint64)
+    A1 = np.zeros_like(A0)
+    c0 = np.zeros((lv + 1, prm.N), dtype=np.uint64)
+    for ct, k in zip(cts, steps):
+        if ct.level != lv:
+            raise ValueError("level mismatch")
+        if k % prm.M == 0:
+            raise ValueError("the identity shift is a plain addition, not a key switch")
+        g = galois_element(k, prm)
+        if g not in keys.rot:
+            raise KeyError("no rotation key for step %d" % k)
+        D = [mod_up(prm, ct.c1, lv, dg) for dg in prm.digits(lv)]
+        acc0, acc1 = _key_inner(prm, [automorph(Dj, g, basis) for Dj in D], keys.rot[g], lv)
+        A0 = poly_add(A0, acc0, basis)
+        A1 = poly_add(A1, acc1, basis)
+        c0 = poly_add(c0, automorph(ct.c0, g, qs), qs)
+    return Ciphertext(c0=poly_add(mod_down(prm, A0, lv), c0, qs), c1=mod_down(prm, A1, lv), level=lv,
+                      scale=cts[0].scale)
+
+
 # ----------------------------------------------------------------------------
 # arithmetic
 # ----------------------------------------------------------------------------

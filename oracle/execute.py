@@ -277,13 +277,20 @@ def aggregate(prm: Params, plan: Plan, li: int, keys, y: ckks.Ciphertext, masks,
         giants = {}
         for d in lp.shifts:
             giants.setdefault(d // G, []).append(d)
+        # inner sums per giant step; the giant rotations are summed with one
+        # ModDown (their key inner products added on the key basis first)
+        rot_in, rot_k = [], []
         for g in sorted(giants):
             ds = giants[g]
             inner = ckks.pt_mul_acc(prm, _zero(prm, y.level, y.scale * st["sM"]),
                                     [rb[d % G] for d in ds], [masks[d] for d in ds])
-            if g != 0:
-                inner = ckks.rotate(prm, keys, inner, g * G)
-            acc = ckks.add(prm, acc, inner)
+            if (g * G) % prm.M == 0:
+                acc = ckks.add(prm, acc, inner)
+            else:
+                rot_in.append(inner)
+                rot_k.append(g * G)
+        if rot_in:
+            acc = ckks.add(prm, acc, ckks.rotate_sum(prm, keys, rot_in, rot_k))
     return ckks.rescale(prm, acc)
 
 

@@ -353,7 +353,16 @@ static void aggregate(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, int g, co
       rotate_one(c, ek, y, lv, b, dst);
       rb[b] = dst;
     }
+    // giant rotations: Sum_gi Rot_{gi G}(inner_gi) with one ModDown,
+    //   out += ModDown(Sum KeyInner(sigma(ModUp(inner_gi.c1)))) + Sum sigma(inner_gi.c0)
+    const int ext = l1 + c->alpha;
+    const int nd = (l1 + c->alpha - 1) / c->alpha;
     uint64_t* inner = (uint64_t*)c->buf(46, ct_words * 8);
+    uint64_t* D = (uint64_t*)c->buf(40, (size_t)nd * ext * N * 8);
+    uint64_t* acc = (uint64_t*)c->buf(41, (size_t)2 * ext * N * 8);
+    uint64_t* A = (uint64_t*)c->buf(78, (size_t)2 * ext * N * 8);
+    uint64_t* t = (uint64_t*)c->buf(79, ct_words * 8);   // (sigma(c0), 0)
+    bool any = false;
     for (auto& kv : giants) {
       int64_t gi = kv.first;
       zero_fill(c, inner, ct_words);
@@ -364,12 +373,27 @@ static void aggregate(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, int g, co
         m.p[0] = mask(si);
         pmul_acc(c, inner, a, m, 1, l1);
       }
-      if (gi != 0) {
-        rotate_one(c, ek, inner, lv, gi * G, rt);
-        add_inplace(c, out, rt, l1, 2);
-      } else {
+      uint64_t gal;
+      const uint64_t* key = gi != 0 ? rot_key(c, ek, gi * G, gal) : nullptr;
+      if (!key) {
         add_inplace(c, out, inner, l1, 2);
+        continue;
       }
+      if (!any) {
+        zero_fill(c, A, (size_t)2 * ext * N);
+        zero_fill(c, t + (size_t)l1 * N, (size_t)l1 * N);
+        any = true;
+      }
+      modup(c, inner + (size_t)l1 * N, lv, D);
+      keymac(c, acc, D, key, lv, gal);
+      mac_ext(c, A, acc, nullptr, lv);
+      automorph_ntt(c, t, inner, gal, l1, 1);
+      add_inplace(c, out, t, l1, 2);
+    }
+    if (any) {
+      uint64_t* md = (uint64_t*)c->buf(44, ct_words * 8);
+      moddown(c, A, lv, md, nullptr, 1, nullptr);
+      add_inplace(c, out, md, l1, 2);
     }
   }
   rescale_inplace(c, out, lv);
@@ -677,8 +701,8 @@ static void aggregate_batched(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, c
       }
     }
     group_mac(c, lv, groups, gouts, false);
-    // giant rotations summed into the outputs by the final ModDown step
-    keyswitch_batch(c, lv, isrc, jobs, outs, true);
+    // giant rotations of each output summed on the key basis, one ModDown per output
+    if (!jobs.empty()) keyswitch_masked_sum(c, lv, isrc, jobs, outs, true);
     group_mac(c, lv, ident, outs, true);
   }
   rescale_batch(c, lv, outs);

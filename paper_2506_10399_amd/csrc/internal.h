@@ -182,6 +182,7 @@ void rescale_inplace(ckks_ctx* c, uint64_t* ct, int level);
 void tensor(ckks_ctx* c, const uint64_t* x, const uint64_t* y, uint64_t* d, int level);
 void copy_d2d(ckks_ctx* c, void* dst, const void* src, size_t bytes);
 // A[c][i] += acc[c][i] (.) pt[i] on the key basis (Q_l limbs then P), both components
+// A (+)= acc (.) pt over the key basis Q_l then P (both components); pt null: A += acc
 void mac_ext(ckks_ctx* c, uint64_t* A, const uint64_t* acc, const uint64_t* pt, int level);
 // plaintexts on the key basis: [level+1+alpha][N], Q_l limbs then P, evaluation form
 void encode_batch_ext(ckks_ctx* c, const double* re, size_t count, size_t n, double scale, int level, uint64_t* dev);

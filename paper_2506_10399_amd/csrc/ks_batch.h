@@ -43,7 +43,8 @@ void keyswitch_batch(ckks_ctx* c, int level, const std::vector<const uint64_t*>&
 // for every output group, A = sum over its jobs of acc_r (.) pt_r on the key
 // basis (pt_r: [l+1+alpha][N], Q_l limbs then P limbs), then
 //   out_grp (+)= ( ModDown(A_0) + sum_r sigma_g(add0_r) (.) pt_r,  ModDown(A_1) ).
-// Every job needs pt; add1 is ignored.
+// A job without pt is taken unmasked (the plain sum of its rotation: the
+// giant steps of the baby-step/giant-step form); add1 is ignored.
 void keyswitch_masked_sum(ckks_ctx* c, int level, const std::vector<const uint64_t*>& sources,
                           const std::vector<KSJob>& jobs, const std::vector<uint64_t*>& outs, bool accumulate);
 void tensor_batch(ckks_ctx* c, int level, const std::vector<TensorJob>& jobs);

@@ -331,7 +331,9 @@ __global__ void k_mask_sum_ext(const uint64_t* __restrict__ acc, const KSJob* __
   int cnt = 0;
   uint64_t v = *a;
   for (int r = gd.start; r < gd.end; ++r) {
-    s += (u128)acc[(((size_t)r * 2 + comp) * ext + i) * N + j] * jobs[r].pt[(size_t)i * N + j];
+    const uint64_t x = acc[(((size_t)r * 2 + comp) * ext + i) * N + j];
+    const uint64_t* pt = jobs[r].pt;
+    s += pt ? (u128)x * pt[(size_t)i * N + j] : (u128)x;   // no mask: the plain sum
     if (++cnt == 8) {
       v = add_mod(v, reduce128(s, md), md.q);
       s = 0;
@@ -362,7 +364,8 @@ __global__ void k_masked_final(const uint64_t* __restrict__ A, const uint64_t* _
     for (int r = gr.start; r < gr.end; ++r) {
       const KSJob jb = jobs[r];
       if (!jb.add0) continue;
-      s += (u128)jb.add0[(size_t)i * N + (jb.g == 1 ? j : auto_idx(j, jb.g, log_n))] * jb.pt[(size_t)i * N + j];
+      const uint64_t x = jb.add0[(size_t)i * N + (jb.g == 1 ? j : auto_idx(j, jb.g, log_n))];
+      s += jb.pt ? (u128)x * jb.pt[(size_t)i * N + j] : (u128)x;
       if (++cnt == 8) {
         v = add_mod(v, reduce128(s, md), q);
         s = 0;
@@ -387,7 +390,7 @@ void keyswitch_masked_sum(ckks_ctx* c, int level, const std::vector<const uint64
   if (n_grp == 0) return;
   for (size_t r = 0; r < jobs.size(); ++r) {
     const KSJob& jb = jobs[r];
-    if (jb.src < 0 || jb.src >= (int)sources.size() || !sources[jb.src] || !jb.key || !jb.pt || jb.grp < 0 ||
+    if (jb.src < 0 || jb.src >= (int)sources.size() || !sources[jb.src] || !jb.key || jb.grp < 0 ||
         jb.grp >= n_grp || (r && jobs[r - 1].grp > jb.grp))
       FICGCN_THROW(EINVAL_, "bad masked key-switch job");
   }

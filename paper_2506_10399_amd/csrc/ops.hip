@@ -344,7 +344,7 @@ __global__ void k_mac_ext(uint64_t* __restrict__ A, const uint64_t* __restrict__
   const int i = blockIdx.y, c = blockIdx.z;
   const Mod m = mods[i < l1 ? i : i - l1 + L];
   const size_t o = ((size_t)c * ext + i) * N + j;
-  A[o] = add_mod(A[o], reduce128((u128)acc[o] * pt[(size_t)i * N + j], m), m.q);
+  A[o] = add_mod(A[o], pt ? reduce128((u128)acc[o] * pt[(size_t)i * N + j], m) : acc[o], m.q);
 }
 
 void mac_ext(ckks_ctx* c, uint64_t* A, const uint64_t* acc, const uint64_t* pt, int level) {

@@ -255,8 +255,10 @@ static double plan_bytes(const ficgcn_plan* p) {
       else if (lp.family == 4)   // inner products, their masked sum on the key basis, one ModDown
         per += modup(la) + nz * (inner(la) + limb * (3.0 * (la + 1 + a) + 2.0 * (la + 1))) + moddown(la) +
                limb * 4.0 * (la + 1 + a);
-      else
-        per += (babies.empty() ? 0.0 : modup(la) + babies.size() * ks_extra(la)) + giants.size() * ks_single(la);
+      else   // hoisted baby steps; giant steps summed on the key basis before one ModDown
+        per += (babies.empty() ? 0.0 : modup(la) + babies.size() * ks_extra(la)) +
+               giants.size() * (modup(la) + inner(la) + limb * (3.0 * (la + 1 + a) + 2.0 * (la + 1))) +
+               (giants.empty() ? 0.0 : moddown(la) + limb * 4.0 * (la + 1 + a));
       bytes += np * (per + rs(la));
       n_out_cts = np;
     }

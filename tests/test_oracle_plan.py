@@ -199,8 +199,8 @@ def test_gcn_normalisations():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("name,mode,fam", [("tiny", "inter", None), ("tiny", "spintra", None), ("tiny", "spintra", 4),
-                                           ("tiny2", "inter", None)])
+@pytest.mark.parametrize("name,mode,fam", [("tiny", "inter", None), ("tiny", "spintra", None), ("tiny", "spintra", 2),
+                                           ("tiny", "spintra", 4), ("tiny2", "inter", None)])
 def test_encrypted_plan_decrypts_to_fp64_gcn(name, mode, fam):
     w, rows = _rows(name)
     prm = Params.from_dict(w.params)

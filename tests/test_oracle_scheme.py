@@ -179,3 +179,35 @@ def test_masked_rotation_sum_slots_and_precision(small):
     assert np.array_equal(m_ext[: lv + 1], m_q) and m_ext.shape[0] == lv + 1 + prm.alpha
     with pytest.raises(ValueError):
         ckks.rotate_masked_sum(prm, keys, ct, [0], [m_ext])
+
+
+def test_rotation_sum_one_moddown(small):
+    """sum_g Rot_{k_g}(ct_g) over distinct ciphertexts with one ModDown: with one
+    term it is the rotation itself word for word; with several it decodes to
+    sum_g roll(z_g, -k_g), and its words differ from the sum of separate
+    rotations only by the ModDown roundings (a difference that decrypts to a
+    few units, far below the scale)."""
+    prm, keys = small
+    lv = prm.L - 1
+    zs = [rng.uniform(-1, 1, prm.M) for _ in range(3)]
+    cts = [ckks.encrypt(prm, 30 + i, i, keys.s, enc.encode(prm, z, prm.scale, lv)) for i, z in enumerate(zs)]
+    one = ckks.rotate_sum(prm, keys, [cts[0]], [5])
+    ref = ckks.rotate(prm, keys, cts[0], 5)
+    assert np.array_equal(one.c0, ref.c0) and np.array_equal(one.c1, ref.c1)
+    steps = [1, -7, 8]
+    out = ckks.rotate_sum(prm, keys, cts, steps)
+    got = np.real(enc.decode(prm, ckks.decrypt(prm, keys.s, out)))
+    want = sum(np.roll(z, -k) for z, k in zip(zs, steps))
+    assert np.max(np.abs(got - want)) < 1e-8
+    sep = None
+    for c, k in zip(cts, steps):
+        r = ckks.rotate(prm, keys, c, k)
+        sep = r if sep is None else ckks.add(prm, sep, r)
+    assert not np.array_equal(sep.c0, out.c0)   # three roundings against one
+    qs = prm.q_level(lv)
+    diff = ckks.Ciphertext(c0=ckks.poly_sub(out.c0, sep.c0, qs), c1=ckks.poly_sub(out.c1, sep.c1, qs), level=lv,
+                           scale=prm.scale)
+    d = ckks.to_signed_coeffs(prm, ckks.decrypt(prm, keys.s, diff))
+    assert max(abs(v) for v in d) < 2 ** 20
+    with pytest.raises(ValueError):
+        ckks.rotate_sum(prm, keys, [cts[0]], [0])
