@@ -315,32 +315,55 @@ struct MaskGroup {
   int start, end;   // job range (all jobs of the batch, sorted by group)
 };
 
-// A[grp][c][i] += sum_r acc_r[c][i] (.) pt_r[i] over the key basis (Q_l then P)
-__global__ void k_mask_sum_ext(const uint64_t* __restrict__ acc, const KSJob* __restrict__ jobs,
-                               const GroupDesc* __restrict__ groups, uint64_t* __restrict__ A, int ext, int l1, int L,
-                               int log_n, const Mod* __restrict__ mods) {
+// The key inner products of a group's jobs and their masked sum in one pass:
+// per job r, acc_r[c][i] = sum_d D_{src(r),d}[i][sigma_g(j)] * key_r[d][c][m(i)][j]
+// (reduced), then A[c][i] += acc_r[c][i] (.) pt_r[i] (or + acc_r without a
+// mask), both components per thread.  acc_r is never stored: the sums are
+// those of the batched key inner product followed by a masked sum of its
+// outputs, in the same order.
+__global__ void k_keymac_masked(const uint64_t* __restrict__ D, const KSJob* __restrict__ jobs,
+                                const GroupDesc* __restrict__ groups, int nd, int ext, int l1, int L, int n_mod,
+                                int log_n, const Mod* __restrict__ mods) {
   const size_t N = (size_t)1 << log_n;
   const uint32_t j = blockIdx.x * KB + threadIdx.x;
   const int i = blockIdx.y;
-  const int comp = blockIdx.z & 1;
-  const GroupDesc gd = groups[blockIdx.z >> 1];
+  const GroupDesc gd = groups[blockIdx.z];
   const int m = i < l1 ? i : i - l1 + L;
   const Mod md = mods[m];
-  uint64_t* a = gd.out + ((size_t)comp * ext + i) * N + j;   // gd.out: this group's A
-  u128 s = 0;
+  uint64_t* a0 = gd.out + (size_t)i * N + j;              // gd.out: this group's A
+  uint64_t* a1 = gd.out + ((size_t)ext + i) * N + j;
+  uint64_t v0 = *a0, v1 = *a1;
+  u128 t0 = 0, t1 = 0;
   int cnt = 0;
-  uint64_t v = *a;
   for (int r = gd.start; r < gd.end; ++r) {
-    const uint64_t x = acc[(((size_t)r * 2 + comp) * ext + i) * N + j];
-    const uint64_t* pt = jobs[r].pt;
-    s += pt ? (u128)x * pt[(size_t)i * N + j] : (u128)x;   // no mask: the plain sum
+    const KSJob jb = jobs[r];
+    const uint32_t jj = jb.g == 1 ? j : auto_idx(j, jb.g, log_n);
+    const uint64_t* Du = D + (size_t)jb.src * nd * ext * N;
+    u128 s0 = 0, s1 = 0;
+    for (int d = 0; d < nd; ++d) {
+      const u128 x = Du[((size_t)d * ext + i) * N + jj];
+      s0 += x * jb.key[(((size_t)d * 2 + 0) * n_mod + m) * N + j];
+      s1 += x * jb.key[(((size_t)d * 2 + 1) * n_mod + m) * N + j];
+    }
+    const uint64_t x0 = reduce128(s0, md), x1 = reduce128(s1, md);
+    if (jb.pt) {
+      const uint64_t p = jb.pt[(size_t)i * N + j];
+      t0 += (u128)x0 * p;
+      t1 += (u128)x1 * p;
+    } else {
+      t0 += x0;
+      t1 += x1;
+    }
     if (++cnt == 8) {
-      v = add_mod(v, reduce128(s, md), md.q);
-      s = 0;
+      v0 = add_mod(v0, reduce128(t0, md), md.q);
+      v1 = add_mod(v1, reduce128(t1, md), md.q);
+      t0 = 0;
+      t1 = 0;
       cnt = 0;
     }
   }
-  *a = add_mod(v, reduce128(s, md), md.q);
+  *a0 = add_mod(v0, reduce128(t0, md), md.q);
+  *a1 = add_mod(v1, reduce128(t1, md), md.q);
 }
 
 // out_grp (+)= (A_Q - conv) P^-1  [+ sum_r sigma_g(add0_r) (.) pt_r on component 0]
@@ -400,7 +423,7 @@ void keyswitch_masked_sum(ckks_ctx* c, int level, const std::vector<const uint64
   // one accumulator on the key basis per output, summed over every chunk
   uint64_t* A = (uint64_t*)dev_scratch(c, S_KM_A, (size_t)n_grp * 2 * ext * N * 8);
   zero_fill(c, A, (size_t)n_grp * 2 * ext * N);
-  const size_t per_job = (size_t)2 * ext * N * 8;
+  const size_t per_job = 0;   // a job's products go straight into its output's accumulator
   const size_t per_src = (size_t)(nd * ext + l1) * N * 8;
   DigitTables dt{};
   for (int d = 0; d < nd; ++d) {
@@ -439,13 +462,12 @@ void keyswitch_masked_sum(ckks_ctx* c, int level, const std::vector<const uint64
       else
         gds.back().end = (int)r + 1;
     }
-    const int U = (int)srcs.size(), R = (int)cj.size();
+    const int U = (int)srcs.size();
     KSJob* jd = upload(c, S_KB_JOBS, cj);
     const uint64_t* const* sd = upload(c, S_KB_SRC, srcs);
     GroupDesc* gd = upload(c, S_KM_CGRP, gds);
     uint64_t* tmp = (uint64_t*)dev_scratch(c, S_KB_TMP, (size_t)U * l1 * N * 8);
     uint64_t* D = (uint64_t*)dev_scratch(c, S_KB_D, (size_t)U * nd * ext * N * 8);
-    uint64_t* acc = (uint64_t*)dev_scratch(c, S_KB_ACC, (size_t)R * 2 * ext * N * 8);
     {
       ProfScope pm(c, "modup");
       hipLaunchKernelGGL(k_gather, dim3(N / KB, l1, U), dim3(KB), 0, c->stream, tmp, sd, l1, c->log_n);
@@ -458,11 +480,9 @@ void keyswitch_masked_sum(ckks_ctx* c, int level, const std::vector<const uint64
     }
     {
       ProfScope pk(c, "keymac");
-      hipLaunchKernelGGL(k_keymac_batch, dim3(N / KB, ext, R), dim3(KB), 0, c->stream, acc, D, jd, nd, ext, l1, c->L,
-                         c->n_mod(), c->log_n, c->t.mods);
-      HIPCHECK(hipGetLastError());
-      hipLaunchKernelGGL(k_mask_sum_ext, dim3(N / KB, ext, 2 * gds.size()), dim3(KB), 0, c->stream, acc, jd, gd, A,
-                         ext, l1, c->L, c->log_n, c->t.mods);
+      if (gds.size() > 65535) FICGCN_THROW(EINVAL_, "too many outputs in one launch");
+      hipLaunchKernelGGL(k_keymac_masked, dim3(N / KB, ext, gds.size()), dim3(KB), 0, c->stream, D, jd, gd, nd, ext, l1,
+                         c->L, c->n_mod(), c->log_n, c->t.mods);
       HIPCHECK(hipGetLastError());
     }
     stream_sync(c);
