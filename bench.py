@@ -70,14 +70,16 @@ def measured_traffic():
     return rec.get("bytes_per_launch") if rec.get("source_sha256") == digest else None
 
 
-def cpu_baseline(params, plan_info, op_counts, sample_features=12):
-    """The CPU oracle on a bounded sample of the same workload, scaled to one
-    inference by the plan's operation counts."""
+def oracle_op_sample(params, K, F_out, la, lr, sample_features=12):
+    """Per-operation seconds of the CPU oracle on a bounded sample of the
+    workload: one layer-1 feature column (Inter-CA PMult over the K copies +
+    F_out scalar MACs, averaged over `sample_features` columns), one rotation
+    and one mask PMult at the aggregation level la, one relinearised square
+    and one rescale at level lr."""
     from oracle import ckks, encoding as enc
     from oracle.params import Params
     prm = Params.from_dict(params)
     rng = np.random.default_rng(0)
-    t_total = 0.0
     timings = {}
     keys = ckks.keygen(prm, 1, [1], relin=True)
     lv = prm.L - 1
@@ -86,8 +88,6 @@ def cpu_baseline(params, plan_info, op_counts, sample_features=12):
         z = rng.uniform(-1, 1, prm.M)
         return ckks.encrypt(prm, 2, cid, keys.s, enc.encode(prm, z, prm.scale, level))
 
-    K = plan_info[0]["K"]
-    F_out = plan_info[0]["f_out"]
     cts = [ct_at(lv, i) for i in range(K)]
     pts = [enc.encode(prm, rng.uniform(0, 1, prm.M), float(prm.q[lv]), lv) for _ in range(K)]
     t0 = time.perf_counter()
@@ -97,7 +97,6 @@ def cpu_baseline(params, plan_info, op_counts, sample_features=12):
         for l in range(F_out):
             acc = ckks.scalar_mul_acc(prm, acc, [z], [12345 + l])
     timings["inter_feature"] = (time.perf_counter() - t0) / sample_features
-    la = plan_info[1]["level_in"] - 2   # aggregation level of layer 2
     y = ct_at(la, 99)
     keys3 = ckks.keygen(prm, 1, [3], relin=False)
     t0 = time.perf_counter()
@@ -107,7 +106,6 @@ def cpu_baseline(params, plan_info, op_counts, sample_features=12):
     t0 = time.perf_counter()
     ckks.pt_mul_acc(prm, ckks.zero_ct(prm, la, 1.0), [y], [mask])
     timings["mask_mac"] = time.perf_counter() - t0
-    lr = plan_info[0]["level_out"]
     h = ct_at(lr, 98)
     t0 = time.perf_counter()
     ckks.ct_mul_relin(prm, keys, h, h)
@@ -115,19 +113,56 @@ def cpu_baseline(params, plan_info, op_counts, sample_features=12):
     t0 = time.perf_counter()
     ckks.rescale(prm, h)
     timings["rescale"] = time.perf_counter() - t0
-    sample_s = sum(timings.values())
+    return timings
+
+
+def oracle_sample_all_cores(params, K, F_out, la, lr, workers):
+    """The same sample in `workers` fresh processes at once (spawned before
+    this process touches the GPU); returns each process's timings."""
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(workers) as pool:
+        return pool.starmap(oracle_op_sample, [(params, K, F_out, la, lr)] * workers)
+
+
+def sample_levels(plan_info):
+    """K, F', aggregation level of layer 2 and the level of layer 1's squares."""
+    return plan_info[0]["K"], plan_info[0]["f_out"], plan_info[1]["level_in"] - 2, plan_info[0]["level_out"]
+
+
+def extrapolate(timings, F, op_counts):
+    return (timings["inter_feature"] * F + timings["rotation_agg_level"] * op_counts["rot"]
+            + timings["mask_mac"] * op_counts["mask_pmult"] + timings["relin"] * op_counts["cmult"]
+            + timings["rescale"] * op_counts["rescale"])
+
+
+def cpu_baseline(params, plan_info, op_counts, all_core=None, sample_features=12):
+    """The CPU oracle on a bounded sample of the same workload, scaled to one
+    inference by the plan's operation counts: single-threaded (the value), and,
+    when given, the all-core figure from the processes that ran the same sample
+    at once (the inference's independent operations split over the cores)."""
+    K, F_out, la, lr = sample_levels(plan_info)
+    timings = oracle_op_sample(params, K, F_out, la, lr, sample_features)
+    sample_s = sum(timings.values()) - timings["inter_feature"] + timings["inter_feature"] * sample_features
     F = plan_info[0]["f_in"]
-    est = (timings["inter_feature"] * F + timings["rotation_agg_level"] * op_counts["rot"]
-           + timings["mask_mac"] * op_counts["mask_pmult"] + timings["relin"] * op_counts["cmult"]
-           + timings["rescale"] * op_counts["rescale"])
-    return dict(value=est * 1e3, unit="ms", cores=1, kind="oracle",
-                sample=("oracle on this host, single thread: %d of %d layer-1 feature columns (Inter-CA "
-                        "PMult over %d copies + %d scalar MACs), one rotation and one mask PMult at the "
-                        "aggregation level, one relinearised square, one rescale; scaled by the plan's "
-                        "counts (%d rotations, %d mask PMults, %d squares, %d rescales); sample %.1f s"
-                        % (sample_features, F, K, F_out, op_counts["rot"], op_counts["mask_pmult"],
-                           op_counts["cmult"], op_counts["rescale"], sample_s * sample_features)),
-                per_op_s=timings)
+    est = extrapolate(timings, F, op_counts)
+    out = dict(value=est * 1e3, unit="ms", cores=1, kind="oracle",
+               sample=("oracle on this host, single thread: %d of %d layer-1 feature columns (Inter-CA "
+                       "PMult over %d copies + %d scalar MACs), one rotation and one mask PMult at the "
+                       "aggregation level, one relinearised square, one rescale; scaled by the plan's "
+                       "counts (%d rotations, %d mask PMults, %d squares, %d rescales); sample %.1f s"
+                       % (sample_features, F, K, F_out, op_counts["rot"], op_counts["mask_pmult"],
+                          op_counts["cmult"], op_counts["rescale"], sample_s)),
+               per_op_s=timings)
+    if all_core:
+        P = len(all_core)
+        mean = {k: float(np.mean([t[k] for t in all_core])) for k in timings}
+        out["all_cores"] = dict(value=extrapolate(mean, F, op_counts) * 1e3 / P, unit="ms", cores=P,
+                                sample=("the same sample in %d processes at once; per-operation times averaged "
+                                        "over them, scaled by the plan's counts and divided by %d (the "
+                                        "inference's feature columns, rotations and squares are independent)"
+                                        % (P, P)),
+                                per_op_s=mean)
+    return out
 
 
 def main():
@@ -178,7 +213,6 @@ def main():
     from paper_2506_10399_amd import ficgcn as fg, graph, costmodel as cm
     from workload import make_workload
 
-    torch.cuda.set_device(0)
     t_setup = time.perf_counter()
     kw = {}
     if args.features:
@@ -190,6 +224,15 @@ def main():
     dims = w.meta["dims"]
     rp, col, val = graph.normalize(w.graph.n, w.neighbors, w.norm)
     ctx = fg.Context.from_dict(w.params)
+    all_core = None
+    if not args.skip_cpu:
+        # the oracle's all-core sample first, in fresh processes, while this
+        # process has not touched the GPU (plans are built on the host)
+        workers = max(1, min(16, os.cpu_count() or 1))
+        info0 = fg.Plan(ctx, rp, col, val, w.graph.n, dims, w.weights, activation=w.activation).ficgcn_plan_info()
+        log("cpu baseline, all cores (%d processes)..." % workers)
+        all_core = oracle_sample_all_cores(w.params, *sample_levels(info0), workers)
+    torch.cuda.set_device(0)
     prm = w.params
     N = 1 << prm["log_n"]
     M = N // 2
@@ -397,8 +440,8 @@ def main():
                       cmult=info[0]["n_out_cts"] + info[1]["n_out_cts"],
                       rescale=2 * info[0]["n_out_cts"] + 2 * info[1]["f_out"] + info[1]["n_out_cts"])
         log("cpu baseline (oracle sample)...")
-        cpu = cpu_baseline(prm, info, counts)
-        log("cpu baseline: %.0f ms extrapolated" % cpu["value"])
+        cpu = cpu_baseline(prm, info, counts, all_core)
+        log("cpu baseline: %.0f ms extrapolated (all cores: %s)" % (cpu["value"], cpu.get("all_cores", {}).get("value")))
 
     out = dict(metric=METRIC, value=round(ms_step, 3), unit="ms", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=round(ms_step, 3), higher_is_better=False, scaling="weak", vs_baseline=None,
