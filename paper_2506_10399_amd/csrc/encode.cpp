@@ -38,9 +38,14 @@ static const FftTables& tables(size_t n) {
   return cache[n] = t;
 }
 
-static void fft(std::vector<cd>& a, bool inverse) {
+// (a.re c.re - a.im c.im, a.re c.im + a.im c.re): the product std::complex
+// computes for finite values, without its out-of-line NaN/infinity handling
+static inline cd cmul(cd a, cd c) {
+  return cd(a.real() * c.real() - a.imag() * c.imag(), a.real() * c.imag() + a.imag() * c.real());
+}
+
+static void fft(std::vector<cd>& a, bool inverse, const FftTables& T) {
   const size_t n = a.size();
-  const FftTables& T = tables(n);
   for (size_t i = 1, j = 0; i < n; ++i) {
     size_t bit = n >> 1;
     for (; j & bit; bit >>= 1) j ^= bit;
@@ -53,7 +58,7 @@ static void fft(std::vector<cd>& a, bool inverse) {
       for (size_t k = 0; k < len / 2; ++k) {
         cd w = T.root[k * step];
         if (inverse) w = std::conj(w);
-        cd u = a[i + k], v = a[i + k + len / 2] * w;
+        cd u = a[i + k], v = cmul(a[i + k + len / 2], w);
         a[i + k] = u + v;
         a[i + k + len / 2] = u - v;
       }
@@ -61,30 +66,36 @@ static void fft(std::vector<cd>& a, bool inverse) {
   }
 }
 
-static std::vector<uint32_t> slot_exponents(int N) {
+// 5^j mod 2N for the N/2 slots, cached per N
+static const std::vector<uint32_t>& slot_exponents(int N) {
+  static std::mutex mu;
+  static std::map<int, std::vector<uint32_t>> cache;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find(N);
+  if (it != cache.end()) return it->second;
   std::vector<uint32_t> r(N / 2);
   uint64_t x = 1;
   for (int j = 0; j < N / 2; ++j) {
     r[j] = (uint32_t)x;
     x = x * 5 % (2 * (uint64_t)N);
   }
-  return r;
+  return cache[N] = r;
 }
 
 // coefficients (rounded, signed) of the encoding of z at `scale`
 void encode_coeffs(int N, const double* re, const double* im, size_t n, double scale, std::vector<int64_t>& out) {
-  std::vector<uint32_t> r = slot_exponents(N);
+  const std::vector<uint32_t>& r = slot_exponents(N);
+  const FftTables& T = tables(N);
   std::vector<cd> v(N, cd(0, 0));
   for (size_t j = 0; j < (size_t)N / 2; ++j) {
     cd z = j < n ? cd(re ? re[j] : 0.0, im ? im[j] : 0.0) : cd(0, 0);
     v[(r[j] - 1) / 2] = z;
     v[((2 * N - r[j]) - 1) / 2] = std::conj(z);
   }
-  fft(v, false);
-  const FftTables& T = tables(N);
+  fft(v, false, T);
   out.resize(N);
   for (int i = 0; i < N; ++i) {
-    double m = (T.twist[i] * v[i]).real() / N * scale;
+    double m = cmul(T.twist[i], v[i]).real() / N * scale;
     if (!(std::fabs(m) < 9.2e18)) FICGCN_THROW(ESCALE_, "encoded coefficient exceeds 63 bits");
     out[i] = (int64_t)std::nearbyint(m);
   }
@@ -93,9 +104,9 @@ void encode_coeffs(int N, const double* re, const double* im, size_t n, double s
 void decode_values(int N, const std::vector<double>& m, double scale, double* re, double* im, size_t n) {
   std::vector<cd> w(N);
   const FftTables& T = tables(N);
-  for (int i = 0; i < N; ++i) w[i] = cd(m[i] / scale, 0) * std::conj(T.twist[i]);
-  fft(w, true);
-  std::vector<uint32_t> r = slot_exponents(N);
+  for (int i = 0; i < N; ++i) w[i] = cmul(cd(m[i] / scale, 0), std::conj(T.twist[i]));
+  fft(w, true, T);
+  const std::vector<uint32_t>& r = slot_exponents(N);
   for (size_t j = 0; j < n && j < (size_t)N / 2; ++j) {
     cd z = w[(r[j] - 1) / 2];
     if (re) re[j] = z.real();
