@@ -3,7 +3,6 @@
 // thread-local message.
 #include <cstring>
 #include <string>
-#include <thread>
 #include <vector>
 
 #include "../../include/ficgcn.h"
@@ -11,7 +10,6 @@
 #include "ks_batch.h"
 
 namespace ficgcn {
-void encode_coeffs(int N, const double* re, const double* im, size_t n, double scale, std::vector<int64_t>& out);
 void decode_values(int N, const std::vector<double>& m, double scale, double* re, double* im, size_t n);
 void crt_center(const std::vector<uint64_t>& mods, const uint64_t* res, int N, std::vector<double>& out);
 
@@ -45,23 +43,6 @@ static void check_level(const ckks_ctx* c, uint32_t level) {
   REQUIRE((int)level < c->L, ELEVEL_, "level " + std::to_string(level) + " >= number of Q primes");
 }
 
-// residues of signed coefficients into [k][N] over the first k Q primes
-// residues of m for the first k moduli of the chain, or (ext_level >= 0) for
-// Q_0..Q_ext_level followed by the special primes
-static void to_residues(const ckks_ctx* c, const std::vector<int64_t>& m, int k, std::vector<uint64_t>& out,
-                        int ext_level = -1) {
-  const size_t N = c->N;
-  out.resize((size_t)k * N);
-  for (int i = 0; i < k; ++i) {
-    uint64_t q = c->mod[ext_level >= 0 && i > ext_level ? c->L + i - ext_level - 1 : i];
-    for (size_t j = 0; j < N; ++j) {
-      int64_t v = m[j];
-      uint64_t a = v >= 0 ? (uint64_t)v % q : (q - (uint64_t)(-(v + 1)) % q - 1) % q;
-      out[i * N + j] = a;
-    }
-  }
-}
-
 static void upload_ntt(ckks_ctx* c, const uint64_t* host, int n_limbs, uint64_t* dev, int n_polys,
                        int ext_level = -1) {
   const size_t bytes = (size_t)n_polys * n_limbs * c->N * 8;
@@ -72,16 +53,7 @@ static void upload_ntt(ckks_ctx* c, const uint64_t* host, int n_limbs, uint64_t*
 
 void encode_batch_ext(ckks_ctx* c, const double* re, size_t count, size_t n, double scale, int level,
                       uint64_t* dev) {
-  const size_t N = c->N;
-  const int k = level + 1 + c->alpha;
-  const size_t per = (size_t)k * N;
-  std::vector<int64_t> m;
-  std::vector<uint64_t> r;
-  for (size_t b = 0; b < count; ++b) {
-    encode_coeffs(c->N, re + b * n, nullptr, n, scale, m);
-    to_residues(c, m, k, r, level);
-    upload_ntt(c, r.data(), k, dev + b * per, 1, level);
-  }
+  encode_gpu(c, re, nullptr, count, n, scale, level + 1 + c->alpha, lm_ext(level, c->L), dev);
 }
 
 void pt_load_ext(ckks_ctx* c, const uint64_t* host, int level, uint64_t* dev) {
@@ -296,11 +268,7 @@ ficgcn_status ckks_encode(ckks_ctx* ctx, const double* re, const double* im, siz
     check_level(ctx, level);
     REQUIRE(pt_dev && (re || n == 0), EINVAL_, "null argument");
     REQUIRE(n <= (size_t)ctx->N / 2, EINVAL_, "more values than slots");
-    std::vector<int64_t> m;
-    encode_coeffs(ctx->N, re, im, n, scale, m);
-    std::vector<uint64_t> r;
-    to_residues(ctx, m, level + 1, r);
-    upload_ntt(ctx, r.data(), level + 1, pt_dev, 1);
+    encode_gpu(ctx, re, im, 1, n, scale, (int)level + 1, lm_q((int)level + 1), pt_dev);
   });
 }
 
@@ -311,34 +279,7 @@ ficgcn_status ckks_encode_batch(ckks_ctx* ctx, const double* re, size_t count, s
     check_level(ctx, level);
     REQUIRE(pt_dev && re, EINVAL_, "null argument");
     REQUIRE(n <= (size_t)ctx->N / 2, EINVAL_, "more values than slots");
-    const size_t N = ctx->N;
-    const int l1 = level + 1;
-    const size_t per = (size_t)l1 * N;
-    const size_t chunk = 64;
-    std::vector<uint64_t> host(chunk * per);
-    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    for (size_t b0 = 0; b0 < count; b0 += chunk) {
-      size_t nb = std::min(chunk, count - b0);
-      std::vector<std::thread> th;
-      std::vector<std::string> errs(nt);
-      for (unsigned t = 0; t < nt; ++t)
-        th.emplace_back([&, t] {
-          try {
-            std::vector<int64_t> m;
-            std::vector<uint64_t> r;
-            for (size_t b = t; b < nb; b += nt) {
-              encode_coeffs(ctx->N, re + (b0 + b) * n, nullptr, n, scale, m);
-              to_residues(ctx, m, l1, r);
-              std::memcpy(host.data() + b * per, r.data(), per * 8);
-            }
-          } catch (const Error& e) {
-            errs[t] = e.msg;
-          }
-        });
-      for (auto& x : th) x.join();
-      for (auto& e : errs) REQUIRE(e.empty(), ESCALE_, e);
-      upload_ntt(ctx, host.data(), l1, pt_dev + b0 * per, (int)nb);
-    }
+    encode_gpu(ctx, re, nullptr, count, n, scale, (int)level + 1, lm_q((int)level + 1), pt_dev);
   });
 }
 

@@ -291,8 +291,10 @@ ckks_ctx::~ckks_ctx() {
     if (s.first) (void)hipFree(s.first);
   for (uint64_t* p : {t.psi, t.psi_s, t.ipsi, t.ipsi_s, t.ninv, t.ninv_s})
     if (p) (void)hipFree(p);
-  for (double* p : {t.psi_f, t.ipsi_f})
+  for (double* p : {t.psi_f, t.ipsi_f, enc_root, enc_twist})
     if (p) (void)hipFree(p);
+  if (enc_pos) (void)hipFree(enc_pos);
+  if (enc_flag) (void)hipFree(enc_flag);
   if (t.mods) (void)hipFree(t.mods);
   for (auto& kv : modup) { (void)hipFree(kv.second.dev); (void)hipFree(kv.second.idx); }
   for (auto& kv : moddown) { (void)hipFree(kv.second.dev); (void)hipFree(kv.second.idx); }

@@ -1,8 +1,9 @@
-// Client-side canonical-embedding encode/decode (host, FP64).
+// Canonical-embedding tables and decode (host, FP64).
 //
 // Slot j of m(X) in Z[X]/(X^N+1) is m(zeta^(5^j)), zeta = exp(i pi / N); the
-// conjugate slots sit at zeta^(-5^j).  Encoding evaluates the inverse
-// embedding with one complex FFT over the N odd powers of zeta:
+// conjugate slots sit at zeta^(-5^j).  Encoding (on the device, from the
+// tables built here) evaluates the inverse embedding with one complex FFT
+// over the N odd powers of zeta:
 //   v_s = value at zeta^(2s+1),  m_i = Re(exp(-i pi i / N) FFT(v)_i) / N,
 // then rounds half-to-even after scaling.  Decoding CRT-lifts each
 // coefficient exactly (multi-word integers), centres it, divides by the scale
@@ -82,22 +83,23 @@ static const std::vector<uint32_t>& slot_exponents(int N) {
   return cache[N] = r;
 }
 
-// coefficients (rounded, signed) of the encoding of z at `scale`
-void encode_coeffs(int N, const double* re, const double* im, size_t n, double scale, std::vector<int64_t>& out) {
-  const std::vector<uint32_t>& r = slot_exponents(N);
+void encode_tables(int N, std::vector<double>& root, std::vector<double>& twist, std::vector<uint32_t>& pos) {
   const FftTables& T = tables(N);
-  std::vector<cd> v(N, cd(0, 0));
-  for (size_t j = 0; j < (size_t)N / 2; ++j) {
-    cd z = j < n ? cd(re ? re[j] : 0.0, im ? im[j] : 0.0) : cd(0, 0);
-    v[(r[j] - 1) / 2] = z;
-    v[((2 * N - r[j]) - 1) / 2] = std::conj(z);
+  const std::vector<uint32_t>& r = slot_exponents(N);
+  root.resize((size_t)N);
+  for (int k = 0; k < N / 2; ++k) {
+    root[2 * k] = T.root[k].real();
+    root[2 * k + 1] = T.root[k].imag();
   }
-  fft(v, false, T);
-  out.resize(N);
+  twist.resize((size_t)2 * N);
   for (int i = 0; i < N; ++i) {
-    double m = cmul(T.twist[i], v[i]).real() / N * scale;
-    if (!(std::fabs(m) < 9.2e18)) FICGCN_THROW(ESCALE_, "encoded coefficient exceeds 63 bits");
-    out[i] = (int64_t)std::nearbyint(m);
+    twist[2 * i] = T.twist[i].real();
+    twist[2 * i + 1] = T.twist[i].imag();
+  }
+  pos.resize((size_t)N);
+  for (int j = 0; j < N / 2; ++j) {
+    pos[2 * j] = (r[j] - 1) / 2;
+    pos[2 * j + 1] = ((2 * (uint32_t)N - r[j]) - 1) / 2;
   }
 }
 

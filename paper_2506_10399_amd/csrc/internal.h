@@ -96,6 +96,11 @@ struct ckks_ctx {
   // ks_batch.hip 50-64 and 80-89, search.cpp 65-66 (a slot's memory moves when it grows, so one
   // user per slot)
   std::vector<std::pair<void*, size_t>> scratch;
+  // device tables of the GPU encoder (built on its first use)
+  double* enc_root = nullptr;    // [N/2] (re, im)
+  double* enc_twist = nullptr;   // [N] (re, im)
+  uint32_t* enc_pos = nullptr;   // [N] slot j -> FFT input of the slot and of its conjugate
+  int* enc_flag = nullptr;       // set when a coefficient leaves 63 bits
   // kernel timing (HIP events on `stream`), see ficgcn_profile_enable
   bool profiling = false;
   std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof;
@@ -181,12 +186,23 @@ void moddown(ckks_ctx* c, uint64_t* acc, int level, uint64_t* out, const uint64_
 void rescale_inplace(ckks_ctx* c, uint64_t* ct, int level);
 void tensor(ckks_ctx* c, const uint64_t* x, const uint64_t* y, uint64_t* d, int level);
 void copy_d2d(ckks_ctx* c, void* dst, const void* src, size_t bytes);
-// A[c][i] += acc[c][i] (.) pt[i] on the key basis (Q_l limbs then P), both components
 // A (+)= acc (.) pt over the key basis Q_l then P (both components); pt null: A += acc
 void mac_ext(ckks_ctx* c, uint64_t* A, const uint64_t* acc, const uint64_t* pt, int level);
 // plaintexts on the key basis: [level+1+alpha][N], Q_l limbs then P, evaluation form
 void encode_batch_ext(ckks_ctx* c, const double* re, size_t count, size_t n, double scale, int level, uint64_t* dev);
 void pt_load_ext(ckks_ctx* c, const uint64_t* host, int level, uint64_t* dev);
+
+// ---- encoding (encode.cpp on the host, encode_gpu.hip on the device) ----
+// host tables of the canonical-embedding encoder: root[k] = exp(-2 pi i k / N)
+// (k < N/2) and twist[i] = exp(-i pi i / N) (i < N) as (re, im) pairs; pos[2j],
+// pos[2j+1] = the FFT inputs of slot j and of its conjugate
+void encode_tables(int N, std::vector<double>& root, std::vector<double>& twist, std::vector<uint32_t>& pos);
+// count plaintexts of the slot values re (and im, may be null) [count][n], at
+// `scale`, as residues over n_limbs limbs (modulus lm_mod(map, i)) in
+// evaluation form: dev [count][n_limbs][N].  ESCALE if a coefficient leaves
+// 63 bits.
+void encode_gpu(ckks_ctx* c, const double* re, const double* im, size_t count, size_t n, double scale, int n_limbs,
+                LimbMap map, uint64_t* dev);
 
 // ---- sampling (sample.hip) ----
 void sample_uniform(ckks_ctx* c, uint64_t* out, uint64_t seed, uint32_t kind, uint32_t a, uint32_t b0,
