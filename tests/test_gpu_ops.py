@@ -186,3 +186,23 @@ def test_encoder_decodes_within_precision(env):
     assert np.mean(m != want) < 1e-3
     back = enc.decode(prm, ckks.Plaintext(m=m, level=lv, scale=prm.scale))
     assert np.abs(back - z).max() < 1e-9
+
+
+def test_batch_encoder_at_mask_scale_and_range_error(env):
+    """The device encoder in batches at the scale masks use (the prime the next
+    rescale drops, about 2^50): a small fraction of coefficients may round the
+    other way than the oracle's independent FFT, the decoded slots agree to
+    1e-9; coefficients beyond 63 bits are rejected with ESCALE."""
+    prm, ctx, fg = env["prm"], env["ctx"], env["fg"]
+    lv = prm.L - 1
+    rows = env["rng"].uniform(-1, 1, (5, prm.M))
+    sM = float(prm.q[lv])
+    d = ctx.ckks_encode_batch(rows, sM, lv)
+    for i in range(len(rows)):
+        m = ctx.ckks_poly_store(d[i], lv, 1)[0]
+        want = enc.encode(prm, rows[i], sM, lv).m
+        assert np.mean(m != want) < 0.05
+        back = enc.decode(prm, ckks.Plaintext(m=m, level=lv, scale=sM))
+        assert np.abs(back - rows[i]).max() < 1e-9
+    with pytest.raises(fg.FicgcnError):
+        ctx.ckks_encode_batch(rows[:2] * 1e9, 2.0 ** 62, lv)
