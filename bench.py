@@ -238,7 +238,7 @@ def main():
     M = N // 2
     L = prm["n_q"]
     ntt_cols = ctx.ckks_ntt_autotune(L + prm["n_p"])
-    log("NTT autotune (column, row workgroup widths): %s" % (ntt_cols,))
+    log("NTT autotune (column width, row width, column-pass log size): %s" % (ntt_cols,))
 
     # plan choice: the paper's rule, and the learned search (cost model trained
     # on SpIntra-CA layer latencies measured here on small synthetic graphs)
@@ -450,7 +450,8 @@ def main():
                            "%d+%d primes, %d input cts resident" % (args.config, w.graph.n, "-".join(map(str, dims)),
                                                                      K, prm["log_n"], L, prm["n_p"], n_in),
                            form="batched, HIP-graph replay (fused Inter-CA pass, batched key switches)",
-                           ntt_tiles=list(ntt_cols)),
+                           ntt_schedule=dict(cols_column=ntt_cols[0], cols_row=ntt_cols[1],
+                                             log_column_pass=ntt_cols[2])),
                plain_ms=None if plain_ms is None else round(plain_ms, 3),
                speedup_vs_plain=None if plain_ms is None else round(plain_ms / ms_step, 3),
                plain_same_plan_ms=None if plain_same_ms is None else round(plain_same_ms, 3),

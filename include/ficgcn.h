@@ -86,11 +86,18 @@ ficgcn_status ckks_sync(ckks_ctx* ctx);
 ficgcn_status ficgcn_profile_enable(ckks_ctx* ctx, int on);
 ficgcn_status ficgcn_profile_read(ckks_ctx* ctx, const char* kernel, double* ms_total, uint64_t* launches);
 
-/* NTT autotuner: times every workgroup width pair (column pass x row pass)
- * on 16 scratch polynomials of n_limbs limbs (a key-switch batch's launch
- * shape) with HIP events on the context's stream and keeps the fastest for
- * this context.  cols_out[2] receives the choice (may be NULL).  Synchronous. */
+/* NTT autotuner: each limb's transform runs as a column pass of 2^s points
+ * and a row pass of 2^(log_n - s) points (both between 2^4 and 2^9); times
+ * every split s in {log_n/2 - 1, log_n/2, log_n/2 + 1} and workgroup width
+ * pair (column pass x row pass) on 16 scratch polynomials of n_limbs limbs (a
+ * key-switch batch's launch shape) with HIP events on the context's stream and
+ * keeps the fastest for this context.  cols_out[3] receives (column width, row
+ * width, s) (may be NULL).  Synchronous. */
 ficgcn_status ckks_ntt_autotune(ckks_ctx* ctx, uint32_t n_limbs, int32_t* cols_out);
+/* Sets the NTT schedule directly: split s (0 = log_n / 2, else both passes
+ * between 2^4 and 2^9 points) and the workgroup widths (1, 2, 4, 8 or 16).
+ * Every schedule computes the same words.  EINVAL otherwise. */
+ficgcn_status ckks_ntt_config(ckks_ctx* ctx, int32_t split, int32_t cols_column, int32_t cols_row);
 
 /* ------------------------------------------------------------------ keys */
 /* [client] Samples the ternary secret and the switching keys (rotation keys

@@ -456,6 +456,24 @@ ficgcn_status ckks_rescale(ckks_ctx* ctx, uint64_t* ct_dev, uint32_t level) {
   });
 }
 
+static bool ntt_split_ok(const ckks_ctx* c, int l1) {
+  const int l2 = c->log_n - l1;
+  return l1 >= 4 && l1 <= 9 && l2 >= 4 && l2 <= 9;
+}
+
+static bool ntt_cols_ok(int v) { return v == 1 || v == 2 || v == 4 || v == 8 || v == 16; }
+
+ficgcn_status ckks_ntt_config(ckks_ctx* ctx, int32_t split, int32_t cols_column, int32_t cols_row) {
+  return guard([&] {
+    REQUIRE(ctx, EINVAL_, "null context");
+    REQUIRE(split == 0 || ntt_split_ok(ctx, split), EINVAL_, "NTT split outside 2^4..2^9 points per pass");
+    REQUIRE(ntt_cols_ok(cols_column) && ntt_cols_ok(cols_row), EINVAL_, "NTT widths must be 1, 2, 4, 8 or 16");
+    ctx->ntt_split = split;
+    ctx->ntt_cols[0] = cols_column;
+    ctx->ntt_cols[1] = cols_row;
+  });
+}
+
 ficgcn_status ckks_ntt_autotune(ckks_ctx* ctx, uint32_t n_limbs, int32_t* cols_out) {
   return guard([&] {
     if (ctx) ensure_device(ctx);
@@ -470,40 +488,47 @@ ficgcn_status ckks_ntt_autotune(ckks_ctx* ctx, uint32_t n_limbs, int32_t* cols_o
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
-    const int saved[2] = {ctx->ntt_cols[0], ctx->ntt_cols[1]};
     const bool prof = ctx->profiling;
     ctx->profiling = false;
     float best = 1e30f;
-    int bc[2] = {saved[0], saved[1]};
-    for (int c0 : {4, 8, 16})
-      for (int c1 : {2, 4, 8, 16}) {
-        ctx->ntt_cols[0] = c0;
-        ctx->ntt_cols[1] = c1;
-        ntt_fwd(ctx, d, (int)n_limbs, lm_q((int)n_limbs), NP, ps);   // warm-up
-        ntt_inv(ctx, d, (int)n_limbs, lm_q((int)n_limbs), NP, ps);
-        HIPCHECK(hipEventRecord(e0, ctx->stream));
-        for (int r = 0; r < 5; ++r) {
-          ntt_fwd(ctx, d, (int)n_limbs, lm_q((int)n_limbs), NP, ps);
+    int bc[3] = {ctx->ntt_cols[0], ctx->ntt_cols[1], ctx->ntt_split};
+    const int mid = ctx->log_n / 2;
+    for (int l1 : {mid - 1, mid, mid + 1}) {
+      if (!ntt_split_ok(ctx, l1)) continue;
+      for (int c0 : {4, 8, 16})
+        for (int c1 : {2, 4, 8, 16}) {
+          ctx->ntt_split = l1;
+          ctx->ntt_cols[0] = c0;
+          ctx->ntt_cols[1] = c1;
+          ntt_fwd(ctx, d, (int)n_limbs, lm_q((int)n_limbs), NP, ps);   // warm-up
           ntt_inv(ctx, d, (int)n_limbs, lm_q((int)n_limbs), NP, ps);
+          HIPCHECK(hipEventRecord(e0, ctx->stream));
+          for (int r = 0; r < 5; ++r) {
+            ntt_fwd(ctx, d, (int)n_limbs, lm_q((int)n_limbs), NP, ps);
+            ntt_inv(ctx, d, (int)n_limbs, lm_q((int)n_limbs), NP, ps);
+          }
+          HIPCHECK(hipEventRecord(e1, ctx->stream));
+          HIPCHECK(hipEventSynchronize(e1));
+          float ms = 0;
+          HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+          if (ms < best) {
+            best = ms;
+            bc[0] = c0;
+            bc[1] = c1;
+            bc[2] = l1;
+          }
         }
-        HIPCHECK(hipEventRecord(e1, ctx->stream));
-        HIPCHECK(hipEventSynchronize(e1));
-        float ms = 0;
-        HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-          best = ms;
-          bc[0] = c0;
-          bc[1] = c1;
-        }
-      }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx->profiling = prof;
     ctx->ntt_cols[0] = bc[0];
     ctx->ntt_cols[1] = bc[1];
+    ctx->ntt_split = bc[2];
     if (cols_out) {
       cols_out[0] = bc[0];
       cols_out[1] = bc[1];
+      cols_out[2] = bc[2];
     }
   });
 }

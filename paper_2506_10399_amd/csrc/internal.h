@@ -88,6 +88,7 @@ struct ckks_ctx {
   std::vector<ficgcn::Mod> h_mods;
   bool on_device = false;
   int ntt_cols[2] = {16, 4};          // NTT workgroup width (column pass, row pass); autotuned
+  int ntt_split = 0;                  // log2 of the column pass's transform size (0: log_n / 2); autotuned
   hipStream_t stream = nullptr;
   int device = 0;
   std::map<std::pair<int, int>, ficgcn::BConv> modup;   // (level, digit)

@@ -379,9 +379,11 @@ static void launch(ckks_ctx* c, int logc, int cols, uint64_t* base, int n_limbs,
   }
 }
 
-static void split(int log_n, int& l1, int& l2) {
-  l1 = log_n / 2;
-  l2 = log_n - l1;
+// N = 2^l1 (column pass) * 2^l2 (row pass); each pass between 2^4 and 2^9 points
+static void split(const ckks_ctx* c, int& l1, int& l2) {
+  l1 = c->ntt_split ? c->ntt_split : c->log_n / 2;
+  l2 = c->log_n - l1;
+  if (l1 < 4 || l1 > 9 || l2 < 4 || l2 > 9) FICGCN_THROW(EINVAL_, "NTT split outside 2^4..2^9 points per pass");
 }
 
 void ntt_fwd(ckks_ctx* c, uint64_t* base, int n_limbs, LimbMap map, int n_polys, size_t poly_stride, int skip_alpha,
@@ -389,7 +391,7 @@ void ntt_fwd(ckks_ctx* c, uint64_t* base, int n_limbs, LimbMap map, int n_polys,
   ProfScope ps(c, "ntt");
   if (n_limbs <= 0 || n_polys <= 0) return;
   int l1, l2;
-  split(c->log_n, l1, l2);
+  split(c, l1, l2);
   launch<false, false>(c, l1, c->ntt_cols[0], base, n_limbs, map, n_polys, poly_stride, skip_alpha, skip_q);
   launch<false, true>(c, l2, c->ntt_cols[1], base, n_limbs, map, n_polys, poly_stride, skip_alpha, skip_q);
   HIPCHECK(hipGetLastError());
@@ -399,7 +401,7 @@ void ntt_inv(ckks_ctx* c, uint64_t* base, int n_limbs, LimbMap map, int n_polys,
   ProfScope ps(c, "ntt");
   if (n_limbs <= 0 || n_polys <= 0) return;
   int l1, l2;
-  split(c->log_n, l1, l2);
+  split(c, l1, l2);
   launch<true, true>(c, l2, c->ntt_cols[1], base, n_limbs, map, n_polys, poly_stride, 0, 0);
   launch<true, false>(c, l1, c->ntt_cols[0], base, n_limbs, map, n_polys, poly_stride, 0, 0);
   HIPCHECK(hipGetLastError());

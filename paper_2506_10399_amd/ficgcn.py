@@ -73,6 +73,7 @@ _SIGS = {
     "ckks_galois_element": (ctypes.c_int, [c_vp, ctypes.c_int64, c_u64p]),
     "ckks_sync": (ctypes.c_int, [c_vp]),
     "ckks_ntt_autotune": (ctypes.c_int, [c_vp, ctypes.c_uint32, c_vp]),
+    "ckks_ntt_config": (ctypes.c_int, [c_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "ficgcn_profile_enable": (ctypes.c_int, [c_vp, ctypes.c_int]),
     "ficgcn_profile_read": (ctypes.c_int, [c_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_uint64)]),
@@ -240,9 +241,13 @@ class Context:
         _check(lib().ckks_sync(self.h))
 
     def ckks_ntt_autotune(self, n_limbs: int):
-        out = np.zeros(2, dtype=np.int32)
+        """(column width, row width, column-pass log size) chosen for this context."""
+        out = np.zeros(3, dtype=np.int32)
         _check(lib().ckks_ntt_autotune(self.h, n_limbs, _ptr(out)))
-        return int(out[0]), int(out[1])
+        return int(out[0]), int(out[1]), int(out[2])
+
+    def ckks_ntt_config(self, split: int, cols_column: int, cols_row: int):
+        _check(lib().ckks_ntt_config(self.h, split, cols_column, cols_row))
 
     def ficgcn_profile_enable(self, on: bool):
         _check(lib().ficgcn_profile_enable(self.h, int(on)))

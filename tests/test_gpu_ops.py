@@ -206,3 +206,39 @@ def test_batch_encoder_at_mask_scale_and_range_error(env):
         assert np.abs(back - rows[i]).max() < 1e-9
     with pytest.raises(fg.FicgcnError):
         ctx.ckks_encode_batch(rows[:2] * 1e9, 2.0 ** 62, lv)
+
+
+def test_ntt_every_schedule_gives_the_same_words(env):
+    """Every NTT schedule the autotuner may pick (column-pass size 2^(log_n/2 - 1 .. log_n/2 + 1),
+    workgroup widths) computes the same transform: the ring product through
+    it equals the oracle's, and the autotuner's choice is one of them."""
+    prm, ctx = env["prm"], env["ctx"]
+    lv = prm.L - 1
+    mods = prm.q_level(lv)
+    a = np.stack([env["rng"].integers(0, q, prm.N, dtype=np.uint64) for q in mods])
+    b = np.stack([env["rng"].integers(0, q, prm.N, dtype=np.uint64) for q in mods])
+    want = ckks.poly_mul(b, a, mods, prm)
+    mid = prm.log_n // 2
+    try:
+        for split in (mid - 1, mid, mid + 1):
+            if not (4 <= split <= 9 and 4 <= prm.log_n - split <= 9):
+                continue
+            for c0, c1 in ((16, 4), (4, 16), (1, 2)):
+                ctx.ckks_ntt_config(split, c0, c1)
+                da = ctx.ckks_pt_load(a, lv)
+                db = ctx.ckks_pt_load(b, lv)
+                ctx.ckks_ntt(da, lv + 1, 0, False)   # da, db: evaluation form; take da back and forth once more
+                ctx.ckks_ntt(da, lv + 1, 0, True)
+                got = ctx.ckks_poly_store(da, lv, 1)[0]
+                assert np.array_equal(got, a), (split, c0, c1)
+                ct = ctx.ckks_ct_load(np.stack([a, a]), lv)
+                out = ctx.ct_buffer(lv)
+                out.zero_()
+                ctx.ckks_pt_mul_acc(out, lv, [ct], [db])
+                assert np.array_equal(ctx.ckks_poly_store(out, lv, 2)[0], want), (split, c0, c1)
+        with pytest.raises(env["fg"].FicgcnError):
+            ctx.ckks_ntt_config(3, 16, 4)
+        c0, c1, split = ctx.ckks_ntt_autotune(prm.L + prm.n_p)
+        assert split in (mid - 1, mid, mid + 1) and c0 in (4, 8, 16) and c1 in (2, 4, 8, 16)
+    finally:
+        ctx.ckks_ntt_config(0, 16, 4)
