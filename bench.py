@@ -135,6 +135,20 @@ def extrapolate(timings, F, op_counts):
             + timings["rescale"] * op_counts["rescale"])
 
 
+def host_cpu():
+    """The host's CPU model name and logical CPU count."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
 def cpu_baseline(params, plan_info, op_counts, all_core=None, sample_features=12):
     """The CPU oracle on a bounded sample of the same workload, scaled to one
     inference by the plan's operation counts: single-threaded (the value), and,
@@ -153,6 +167,7 @@ def cpu_baseline(params, plan_info, op_counts, all_core=None, sample_features=12
                        % (sample_features, F, K, F_out, op_counts["rot"], op_counts["mask_pmult"],
                           op_counts["cmult"], op_counts["rescale"], sample_s)),
                per_op_s=timings)
+    out["host_cpu"], out["nproc"] = host_cpu()
     if all_core:
         P = len(all_core)
         mean = {k: float(np.mean([t[k] for t in all_core])) for k in timings}
