@@ -614,16 +614,27 @@ void rescale_batch(ckks_ctx* c, int level, const std::vector<uint64_t*>& cts) {
 
 // outs[g] (+)= sum over the terms of group g of ct (.) pt, or ct when pt is null
 __global__ void k_group_mac(const MacTerm* __restrict__ terms, const int* __restrict__ group_start,
-                            uint64_t* const* __restrict__ outs, int l1, int accumulate, int log_n,
-                            const Mod* __restrict__ mods) {
+                            uint64_t* const* __restrict__ outs, int l1, int accumulate, int log_n, int n_groups,
+                            int xcd_order, const Mod* __restrict__ mods) {
   const size_t N = (size_t)1 << log_n;
-  const size_t j = blockIdx.x * (size_t)KB + threadIdx.x;
-  // limb slowest: one limb of every group's terms is in flight at a time, so
-  // ciphertexts shared by many groups (baby steps) are re-read from cache.
-  // One thread takes both components of a coefficient: each plaintext word
-  // is read once for the two products.
+  // limb slowest: one limb of every group's terms is in flight at a time.
+  // With xcd_order, blocks go round-robin over the 8 XCDs by linear id, so
+  // block b runs coefficient block 8 (b / 8 / n_groups) + b % 8 for group
+  // (b / 8) % n_groups: every group of one coefficient block runs on one XCD,
+  // back to back, and the ciphertexts the groups share (baby steps) are read
+  // into that XCD's L2 once.  One thread takes both components of a
+  // coefficient: each plaintext word is read once for the two products.
   const int i = blockIdx.z;
-  const int g = blockIdx.y;
+  int jb, g;
+  if (xcd_order) {
+    const int b = blockIdx.x, idx = b >> 3;
+    jb = (b & 7) + 8 * (idx / n_groups);
+    g = idx % n_groups;
+  } else {
+    jb = blockIdx.x;
+    g = blockIdx.y;
+  }
+  const size_t j = (size_t)jb * KB + threadIdx.x;
   const Mod m = mods[i];
   const size_t o0 = (size_t)i * N + j, o1 = ((size_t)l1 + i) * N + j;
   uint64_t* out = outs[g];
@@ -674,8 +685,11 @@ void group_mac(ckks_ctx* c, int level, const std::vector<std::vector<MacTerm>>& 
   int* sd = upload(c, S_GM_START, start);
   uint64_t* const* od = upload(c, S_GM_OUT, outs);
   if (groups.size() > 65535) FICGCN_THROW(EINVAL_, "too many groups in one launch");
-  hipLaunchKernelGGL(k_group_mac, dim3(c->N / KB, groups.size(), level + 1), dim3(KB), 0, c->stream, td, sd, od,
-                     level + 1, accumulate ? 1 : 0, c->log_n, c->t.mods);
+  const int n_jb = c->N / KB, ng = (int)groups.size();
+  const bool xcd = n_jb % 8 == 0 && (size_t)n_jb * ng < ((size_t)1 << 31);
+  const dim3 grid = xcd ? dim3(n_jb * ng, 1, level + 1) : dim3(n_jb, ng, level + 1);
+  hipLaunchKernelGGL(k_group_mac, grid, dim3(KB), 0, c->stream, td, sd, od, level + 1, accumulate ? 1 : 0, c->log_n, ng,
+                     xcd ? 1 : 0, c->t.mods);
   HIPCHECK(hipGetLastError());
   stream_sync(c);
 }
