@@ -323,11 +323,23 @@ struct MaskGroup {
 // outputs, in the same order.
 __global__ void k_keymac_masked(const uint64_t* __restrict__ D, const KSJob* __restrict__ jobs,
                                 const GroupDesc* __restrict__ groups, int nd, int ext, int l1, int L, int n_mod,
-                                int log_n, const Mod* __restrict__ mods) {
+                                int log_n, int n_groups, int xcd_order, const Mod* __restrict__ mods) {
   const size_t N = (size_t)1 << log_n;
-  const uint32_t j = blockIdx.x * KB + threadIdx.x;
+  // xcd_order: the groups of one coefficient block run back to back on one XCD
+  // (blocks go round-robin over the 8 XCDs by linear id), so the keys the
+  // groups share (one per shift) are read into that XCD's L2 once
+  int jb, gi;
+  if (xcd_order) {
+    const int b = blockIdx.x, idx = b >> 3;
+    jb = (b & 7) + 8 * (idx / n_groups);
+    gi = idx % n_groups;
+  } else {
+    jb = blockIdx.x;
+    gi = blockIdx.z;
+  }
+  const uint32_t j = (uint32_t)jb * KB + threadIdx.x;
   const int i = blockIdx.y;
-  const GroupDesc gd = groups[blockIdx.z];
+  const GroupDesc gd = groups[gi];
   const int m = i < l1 ? i : i - l1 + L;
   const Mod md = mods[m];
   uint64_t* a0 = gd.out + (size_t)i * N + j;              // gd.out: this group's A
@@ -481,8 +493,11 @@ void keyswitch_masked_sum(ckks_ctx* c, int level, const std::vector<const uint64
     {
       ProfScope pk(c, "keymac");
       if (gds.size() > 65535) FICGCN_THROW(EINVAL_, "too many outputs in one launch");
-      hipLaunchKernelGGL(k_keymac_masked, dim3(N / KB, ext, gds.size()), dim3(KB), 0, c->stream, D, jd, gd, nd, ext, l1,
-                         c->L, c->n_mod(), c->log_n, c->t.mods);
+      const int n_jb = (int)(N / KB), ng = (int)gds.size();
+      const bool xcd = n_jb % 8 == 0 && (size_t)n_jb * ng < ((size_t)1 << 31);
+      const dim3 grid = xcd ? dim3(n_jb * ng, ext, 1) : dim3(n_jb, ext, ng);
+      hipLaunchKernelGGL(k_keymac_masked, grid, dim3(KB), 0, c->stream, D, jd, gd, nd, ext, l1, c->L, c->n_mod(),
+                         c->log_n, ng, xcd ? 1 : 0, c->t.mods);
       HIPCHECK(hipGetLastError());
     }
     stream_sync(c);
