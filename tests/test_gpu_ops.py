@@ -242,3 +242,23 @@ def test_ntt_every_schedule_gives_the_same_words(env):
         assert split in (mid - 1, mid, mid + 1) and c0 in (4, 8, 16) and c1 in (2, 4, 8, 16)
     finally:
         ctx.ckks_ntt_config(0, 16, 4)
+
+
+@pytest.mark.parametrize("log_n", [9, 10, 11, 12, 14])
+def test_encoder_every_ring_degree(log_n):
+    """The device encoder's four-step FFT at every split shape (N1 x N2 from
+    16 x 32 up): coefficients as the oracle's encoder gives them (a few may
+    round the other way) and the slots decoded back within 1e-9."""
+    import torch
+    from paper_2506_10399_amd import ficgcn as fg
+    assert torch.cuda.is_available()
+    d = dict(log_n=log_n, n_q=3, q_bits=50, n_p=1, p_bits=60, log_scale=40)
+    prm = Params.from_dict(d)
+    ctx = fg.Context.from_dict(d)
+    lv = prm.L - 1
+    z = np.random.default_rng(log_n).uniform(-1, 1, prm.M)
+    m = ctx.ckks_poly_store(ctx.ckks_encode(z, prm.scale, lv), lv, 1)[0]
+    want = enc.encode(prm, z, prm.scale, lv).m
+    assert np.mean(m != want) < 1e-3
+    back = enc.decode(prm, ckks.Plaintext(m=m, level=lv, scale=prm.scale))
+    assert np.abs(back - z).max() < 1e-9
