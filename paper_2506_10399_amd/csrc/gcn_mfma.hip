@@ -206,6 +206,167 @@ __global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   for (int rr = 0; rr < 4; ++rr) o[rr] = h[rr];
 }
 
+// ---- inputs stored as the pass's matrix operands ---------------------------
+// The layer-1 inputs rearranged once into what the pass feeds the matrix
+// cores: for every wave (the pass's wave order: tile, limb, component) and
+// every (copy, 64-feature block) step, the 7 digit planes of its 64 lanes,
+// [wave][step][plane][lane] x 16 bytes (7 bytes per residue instead of 8, no
+// digit work in the pass).  Features past F hold zero digits.
+
+size_t mfma_packed_words(ckks_ctx* c, int K, int F, int level) {
+  const size_t waves = ((size_t)c->N >> 4) * (size_t)(level + 1) * 2;
+  const size_t steps = (size_t)(K > 0 ? K : 1) * (size_t)((F + 63) / 64);
+  return waves * steps * 7 * 64 * 2;
+}
+
+// one wave per (pass wave, step): the 16 words of each lane, their digit planes
+template <bool STRIDED>
+__global__ __launch_bounds__(MW) void k_mfma_pack(const uint64_t* __restrict__ in_base, size_t in_stride,
+                                                  const uint64_t* const* __restrict__ in_ptrs, int K, int F, int n_fb,
+                                                  int l1, int log_n, v4i* __restrict__ packed) {
+  const int lane = threadIdx.x & 63;
+  const size_t N = (size_t)1 << log_n;
+  const size_t tiles = N >> 4;
+  const size_t n_steps = (size_t)(K > 0 ? K : 1) * n_fb;
+  const size_t gw = (size_t)blockIdx.x * (MW / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const size_t wave = gw / n_steps;
+  if (wave >= tiles * (size_t)l1 * 2) return;
+  const int st = (int)(gw % n_steps);
+  const size_t tile = wave % tiles;
+  const int rest = (int)(wave / tiles);
+  const int i = rest % l1, comp = rest / l1;
+  const int k = st / n_fb, fb = st % n_fb;
+  const int r = lane & 15, g = lane >> 4;
+  const size_t off = ((size_t)comp * l1 + i) * N + tile * 16 + r;
+  uint64_t x[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int f = fb * 64 + g * 16 + e;
+    x[e] = f < F ? (STRIDED ? in_base[((size_t)k * F + f) * in_stride + off] : in_ptrs[(size_t)k * F + f][off]) : 0;
+  }
+  v4i A[7];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) digit_planes_w(x, A, w);
+  v4i* dst = packed + gw * 7 * 64 + lane;
+#pragma unroll
+  for (int a = 0; a < 7; ++a) dst[(size_t)a * 64] = A[a];
+}
+
+void mfma_pack(ckks_ctx* c, const uint64_t* in_base, size_t in_stride, const uint64_t* const* in_ptrs, int K, int F,
+               int level, uint64_t* packed) {
+  const int l1 = level + 1;
+  const int n_fb = (F + 63) / 64;
+  const size_t items = ((size_t)c->N >> 4) * l1 * 2 * (size_t)(K > 0 ? K : 1) * n_fb;
+  const size_t blocks = (items + MW / 64 - 1) / (MW / 64);
+  if (blocks >= ((size_t)1 << 31)) FICGCN_THROW(EINVAL_, "input block too large to rearrange in one launch");
+  if (in_base)
+    hipLaunchKernelGGL(k_mfma_pack<true>, dim3((unsigned)blocks), dim3(MW), 0, c->stream, in_base, in_stride, in_ptrs, K,
+                       F, n_fb, l1, c->log_n, (v4i*)packed);
+  else
+    hipLaunchKernelGGL(k_mfma_pack<false>, dim3((unsigned)blocks), dim3(MW), 0, c->stream, in_base, in_stride, in_ptrs,
+                       K, F, n_fb, l1, c->log_n, (v4i*)packed);
+  HIPCHECK(hipGetLastError());
+}
+
+// The pass on rearranged inputs: per step the 7 planes are one 16-byte load
+// each (the next step's issued before this step's matrix products), then the
+// same products, folds and output as the pass on ciphertext words.
+__global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_fused_mfma_packed(
+    OutList out, int n_out, const v4i* __restrict__ packed, PtrList pts, int K, int n_fb, int l1,
+    const v4i* __restrict__ wd, const uint64_t* __restrict__ pow256, int log_n, const Mod* __restrict__ mods) {
+  const int lane = threadIdx.x & 63;
+  const size_t N = (size_t)1 << log_n;
+  const size_t tiles = N >> 4;
+  const size_t wave = (size_t)blockIdx.x * (MW / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const size_t tile = wave % tiles;
+  const int rest = (int)(wave / tiles);
+  const int i = rest % l1, comp = rest / l1;
+  const int g = lane >> 4;
+  const size_t limb_off = ((size_t)comp * l1 + i) * N;
+  const Mod m = mods[i];
+  const int KK = K > 0 ? K : 1;
+  const int n_steps = KK * n_fb;
+  const v4i* src = packed + wave * (size_t)n_steps * 7 * 64 + lane;
+  const uint64_t* pw = pow256 + (size_t)i * 13;
+  uint64_t h[4] = {0, 0, 0, 0};
+  v4i acc[13];
+#pragma unroll
+  for (int s = 0; s < 13; ++s) acc[s] = v4i{0, 0, 0, 0};
+  v4i Aa[7], Ab[7];
+#pragma unroll
+  for (int a = 0; a < 7; ++a) Aa[a] = src[(size_t)a * 64];
+  int k = 0, fb = 0;
+  for (int step = 0; step < n_steps; step += 2) {
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int st = step + half;
+      if (st >= n_steps) break;
+      v4i (&A)[7] = half ? Ab : Aa;
+      v4i (&An)[7] = half ? Aa : Ab;
+      const bool last = fb == n_fb - 1;
+      v4i B[7];
+#pragma unroll
+      for (int b = 0; b < 7; ++b) B[b] = wd[((size_t)fb * 7 + b) * 64 + lane];
+      uint64_t pk[4] = {1, 1, 1, 1};
+      if (K > 0 && last) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) pk[rr] = pts.p[k][(size_t)i * N + tile * 16 + 4 * g + rr];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (st + 1 < n_steps) {
+#pragma unroll
+        for (int a = 0; a < 7; ++a) An[a] = src[((size_t)(st + 1) * 7 + a) * 64];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int b = 0; b < 7; ++b)
+#pragma unroll
+        for (int a = 0; a < 7; ++a) acc[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[a], B[b], acc[a + b], 0, 0, 0);
+      if (last) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          u128 sum = 0;
+#pragma unroll
+          for (int d = 0; d < 13; ++d) {
+            const int v = acc[d][rr];
+            const uint64_t res = v >= 0 ? (uint64_t)v : m.q - (uint64_t)(-(int64_t)v);
+            sum += (u128)res * pw[d];
+          }
+          uint64_t t = reduce128(sum, m);
+          if (K > 0) t = reduce128((u128)t * pk[rr], m);
+          h[rr] = add_mod(h[rr], t, m.q);
+        }
+#pragma unroll
+        for (int s = 0; s < 13; ++s) acc[s] = v4i{0, 0, 0, 0};
+        k = k + 1;
+        fb = 0;
+      } else {
+        fb = fb + 1;
+      }
+    }
+  }
+  const int n = lane & 15;
+  if (n >= n_out) return;
+  uint64_t* o = out.p[n] + limb_off + tile * 16 + 4 * g;
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) o[rr] = h[rr];
+}
+
+void comb_mfma_packed(ckks_ctx* c, const std::vector<uint64_t*>& outs, const uint64_t* packed, const PtrList& pts, int K,
+                      int F, int level, const void* wd, const uint64_t* pw, const char* prof_name) {
+  ProfScope ps(c, prof_name);
+  const int n_out = (int)outs.size();
+  if (n_out > 16 || K > PtrList::MAX || F > 16384 || !packed) FICGCN_THROW(EINVAL_, "shape outside the matrix-core pass");
+  const int l1 = level + 1;
+  OutList o{};
+  for (int l = 0; l < n_out; ++l) o.p[l] = outs[l];
+  const int n_fb = (F + 63) / 64;
+  const size_t waves = ((size_t)c->N >> 4) * l1 * 2;
+  hipLaunchKernelGGL(k_fused_mfma_packed, dim3((unsigned)(waves / (MW / 64))), dim3(MW), 0, c->stream, o, n_out,
+                     (const v4i*)packed, pts, K, n_fb, l1, (const v4i*)wd, pw, c->log_n, c->t.mods);
+  HIPCHECK(hipGetLastError());
+}
+
 // Weight digit planes of one 16-column group: [n_fb][7][64 lanes] x 16 bytes;
 // lane (n, g), byte e holds digit b of w[f = 64 fb + 16 g + e][l0 + n] (zero
 // outside F x F').  Returns false when a weight is outside the digit range.

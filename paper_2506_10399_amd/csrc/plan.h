@@ -77,6 +77,10 @@ struct LayerPlan {
   uint8_t* wm_dev = nullptr;       // [groups][n_fb][7][64][16]
   size_t wm_group_bytes = 0;
   uint64_t* pw_dev = nullptr;      // [level+1][13]
+  // inputs rearranged as the matrix-core pass's operands (caller-owned buffer,
+  // registered by ficgcn_plan_pack_inputs; read when the layer is called
+  // without input ciphertexts)
+  const uint64_t* packed_in = nullptr;
   int n_packed() const { return kind == 0 ? f_out : (f_out + t - 1) / t; }
   int n_in_cts() const { return kind == 0 ? K * f_in : f_in; }
 };

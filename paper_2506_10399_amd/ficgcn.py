@@ -117,6 +117,9 @@ _SIGS = {
                                                  ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_double)]),
     "ficgcn_plan_radix2_stats": (ctypes.c_int, [c_vp, ctypes.c_uint32, c_vp]),
     "ficgcn_plan_encode": (ctypes.c_int, [c_vp, c_vp]),
+    "ficgcn_plan_packed_input_words": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, c_vp]),
+    "ficgcn_plan_pack_inputs": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, c_vp, ctypes.c_size_t, c_vp,
+                                               ctypes.c_uint64]),
     "ficgcn_plan_load_operand": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, ctypes.c_size_t, c_vp]),
     "ficgcn_gcn_layer": (ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_uint32, c_vp, ctypes.c_size_t, c_vp,
                                         ctypes.c_size_t, ctypes.c_int32]),
@@ -503,8 +506,27 @@ class Plan:
         _check(lib().ficgcn_plan_load_operand(self.ctx.h, self.h, layer, i, _ptr(coeffs)))
 
     def ficgcn_gcn_layer(self, eval_keys: Keys, layer: int, in_cts, out_cts, mode: int = 1):
-        _check(lib().ficgcn_gcn_layer(self.ctx.h, eval_keys.h, self.h, layer, _ptr_array(in_cts), len(in_cts),
+        """in_cts None: the layer reads the inputs ficgcn_plan_pack_inputs rearranged."""
+        ins = None if in_cts is None else _ptr_array(in_cts)
+        _check(lib().ficgcn_gcn_layer(self.ctx.h, eval_keys.h, self.h, layer, ins, 0 if in_cts is None else len(in_cts),
                                       _ptr_array(out_cts), len(out_cts), mode))
+
+    def ficgcn_plan_packed_input_words(self, layer: int) -> int:
+        n = ctypes.c_uint64()
+        _check(lib().ficgcn_plan_packed_input_words(self.h, self.ctx.h, layer, ctypes.byref(n)))
+        return int(n.value)
+
+    def ficgcn_plan_pack_inputs(self, layer: int, in_cts, out=None):
+        """Rearranges the layer's input ciphertexts into a device buffer (a new
+        int64 tensor unless `out` is given) and registers it with the plan."""
+        import torch
+        words = self.ficgcn_plan_packed_input_words(layer)
+        if out is None:
+            out = torch.empty(words, dtype=torch.int64, device="cuda")
+        _check(lib().ficgcn_plan_pack_inputs(self.ctx.h, self.h, layer, _ptr_array(in_cts), len(in_cts), _ptr(out),
+                                             out.numel()))
+        self._packed = out   # the plan reads it until replaced
+        return out
 
 
 # ------------------------------------------------------------------ plan search

@@ -6,7 +6,8 @@ ciphertexts zero except a few at random (copy, feature) positions the oracle
 computes the exact result from those terms alone: Z_f = sum_k P_k (.) X_{k,f},
 H_l = sum_f w_{f,l} Z_f, two rescales, then the relinearised square.  The
 GPU runs the whole layer (fused matrix-core pass over every input, batched
-rescales and relinearisation) in the batched and the graph form; all 16
+rescales and relinearisation) in the batched and the graph form, from the
+ciphertexts and from the inputs rearranged as the pass's operands; all 16
 output ciphertexts must equal the oracle's words."""
 import numpy as np
 import pytest
@@ -74,5 +75,15 @@ def test_cora_first_layer_sparse_inputs_bit_exact():
         for l in range(Fo):
             got = ctx.ckks_poly_store(outs[l], d["level_out"], 2)
             assert np.array_equal(got, want[l]), ("mode", mode, "output", l, "picks", picks)
-    del block
+    # the same layer from the inputs rearranged as the matrix-core pass's operands
+    packed = p.ficgcn_plan_pack_inputs(0, ins)
+    assert packed.numel() < 0.91 * block.numel()      # 7 bytes per residue, the last feature block padded
+    for mode in (1, 2, 2):
+        for x in outs:
+            x.zero_()
+        p.ficgcn_gcn_layer(ev, 0, None, outs, mode=mode)
+        for l in range(Fo):
+            got = ctx.ckks_poly_store(outs[l], d["level_out"], 2)
+            assert np.array_equal(got, want[l]), ("rearranged, mode", mode, "output", l, "picks", picks)
+    del block, packed
     torch.cuda.empty_cache()

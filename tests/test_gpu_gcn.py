@@ -223,3 +223,37 @@ def test_three_layer_model_bit_exact_all_forms():
              for x in res[-1][0]]
     y = e["graph"].read_output(e["o"].pi, slots, lp.f_out, lp.t, lp.B, True)
     assert gcn.max_rel_error(y, e["ref"][-1]) < 1e-3
+
+
+@pytest.mark.parametrize("name,contiguous", [("tiny", False), ("tiny2", True)])
+def test_rearranged_inputs_give_the_same_words(name, contiguous):
+    """An Inter-CA first layer run on its inputs rearranged as the matrix-core
+    pass's operands (ficgcn_plan_pack_inputs, then the layer without input
+    ciphertexts) gives the oracle's words in the batched and graph forms,
+    from separate buffers (pointer reads) and from one block (strided reads);
+    the plain form and a SpIntra-CA layer refuse the rearranged inputs."""
+    import torch
+    e = _setup(name, "inter")
+    _load_operands(e)
+    ctx, p, info = e["ctx"], e["p"], e["p"].ficgcn_plan_info()
+    lv0 = e["prm"].L - 1
+    ins = [ctx.ckks_ct_load(_ct(c), lv0) for c in e["cts"]]
+    if contiguous:
+        block = torch.stack(ins)
+        ins = [block[i] for i in range(len(ins))]
+    packed = p.ficgcn_plan_pack_inputs(0, ins)
+    assert packed.numel() == p.ficgcn_plan_packed_input_words(0)
+    d = info[0]
+    outs = [ctx.ct_buffer(d["level_in"]) for _ in range(d["n_out_cts"])]
+    for mode in (1, 2, 2, 1):
+        for x in outs:
+            x.zero_()
+        p.ficgcn_gcn_layer(e["ev"], 0, None, outs, mode=mode)
+        for g, (x, b) in enumerate(zip(outs, e["outs"][0])):
+            assert np.array_equal(ctx.ckks_poly_store(x, d["level_out"], 2), _ct(b)), (name, mode, g)
+    with pytest.raises(e["fg"].FicgcnError):
+        p.ficgcn_gcn_layer(e["ev"], 0, None, outs, mode=0)
+    if len(info) > 1:
+        nxt = [ctx.ct_buffer(info[1]["level_in"]) for _ in range(info[1]["n_out_cts"])]
+        with pytest.raises(e["fg"].FicgcnError):
+            p.ficgcn_gcn_layer(e["ev"], 1, None, nxt, mode=1)
