@@ -37,6 +37,9 @@ METRIC = "enc. GCN latency: batched+planned vs plain (same GPU); key-switch/s; H
 HBM_PEAK_GBS = 8000.0
 
 
+# library profile scopes reported per step (each a sum of HIP-event intervals)
+PROF_NAMES = ("inter_fused", "comb_fused", "keymac", "moddown", "modup", "ntt", "group_mac", "ks_masked", "rescale")
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -353,7 +356,7 @@ def main():
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
         ctx.ficgcn_profile_enable(True)
-        for k in ("inter_fused", "comb_fused", "keymac", "moddown", "modup", "ntt"):
+        for k in PROF_NAMES:
             ctx.ficgcn_profile_read(k)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -362,7 +365,7 @@ def main():
         torch.cuda.synchronize()
         ms_e = (time.perf_counter() - t0) * 1e3 / args.steps
         ctx.ficgcn_profile_enable(False)
-        pr = {k: ctx.ficgcn_profile_read(k) for k in ("inter_fused", "comb_fused", "keymac", "moddown", "modup", "ntt")}
+        pr = {k: ctx.ficgcn_profile_read(k) for k in PROF_NAMES}
         return ms, ms_e, pr
 
     last = info[-1]

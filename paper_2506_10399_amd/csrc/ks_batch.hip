@@ -26,6 +26,16 @@ void zero_fill(ckks_ctx* c, uint64_t* p, size_t words);
 
 constexpr int KB = 256;
 
+// Accesses through pointers read from device tables (job lists, term lists,
+// pointer arrays).  The compiler cannot tell that such a pointer addresses
+// global memory and would emit flat accesses, which also count on the
+// scalar-load counter: every read of the next table entry would then wait for
+// all vector loads in flight.  These pin the access to the global segment.
+typedef __attribute__((address_space(1))) uint64_t gu64;
+__device__ __forceinline__ uint64_t gld(const uint64_t* p) { return *(const gu64*)p; }
+__device__ __forceinline__ void gst(uint64_t* p, uint64_t v) { *(gu64*)p = v; }
+__device__ const uint64_t k_one_word = 1;
+
 __device__ __forceinline__ uint32_t auto_idx(uint32_t k, uint64_t g, int log_n) {
   // evaluation index k holds A(psi^(2 brev(k) + 1)); sigma_g reads the index of psi^(g (2 brev(k) + 1))
   uint32_t N2 = 2u << log_n;
@@ -39,7 +49,7 @@ __global__ void k_gather(uint64_t* __restrict__ tmp, const uint64_t* const* __re
   const size_t N = (size_t)1 << log_n;
   const size_t j = blockIdx.x * (size_t)KB + threadIdx.x;
   const int i = blockIdx.y, u = blockIdx.z;
-  tmp[((size_t)u * l1 + i) * N + j] = src[u][(size_t)i * N + j];
+  tmp[((size_t)u * l1 + i) * N + j] = gld(src[u] + (size_t)i * N + j);
 }
 
 struct DigitTables {
@@ -69,7 +79,7 @@ __global__ void k_modup_conv(const uint64_t* __restrict__ tmp, const uint64_t* c
   for (int t = 0; t < ns; ++t) {
     const uint64_t b = mods[idx[t]].q;
     y[t] = mul_shoup(s[t * N + j], tab[t], tab[ns + t], b);
-    Dd[((size_t)d * alpha + t) * N + j] = own[t * N + j];
+    Dd[((size_t)d * alpha + t) * N + j] = gld(own + t * N + j);
   }
   const uint64_t* hm = tab + 2 * ns;
   for (int k = 0; k < ndst; ++k) {
@@ -96,8 +106,8 @@ __global__ void k_keymac_batch(uint64_t* __restrict__ acc, const uint64_t* __res
   u128 s0 = 0, s1 = 0;
   for (int d = 0; d < nd; ++d) {
     const u128 x = Du[((size_t)d * ext + i) * N + jj];
-    s0 += x * jb.key[(((size_t)d * 2 + 0) * n_mod + m) * N + j];
-    s1 += x * jb.key[(((size_t)d * 2 + 1) * n_mod + m) * N + j];
+    s0 += x * gld(jb.key + (((size_t)d * 2 + 0) * n_mod + m) * N + j);
+    s1 += x * gld(jb.key + (((size_t)d * 2 + 1) * n_mod + m) * N + j);
   }
   const Mod md = mods[m];
   acc[(((size_t)r * 2 + 0) * ext + i) * N + j] = reduce128(s0, md);
@@ -151,7 +161,7 @@ __global__ void k_ks_final(const uint64_t* __restrict__ acc, const uint64_t* __r
   const Mod md = mods[i];
   const uint64_t q = md.q;
   const size_t o = ((size_t)comp * l1 + i) * N + j;
-  uint64_t a = gd.accumulate ? gd.out[o] : 0;
+  uint64_t a = gd.accumulate ? gld(gd.out + o) : 0;
   u128 s = 0;
   int cnt = 0;
   for (int r = gd.start; r < gd.end; ++r) {
@@ -159,10 +169,10 @@ __global__ void k_ks_final(const uint64_t* __restrict__ acc, const uint64_t* __r
     uint64_t v = sub_mod(acc[(((size_t)r * 2 + comp) * ext + i) * N + j],
                          conv[(((size_t)r * 2 + comp) * l1 + i) * N + j], q);
     v = mul_shoup(v, k.pinv[i], k.pinv_s[i], q);
-    if (comp == 0 && jb.add0) v = add_mod(v, jb.add0[(size_t)i * N + (jb.g == 1 ? j : auto_idx(j, jb.g, log_n))], q);
-    if (comp == 1 && jb.add1) v = add_mod(v, jb.add1[(size_t)i * N + j], q);
+    if (comp == 0 && jb.add0) v = add_mod(v, gld(jb.add0 + (size_t)i * N + (jb.g == 1 ? j : auto_idx(j, jb.g, log_n))), q);
+    if (comp == 1 && jb.add1) v = add_mod(v, gld(jb.add1 + (size_t)i * N + j), q);
     if (jb.pt) {
-      s += (u128)v * jb.pt[(size_t)i * N + j];
+      s += (u128)v * gld(jb.pt + (size_t)i * N + j);
       if (++cnt == 8) {
         a = add_mod(a, reduce128(s, md), q);
         s = 0;
@@ -172,7 +182,7 @@ __global__ void k_ks_final(const uint64_t* __restrict__ acc, const uint64_t* __r
       a = add_mod(a, v, q);
     }
   }
-  gd.out[o] = add_mod(a, reduce128(s, md), q);
+  gst(gd.out + o, add_mod(a, reduce128(s, md), q));
 }
 
 static MDK mdk(ckks_ctx* c, int level) {
@@ -344,7 +354,7 @@ __global__ void k_keymac_masked(const uint64_t* __restrict__ D, const KSJob* __r
   const Mod md = mods[m];
   uint64_t* a0 = gd.out + (size_t)i * N + j;              // gd.out: this group's A
   uint64_t* a1 = gd.out + ((size_t)ext + i) * N + j;
-  uint64_t v0 = *a0, v1 = *a1;
+  uint64_t v0 = gld(a0), v1 = gld(a1);
   u128 t0 = 0, t1 = 0;
   int cnt = 0;
   for (int r = gd.start; r < gd.end; ++r) {
@@ -354,12 +364,12 @@ __global__ void k_keymac_masked(const uint64_t* __restrict__ D, const KSJob* __r
     u128 s0 = 0, s1 = 0;
     for (int d = 0; d < nd; ++d) {
       const u128 x = Du[((size_t)d * ext + i) * N + jj];
-      s0 += x * jb.key[(((size_t)d * 2 + 0) * n_mod + m) * N + j];
-      s1 += x * jb.key[(((size_t)d * 2 + 1) * n_mod + m) * N + j];
+      s0 += x * gld(jb.key + (((size_t)d * 2 + 0) * n_mod + m) * N + j);
+      s1 += x * gld(jb.key + (((size_t)d * 2 + 1) * n_mod + m) * N + j);
     }
     const uint64_t x0 = reduce128(s0, md), x1 = reduce128(s1, md);
     if (jb.pt) {
-      const uint64_t p = jb.pt[(size_t)i * N + j];
+      const uint64_t p = gld(jb.pt + (size_t)i * N + j);
       t0 += (u128)x0 * p;
       t1 += (u128)x1 * p;
     } else {
@@ -374,8 +384,8 @@ __global__ void k_keymac_masked(const uint64_t* __restrict__ D, const KSJob* __r
       cnt = 0;
     }
   }
-  *a0 = add_mod(v0, reduce128(t0, md), md.q);
-  *a1 = add_mod(v1, reduce128(t1, md), md.q);
+  gst(a0, add_mod(v0, reduce128(t0, md), md.q));
+  gst(a1, add_mod(v1, reduce128(t1, md), md.q));
 }
 
 // out_grp (+)= (A_Q - conv) P^-1  [+ sum_r sigma_g(add0_r) (.) pt_r on component 0]
@@ -399,8 +409,8 @@ __global__ void k_masked_final(const uint64_t* __restrict__ A, const uint64_t* _
     for (int r = gr.start; r < gr.end; ++r) {
       const KSJob jb = jobs[r];
       if (!jb.add0) continue;
-      const uint64_t x = jb.add0[(size_t)i * N + (jb.g == 1 ? j : auto_idx(j, jb.g, log_n))];
-      s += jb.pt ? (u128)x * jb.pt[(size_t)i * N + j] : (u128)x;
+      const uint64_t x = gld(jb.add0 + (size_t)i * N + (jb.g == 1 ? j : auto_idx(j, jb.g, log_n)));
+      s += jb.pt ? (u128)x * gld(jb.pt + (size_t)i * N + j) : (u128)x;
       if (++cnt == 8) {
         v = add_mod(v, reduce128(s, md), q);
         s = 0;
@@ -410,7 +420,7 @@ __global__ void k_masked_final(const uint64_t* __restrict__ A, const uint64_t* _
     v = add_mod(v, reduce128(s, md), q);
   }
   uint64_t* out = outs[g];
-  out[o] = accumulate ? add_mod(out[o], v, q) : v;
+  gst(out + o, accumulate ? add_mod(gld(out + o), v, q) : v);
 }
 
 enum { S_KM_A = 80, S_KM_CONV, S_KM_JOBS, S_KM_GRP, S_KM_OUT, S_KM_CGRP };
@@ -541,10 +551,10 @@ __global__ void k_tensor_batch(const TensorJob* __restrict__ jobs, int l1, int l
   const TensorJob jb = jobs[blockIdx.z];
   const Mod m = mods[i];
   const size_t o0 = i * N + j, o1 = (l1 + i) * N + j;
-  const uint64_t x0 = jb.x[o0], x1 = jb.x[o1], y0 = jb.y[o0], y1 = jb.y[o1];
-  jb.d[o0] = reduce128((u128)x0 * y0, m);
-  jb.d[o1] = reduce128((u128)x0 * y1 + (u128)x1 * y0, m);
-  jb.d[(2 * l1 + i) * N + j] = reduce128((u128)x1 * y1, m);
+  const uint64_t x0 = gld(jb.x + o0), x1 = gld(jb.x + o1), y0 = gld(jb.y + o0), y1 = gld(jb.y + o1);
+  gst(jb.d + o0, reduce128((u128)x0 * y0, m));
+  gst(jb.d + o1, reduce128((u128)x0 * y1 + (u128)x1 * y0, m));
+  gst(jb.d + (2 * l1 + i) * N + j, reduce128((u128)x1 * y1, m));
 }
 
 void tensor_batch(ckks_ctx* c, int level, const std::vector<TensorJob>& jobs) {
@@ -565,7 +575,7 @@ __global__ void k_rs_gather(uint64_t* __restrict__ last, uint64_t* const* __rest
   const size_t N = (size_t)1 << log_n;
   const size_t j = blockIdx.x * (size_t)KB + threadIdx.x;
   const int z = blockIdx.y;   // ct * 2 + component
-  last[(size_t)z * N + j] = cts[z >> 1][((size_t)(z & 1) * (lvl + 1) + lvl) * N + j];
+  last[(size_t)z * N + j] = gld(cts[z >> 1] + ((size_t)(z & 1) * (lvl + 1) + lvl) * N + j);
 }
 
 // d[z][i] = (h - ((x + h) mod q_l)) mod q_i for the last limb x in coefficient form
@@ -592,8 +602,8 @@ __global__ void k_rs_final(uint64_t* const* __restrict__ cts, const uint64_t* __
   uint64_t* ct = cts[z >> 1];
   for (int i = 0; i < lvl; ++i) {
     const uint64_t q = mods[i].q;
-    const uint64_t v = add_mod(ct[((size_t)comp * (lvl + 1) + i) * N + j], d[((size_t)z * lvl + i) * N + j], q);
-    ct[((size_t)comp * lvl + i) * N + j] = mul_shoup(v, k.inv[i], k.inv_s[i], q);
+    const uint64_t v = add_mod(gld(ct + ((size_t)comp * (lvl + 1) + i) * N + j), d[((size_t)z * lvl + i) * N + j], q);
+    gst(ct + ((size_t)comp * lvl + i) * N + j, mul_shoup(v, k.inv[i], k.inv_s[i], q));
   }
 }
 
@@ -653,32 +663,43 @@ __global__ void k_group_mac(const MacTerm* __restrict__ terms, const int* __rest
   const Mod m = mods[i];
   const size_t o0 = (size_t)i * N + j, o1 = ((size_t)l1 + i) * N + j;
   uint64_t* out = outs[g];
-  uint64_t a0 = accumulate ? out[o0] : 0, a1 = accumulate ? out[o1] : 0;
-  u128 s0 = 0, s1 = 0;
-  int cnt = 0;
-  for (int t = group_start[g]; t < group_start[g + 1]; ++t) {
+  uint64_t a0 = accumulate ? gld(out + o0) : 0, a1 = accumulate ? gld(out + o1) : 0;
+  // A term without a plaintext adds its ciphertext: it is multiplied by a
+  // stored 1 instead (the words are below q, so the sum is the same), which
+  // keeps the term loop free of branches.  Terms go in fours: the twelve loads
+  // of four terms are issued before their products, summed in 128 bits and
+  // reduced once per four.
+  const size_t pj = (size_t)i * N + j;
+  auto load = [&](int t, uint64_t& x0, uint64_t& x1, uint64_t& p) {
     const MacTerm tm = terms[t];
-    const size_t c0 = tm.l1 ? (size_t)i * N + j : o0;
-    const size_t c1 = tm.l1 ? ((size_t)tm.l1 + i) * N + j : o1;
-    const uint64_t x0 = tm.ct[c0], x1 = tm.ct[c1];
-    if (tm.pt) {
-      const uint64_t p = tm.pt[(size_t)i * N + j];
-      s0 += (u128)x0 * p;
-      s1 += (u128)x1 * p;
-      if (++cnt == 8) {
-        a0 = add_mod(a0, reduce128(s0, m), m.q);
-        a1 = add_mod(a1, reduce128(s1, m), m.q);
-        s0 = 0;
-        s1 = 0;
-        cnt = 0;
-      }
-    } else {
-      a0 = add_mod(a0, x0, m.q);
-      a1 = add_mod(a1, x1, m.q);
+    x0 = gld(tm.ct + (tm.l1 ? pj : o0));
+    x1 = gld(tm.ct + (tm.l1 ? ((size_t)tm.l1 + i) * N + j : o1));
+    p = gld(tm.pt ? tm.pt + pj : &k_one_word);
+  };
+  const int t_end = group_start[g + 1];
+  int t = group_start[g];
+  for (; t + 4 <= t_end; t += 4) {
+    uint64_t x0[4], x1[4], p[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) load(t + u, x0[u], x1[u], p[u]);
+    u128 s0 = 0, s1 = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      s0 += (u128)x0[u] * p[u];
+      s1 += (u128)x1[u] * p[u];
     }
+    a0 = add_mod(a0, reduce128(s0, m), m.q);
+    a1 = add_mod(a1, reduce128(s1, m), m.q);
   }
-  out[o0] = add_mod(a0, reduce128(s0, m), m.q);
-  out[o1] = add_mod(a1, reduce128(s1, m), m.q);
+  u128 s0 = 0, s1 = 0;
+  for (; t < t_end; ++t) {
+    uint64_t x0, x1, p;
+    load(t, x0, x1, p);
+    s0 += (u128)x0 * p;
+    s1 += (u128)x1 * p;
+  }
+  gst(out + o0, add_mod(a0, reduce128(s0, m), m.q));
+  gst(out + o1, add_mod(a1, reduce128(s1, m), m.q));
 }
 
 void group_mac(ckks_ctx* c, int level, const std::vector<std::vector<MacTerm>>& groups,
