@@ -465,7 +465,7 @@ def main():
         log("key-switch/s: %s" % ks)
 
     # roofline of the dominant kernel: the fused Inter-CA + combination pass on the
-    # rearranged inputs (7 bytes per residue), K plaintexts, F' outputs, weight planes
+    # rearranged inputs (6.5 bytes per residue), K plaintexts, F' outputs, weight planes
     F_out = info[0]["f_out"]
     l1 = lv0 + 1
     alg_bytes = packed_bytes + 8.0 * N * l1 * (K + 2 * F_out) + 8.0 * l1 * F * F_out
@@ -496,7 +496,7 @@ def main():
                            "%d+%d primes, %d input cts resident" % (args.config, w.graph.n, "-".join(map(str, dims)),
                                                                      K, prm["log_n"], L, prm["n_p"], n_in),
                            form="batched, HIP-graph replay (fused Inter-CA pass, batched key switches); layer-1 "
-                                "inputs resident as the matrix-core pass's operands (7 bytes per residue, rearranged "
+                                "inputs resident as the matrix-core pass's operands (6.5 bytes per residue, rearranged "
                                 "once on arrival)",
                            ntt_schedule=dict(cols_column=ntt_cols[0], cols_row=ntt_cols[1],
                                              log_column_pass=ntt_cols[2])),

@@ -288,10 +288,13 @@ ficgcn_status ficgcn_gcn_layer(ckks_ctx* ctx, const ckks_keys* eval_keys, const 
 /* Inputs of an Inter-CA layer stored as the operands of its matrix-core pass
  * (Sec. 3.3.2's aggregation fused with App. B's combination): for each wave
  * of the pass (16 coefficients of one limb of one component) and each (copy,
- * 64-feature block), the seven balanced base-256 digit planes of its 64 lanes,
- * 16 bytes each: 7 bytes per residue instead of 8, and no digit work in the
- * pass.  packed_input_words: the buffer size in 64-bit words (K copies x
- * ceil(F / 64) blocks x (N / 16) x (level + 1) x 2 waves x 896 words). */
+ * 64-feature block), the seven balanced base-256 digit planes of its 64 lanes:
+ * digits 0..5 as int8 planes of 16 bytes per lane, digit 6 (in [0, 8] for a
+ * residue below 2^51) as 4-bit values, 8 bytes per lane.  6.5 bytes per
+ * residue instead of 8, and no digit work in the pass.  packed_input_words:
+ * the buffer size in 64-bit words (K copies x ceil(F / 64) blocks x (N / 16)
+ * x (level + 1) x 2 waves x 832 words); EPLAN if the layer is not Inter-CA or
+ * a prime of the chain is 2^51 or more. */
 ficgcn_status ficgcn_plan_packed_input_words(const ficgcn_plan* plan, ckks_ctx* ctx, uint32_t layer,
                                              uint64_t* words_out);
 /* Rearranges the layer's K*F input ciphertexts (as for ficgcn_gcn_layer)
@@ -299,7 +302,8 @@ ficgcn_status ficgcn_plan_packed_input_words(const ficgcn_plan* plan, ckks_ctx* 
  * words; it must stay allocated while the plan may read it) and registers it
  * with the plan's layer.  Synchronous.  EPLAN if the layer is not Inter-CA or
  * its shape or weights are outside the matrix-core pass (K <= 16, F <= 16384,
- * integer weights within 7 balanced digits). */
+ * integer weights within 7 balanced digits); EINVAL if a prime of the chain
+ * is 2^51 or more or the buffer is too small. */
 ficgcn_status ficgcn_plan_pack_inputs(ckks_ctx* ctx, ficgcn_plan* plan, uint32_t layer, const uint64_t* const* in_cts,
                                       size_t n_in, uint64_t* packed_dev, uint64_t packed_words);
 

@@ -32,6 +32,7 @@ bool mfma_weight_planes(const std::vector<int64_t>& w_int, int F, int F_out, int
                         int& n_fb);
 void mfma_pow256(ckks_ctx* c, int l1, std::vector<uint64_t>& out);
 size_t mfma_packed_words(ckks_ctx* c, int K, int F, int level);
+bool mfma_pack_supported(ckks_ctx* c);
 void mfma_pack(ckks_ctx* c, const uint64_t* in_base, size_t in_stride, const uint64_t* const* in_ptrs, int K, int F,
                int level, uint64_t* packed);
 void comb_mfma_packed(ckks_ctx* c, const std::vector<uint64_t*>& outs, const uint64_t* packed, const PtrList& pts, int K,
@@ -1285,6 +1286,7 @@ ficgcn_status ficgcn_plan_packed_input_words(const ficgcn_plan* plan, ckks_ctx* 
   if (layer >= plan->layers.size()) FICGCN_THROW(EINVAL_, "layer index out of range");
   const LayerPlan& lp = plan->layers[layer];
   if (lp.kind != 0) FICGCN_THROW(EPLAN_, "only an Inter-CA layer's inputs are rearranged");
+  if (!mfma_pack_supported(ctx)) FICGCN_THROW(EPLAN_, "rearranged inputs need primes below 2^51");
   *words_out = mfma_packed_words(ctx, lp.K, lp.f_in, lp.level_in);
   GUARD_END
 }

@@ -209,21 +209,41 @@ __global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 // ---- inputs stored as the pass's matrix operands ---------------------------
 // The layer-1 inputs rearranged once into what the pass feeds the matrix
 // cores: for every wave (the pass's wave order: tile, limb, component) and
-// every (copy, 64-feature block) step, the 7 digit planes of its 64 lanes,
-// [wave][step][plane][lane] x 16 bytes (7 bytes per residue instead of 8, no
-// digit work in the pass).  Features past F hold zero digits.
+// every (copy, 64-feature block) step, the digit planes of its 64 lanes.
+// Digits 0..5 are full int8 planes, [plane][lane] x 16 bytes; digit 6 of a
+// residue below 2^51 lies in [0, 8], so its plane is stored as 4-bit values,
+// one 8-byte word per lane: byte k of the low dword holds the values of bytes
+// k (low nibble) and 4 + k (high nibble) of the plane's first two dwords, the
+// high dword likewise for the last two.  A step is PK_STEP_WORDS 64-bit words
+// (6.5 bytes per residue instead of 8, no digit work in the pass).  Features
+// past F hold zero digits.
+constexpr size_t PK_STEP_WORDS = 6 * 64 * 2 + 64;
+
+bool mfma_pack_supported(ckks_ctx* c) { return c->mod[0] < (1ull << 51); }
 
 size_t mfma_packed_words(ckks_ctx* c, int K, int F, int level) {
   const size_t waves = ((size_t)c->N >> 4) * (size_t)(level + 1) * 2;
   const size_t steps = (size_t)(K > 0 ? K : 1) * (size_t)((F + 63) / 64);
-  return waves * steps * 7 * 64 * 2;
+  return waves * steps * PK_STEP_WORDS;
+}
+
+__device__ __forceinline__ uint64_t nibble_pack(v4i a) {
+  const uint32_t lo = ((uint32_t)a.x & 0x0F0F0F0Fu) | (((uint32_t)a.y & 0x0F0F0F0Fu) << 4);
+  const uint32_t hi = ((uint32_t)a.z & 0x0F0F0F0Fu) | (((uint32_t)a.w & 0x0F0F0F0Fu) << 4);
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+__device__ __forceinline__ v4i nibble_unpack(uint64_t v) {
+  const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  return v4i{(int)(lo & 0x0F0F0F0Fu), (int)((lo >> 4) & 0x0F0F0F0Fu), (int)(hi & 0x0F0F0F0Fu),
+             (int)((hi >> 4) & 0x0F0F0F0Fu)};
 }
 
 // one wave per (pass wave, step): the 16 words of each lane, their digit planes
 template <bool STRIDED>
 __global__ __launch_bounds__(MW) void k_mfma_pack(const uint64_t* __restrict__ in_base, size_t in_stride,
                                                   const uint64_t* const* __restrict__ in_ptrs, int K, int F, int n_fb,
-                                                  int l1, int log_n, v4i* __restrict__ packed) {
+                                                  int l1, int log_n, uint64_t* __restrict__ packed) {
   const int lane = threadIdx.x & 63;
   const size_t N = (size_t)1 << log_n;
   const size_t tiles = N >> 4;
@@ -247,9 +267,11 @@ __global__ __launch_bounds__(MW) void k_mfma_pack(const uint64_t* __restrict__ i
   v4i A[7];
 #pragma unroll
   for (int w = 0; w < 4; ++w) digit_planes_w(x, A, w);
-  v4i* dst = packed + gw * 7 * 64 + lane;
+  uint64_t* step = packed + gw * PK_STEP_WORDS;
+  v4i* dst = (v4i*)step + lane;
 #pragma unroll
-  for (int a = 0; a < 7; ++a) dst[(size_t)a * 64] = A[a];
+  for (int a = 0; a < 6; ++a) dst[(size_t)a * 64] = A[a];
+  step[6 * 64 * 2 + lane] = nibble_pack(A[6]);
 }
 
 void mfma_pack(ckks_ctx* c, const uint64_t* in_base, size_t in_stride, const uint64_t* const* in_ptrs, int K, int F,
@@ -259,20 +281,22 @@ void mfma_pack(ckks_ctx* c, const uint64_t* in_base, size_t in_stride, const uin
   const size_t items = ((size_t)c->N >> 4) * l1 * 2 * (size_t)(K > 0 ? K : 1) * n_fb;
   const size_t blocks = (items + MW / 64 - 1) / (MW / 64);
   if (blocks >= ((size_t)1 << 31)) FICGCN_THROW(EINVAL_, "input block too large to rearrange in one launch");
+  if (!mfma_pack_supported(c)) FICGCN_THROW(EINVAL_, "rearranged inputs need primes below 2^51");
   if (in_base)
     hipLaunchKernelGGL(k_mfma_pack<true>, dim3((unsigned)blocks), dim3(MW), 0, c->stream, in_base, in_stride, in_ptrs, K,
-                       F, n_fb, l1, c->log_n, (v4i*)packed);
+                       F, n_fb, l1, c->log_n, packed);
   else
     hipLaunchKernelGGL(k_mfma_pack<false>, dim3((unsigned)blocks), dim3(MW), 0, c->stream, in_base, in_stride, in_ptrs,
-                       K, F, n_fb, l1, c->log_n, (v4i*)packed);
+                       K, F, n_fb, l1, c->log_n, packed);
   HIPCHECK(hipGetLastError());
 }
 
-// The pass on rearranged inputs: per step the 7 planes are one 16-byte load
-// each (the next step's issued before this step's matrix products), then the
+// The pass on rearranged inputs: per step six 16-byte plane loads and one
+// 8-byte load of the top digit's nibbles (the next step's issued before this
+// step's matrix products), the nibbles widened to bytes in registers, then the
 // same products, folds and output as the pass on ciphertext words.
 __global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_fused_mfma_packed(
-    OutList out, int n_out, const v4i* __restrict__ packed, PtrList pts, int K, int n_fb, int l1,
+    OutList out, int n_out, const uint64_t* __restrict__ packed, PtrList pts, int K, int n_fb, int l1,
     const v4i* __restrict__ wd, const uint64_t* __restrict__ pow256, int log_n, const Mod* __restrict__ mods) {
   const int lane = threadIdx.x & 63;
   const size_t N = (size_t)1 << log_n;
@@ -286,23 +310,32 @@ __global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   const Mod m = mods[i];
   const int KK = K > 0 ? K : 1;
   const int n_steps = KK * n_fb;
-  const v4i* src = packed + wave * (size_t)n_steps * 7 * 64 + lane;
+  const uint64_t* src = packed + wave * (size_t)n_steps * PK_STEP_WORDS;
   const uint64_t* pw = pow256 + (size_t)i * 13;
   uint64_t h[4] = {0, 0, 0, 0};
   v4i acc[13];
 #pragma unroll
   for (int s = 0; s < 13; ++s) acc[s] = v4i{0, 0, 0, 0};
-  v4i Aa[7], Ab[7];
+  // per step: planes 0..5 as 16-byte loads, plane 6 as one 8-byte nibble word
+  v4i Aa[6], Ab[6];
+  uint64_t Ta, Tb;
+  auto load_step = [&](int st, v4i (&A)[6], uint64_t& T) {
+    const uint64_t* w = src + (size_t)st * PK_STEP_WORDS;
 #pragma unroll
-  for (int a = 0; a < 7; ++a) Aa[a] = src[(size_t)a * 64];
+    for (int a = 0; a < 6; ++a) A[a] = ((const v4i*)w)[(size_t)a * 64 + lane];
+    T = w[6 * 64 * 2 + lane];
+  };
+  load_step(0, Aa, Ta);
   int k = 0, fb = 0;
   for (int step = 0; step < n_steps; step += 2) {
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       const int st = step + half;
       if (st >= n_steps) break;
-      v4i (&A)[7] = half ? Ab : Aa;
-      v4i (&An)[7] = half ? Aa : Ab;
+      v4i (&A6)[6] = half ? Ab : Aa;
+      v4i (&An)[6] = half ? Aa : Ab;
+      const uint64_t T = half ? Tb : Ta;
+      uint64_t& Tn = half ? Ta : Tb;
       const bool last = fb == n_fb - 1;
       v4i B[7];
 #pragma unroll
@@ -313,11 +346,9 @@ __global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         for (int rr = 0; rr < 4; ++rr) pk[rr] = pts.p[k][(size_t)i * N + tile * 16 + 4 * g + rr];
       }
       __builtin_amdgcn_sched_barrier(0);
-      if (st + 1 < n_steps) {
-#pragma unroll
-        for (int a = 0; a < 7; ++a) An[a] = src[((size_t)(st + 1) * 7 + a) * 64];
-      }
+      if (st + 1 < n_steps) load_step(st + 1, An, Tn);
       __builtin_amdgcn_sched_barrier(0);
+      const v4i A[7] = {A6[0], A6[1], A6[2], A6[3], A6[4], A6[5], nibble_unpack(T)};
 #pragma unroll
       for (int b = 0; b < 7; ++b)
 #pragma unroll
@@ -357,13 +388,14 @@ void comb_mfma_packed(ckks_ctx* c, const std::vector<uint64_t*>& outs, const uin
   ProfScope ps(c, prof_name);
   const int n_out = (int)outs.size();
   if (n_out > 16 || K > PtrList::MAX || F > 16384 || !packed) FICGCN_THROW(EINVAL_, "shape outside the matrix-core pass");
+  if (!mfma_pack_supported(c)) FICGCN_THROW(EINVAL_, "rearranged inputs need primes below 2^51");
   const int l1 = level + 1;
   OutList o{};
   for (int l = 0; l < n_out; ++l) o.p[l] = outs[l];
   const int n_fb = (F + 63) / 64;
   const size_t waves = ((size_t)c->N >> 4) * l1 * 2;
   hipLaunchKernelGGL(k_fused_mfma_packed, dim3((unsigned)(waves / (MW / 64))), dim3(MW), 0, c->stream, o, n_out,
-                     (const v4i*)packed, pts, K, n_fb, l1, (const v4i*)wd, pw, c->log_n, c->t.mods);
+                     packed, pts, K, n_fb, l1, (const v4i*)wd, pw, c->log_n, c->t.mods);
   HIPCHECK(hipGetLastError());
 }
 

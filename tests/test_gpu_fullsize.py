@@ -77,7 +77,9 @@ def test_cora_first_layer_sparse_inputs_bit_exact():
             assert np.array_equal(got, want[l]), ("mode", mode, "output", l, "picks", picks)
     # the same layer from the inputs rearranged as the matrix-core pass's operands
     packed = p.ficgcn_plan_pack_inputs(0, ins)
-    assert packed.numel() < 0.91 * block.numel()      # 7 bytes per residue, the last feature block padded
+    # digits 0..5 as bytes, digit 6 as a nibble: 832 words per (wave, step), the last feature block padded
+    assert packed.numel() == K * -(-F // 64) * (prm.N // 16) * (lv + 1) * 2 * 832
+    assert packed.numel() < 0.85 * block.numel()
     for mode in (1, 2, 2):
         for x in outs:
             x.zero_()

@@ -255,3 +255,30 @@ def test_radix2_plan_matches_oracle(fg, name, mode, cpoo, kw):
             assert p.ficgcn_plan_operand_level(li, i) == (lvl, float(prm.q[lvl]))
             assert np.array_equal(p.ficgcn_plan_operand_slots(li, i), v)
     assert p.ficgcn_plan_rot_steps() == o.rot_steps(prm.M)
+
+
+def test_top_digit_of_rearranged_inputs_fits_a_nibble():
+    """The rearranged-input layout stores digit 6 of each residue's balanced
+    base-256 form as a 4-bit value, which needs it in [0, 15] for every
+    residue the layout accepts (primes below 2^51).  Digits are computed from
+    their definition: x = sum_a d_a 256^a with every d_a in [-128, 127]."""
+    def digits(x):
+        out = []
+        for _ in range(7):
+            d = x % 256
+            if d >= 128:
+                d -= 256
+            out.append(d)
+            x = (x - d) // 256
+        assert x == 0
+        return out
+    rng = np.random.default_rng(7)
+    edge = [0, 1, 127, 128, (1 << 48) - 1, 1 << 48, (1 << 50) - 1, (1 << 51) - 1,
+            sum(127 << (8 * a) for a in range(6)) + (1 << 48)]
+    xs = edge + [int(v) for v in rng.integers(0, 1 << 51, 20000, dtype=np.int64)]
+    tops = []
+    for x in xs:
+        d = digits(x)
+        assert sum(v * 256 ** a for a, v in enumerate(d)) == x
+        tops.append(d[6])
+    assert min(tops) >= 0 and max(tops) <= 8
