@@ -257,3 +257,28 @@ def test_rearranged_inputs_give_the_same_words(name, contiguous):
         nxt = [ctx.ct_buffer(info[1]["level_in"]) for _ in range(info[1]["n_out_cts"])]
         with pytest.raises(e["fg"].FicgcnError):
             p.ficgcn_gcn_layer(e["ev"], 1, None, nxt, mode=1)
+
+
+def test_rearranged_inputs_refuse_primes_of_51_bits_or_more():
+    """The rearranged layout stores the top digit of each residue in 4 bits,
+    which holds only below 2^51: with 52-bit primes the size query and the
+    rearrangement itself (given a buffer of the full size) are refused."""
+    from paper_2506_10399_amd import ficgcn as fg, graph
+    w = make_workload("tiny")
+    params = dict(w.params, q_bits=52)
+    ctx = fg.Context.from_dict(params)
+    assert min(ctx.ckks_ctx_moduli()[:params["n_q"]]) >= 1 << 51
+    rp, col, val = graph.normalize(w.graph.n, w.neighbors, w.norm)
+    p = fg.Plan(ctx, rp, col, val, w.graph.n, w.meta["dims"], w.weights, first_mode=0, family=0,
+                activation=w.activation)
+    d = p.ficgcn_plan_info()[0]
+    with pytest.raises(fg.FicgcnError):
+        p.ficgcn_plan_packed_input_words(0)
+    import torch
+    ins = [ctx.ct_buffer(d["level_in"]) for _ in range(d["n_in_cts"])]
+    # a buffer of the full size (K copies x 64-feature blocks x waves x 832 words), so that only the
+    # prime bound can refuse the call; the library checks it before any launch
+    words = d["K"] * -(-d["f_in"] // 64) * (ctx.N // 16) * (d["level_in"] + 1) * 2 * 832
+    out = torch.empty(words, dtype=torch.int64, device="cuda")
+    st = fg.lib().ficgcn_plan_pack_inputs(ctx.h, p.h, 0, fg._ptr_array(ins), len(ins), fg._ptr(out), out.numel())
+    assert st != 0
