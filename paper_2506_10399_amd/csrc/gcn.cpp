@@ -908,8 +908,7 @@ static void run_layer_eager(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, in
       }
     }
     if (mode == 1) {
-      rescale_batch(c, lv, pre);
-      rescale_batch(c, lv - 1, pre);
+      rescale2_batch(c, lv, pre);
     } else {
       for (int l = 0; l < lp.f_out; ++l) {
         rescale_inplace(c, pre[l], lv);
@@ -944,12 +943,19 @@ static void run_layer_eager(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, in
       }
     }
     int lvc = lv;
-    for (int r = 0; r < lp.n_rescale_comb; ++r) {
+    for (int r = 0; r < lp.n_rescale_comb;) {
+      if (mode == 1 && r + 2 <= lp.n_rescale_comb) {
+        rescale2_batch(c, lvc, colp);
+        lvc -= 2;
+        r += 2;
+        continue;
+      }
       if (mode == 1)
         rescale_batch(c, lvc, colp);
       else
         for (int l = 0; l < lp.f_out; ++l) rescale_inplace(c, colp[l], lvc);
       --lvc;
+      ++r;
     }
     if (lvc != lp.level_agg) FICGCN_THROW(EPLAN_, "inconsistent schedule");
     const size_t agg_words = (size_t)2 * (lvc + 1) * N;

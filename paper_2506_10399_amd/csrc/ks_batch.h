@@ -50,6 +50,9 @@ void keyswitch_masked_sum(ckks_ctx* c, int level, const std::vector<const uint64
 void tensor_batch(ckks_ctx* c, int level, const std::vector<TensorJob>& jobs);
 // rounding rescale of each ciphertext in place ([2][l+1][N] -> [2][l][N])
 void rescale_batch(ckks_ctx* c, int level, const std::vector<uint64_t*>& cts);
+// two rescales in a row (level, then level - 1) in one pass over the limbs;
+// the same words as two rescale_batch calls
+void rescale2_batch(ckks_ctx* c, int level, const std::vector<uint64_t*>& cts);
 // outs[g] (accumulate ? += : =) sum of groups[g]'s terms
 void group_mac(ckks_ctx* c, int level, const std::vector<std::vector<MacTerm>>& groups,
                const std::vector<uint64_t*>& outs, bool accumulate);

@@ -637,6 +637,106 @@ void rescale_batch(ckks_ctx* c, int level, const std::vector<uint64_t*>& cts) {
   stream_sync(c);
 }
 
+// Two rescales in one call, c'' = round(round(c / q_l) / q_{l-1}), word for
+// word.  With x_l and x_{l-1} the last two limbs in coefficient form,
+//   d_i = (h_l - [x_l + h_l]_{q_l}) mod q_i            (first correction),
+//   y   = (x_{l-1} + d_{l-1}) q_l^-1 mod q_{l-1}        (limb l-1 after it),
+//   e_i = (h_{l-1} - [y + h_{l-1}]_{q_{l-1}}) mod q_i   (second correction),
+// and, the NTT being linear modulo each q_i, for i < l - 1
+//   c''_i = c_i (q_l q_{l-1})^-1 + NTT_i((d_i q_l^-1 + e_i) q_{l-1}^-1)  mod q_i,
+// which is what two rescales in a row compute, with one forward NTT of l - 1
+// limbs instead of l + (l - 1).  h_k = floor(q_k / 2).
+constexpr int RS2_MAX = 32;
+struct RSK2 {
+  uint64_t h1[RS2_MAX], h2[RS2_MAX];            // h_l, h_{l-1} mod q_i
+  uint64_t inv1[RS2_MAX], inv1_s[RS2_MAX];      // q_l^-1 mod q_i, Shoup
+  uint64_t inv2[RS2_MAX], inv2_s[RS2_MAX];      // q_{l-1}^-1 mod q_i
+  uint64_t inv12[RS2_MAX], inv12_s[RS2_MAX];    // (q_l q_{l-1})^-1 mod q_i
+};
+
+// last[z][0] = limb l-1, last[z][1] = limb l of component z
+__global__ void k_rs2_gather(uint64_t* __restrict__ last, uint64_t* const* __restrict__ cts, int lvl, int log_n) {
+  const size_t N = (size_t)1 << log_n;
+  const size_t j = blockIdx.x * (size_t)KB + threadIdx.x;
+  const int z = blockIdx.y, u = blockIdx.z;   // z = ct * 2 + component; u = 0: limb l-1, 1: limb l
+  last[((size_t)z * 2 + u) * N + j] = gld(cts[z >> 1] + ((size_t)(z & 1) * (lvl + 1) + lvl - 1 + u) * N + j);
+}
+
+// f[z][i] = (d_i q_l^-1 + e_i) q_{l-1}^-1 mod q_i for i < l - 1, coefficient form
+__global__ void k_rs2_prep(const uint64_t* __restrict__ last, uint64_t* __restrict__ f, int lvl, RSK2 k, int log_n,
+                           const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << log_n;
+  const size_t j = blockIdx.x * (size_t)KB + threadIdx.x;
+  const int i = blockIdx.y, z = blockIdx.z;
+  const uint64_t ql = mods[lvl].q, qm = mods[lvl - 1].q, q = mods[i].q;
+  const uint64_t xm = last[((size_t)z * 2 + 0) * N + j], xl = last[((size_t)z * 2 + 1) * N + j];
+  const uint64_t y1 = add_mod(xl, ql / 2, ql);                        // < q_l < q_{l-1} < q_i (descending chain)
+  const uint64_t dm = sub_mod(k.h1[lvl - 1], y1, qm);
+  const uint64_t y = mul_shoup(add_mod(xm, dm, qm), k.inv1[lvl - 1], k.inv1_s[lvl - 1], qm);
+  const uint64_t y2 = add_mod(y, qm / 2, qm);                         // < q_{l-1} < q_i
+  const uint64_t d = sub_mod(k.h1[i], y1, q), e = sub_mod(k.h2[i], y2, q);
+  const uint64_t t = add_mod(mul_shoup(d, k.inv1[i], k.inv1_s[i], q), e, q);
+  f[((size_t)z * (lvl - 1) + i) * N + j] = mul_shoup(t, k.inv2[i], k.inv2_s[i], q);
+}
+
+// c''_i = c_i (q_l q_{l-1})^-1 + f_i, compacted in place from [2][l+1][N] to
+// [2][l-1][N]: one thread walks the limbs of one component upwards, so each
+// write lands on a limb this thread has already read (or on a dropped limb of
+// the first component, which no thread reads).
+__global__ void k_rs2_final(uint64_t* const* __restrict__ cts, const uint64_t* __restrict__ f, int lvl, RSK2 k,
+                            int log_n, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << log_n;
+  const size_t j = blockIdx.x * (size_t)KB + threadIdx.x;
+  const int z = blockIdx.y;
+  const int comp = z & 1;
+  uint64_t* ct = cts[z >> 1];
+  for (int i = 0; i < lvl - 1; ++i) {
+    const uint64_t q = mods[i].q;
+    const uint64_t v = mul_shoup(gld(ct + ((size_t)comp * (lvl + 1) + i) * N + j), k.inv12[i], k.inv12_s[i], q);
+    gst(ct + ((size_t)comp * (lvl - 1) + i) * N + j, add_mod(v, f[((size_t)z * (lvl - 1) + i) * N + j], q));
+  }
+}
+
+void rescale2_batch(ckks_ctx* c, int level, const std::vector<uint64_t*>& cts) {
+  if (cts.empty()) return;
+  if (level < 2 || level > RS2_MAX) {
+    rescale_batch(c, level, cts);
+    rescale_batch(c, level - 1, cts);
+    return;
+  }
+  ProfScope ps(c, "rescale");
+  const size_t N = c->N;
+  const int n = (int)cts.size();
+  uint64_t* const* cd = upload(c, S_RS_PTR, cts);
+  uint64_t* last = (uint64_t*)dev_scratch(c, S_RS_LAST, (size_t)2 * n * 2 * N * 8);
+  uint64_t* f = (uint64_t*)dev_scratch(c, S_RS_D, (size_t)2 * n * (level - 1) * N * 8);
+  hipLaunchKernelGGL(k_rs2_gather, dim3(N / KB, 2 * n, 2), dim3(KB), 0, c->stream, last, cd, level, c->log_n);
+  HIPCHECK(hipGetLastError());
+  ntt_inv(c, last, 2, LimbMap{level - 1, 1 << 30, 0}, 2 * n, 2 * N);
+  RSK2 k{};
+  const uint64_t ql = c->mod[level], qm = c->mod[level - 1];
+  for (int i = 0; i < level; ++i) {
+    const uint64_t q = c->mod[i];
+    k.h1[i] = (ql / 2) % q;
+    k.inv1[i] = invmod(ql % q, q);
+    k.inv1_s[i] = shoup(k.inv1[i], q);
+    if (i < level - 1) {
+      k.h2[i] = (qm / 2) % q;
+      k.inv2[i] = invmod(qm % q, q);
+      k.inv2_s[i] = shoup(k.inv2[i], q);
+      k.inv12[i] = (uint64_t)((u128)k.inv1[i] * k.inv2[i] % q);
+      k.inv12_s[i] = shoup(k.inv12[i], q);
+    }
+  }
+  hipLaunchKernelGGL(k_rs2_prep, dim3(N / KB, level - 1, 2 * n), dim3(KB), 0, c->stream, last, f, level, k, c->log_n,
+                     c->t.mods);
+  HIPCHECK(hipGetLastError());
+  ntt_fwd(c, f, level - 1, lm_q(level - 1), 2 * n, (size_t)(level - 1) * N);
+  hipLaunchKernelGGL(k_rs2_final, dim3(N / KB, 2 * n), dim3(KB), 0, c->stream, cd, f, level, k, c->log_n, c->t.mods);
+  HIPCHECK(hipGetLastError());
+  stream_sync(c);
+}
+
 // outs[g] (+)= sum over the terms of group g of ct (.) pt, or ct when pt is null
 __global__ void k_group_mac(const MacTerm* __restrict__ terms, const int* __restrict__ group_start,
                             uint64_t* const* __restrict__ outs, int l1, int accumulate, int log_n, int n_groups,
