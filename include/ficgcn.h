@@ -182,6 +182,24 @@ ficgcn_status ckks_rescale(ckks_ctx* ctx, uint64_t* ct_dev, uint32_t level);
 ficgcn_status ckks_mul_relin(ckks_ctx* ctx, const ckks_keys* eval_keys, const uint64_t* x_dev, const uint64_t* y_dev,
                              uint32_t level, uint64_t* out_dev);
 
+/* ckks_mul_relin without device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments and the same output words as ckks_mul_relin;
+ * its intermediates (tensor product, ModUp digits, inner products, ModDown
+ * conversion: (3 (level+1) + ceil((level+1)/n_p) (level+1+n_p) + 2 (level+1+n_p))
+ * limbs of N words) live in one fixed device array of
+ * ckks_mul_relin_noalloc_limit() bytes (64 MiB) that each GPU holds from the
+ * library's load until the process ends; a call that needs more returns
+ * FICGCN_ENOMEM and enqueues nothing.  The context must already have its
+ * device tables (any earlier device call on it, such as ckks_keygen, sets
+ * them up; else EINVAL) and must belong to the current device.  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other host threads) race and must be serialised by the caller;
+ * nothing in the array needs clearing between calls. */
+ficgcn_status ckks_mul_relin_noalloc(ckks_ctx* ctx, const ckks_keys* eval_keys, const uint64_t* x_dev,
+                                     const uint64_t* y_dev, uint32_t level, uint64_t* out_dev);
+size_t ckks_mul_relin_noalloc_limit(void);
+
 /* ------------------------------------------------------------ plan [server] */
 /* Plan options. */
 typedef struct {

@@ -12,7 +12,8 @@ OUT = os.path.join(HERE, "libficgcn.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 SOURCES = ["context.cpp", "encode.cpp", "capi.cpp", "plan.cpp", "gcn.cpp",
            "ntt.hip", "ops.hip", "sample.hip", "gcn_kernels.hip",
-           "ks_batch.hip", "gcn_mfma.hip", "search.cpp", "mlp.hip", "server.cpp", "radix2.cpp", "encode_gpu.hip"]
+           "ks_batch.hip", "gcn_mfma.hip", "search.cpp", "mlp.hip", "server.cpp", "radix2.cpp", "encode_gpu.hip",
+           "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

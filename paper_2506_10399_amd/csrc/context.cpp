@@ -158,6 +158,11 @@ void ensure_device(ckks_ctx* c) {
   HIPCHECK(hipMalloc(&c->t.mods, c->h_mods.size() * sizeof(Mod)));
   HIPCHECK(hipMemcpy(c->t.mods, c->h_mods.data(), c->h_mods.size() * sizeof(Mod), hipMemcpyHostToDevice));
   c->on_device = true;
+  // every base-conversion table of the chain, so later calls find them built
+  for (int level = 0; level < c->L; ++level) {
+    for (int d = 0; d * c->alpha <= level; ++d) get_modup(c, level, d);
+    get_moddown(c, level);
+  }
 }
 
 // FastBConv constants: hat_b = prod_{s' != s} b_{s'}; hat_inv[s] = hat_b^-1 mod b_s;

@@ -180,10 +180,11 @@ void add_inplace(ckks_ctx* c, uint64_t* acc, const uint64_t* in, int n_limbs, in
 void automorph_ntt(ckks_ctx* c, uint64_t* out, const uint64_t* in, uint64_t g, int n_limbs, int n_polys);
 void bconv(ckks_ctx* c, const BConv& bc, const uint64_t* src, uint64_t* dst_base, const int* dst_pos_dev,
            int n_polys, size_t src_poly_stride, size_t dst_poly_stride);
-void modup(ckks_ctx* c, const uint64_t* a_ntt, int level, uint64_t* D);
+// tmp / conv: caller scratch of (level+1) resp. 2 (level+1) limbs, or null for the context's own
+void modup(ckks_ctx* c, const uint64_t* a_ntt, int level, uint64_t* D, uint64_t* tmp = nullptr);
 void keymac(ckks_ctx* c, uint64_t* acc, const uint64_t* D, const uint64_t* key, int level, uint64_t g);
 void moddown(ckks_ctx* c, uint64_t* acc, int level, uint64_t* out, const uint64_t* add0, uint64_t g_add0,
-             const uint64_t* add1);
+             const uint64_t* add1, uint64_t* conv = nullptr);
 void rescale_inplace(ckks_ctx* c, uint64_t* ct, int level);
 void tensor(ckks_ctx* c, const uint64_t* x, const uint64_t* y, uint64_t* d, int level);
 void copy_d2d(ckks_ctx* c, void* dst, const void* src, size_t bytes);

@@ -129,12 +129,12 @@ static BConvDev bconv_indices(ckks_ctx*, const BConv& bc, int) { return BConvDev
 // scratch slots used here (contexts own them)
 enum { S_MODUP_TMP = 1, S_IDX_A = 2, S_IDX_B = 3, S_MD_TMP = 4, S_RS_TMP = 5, S_RS_D = 6 };
 
-void modup(ckks_ctx* c, const uint64_t* a_ntt, int level, uint64_t* D) {
+void modup(ckks_ctx* c, const uint64_t* a_ntt, int level, uint64_t* D, uint64_t* tmp) {
   ProfScope ps(c, "modup");
   const size_t N = c->N;
   const int l1 = level + 1, ext = l1 + c->alpha;
   const int nd = (l1 + c->alpha - 1) / c->alpha;
-  uint64_t* tmp = (uint64_t*)c->buf(S_MODUP_TMP, (size_t)l1 * N * 8);
+  if (!tmp) tmp = (uint64_t*)c->buf(S_MODUP_TMP, (size_t)l1 * N * 8);
   HIPCHECK(hipMemcpyAsync(tmp, a_ntt, (size_t)l1 * N * 8, hipMemcpyDeviceToDevice, c->stream));
   ntt_inv(c, tmp, l1, lm_q(l1), 1, 0);
   for (int d = 0; d < nd; ++d) {
@@ -242,7 +242,7 @@ static MDConst md_const(ckks_ctx* c, int level) {
 }
 
 void moddown(ckks_ctx* c, uint64_t* acc, int level, uint64_t* out, const uint64_t* add0, uint64_t g_add0,
-             const uint64_t* add1) {
+             const uint64_t* add1, uint64_t* conv) {
   ProfScope ps(c, "moddown");
   const size_t N = c->N;
   const int l1 = level + 1, ext = l1 + c->alpha;
@@ -251,7 +251,7 @@ void moddown(ckks_ctx* c, uint64_t* acc, int level, uint64_t* out, const uint64_
   const BConv& bc = get_moddown(c, level);
   BConvDev idx = bconv_indices(c, bc, S_IDX_B);
   MDConst k = md_const(c, level);
-  uint64_t* conv = (uint64_t*)c->buf(S_MD_TMP, (size_t)2 * l1 * N * 8);
+  if (!conv) conv = (uint64_t*)c->buf(S_MD_TMP, (size_t)2 * l1 * N * 8);
   hipLaunchKernelGGL(k_moddown_conv, dim3(N / EW, 2), dim3(EW), 0, c->stream, acc + (size_t)l1 * N, (size_t)ext * N,
                      idx.src_mod, idx.dst_mod, bc.n_src, bc.n_dst, (const uint64_t*)bc.dev, k, conv, (size_t)l1 * N,
                      c->log_n, c->t.mods);

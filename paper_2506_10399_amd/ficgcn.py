@@ -101,6 +101,8 @@ _SIGS = {
     "ckks_add": (ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_uint32]),
     "ckks_rescale": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32]),
     "ckks_mul_relin": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.c_uint32, c_vp]),
+    "ckks_mul_relin_noalloc": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.c_uint32, c_vp]),
+    "ckks_mul_relin_noalloc_limit": (ctypes.c_size_t, []),
     "ficgcn_plan_create": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.c_uint32, c_vp, ctypes.c_uint32, c_vp,
                                           ctypes.POINTER(PlanOpts), ctypes.POINTER(c_vp)]),
     "ficgcn_plan_destroy": (None, [c_vp]),
@@ -364,6 +366,10 @@ class Context:
     def ckks_mul_relin(self, eval_keys: "Keys", x, y, level: int, out=None):
         out = self.ct_buffer(level) if out is None else out
         _check(lib().ckks_mul_relin(self.h, eval_keys.h, _ptr(x), _ptr(y), level, _ptr(out)))
+        return out
+
+    def ckks_mul_relin_noalloc(self, eval_keys: "Keys", x, y, level: int, out):
+        _check(lib().ckks_mul_relin_noalloc(self.h, eval_keys.h, _ptr(x), _ptr(y), level, _ptr(out)))
         return out
 
 

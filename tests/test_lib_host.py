@@ -20,7 +20,7 @@ HEADER = os.path.join(ROOT, "include", "ficgcn.h")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:ficgcn_status|void|const char\*)\s+(\w+)\s*\(", src, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:ficgcn_status|void|const char\*|size_t)\s+(\w+)\s*\(", src, flags=re.M)))
 
 
 @pytest.fixture(scope="module")
