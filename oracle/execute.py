@@ -47,7 +47,16 @@ def schedule(prm: Params, plan: Plan) -> List[dict]:
     out = []
     for lp in plan.layers:
         st = dict(level_in=lv, scale_in=s)
-        if lp.kind == "inter":
+        if lp.kind == "inter" and lp.pack == "rep":
+            # case-1 layout: the plaintexts carry A_hat_k (x) W, one level
+            if lv < 1:
+                raise ValueError("not enough levels")
+            st["sP"] = float(prm.q[lv])
+            st["sW"] = 0.0
+            s = s * st["sP"]
+            s = s / float(prm.q[lv])
+            lv -= 1
+        elif lp.kind == "inter":
             if lv < 2:
                 raise ValueError("not enough levels")
             st["sP"] = float(prm.q[lv])
@@ -133,7 +142,17 @@ def encode_operands(prm: Params, plan: Plan, weights, sched=None) -> List[dict]:
     ops = []
     for li, (lp, w, st) in enumerate(zip(plan.layers, weights, sched)):
         d = dict(W=weight_ints(w, st["sW"]))
-        if lp.kind == "inter":
+        if lp.kind == "spintra" and lp.comb == "diag":
+            # block-rotation combination masks at the weight scale, on the key basis for the
+            # nonzero offsets (their products are taken before the one ModDown)
+            cm = sim.diag_masks(plan, lp, w)
+            lv = st["level_in"]
+            d["CM"] = {s_: (enc.encode(prm, cm[s_], st["sW"], lv) if s_ == 0
+                            else enc.encode_ext(prm, cm[s_], st["sW"], lv)) for s_ in lp.comb_shifts}
+        if lp.kind == "inter" and lp.pack == "rep":
+            lv = st["level_in"]
+            d["P"] = [enc.encode(prm, p, st["sP"], lv) for p in sim.rep_plaintexts(plan, lp, w)]
+        elif lp.kind == "inter":
             lv = st["level_in"]
             d["P"] = [enc.encode(prm, p, st["sP"], lv) for p in sim.inter_plaintexts(plan, lp)]
         elif lp.family == 4:
@@ -153,14 +172,15 @@ def encode_operands(prm: Params, plan: Plan, weights, sched=None) -> List[dict]:
 
 
 def client_encrypt(prm: Params, plan: Plan, x: np.ndarray, keys: ckks.Keys, seed: int) -> List[ckks.Ciphertext]:
-    """The client's input ciphertexts, ct id = k * F + f (copy k, column f)."""
+    """The client's input ciphertexts, ct id = k * J + j (copy k, ciphertext j of the copy:
+    column j, or columns j t .. j t + t - 1 in the case-1 layout)."""
     lp = plan.layers[0]
     copies = sim.client_layout(plan, x, lp)
     cts = []
     for k, vecs in enumerate(copies):
         for f, v in enumerate(vecs):
             pt = enc.encode(prm, v, prm.scale, prm.L - 1)
-            cts.append(ckks.encrypt(prm, seed, k * lp.f_in + f, keys.s, pt))
+            cts.append(ckks.encrypt(prm, seed, k * len(vecs) + f, keys.s, pt))
     return cts
 
 
@@ -171,7 +191,28 @@ def _zero(prm, level, scale):
 def run_layer(prm: Params, plan: Plan, li: int, keys: ckks.Keys, cts: List[ckks.Ciphertext],
               ops: dict, st: dict) -> List[ckks.Ciphertext]:
     lp = plan.layers[li]
-    if lp.kind == "inter":
+    if lp.kind == "inter" and lp.pack == "rep":
+        # Sec. 3.2 case 1: every input ciphertext times its A_hat_k (x) W plaintext, summed;
+        # rescale; the t column blocks folded onto the first by ceil(log2 t) rotations
+        lv = st["level_in"]
+        acc = ckks.pt_mul_acc(prm, _zero(prm, lv, st["scale_in"] * st["sP"]), cts, ops["P"])
+        acc = ckks.rescale(prm, acc)
+        for step in lp.fold_steps:
+            acc = ckks.add(prm, acc, ckks.rotate(prm, keys, acc, step))
+        outs = [acc]
+    elif lp.kind == "spintra" and lp.comb == "diag":
+        # block-rotation combination of the packed input (one ModUp, the mask products on the
+        # key basis, one ModDown), its rescales, then the aggregation on the packed blocks
+        h = cts[0]
+        steps = [s_ for s_ in lp.comb_shifts if s_ != 0]
+        y = ckks.rotate_masked_sum(prm, keys, h, [s_ * lp.B for s_ in steps], [ops["CM"][s_] for s_ in steps])
+        if 0 in lp.comb_shifts:
+            y = ckks.pt_mul_acc(prm, y, [h], [ops["CM"][0]])
+        y.scale = st["scale_in"] * st["sW"]
+        for _ in range(st["n_rescale_comb"]):
+            y = ckks.rescale(prm, y)
+        outs = [aggregate(prm, plan, li, keys, y, ops["masks"][0], st)]
+    elif lp.kind == "inter":
         lv = st["level_in"]
         F = lp.f_in
         Z = []
@@ -310,6 +351,8 @@ def decrypt_output(prm: Params, plan: Plan, keys: ckks.Keys, cts: List[ckks.Ciph
     li = len(plan.layers) - 1 if li is None else li
     lp = plan.layers[li]
     slots = [np.real(enc.decode(prm, ckks.decrypt(prm, keys.s, c))) for c in cts]
+    if lp.kind == "inter" and lp.pack == "rep":
+        return sim.read_output_layer(plan, lp, slots, ("packed", plan.M // lp.B, lp.B))
     if lp.kind == "inter":
         return sim.read_output_layer(plan, lp, slots, ("cols",))
     return sim.read_output_layer(plan, lp, slots, ("packed", lp.t, lp.B))

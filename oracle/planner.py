@@ -80,6 +80,34 @@ def paper_packing_t(F: int, n: int, n_nodes: int, F_out: int, M: int) -> int:
     return best
 
 
+def rep_block(t: int, f_out: int, n_nodes: int, M: int) -> Optional[int]:
+    """Node block Bc of the case-1 layout (Sec. 3.2, App. B): a ciphertext holds t input
+    columns, each repeated for the layer's F' output columns, every (input column, output
+    column) pair a block of Bc = M / (t pow2(F')) slots holding the nodes; None when
+    pow2(n_nodes) does not fit Bc (the paper's t N F' <= M with N and F' rounded up to
+    powers of two)."""
+    if t < 1 or f_out < 1:
+        return None
+    Bc = M // (t * next_pow2(f_out))
+    return Bc if Bc >= next_pow2(n_nodes) else None
+
+
+def rule_packing(F: int, n: int, n_nodes: int, F_out: int, M: int, later_widths=()) -> tuple:
+    """The first layer's packing by the paper's rule (Sec. 3.2, App. B): case M <= N F' ->
+    one column per ciphertext ("cols", 1); else the case-1 layout at the J argmin t
+    (paper_packing_t), halved while the layout does not fit or a later layer's width
+    exceeds its column capacity M / Bc."""
+    if M <= n_nodes * F_out:
+        return ("cols", 1)
+    t = paper_packing_t(F, n, n_nodes, F_out, M)
+    while t >= 1:
+        Bc = rep_block(t, F_out, n_nodes, M)
+        if Bc is not None and all(f <= M // Bc for f in later_widths):
+            return ("rep", t)
+        t //= 2
+    return ("cols", 1)
+
+
 def paper_agg_mode(F: int, n: int, t: int, n_nodes: int, c: float) -> str:
     """argmin{ Inter-CA: 2 ceil(F n / t), SpIntra-CA: 10 c n log^2 N } (Sec. 3.3.2)."""
     inter = 2 * ceil_div(F * n, t)
@@ -269,6 +297,22 @@ class LayerPlan:
     cpoo: Optional[float] = None   # family 3: CPOO sparsity threshold (None = off)
     # shifts per (ciphertext) of the pack step: -l*B for l = 1..t-1
     pack_steps: List[int] = field(default_factory=list)
+    # inter: "cols" (one input column per ciphertext, the combination as integer-weight
+    # sums) or "rep" (the case-1 layout of Sec. 3.2 / App. B: t input columns per
+    # ciphertext repeated over the F' output columns, plaintexts A_hat_k (x) W-slice,
+    # the t column blocks summed by ceil(log2 t) rotations; t, B = Bc, fold_steps)
+    pack: str = "cols"
+    fold_steps: List[int] = field(default_factory=list)
+    # spintra: "scalar" (columns combined by integer weights, then packed by rotations)
+    # or "diag" (input already packed in blocks of B: output block c = sum_l W[l, c] *
+    # input block l, as sum over s of Rot_{sB}(input) (.) cm_s with cm_s block c =
+    # W[c + s, c]; s in comb_shifts)
+    comb: str = "scalar"
+    comb_shifts: List[int] = field(default_factory=list)
+    # Sec. 3.3.2's aggregation-mode formula for this layer (later layers): the chosen mode
+    # and both costs (Inter-CA 2 ceil(F n / t), SpIntra-CA 10 c n log2(N)^2)
+    paper_mode: Optional[str] = None
+    paper_mode_costs: tuple = ()
 
 
 @dataclass
@@ -284,11 +328,15 @@ class Plan:
     @property
     def n_out_cts(self) -> int:
         last = self.layers[-1]
-        return last.f_out if last.kind == "inter" else ceil_div(last.f_out, last.t)
+        if last.kind == "inter":
+            return 1 if last.pack == "rep" else last.f_out
+        return ceil_div(last.f_out, last.t)
 
     def rot_steps(self, M: int) -> List[int]:
         steps = set()
         for lp in self.layers:
+            steps.update(s % M for s in lp.fold_steps)
+            steps.update((s * lp.B) % M for s in lp.comb_shifts)
             if lp.kind != "spintra":
                 continue
             steps.update(s % M for s in lp.pack_steps)
@@ -331,10 +379,71 @@ def rotation_steps_of(lp: LayerPlan) -> List[int]:
     return sorted(babies | giants)
 
 
+def _inter_copies(n_v: int, rows, K: int):
+    """Copy k of node v: its k-th non-self term (copy 0 = the node itself)."""
+    src = np.full((K, n_v), -1, dtype=np.int64)
+    val = np.zeros((K, n_v))
+    for v, row in enumerate(rows):
+        k = 1
+        for u, a in row:
+            if u == v:
+                src[0, v], val[0, v] = v, a
+            else:
+                src[k, v], val[k, v] = u, a
+                k += 1
+    return src, val
+
+
+def _mode_costs(f_in: int, n: int, t: int, n_v: int, c: float):
+    inter = 2 * ceil_div(f_in * n, t)
+    spintra = 10.0 * c * n * math.log2(max(n_v, 2)) ** 2
+    return ("inter" if inter <= spintra else "spintra"), (inter, spintra)
+
+
+def _spintra_layer(n_v, rows, pi, M, B, f_in, f_out, activation, family, cpoo, aoo):
+    """SpIntra-CA routing of one layer on blocks of B slots (shared by both layouts)."""
+    wrap = B == M
+    shifts = sorted({reduce_shift(int(pi[u] - pi[v]), M, wrap) for v, row in enumerate(rows) for u, _ in row})
+    G, c2 = bsgs_split(shifts, B)
+    c1 = len(set(shifts) - {0})
+    fam = family if family is not None else (2 if c2 < c1 else 1)
+    prog = radix2.build_program(pi, rows, M, B, wrap and aoo, cpoo) if fam == 3 else None
+    return LayerPlan("spintra", f_in, f_out, activation, t=M // B, B=B, shifts=shifts, family=fam, G=G,
+                     program=prog, cpoo=cpoo if fam == 3 else None)
+
+
+def _build_rep_plan(n_v, rows, dims, activation, M, use_noo, TH, family, t1, cpoo, agg_c, K):
+    """Inter-CA first layer in the case-1 layout at packing t1; every later layer is
+    SpIntra-CA on the packed blocks of Bc slots with the block-rotation combination."""
+    n_layers = len(dims) - 1
+    Bc = rep_block(t1, dims[1], n_v, M)
+    if TH is None:
+        TH = 1024 if n_v < 10000 else 4096
+    if use_noo:
+        pi, regions = noo(rows, Bc, M, TH)
+    else:
+        if n_v > Bc:
+            raise ValueError("graph does not fit the column block")
+        pi, regions = np.arange(n_v, dtype=np.int64), [list(range(n_v))]
+    src, val = _inter_copies(n_v, rows, K)
+    S = next_pow2(dims[1]) * Bc
+    lp0 = LayerPlan("inter", dims[0], dims[1], activation, K=K, copy_src=src, copy_val=val, pack="rep",
+                    t=t1, B=Bc, fold_steps=[(1 << i) * S for i in range(clog2(t1))])
+    layers = [lp0]
+    for li in range(1, n_layers):
+        f_in, f_out = dims[li], dims[li + 1]
+        lp = _spintra_layer(n_v, rows, pi, M, Bc, f_in, f_out, activation, family, cpoo, True)
+        lp.comb = "diag"
+        lp.comb_shifts = list(range(-(f_out - 1), f_in))
+        lp.paper_mode, lp.paper_mode_costs = _mode_costs(f_in, K - 1, lp.t, n_v, agg_c)
+        layers.append(lp)
+    return Plan(n_v=n_v, M=M, B_pi=Bc, pi=pi, rows=rows, layers=layers, regions=regions)
+
+
 def build_plan(n_v: int, rows, dims: Sequence[int], activation: bool, M: int,
                use_noo: bool = True, TH: Optional[int] = None, family: Optional[int] = None,
                first_mode: str = "inter", t: Optional[int] = None, cpoo: Optional[float] = None,
-               aoo: bool = True) -> Plan:
+               aoo: bool = True, first_pack="cols", agg_c: float = 1.0) -> Plan:
     """The executable plan: layer 1 by `first_mode` ("inter" per the paper's
     first-layer rule, or "spintra"), later layers SpIntra-CA; SpIntra layers
     combine first (F -> F' at one column per ciphertext), pack t = min(pow2(F'),
@@ -344,11 +453,30 @@ def build_plan(n_v: int, rows, dims: Sequence[int], activation: bool, M: int,
     and M / pow2(n_v)) replaces that rule for every SpIntra layer.
     family: None = the cheaper of 1 and 2 by rotation count; 3 = the paper's
     radix-2 routing (Sec. 3.3), with CPOO at threshold `cpoo` when given;
-    aoo=False takes its shifts unreduced around the ring (the AOO ablation)."""
+    aoo=False takes its shifts unreduced around the ring (the AOO ablation).
+    first_pack (Inter-CA first layer): "cols" = one column per ciphertext; "rule" = the
+    paper's packing rule (rule_packing: case 1 layout at the J argmin t, else "cols"); an
+    int t = the case-1 layout at that t.  With the case-1 layout every later layer takes its
+    input packed in blocks of Bc and combines it by block rotations ("diag").
+    agg_c: the factor c of Sec. 3.3.2's aggregation-mode formula, recorded per later layer."""
     n_layers = len(dims) - 1
     if first_mode == "spintra" and n_layers > 1:
         raise ValueError("a SpIntra-CA layer leaves packed ciphertexts; only the last layer may be SpIntra-CA "
                          "when it is also the first")
+    K_all = 1 + max(sum(1 for u, _ in row if u != v) for v, row in enumerate(rows))
+    pack1, t1 = "cols", 1
+    if first_mode == "inter" and first_pack != "cols":
+        later = list(dims[2:])
+        if first_pack == "rule":
+            pack1, t1 = rule_packing(dims[0], K_all - 1, n_v, dims[1], M, later)
+        else:
+            t1 = int(first_pack)
+            Bc = rep_block(t1, dims[1], n_v, M) if t1 >= 1 and not t1 & (t1 - 1) else None
+            if Bc is None or any(f > M // Bc for f in later):
+                raise ValueError("the case-1 layout does not fit at t = %d" % t1)
+            pack1 = "rep"
+    if pack1 == "rep":
+        return _build_rep_plan(n_v, rows, dims, activation, M, use_noo, TH, family, t1, cpoo, agg_c, K_all)
     # packing of the SpIntra layers fixes the block the node order must fit; a
     # SpIntra layer that feeds another layer leaves one column per ciphertext
     # (the next combination reads columns), so then every SpIntra layer packs t = 1
@@ -396,9 +524,12 @@ def build_plan(n_v: int, rows, dims: Sequence[int], activation: bool, M: int,
             fam = family if family is not None else (2 if c2 < c1 else 1)
             prog = radix2.build_program(pi, rows, M, Bl, wrap and aoo, cpoo) if fam == 3 else None
             pack = [-(l % t_l) * Bl for l in range(f_out) if l % t_l != 0]
-            layers.append(LayerPlan("spintra", f_in, f_out, activation, t=t_l, B=Bl, shifts=shifts,
-                                    family=fam, G=G, pack_steps=sorted(set(pack)), program=prog,
-                                    cpoo=cpoo if fam == 3 else None))
+            lpl = LayerPlan("spintra", f_in, f_out, activation, t=t_l, B=Bl, shifts=shifts,
+                            family=fam, G=G, pack_steps=sorted(set(pack)), program=prog,
+                            cpoo=cpoo if fam == 3 else None)
+            if li > 0:
+                lpl.paper_mode, lpl.paper_mode_costs = _mode_costs(f_in, K_all - 1, 1, n_v, agg_c)
+            layers.append(lpl)
     return Plan(n_v=n_v, M=M, B_pi=B, pi=pi, rows=rows, layers=layers, regions=regions)
 
 
@@ -409,18 +540,34 @@ def op_counts(plan: Plan) -> dict:
     c = dict(rot=0, pmult=0, cmult=0, smult=0, add=0, rescale=0, keyswitch=0)
     n_cts = None
     for li, lp in enumerate(plan.layers):
-        if lp.kind == "inter":
+        if lp.kind == "inter" and lp.pack == "rep":
+            # Sec. 3.2 case 1: ceil(F K / t) PMult and Add (one per input ciphertext, each with its
+            # A_hat_k (x) W plaintext, accumulated), ceil(log2 t) rotations folding the column blocks
+            n_in = lp.K * ceil_div(lp.f_in, lp.t)
+            c["pmult"] += n_in
+            c["add"] += n_in
+            c["rot"] += clog2(lp.t)
+            c["rescale"] += 1
+            n_cts = 1
+        elif lp.kind == "inter":
             c["pmult"] += lp.K * lp.f_in
             c["add"] += lp.K * lp.f_in
             c["smult"] += lp.f_in * lp.f_out
             c["rescale"] += 2 * lp.f_out
             n_cts = lp.f_out
         else:
-            n_in = lp.f_in
-            c["smult"] += n_in * lp.f_out
-            c["rescale"] += lp.f_out
             n_packed = ceil_div(lp.f_out, lp.t)
-            c["rot"] += lp.f_out - n_packed
+            if lp.comb == "diag":
+                # the block-rotation combination: one mask product per block offset, a rotation per
+                # nonzero offset (one packed input, one packed output)
+                c["pmult"] += len(lp.comb_shifts)
+                c["add"] += len(lp.comb_shifts)
+                c["rot"] += sum(1 for d in lp.comb_shifts if d != 0)
+                c["rescale"] += 1
+            else:
+                c["smult"] += lp.f_in * lp.f_out
+                c["rescale"] += lp.f_out
+                c["rot"] += lp.f_out - n_packed
             steps = rotation_steps_of(lp)
             if lp.family == 3:
                 c["rot"] += n_packed * len(lp.program.rotations())

@@ -27,6 +27,8 @@ def client_layout(plan: Plan, x: np.ndarray, lp: LayerPlan) -> List[List[np.ndar
     spintra: copies[0][f][pi(v)] = x[v, f] (one column per ciphertext)."""
     M = plan.M
     n = plan.n_v
+    if lp.kind == "inter" and lp.pack == "rep":
+        return rep_client_layout(plan, x, lp)
     if lp.kind == "inter":
         out = []
         for k in range(lp.K):
@@ -56,6 +58,73 @@ def inter_plaintexts(plan: Plan, lp: LayerPlan) -> List[np.ndarray]:
         p = np.zeros(plan.M)
         p[plan.pi[have]] = lp.copy_val[k][have]
         out.append(p)
+    return out
+
+
+def rep_slot(lp: LayerPlan, b: int, l: int) -> int:
+    """First slot of the block of input column b (within the ciphertext) and output column l
+    in the case-1 layout: (b pow2(F') + l) Bc."""
+    Fp = 1
+    while Fp < lp.f_out:
+        Fp *= 2
+    return (b * Fp + l) * lp.B
+
+
+def rep_client_layout(plan: Plan, x: np.ndarray, lp: LayerPlan) -> List[List[np.ndarray]]:
+    """Case-1 layout (Sec. 3.2, App. B): ciphertext j of copy k holds input columns
+    j t + b (b < t) of the copy, column b repeated for every output column l < F':
+    slot rep_slot(b, l) + pi(v) = x[src_k(v), j t + b]."""
+    J = -(-lp.f_in // lp.t)
+    out = []
+    for k in range(lp.K):
+        src = lp.copy_src[k]
+        have = src >= 0
+        vecs = []
+        for j in range(J):
+            v = np.zeros(plan.M)
+            for b in range(lp.t):
+                f = j * lp.t + b
+                if f >= lp.f_in:
+                    break
+                for l in range(lp.f_out):
+                    v[rep_slot(lp, b, l) + plan.pi[have]] = x[src[have], f]
+            vecs.append(v)
+        out.append(vecs)
+    return out
+
+
+def rep_plaintexts(plan: Plan, lp: LayerPlan, w: np.ndarray) -> List[np.ndarray]:
+    """Operand k * J + j of the case-1 layout: slot rep_slot(b, l) + pi(v) =
+    A_hat[v, src_k(v)] * W[j t + b, l] (the copy's adjacency value times the weight)."""
+    J = -(-lp.f_in // lp.t)
+    out = []
+    for k in range(lp.K):
+        src = lp.copy_src[k]
+        have = src >= 0
+        for j in range(J):
+            p = np.zeros(plan.M)
+            for b in range(lp.t):
+                f = j * lp.t + b
+                if f >= lp.f_in:
+                    break
+                for l in range(lp.f_out):
+                    p[rep_slot(lp, b, l) + plan.pi[have]] = lp.copy_val[k][have] * w[f, l]
+            out.append(p)
+    return out
+
+
+def diag_masks(plan: Plan, lp: LayerPlan, w: np.ndarray) -> dict:
+    """Block-rotation combination of an input packed in blocks of B: cm_s[c B + pi(v)] =
+    W[c + s, c] for output column c < F' and input column c + s < F, so that
+    sum_s Rot_{sB}(H) (.) cm_s holds sum_l W[l, c] H_l in block c."""
+    out = {}
+    for s_ in lp.comb_shifts:
+        v = np.zeros(plan.M)
+        for c in range(lp.f_out):
+            l = c + s_
+            if 0 <= l < lp.f_in:
+                v[c * lp.B + plan.pi] = w[l, c]
+        out[s_] = v
     return out
 
 
@@ -110,7 +179,18 @@ def run(plan: Plan, x: np.ndarray, weights, counts: dict = None) -> List[np.ndar
     cur = None          # list of slot vectors, one column per vector (t = 1) or packed
     layout = None       # ("cols", None) or ("packed", t, B)
     for li, (lp, w) in enumerate(zip(plan.layers, weights)):
-        if lp.kind == "inter":
+        if lp.kind == "inter" and lp.pack == "rep":
+            copies = client_layout(plan, x, lp)
+            pts = rep_plaintexts(plan, lp, w)
+            J = len(copies[0])
+            acc = sum(pts[k * J + j] * copies[k][j] for k in range(lp.K) for j in range(J))
+            counts["pmult"] += lp.K * J
+            for st in lp.fold_steps:
+                acc = acc + rot(acc, st)
+                counts["rot"] += 1
+            cur = [acc]
+            layout = ("packed", plan.M // lp.B, lp.B)
+        elif lp.kind == "inter":
             copies = client_layout(plan, x, lp)
             pts = inter_plaintexts(plan, lp)
             z = [sum(pts[k] * copies[k][f] for k in range(lp.K)) for f in range(lp.f_in)]
@@ -118,6 +198,13 @@ def run(plan: Plan, x: np.ndarray, weights, counts: dict = None) -> List[np.ndar
             cur = [sum(w[f, l] * z[f] for f in range(lp.f_in)) for l in range(lp.f_out)]
             counts["smult"] += lp.f_in * lp.f_out
             layout = ("cols",)
+        elif lp.comb == "diag":
+            cm = diag_masks(plan, lp, w)
+            y = sum(rot(cur[0], s_ * lp.B) * cm[s_] for s_ in lp.comb_shifts)
+            counts["pmult"] += len(lp.comb_shifts)
+            counts["rot"] += sum(1 for s_ in lp.comb_shifts if s_ != 0)
+            cur = [aggregate_packed(plan, lp, y, lp.f_out, counts)]
+            layout = ("packed", lp.t, lp.B)
         else:
             if li == 0:
                 cur = client_layout(plan, x, lp)[0]

@@ -213,3 +213,120 @@ def test_encrypted_plan_decrypts_to_fp64_gcn(name, mode, fam):
     outs = ex.run(prm, plan, keys, cts, ops, sched)
     y = ex.decrypt_output(prm, plan, keys, outs[-1])
     assert gcn.max_rel_error(y, ref) < 1e-3
+
+
+def _hand_regions_fixture():
+    with open(os.path.join(GOLD, "noo_regions_hand.txt")) as f:
+        lines = [l.strip() for l in f if l.strip() and not l.startswith("#")]
+    edges = [tuple(map(int, e.split("-"))) for e in lines[0].split()[1:]]
+    n = int(lines[1].split()[1])
+    cases = []
+    for l in lines[2:]:
+        head, body = l.split(":")
+        cases.append((int(head.split()[1]), [list(map(int, r.split())) for r in body.split("|")]))
+    return n, edges, cases
+
+
+def test_noo_regions_hand_worked_example():
+    """Alg. 1 stage 1 against regions worked out by hand (tests/golden): sibling BFS
+    from the highest-degree node, ascending enqueue, restart inside the region when
+    the BFS runs dry."""
+    n, edges, cases = _hand_regions_fixture()
+    adj = [set([v]) for v in range(n)]
+    for a, b in edges:
+        adj[a].add(b)
+        adj[b].add(a)
+    rows = [[(u, 1.0) for u in sorted(adj[v])] for v in range(n)]
+    for TH, want in cases:
+        assert planner.noo_regions(rows, TH) == want, TH
+
+
+def test_rule_packing_picks_the_papers_t():
+    """App. B's rule on the case-1 layout: the tiny configuration (F 32, F' 16, 128 nodes,
+    M 4096) packs t = 2; the citation-graph shapes and the clustered shape are case 2
+    (M <= N F'), one column per ciphertext."""
+    assert planner.rule_packing(32, 4, 128, 16, 4096) == ("rep", 2)
+    assert planner.rep_block(2, 16, 128, 4096) == 128
+    assert planner.rep_block(4, 16, 128, 4096) is None
+    assert planner.rule_packing(1433, 4, 2708, 16, 32768) == ("cols", 1)
+    assert planner.rule_packing(3703, 3, 3327, 16, 32768) == ("cols", 1)
+    assert planner.rule_packing(500, 5, 19717, 16, 32768) == ("cols", 1)
+    # a later layer wider than the packed capacity M / Bc (32 at t = 2, 16 at t = 1) falls
+    # back to smaller t, then to one column per ciphertext
+    assert planner.rule_packing(32, 4, 64, 16, 4096, later_widths=[40]) == ("rep", 4)
+    assert planner.rule_packing(32, 4, 128, 16, 4096, later_widths=[20]) == ("rep", 2)
+    assert planner.rule_packing(32, 4, 128, 16, 4096, later_widths=[40]) == ("cols", 1)
+    w, rows = _rows("tiny")
+    plan = planner.build_plan(w.graph.n, rows, w.meta["dims"], False, 4096, first_pack="rule")
+    assert plan.layers[0].pack == "rep" and plan.layers[0].t == 2 and plan.B_pi == 128
+
+
+@pytest.mark.parametrize("n_nodes,t", [(128, 1), (128, 2), (64, 4)])
+def test_case1_counts_equal_the_papers_formulas(n_nodes, t):
+    """Sec. 3.2 case 1 / App. B: PMult = Add = ceil(F n / t) (n counted as the K = n + 1
+    copies the layer reads) and ceil(log2 t) rotations, as equalities; the simulator
+    performs exactly those operations and equals the FP64 GCN."""
+    w, rows = _rows("tiny", n_nodes=n_nodes)
+    F, Fo = w.meta["dims"]
+    plan = planner.build_plan(w.graph.n, rows, w.meta["dims"], False, 4096, first_pack=t)
+    lp = plan.layers[0]
+    oc = planner.op_counts(plan)
+    assert oc["pmult"] == lp.K * math.ceil(F / t) and oc["add"] == lp.K * math.ceil(F / t)
+    assert oc["rot"] == math.ceil(math.log2(t)) if t > 1 else oc["rot"] == 0
+    assert oc["smult"] == 0 and oc["rescale"] == 1
+    counts = dict(rot=0, pmult=0, smult=0, cmult=0)
+    out = sim.run(plan, w.x, w.weights, counts)
+    ref = gcn.gcn_forward(rows, w.x, w.weights, False)[-1]
+    assert gcn.max_rel_error(out, ref) < 1e-12
+    assert counts["pmult"] == oc["pmult"] and counts["rot"] == oc["rot"]
+
+
+@pytest.mark.parametrize("name,kw,t,noo", [("tiny2", dict(n_nodes=100), 2, True), ("tiny2", dict(n_nodes=100), 1, False),
+                                           ("ntu_small", {}, "rule", True)])
+def test_case1_layout_deeper_models_equal_fp64(name, kw, t, noo):
+    """Later layers on the packed blocks (block-rotation combination, then SpIntra-CA):
+    the slot simulator equals the FP64 GCN and its operation counts equal op_counts."""
+    w, rows = _rows(name, **kw)
+    M = 2 ** (w.params["log_n"] - 1)
+    plan = planner.build_plan(w.graph.n, rows, w.meta["dims"], w.activation, M, use_noo=noo, first_pack=t)
+    assert plan.layers[0].pack == "rep" and all(lp.comb == "diag" for lp in plan.layers[1:])
+    counts = dict(rot=0, pmult=0, smult=0, cmult=0)
+    out = sim.run(plan, w.x, w.weights, counts)
+    ref = gcn.gcn_forward(rows, w.x, w.weights, w.activation)[-1]
+    assert gcn.max_rel_error(out, ref) < 1e-12
+    oc = planner.op_counts(plan)
+    assert all(oc[k] == counts[k] for k in counts)
+    # the block combination's offsets span every (input block, output block) pair once
+    lp = plan.layers[1]
+    assert lp.comb_shifts == list(range(-(lp.f_out - 1), lp.f_in))
+
+
+def test_aggregation_mode_formula_recorded_per_layer():
+    """Sec. 3.3.2's argmin for later layers: Inter-CA 2 ceil(F n / t) against SpIntra-CA
+    10 c n log2(N)^2; at the citation-graph shape's second layer (F 16, n 4, t 1, 2708
+    nodes) Inter-CA wins unless c < 128 / 5201."""
+    w, rows = _rows("cora", n_nodes=2708, dims=[8, 16, 7])
+    for c, want in ((1.0, "inter"), (0.01, "spintra")):
+        plan = planner.build_plan(w.graph.n, rows, [8, 16, 7], True, 32768, use_noo=False, agg_c=c)
+        lp = plan.layers[1]
+        n = plan.layers[0].K - 1
+        assert lp.paper_mode == want
+        assert lp.paper_mode_costs[0] == 2 * math.ceil(16 * n / 1)
+        assert lp.paper_mode_costs[1] == pytest.approx(10 * c * n * math.log2(2708) ** 2)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,kw", [("tiny", {}), ("tiny2", dict(n_nodes=100))])
+def test_case1_encrypted_plan_decrypts_to_fp64_gcn(name, kw):
+    w, rows = _rows(name, **kw)
+    prm = Params.from_dict(w.params)
+    ref = gcn.gcn_forward(rows, w.x, w.weights, w.activation)[-1]
+    plan = planner.build_plan(w.graph.n, rows, w.meta["dims"], w.activation, prm.M, first_pack="rule")
+    assert plan.layers[0].pack == "rep" and plan.layers[0].t == 2
+    keys = ckks.keygen(prm, 11, plan.rot_steps(prm.M), relin=w.activation)
+    sched = ex.schedule(prm, plan)
+    ops = ex.encode_operands(prm, plan, w.weights, sched)
+    cts = ex.client_encrypt(prm, plan, w.x, keys, 12)
+    outs = ex.run(prm, plan, keys, cts, ops, sched)
+    y = ex.decrypt_output(prm, plan, keys, outs[-1])
+    assert gcn.max_rel_error(y, ref) < 1e-3
