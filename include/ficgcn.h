@@ -219,6 +219,18 @@ typedef struct {
                            shorter way round the ring (AOO, Sec. 3.3.1, off: for its ablation) */
   double cpoo;          /* family 3: CPOO sparsity threshold in [0, 1] (Sec. 3.3.1; the paper's ablation,
                            Sec. 4.2.2, finds 0.2-0.3 best); 0 = CPOO off */
+  int32_t first_pack;   /* Inter-CA first layer's packing (Sec. 3.2, App. B): 0 = one input column per
+                           ciphertext (combination as integer-weight sums); -1 = the paper's rule: when
+                           M > N F', the case-1 layout at the argmin t of J(t; F, n) = 2 ceil(F n / t)
+                           + 20 ceil(log2 t) over powers of two with t pow2(F') pow2(N) <= M (halved
+                           while a later layer is wider than t pow2(F')), else 0; t > 0 = the case-1
+                           layout at that t.  In the case-1 layout ciphertext j of copy k holds input
+                           columns j t .. j t + t - 1, each repeated for the F' output columns in
+                           blocks of Bc = M / (t pow2(F')) slots, node v at offset pi(v); the layer's
+                           operands are A_hat_k (x) W-slices, its ceil(log2 t) rotations fold the
+                           column blocks, and it outputs one ciphertext whose block l holds output
+                           column l; later layers combine such blocks by block rotations */
+  double agg_c;         /* the factor c of Sec. 3.3.2's aggregation-mode formula (0 = 1.0) */
 } ficgcn_plan_opts;
 
 /* Builds the plan of an n_layers-layer GCN over the normalised adjacency
@@ -243,8 +255,17 @@ ficgcn_status ficgcn_plan_copy_sources(const ficgcn_plan* plan, uint32_t layer, 
 /* Rotation steps whose keys the client must generate (sorted, in [1, M)). */
 ficgcn_status ficgcn_plan_rot_steps(const ficgcn_plan* plan, int64_t* steps_out, size_t cap, size_t* n_out);
 /* Plan description: per layer {kind, f_in, f_out, K, t, B, family, G,
- * n_shifts, level_in, level_out, n_in_cts, n_out_cts} as int64, 13 per layer,
- * then 3 doubles per layer in scales_out {scale_in, scale_out, weight scale}. */
+ * n_shifts, level_in, level_out, n_in_cts, n_out_cts, pack (1 = the case-1
+ * layout of an Inter-CA layer), comb (1 = block-rotation combination of a
+ * packed input), fold rotations, combination offsets, paper_mode (Sec. 3.3.2's
+ * formula for a later layer: 0 Inter-CA, 1 SpIntra-CA, -1 not evaluated)} as
+ * int64, 18 per layer, then 5 doubles per layer in scales_out {scale_in,
+ * scale_out, weight scale, Inter-CA cost 2 ceil(F n / t), SpIntra-CA cost
+ * 10 c n log2(N)^2}.  The executed mode of a later layer is SpIntra-CA either
+ * way: an Inter-CA later layer would first build its K neighbour copies from
+ * the previous layer's ciphertext by rotations and masks, and those copies'
+ * products with the K adjacency plaintexts merge into exactly the diagonal
+ * SpIntra-CA form. */
 ficgcn_status ficgcn_plan_info(const ficgcn_plan* plan, int64_t* info_out, double* scales_out, uint32_t* n_layers);
 /* Shifts of layer `layer` (SpIntra-CA), sorted. */
 ficgcn_status ficgcn_plan_shifts(const ficgcn_plan* plan, uint32_t layer, int64_t* out, size_t cap, size_t* n_out);

@@ -280,13 +280,17 @@ static void aggregate_r2_plain(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, 
 // product of the automorphed digits, multiplied by the mask on the key basis
 // and summed, and sigma(c0) (.) mask summed on Q_l; one ModDown of the sum;
 // the identity shift's plain mask product; rescale.
-static void aggregate_dh_plain(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, int g, const uint64_t* y,
-                               uint64_t* out) {
+// out = sum_k Rot_{steps[k]}(y) (.) masks[k] at level lv, one operation per call: the nonzero
+// steps' key inner products times their masks summed on the key basis (masks of those steps
+// hold level+1+alpha limbs), one ModDown; a zero step is a plain mask product.  No rescale.
+static void masked_sum_plain(ckks_ctx* c, const ckks_keys* ek, const uint64_t* y, int lv,
+                             const std::vector<int64_t>& steps, const std::vector<const uint64_t*>& masks,
+                             uint64_t* out) {
   const size_t N = c->N;
-  const int lv = lp.level_agg, l1 = lv + 1, ext = l1 + c->alpha;
+  const int l1 = lv + 1, ext = l1 + c->alpha;
   const int nd = (l1 + c->alpha - 1) / c->alpha;
-  const size_t ns = lp.shifts.size();
-  auto mask = [&](size_t si) { return (const uint64_t*)lp.ops[(size_t)g * ns + si]; };
+  const size_t ns = steps.size();
+  auto mask = [&](size_t si) { return masks[si]; };
   uint64_t* D = (uint64_t*)c->buf(40, (size_t)nd * ext * N * 8);
   uint64_t* acc = (uint64_t*)c->buf(41, (size_t)2 * ext * N * 8);
   uint64_t* A = (uint64_t*)c->buf(78, (size_t)2 * ext * N * 8);
@@ -302,13 +306,13 @@ static void aggregate_dh_plain(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, 
     pmul_acc(c, out, a, b, 1, l1);
   };
   for (size_t si = 0; si < ns; ++si) {
-    const int64_t d = lp.shifts[si];
-    if (d == 0) {
+    const int64_t d = steps[si];
+    uint64_t gal;
+    const uint64_t* key = rot_key(c, ek, d, gal);
+    if (!key) {
       mac(y, mask(si));
       continue;
     }
-    uint64_t gal;
-    const uint64_t* key = rot_key(c, ek, d, gal);
     keymac(c, acc, D, key, lv, gal);
     mac_ext(c, A, acc, mask(si), lv);
     automorph_ntt(c, t, y, gal, l1, 1);
@@ -317,7 +321,15 @@ static void aggregate_dh_plain(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, 
   uint64_t* md = (uint64_t*)c->buf(44, (size_t)2 * l1 * N * 8);
   moddown(c, A, lv, md, nullptr, 1, nullptr);
   add_inplace(c, out, md, l1, 2);
-  rescale_inplace(c, out, lv);
+}
+
+static void aggregate_dh_plain(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, int g, const uint64_t* y,
+                               uint64_t* out) {
+  const size_t ns = lp.shifts.size();
+  std::vector<const uint64_t*> masks(ns);
+  for (size_t si = 0; si < ns; ++si) masks[si] = lp.ops[(size_t)g * ns + si];
+  masked_sum_plain(c, ek, y, lp.level_agg, lp.shifts, masks, out);
+  rescale_inplace(c, out, lp.level_agg);
 }
 
 static void aggregate(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, int g, const uint64_t* y, uint64_t* out) {
@@ -832,6 +844,82 @@ void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const u
   run_layer_eager(c, ek, p, li, in, n_in, out, n_out, mode);
 }
 
+// Case-1 Inter-CA layer (Sec. 3.2, App. B): acc = sum_i in_i (.) P_i (P_i = A_hat_k (x) W-slice
+// of input ciphertext i), rescale, then acc += Rot(acc, step) for each fold step, so the first
+// column group's blocks hold sum over every input column
+static void inter_rep(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, const uint64_t* const* in, size_t n_in,
+                      uint64_t* out, int mode) {
+  const size_t N = c->N;
+  const int lv = lp.level_in, l1 = lv + 1, lo = lv - 1;
+  const size_t lo_words = (size_t)2 * (lo + 1) * N;
+  for (int64_t step : lp.fold_steps) {
+    uint64_t gal;
+    if (!rot_key(c, ek, step, gal)) FICGCN_THROW(EPLAN_, "identity fold step");
+  }
+  if (mode == 1) {
+    std::vector<std::vector<MacTerm>> grp(1);
+    for (size_t i = 0; i < n_in; ++i) grp[0].push_back(MacTerm{in[i], lp.ops[i]});
+    group_mac(c, lv, grp, {out}, false);
+    rescale_batch(c, lv, {out});
+    if (lp.fold_steps.empty()) return;
+    uint64_t* tmp = (uint64_t*)dev_scratch(c, 38, lo_words * 8);
+    for (int64_t step : lp.fold_steps) {
+      uint64_t gal;
+      const uint64_t* key = rot_key(c, ek, step, gal);
+      keyswitch_batch(c, lo, {out + (size_t)(lo + 1) * N}, {KSJob{key, out, nullptr, nullptr, gal, 0, 0}}, {tmp},
+                      false);
+      group_mac(c, lo, {{MacTerm{tmp, nullptr}}}, {out}, true);
+    }
+    return;
+  }
+  zero_fill(c, out, (size_t)2 * l1 * N);
+  for (size_t i0 = 0; i0 < n_in; i0 += PtrList::MAX) {
+    PtrList a{}, b{};
+    const int nk = (int)std::min<size_t>(PtrList::MAX, n_in - i0);
+    for (int k = 0; k < nk; ++k) {
+      a.p[k] = in[i0 + k];
+      b.p[k] = lp.ops[i0 + k];
+    }
+    pmul_acc(c, out, a, b, nk, l1);
+  }
+  rescale_inplace(c, out, lv);
+  uint64_t* rt = (uint64_t*)c->buf(37, lo_words * 8);
+  for (int64_t step : lp.fold_steps) {
+    rotate_one(c, ek, out, lo, step, rt);
+    add_inplace(c, out, rt, lo + 1, 2);
+  }
+}
+
+// Block-rotation combination of an input packed in blocks of B: y = sum_s Rot_{sB}(h) (.) cm_s,
+// the nonzero offsets' mask products on the key basis before one ModDown.  No rescale.
+static void comb_diag(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, const uint64_t* h, uint64_t* y, int mode) {
+  const size_t N = c->N;
+  const int lv = lp.level_in, l1 = lv + 1;
+  const size_t na = lp.n_agg_ops();
+  std::vector<int64_t> steps;
+  std::vector<const uint64_t*> masks;
+  for (size_t k = 0; k < lp.comb_shifts.size(); ++k) {
+    steps.push_back(lp.comb_shifts[k] * lp.B);
+    masks.push_back(lp.ops[na + k]);
+  }
+  if (mode != 1) {
+    masked_sum_plain(c, ek, h, lv, steps, masks, y);
+    return;
+  }
+  std::vector<std::vector<MacTerm>> init(1);
+  std::vector<KSJob> jobs;
+  for (size_t k = 0; k < steps.size(); ++k) {
+    uint64_t gal;
+    const uint64_t* key = rot_key(c, ek, steps[k], gal);
+    if (!key)
+      init[0].push_back(MacTerm{h, masks[k]});
+    else
+      jobs.push_back(KSJob{key, h, nullptr, masks[k], gal, 0, 0});
+  }
+  group_mac(c, lv, init, {y}, false);
+  if (!jobs.empty()) keyswitch_masked_sum(c, lv, {h + (size_t)l1 * N}, jobs, {y}, true);
+}
+
 static void run_layer_eager(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const uint64_t* const* in,
                             size_t n_in, uint64_t* const* out, size_t n_out, int mode) {
   LayerPlan& lp = p->layers[li];
@@ -860,7 +948,33 @@ static void run_layer_eager(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, in
   } else {
     for (size_t i = 0; i < n_out; ++i) pre[i] = out[i];
   }
-  if (lp.kind == 0) {
+  if (lp.kind == 0 && lp.pack) {
+    if (packed) FICGCN_THROW(EPLAN_, "rearranged inputs are for one column per ciphertext");
+    inter_rep(c, ek, lp, in, n_in, pre[0], mode);
+  } else if (lp.kind == 1 && lp.comb) {
+    uint64_t* y = (uint64_t*)dev_scratch(c, 36, ct_words * 8);
+    comb_diag(c, ek, lp, in[0], y, mode);
+    int lvc = lv;
+    for (int r = 0; r < lp.n_rescale_comb;) {
+      if (mode == 1 && r + 2 <= lp.n_rescale_comb) {
+        rescale2_batch(c, lvc, {y});
+        lvc -= 2;
+        r += 2;
+        continue;
+      }
+      if (mode == 1)
+        rescale_batch(c, lvc, {y});
+      else
+        rescale_inplace(c, y, lvc);
+      --lvc;
+      ++r;
+    }
+    if (lvc != lp.level_agg) FICGCN_THROW(EPLAN_, "inconsistent schedule");
+    if (mode == 1)
+      aggregate_batched(c, ek, lp, {y}, pre);
+    else
+      aggregate(c, ek, lp, 0, y, pre[0]);
+  } else if (lp.kind == 0) {
     const int F = lp.f_in, K = lp.K;
     if (mode == 1) {
       if (K > PtrList::MAX) FICGCN_THROW(EPLAN_, "batched form supports at most 16 Inter-CA copies");
@@ -1110,7 +1224,7 @@ ficgcn_status ficgcn_plan_info(const ficgcn_plan* plan, int64_t* info_out, doubl
   for (size_t li = 0; li < plan->layers.size(); ++li) {
     const LayerPlan& lp = plan->layers[li];
     if (info_out) {
-      int64_t* o = info_out + li * 13;
+      int64_t* o = info_out + li * 18;
       o[0] = lp.kind;
       o[1] = lp.f_in;
       o[2] = lp.f_out;
@@ -1124,11 +1238,18 @@ ficgcn_status ficgcn_plan_info(const ficgcn_plan* plan, int64_t* info_out, doubl
       o[10] = lp.level_out;
       o[11] = lp.n_in_cts();
       o[12] = lp.n_packed();
+      o[13] = lp.pack;
+      o[14] = lp.comb;
+      o[15] = (int64_t)lp.fold_steps.size();
+      o[16] = (int64_t)lp.comb_shifts.size();
+      o[17] = lp.paper_mode;
     }
     if (scales_out) {
-      scales_out[li * 3] = lp.scale_in;
-      scales_out[li * 3 + 1] = lp.scale_out;
-      scales_out[li * 3 + 2] = lp.sW;
+      scales_out[li * 5] = lp.scale_in;
+      scales_out[li * 5 + 1] = lp.scale_out;
+      scales_out[li * 5 + 2] = lp.sW;
+      scales_out[li * 5 + 3] = lp.mode_cost_inter;
+      scales_out[li * 5 + 4] = lp.mode_cost_spintra;
     }
   }
   GUARD_END
@@ -1222,21 +1343,23 @@ ficgcn_status ficgcn_plan_encode(ckks_ctx* ctx, ficgcn_plan* plan) {
     const size_t chunk = 256;
     std::vector<double> all;
     std::vector<double> v;
-    // runs of operands with one level (all of them, except for the radix-2 masks)
+    // runs of operands with one level, basis and scale
     for (size_t b0 = 0; b0 < n;) {
       size_t nb = 1;
-      while (b0 + nb < n && nb < chunk && lp.op_lv[b0 + nb] == lp.op_lv[b0]) ++nb;
+      const double sc = plan_operand_scale(plan, (int)li, b0);
+      while (b0 + nb < n && nb < chunk && lp.op_lv[b0 + nb] == lp.op_lv[b0] && lp.op_x[b0 + nb] == lp.op_x[b0] &&
+             plan_operand_scale(plan, (int)li, b0 + nb) == sc)
+        ++nb;
       all.assign(nb * plan->M, 0.0);
       for (size_t b = 0; b < nb; ++b) {
         plan_operand_slots(plan, (int)li, b0 + b, v);
         std::memcpy(all.data() + b * plan->M, v.data(), plan->M * 8);
       }
-      if (lp.op_ext) {
-        encode_batch_ext(ctx, all.data(), nb, plan->M, plan_operand_scale(plan, (int)li, b0), lp.op_lv[b0],
-                         lp.ops_block + lp.op_off[b0]);
+      if (lp.op_x[b0]) {
+        encode_batch_ext(ctx, all.data(), nb, plan->M, sc, lp.op_lv[b0], lp.ops_block + lp.op_off[b0]);
       } else {
-        ficgcn_status st = ckks_encode_batch(ctx, all.data(), nb, plan->M, plan_operand_scale(plan, (int)li, b0),
-                                             lp.op_lv[b0], lp.ops_block + lp.op_off[b0]);
+        ficgcn_status st = ckks_encode_batch(ctx, all.data(), nb, plan->M, sc, lp.op_lv[b0],
+                                             lp.ops_block + lp.op_off[b0]);
         if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
       }
       for (size_t b = 0; b < nb; ++b) lp.ops[b0 + b] = lp.ops_block + lp.op_off[b0 + b];
@@ -1255,7 +1378,7 @@ ficgcn_status ficgcn_plan_load_operand(ckks_ctx* ctx, ficgcn_plan* plan, uint32_
   if (i >= lp.ops.size()) FICGCN_THROW(EINVAL_, "operand index out of range");
   ensure_ops_block(ctx, lp);
   uint64_t* dst = lp.ops_block + lp.op_off[i];
-  if (lp.op_ext) {
+  if (lp.op_x[i]) {
     pt_load_ext(ctx, host_coeffs, lp.op_lv[i], dst);
   } else {
     ficgcn_status st = ckks_pt_load(ctx, host_coeffs, lp.op_lv[i], dst);
@@ -1276,8 +1399,8 @@ ficgcn_status ficgcn_plan_fill_operands(ckks_ctx* ctx, ficgcn_plan* plan, uint64
       uint64_t* dst = lp.ops_block + lp.op_off[i];
       const int l1 = lp.op_lv[i] + 1;
       // stream (6, layer * 2^20 + i, limb): a stream the scheme itself never draws
-      sample_uniform(ctx, dst, seed, 6, (uint32_t)(li << 20 | i), 0, l1 + (lp.op_ext ? ctx->alpha : 0),
-                     lp.op_ext ? lm_ext(lp.op_lv[i], ctx->L) : lm_q(l1), 1);
+      sample_uniform(ctx, dst, seed, 6, (uint32_t)(li << 20 | i), 0, l1 + (lp.op_x[i] ? ctx->alpha : 0),
+                     lp.op_x[i] ? lm_ext(lp.op_lv[i], ctx->L) : lm_q(l1), 1);
       lp.ops[i] = dst;
     }
   }

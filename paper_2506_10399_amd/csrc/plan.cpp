@@ -50,6 +50,58 @@ static int64_t reduce_shift(int64_t d, int64_t M, bool wrap) {
   return r > M / 2 ? r - M : r;
 }
 
+static int clog2(int64_t x) {
+  int r = 0;
+  while (((int64_t)1 << r) < x) ++r;
+  return r;
+}
+
+// J(t; F, n) = 2 ceil(F n / t) + 20 ceil(log2 t)  (Sec. 3.2 case M > N F', App. B)
+static int64_t j_objective(int64_t t, int64_t F, int64_t n) { return 2 * ((F * n + t - 1) / t) + 20 * clog2(t); }
+
+// The paper's t: the argmin of J over powers of two with t N F' <= M (ties -> smaller t);
+// 1 when M <= N F' (case 2)
+static int paper_packing_t(int64_t F, int64_t n, int64_t N, int64_t Fo, int64_t M) {
+  if (M <= N * Fo) return 1;
+  int64_t best = 1, bj = j_objective(1, F, n);
+  for (int64_t t = 2; t * N * Fo <= M; t *= 2) {
+    int64_t j = j_objective(t, F, n);
+    if (j < bj) {
+      best = t;
+      bj = j;
+    }
+  }
+  return (int)best;
+}
+
+// node block of the case-1 layout: M / (t pow2(F')), or 0 when pow2(N) does not fit it
+static int rep_block(int t, int Fo, int N, int M) {
+  if (t < 1 || Fo < 1) return 0;
+  const int Bc = M / (t * next_pow2(Fo));
+  return Bc >= next_pow2(N) ? Bc : 0;
+}
+
+// the first layer's packing by the paper's rule on the case-1 layout: t > 0 (that layout) or
+// 0 (one column per ciphertext); t halved while the layout or a later width does not fit
+static int rule_packing(int F, int n, int N, int Fo, int M, const std::vector<int>& later) {
+  if ((int64_t)M <= (int64_t)N * Fo) return 0;
+  for (int t = paper_packing_t(F, n, N, Fo, M); t >= 1; t /= 2) {
+    const int Bc = rep_block(t, Fo, N, M);
+    bool ok = Bc > 0;
+    for (int f : later) ok = ok && f <= M / std::max(Bc, 1);
+    if (ok) return t;
+  }
+  return 0;
+}
+
+// Sec. 3.3.2: Inter-CA 2 ceil(F n / t) against SpIntra-CA 10 c n log2(N)^2
+static void mode_costs(LayerPlan& lp, int n, int t, int N, double c) {
+  lp.mode_cost_inter = (double)(2 * (((int64_t)lp.f_in * n + t - 1) / t));
+  const double lg = std::log2((double)std::max(N, 2));
+  lp.mode_cost_spintra = 10.0 * c * n * (lg * lg);
+  lp.paper_mode = lp.mode_cost_inter <= lp.mode_cost_spintra ? 0 : 1;
+}
+
 struct Rows {
   int n;
   const std::vector<int32_t>& rp;
@@ -262,7 +314,17 @@ static void schedule(ckks_ctx* c, ficgcn_plan* p) {
   for (LayerPlan& lp : p->layers) {
     lp.level_in = lv;
     lp.scale_in = s;
-    if (lp.kind == 0) {
+    if (lp.kind == 0 && lp.pack) {
+      // case-1 layout: the operands carry A_hat_k (x) W, one level
+      if (lv < 1) FICGCN_THROW(EPLAN_, "not enough levels for the Inter-CA layer");
+      lp.sP = (double)c->mod[lv];
+      lp.sW = 0.0;
+      s = s * lp.sP;
+      s = s / (double)c->mod[lv];
+      lv -= 1;
+      lp.op_level = lp.level_in;
+      lp.op_scale = lp.sP;
+    } else if (lp.kind == 0) {
       if (lv < 2) FICGCN_THROW(EPLAN_, "not enough levels for the Inter-CA layer");
       lp.sP = (double)c->mod[lv];
       lp.sW = (double)c->mod[lv - 1];
@@ -315,23 +377,42 @@ static void schedule(ckks_ctx* c, ficgcn_plan* p) {
   }
 }
 
+size_t LayerPlan::n_agg_ops() const {
+  if (kind == 0) return 0;
+  if (family == 3) return (size_t)n_packed() * r2.ops.size();
+  return (size_t)n_packed() * shifts.size();
+}
+
+// Operands of a layer, in order: Inter-CA: the K copies' adjacency plaintexts, or, in the
+// case-1 layout, K * ceil(F / t) plaintexts (copy k, input ciphertext j at k * J + j);
+// SpIntra-CA: the aggregation masks (packed ciphertext g, then shift or program operand),
+// then, for the block-rotation combination, one mask per block offset (comb_shifts order)
 size_t plan_operand_count(const ficgcn_plan* p, int li) {
   const LayerPlan& lp = p->layers[li];
-  if (lp.kind == 0) return (size_t)lp.K;
-  if (lp.family == 3) return (size_t)lp.n_packed() * lp.r2.ops.size();
-  return (size_t)lp.n_packed() * lp.shifts.size();
+  if (lp.kind == 0) return lp.pack ? (size_t)lp.n_in_cts() : (size_t)lp.K;
+  return lp.n_agg_ops() + (lp.comb ? lp.comb_shifts.size() : 0);
 }
+
+static bool is_comb_operand(const LayerPlan& lp, size_t i) { return lp.kind == 1 && lp.comb && i >= lp.n_agg_ops(); }
 
 int plan_operand_level(const ficgcn_plan* p, int li, size_t i) {
   const LayerPlan& lp = p->layers[li];
+  if (is_comb_operand(lp, i)) return lp.level_in;
   if (lp.kind == 1 && lp.family == 3) return lp.level_agg - lp.r2.ops[i % lp.r2.ops.size()].depth;
   return lp.op_level;
 }
 
 double plan_operand_scale(const ficgcn_plan* p, int li, size_t i) {
   const LayerPlan& lp = p->layers[li];
+  if (is_comb_operand(lp, i)) return lp.sW;
   if (lp.kind == 1 && lp.family == 3) return (double)p->ctx->mod[plan_operand_level(p, li, i)];
   return lp.op_scale;
+}
+
+bool plan_operand_ext(const ficgcn_plan* p, int li, size_t i) {
+  const LayerPlan& lp = p->layers[li];
+  if (is_comb_operand(lp, i)) return lp.comb_shifts[i - lp.n_agg_ops()] != 0;
+  return lp.kind == 1 && lp.family == 4;
 }
 
 static void layout_operands(ficgcn_plan* p) {
@@ -339,26 +420,56 @@ static void layout_operands(ficgcn_plan* p) {
   for (size_t li = 0; li < p->layers.size(); ++li) {
     LayerPlan& lp = p->layers[li];
     const size_t n = plan_operand_count(p, (int)li);
-    lp.op_ext = lp.kind == 1 && lp.family == 4;
+    lp.op_x.resize(n);
     lp.op_lv.resize(n);
     lp.op_off.resize(n);
     size_t off = 0;
     for (size_t i = 0; i < n; ++i) {
+      lp.op_x[i] = plan_operand_ext(p, (int)li, i) ? 1 : 0;
       lp.op_lv[i] = plan_operand_level(p, (int)li, i);
       lp.op_off[i] = off;
-      off += (size_t)(lp.op_lv[i] + 1 + (lp.op_ext ? p->ctx->alpha : 0)) * N;
+      off += (size_t)(lp.op_lv[i] + 1 + (lp.op_x[i] ? p->ctx->alpha : 0)) * N;
     }
     lp.op_words = off;
   }
 }
 
+// first slot of the block of input column b and output column l in the case-1 layout
+static size_t rep_slot(const LayerPlan& lp, int b, int l) { return ((size_t)b * next_pow2(lp.f_out) + l) * lp.B; }
+
 void plan_operand_slots(const ficgcn_plan* p, int li, size_t i, std::vector<double>& out) {
   const LayerPlan& lp = p->layers[li];
   const int M = p->M, n = p->n_v;
   out.assign(M, 0.0);
+  if (lp.kind == 0 && lp.pack) {
+    // A_hat[v, src_k(v)] * W[j t + b, l] at rep_slot(b, l) + pi(v)
+    const int J = (lp.f_in + lp.t - 1) / lp.t;
+    const int k = (int)(i / J), j = (int)(i % J);
+    for (int b = 0; b < lp.t && j * lp.t + b < lp.f_in; ++b) {
+      const int f = j * lp.t + b;
+      for (int l = 0; l < lp.f_out; ++l) {
+        const double wv = lp.w[(size_t)f * lp.f_out + l];
+        const size_t base = rep_slot(lp, b, l);
+        for (int v = 0; v < n; ++v)
+          if (lp.copy_src[(size_t)k * n + v] >= 0) out[base + p->pi[v]] = lp.copy_val[(size_t)k * n + v] * wv;
+      }
+    }
+    return;
+  }
   if (lp.kind == 0) {
     for (int v = 0; v < n; ++v)
       if (lp.copy_src[i * n + v] >= 0) out[p->pi[v]] = lp.copy_val[i * n + v];
+    return;
+  }
+  if (is_comb_operand(lp, i)) {
+    // block offset s: cm_s[c B + pi(v)] = W[c + s, c]
+    const int64_t s = lp.comb_shifts[i - lp.n_agg_ops()];
+    for (int c = 0; c < lp.f_out; ++c) {
+      const int64_t l = c + s;
+      if (l < 0 || l >= lp.f_in) continue;
+      const double wv = lp.w[(size_t)l * lp.f_out + c];
+      for (int v = 0; v < n; ++v) out[(size_t)c * lp.B + p->pi[v]] = wv;
+    }
     return;
   }
   if (lp.family == 3) {
@@ -435,6 +546,137 @@ size_t plan_operand_bytes(const ficgcn_plan* p) {
 
 namespace ficgcn {
 
+static void inter_copies(const ficgcn_plan* p, LayerPlan& lp, int K) {
+  const int n = p->n_v;
+  lp.K = K;
+  lp.copy_src.assign((size_t)lp.K * n, -1);
+  lp.copy_val.assign((size_t)lp.K * n, 0.0);
+  for (int v = 0; v < n; ++v) {
+    int k = 1;
+    for (int e = p->rowptr[v]; e < p->rowptr[v + 1]; ++e) {
+      int u = p->col[e];
+      if (u == v) {
+        lp.copy_src[v] = v;
+        lp.copy_val[v] = p->val[e];
+      } else {
+        lp.copy_src[(size_t)k * n + v] = u;
+        lp.copy_val[(size_t)k * n + v] = p->val[e];
+        ++k;
+      }
+    }
+  }
+}
+
+// routing of a SpIntra-CA layer on blocks of B slots
+static void spintra_routing(const ficgcn_plan* p, LayerPlan& lp, int B, const ficgcn_plan_opts& o) {
+  const int n = p->n_v, M = p->M;
+  lp.B = B;
+  lp.t = M / B;
+  const bool wrap = lp.B == M;
+  std::set<int64_t> sh;
+  for (int v = 0; v < n; ++v)
+    for (int e = p->rowptr[v]; e < p->rowptr[v + 1]; ++e)
+      sh.insert(reduce_shift((int64_t)p->pi[p->col[e]] - p->pi[v], M, wrap));
+  lp.shifts.assign(sh.begin(), sh.end());
+  int c2;
+  bsgs_split(lp.shifts, lp.B, lp.G, c2);
+  int c1 = (int)lp.shifts.size() - (sh.count(0) ? 1 : 0);
+  lp.family = (o.family >= 1 && o.family <= 4) ? o.family : (c2 < c1 ? 2 : 1);
+  if (lp.family == 3) {
+    if (!(o.cpoo >= 0.0 && o.cpoo <= 1.0)) FICGCN_THROW(EPLAN_, "CPOO threshold must lie in [0, 1]");
+    lp.cpoo = o.cpoo;
+    build_radix2(p->pi, p->rowptr, p->col, p->val, M, lp.B, wrap && !o.aoo_off, o.cpoo, lp.r2);
+  }
+}
+
+static void schedule(ckks_ctx* c, ficgcn_plan* p);
+static void layout_operands(ficgcn_plan* p);
+static std::vector<int64_t> rotation_steps_of(const LayerPlan& lp);
+
+// node order over blocks of B slots (Alg. 1, or the identity)
+static void node_order(ficgcn_plan* p, int B, const ficgcn_plan_opts& o) {
+  const int n = p->n_v;
+  p->B_pi = B;
+  const int TH = o.TH > 0 ? o.TH : (n < 10000 ? 1024 : 4096);
+  if (o.use_noo) {
+    p->regions = regions_of(p, TH);
+    std::vector<int> sizes;
+    for (auto& r : p->regions) sizes.push_back((int)r.size());
+    auto slots = interleave(sizes, B);
+    place(p, p->regions, slots, B == p->M);
+  } else {
+    if (n > B) FICGCN_THROW(EPLAN_, "graph does not fit the column block");
+    p->pi.resize(n);
+    for (int v = 0; v < n; ++v) p->pi[v] = v;
+    p->regions = {std::vector<int>()};
+    for (int v = 0; v < n; ++v) p->regions[0].push_back(v);
+  }
+}
+
+static void finish_plan(ckks_ctx* c, ficgcn_plan* p, const double* const* weights) {
+  schedule(c, p);
+  layout_operands(p);
+  for (size_t li = 0; li < p->layers.size(); ++li) {
+    LayerPlan& lp = p->layers[li];
+    lp.w.assign(weights[li], weights[li] + (size_t)lp.f_in * lp.f_out);
+    lp.w_int.resize((size_t)lp.f_in * lp.f_out);
+    for (size_t i = 0; i < lp.w_int.size(); ++i) {
+      double x = weights[li][i] * lp.sW;
+      if (!(std::fabs(x) < 9.2e18)) FICGCN_THROW(ESCALE_, "weight times scale exceeds 63 bits");
+      lp.w_int[i] = (int64_t)std::nearbyint(x);
+    }
+  }
+  std::set<int64_t> steps;
+  const int M = p->M;
+  for (auto& lp : p->layers) {
+    for (int64_t s : lp.fold_steps) steps.insert(fmod_(s, M));
+    for (int64_t s : lp.comb_shifts) steps.insert(fmod_(s * lp.B, M));
+    if (lp.kind != 1) continue;
+    for (int64_t s : lp.pack_steps) steps.insert(fmod_(s, M));
+    for (int64_t s : rotation_steps_of(lp)) steps.insert(fmod_(s, M));
+  }
+  steps.erase(0);
+  p->rot_steps.assign(steps.begin(), steps.end());
+}
+
+// Inter-CA first layer in the case-1 layout at packing t1; every later layer SpIntra-CA on
+// the packed blocks with the block-rotation combination
+static void build_rep_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_layers,
+                           const double* const* weights, const ficgcn_plan_opts& o, int t1, int K) {
+  const int M = p->M;
+  const int Bc = rep_block(t1, (int)dims[1], p->n_v, M);
+  if (!Bc) FICGCN_THROW(EPLAN_, "the case-1 layout does not fit at t = " + std::to_string(t1));
+  node_order(p, Bc, o);
+  const double agg_c = o.agg_c > 0 ? o.agg_c : 1.0;
+  p->layers.clear();
+  LayerPlan l0;
+  l0.kind = 0;
+  l0.f_in = (int)dims[0];
+  l0.f_out = (int)dims[1];
+  l0.act = o.activation != 0;
+  inter_copies(p, l0, K);
+  l0.pack = 1;
+  l0.t = t1;
+  l0.B = Bc;
+  const int64_t S = (int64_t)next_pow2(l0.f_out) * Bc;
+  for (int i = 0; (1 << i) < t1; ++i) l0.fold_steps.push_back(((int64_t)1 << i) * S);
+  p->layers.push_back(l0);
+  for (uint32_t li = 1; li < n_layers; ++li) {
+    LayerPlan lp;
+    lp.kind = 1;
+    lp.f_in = (int)dims[li];
+    lp.f_out = (int)dims[li + 1];
+    lp.act = o.activation != 0;
+    if (lp.f_out > M / Bc) FICGCN_THROW(EPLAN_, "a later layer is wider than the packed blocks hold");
+    spintra_routing(p, lp, Bc, o);
+    lp.comb = 1;
+    for (int s = -(lp.f_out - 1); s < lp.f_in; ++s) lp.comb_shifts.push_back(s);
+    mode_costs(lp, K - 1, lp.t, p->n_v, agg_c);
+    p->layers.push_back(lp);
+  }
+  finish_plan(c, p, weights);
+}
+
 void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_layers, const double* const* weights,
                 const ficgcn_plan_opts& o) {
   const int n = p->n_v;
@@ -442,6 +684,29 @@ void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_la
   p->M = M;
   if (o.first_mode == 1 && n_layers > 1)
     FICGCN_THROW(EPLAN_, "a SpIntra-CA first layer is only supported for one-layer models");
+  int K_all = 0;
+  for (int v = 0; v < n; ++v) {
+    int off = 0;
+    for (int e = p->rowptr[v]; e < p->rowptr[v + 1]; ++e) off += p->col[e] != v;
+    K_all = std::max(K_all, off);
+  }
+  K_all += 1;
+  if (o.first_mode == 0 && o.first_pack != 0) {
+    std::vector<int> later(dims + 2, dims + n_layers + 1);
+    int t1 = o.first_pack;
+    if (t1 < 0) {
+      t1 = rule_packing((int)dims[0], K_all - 1, n, (int)dims[1], M, later);
+    } else {
+      const int Bc = (t1 & (t1 - 1)) ? 0 : rep_block(t1, (int)dims[1], n, M);
+      bool ok = Bc > 0;
+      for (int f : later) ok = ok && f <= M / std::max(Bc, 1);
+      if (!ok) FICGCN_THROW(EPLAN_, "the case-1 layout does not fit at t = " + std::to_string(t1));
+    }
+    if (t1 > 0) {
+      build_rep_plan(c, p, dims, n_layers, weights, o, t1, K_all);
+      return;
+    }
+  }
   std::vector<int> spin_f;
   bool chained = false;     // a SpIntra-CA layer feeds another layer: its outputs stay one column each
   for (uint32_t i = 0; i < n_layers; ++i)
@@ -462,21 +727,8 @@ void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_la
     t_pack = o.t;
   }
   const int B = M / t_pack;
-  p->B_pi = B;
-  const int TH = o.TH > 0 ? o.TH : (n < 10000 ? 1024 : 4096);
-  if (o.use_noo) {
-    p->regions = regions_of(p, TH);
-    std::vector<int> sizes;
-    for (auto& r : p->regions) sizes.push_back((int)r.size());
-    auto slots = interleave(sizes, B);
-    place(p, p->regions, slots, B == M);
-  } else {
-    if (n > B) FICGCN_THROW(EPLAN_, "graph does not fit the column block");
-    p->pi.resize(n);
-    for (int v = 0; v < n; ++v) p->pi[v] = v;
-    p->regions = {std::vector<int>()};
-    for (int v = 0; v < n; ++v) p->regions[0].push_back(v);
-  }
+  node_order(p, B, o);
+  const double agg_c = o.agg_c > 0 ? o.agg_c : 1.0;
   p->layers.clear();
   for (uint32_t li = 0; li < n_layers; ++li) {
     LayerPlan lp;
@@ -485,47 +737,10 @@ void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_la
     lp.act = o.activation != 0;
     lp.kind = (li == 0 && o.first_mode == 0) ? 0 : 1;
     if (lp.kind == 0) {
-      int K = 0;
-      for (int v = 0; v < n; ++v) {
-        int off = 0;
-        for (int e = p->rowptr[v]; e < p->rowptr[v + 1]; ++e) off += p->col[e] != v;
-        K = std::max(K, off);
-      }
-      lp.K = K + 1;
-      lp.copy_src.assign((size_t)lp.K * n, -1);
-      lp.copy_val.assign((size_t)lp.K * n, 0.0);
-      for (int v = 0; v < n; ++v) {
-        int k = 1;
-        for (int e = p->rowptr[v]; e < p->rowptr[v + 1]; ++e) {
-          int u = p->col[e];
-          if (u == v) {
-            lp.copy_src[v] = v;
-            lp.copy_val[v] = p->val[e];
-          } else {
-            lp.copy_src[(size_t)k * n + v] = u;
-            lp.copy_val[(size_t)k * n + v] = p->val[e];
-            ++k;
-          }
-        }
-      }
+      inter_copies(p, lp, K_all);
     } else {
-      lp.t = t_pack;
-      lp.B = M / lp.t;
-      const bool wrap = lp.B == M;
-      std::set<int64_t> sh;
-      for (int v = 0; v < n; ++v)
-        for (int e = p->rowptr[v]; e < p->rowptr[v + 1]; ++e)
-          sh.insert(reduce_shift((int64_t)p->pi[p->col[e]] - p->pi[v], M, wrap));
-      lp.shifts.assign(sh.begin(), sh.end());
-      int c2;
-      bsgs_split(lp.shifts, lp.B, lp.G, c2);
-      int c1 = (int)lp.shifts.size() - (sh.count(0) ? 1 : 0);
-      lp.family = (o.family >= 1 && o.family <= 4) ? o.family : (c2 < c1 ? 2 : 1);
-      if (lp.family == 3) {
-        if (!(o.cpoo >= 0.0 && o.cpoo <= 1.0)) FICGCN_THROW(EPLAN_, "CPOO threshold must lie in [0, 1]");
-        lp.cpoo = o.cpoo;
-        build_radix2(p->pi, p->rowptr, p->col, p->val, M, lp.B, wrap && !o.aoo_off, o.cpoo, lp.r2);
-      }
+      spintra_routing(p, lp, M / t_pack, o);
+      if (li > 0) mode_costs(lp, K_all - 1, 1, n, agg_c);
       std::set<int64_t> pk;
       for (int l = 0; l < lp.f_out; ++l)
         if (l % lp.t) pk.insert(-(int64_t)(l % lp.t) * lp.B);
@@ -533,25 +748,7 @@ void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_la
     }
     p->layers.push_back(lp);
   }
-  schedule(c, p);
-  layout_operands(p);
-  for (uint32_t li = 0; li < n_layers; ++li) {
-    LayerPlan& lp = p->layers[li];
-    lp.w_int.resize((size_t)lp.f_in * lp.f_out);
-    for (size_t i = 0; i < lp.w_int.size(); ++i) {
-      double x = weights[li][i] * lp.sW;
-      if (!(std::fabs(x) < 9.2e18)) FICGCN_THROW(ESCALE_, "weight times scale exceeds 63 bits");
-      lp.w_int[i] = (int64_t)std::nearbyint(x);
-    }
-  }
-  std::set<int64_t> steps;
-  for (auto& lp : p->layers) {
-    if (lp.kind != 1) continue;
-    for (int64_t s : lp.pack_steps) steps.insert(fmod_(s, M));
-    for (int64_t s : rotation_steps_of(lp)) steps.insert(fmod_(s, M));
-  }
-  steps.erase(0);
-  p->rot_steps.assign(steps.begin(), steps.end());
+  finish_plan(c, p, weights);
 }
 
 std::vector<int64_t> layer_rotation_steps(const LayerPlan& lp) { return rotation_steps_of(lp); }

@@ -53,6 +53,19 @@ struct LayerPlan {
   std::vector<int64_t> pack_steps; // sorted distinct, negative
   R2Program r2;                    // family 3
   double cpoo = 0;                 // family 3: CPOO threshold (0 = off)
+  // Inter-CA packing: 0 = one input column per ciphertext (weights as integer sums), 1 = the
+  // case-1 layout of Sec. 3.2 / App. B (t input columns per ciphertext, each repeated for the
+  // F' output columns in blocks of B slots; operands A_hat_k (x) W-slice, ceil(log2 t) folds)
+  int pack = 0;
+  std::vector<int64_t> fold_steps;
+  // SpIntra-CA combination: 0 = columns by integer weights then packed by rotations, 1 = input
+  // already packed in blocks of B, output block c = sum over s of Rot_{sB}(in) (.) cm_s
+  int comb = 0;
+  std::vector<int64_t> comb_shifts;
+  std::vector<double> w;           // [f_in][f_out] weights (case-1 operands, combination masks)
+  // Sec. 3.3.2's aggregation-mode formula (later layers): -1 not evaluated, 0 Inter-CA, 1 SpIntra-CA
+  int paper_mode = -1;
+  double mode_cost_inter = 0, mode_cost_spintra = 0;
   // schedule
   int level_in = 0, level_agg = 0, level_out = 0, n_rescale_comb = 0;
   double scale_in = 0, sP = 0, sW = 0, sM = 0, scale_agg = 0, scale_out = 0;
@@ -62,7 +75,8 @@ struct LayerPlan {
   // SpIntra-CA: n_packed * n_shifts masks at level_agg
   int op_level = 0;
   double op_scale = 0;
-  bool op_ext = false;             // operands on the key basis (level+1+alpha limbs): family 4 masks
+  std::vector<char> op_x;          // operand on the key basis (level+1+alpha limbs): family 4 masks,
+                                   // the nonzero-offset block-combination masks
   std::vector<int32_t> op_lv;      // level of each operand
   std::vector<size_t> op_off;      // word offset of each operand in ops_block
   size_t op_words = 0;
@@ -81,8 +95,9 @@ struct LayerPlan {
   // registered by ficgcn_plan_pack_inputs; read when the layer is called
   // without input ciphertexts)
   const uint64_t* packed_in = nullptr;
-  int n_packed() const { return kind == 0 ? f_out : (f_out + t - 1) / t; }
-  int n_in_cts() const { return kind == 0 ? K * f_in : f_in; }
+  int n_packed() const { return kind == 0 ? (pack ? 1 : f_out) : (f_out + t - 1) / t; }
+  int n_in_cts() const { return kind == 0 ? K * (pack ? (f_in + t - 1) / t : f_in) : (comb ? 1 : f_in); }
+  size_t n_agg_ops() const;        // aggregation masks (SpIntra-CA): the first operands of the layer
 };
 
 }  // namespace ficgcn
@@ -123,6 +138,8 @@ size_t plan_operand_count(const ficgcn_plan* p, int li);
 // level and encoding scale of operand i of layer li
 int plan_operand_level(const ficgcn_plan* p, int li, size_t i);
 double plan_operand_scale(const ficgcn_plan* p, int li, size_t i);
+// operand i held on the key basis (level+1+alpha limbs: Q_l residues, then the special primes')
+bool plan_operand_ext(const ficgcn_plan* p, int li, size_t i);
 void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const uint64_t* const* in, size_t n_in,
                uint64_t* const* out, size_t n_out, int mode);
 // frees the plan's device memory (operands and layer constants); the plan can be encoded again

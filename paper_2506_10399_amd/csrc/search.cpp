@@ -202,18 +202,35 @@ static double plan_bytes(const ficgcn_plan* p) {
   for (const LayerPlan& lp : p->layers) {
     const int l1 = lp.level_in + 1;
     int n_out_cts;
-    if (lp.kind == 0) {
+    if (lp.kind == 0 && lp.pack) {
+      // case-1 layout: every input ciphertext and its plaintext once, one output, its rescale,
+      // then one switch and one addition per fold rotation
+      const int n_in = lp.n_in_cts(), lo = lp.level_in - 1;
+      bytes += limb * l1 * (3.0 * n_in + 2.0) + rs(lp.level_in);
+      bytes += lp.fold_steps.size() * (ks_single(lo) + limb * 6.0 * (lo + 1));
+      n_out_cts = 1;
+    } else if (lp.kind == 0) {
       bytes += limb * l1 * (2.0 * lp.K * lp.f_in + lp.K + 2.0 * lp.f_out) + 8.0 * l1 * lp.f_in * lp.f_out;
       bytes += lp.f_out * (rs(lp.level_in) + rs(lp.level_in - 1));
       n_out_cts = lp.f_out;
     } else {
-      bytes += limb * l1 * 2.0 * (lp.f_in + lp.f_out);
-      for (int r = 0; r < lp.n_rescale_comb; ++r) bytes += lp.f_out * rs(lp.level_in - r);
       const int la = lp.level_agg;
       const int np = lp.n_packed();
-      for (int g = 0; g < np; ++g) {
-        const int cols = std::min(lp.f_out, (g + 1) * lp.t) - g * lp.t;
-        bytes += (cols - 1) * ks_single(la);
+      if (lp.comb) {
+        // block-rotation combination: one ModUp, per nonzero offset an inner product and its
+        // masked sum on the key basis, one ModDown, the zero offset's product; its rescales
+        const int lv = lp.level_in;
+        const double nz = (double)lp.comb_shifts.size() - 1.0;
+        bytes += modup(lv) + nz * (inner(lv) + limb * (3.0 * (lv + 1 + a) + 2.0 * (lv + 1))) + moddown(lv) +
+                 limb * 4.0 * (lv + 1 + a) + mask(lv);
+        for (int r = 0; r < lp.n_rescale_comb; ++r) bytes += rs(lv - r);
+      } else {
+        bytes += limb * l1 * 2.0 * (lp.f_in + lp.f_out);
+        for (int r = 0; r < lp.n_rescale_comb; ++r) bytes += lp.f_out * rs(lp.level_in - r);
+        for (int g = 0; g < np; ++g) {
+          const int cols = std::min(lp.f_out, (g + 1) * lp.t) - g * lp.t;
+          bytes += (cols - 1) * ks_single(la);
+        }
       }
       if (lp.family == 3) {
         // radix-2 program: every term one masked product at its step's level, every

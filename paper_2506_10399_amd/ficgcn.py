@@ -37,7 +37,8 @@ class CkksParams(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("first_mode", ctypes.c_int32), ("use_noo", ctypes.c_int32), ("family", ctypes.c_int32),
                 ("TH", ctypes.c_int32), ("activation", ctypes.c_int32), ("t", ctypes.c_int32),
-                ("aoo_off", ctypes.c_int32), ("cpoo", ctypes.c_double)]
+                ("aoo_off", ctypes.c_int32), ("cpoo", ctypes.c_double), ("first_pack", ctypes.c_int32),
+                ("agg_c", ctypes.c_double)]
 
 
 class SearchStats(ctypes.Structure):
@@ -405,7 +406,8 @@ class Plan:
 
     def __init__(self, ctx: Context, rowptr, col, val, n_v: int, dims: Sequence[int], weights,
                  first_mode: int = 0, use_noo: bool = True, family: int = 0, TH: int = 0, activation: bool = False,
-                 t: int = 0, cpoo: float = 0.0, aoo: bool = True, opts: "PlanOpts" = None):
+                 t: int = 0, cpoo: float = 0.0, aoo: bool = True, first_pack: int = 0, agg_c: float = 0.0,
+                 opts: "PlanOpts" = None):
         self.ctx = ctx
         self._rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
         self._col = np.ascontiguousarray(col, dtype=np.int32)
@@ -415,7 +417,8 @@ class Plan:
         wp = _ptr_array(self._w)
         if opts is None:
             opts = PlanOpts(first_mode=first_mode, use_noo=int(use_noo), family=family, TH=TH,
-                            activation=int(activation), t=t, aoo_off=int(not aoo), cpoo=cpoo)
+                            activation=int(activation), t=t, aoo_off=int(not aoo), cpoo=cpoo,
+                            first_pack=first_pack, agg_c=agg_c)
         self.opts = opts
         h = c_vp()
         _check(lib().ficgcn_plan_create(ctx.h, _ptr(self._rowptr), _ptr(self._col), _ptr(self._val), n_v,
@@ -457,15 +460,16 @@ class Plan:
     def ficgcn_plan_info(self) -> List[dict]:
         n = ctypes.c_uint32()
         _check(lib().ficgcn_plan_info(self.h, None, None, ctypes.byref(n)))
-        info = np.zeros(13 * n.value, dtype=np.int64)
-        sc = np.zeros(3 * n.value, dtype=np.float64)
+        info = np.zeros(18 * n.value, dtype=np.int64)
+        sc = np.zeros(5 * n.value, dtype=np.float64)
         _check(lib().ficgcn_plan_info(self.h, _ptr(info), _ptr(sc), ctypes.byref(n)))
         keys = ["kind", "f_in", "f_out", "K", "t", "B", "family", "G", "n_shifts", "level_in", "level_out",
-                "n_in_cts", "n_out_cts"]
+                "n_in_cts", "n_out_cts", "pack", "comb", "n_fold", "n_comb_shifts", "paper_mode"]
         out = []
         for li in range(n.value):
-            d = {k: int(info[13 * li + i]) for i, k in enumerate(keys)}
-            d.update(scale_in=float(sc[3 * li]), scale_out=float(sc[3 * li + 1]), sW=float(sc[3 * li + 2]))
+            d = {k: int(info[18 * li + i]) for i, k in enumerate(keys)}
+            d.update(scale_in=float(sc[5 * li]), scale_out=float(sc[5 * li + 1]), sW=float(sc[5 * li + 2]),
+                     mode_cost_inter=float(sc[5 * li + 3]), mode_cost_spintra=float(sc[5 * li + 4]))
             out.append(d)
         return out
 

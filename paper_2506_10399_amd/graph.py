@@ -4,7 +4,8 @@ normalize  : the GCN's normalised adjacency A_hat (paper Sec. 2.2) as CSR with
              the diagonal: "sym" D^-1/2 (A + I) D^-1/2 (entry 1/sqrt(d_v d_u),
              d = degree + 1) or "mean" (GraphSage MEAN over the sampled
              neighbours and the node: 1 / (|S(v)| + 1)).
-client_slots: the slot vectors the client encrypts for the first layer.
+client_slots: the slot vectors the client encrypts for the first layer
+             (client_slots_rep: the same in the case-1 layout of Sec. 3.2).
 read_output : the n_v x F' output from decrypted slot vectors.
 """
 from __future__ import annotations
@@ -49,6 +50,29 @@ def client_slots(pi: np.ndarray, x: np.ndarray, M: int, copy_src: np.ndarray = N
     for k in range(K):
         have = copy_src[k] >= 0
         out[k * F:(k + 1) * F][:, pi[have]] = x[copy_src[k][have]].T
+    return out
+
+
+def client_slots_rep(pi: np.ndarray, x: np.ndarray, M: int, copy_src: np.ndarray, t: int, B: int,
+                     f_out: int) -> np.ndarray:
+    """The case-1 layout of an Inter-CA first layer (paper Sec. 3.2, App. B): row k*J + j
+    (J = ceil(F / t)) holds input columns j t + b (b < t) of copy k, column b repeated for
+    every output column l < F' in the block starting at (b pow2(F') + l) B, node v at
+    offset pi(v)."""
+    n, F = x.shape
+    K = copy_src.shape[0]
+    J = -(-F // t)
+    Fp = 1
+    while Fp < f_out:
+        Fp *= 2
+    out = np.zeros((K * J, M))
+    for k in range(K):
+        have = copy_src[k] >= 0
+        xs = x[copy_src[k][have]]
+        for j in range(J):
+            for b in range(min(t, F - j * t)):
+                for l in range(f_out):
+                    out[k * J + j, (b * Fp + l) * B + pi[have]] = xs[:, j * t + b]
     return out
 
 

@@ -9,7 +9,7 @@ import re
 import numpy as np
 import pytest
 
-from oracle import gcn, planner, execute as ex
+from oracle import gcn, planner, execute as ex, simulate as sim
 from oracle.params import Params
 from workload import make_workload
 
@@ -282,3 +282,71 @@ def test_top_digit_of_rearranged_inputs_fits_a_nibble():
         assert sum(v * 256 ** a for a, v in enumerate(d)) == x
         tops.append(d[6])
     assert min(tops) >= 0 and max(tops) <= 8
+
+
+@pytest.mark.parametrize("name,kw,first_pack,noo,family", [
+    ("tiny", {}, "rule", True, None), ("tiny", {"n_nodes": 64}, 4, False, None), ("tiny", {}, 1, True, None),
+    ("tiny2", {"n_nodes": 100}, "rule", True, None), ("tiny2", {"n_nodes": 100}, 1, False, 2),
+    ("tiny2", {"n_nodes": 100}, 2, True, 4), ("ntu_small", {}, "rule", True, None)])
+def test_case1_plan_matches_oracle(fg, name, kw, first_pack, noo, family):
+    """The library's planner on the case-1 layout (Sec. 3.2, App. B) and the block-rotation
+    combination equals the oracle's: node order, packing, schedule, every operand's slot
+    vector, level, scale and basis, the rotation keys, and the mode formula per layer."""
+    from paper_2506_10399_amd import graph
+    w = make_workload(name, **kw)
+    prm = Params.from_dict(w.params)
+    rows = gcn.normalized_rows(w.graph.n, w.neighbors, w.norm)
+    o = planner.build_plan(w.graph.n, rows, w.meta["dims"], w.activation, prm.M, use_noo=noo, family=family,
+                           first_pack=first_pack)
+    rp, col, val = graph.normalize(w.graph.n, w.neighbors, w.norm)
+    ctx = fg.Context.from_dict(w.params)
+    fp = -1 if first_pack == "rule" else first_pack
+    p = fg.Plan(ctx, rp, col, val, w.graph.n, w.meta["dims"], w.weights, use_noo=noo, family=family or 0,
+                activation=w.activation, first_pack=fp)
+    assert np.array_equal(p.ficgcn_plan_node_order(), o.pi.astype(np.int32))
+    info = p.ficgcn_plan_info()
+    sched = ex.schedule(prm, o)
+    assert o.layers[0].pack == "rep" and info[0]["pack"] == 1
+    for li, (lp, d, st) in enumerate(zip(o.layers, info, sched)):
+        assert (d["t"], d["B"]) == (lp.t, lp.B)
+        assert d["level_in"] == st["level_in"] and d["level_out"] == st["level_out"]
+        assert d["scale_in"] == st["scale_in"] and d["scale_out"] == st["scale_out"] and d["sW"] == st["sW"]
+        assert d["n_fold"] == len(lp.fold_steps) and d["n_comb_shifts"] == len(lp.comb_shifts)
+        if li == 0:
+            want = sim.rep_plaintexts(o, lp, w.weights[0])
+            levels = [(st["level_in"], st["sP"])] * len(want)
+        else:
+            assert d["comb"] == 1 and d["family"] == lp.family and d["G"] == lp.G
+            assert p.ficgcn_plan_shifts(li) == list(lp.shifts)
+            assert d["paper_mode"] == (0 if lp.paper_mode == "inter" else 1)
+            assert d["mode_cost_inter"] == lp.paper_mode_costs[0]
+            assert d["mode_cost_spintra"] == lp.paper_mode_costs[1]
+            mv = ex.mask_vectors(o, li)
+            cm = sim.diag_masks(o, lp, w.weights[li])
+            agg = [mv[g][s] for g in range(len(mv)) for s in lp.shifts]
+            want = agg + [cm[s] for s in lp.comb_shifts]
+            levels = [(st["level_agg"], st["sM"])] * len(agg) + [(st["level_in"], st["sW"])] * len(cm)
+        assert p.ficgcn_plan_operand_count(li) == len(want)
+        for i in range(0, len(want), max(1, len(want) // 23)):
+            assert np.array_equal(p.ficgcn_plan_operand_slots(li, i), want[i]), (li, i)
+            assert p.ficgcn_plan_operand_level(li, i) == levels[i]
+    assert p.ficgcn_plan_rot_steps() == o.rot_steps(prm.M)
+
+
+def test_case1_rule_and_rejections(fg):
+    w = make_workload("tiny")
+    from paper_2506_10399_amd import graph
+    rp, col, val = graph.normalize(w.graph.n, w.neighbors, w.norm)
+    ctx = fg.Context.from_dict(w.params)
+    p = fg.Plan(ctx, rp, col, val, w.graph.n, w.meta["dims"], w.weights, first_pack=-1)
+    d = p.ficgcn_plan_info()[0]
+    assert (d["pack"], d["t"], d["B"], d["n_in_cts"], d["n_out_cts"]) == (1, 2, 128, d["K"] * 16, 1)
+    with pytest.raises(fg.FicgcnError) as e:      # t = 4 does not fit 128 nodes at F' = 16, M = 4096
+        fg.Plan(ctx, rp, col, val, w.graph.n, w.meta["dims"], w.weights, first_pack=4)
+    assert e.value.status == -7
+    # the citation-graph shape is case 2: the rule keeps one column per ciphertext
+    wc = make_workload("cora", dims=[24, 16, 7])
+    rp, col, val = graph.normalize(wc.graph.n, wc.neighbors, wc.norm)
+    ctx2 = fg.Context.from_dict(wc.params)
+    p2 = fg.Plan(ctx2, rp, col, val, wc.graph.n, [24, 16, 7], wc.weights, activation=True, first_pack=-1)
+    assert p2.ficgcn_plan_info()[0]["pack"] == 0
