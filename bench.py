@@ -183,123 +183,102 @@ def cpu_baseline(params, plan_info, op_counts, all_core=None, sample_features=12
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="cora")
-    ap.add_argument("--features", type=int, default=None, help="shrink F (quick runs only)")
-    ap.add_argument("--skip-plain", action="store_true")
-    ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--skip-ks", action="store_true")
-    ap.add_argument("--rule-plan", action="store_true", help="batched form on the paper-rule plan (no learned search)")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a plain 1 GiB device copy (scale reference for HBM counters)")
-    ap.add_argument("--serving", action="store_true",
-                    help="instead: a Poisson stream of encrypted GCN requests through the server (rate sweep)")
-    ap.add_argument("--requests", type=int, default=10)
-    ap.add_argument("--keyswitch", action="store_true",
-                    help="instead: key switching alone at the citation-graph parameters (hoisted rotations of one "
-                         "ciphertext, rotations of distinct ciphertexts, relinearisations)")
-    ap.add_argument("--ntu", action="store_true",
-                    help="instead: the 3-layer x^2 GCN (3-64-128-128) on the multi-frame skeleton shape "
-                         "(25 joints x 256 frames, N=2^14)")
-    ap.add_argument("--radix2", action="store_true",
-                    help="instead: the paper's radix-2 SpIntra-CA (per-round masks, CPOO, AOO): rotation/level "
-                         "ablation on synthetic graphs and the second layer of the citation-graph shape on a deep "
-                         "prime chain, timed against the baby-step/giant-step form")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU path "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
-    if args.serving:
-        serving_bench(args)
-        return
-    if args.radix2:
-        radix2_bench(args)
-        return
-    if args.ntu:
-        ntu_bench(args)
-        return
-    if args.keyswitch:
-        keyswitch_bench(args)
-        return
+def train_cost_model():
+    """The learned cost model: SpIntra-CA layer latencies of small synthetic graphs
+    measured here (the library's own kernels), fitted by the library's MLP kernels."""
+    from paper_2506_10399_amd import ficgcn as fg, costmodel as cm
+    t0 = time.perf_counter()
+    base = fg.PlanOpts(0, 1, 0, 0, 1, 0)
+    ctx_m = fg.Context.from_dict(dict(log_n=13, n_q=8, q_bits=50, n_p=2, p_bits=60, log_scale=40))
+    Xs, ys = [], []
+    for c in cm.synthetic_cases(8, 100, n_range=(128, 1400)):
+        _, F, ms = cm.measure_case(ctx_m, c, base)
+        Xs.append(F)
+        ys.append(ms)
+    net, losses = cm.train(ctx_m, np.concatenate(Xs), np.concatenate(ys), epochs=300)
+    return net, dict(samples=int(sum(len(x) for x in Xs)), train_loss=[round(losses[0], 4), round(losses[-1], 5)],
+                     measure_and_train_s=round(time.perf_counter() - t0, 1))
 
+
+def ctypes_copy(dst, src):
+    for f, _ in src._fields_:
+        setattr(dst, f, getattr(src, f))
+
+
+def run_config(name, args, net, all_core=None, with_plain=True, with_ks=True, with_rearranged=False,
+               with_cpu=True, with_top=False):
+    """One configuration end to end: plans (paper rule; learned search when a model is
+    given), keys, the client's ciphertexts encrypted on the GPU and resident, then
+    batched inferences from the ciphertext words (HIP-graph replay, then eager with
+    kernel events), the plain per-operation form of the paper-rule plan, key-switch
+    rates at the configuration's parameters, the CPU oracle sample."""
     import torch
-    from paper_2506_10399_amd import ficgcn as fg, graph, costmodel as cm
+    from paper_2506_10399_amd import ficgcn as fg, graph
     from workload import make_workload
 
     t_setup = time.perf_counter()
     kw = {}
-    if args.features:
+    if args.features and name == args.config:
         from workload.configs import CONFIGS
-        d = list(CONFIGS[args.config]["dims"])
+        d = list(CONFIGS[name]["dims"])
         d[0] = args.features
         kw["dims"] = d
-    w = make_workload(args.config, **kw)
+    w = make_workload(name, **kw)
     dims = w.meta["dims"]
     rp, col, val = graph.normalize(w.graph.n, w.neighbors, w.norm)
     ctx = fg.Context.from_dict(w.params)
-    all_core = None
-    if not args.skip_cpu:
-        # the oracle's all-core sample first, in fresh processes, while this
-        # process has not touched the GPU (plans are built on the host)
-        workers = max(1, min(16, os.cpu_count() or 1))
-        info0 = fg.Plan(ctx, rp, col, val, w.graph.n, dims, w.weights, activation=w.activation).ficgcn_plan_info()
-        log("cpu baseline, all cores (%d processes)..." % workers)
-        all_core = oracle_sample_all_cores(w.params, *sample_levels(info0), workers)
-    torch.cuda.set_device(0)
     prm = w.params
     N = 1 << prm["log_n"]
     M = N // 2
     L = prm["n_q"]
     ntt_cols = ctx.ckks_ntt_autotune(L + prm["n_p"])
-    log("NTT autotune (column width, row width, column-pass log size): %s" % (ntt_cols,))
-
-    # plan choice: the paper's rule, and the learned search (cost model trained
-    # on SpIntra-CA layer latencies measured here on small synthetic graphs)
+    log("[%s] NTT autotune (column width, row width, column-pass log size): %s" % (name, ntt_cols,))
     base = fg.PlanOpts(0, 1, 0, 0, int(w.activation), 0)
-    rule_plan = fg.Plan(ctx, rp, col, val, w.graph.n, dims, w.weights, activation=w.activation)
-    learned = None
-    plan = rule_plan
-    if not args.rule_plan:
-        t0 = time.perf_counter()
-        ctx_m = fg.Context.from_dict(dict(log_n=13, n_q=8, q_bits=50, n_p=2, p_bits=60, log_scale=40))
-        Xs, ys = [], []
-        for c in cm.synthetic_cases(8, 100, n_range=(128, 1400)):
-            _, F, ms = cm.measure_case(ctx_m, c, base)
-            Xs.append(F)
-            ys.append(ms)
-        net, losses = cm.train(ctx_m, np.concatenate(Xs), np.concatenate(ys), epochs=300)
-        t_train = time.perf_counter() - t0
+    base.low_level = 1
+    # the paper's rule: packing by J(t) / case 2, NOO with the default cap, the cheaper routing;
+    # both plans take the client's ciphertexts at the lowest level their layers need
+    rule_plan = fg.Plan(ctx, rp, col, val, w.graph.n, dims, w.weights, activation=w.activation, first_pack=-1,
+                        low_level=True)
+    plan, learned = rule_plan, None
+    if net is not None:
         best_l, st_l = fg.ficgcn_plan_search(ctx, rp, col, val, w.graph.n, dims, w.weights, base, model=net, keep=4)
         best_x, st_x = fg.ficgcn_plan_search(ctx, rp, col, val, w.graph.n, dims, w.weights, base)
         plan = fg.Plan(ctx, rp, col, val, w.graph.n, dims, w.weights, opts=best_l)
-        learned = dict(samples=int(sum(len(x) for x in Xs)), train_loss=[round(losses[0], 4), round(losses[-1], 5)],
-                       measure_and_train_s=round(t_train, 1),
-                       chosen=dict(t=best_l.t, use_noo=best_l.use_noo, TH=best_l.TH, family=best_l.family),
+        learned = dict(chosen=dict(t=best_l.t, use_noo=best_l.use_noo, TH=best_l.TH, family=best_l.family),
                        built=[st_l.n_built, st_x.n_built], search_s=[round(st_l.build_seconds, 3),
                                                                     round(st_x.build_seconds, 3)],
                        judge_bytes=dict(learned=st_l.best_cost, exhaustive=st_x.best_cost,
                                         paper_rule=rule_plan.ficgcn_plan_cost()),
                        within_5pct=bool(st_l.best_cost <= 1.05 * st_x.best_cost))
-        log("learned plan search: %s" % learned)
+        log("[%s] learned plan search: %s" % (name, learned))
     info = plan.ficgcn_plan_info()
     steps_needed = sorted(set(plan.ficgcn_plan_rot_steps()) | set(rule_plan.ficgcn_plan_rot_steps()))
-    log("plan: %s ; %d rotation keys" % (info, len(steps_needed)))
+    log("[%s] plan: %s ; %d rotation keys" % (name, info, len(steps_needed)))
     cl, ev = ctx.ckks_keygen(7, steps_needed, with_relin=True)
     K, F = info[0]["K"], info[0]["f_in"]
-    lv0 = L - 1
-    n_in = K * F
+    lv0 = info[0]["level_in"]
+    if rule_plan.ficgcn_plan_info()[0]["level_in"] != lv0:
+        raise RuntimeError("the paper-rule and learned plans start at different levels")
+    n_in = info[0]["n_in_cts"]
     inputs = torch.empty((n_in, 2, lv0 + 1, N), dtype=torch.int64, device="cuda")
     in_list = [inputs[i] for i in range(n_in)]
 
-    def encrypt_for(p):
-        """The client's ciphertexts for plan p: copy k of column f in p's slot order."""
+    def encrypt_for(p, dst=None):
+        """The client's ciphertexts for plan p (its node order, copies and packing), at the
+        plan's first level, into dst (default: the resident input block)."""
+        dst = inputs if dst is None else dst
+        d0 = p.ficgcn_plan_info()[0]
+        lv0 = d0["level_in"]
         pi = p.ficgcn_plan_node_order()
         src = p.ficgcn_plan_copy_sources(0)
+        if d0["pack"]:
+            rows = graph.client_slots_rep(pi, w.x, M, src, d0["t"], d0["B"], d0["f_out"])
+            for i0 in range(0, rows.shape[0], 256):
+                pts = ctx.ckks_encode_batch(rows[i0:i0 + 256], 2.0 ** prm["log_scale"], lv0)
+                for i in range(pts.shape[0]):
+                    ctx.ckks_encrypt(cl, pts[i], lv0, 1234, i0 + i, out=dst[i0 + i])
+            ctx.ckks_sync()
+            return
         CH = 256
         for k in range(K):
             have = src[k] >= 0
@@ -309,37 +288,31 @@ def main():
                 rows[:, pi[have]] = w.x[src[k][have], f0:f0 + nf].T
                 pts = ctx.ckks_encode_batch(rows, 2.0 ** prm["log_scale"], lv0)
                 for i in range(nf):
-                    ctx.ckks_encrypt(cl, pts[i], lv0, 1234, k * F + f0 + i, out=inputs[k * F + f0 + i])
+                    ctx.ckks_encrypt(cl, pts[i], lv0, 1234, k * F + f0 + i, out=dst[k * F + f0 + i])
         ctx.ckks_sync()
-        return pi
 
-    log("encrypting %d client ciphertexts (%.1f GiB)" % (n_in, inputs.numel() * 8 / 2 ** 30))
+    log("[%s] encrypting %d client ciphertexts (%.1f GiB)" % (name, n_in, inputs.numel() * 8 / 2 ** 30))
     plan.ficgcn_plan_encode()
-    pi = encrypt_for(plan)
+    encrypt_for(plan)
     outs = [[ctx.ct_buffer(d["level_in"]) for _ in range(d["n_out_cts"])] for d in info]
-    log("setup %.1f s" % (time.perf_counter() - t_setup))
+    setup_s = time.perf_counter() - t_setup
+    log("[%s] setup %.1f s" % (name, setup_s))
 
-    if args.calibrate_copy:
-        a = torch.ones(1 << 27, dtype=torch.int64, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-
-    def step(p, mode, outs_):
-        cur = in_list
+    def step(p, mode, outs_, ins=None):
+        cur = in_list if ins is None else ins
         for li in range(len(outs_)):
             p.ficgcn_gcn_layer(ev, li, cur, outs_[li], mode=mode)
             cur = outs_[li]
 
+    ref = fp64_gcn(rp, col, val, w.x, w.weights)
+
     def decrypt_err(p, outs_):
         d = p.ficgcn_plan_info()[-1]
         slots = [np.real(ctx.ckks_decrypt(cl, x, d["level_out"], d["scale_out"], M)) for x in outs_[-1]]
-        y = graph.read_output(p.ficgcn_plan_node_order(), slots, d["f_out"], d["t"], d["B"], d["kind"] == 1)
+        t = M // d["B"] if d["kind"] == 1 or d["pack"] else d["t"]
+        y = graph.read_output(p.ficgcn_plan_node_order(), slots, d["f_out"], t, d["B"],
+                              d["kind"] == 1 or d["pack"] == 1)
         return float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
-
-    ref = fp64_gcn(rp, col, val, w.x, w.weights)
 
     def timed(step_fn):
         """Graph-replayed steps (the first graph-mode call per layer records and
@@ -369,39 +342,47 @@ def main():
         return ms, ms_e, pr
 
     last = info[-1]
-    # 1. the layers on the client's ciphertext words
-    ms_ct, ms_eager_ct, _ = timed(lambda mode: step(plan, mode, outs))
-    log("batched, graph replay, from ciphertext words: %.2f ms per inference (eager %.2f)" % (ms_ct, ms_eager_ct))
+    # the layers on the client's ciphertext words: every inference starts from fresh inputs
+    ms_step, ms_eager, prof = timed(lambda mode: step(plan, mode, outs))
+    log("[%s] batched, graph replay, from ciphertext words: %.2f ms per inference (eager %.2f); kernel event "
+        "totals %s" % (name, ms_step, ms_eager, prof))
     batched_words = [ctx.ckks_poly_store(x, last["level_out"], 2) for x in outs[-1]]
-    # 2. the layer-1 inputs held as the matrix-core pass's operands (rearranged
-    #    once, on arrival, like the upload itself; not part of an inference)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    packed = plan.ficgcn_plan_pack_inputs(0, in_list)
-    torch.cuda.synchronize()
-    pack_ms = (time.perf_counter() - t0) * 1e3
-    packed_bytes = packed.numel() * 8
-
-    def step_packed(mode):
-        cur = None
-        for li in range(len(outs)):
-            plan.ficgcn_gcn_layer(ev, li, cur, outs[li], mode=mode)
-            cur = outs[li]
-
-    ms_step, ms_eager, prof = timed(step_packed)
-    log("batched, graph replay: %.2f ms per inference (layer-1 inputs as matrix operands, %.1f GB, rearranged "
-        "once in %.0f ms)" % (ms_step, packed_bytes / 1e9, pack_ms))
-    log("batched, eager with events: %.2f ms per inference; kernel event totals %s" % (ms_eager, prof))
-    packed_words = [ctx.ckks_poly_store(x, last["level_out"], 2) for x in outs[-1]]
-    packed_same = all(np.array_equal(a, b) for a, b in zip(packed_words, batched_words))
-    log("words equal to the run on ciphertext words: %s" % packed_same)
     err = decrypt_err(plan, outs)
-    log("max rel err vs FP64 GCN: %.3e" % err)
+    log("[%s] max rel err vs FP64 GCN: %.3e" % (name, err))
+    res = dict(workload="%s-shape %d-layer x^2 GCN: %d nodes, %s, K=%d copies, CKKS N=2^%d, %d+%d primes, "
+                        "%d input cts resident at level %d" % (name, len(dims) - 1, w.graph.n, "-".join(map(str, dims)),
+                                                               K, prm["log_n"], L, prm["n_p"], n_in, lv0),
+               input_level=lv0,
+               ms=round(ms_step, 3), batched_eager_ms=round(ms_eager, 3), max_rel_err=err,
+               learned_planner=learned, setup_s=round(setup_s, 1),
+               ntt_schedule=dict(cols_column=ntt_cols[0], cols_row=ntt_cols[1], log_column_pass=ntt_cols[2]),
+               kernel_ms_per_step={k: round(v[0] / args.steps, 3) for k, v in prof.items()},
+               plan=[{k: d[k] for k in ("kind", "f_in", "f_out", "K", "t", "B", "family", "G", "n_shifts",
+                                         "n_in_cts", "n_out_cts", "pack", "comb", "paper_mode")} for d in info])
+    if with_rearranged:
+        # the layer-1 inputs rearranged once as the matrix-core pass's operands: a second
+        # figure that assumes inputs kept in that form (the rearrangement is timed beside it)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        packed = plan.ficgcn_plan_pack_inputs(0, in_list)
+        torch.cuda.synchronize()
+        pack_ms = (time.perf_counter() - t0) * 1e3
 
-    plain_ms = plain_same_ms = None
-    same = None
-    err_plain = None
-    if not args.skip_plain:
+        def step_packed(mode):
+            cur = None
+            for li in range(len(outs)):
+                plan.ficgcn_gcn_layer(ev, li, cur, outs[li], mode=mode)
+                cur = outs[li]
+
+        ms_p, _, _ = timed(step_packed)
+        same_p = all(np.array_equal(a, ctx.ckks_poly_store(x, last["level_out"], 2))
+                     for a, x in zip(batched_words, outs[-1]))
+        res.update(rearranged_inputs_ms=round(ms_p, 3), rearrange_inputs_ms=round(pack_ms, 1),
+                   rearranged_equals_ciphertext_words=same_p)
+        log("[%s] over inputs rearranged once (%.0f ms): %.2f ms per inference, words equal %s"
+            % (name, pack_ms, ms_p, same_p))
+        del packed
+    if with_plain:
         # the same plan op by op: identical words
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -410,7 +391,7 @@ def main():
         plain_same_ms = (time.perf_counter() - t0) * 1e3
         plain_words = [ctx.ckks_poly_store(x, last["level_out"], 2) for x in outs[-1]]
         same = all(np.array_equal(a, b) for a, b in zip(plain_words, batched_words))
-        log("plain, same plan: %.2f ms, words equal to batched: %s" % (plain_same_ms, same))
+        log("[%s] plain, same plan: %.2f ms, words equal to batched: %s" % (name, plain_same_ms, same))
         if plan is rule_plan:
             plain_ms, err_plain = plain_same_ms, err
         else:
@@ -425,15 +406,39 @@ def main():
             torch.cuda.synchronize()
             plain_ms = (time.perf_counter() - t0) * 1e3
             err_plain = decrypt_err(rule_plan, outs_r)
-        log("plain, paper-rule plan: %.2f ms, max rel err %.3e" % (plain_ms, err_plain))
-
-    ks = {}
-    if not args.skip_ks:
+            del outs_r
+        log("[%s] plain, paper-rule plan: %.2f ms, max rel err %.3e" % (name, plain_ms, err_plain))
+        res.update(plain_ms=round(plain_ms, 3), speedup_vs_plain=round(plain_ms / ms_step, 3),
+                   plain_same_plan_ms=round(plain_same_ms, 3), plain_equals_batched=same,
+                   max_rel_err_plain=err_plain)
+    if with_top:
+        # the same plan with the client's ciphertexts at the top of the chain (every prime used)
+        opts_top = fg.PlanOpts()
+        ctypes_copy(opts_top, plan.opts)
+        opts_top.low_level = 0
+        ptop = fg.Plan(ctx, rp, col, val, w.graph.n, dims, w.weights, opts=opts_top)
+        itop = ptop.ficgcn_plan_info()
+        ptop.ficgcn_plan_encode()
+        lvt = itop[0]["level_in"]
+        in_top = torch.empty((n_in, 2, lvt + 1, N), dtype=torch.int64, device="cuda")
+        encrypt_for(ptop, in_top)
+        outs_t = [[ctx.ct_buffer(d["level_in"]) for _ in range(d["n_out_cts"])] for d in itop]
+        tl = [in_top[i] for i in range(n_in)]
+        ms_top, _, _ = timed(lambda mode: step(ptop, mode, outs_t, tl))
+        err_top = decrypt_err(ptop, outs_t)
+        log("[%s] the same plan from the top level (%d): %.2f ms per inference, err %.2e" % (name, lvt, ms_top,
+                                                                                           err_top))
+        res.update(top_level_ms=round(ms_top, 3), top_level=lvt, top_level_max_rel_err=err_top)
+        del in_top, tl, outs_t, ptop
+    if with_ks:
+        ks = {}
         nrot = 16
         rsteps = [s for s in steps_needed[:nrot]]
-        for lv in (lv0, info[1]["level_in"] - 2):
-            x = ctx.ct_buffer(lv)
-            x.copy_(inputs[0][:, : lv + 1, :])
+        lv_agg = info[1]["level_in"] - 2 if len(info) > 1 else lv0 - 1
+        rng_ks = np.random.default_rng(9)
+        for lv in (L - 1, lv_agg):
+            zs = ctx.ckks_encode_batch(rng_ks.uniform(-1, 1, (17, M)), 2.0 ** prm["log_scale"], lv)
+            x = ctx.ckks_encrypt(cl, zs[0], lv, 3, 0)
             outs_ks = [ctx.ct_buffer(lv) for _ in rsteps]
             ctx.ckks_rotate_hoisted(ev, x, lv, rsteps, outs_ks)
             torch.cuda.synchronize()
@@ -445,14 +450,11 @@ def main():
             hoisted = reps * len(rsteps) / (time.perf_counter() - t0)
             t0 = time.perf_counter()
             for _ in range(reps):
-                for s, o in zip(rsteps, outs_ks):
-                    ctx.ckks_rotate_hoisted(ev, x, lv, [s], [o])
+                for s_, o in zip(rsteps, outs_ks):
+                    ctx.ckks_rotate_hoisted(ev, x, lv, [s_], [o])
             torch.cuda.synchronize()
             single = reps * len(rsteps) / (time.perf_counter() - t0)
-            # batch of distinct ciphertexts (no shared ModUp), one call
-            xs = [ctx.ct_buffer(lv) for _ in rsteps]
-            for i, xi in enumerate(xs):
-                xi.copy_(inputs[i + 1][:, : lv + 1, :])
+            xs = [ctx.ckks_encrypt(cl, zs[i + 1], lv, 3, i + 1) for i in range(len(rsteps))]
             ctx.ckks_rotate_batch(ev, xs, lv, rsteps, outs_ks)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -462,54 +464,153 @@ def main():
             batch = reps * len(rsteps) / (time.perf_counter() - t0)
             ks["level_%d" % lv] = dict(hoisted_per_s=round(hoisted, 1), batch_per_s=round(batch, 1),
                                        single_per_s=round(single, 1), n=len(rsteps))
-        log("key-switch/s: %s" % ks)
-
-    # roofline of the dominant kernel: the fused Inter-CA + combination pass on the
-    # rearranged inputs (6.5 bytes per residue), K plaintexts, F' outputs, weight planes
-    F_out = info[0]["f_out"]
-    l1 = lv0 + 1
-    alg_bytes = packed_bytes + 8.0 * N * l1 * (K + 2 * F_out) + 8.0 * l1 * F * F_out
-    ms_k, n_k = prof["inter_fused"]
-    per_step_ms = ms_k / args.steps       # one fused pass (F' <= 16 outputs per launch) per inference
-    achieved = alg_bytes / (per_step_ms * 1e-3) / 1e9
-    roofline = dict(kernel="k_fused_mfma_packed (Inter-CA aggregation + combination on int8 matrix cores, inputs "
-                           "held as the matrix operands)", bound="hbm",
-                    achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(),
-                    alg_bytes_per_launch=alg_bytes, avg_launch_ms=per_step_ms, launches=n_k,
-                    share_of_step=round(ms_k / args.steps / ms_eager, 3))
-
-    cpu = None
-    if not args.skip_cpu:
+        log("[%s] key-switch/s: %s" % (name, ks))
+        res["keyswitch"] = ks
+    if with_cpu:
         counts = dict(rot=plan_rot_count(plan, info),
                       mask_pmult=info[1]["n_shifts"] * info[1]["n_out_cts"],
                       cmult=info[0]["n_out_cts"] + info[1]["n_out_cts"],
                       rescale=2 * info[0]["n_out_cts"] + 2 * info[1]["f_out"] + info[1]["n_out_cts"])
-        log("cpu baseline (oracle sample)...")
-        cpu = cpu_baseline(prm, info, counts, all_core)
-        log("cpu baseline: %.0f ms extrapolated (all cores: %s)" % (cpu["value"], cpu.get("all_cores", {}).get("value")))
+        log("[%s] cpu baseline (oracle sample)..." % name)
+        res["cpu_baseline"] = cpu_baseline(prm, info, counts, all_core)
+        log("[%s] cpu baseline: %.0f ms extrapolated (all cores: %s)"
+            % (name, res["cpu_baseline"]["value"], res["cpu_baseline"].get("all_cores", {}).get("value")))
+    res["_prof"] = prof
+    res["_info"] = info
+    res["_prm"] = prm
+    del inputs, in_list, outs
+    return res
 
-    out = dict(metric=METRIC, value=round(ms_step, 3), unit="ms", n_gpus=1, steps=args.steps, warmup=args.warmup,
-               ms_per_step=round(ms_step, 3), higher_is_better=False, scaling="weak", vs_baseline=None,
+
+def headline_roofline(args, prof, info, prm):
+    """Roofline of the fused Inter-CA + combination pass over the client's ciphertext
+    words: algorithmic bytes per launch (2 K F input limb-polynomials, K plaintexts,
+    2 F' outputs at the layer's l1 limbs, the integer weights) over its mean launch time
+    from HIP events on the context's stream."""
+    N = 1 << prm["log_n"]
+    d0 = info[0]
+    K, F, F_out, l1 = d0["K"], d0["f_in"], d0["f_out"], d0["level_in"] + 1
+    alg_bytes = 8.0 * N * l1 * (2 * K * F + K + 2 * F_out) + 8.0 * l1 * F * F_out
+    ms_k, n_k = prof["inter_fused"]
+    per_launch_ms = ms_k / max(1, n_k)
+    achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
+    return dict(kernel="k_fused_mfma (Inter-CA aggregation + combination on int8 matrix cores over the client's "
+                       "ciphertext words)", bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, alg_bytes_per_launch=alg_bytes,
+                avg_launch_ms=per_launch_ms, launches=n_k)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="pubmed",
+                    help="headline configuration (default: the clustered 19717-node shape, batched + learned planner)")
+    ap.add_argument("--extra", default="cora,citeseer",
+                    help="configurations measured after the headline and reported as extra fields ('' for none)")
+    ap.add_argument("--features", type=int, default=None, help="shrink F of the headline config (quick runs only)")
+    ap.add_argument("--skip-plain", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-ks", action="store_true")
+    ap.add_argument("--skip-top", action="store_true", help="skip the same plan from the top of the prime chain")
+    ap.add_argument("--rule-plan", action="store_true", help="batched form on the paper-rule plan (no learned search)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (scale reference for HBM counters)")
+    ap.add_argument("--serving", action="store_true",
+                    help="instead: a Poisson stream of encrypted GCN requests through the server (rate sweep)")
+    ap.add_argument("--requests", type=int, default=50)
+    ap.add_argument("--keyswitch", action="store_true",
+                    help="instead: key switching alone at the citation-graph parameters (hoisted rotations of one "
+                         "ciphertext, rotations of distinct ciphertexts, relinearisations)")
+    ap.add_argument("--ntu", action="store_true",
+                    help="instead: the 3-layer x^2 GCN (3-64-128-128) on the multi-frame skeleton shape "
+                         "(25 joints x 256 frames, N=2^14)")
+    ap.add_argument("--radix2", action="store_true",
+                    help="instead: the paper's radix-2 SpIntra-CA (per-round masks, CPOO, AOO): rotation/level "
+                         "ablation on synthetic graphs and the second layer of the citation-graph shape on a deep "
+                         "prime chain, timed against the baby-step/giant-step form")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.serving:
+        serving_bench(args)
+        return
+    if args.radix2:
+        radix2_bench(args)
+        return
+    if args.ntu:
+        ntu_bench(args)
+        return
+    if args.keyswitch:
+        keyswitch_bench(args)
+        return
+
+    import torch
+    from paper_2506_10399_amd import ficgcn as fg, graph
+    from workload import make_workload
+
+    all_core = None
+    if not args.skip_cpu:
+        # the oracle's all-core sample first, in fresh processes, while this
+        # process has not touched the GPU (plans are built on the host)
+        w = make_workload(args.config)
+        rp, col, val = graph.normalize(w.graph.n, w.neighbors, w.norm)
+        ctx0 = fg.Context.from_dict(w.params)
+        info0 = fg.Plan(ctx0, rp, col, val, w.graph.n, w.meta["dims"], w.weights, activation=w.activation,
+                        first_pack=-1).ficgcn_plan_info()
+        workers = max(1, min(16, os.cpu_count() or 1))
+        log("cpu baseline, all cores (%d processes)..." % workers)
+        all_core = oracle_sample_all_cores(w.params, *sample_levels(info0), workers)
+        del ctx0, w
+    torch.cuda.set_device(0)
+    net, learned_training = (None, None) if args.rule_plan else train_cost_model()
+    if learned_training:
+        log("cost model: %s" % learned_training)
+
+    if args.calibrate_copy:
+        a = torch.ones(1 << 27, dtype=torch.int64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    head = run_config(args.config, args, net, all_core, with_plain=not args.skip_plain, with_ks=not args.skip_ks,
+                      with_cpu=not args.skip_cpu, with_top=not args.skip_top)
+    prof, info, prm = head.pop("_prof"), head.pop("_info"), head.pop("_prm")
+    torch.cuda.empty_cache()
+    extras = {}
+    for name in [x for x in args.extra.split(",") if x and x != args.config]:
+        r = run_config(name, args, net, with_plain=not args.skip_plain and name == "cora",
+                       with_ks=not args.skip_ks and name == "cora", with_rearranged=name == "cora",
+                       with_cpu=False)
+        for k in ("_prof", "_info", "_prm"):
+            r.pop(k)
+        extras[name] = r
+        torch.cuda.empty_cache()
+
+    roofline = headline_roofline(args, prof, info, prm)
+    ms_step = head["ms"]
+    out = dict(metric=METRIC, value=ms_step, unit="ms", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=ms_step, higher_is_better=False, scaling="weak", vs_baseline=None,
                dtype="u64", data="synthetic",
-               config=dict(workload="%s-shape 2-layer x^2 GCN: %d nodes, %s, K=%d copies, CKKS N=2^%d, "
-                           "%d+%d primes, %d input cts resident" % (args.config, w.graph.n, "-".join(map(str, dims)),
-                                                                     K, prm["log_n"], L, prm["n_p"], n_in),
-                           form="batched, HIP-graph replay (fused Inter-CA pass, batched key switches); layer-1 "
-                                "inputs resident as the matrix-core pass's operands (6.5 bytes per residue, rearranged "
-                                "once on arrival)",
-                           ntt_schedule=dict(cols_column=ntt_cols[0], cols_row=ntt_cols[1],
-                                             log_column_pass=ntt_cols[2])),
-               plain_ms=None if plain_ms is None else round(plain_ms, 3),
-               speedup_vs_plain=None if plain_ms is None else round(plain_ms / ms_step, 3),
-               plain_same_plan_ms=None if plain_same_ms is None else round(plain_same_ms, 3),
-               batched_eager_ms=round(ms_eager, 3),
-               batched_from_ciphertext_words_ms=round(ms_ct, 3), rearrange_inputs_ms=round(pack_ms, 1),
-               rearranged_equals_ciphertext_words=packed_same,
-               plain_equals_batched=same, max_rel_err=err, max_rel_err_plain=err_plain,
-               learned_planner=learned, keyswitch=ks, roofline=roofline,
-               kernel_ms_per_step={k: round(v[0] / args.steps, 3) for k, v in prof.items()},
-               cpu_baseline=cpu)
+               config=dict(workload=head["workload"],
+                           form="batched + learned planner, HIP-graph replay (fused Inter-CA pass over the "
+                                "client's ciphertext words, batched key switches); every inference reads the "
+                                "client's ciphertexts as they arrive",
+                           ntt_schedule=head["ntt_schedule"]),
+               plain_ms=head.get("plain_ms"), speedup_vs_plain=head.get("speedup_vs_plain"),
+               plain_same_plan_ms=head.get("plain_same_plan_ms"), batched_eager_ms=head["batched_eager_ms"],
+               plain_equals_batched=head.get("plain_equals_batched"), max_rel_err=head["max_rel_err"],
+               input_level=head["input_level"], top_level_ms=head.get("top_level_ms"),
+               top_level_max_rel_err=head.get("top_level_max_rel_err"),
+               max_rel_err_plain=head.get("max_rel_err_plain"),
+               learned_planner=dict(head["learned_planner"] or {}, **(learned_training or {})),
+               keyswitch=head.get("keyswitch"), roofline=roofline, kernel_ms_per_step=head["kernel_ms_per_step"],
+               plan=head["plan"], extra_configs=extras, cpu_baseline=head.get("cpu_baseline"))
     print(json.dumps(out), flush=True)
 
 

@@ -231,6 +231,9 @@ typedef struct {
                            column blocks, and it outputs one ciphertext whose block l holds output
                            column l; later layers combine such blocks by block rotations */
   double agg_c;         /* the factor c of Sec. 3.3.2's aggregation-mode formula (0 = 1.0) */
+  int32_t low_level;    /* 1: the first layer's inputs sit at the lowest level the layers need (their
+                           rescales, Sec. 2.1, plus one spare prime for the output) instead of the top
+                           of the chain; the client encrypts at plan info level_in of layer 0 */
 } ficgcn_plan_opts;
 
 /* Builds the plan of an n_layers-layer GCN over the normalised adjacency

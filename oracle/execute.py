@@ -39,10 +39,30 @@ from .params import Params
 from .planner import Plan
 
 
+OUT_LEVEL = 1   # the model output keeps two primes (its scale reaches Delta^2 after x^2)
+
+
+def levels_needed(plan: Plan) -> int:
+    """Levels the layers consume: Inter-CA 2 (combination by integer weights) or 1 (case-1
+    layout), SpIntra-CA 1 or 2 combination rescales (2 after a squared input) plus 1 mask
+    level (the radix-2 program: its depth)."""
+    need, pending = 0, False
+    for lp in plan.layers:
+        if lp.kind == "inter":
+            need += 1 if lp.pack == "rep" else 2
+        else:
+            need += (2 if pending else 1) + (lp.program.depth if lp.family == 3 else 1)
+        pending = lp.activation
+    return need
+
+
 def schedule(prm: Params, plan: Plan) -> List[dict]:
     s = float(2 ** prm.log_scale)
     delta = float(2 ** prm.log_scale)
     lv = prm.L - 1
+    if plan.low_level:
+        # the client's ciphertexts at the lowest level that leaves OUT_LEVEL for the output
+        lv = min(lv, levels_needed(plan) + OUT_LEVEL)
     pending = False
     out = []
     for lp in plan.layers:
@@ -176,10 +196,11 @@ def client_encrypt(prm: Params, plan: Plan, x: np.ndarray, keys: ckks.Keys, seed
     column j, or columns j t .. j t + t - 1 in the case-1 layout)."""
     lp = plan.layers[0]
     copies = sim.client_layout(plan, x, lp)
+    level = schedule(prm, plan)[0]["level_in"]
     cts = []
     for k, vecs in enumerate(copies):
         for f, v in enumerate(vecs):
-            pt = enc.encode(prm, v, prm.scale, prm.L - 1)
+            pt = enc.encode(prm, v, prm.scale, level)
             cts.append(ckks.encrypt(prm, seed, k * len(vecs) + f, keys.s, pt))
     return cts
 

@@ -324,6 +324,9 @@ class Plan:
     rows: list
     layers: List[LayerPlan]
     regions: List[List[int]] = field(default_factory=list)
+    # the client encrypts at the lowest level the layers need (the spare primes of the chain
+    # are never used) instead of the top level
+    low_level: bool = False
 
     @property
     def n_out_cts(self) -> int:
@@ -443,7 +446,19 @@ def _build_rep_plan(n_v, rows, dims, activation, M, use_noo, TH, family, t1, cpo
 def build_plan(n_v: int, rows, dims: Sequence[int], activation: bool, M: int,
                use_noo: bool = True, TH: Optional[int] = None, family: Optional[int] = None,
                first_mode: str = "inter", t: Optional[int] = None, cpoo: Optional[float] = None,
-               aoo: bool = True, first_pack="cols", agg_c: float = 1.0) -> Plan:
+               aoo: bool = True, first_pack="cols", agg_c: float = 1.0, low_level: bool = False) -> Plan:
+    """The executable plan (_build_plan); low_level: the client encrypts at the lowest level
+    the layers need instead of the top of the chain (execute.schedule)."""
+    plan = _build_plan(n_v, rows, dims, activation, M, use_noo, TH, family, first_mode, t, cpoo, aoo, first_pack,
+                       agg_c)
+    plan.low_level = low_level
+    return plan
+
+
+def _build_plan(n_v: int, rows, dims: Sequence[int], activation: bool, M: int,
+                use_noo: bool = True, TH: Optional[int] = None, family: Optional[int] = None,
+                first_mode: str = "inter", t: Optional[int] = None, cpoo: Optional[float] = None,
+                aoo: bool = True, first_pack="cols", agg_c: float = 1.0) -> Plan:
     """The executable plan: layer 1 by `first_mode` ("inter" per the paper's
     first-layer rule, or "spintra"), later layers SpIntra-CA; SpIntra layers
     combine first (F -> F' at one column per ciphertext), pack t = min(pow2(F'),

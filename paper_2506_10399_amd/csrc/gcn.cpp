@@ -700,12 +700,15 @@ static void aggregate_batched(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, c
     std::vector<const uint64_t*> isrc;
     std::vector<std::vector<MacTerm>> ident(np);
     std::vector<KSJob> jobs;
-    for (int g = 0; g < np; ++g) {
-      if (!giants.count(0)) {
+    if (!giants.count(0))
+      for (int g = 0; g < np; ++g) {
         groups.emplace_back();   // an empty group clears the output
         gouts.push_back(outs[g]);
       }
-      for (auto& kv : giants) {
+    // giant-major: the groups of one giant step (one per packed ciphertext) are launched
+    // next to each other, so its masks, shared by the packed ciphertexts, come from L2
+    for (auto& kv : giants) {
+      for (int g = 0; g < np; ++g) {
         std::vector<MacTerm> terms;
         for (size_t si : kv.second) {
           const int64_t b = fmodp(lp.shifts[si], G);
@@ -729,7 +732,37 @@ static void aggregate_batched(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, c
         isrc.push_back(inner + (size_t)l1 * N);
       }
     }
-    group_mac(c, lv, groups, gouts, false);
+    std::stable_sort(jobs.begin(), jobs.end(), [](const KSJob& x, const KSJob& y) { return x.grp < y.grp; });
+    // packed ciphertexts with the same column count share their masks (one plaintext per
+    // shift): then a thread reads each mask word once for up to four of them
+    bool shared = c->N >= 512;
+    for (int g = 1; g < np && shared; ++g) shared = mask(g, 0) == mask(0, 0);
+    if (shared) {
+      for (int c0 = 0; c0 < np; c0 += MacTermNP::MAX) {
+        const int nc = std::min((int)MacTermNP::MAX, np - c0);
+        std::vector<std::vector<MacTermNP>> mg;
+        std::vector<uint64_t*> mo;
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+          const int g = (int)(gi % np);   // groups go giant-major, packed ciphertext fastest
+          if (g != c0) continue;
+          std::vector<MacTermNP> terms;
+          for (const MacTerm& tm : groups[gi]) {
+            MacTermNP t{};
+            t.pt = tm.pt;
+            terms.push_back(t);
+          }
+          for (int k = 0; k < nc; ++k) {
+            const std::vector<MacTerm>& src = groups[gi + k];
+            for (size_t u = 0; u < src.size(); ++u) terms[u].ct[k] = src[u].ct;
+            mo.push_back(gouts[gi + k]);
+          }
+          mg.push_back(terms);
+        }
+        group_mac_np(c, lv, nc, mg, mo, false);
+      }
+    } else {
+      group_mac(c, lv, groups, gouts, false);
+    }
     // giant rotations of each output summed on the key basis, one ModDown per output
     if (!jobs.empty()) keyswitch_masked_sum(c, lv, isrc, jobs, outs, true);
     group_mac(c, lv, ident, outs, true);
@@ -933,6 +966,8 @@ static void run_layer_eager(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, in
     if (!in[i]) FICGCN_THROW(EINVAL_, "null input ciphertext");
   for (size_t i = 0; i < n_out; ++i)
     if (!out[i]) FICGCN_THROW(EINVAL_, "null output ciphertext");
+  for (size_t i = 0; i < lp.ops.size(); ++i)
+    if (!lp.ops[i] && lp.op_alias[i] >= 0) lp.ops[i] = lp.ops[lp.op_alias[i]];
   for (uint64_t* o : lp.ops)
     if (!o) FICGCN_THROW(EPLAN_, "plan operands not encoded or loaded");
   ensure_weights(c, lp);
@@ -1289,6 +1324,12 @@ ficgcn_status ficgcn_plan_operand_slots(const ficgcn_plan* plan, uint32_t layer,
   GUARD_END
 }
 
+// operands sharing another's memory point where it points once it is set
+static void resolve_aliases(LayerPlan& lp) {
+  for (size_t i = 0; i < lp.ops.size(); ++i)
+    if (lp.op_alias[i] >= 0 && !lp.ops[i]) lp.ops[i] = lp.ops[lp.op_alias[i]];
+}
+
 static void ensure_ops_block(ckks_ctx* ctx, LayerPlan& lp) {
   if (lp.ops_block) return;
   if (hipMalloc(&lp.ops_block, std::max<size_t>(1, lp.op_words) * 8) != hipSuccess)
@@ -1343,12 +1384,17 @@ ficgcn_status ficgcn_plan_encode(ckks_ctx* ctx, ficgcn_plan* plan) {
     const size_t chunk = 256;
     std::vector<double> all;
     std::vector<double> v;
-    // runs of operands with one level, basis and scale
+    // runs of operands with one level, basis and scale; operands sharing another's memory
+    // (op_alias) are that operand
     for (size_t b0 = 0; b0 < n;) {
+      if (lp.op_alias[b0] >= 0) {
+        ++b0;
+        continue;
+      }
       size_t nb = 1;
       const double sc = plan_operand_scale(plan, (int)li, b0);
-      while (b0 + nb < n && nb < chunk && lp.op_lv[b0 + nb] == lp.op_lv[b0] && lp.op_x[b0 + nb] == lp.op_x[b0] &&
-             plan_operand_scale(plan, (int)li, b0 + nb) == sc)
+      while (b0 + nb < n && nb < chunk && lp.op_alias[b0 + nb] < 0 && lp.op_lv[b0 + nb] == lp.op_lv[b0] &&
+             lp.op_x[b0 + nb] == lp.op_x[b0] && plan_operand_scale(plan, (int)li, b0 + nb) == sc)
         ++nb;
       all.assign(nb * plan->M, 0.0);
       for (size_t b = 0; b < nb; ++b) {
@@ -1365,6 +1411,7 @@ ficgcn_status ficgcn_plan_encode(ckks_ctx* ctx, ficgcn_plan* plan) {
       for (size_t b = 0; b < nb; ++b) lp.ops[b0 + b] = lp.ops_block + lp.op_off[b0 + b];
       b0 += nb;
     }
+    resolve_aliases(lp);
   }
   GUARD_END
 }
@@ -1396,6 +1443,7 @@ ficgcn_status ficgcn_plan_fill_operands(ckks_ctx* ctx, ficgcn_plan* plan, uint64
     LayerPlan& lp = plan->layers[li];
     ensure_ops_block(ctx, lp);
     for (size_t i = 0; i < lp.ops.size(); ++i) {
+      if (lp.op_alias[i] >= 0) continue;
       uint64_t* dst = lp.ops_block + lp.op_off[i];
       const int l1 = lp.op_lv[i] + 1;
       // stream (6, layer * 2^20 + i, limb): a stream the scheme itself never draws
@@ -1403,6 +1451,7 @@ ficgcn_status ficgcn_plan_fill_operands(ckks_ctx* ctx, ficgcn_plan* plan, uint64
                      lp.op_x[i] ? lm_ext(lp.op_lv[i], ctx->L) : lm_q(l1), 1);
       lp.ops[i] = dst;
     }
+    resolve_aliases(lp);
   }
   HIPCHECK(hipStreamSynchronize(ctx->stream));
   GUARD_END

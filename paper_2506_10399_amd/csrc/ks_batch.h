@@ -53,6 +53,15 @@ void rescale_batch(ckks_ctx* c, int level, const std::vector<uint64_t*>& cts);
 // two rescales in a row (level, then level - 1) in one pass over the limbs;
 // the same words as two rescale_batch calls
 void rescale2_batch(ckks_ctx* c, int level, const std::vector<uint64_t*>& cts);
+// a term of a sum over up to four ciphertexts under one shared plaintext
+struct MacTermNP {
+  enum { MAX = 4 };
+  const uint64_t* ct[MAX];   // [2][l+1][N] each
+  const uint64_t* pt;        // [l+1][N], null = plain addition
+};
+// outs[g * np + c] (accumulate ? += : =) sum over groups[g]'s terms of ct[c] (.) pt
+void group_mac_np(ckks_ctx* c, int level, int np, const std::vector<std::vector<MacTermNP>>& groups,
+                  const std::vector<uint64_t*>& outs, bool accumulate);
 // outs[g] (accumulate ? += : =) sum of groups[g]'s terms
 void group_mac(ckks_ctx* c, int level, const std::vector<std::vector<MacTerm>>& groups,
                const std::vector<uint64_t*>& outs, bool accumulate);

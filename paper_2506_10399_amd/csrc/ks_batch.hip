@@ -830,4 +830,158 @@ void group_mac(ckks_ctx* c, int level, const std::vector<std::vector<MacTerm>>& 
   stream_sync(c);
 }
 
+
+// ---- masked sums of several ciphertexts under shared masks ----------------------
+
+// outs[g * NP + c] (+)= sum over the terms of group g of ct_c (.) pt (ct_c alone when pt is
+// null).  The NP ciphertexts of a term share its plaintext word, read once; a thread takes
+// two neighbouring coefficients of one limb with 16-byte loads, so every load instruction
+// moves two words and NP + 1 streams are in flight per term.
+template <int NP>
+__global__ void __launch_bounds__(KB) k_group_mac_np(const MacTermNP* __restrict__ terms, const int* __restrict__ group_start,
+                               uint64_t* const* __restrict__ outs, int l1, int accumulate, int log_n, int n_groups,
+                               int xcd_order, const Mod* __restrict__ mods) {
+  typedef uint64_t v2 __attribute__((ext_vector_type(2)));
+  typedef __attribute__((address_space(1))) const v2 gv2;
+  typedef __attribute__((address_space(1))) v2 gv2w;
+  const size_t N = (size_t)1 << log_n;
+  const int i = blockIdx.z;
+  int jb, g;
+  if (xcd_order) {   // every group of one coefficient block back to back on one XCD
+    const int b = blockIdx.x, idx = b >> 3;
+    jb = (b & 7) + 8 * (idx / n_groups);
+    g = idx % n_groups;
+  } else {
+    jb = blockIdx.x;
+    g = blockIdx.y;
+  }
+  const size_t j = 2 * ((size_t)jb * KB + threadIdx.x);
+  const Mod m = mods[i];
+  const size_t o0 = (size_t)i * N + j, o1 = ((size_t)l1 + i) * N + j;
+  uint64_t a[NP][4];   // per ciphertext: component 0 at j, j+1, component 1 at j, j+1
+#pragma unroll
+  for (int c = 0; c < NP; ++c) {
+    uint64_t* out = outs[(size_t)g * NP + c];
+    if (accumulate) {
+      const v2 u = *(gv2*)(out + o0), v = *(gv2*)(out + o1);
+      a[c][0] = u.x, a[c][1] = u.y, a[c][2] = v.x, a[c][3] = v.y;
+    } else {
+      a[c][0] = a[c][1] = a[c][2] = a[c][3] = 0;
+    }
+  }
+  const int t_end = group_start[g + 1];
+  int t = group_start[g];
+  u128 s[NP][4];
+#pragma unroll
+  for (int c = 0; c < NP; ++c) s[c][0] = s[c][1] = s[c][2] = s[c][3] = 0;
+  auto mac = [&](const v2& p, const v2 (&x)[NP], const v2 (&y)[NP]) {
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
+      s[c][0] += (u128)x[c].x * p.x;
+      s[c][1] += (u128)x[c].y * p.y;
+      s[c][2] += (u128)y[c].x * p.x;
+      s[c][3] += (u128)y[c].y * p.y;
+    }
+  };
+  auto fold = [&]() {
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        a[c][k] = add_mod(a[c][k], reduce128(s[c][k], m), m.q);
+        s[c][k] = 0;
+      }
+  };
+  // two terms' loads in flight together; products of four terms summed in 128 bits
+  // (each below 2^100 for words below 2^50) before one reduction
+  int cnt = 0;
+  for (; t + 2 <= t_end; t += 2) {
+    const MacTermNP ta = terms[t], tb = terms[t + 1];
+    v2 pa = {1, 1}, pb = {1, 1};
+    if (ta.pt) pa = *(gv2*)(ta.pt + (size_t)i * N + j);
+    if (tb.pt) pb = *(gv2*)(tb.pt + (size_t)i * N + j);
+    v2 xa[NP], ya[NP], xb[NP], yb[NP];
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
+      xa[c] = *(gv2*)(ta.ct[c] + o0);
+      ya[c] = *(gv2*)(ta.ct[c] + o1);
+      xb[c] = *(gv2*)(tb.ct[c] + o0);
+      yb[c] = *(gv2*)(tb.ct[c] + o1);
+    }
+    mac(pa, xa, ya);
+    mac(pb, xb, yb);
+    if ((cnt += 2) == 4) {
+      fold();
+      cnt = 0;
+    }
+  }
+  if (t < t_end) {
+    const MacTermNP ta = terms[t];
+    v2 pa = {1, 1};
+    if (ta.pt) pa = *(gv2*)(ta.pt + (size_t)i * N + j);
+    v2 xa[NP], ya[NP];
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
+      xa[c] = *(gv2*)(ta.ct[c] + o0);
+      ya[c] = *(gv2*)(ta.ct[c] + o1);
+    }
+    mac(pa, xa, ya);
+  }
+  fold();
+#pragma unroll
+  for (int c = 0; c < NP; ++c) {
+    uint64_t* out = outs[(size_t)g * NP + c];
+    const v2 r0 = {a[c][0], a[c][1]}, r1 = {a[c][2], a[c][3]};
+    *(gv2w*)(out + o0) = r0;
+    *(gv2w*)(out + o1) = r1;
+  }
+}
+
+void group_mac_np(ckks_ctx* c, int level, int np, const std::vector<std::vector<MacTermNP>>& groups,
+                  const std::vector<uint64_t*>& outs, bool accumulate) {
+  if (groups.empty()) return;
+  if (np < 1 || np > MacTermNP::MAX) FICGCN_THROW(EINVAL_, "shared-mask sum: 1 to 4 ciphertexts per term");
+  if (outs.size() != groups.size() * np) FICGCN_THROW(EINVAL_, "group/output count mismatch");
+  if (c->N < 2 * KB) FICGCN_THROW(EINVAL_, "ring too small for the shared-mask sum");
+  ProfScope ps(c, "group_mac");
+  std::vector<MacTermNP> flat;
+  std::vector<int> start{0};
+  for (const auto& g : groups) {
+    for (const MacTermNP& t : g)
+      for (int k = 0; k < np; ++k)
+        if (!t.ct[k]) FICGCN_THROW(EINVAL_, "null term");
+    flat.insert(flat.end(), g.begin(), g.end());
+    start.push_back((int)flat.size());
+  }
+  for (uint64_t* o : outs)
+    if (!o) FICGCN_THROW(EINVAL_, "null output");
+  MacTermNP* td = upload(c, S_GM_TERMS, flat);
+  int* sd = upload(c, S_GM_START, start);
+  uint64_t* const* od = upload(c, S_GM_OUT, outs);
+  if (groups.size() > 65535) FICGCN_THROW(EINVAL_, "too many groups in one launch");
+  const int n_jb = c->N / (2 * KB), ng = (int)groups.size();
+  const bool xcd = n_jb % 8 == 0 && (size_t)n_jb * ng < ((size_t)1 << 31);
+  const dim3 grid = xcd ? dim3(n_jb * ng, 1, level + 1) : dim3(n_jb, ng, level + 1);
+  const int acc = accumulate ? 1 : 0;
+  switch (np) {
+    case 1:
+      hipLaunchKernelGGL(k_group_mac_np<1>, grid, dim3(KB), 0, c->stream, td, sd, od, level + 1, acc, c->log_n, ng,
+                         xcd ? 1 : 0, c->t.mods);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_group_mac_np<2>, grid, dim3(KB), 0, c->stream, td, sd, od, level + 1, acc, c->log_n, ng,
+                         xcd ? 1 : 0, c->t.mods);
+      break;
+    case 3:
+      hipLaunchKernelGGL(k_group_mac_np<3>, grid, dim3(KB), 0, c->stream, td, sd, od, level + 1, acc, c->log_n, ng,
+                         xcd ? 1 : 0, c->t.mods);
+      break;
+    default:
+      hipLaunchKernelGGL(k_group_mac_np<4>, grid, dim3(KB), 0, c->stream, td, sd, od, level + 1, acc, c->log_n, ng,
+                         xcd ? 1 : 0, c->t.mods);
+  }
+  HIPCHECK(hipGetLastError());
+  stream_sync(c);
+}
+
 }  // namespace ficgcn

@@ -306,10 +306,29 @@ static std::vector<int64_t> rotation_steps_of(const LayerPlan& lp) {
   return std::vector<int64_t>(s.begin(), s.end());
 }
 
+// levels the layers consume: Inter-CA 2 (integer-weight combination) or 1 (case-1 layout),
+// SpIntra-CA 1 or 2 combination rescales (2 after a squared input) plus 1 mask level (the
+// radix-2 program: its depth)
+static int levels_needed(const ficgcn_plan* p) {
+  int need = 0;
+  bool pending = false;
+  for (const LayerPlan& lp : p->layers) {
+    if (lp.kind == 0)
+      need += lp.pack ? 1 : 2;
+    else
+      need += (pending ? 2 : 1) + (lp.family == 3 ? lp.r2.depth : 1);
+    pending = lp.act;
+  }
+  return need;
+}
+
+static constexpr int OUT_LEVEL = 1;   // the output keeps two primes (scale Delta^2 after x^2)
+
 static void schedule(ckks_ctx* c, ficgcn_plan* p) {
   const double delta = std::ldexp(1.0, c->log_scale);
   double s = delta;
   int lv = c->L - 1;
+  if (p->low_level) lv = std::min(lv, levels_needed(p) + OUT_LEVEL);
   bool pending = false;
   for (LayerPlan& lp : p->layers) {
     lp.level_in = lv;
@@ -423,10 +442,25 @@ static void layout_operands(ficgcn_plan* p) {
     lp.op_x.resize(n);
     lp.op_lv.resize(n);
     lp.op_off.resize(n);
+    lp.op_alias.assign(n, -1);
+    // aggregation masks depend on the packed ciphertext only through its column count
+    // (mask slots c B + pi(v) for c < n_cols): packed ciphertexts with the first one's
+    // count share its masks
+    const size_t nag = lp.n_agg_ops(), np = lp.kind == 1 ? (size_t)lp.n_packed() : 1;
+    const size_t per = np ? nag / np : 0;
+    const int cols0 = std::min(lp.t, lp.f_out);
     size_t off = 0;
     for (size_t i = 0; i < n; ++i) {
       lp.op_x[i] = plan_operand_ext(p, (int)li, i) ? 1 : 0;
       lp.op_lv[i] = plan_operand_level(p, (int)li, i);
+      if (i < nag && per && i >= per) {
+        const int g = (int)(i / per);
+        if (std::min(lp.t, lp.f_out - g * lp.t) == cols0) {
+          lp.op_alias[i] = (int32_t)(i % per);
+          lp.op_off[i] = lp.op_off[i % per];
+          continue;
+        }
+      }
       lp.op_off[i] = off;
       off += (size_t)(lp.op_lv[i] + 1 + (lp.op_x[i] ? p->ctx->alpha : 0)) * N;
     }
@@ -682,6 +716,7 @@ void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_la
   const int n = p->n_v;
   const int M = c->N / 2;
   p->M = M;
+  p->low_level = o.low_level != 0;
   if (o.first_mode == 1 && n_layers > 1)
     FICGCN_THROW(EPLAN_, "a SpIntra-CA first layer is only supported for one-layer models");
   int K_all = 0;

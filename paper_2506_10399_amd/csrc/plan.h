@@ -77,6 +77,8 @@ struct LayerPlan {
   double op_scale = 0;
   std::vector<char> op_x;          // operand on the key basis (level+1+alpha limbs): family 4 masks,
                                    // the nonzero-offset block-combination masks
+  std::vector<int32_t> op_alias;   // operand whose memory this one shares (-1: its own): the masks of
+                                   // packed ciphertexts with as many columns as the first one are equal
   std::vector<int32_t> op_lv;      // level of each operand
   std::vector<size_t> op_off;      // word offset of each operand in ops_block
   size_t op_words = 0;
@@ -128,6 +130,7 @@ struct ficgcn_plan {
   std::vector<std::vector<int>> regions;
   std::vector<ficgcn::LayerPlan> layers;
   std::vector<int64_t> rot_steps;
+  bool low_level = false;    // inputs at the lowest level the layers need
   ~ficgcn_plan();
 };
 

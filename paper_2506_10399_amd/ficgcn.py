@@ -38,7 +38,7 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("first_mode", ctypes.c_int32), ("use_noo", ctypes.c_int32), ("family", ctypes.c_int32),
                 ("TH", ctypes.c_int32), ("activation", ctypes.c_int32), ("t", ctypes.c_int32),
                 ("aoo_off", ctypes.c_int32), ("cpoo", ctypes.c_double), ("first_pack", ctypes.c_int32),
-                ("agg_c", ctypes.c_double)]
+                ("agg_c", ctypes.c_double), ("low_level", ctypes.c_int32)]
 
 
 class SearchStats(ctypes.Structure):
@@ -407,7 +407,7 @@ class Plan:
     def __init__(self, ctx: Context, rowptr, col, val, n_v: int, dims: Sequence[int], weights,
                  first_mode: int = 0, use_noo: bool = True, family: int = 0, TH: int = 0, activation: bool = False,
                  t: int = 0, cpoo: float = 0.0, aoo: bool = True, first_pack: int = 0, agg_c: float = 0.0,
-                 opts: "PlanOpts" = None):
+                 low_level: bool = False, opts: "PlanOpts" = None):
         self.ctx = ctx
         self._rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
         self._col = np.ascontiguousarray(col, dtype=np.int32)
@@ -418,7 +418,7 @@ class Plan:
         if opts is None:
             opts = PlanOpts(first_mode=first_mode, use_noo=int(use_noo), family=family, TH=TH,
                             activation=int(activation), t=t, aoo_off=int(not aoo), cpoo=cpoo,
-                            first_pack=first_pack, agg_c=agg_c)
+                            first_pack=first_pack, agg_c=agg_c, low_level=int(low_level))
         self.opts = opts
         h = c_vp()
         _check(lib().ficgcn_plan_create(ctx.h, _ptr(self._rowptr), _ptr(self._col), _ptr(self._val), n_v,

@@ -23,14 +23,14 @@ def _ct(c):
     return np.stack([c.c0, c.c1])
 
 
-def _setup(name, mode, family=None, cpoo=None, **kw):
+def _setup(name, mode, family=None, cpoo=None, t=None, low_level=False, **kw):
     from paper_2506_10399_amd import ficgcn as fg, graph
     w = make_workload(name, **kw)
     prm = Params.from_dict(w.params)
     rows = gcn.normalized_rows(w.graph.n, w.neighbors, w.norm)
     ref = gcn.gcn_forward(rows, w.x, w.weights, w.activation)
     o = planner.build_plan(w.graph.n, rows, w.meta["dims"], w.activation, prm.M, family=family, first_mode=mode,
-                           cpoo=cpoo)
+                           cpoo=cpoo, t=t, low_level=low_level)
     okeys = ckks.keygen(prm, KEY_SEED, o.rot_steps(prm.M), relin=w.activation)
     sched = ex.schedule(prm, o)
     ops = ex.encode_operands(prm, o, w.weights, sched)
@@ -39,7 +39,7 @@ def _setup(name, mode, family=None, cpoo=None, **kw):
     ctx = fg.Context.from_dict(w.params)
     rp, col, val = graph.normalize(w.graph.n, w.neighbors, w.norm)
     p = fg.Plan(ctx, rp, col, val, w.graph.n, w.meta["dims"], w.weights, first_mode=0 if mode == "inter" else 1,
-                family=family or 0, activation=w.activation, cpoo=cpoo or 0.0)
+                family=family or 0, activation=w.activation, cpoo=cpoo or 0.0, t=t or 0, low_level=low_level)
     assert np.array_equal(p.ficgcn_plan_node_order(), o.pi)
     cl, ev = ctx.ckks_keygen(KEY_SEED, p.ficgcn_plan_rot_steps(), with_relin=w.activation)
     return dict(w=w, prm=prm, rows=rows, ref=ref, o=o, okeys=okeys, sched=sched, ops=ops, cts=cts, outs=outs,
@@ -65,7 +65,8 @@ def _load_operands(e):
 
 def _run_gpu(e, mode, contiguous=False):
     ctx, p, info = e["ctx"], e["p"], e["p"].ficgcn_plan_info()
-    lv0 = e["prm"].L - 1
+    lv0 = e["cts"][0].level
+    assert lv0 == info[0]["level_in"]
     cur = [ctx.ckks_ct_load(_ct(c), lv0) for c in e["cts"]]
     if contiguous:
         # the inputs as equally spaced views of one block (the strided read path)
@@ -282,3 +283,39 @@ def test_rearranged_inputs_refuse_primes_of_51_bits_or_more():
     out = torch.empty(words, dtype=torch.int64, device="cuda")
     st = fg.lib().ficgcn_plan_pack_inputs(ctx.h, p.h, 0, fg._ptr_array(ins), len(ins), fg._ptr(out), out.numel())
     assert st != 0
+
+
+@pytest.mark.parametrize("t,family", [(1, 2), (2, 2), (1, 1)])
+def test_second_layer_packed_ciphertexts_share_masks(t, family):
+    """Seven output columns packed t per ciphertext: at t = 1 the seven packed ciphertexts
+    share their masks (the baby-step/giant-step inner sums read each mask word once for
+    four, then three, of them); at t = 2 the last one holds a single column, so its masks
+    differ and the general sum runs.  Words equal the oracle's in both forms."""
+    e = _setup("tiny2", "inter", family, t=t)
+    _load_operands(e)
+    assert e["p"].ficgcn_plan_info()[1]["n_out_cts"] == -(-7 // t)
+    for m in (0, 1):
+        for li, ((outs, lvo), want) in enumerate(zip(_run_gpu(e, m), e["outs"])):
+            for g, (a, b) in enumerate(zip(outs, want)):
+                assert np.array_equal(e["ctx"].ckks_poly_store(a, lvo, 2), _ct(b)), (t, family, m, li, g)
+
+
+@pytest.mark.parametrize("name,mode,family", [("tiny2", "inter", None), ("tiny2", "inter", 4), ("tiny", "spintra", 2)])
+def test_lowest_level_plans_bit_exact(name, mode, family):
+    """Inputs at the lowest level the layers need (the output keeps one spare prime):
+    plain and batched words equal the oracle's; decrypted within 1e-3."""
+    e = _setup(name, mode, family, low_level=True)
+    _load_operands(e)
+    assert e["cts"][0].level < e["prm"].L - 1 or name == "tiny"
+    for m in (0, 1):
+        for li, ((outs, lvo), want) in enumerate(zip(_run_gpu(e, m), e["outs"])):
+            for g, (a, b) in enumerate(zip(outs, want)):
+                assert np.array_equal(e["ctx"].ckks_poly_store(a, lvo, 2), _ct(b)), (name, family, m, li, g)
+    lp = e["o"].layers[-1]
+    info = e["p"].ficgcn_plan_info()[-1]
+    assert info["level_out"] == 1
+    res = _run_gpu(e, 1)[-1]
+    slots = [np.real(e["ctx"].ckks_decrypt(e["cl"], x, info["level_out"], info["scale_out"], e["prm"].M))
+             for x in res[0]]
+    y = e["graph"].read_output(e["o"].pi, slots, lp.f_out, lp.t, lp.B, lp.kind == "spintra")
+    assert gcn.max_rel_error(y, e["ref"][-1]) < 1e-3

@@ -350,3 +350,23 @@ def test_case1_rule_and_rejections(fg):
     ctx2 = fg.Context.from_dict(wc.params)
     p2 = fg.Plan(ctx2, rp, col, val, wc.graph.n, [24, 16, 7], wc.weights, activation=True, first_pack=-1)
     assert p2.ficgcn_plan_info()[0]["pack"] == 0
+
+
+@pytest.mark.parametrize("name,kw,fp", [("cora", {"dims": [24, 16, 7]}, 0), ("tiny", {}, -1), ("tiny2", {}, 0),
+                                         ("pubmed", {"dims": [8, 16, 3], "n_nodes": 3000}, 0)])
+def test_lowest_level_schedule_matches_oracle(fg, name, kw, fp):
+    from paper_2506_10399_amd import graph
+    w = make_workload(name, **kw)
+    prm = Params.from_dict(w.params)
+    rows = gcn.normalized_rows(w.graph.n, w.neighbors, w.norm)
+    o = planner.build_plan(w.graph.n, rows, w.meta["dims"], w.activation, prm.M, low_level=True,
+                           first_pack="rule" if fp < 0 else "cols")
+    rp, col, val = graph.normalize(w.graph.n, w.neighbors, w.norm)
+    ctx = fg.Context.from_dict(w.params)
+    p = fg.Plan(ctx, rp, col, val, w.graph.n, w.meta["dims"], w.weights, activation=w.activation, first_pack=fp,
+                low_level=True)
+    sched = ex.schedule(prm, o)
+    assert sched[-1]["level_out"] == ex.OUT_LEVEL
+    for d, st in zip(p.ficgcn_plan_info(), sched):
+        assert (d["level_in"], d["level_out"]) == (st["level_in"], st["level_out"])
+        assert d["scale_in"] == st["scale_in"] and d["scale_out"] == st["scale_out"] and d["sW"] == st["sW"]

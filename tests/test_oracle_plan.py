@@ -330,3 +330,39 @@ def test_case1_encrypted_plan_decrypts_to_fp64_gcn(name, kw):
     outs = ex.run(prm, plan, keys, cts, ops, sched)
     y = ex.decrypt_output(prm, plan, keys, outs[-1])
     assert gcn.max_rel_error(y, ref) < 1e-3
+
+
+def test_lowest_level_schedule():
+    """With low_level the client encrypts at the level the layers consume plus the output's
+    one spare prime: citation shape 2 (Inter-CA) + 2 + 1 (SpIntra-CA after x^2) = 5 -> level 6;
+    tiny case-1 one-layer plan 1 -> level 2; the schedule then ends at level 1 exactly."""
+    w, rows = _rows("cora", n_nodes=600, dims=[8, 16, 7])
+    for L, lv0 in ((8, 6), (10, 6)):
+        prm = Params.from_dict(dict(w.params, n_q=L))
+        plan = planner.build_plan(w.graph.n, rows, [8, 16, 7], True, prm.M, low_level=True)
+        sched = ex.schedule(prm, plan)
+        assert ex.levels_needed(plan) == 5
+        assert sched[0]["level_in"] == lv0 and sched[-1]["level_out"] == ex.OUT_LEVEL
+        top = ex.schedule(prm, planner.build_plan(w.graph.n, rows, [8, 16, 7], True, prm.M))
+        assert top[0]["level_in"] == L - 1 and top[-1]["level_out"] == L - 1 - 5
+    w, rows = _rows("tiny")
+    prm = Params.from_dict(w.params)
+    plan = planner.build_plan(w.graph.n, rows, w.meta["dims"], False, prm.M, first_pack="rule", low_level=True)
+    assert ex.schedule(prm, plan)[0]["level_in"] == 2
+
+
+@pytest.mark.slow
+def test_lowest_level_encrypted_plan_decrypts_to_fp64_gcn():
+    w, rows = _rows("tiny2")
+    prm = Params.from_dict(w.params)
+    ref = gcn.gcn_forward(rows, w.x, w.weights, w.activation)[-1]
+    plan = planner.build_plan(w.graph.n, rows, w.meta["dims"], w.activation, prm.M, low_level=True)
+    sched = ex.schedule(prm, plan)
+    assert sched[0]["level_in"] == 6 and sched[-1]["level_out"] == 1
+    keys = ckks.keygen(prm, 11, plan.rot_steps(prm.M), relin=w.activation)
+    ops = ex.encode_operands(prm, plan, w.weights, sched)
+    cts = ex.client_encrypt(prm, plan, w.x, keys, 12)
+    assert cts[0].level == 6
+    outs = ex.run(prm, plan, keys, cts, ops, sched)
+    y = ex.decrypt_output(prm, plan, keys, outs[-1])
+    assert gcn.max_rel_error(y, ref) < 1e-3
