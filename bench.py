@@ -38,7 +38,8 @@ HBM_PEAK_GBS = 8000.0
 
 
 # library profile scopes reported per step (each a sum of HIP-event intervals)
-PROF_NAMES = ("inter_fused", "comb_fused", "keymac", "moddown", "modup", "ntt", "group_mac", "ks_masked", "rescale")
+PROF_NAMES = ("inter_fused", "comb_fused", "keymac", "moddown", "modup", "ntt", "group_mac", "ks_masked", "rescale",
+              "bsgs_inner")
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -54,23 +55,6 @@ def fp64_gcn(rp, col, val, x, weights):
         h = A @ (h @ w)
         h = h * h
     return h
-
-
-def measured_traffic():
-    """HBM bytes per launch of the fused pass (on rearranged inputs) from the committed rocprofv3
-    counter runs (FETCH_SIZE + WRITE_SIZE scaled by a copy of known size), or
-    None when the kernel source changed since the counters were taken."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "fused_mfma_packed_cora_traffic.json")
-    src = os.path.join(ROOT, "paper_2506_10399_amd", "csrc", "gcn_mfma.hip")
-    try:
-        with open(path) as f:
-            rec = json.load(f)
-        with open(src, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
-    except OSError:
-        return None
-    return rec.get("bytes_per_launch") if rec.get("source_sha256") == digest else None
 
 
 def oracle_op_sample(params, K, F_out, la, lr, sample_features=12):
@@ -123,8 +107,14 @@ def oracle_sample_all_cores(params, K, F_out, la, lr, workers):
     """The same sample in `workers` fresh processes at once (spawned before
     this process touches the GPU); returns each process's timings."""
     import multiprocessing as mp
-    with mp.get_context("spawn").Pool(workers) as pool:
-        return pool.starmap(oracle_op_sample, [(params, K, F_out, la, lr)] * workers)
+    pool = mp.get_context("spawn").Pool(workers)
+    try:
+        res = pool.starmap(oracle_op_sample, [(params, K, F_out, la, lr)] * workers)
+    finally:
+        # no worker (nor the pool's helper threads) outlives the sample
+        pool.close()
+        pool.join()
+    return res
 
 
 def sample_levels(plan_info):
@@ -478,26 +468,77 @@ def run_config(name, args, net, all_core=None, with_plain=True, with_ks=True, wi
     res["_prof"] = prof
     res["_info"] = info
     res["_prm"] = prm
+    res["_bsgs"] = bsgs_inner_bytes(plan, info, N) if info[-1]["kind"] == 1 and info[-1]["family"] == 2 else None
     del inputs, in_list, outs
     return res
 
 
-def headline_roofline(args, prof, info, prm):
-    """Roofline of the fused Inter-CA + combination pass over the client's ciphertext
-    words: algorithmic bytes per launch (2 K F input limb-polynomials, K plaintexts,
-    2 F' outputs at the layer's l1 limbs, the integer weights) over its mean launch time
-    from HIP events on the context's stream."""
+def bsgs_inner_bytes(plan, info, N):
+    """Algorithmic bytes of the baby-step/giant-step inner sums of the SpIntra-CA layer
+    (one launch per four packed ciphertexts): every mask once (the packed ciphertexts share
+    them), every baby-step rotation and the packed input once, every inner sum written once;
+    l1 limbs of 8N bytes at the aggregation level."""
+    li = len(info) - 1
+    d = info[li]
+    la = d["level_out"] + 1
+    l1 = la + 1
+    shifts = plan.ficgcn_plan_shifts(li)
+    G = d["G"]
+    babies = {s % G for s in shifts} - {0}
+    giants = {s // G for s in shifts}
+    np_ = d["n_out_cts"]
+    limb = 8.0 * N
+    per_ct = (2 * l1 * (len(babies) + 1) + 2 * l1 * len(giants)) * limb
+    masks = len(shifts) * l1 * limb
+    launches = -(-np_ // 4)
+    return (masks * launches + per_ct * np_) / launches, launches
+
+
+def measured_traffic(kernel_file, src_file):
+    """HBM bytes per launch from the committed rocprofv3 counter runs (FETCH_SIZE + WRITE_SIZE,
+    each scaled by what the counter reads for a device copy of known size), or None when
+    the kernel's source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", kernel_file)
+    src = os.path.join(ROOT, "paper_2506_10399_amd", "csrc", src_file)
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    return rec.get("bytes_per_launch") if rec.get("source_sha256") == digest else None
+
+
+def headline_roofline(args, prof, info, prm, bsgs=None):
+    """Roofline of the dominant kernel of one inference, k_group_mac_np (the SpIntra-CA
+    layer's baby-step/giant-step inner sums): algorithmic bytes per launch over its mean
+    launch time from HIP events on the context's stream.  The fused Inter-CA +
+    combination pass over the client's ciphertext words is given beside it."""
     N = 1 << prm["log_n"]
     d0 = info[0]
     K, F, F_out, l1 = d0["K"], d0["f_in"], d0["f_out"], d0["level_in"] + 1
-    alg_bytes = 8.0 * N * l1 * (2 * K * F + K + 2 * F_out) + 8.0 * l1 * F * F_out
+    fused_bytes = 8.0 * N * l1 * (2 * K * F + K + 2 * F_out) + 8.0 * l1 * F * F_out
     ms_k, n_k = prof["inter_fused"]
-    per_launch_ms = ms_k / max(1, n_k)
-    achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
-    return dict(kernel="k_fused_mfma (Inter-CA aggregation + combination on int8 matrix cores over the client's "
-                       "ciphertext words)", bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, alg_bytes_per_launch=alg_bytes,
-                avg_launch_ms=per_launch_ms, launches=n_k)
+    fused_ms = ms_k / max(1, n_k)
+    fused = dict(kernel="k_fused_mfma (Inter-CA aggregation + combination on int8 matrix cores over the client's "
+                        "ciphertext words)", bound="hbm", achieved=round(fused_bytes / (fused_ms * 1e-3) / 1e9, 1),
+                 peak=HBM_PEAK_GBS, unit="GB/s", alg_bytes_per_launch=fused_bytes, avg_launch_ms=fused_ms,
+                 launches=n_k)
+    fused["frac"] = round(fused["achieved"] / HBM_PEAK_GBS, 4)
+    ms_b, n_b = prof["bsgs_inner"]
+    if bsgs is None or n_b == 0:
+        return dict(fused, traffic=None)
+    alg, per_step = bsgs
+    b_ms = ms_b / n_b
+    achieved = alg / (b_ms * 1e-3) / 1e9
+    return dict(kernel="k_group_mac_np (SpIntra-CA baby-step/giant-step inner sums, masks shared by the packed "
+                       "ciphertexts)", bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=measured_traffic("group_mac_np_pubmed_traffic.json", "ks_batch.hip"),
+                alg_bytes_per_launch=alg, avg_launch_ms=b_ms, launches=n_b, launches_per_step=per_step,
+                fused_inter_ca_pass=fused)
 
 
 def main():
@@ -580,19 +621,19 @@ def main():
 
     head = run_config(args.config, args, net, all_core, with_plain=not args.skip_plain, with_ks=not args.skip_ks,
                       with_cpu=not args.skip_cpu, with_top=not args.skip_top)
-    prof, info, prm = head.pop("_prof"), head.pop("_info"), head.pop("_prm")
+    prof, info, prm, bsgs = head.pop("_prof"), head.pop("_info"), head.pop("_prm"), head.pop("_bsgs")
     torch.cuda.empty_cache()
     extras = {}
     for name in [x for x in args.extra.split(",") if x and x != args.config]:
         r = run_config(name, args, net, with_plain=not args.skip_plain and name == "cora",
                        with_ks=not args.skip_ks and name == "cora", with_rearranged=name == "cora",
                        with_cpu=False)
-        for k in ("_prof", "_info", "_prm"):
+        for k in ("_prof", "_info", "_prm", "_bsgs"):
             r.pop(k)
         extras[name] = r
         torch.cuda.empty_cache()
 
-    roofline = headline_roofline(args, prof, info, prm)
+    roofline = headline_roofline(args, prof, info, prm, bsgs)
     ms_step = head["ms"]
     out = dict(metric=METRIC, value=ms_step, unit="ms", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=ms_step, higher_is_better=False, scaling="weak", vs_baseline=None,

@@ -132,11 +132,14 @@ struct ProfScope {
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
     (void)hipEventRecord(a, c->stream);
   }
-  ~ProfScope() {
+  // records the end event now (before a host wait that follows the timed launches)
+  void stop() {
     if (!c->profiling || c->rec || !a || !b) return;
     (void)hipEventRecord(b, c->stream);
     c->prof[name].push_back({a, b});
+    a = b = nullptr;
   }
+  ~ProfScope() { stop(); }
 };
 
 // Scratch of `bytes` (context slot, or the recorder's buffer), a device copy

@@ -837,8 +837,12 @@ void group_mac(ckks_ctx* c, int level, const std::vector<std::vector<MacTerm>>& 
 // null).  The NP ciphertexts of a term share its plaintext word, read once; a thread takes
 // two neighbouring coefficients of one limb with 16-byte loads, so every load instruction
 // moves two words and NP + 1 streams are in flight per term.
+// GM_TB threads per block: the baby-step ciphertexts of one block's 2 GM_TB coefficients
+// (every packed ciphertext, both components) stay in L2 while the masks stream past them
+constexpr int GM_TB = 128;
+
 template <int NP>
-__global__ void __launch_bounds__(KB) k_group_mac_np(const MacTermNP* __restrict__ terms, const int* __restrict__ group_start,
+__global__ void __launch_bounds__(GM_TB) k_group_mac_np(const MacTermNP* __restrict__ terms, const int* __restrict__ group_start,
                                uint64_t* const* __restrict__ outs, int l1, int accumulate, int log_n, int n_groups,
                                int xcd_order, const Mod* __restrict__ mods) {
   typedef uint64_t v2 __attribute__((ext_vector_type(2)));
@@ -855,7 +859,7 @@ __global__ void __launch_bounds__(KB) k_group_mac_np(const MacTermNP* __restrict
     jb = blockIdx.x;
     g = blockIdx.y;
   }
-  const size_t j = 2 * ((size_t)jb * KB + threadIdx.x);
+  const size_t j = 2 * ((size_t)jb * GM_TB + threadIdx.x);
   const Mod m = mods[i];
   const size_t o0 = (size_t)i * N + j, o1 = ((size_t)l1 + i) * N + j;
   uint64_t a[NP][4];   // per ciphertext: component 0 at j, j+1, component 1 at j, j+1
@@ -942,8 +946,7 @@ void group_mac_np(ckks_ctx* c, int level, int np, const std::vector<std::vector<
   if (groups.empty()) return;
   if (np < 1 || np > MacTermNP::MAX) FICGCN_THROW(EINVAL_, "shared-mask sum: 1 to 4 ciphertexts per term");
   if (outs.size() != groups.size() * np) FICGCN_THROW(EINVAL_, "group/output count mismatch");
-  if (c->N < 2 * KB) FICGCN_THROW(EINVAL_, "ring too small for the shared-mask sum");
-  ProfScope ps(c, "group_mac");
+  if (c->N < 2 * GM_TB) FICGCN_THROW(EINVAL_, "ring too small for the shared-mask sum");
   std::vector<MacTermNP> flat;
   std::vector<int> start{0};
   for (const auto& g : groups) {
@@ -959,28 +962,30 @@ void group_mac_np(ckks_ctx* c, int level, int np, const std::vector<std::vector<
   int* sd = upload(c, S_GM_START, start);
   uint64_t* const* od = upload(c, S_GM_OUT, outs);
   if (groups.size() > 65535) FICGCN_THROW(EINVAL_, "too many groups in one launch");
-  const int n_jb = c->N / (2 * KB), ng = (int)groups.size();
+  const int n_jb = c->N / (2 * GM_TB), ng = (int)groups.size();
   const bool xcd = n_jb % 8 == 0 && (size_t)n_jb * ng < ((size_t)1 << 31);
   const dim3 grid = xcd ? dim3(n_jb * ng, 1, level + 1) : dim3(n_jb, ng, level + 1);
   const int acc = accumulate ? 1 : 0;
+  ProfScope ps(c, "bsgs_inner");   // the launch alone (its tables are uploaded above)
   switch (np) {
     case 1:
-      hipLaunchKernelGGL(k_group_mac_np<1>, grid, dim3(KB), 0, c->stream, td, sd, od, level + 1, acc, c->log_n, ng,
+      hipLaunchKernelGGL(k_group_mac_np<1>, grid, dim3(GM_TB), 0, c->stream, td, sd, od, level + 1, acc, c->log_n, ng,
                          xcd ? 1 : 0, c->t.mods);
       break;
     case 2:
-      hipLaunchKernelGGL(k_group_mac_np<2>, grid, dim3(KB), 0, c->stream, td, sd, od, level + 1, acc, c->log_n, ng,
+      hipLaunchKernelGGL(k_group_mac_np<2>, grid, dim3(GM_TB), 0, c->stream, td, sd, od, level + 1, acc, c->log_n, ng,
                          xcd ? 1 : 0, c->t.mods);
       break;
     case 3:
-      hipLaunchKernelGGL(k_group_mac_np<3>, grid, dim3(KB), 0, c->stream, td, sd, od, level + 1, acc, c->log_n, ng,
+      hipLaunchKernelGGL(k_group_mac_np<3>, grid, dim3(GM_TB), 0, c->stream, td, sd, od, level + 1, acc, c->log_n, ng,
                          xcd ? 1 : 0, c->t.mods);
       break;
     default:
-      hipLaunchKernelGGL(k_group_mac_np<4>, grid, dim3(KB), 0, c->stream, td, sd, od, level + 1, acc, c->log_n, ng,
+      hipLaunchKernelGGL(k_group_mac_np<4>, grid, dim3(GM_TB), 0, c->stream, td, sd, od, level + 1, acc, c->log_n, ng,
                          xcd ? 1 : 0, c->t.mods);
   }
   HIPCHECK(hipGetLastError());
+  ps.stop();
   stream_sync(c);
 }
 
