@@ -246,25 +246,36 @@ def run_layer(prm: Params, plan: Plan, li: int, keys: ckks.Keys, cts: List[ckks.
             h = ckks.scalar_mul_acc(prm, acc, Z, [int(ops["W"][f, l]) for f in range(F)])
             outs.append(ckks.rescale(prm, ckks.rescale(prm, h)))
     else:
-        lv = st["level_in"]
-        cols = []
-        for l in range(lp.f_out):
-            acc = _zero(prm, lv, st["scale_in"] * st["sW"])
-            h = ckks.scalar_mul_acc(prm, acc, cts, [int(ops["W"][f, l]) for f in range(lp.f_in)])
-            for _ in range(st["n_rescale_comb"]):
-                h = ckks.rescale(prm, h)
-            cols.append(h)
-        outs = []
-        for g in range(-(-lp.f_out // lp.t)):
-            y = None
-            for l in range(g * lp.t, min(lp.f_out, (g + 1) * lp.t)):
-                c = l % lp.t
-                term = cols[l] if c == 0 else ckks.rotate(prm, keys, cols[l], -c * lp.B)
-                y = term if y is None else ckks.add(prm, y, term)
-            outs.append(aggregate(prm, plan, li, keys, y, ops["masks"][g], st))
+        outs = [aggregate(prm, plan, li, keys, y, ops["masks"][g], st)
+                for g, y in enumerate(combine_and_pack(prm, plan, li, keys, cts, ops, st))]
     if lp.activation:
         outs = [ckks.ct_mul_relin(prm, keys, c, c) for c in outs]
     return outs
+
+
+def combine_and_pack(prm: Params, plan: Plan, li: int, keys: ckks.Keys, cts: List[ckks.Ciphertext],
+                     ops: dict, st: dict) -> List[ckks.Ciphertext]:
+    """SpIntra-CA layer with integer-weight combination: H_l = sum_f w_{f,l} X_f, its
+    rescales, then columns g t .. g t + t - 1 packed into ciphertext g (column c moved
+    to block c by a rotation of -c B).  One packed ciphertext per g."""
+    lp = plan.layers[li]
+    lv = st["level_in"]
+    cols = []
+    for l in range(lp.f_out):
+        acc = _zero(prm, lv, st["scale_in"] * st["sW"])
+        h = ckks.scalar_mul_acc(prm, acc, cts, [int(ops["W"][f, l]) for f in range(lp.f_in)])
+        for _ in range(st["n_rescale_comb"]):
+            h = ckks.rescale(prm, h)
+        cols.append(h)
+    packed = []
+    for g in range(-(-lp.f_out // lp.t)):
+        y = None
+        for l in range(g * lp.t, min(lp.f_out, (g + 1) * lp.t)):
+            c = l % lp.t
+            term = cols[l] if c == 0 else ckks.rotate(prm, keys, cols[l], -c * lp.B)
+            y = term if y is None else ckks.add(prm, y, term)
+        packed.append(y)
+    return packed
 
 
 def aggregate_radix2(prm: Params, lp, keys, y: ckks.Ciphertext, masks: list, st: dict) -> ckks.Ciphertext:

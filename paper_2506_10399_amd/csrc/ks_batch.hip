@@ -838,10 +838,19 @@ void group_mac(ckks_ctx* c, int level, const std::vector<std::vector<MacTerm>>& 
 // two neighbouring coefficients of one limb with 16-byte loads, so every load instruction
 // moves two words and NP + 1 streams are in flight per term.
 // GM_TB threads per block: the baby-step ciphertexts of one block's 2 GM_TB coefficients
-// (every packed ciphertext, both components) stay in L2 while the masks stream past them
+// (every packed ciphertext, both components) stay in L2 while the masks stream past them.
+//
+// Products (L25 = every prime of the level below 2^50): a word w < 2^50 is split into
+// w0 = w mod 2^25 and w1 = floor(w / 2^25), both below 2^25, and
+//   x p = x0 p0 + (x0 p1 + x1 p0) 2^25 + x1 p1 2^50;
+// the three partial sums are kept in 64-bit registers, each partial product added by one
+// 32 x 32 + 64 multiply-add (every partial below 2^51, so GM_MAX_TERMS terms fit), and the
+// group's sum is assembled to 128 bits and reduced once at the end.  Otherwise (wider
+// primes) products are summed in 128 bits and reduced every four terms.
 constexpr int GM_TB = 128;
+constexpr int GM_MAX_TERMS = 8191;   // 64-bit partial sums: 8191 * 2^51 < 2^64
 
-template <int NP>
+template <int NP, bool L25>
 __global__ void __launch_bounds__(GM_TB) k_group_mac_np(const MacTermNP* __restrict__ terms, const int* __restrict__ group_start,
                                uint64_t* const* __restrict__ outs, int l1, int accumulate, int log_n, int n_groups,
                                int xcd_order, const Mod* __restrict__ mods) {
@@ -862,80 +871,141 @@ __global__ void __launch_bounds__(GM_TB) k_group_mac_np(const MacTermNP* __restr
   const size_t j = 2 * ((size_t)jb * GM_TB + threadIdx.x);
   const Mod m = mods[i];
   const size_t o0 = (size_t)i * N + j, o1 = ((size_t)l1 + i) * N + j;
-  uint64_t a[NP][4];   // per ciphertext: component 0 at j, j+1, component 1 at j, j+1
+  const int t_end = group_start[g + 1];
+  int t = group_start[g];
+  // per ciphertext, the four words of a thread: component 0 at j, j+1, component 1 at j, j+1
+  uint64_t res[NP][4];
+  if (L25) {
+    constexpr uint32_t M25 = (1u << 25) - 1;
+    uint64_t A[NP][4], B[NP][4], C[NP][4];
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) A[c][k] = B[c][k] = C[c][k] = 0;
+    auto part = [&](uint64_t& a, uint64_t& b, uint64_t& cc, uint64_t w, uint32_t p0, uint32_t p1) {
+      const uint32_t w0 = (uint32_t)w & M25, w1 = (uint32_t)(w >> 25);
+      a += (uint64_t)w0 * p0;
+      b += (uint64_t)w0 * p1;
+      b += (uint64_t)w1 * p0;
+      cc += (uint64_t)w1 * p1;
+    };
+    auto mac = [&](const v2& p, const v2 (&x)[NP], const v2 (&y)[NP]) {
+      const uint32_t px0 = (uint32_t)p.x & M25, px1 = (uint32_t)(p.x >> 25);
+      const uint32_t py0 = (uint32_t)p.y & M25, py1 = (uint32_t)(p.y >> 25);
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+        part(A[c][0], B[c][0], C[c][0], x[c].x, px0, px1);
+        part(A[c][1], B[c][1], C[c][1], x[c].y, py0, py1);
+        part(A[c][2], B[c][2], C[c][2], y[c].x, px0, px1);
+        part(A[c][3], B[c][3], C[c][3], y[c].y, py0, py1);
+      }
+    };
+    for (; t + 2 <= t_end; t += 2) {
+      const MacTermNP ta = terms[t], tb = terms[t + 1];
+      v2 pa = {1, 1}, pb = {1, 1};
+      if (ta.pt) pa = *(gv2*)(ta.pt + (size_t)i * N + j);
+      if (tb.pt) pb = *(gv2*)(tb.pt + (size_t)i * N + j);
+      v2 xa[NP], ya[NP], xb[NP], yb[NP];
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+        xa[c] = *(gv2*)(ta.ct[c] + o0);
+        ya[c] = *(gv2*)(ta.ct[c] + o1);
+        xb[c] = *(gv2*)(tb.ct[c] + o0);
+        yb[c] = *(gv2*)(tb.ct[c] + o1);
+      }
+      mac(pa, xa, ya);
+      mac(pb, xb, yb);
+    }
+    if (t < t_end) {
+      const MacTermNP ta = terms[t];
+      v2 pa = {1, 1};
+      if (ta.pt) pa = *(gv2*)(ta.pt + (size_t)i * N + j);
+      v2 xa[NP], ya[NP];
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+        xa[c] = *(gv2*)(ta.ct[c] + o0);
+        ya[c] = *(gv2*)(ta.ct[c] + o1);
+      }
+      mac(pa, xa, ya);
+    }
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        res[c][k] = reduce128((u128)A[c][k] + ((u128)B[c][k] << 25) + ((u128)C[c][k] << 50), m);
+  } else {
+    u128 s[NP][4];
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
+      res[c][0] = res[c][1] = res[c][2] = res[c][3] = 0;
+      s[c][0] = s[c][1] = s[c][2] = s[c][3] = 0;
+    }
+    auto mac = [&](const v2& p, const v2 (&x)[NP], const v2 (&y)[NP]) {
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+        s[c][0] += (u128)x[c].x * p.x;
+        s[c][1] += (u128)x[c].y * p.y;
+        s[c][2] += (u128)y[c].x * p.x;
+        s[c][3] += (u128)y[c].y * p.y;
+      }
+    };
+    auto fold = [&]() {
+#pragma unroll
+      for (int c = 0; c < NP; ++c)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          res[c][k] = add_mod(res[c][k], reduce128(s[c][k], m), m.q);
+          s[c][k] = 0;
+        }
+    };
+    // two terms' loads in flight together; products of four terms summed in 128 bits
+    // (each below 2^124 for words below 2^62) before one reduction
+    int cnt = 0;
+    for (; t + 2 <= t_end; t += 2) {
+      const MacTermNP ta = terms[t], tb = terms[t + 1];
+      v2 pa = {1, 1}, pb = {1, 1};
+      if (ta.pt) pa = *(gv2*)(ta.pt + (size_t)i * N + j);
+      if (tb.pt) pb = *(gv2*)(tb.pt + (size_t)i * N + j);
+      v2 xa[NP], ya[NP], xb[NP], yb[NP];
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+        xa[c] = *(gv2*)(ta.ct[c] + o0);
+        ya[c] = *(gv2*)(ta.ct[c] + o1);
+        xb[c] = *(gv2*)(tb.ct[c] + o0);
+        yb[c] = *(gv2*)(tb.ct[c] + o1);
+      }
+      mac(pa, xa, ya);
+      mac(pb, xb, yb);
+      if ((cnt += 2) == 4) {
+        fold();
+        cnt = 0;
+      }
+    }
+    if (t < t_end) {
+      const MacTermNP ta = terms[t];
+      v2 pa = {1, 1};
+      if (ta.pt) pa = *(gv2*)(ta.pt + (size_t)i * N + j);
+      v2 xa[NP], ya[NP];
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+        xa[c] = *(gv2*)(ta.ct[c] + o0);
+        ya[c] = *(gv2*)(ta.ct[c] + o1);
+      }
+      mac(pa, xa, ya);
+    }
+    fold();
+  }
 #pragma unroll
   for (int c = 0; c < NP; ++c) {
     uint64_t* out = outs[(size_t)g * NP + c];
     if (accumulate) {
       const v2 u = *(gv2*)(out + o0), v = *(gv2*)(out + o1);
-      a[c][0] = u.x, a[c][1] = u.y, a[c][2] = v.x, a[c][3] = v.y;
-    } else {
-      a[c][0] = a[c][1] = a[c][2] = a[c][3] = 0;
+      res[c][0] = add_mod(res[c][0], u.x, m.q);
+      res[c][1] = add_mod(res[c][1], u.y, m.q);
+      res[c][2] = add_mod(res[c][2], v.x, m.q);
+      res[c][3] = add_mod(res[c][3], v.y, m.q);
     }
-  }
-  const int t_end = group_start[g + 1];
-  int t = group_start[g];
-  u128 s[NP][4];
-#pragma unroll
-  for (int c = 0; c < NP; ++c) s[c][0] = s[c][1] = s[c][2] = s[c][3] = 0;
-  auto mac = [&](const v2& p, const v2 (&x)[NP], const v2 (&y)[NP]) {
-#pragma unroll
-    for (int c = 0; c < NP; ++c) {
-      s[c][0] += (u128)x[c].x * p.x;
-      s[c][1] += (u128)x[c].y * p.y;
-      s[c][2] += (u128)y[c].x * p.x;
-      s[c][3] += (u128)y[c].y * p.y;
-    }
-  };
-  auto fold = [&]() {
-#pragma unroll
-    for (int c = 0; c < NP; ++c)
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        a[c][k] = add_mod(a[c][k], reduce128(s[c][k], m), m.q);
-        s[c][k] = 0;
-      }
-  };
-  // two terms' loads in flight together; products of four terms summed in 128 bits
-  // (each below 2^100 for words below 2^50) before one reduction
-  int cnt = 0;
-  for (; t + 2 <= t_end; t += 2) {
-    const MacTermNP ta = terms[t], tb = terms[t + 1];
-    v2 pa = {1, 1}, pb = {1, 1};
-    if (ta.pt) pa = *(gv2*)(ta.pt + (size_t)i * N + j);
-    if (tb.pt) pb = *(gv2*)(tb.pt + (size_t)i * N + j);
-    v2 xa[NP], ya[NP], xb[NP], yb[NP];
-#pragma unroll
-    for (int c = 0; c < NP; ++c) {
-      xa[c] = *(gv2*)(ta.ct[c] + o0);
-      ya[c] = *(gv2*)(ta.ct[c] + o1);
-      xb[c] = *(gv2*)(tb.ct[c] + o0);
-      yb[c] = *(gv2*)(tb.ct[c] + o1);
-    }
-    mac(pa, xa, ya);
-    mac(pb, xb, yb);
-    if ((cnt += 2) == 4) {
-      fold();
-      cnt = 0;
-    }
-  }
-  if (t < t_end) {
-    const MacTermNP ta = terms[t];
-    v2 pa = {1, 1};
-    if (ta.pt) pa = *(gv2*)(ta.pt + (size_t)i * N + j);
-    v2 xa[NP], ya[NP];
-#pragma unroll
-    for (int c = 0; c < NP; ++c) {
-      xa[c] = *(gv2*)(ta.ct[c] + o0);
-      ya[c] = *(gv2*)(ta.ct[c] + o1);
-    }
-    mac(pa, xa, ya);
-  }
-  fold();
-#pragma unroll
-  for (int c = 0; c < NP; ++c) {
-    uint64_t* out = outs[(size_t)g * NP + c];
-    const v2 r0 = {a[c][0], a[c][1]}, r1 = {a[c][2], a[c][3]};
+    const v2 r0 = {res[c][0], res[c][1]}, r1 = {res[c][2], res[c][3]};
     *(gv2w*)(out + o0) = r0;
     *(gv2w*)(out + o1) = r1;
   }
@@ -966,24 +1036,26 @@ void group_mac_np(ckks_ctx* c, int level, int np, const std::vector<std::vector<
   const bool xcd = n_jb % 8 == 0 && (size_t)n_jb * ng < ((size_t)1 << 31);
   const dim3 grid = xcd ? dim3(n_jb * ng, 1, level + 1) : dim3(n_jb, ng, level + 1);
   const int acc = accumulate ? 1 : 0;
+  // split-limb products need every prime of the level below 2^50 and at most GM_MAX_TERMS
+  // terms per group
+  bool l25 = true;
+  for (int i = 0; i <= level; ++i) l25 = l25 && c->mod[i] < (1ull << 50);
+  for (size_t gi = 0; gi < groups.size(); ++gi) l25 = l25 && groups[gi].size() <= (size_t)GM_MAX_TERMS;
   ProfScope ps(c, "bsgs_inner");   // the launch alone (its tables are uploaded above)
-  switch (np) {
-    case 1:
-      hipLaunchKernelGGL(k_group_mac_np<1>, grid, dim3(GM_TB), 0, c->stream, td, sd, od, level + 1, acc, c->log_n, ng,
-                         xcd ? 1 : 0, c->t.mods);
-      break;
-    case 2:
-      hipLaunchKernelGGL(k_group_mac_np<2>, grid, dim3(GM_TB), 0, c->stream, td, sd, od, level + 1, acc, c->log_n, ng,
-                         xcd ? 1 : 0, c->t.mods);
-      break;
-    case 3:
-      hipLaunchKernelGGL(k_group_mac_np<3>, grid, dim3(GM_TB), 0, c->stream, td, sd, od, level + 1, acc, c->log_n, ng,
-                         xcd ? 1 : 0, c->t.mods);
-      break;
-    default:
-      hipLaunchKernelGGL(k_group_mac_np<4>, grid, dim3(GM_TB), 0, c->stream, td, sd, od, level + 1, acc, c->log_n, ng,
-                         xcd ? 1 : 0, c->t.mods);
+#define GM_LAUNCH(NPV, LV)                                                                                     \
+  hipLaunchKernelGGL((k_group_mac_np<NPV, LV>), grid, dim3(GM_TB), 0, c->stream, td, sd, od, level + 1, acc, \
+                     c->log_n, ng, xcd ? 1 : 0, c->t.mods)
+  switch (np * 2 + (l25 ? 1 : 0)) {
+    case 2: GM_LAUNCH(1, false); break;
+    case 3: GM_LAUNCH(1, true); break;
+    case 4: GM_LAUNCH(2, false); break;
+    case 5: GM_LAUNCH(2, true); break;
+    case 6: GM_LAUNCH(3, false); break;
+    case 7: GM_LAUNCH(3, true); break;
+    case 8: GM_LAUNCH(4, false); break;
+    default: GM_LAUNCH(4, true);
   }
+#undef GM_LAUNCH
   HIPCHECK(hipGetLastError());
   ps.stop();
   stream_sync(c);

@@ -9,7 +9,8 @@ from .graphs import (Graph, erdos_renyi, chung_lu, dc_sbm, sample_neighbors)
 from .features import (binary_features, uniform_features, tfidf_features,
                        gaussian_weights)
 from .configs import CONFIGS, make_workload, Workload
+from .ciphertexts import uniform_ct_words
 
 __all__ = ["Graph", "erdos_renyi", "chung_lu", "dc_sbm", "sample_neighbors",
            "binary_features", "uniform_features", "tfidf_features",
-           "gaussian_weights", "CONFIGS", "make_workload", "Workload"]
+           "gaussian_weights", "CONFIGS", "make_workload", "Workload", "uniform_ct_words"]
