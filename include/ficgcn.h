@@ -63,20 +63,30 @@ typedef struct {
 const char* ficgcn_last_error(void);
 
 /* ---------------------------------------------------------------- context */
-/* Builds the prime chain (the n_q largest primes below 2^q_bits congruent to
- * 1 mod 2N, descending, then the n_p largest below 2^p_bits), NTT tables
- * and base-conversion constants on the current HIP device.  Synchronous. */
+/* RNS-CKKS context (paper Sec. 2.1; the paper takes its parameters from its
+ * HE library, Sec. 4.1).  Builds the prime chain (the n_q largest primes
+ * below 2^q_bits congruent to 1 mod 2N, descending, then the n_p largest
+ * below 2^p_bits not already in Q), NTT tables and base-conversion constants
+ * on the host; device tables follow on the first device call.  EINVAL for
+ * log_n outside 9..17 or primes outside 20..61 bits.  *out is owned by the caller
+ * (ckks_ctx_destroy).  Synchronous. */
 ficgcn_status ckks_context_create(const ckks_params* p, ckks_ctx** out);
+/* Releases a context (host and device tables); NULL is a no-op. */
 void ckks_ctx_destroy(ckks_ctx* ctx);
-/* stream: a hipStream_t (NULL = default stream). */
+/* Every later device call on ctx is enqueued on stream, a hipStream_t
+ * (NULL = default stream); the caller keeps the stream alive. */
 ficgcn_status ckks_ctx_set_stream(ckks_ctx* ctx, void* stream);
-/* moduli_out[n_q + n_p]: Q primes then P primes. */
+/* The RNS moduli of Sec. 2.1's ciphertext modulus: moduli_out[n_q + n_p],
+ * Q primes (q_0 > q_1 > ...) then P primes.  Host only. */
 ficgcn_status ckks_ctx_moduli(const ckks_ctx* ctx, uint64_t* moduli_out);
-/* Galois element 5^(step mod M) mod 2N of a slot rotation. */
+/* Galois element 5^(step mod M) mod 2N of the slot rotation Rot(., step)
+ * of Sec. 2.1.  Host only. */
 ficgcn_status ckks_galois_element(const ckks_ctx* ctx, int64_t step, uint64_t* g_out);
-/* Waits for all work enqueued on the context's stream. */
+/* Waits for all work enqueued on the context's stream; EDEVICE carries the
+ * first asynchronous HIP error. */
 ficgcn_status ckks_sync(ckks_ctx* ctx);
-/* Kernel timing: while enabled, HIP events are recorded on the context's
+/* Measurement infrastructure (no operation of the paper).
+ * Kernel timing: while enabled, HIP events are recorded on the context's
  * stream around every launch of the instrumented kernels ("inter_fused":
  * the fused Inter-CA + combination pass, "comb_fused": the fused
  * combination of a SpIntra-CA layer,
@@ -86,7 +96,8 @@ ficgcn_status ckks_sync(ckks_ctx* ctx);
 ficgcn_status ficgcn_profile_enable(ckks_ctx* ctx, int on);
 ficgcn_status ficgcn_profile_read(ckks_ctx* ctx, const char* kernel, double* ms_total, uint64_t* launches);
 
-/* NTT autotuner: each limb's transform runs as a column pass of 2^s points
+/* NTT autotuner (execution schedule of the Sec. 2.1 transform; no operation
+ * of the paper): each limb's transform runs as a column pass of 2^s points
  * and a row pass of 2^(log_n - s) points (both between 2^4 and 2^9); times
  * every split s in {log_n/2 - 1, log_n/2, log_n/2 + 1} and workgroup width
  * pair (column pass x row pass) on 16 scratch polynomials of n_limbs limbs (a
@@ -94,62 +105,81 @@ ficgcn_status ficgcn_profile_read(ckks_ctx* ctx, const char* kernel, double* ms_
  * keeps the fastest for this context.  cols_out[3] receives (column width, row
  * width, s) (may be NULL).  Synchronous. */
 ficgcn_status ckks_ntt_autotune(ckks_ctx* ctx, uint32_t n_limbs, int32_t* cols_out);
-/* Sets the NTT schedule directly: split s (0 = log_n / 2, else both passes
+/* Sets the NTT schedule (as the autotuner would) directly: split s (0 = log_n / 2, else both passes
  * between 2^4 and 2^9 points) and the workgroup widths (1, 2, 4, 8 or 16).
  * Every schedule computes the same words.  EINVAL otherwise. */
 ficgcn_status ckks_ntt_config(ckks_ctx* ctx, int32_t split, int32_t cols_column, int32_t cols_row);
 
 /* ------------------------------------------------------------------ keys */
-/* [client] Samples the ternary secret and the switching keys (rotation keys
+/* [client] Key generation of the threat model of Sec. 2.4 (the client owns
+ * the secret; the server receives evaluation keys only) for the rotations
+ * and products of Sec. 2.1.  Samples the ternary secret and the switching keys (rotation keys
  * for every step in rot_steps, the relinearisation key if with_relin) from
  * the ChaCha20 streams of `seed`.  *client_keys holds the secret and can
  * decrypt; *eval_keys holds only switching keys (what the server receives).
  * Either output pointer may be NULL if that object is not wanted. */
 ficgcn_status ckks_keygen(ckks_ctx* ctx, uint64_t seed, const int64_t* rot_steps, size_t n_steps, int with_relin,
                           ckks_keys** client_keys, ckks_keys** eval_keys);
-/* Number of switching keys held and their tags (Galois element; 0 = relin). */
+/* Number of switching keys held and their tags (Galois element; 0 = relin).
+ * tags_out may be NULL (count only); up to cap tags written.  Host only. */
 ficgcn_status ckks_keys_tags(const ckks_keys* keys, uint64_t* tags_out, size_t cap, size_t* n_out);
-/* Copies one switching key to the host in coefficient form,
- * [beta][2][n_q + n_p][N] (b then a per digit).  Synchronous. */
+/* Copies one switching key (hybrid key switching, Sec. 2.1's rotation) to the
+ * host in coefficient form, [beta][2][n_q + n_p][N] (b then a per digit);
+ * host_out is caller-owned.  ENOKEY if the tag is absent.  Synchronous. */
 ficgcn_status ckks_keys_export(ckks_ctx* ctx, const ckks_keys* keys, uint64_t tag, uint64_t* host_out);
-/* Installs a switching key given in coefficient form (layout as export). */
+/* Installs a switching key given in coefficient form (layout as export), for
+ * a server that receives the client's evaluation keys (Sec. 2.4). */
 ficgcn_status ckks_keys_import(ckks_ctx* ctx, ckks_keys* keys, uint64_t tag, const uint64_t* host_in);
-/* An empty evaluation key set, to be filled with ckks_keys_import. */
+/* An empty evaluation key set (Sec. 2.4's server side), to be filled with
+ * ckks_keys_import; owned by the caller (ckks_keys_destroy). */
 ficgcn_status ckks_keys_create_empty(ckks_ctx* ctx, ckks_keys** out);
+/* Releases a key set (device keys, the secret of a client set); NULL is a no-op. */
 void ckks_keys_destroy(ckks_keys* keys);
 
 /* ------------------------------------------------- encode / encrypt [client] */
-/* Encodes n <= M complex slots (im may be NULL) at `scale` into a device
- * plaintext [level+1][N]: round-half-even of the scaled inverse canonical
- * embedding (FP64 FFT on the host), then residues and NTT. */
+/* CKKS encoding of Sec. 2.1: n <= M complex slots (im may be NULL) at
+ * `scale` into a caller-owned device plaintext [level+1][N]: round-half-even
+ * of the scaled inverse canonical embedding (an FP64 FFT on the device), then
+ * residues and NTT.  ESCALE if a scaled coefficient exceeds 63 bits. */
 ficgcn_status ckks_encode(ckks_ctx* ctx, const double* re, const double* im, size_t n, double scale, uint32_t level,
                           uint64_t* pt_dev);
-/* Batch form: `count` slot vectors of n doubles each (real parts only,
- * row-major), encoded on host threads into pt_dev[count][level+1][N]. */
+/* Batch form of the Sec. 2.1 encoding: `count` slot vectors of n doubles each
+ * (real parts only, row-major, host memory), encoded on the device into
+ * pt_dev[count][level+1][N]. */
 ficgcn_status ckks_encode_batch(ckks_ctx* ctx, const double* re, size_t count, size_t n, double scale, uint32_t level,
                                 uint64_t* pt_dev);
-/* Uploads a plaintext given as coefficient-form residues [level+1][N]. */
+/* Uploads a plaintext (Sec. 2.1) given as coefficient-form residues
+ * [level+1][N] (host) into a caller-owned device buffer, then NTT. */
 ficgcn_status ckks_pt_load(ckks_ctx* ctx, const uint64_t* host_coeffs, uint32_t level, uint64_t* pt_dev);
-/* ct = (-a s + e + m, a) mod Q_level with a, e from the streams of (seed, ct_id). */
+/* [client] Symmetric CKKS encryption (Sec. 2.1; the client encrypts X,
+ * Sec. 2.4): ct = (-a s + e + m, a) mod Q_level with a, e from the ChaCha20
+ * streams of (seed, ct_id).  EINVAL without the secret. */
 ficgcn_status ckks_encrypt(ckks_ctx* ctx, const ckks_keys* client_keys, const uint64_t* pt_dev, uint32_t level,
                            uint64_t seed, uint32_t ct_id, uint64_t* ct_dev);
-/* Decrypts and decodes n_slots slots (im may be NULL) at `scale`.  Synchronous. */
+/* [client] Decryption and decoding (Sec. 2.1, Sec. 2.4): n_slots slots
+ * (im may be NULL) at `scale` into host arrays.  Synchronous. */
 ficgcn_status ckks_decrypt(ckks_ctx* ctx, const ckks_keys* client_keys, const uint64_t* ct_dev, uint32_t level,
                            double scale, double* re, double* im, size_t n_slots);
 
 /* -------------------------------------------------- transfers (either side) */
-/* Uploads a ciphertext given in coefficient form [2][level+1][N]. */
+/* Uploads a ciphertext (Sec. 2.1) given in coefficient form
+ * [2][level+1][N] (host) into a caller-owned device buffer, then NTT. */
 ficgcn_status ckks_ct_load(ckks_ctx* ctx, const uint64_t* host_coeffs, uint32_t level, uint64_t* ct_dev);
-/* Downloads a ciphertext (or, with n_polys = 1, a plaintext) in coefficient
- * form [n_polys][level+1][N].  Synchronous. */
+/* Downloads a ciphertext (or, with n_polys = 1, a plaintext) of Sec. 2.1 in
+ * coefficient form [n_polys][level+1][N] into caller-owned host memory.
+ * Synchronous. */
 ficgcn_status ckks_poly_store(ckks_ctx* ctx, const uint64_t* dev, uint32_t level, uint32_t n_polys,
                               uint64_t* host_coeffs);
-/* Forward (inverse = 0) or inverse NTT in place on n_limbs limbs starting at
- * modulus index first_mod (Q primes 0..n_q-1, then P primes). */
+/* The negacyclic number-theoretic transform under every RNS-CKKS product
+ * (Sec. 2.1): forward (inverse = 0) or inverse, in place on n_limbs device
+ * limbs starting at modulus index first_mod (Q primes 0..n_q-1, then P
+ * primes); evaluation order is bit-reversed. */
 ficgcn_status ckks_ntt(ckks_ctx* ctx, uint64_t* dev, uint32_t n_limbs, uint32_t first_mod, int inverse);
 
 /* ------------------------------------------------------ evaluation [server] */
-/* Rotations of one ciphertext by each of steps[0..k): one ModUp of c1 is
+/* Rot of Sec. 2.1 (the dominant cost of SpIntra-CA, Sec. 3.3, and of the
+ * App. A overhead table), hoisted.
+ * Rotations of one ciphertext by each of steps[0..k): one ModUp of c1 is
  * shared by all k (hoisting).  Each rotation is computed as ModUp, then the
  * Galois automorphism on every extended digit, the key inner product and a
  * rounding ModDown (words equal to k single rotations).  outs[i] are k
@@ -157,28 +187,35 @@ ficgcn_status ckks_ntt(ckks_ctx* ctx, uint64_t* dev, uint32_t n_limbs, uint32_t 
  * a step's key is missing (nothing enqueued). */
 ficgcn_status ckks_rotate_hoisted(ckks_ctx* ctx, const ckks_keys* eval_keys, const uint64_t* ct_dev, uint32_t level,
                                   const int64_t* steps, size_t k, uint64_t* const* outs);
-/* n rotations Rot(cts[i], steps[i]) -> outs[i] at one level, run as one
+/* Rot of Sec. 2.1, batched over distinct ciphertexts.
+ * n rotations Rot(cts[i], steps[i]) -> outs[i] at one level, run as one
  * key-switch batch (one ModUp per distinct input pointer, one inner-product
  * launch and one ModDown sequence for all n).  Words equal n single
  * rotations.  Outputs may not alias each other or any input; ENOKEY if a
  * step's key is missing (nothing enqueued). */
 ficgcn_status ckks_rotate_batch(ckks_ctx* ctx, const ckks_keys* eval_keys, const uint64_t* const* cts, uint32_t level,
                                 const int64_t* steps, size_t n, uint64_t* const* outs);
-/* acc += sum_i pts[i] (.) cts[i]  (plaintext-ciphertext multiply-accumulate
- * of Sec. 3.3's masks and Inter-CA copies); no rescale. */
+/* PMult and Add of Sec. 2.1: acc += sum_i pts[i] (.) cts[i]
+ * (plaintext-ciphertext multiply-accumulate of Sec. 3.3's masks and
+ * Sec. 3.3.2's Inter-CA copies); every operand at `level`, caller-owned
+ * device buffers; no rescale.  The *_op form below checks levels and scales. */
 ficgcn_status ckks_pt_mul_acc(ckks_ctx* ctx, uint64_t* acc_dev, uint32_t level, const uint64_t* const* cts,
                               const uint64_t* const* pts, size_t k);
-/* acc += sum_i consts[i] * cts[i] for signed integer constants (a weight w
- * encoded at scale s is round_half_even(w * s)); no rescale. */
+/* Constant multiplication of Sec. 2.1 for the combination X W (Sec. 3.2,
+ * App. B): acc += sum_i consts[i] * cts[i] for signed integer constants (a
+ * weight w encoded at scale s is round_half_even(w * s)); no rescale. */
 ficgcn_status ckks_scalar_mul_acc(ckks_ctx* ctx, uint64_t* acc_dev, uint32_t level, const uint64_t* const* cts,
                                   const int64_t* consts, size_t k);
-/* acc += in (ciphertexts at the same level). */
+/* Add of Sec. 2.1: acc += in (ciphertexts at the same level). */
 ficgcn_status ckks_add(ckks_ctx* ctx, uint64_t* acc_dev, const uint64_t* in_dev, uint32_t level);
-/* In place: round(c / q_level) on both components; the result is the
- * ciphertext at level-1, packed as [2][level][N] at the start of the buffer. */
+/* Rescale of Sec. 2.1 (each multiplication consumes a level): in place,
+ * round(c / q_level) on both components; the result is the ciphertext at
+ * level-1, packed as [2][level][N] at the start of the buffer.  ELEVEL at
+ * level 0. */
 ficgcn_status ckks_rescale(ckks_ctx* ctx, uint64_t* ct_dev, uint32_t level);
-/* out = x * y relinearised (tensor, then the relin key switches the a1 a2
- * term); no rescale.  out may not alias x or y. */
+/* CMult of Sec. 2.1 (the x^2 activation of Sec. 4.1's models): out = x * y
+ * relinearised (tensor, then the relin key switches the a1 a2 term); no
+ * rescale.  out may not alias x or y; ENOKEY without the relin key. */
 ficgcn_status ckks_mul_relin(ckks_ctx* ctx, const ckks_keys* eval_keys, const uint64_t* x_dev, const uint64_t* y_dev,
                              uint32_t level, uint64_t* out_dev);
 
@@ -199,6 +236,53 @@ ficgcn_status ckks_mul_relin(ckks_ctx* ctx, const ckks_keys* eval_keys, const ui
 ficgcn_status ckks_mul_relin_noalloc(ckks_ctx* ctx, const ckks_keys* eval_keys, const uint64_t* x_dev,
                                      const uint64_t* y_dev, uint32_t level, uint64_t* out_dev);
 size_t ckks_mul_relin_noalloc_limit(void);
+
+/* ------------------------------------------- operands with level and scale
+ * The same operations on descriptors that carry each operand's level and
+ * scale (Sec. 2.1: a product's scale is the product of its factors' scales
+ * and each multiplication consumes a level; a rescale divides the scale by
+ * the prime it drops).  Every operand is checked before anything is
+ * enqueued: ELEVEL when an operand sits at another level than the call
+ * needs, ESCALE when a sum would add terms of different scales (relative
+ * difference above 1e-9) or a scale is not positive, EINVAL for a null
+ * buffer or a plaintext where a ciphertext is expected.  On success the
+ * output descriptors' level and scale are updated; on failure nothing is
+ * enqueued and no descriptor changes.  data stays caller-owned. */
+typedef struct {
+  uint64_t* data;    /* device buffer [n_poly][level+1][N], evaluation form */
+  uint32_t level;
+  uint32_t n_poly;   /* 2 = ciphertext, 1 = plaintext */
+  double scale;
+} ckks_operand;
+
+/* [client] ckks_encrypt (Sec. 2.1, Sec. 2.4) of a plaintext operand into
+ * ct->data; ct takes the plaintext's level and scale. */
+ficgcn_status ckks_encrypt_op(ckks_ctx* ctx, const ckks_keys* client_keys, const ckks_operand* pt, uint64_t seed,
+                              uint32_t ct_id, ckks_operand* ct);
+/* [client] ckks_decrypt at the ciphertext's own level and scale. */
+ficgcn_status ckks_decrypt_op(ckks_ctx* ctx, const ckks_keys* client_keys, const ckks_operand* ct, double* re,
+                              double* im, size_t n_slots);
+/* ckks_rotate_hoisted (Rot, Sec. 2.1): every outs[i] must be a ciphertext
+ * buffer at in's level; each takes in's scale. */
+ficgcn_status ckks_rotate_hoisted_op(ckks_ctx* ctx, const ckks_keys* eval_keys, const ckks_operand* in,
+                                     const int64_t* steps, size_t k, ckks_operand* outs);
+/* ckks_pt_mul_acc (PMult, Add, Sec. 2.1): cts and pts at acc's level; every
+ * product's scale cts[i].scale * pts[i].scale must equal acc->scale, or,
+ * when acc->scale is 0 (a fresh zero accumulator), the first product's. */
+ficgcn_status ckks_pt_mul_acc_op(ckks_ctx* ctx, ckks_operand* acc, const ckks_operand* cts, const ckks_operand* pts,
+                                 size_t k);
+/* ckks_scalar_mul_acc (Sec. 3.2's combination): constants encoded at
+ * const_scale; products' scales checked as in ckks_pt_mul_acc_op. */
+ficgcn_status ckks_scalar_mul_acc_op(ckks_ctx* ctx, ckks_operand* acc, const ckks_operand* cts, const int64_t* consts,
+                                     double const_scale, size_t k);
+/* ckks_add (Sec. 2.1): equal levels and scales. */
+ficgcn_status ckks_add_op(ckks_ctx* ctx, ckks_operand* acc, const ckks_operand* in);
+/* ckks_rescale (Sec. 2.1): level -> level - 1, scale -> scale / q_level. */
+ficgcn_status ckks_rescale_op(ckks_ctx* ctx, ckks_operand* ct);
+/* ckks_mul_relin (CMult, Sec. 2.1): x, y and out at one level; out takes
+ * x.scale * y.scale. */
+ficgcn_status ckks_mul_relin_op(ckks_ctx* ctx, const ckks_keys* eval_keys, const ckks_operand* x,
+                                const ckks_operand* y, ckks_operand* out);
 
 /* ------------------------------------------------------------ plan [server] */
 /* Plan options. */
@@ -236,7 +320,11 @@ typedef struct {
                            of the chain; the client encrypts at plan info level_in of layer 0 */
 } ficgcn_plan_opts;
 
-/* Builds the plan of an n_layers-layer GCN over the normalised adjacency
+/* The server's plan of the method (Sec. 3.1's workflow): latency-aware
+ * packing (Sec. 3.2, App. B), aggregation mode per layer (Sec. 3.3.2, App.
+ * B), SpIntra-CA shift routing (Sec. 3.3, 3.3.1) and node order (Sec. 3.4,
+ * Alg. 1) for the GCN of Sec. 2.2.
+ * Builds the plan of an n_layers-layer GCN over the normalised adjacency
  * A_hat given as CSR (row v: columns col[rowptr[v]..rowptr[v+1]) with values
  * val, the diagonal included): node order, per-layer aggregation mode,
  * packing, shift routing, scale schedule and integer weights.  weights[l]
@@ -246,16 +334,20 @@ typedef struct {
 ficgcn_status ficgcn_plan_create(ckks_ctx* ctx, const int32_t* rowptr, const int32_t* col, const double* val,
                                  uint32_t n_v, const uint32_t* dims, uint32_t n_layers, const double* const* weights,
                                  const ficgcn_plan_opts* opts, ficgcn_plan** out);
+/* Releases a plan with its operands and graphs; NULL is a no-op. */
 void ficgcn_plan_destroy(ficgcn_plan* plan);
-/* The node order: pi_out[v] = slot of node v inside a column block (the
- * client packs its inputs in this order, paper App. B). */
+/* The node order of Sec. 3.4 / Alg. 1: pi_out[v] (n_v int32, host) = slot of
+ * node v inside a column block (the client packs its inputs in this order,
+ * App. B's node order back propagation). */
 ficgcn_status ficgcn_plan_node_order(const ficgcn_plan* plan, int32_t* pi_out);
 /* Inter-CA copy structure of layer `layer` (the client builds its encrypted
  * copies from it, paper Sec. 3.3.2): src_out[k * n_v + v] = the node whose
  * features copy k holds at node v's slot, -1 for none; copy 0 is the node
  * itself.  K = info "K". */
 ficgcn_status ficgcn_plan_copy_sources(const ficgcn_plan* plan, uint32_t layer, int32_t* src_out);
-/* Rotation steps whose keys the client must generate (sorted, in [1, M)). */
+/* Rotation steps of the plan's Rot operations (Sec. 3.3's SpIntra-CA shifts,
+ * Sec. 3.2's packing folds), whose keys the client must generate (Sec. 2.4):
+ * sorted, in [1, M); steps_out may be NULL (count only). */
 ficgcn_status ficgcn_plan_rot_steps(const ficgcn_plan* plan, int64_t* steps_out, size_t cap, size_t* n_out);
 /* Plan description: per layer {kind, f_in, f_out, K, t, B, family, G,
  * n_shifts, level_in, level_out, n_in_cts, n_out_cts, pack (1 = the case-1
@@ -270,11 +362,15 @@ ficgcn_status ficgcn_plan_rot_steps(const ficgcn_plan* plan, int64_t* steps_out,
  * products with the K adjacency plaintexts merge into exactly the diagonal
  * SpIntra-CA form. */
 ficgcn_status ficgcn_plan_info(const ficgcn_plan* plan, int64_t* info_out, double* scales_out, uint32_t* n_layers);
-/* Shifts of layer `layer` (SpIntra-CA), sorted. */
+/* Shifts pi(u) - pi(v) routed by layer `layer`'s SpIntra-CA aggregation
+ * (Sec. 3.3, shortest way round the ring per Sec. 3.3.1's AOO), sorted. */
 ficgcn_status ficgcn_plan_shifts(const ficgcn_plan* plan, uint32_t layer, int64_t* out, size_t cap, size_t* n_out);
-/* Integer weights of a layer as the plan encodes them (round_half_even(w * sW)). */
+/* Integer weights of a layer's combination (Sec. 3.2's X W) as the plan
+ * encodes them: round_half_even(w * sW), dims[l] x dims[l+1] int64. */
 ficgcn_status ficgcn_plan_weights_int(const ficgcn_plan* plan, uint32_t layer, int64_t* out);
-/* Number of plaintext operands of a layer and the slot vector of operand i
+/* The plaintext operands of a layer: Sec. 3.3's masks or Sec. 3.3.2's
+ * Inter-CA adjacency plaintexts.
+ * Number of plaintext operands of a layer and the slot vector of operand i
  * (M doubles): Inter-CA adjacency plaintext of copy i, or SpIntra-CA mask i
  * (families 1 and 2: packed ciphertext i / n_shifts, shift index
  * i % n_shifts; family 3: see ficgcn_plan_radix2_stats). */
@@ -296,22 +392,29 @@ ficgcn_status ficgcn_plan_operand_level(const ficgcn_plan* plan, uint32_t layer,
  * is mask i % (masks per packed ciphertext) of packed ciphertext
  * i / (masks per packed ciphertext).  EPLAN for other layers. */
 ficgcn_status ficgcn_plan_radix2_stats(const ficgcn_plan* plan, uint32_t layer, int64_t* out);
-/* Encodes every operand with the library's encoder.  Synchronous. */
+/* Encodes every operand (Sec. 2.1's encoding of the masks and adjacency
+ * plaintexts) with the library's device encoder.  Synchronous. */
 ficgcn_status ficgcn_plan_encode(ckks_ctx* ctx, ficgcn_plan* plan);
-/* Installs operand i of a layer from coefficient-form residues [level+1][N]
- * at the operand's level (ficgcn_plan_operand_level), for operands encoded
- * elsewhere. */
+/* Installs operand i of a layer (Sec. 3.3's masks, Sec. 3.3.2's plaintexts)
+ * from coefficient-form host residues [level+1][N] at the operand's level
+ * (ficgcn_plan_operand_level), for operands encoded elsewhere.  EINVAL for an
+ * index out of range. */
 ficgcn_status ficgcn_plan_load_operand(ckks_ctx* ctx, ficgcn_plan* plan, uint32_t layer, size_t i,
                                        const uint64_t* host_coeffs);
 
-/* Fills every operand of the plan with uniform residues drawn on the device
+/* Measurement only (no operation of the paper).
+ * Fills every operand of the plan with uniform residues drawn on the device
  * (ChaCha20 stream (6, layer * 2^20 + operand, limb) of `seed`, one the
  * scheme never uses).  For latency measurement only: the layer runs exactly
  * as with encoded operands, but its words mean nothing. */
 ficgcn_status ficgcn_plan_fill_operands(ckks_ctx* ctx, ficgcn_plan* plan, uint64_t seed);
 
-/* Runs layer `layer` of the plan (combination, packing, aggregation,
- * rescales and the x^2 activation as the plan schedules them).
+/* One encrypted GCN layer X' = A_hat X W (Sec. 2.2, the problem statement of
+ * Sec. 3): Inter-CA (Sec. 3.3.2) or SpIntra-CA (Sec. 3.3) aggregation, the
+ * combination and packing of Sec. 3.2 / App. B, rescales (Sec. 2.1) and the
+ * x^2 activation, as the plan schedules them.  Server side (Sec. 2.4):
+ * evaluation keys only; ENOKEY if a key is missing, EPLAN if the buffers do
+ * not match the plan (counts, levels), nothing enqueued then.
  * Inputs: Inter-CA first layer: K*F client ciphertexts, copy k of column f at
  * index k*F + f; later / SpIntra-CA layers: the previous layer's outputs.
  * mode 0 = one library operation at a time ("plain"), mode 1 = fused,
@@ -359,7 +462,9 @@ ficgcn_status ficgcn_plan_pack_inputs(ckks_ctx* ctx, ficgcn_plan* plan, uint32_t
 /* Number of floats ficgcn_candidate_features writes. */
 #define FICGCN_N_FEATURES 24
 
-/* Enumerates the candidate options for this graph size and model: every
+/* Candidates of Sec. 3.2's packing (t), Sec. 3.4's NOO (on/off, TH) and the
+ * routing family.
+ * Enumerates the candidate options for this graph size and model: every
  * feasible t, NOO off (when the graph fits one column block) or on with TH
  * in {64, 256, 1024, 4096} below n_v (plus TH = n_v), families 1, 2 and 4;
  * the other fields are copied from base.  Writes up to cap entries, *n_out =
@@ -367,14 +472,18 @@ ficgcn_status ficgcn_plan_pack_inputs(ckks_ctx* ctx, ficgcn_plan* plan, uint32_t
 ficgcn_status ficgcn_plan_candidates(uint32_t n_v, const uint32_t* dims, uint32_t n_layers, uint32_t log_n,
                                      const ficgcn_plan_opts* base, ficgcn_plan_opts* out, size_t cap,
                                      size_t* n_out);
-/* Local-adjacency features of one candidate, computed from the CSR graph
+/* Features for the learned cost model (the paper quantifies such effects by
+ * its factor c, Sec. 3.3.2, and notes that conflicts resist a closed form,
+ * App. C).
+ * Local-adjacency features of one candidate, computed from the CSR graph
  * (as ficgcn_plan_create takes it) without building the plan: degree
  * statistics, locality of the given node order, shift counts of the
  * identity order, and the candidate's t, B, TH, family.  Host only; out
  * holds FICGCN_N_FEATURES floats. */
 ficgcn_status ficgcn_candidate_features(const int32_t* rowptr, const int32_t* col, uint32_t n_v, const uint32_t* dims,
                                         uint32_t n_layers, uint32_t log_n, const ficgcn_plan_opts* opts, float* out);
-/* Analytic judge: algorithmic HBM bytes of one batched inference of the
+/* Analytic judge in the role of App. B's latency-aware objective, in bytes:
+ * algorithmic HBM bytes of one batched inference of the
  * plan (inputs, keys, masks and outputs of every operation, per the key
  * switching, MAC and rescale byte counts), as a double.  Host only. */
 ficgcn_status ficgcn_plan_cost(const ficgcn_plan* plan, double* bytes_out);
@@ -388,7 +497,8 @@ typedef struct {
   double build_seconds;    /* host time spent building candidate plans */
 } ficgcn_search_stats;
 
-/* Picks the options of the plan to build.  model == NULL: exhaustive
+/* The packing / node-order search of Sec. 3.2 and Sec. 3.4 (App. B's
+ * objective as the judge).  Picks the options of the plan to build.  model == NULL: exhaustive
  * analytic search (every candidate built and judged).  Otherwise the model
  * predicts each candidate's latency from its features, the `keep` fastest
  * predictions are built and judged, and the judge's best of those wins

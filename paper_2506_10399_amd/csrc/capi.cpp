@@ -1,6 +1,7 @@
 // extern "C" entry points: argument validation, then the device routines.
 // No exception crosses the boundary; failures return a status and leave a
 // thread-local message.
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -581,6 +582,157 @@ ficgcn_status ckks_mul_relin(ckks_ctx* ctx, const ckks_keys* eval_keys, const ui
     modup(ctx, d + (size_t)2 * l1 * N, level, D);
     keymac(ctx, acc, D, rk, level, 1);
     moddown(ctx, acc, level, out_dev, d, 1, d + (size_t)l1 * N);
+  });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- operands
+// Level and scale checks of the descriptor forms; nothing touches the device
+// before they pass.
+static void check_op(const ckks_ctx* c, const ckks_operand* op, uint32_t n_poly, const char* what) {
+  REQUIRE(c != nullptr, EINVAL_, "null context");
+  REQUIRE(op != nullptr && op->data != nullptr, EINVAL_, std::string("null ") + what);
+  REQUIRE(op->n_poly == n_poly, EINVAL_,
+          std::string(what) + (n_poly == 2 ? " is not a ciphertext (n_poly != 2)" : " is not a plaintext (n_poly != 1)"));
+  check_level(c, op->level);
+  REQUIRE(op->scale > 0.0 && std::isfinite(op->scale), ESCALE_, std::string(what) + ": scale must be positive");
+}
+
+static void same_level(const ckks_operand* a, const ckks_operand* b, const char* what) {
+  REQUIRE(a->level == b->level, ELEVEL_,
+          std::string(what) + ": level " + std::to_string(b->level) + " against " + std::to_string(a->level));
+}
+
+static bool scale_eq(double a, double b) { return std::fabs(a - b) <= 1e-9 * std::fabs(a); }
+
+// acc's scale: 0 = fresh (takes the first product's), else every product must carry it
+static double product_scale(const ckks_operand* acc, double first, const char* what) {
+  if (acc->scale == 0.0) return first;
+  REQUIRE(scale_eq(acc->scale, first), ESCALE_,
+          std::string(what) + ": product scale " + std::to_string(first) + " against accumulator " +
+              std::to_string(acc->scale));
+  return acc->scale;
+}
+
+extern "C" {
+
+ficgcn_status ckks_encrypt_op(ckks_ctx* ctx, const ckks_keys* client_keys, const ckks_operand* pt, uint64_t seed,
+                              uint32_t ct_id, ckks_operand* ct) {
+  return guard([&] {
+    check_op(ctx, pt, 1, "plaintext");
+    REQUIRE(ct && ct->data && ct->n_poly == 2, EINVAL_, "output is not a ciphertext buffer");
+    const ficgcn_status st = ckks_encrypt(ctx, client_keys, pt->data, pt->level, seed, ct_id, ct->data);
+    if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
+    ct->level = pt->level;
+    ct->scale = pt->scale;
+  });
+}
+
+ficgcn_status ckks_decrypt_op(ckks_ctx* ctx, const ckks_keys* client_keys, const ckks_operand* ct, double* re,
+                              double* im, size_t n_slots) {
+  return guard([&] {
+    check_op(ctx, ct, 2, "ciphertext");
+    const ficgcn_status st = ckks_decrypt(ctx, client_keys, ct->data, ct->level, ct->scale, re, im, n_slots);
+    if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
+  });
+}
+
+ficgcn_status ckks_rotate_hoisted_op(ckks_ctx* ctx, const ckks_keys* eval_keys, const ckks_operand* in,
+                                     const int64_t* steps, size_t k, ckks_operand* outs) {
+  return guard([&] {
+    check_op(ctx, in, 2, "input ciphertext");
+    REQUIRE(k == 0 || (steps && outs), EINVAL_, "null argument");
+    std::vector<uint64_t*> o(k);
+    for (size_t i = 0; i < k; ++i) {
+      REQUIRE(outs[i].data && outs[i].n_poly == 2, EINVAL_, "output " + std::to_string(i) + " is not a ciphertext");
+      REQUIRE(outs[i].level == in->level, ELEVEL_, "output " + std::to_string(i) + " is at another level");
+      o[i] = outs[i].data;
+    }
+    const ficgcn_status st = ckks_rotate_hoisted(ctx, eval_keys, in->data, in->level, steps, k, o.data());
+    if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
+    for (size_t i = 0; i < k; ++i) outs[i].scale = in->scale;
+  });
+}
+
+ficgcn_status ckks_pt_mul_acc_op(ckks_ctx* ctx, ckks_operand* acc, const ckks_operand* cts, const ckks_operand* pts,
+                                 size_t k) {
+  return guard([&] {
+    check_op(ctx, acc, 2, "accumulator");
+    REQUIRE(k == 0 || (cts && pts), EINVAL_, "null argument");
+    double sc = acc->scale;
+    std::vector<const uint64_t*> c(k), p(k);
+    for (size_t i = 0; i < k; ++i) {
+      check_op(ctx, &cts[i], 2, "ciphertext");
+      check_op(ctx, &pts[i], 1, "plaintext");
+      same_level(acc, &cts[i], "ciphertext");
+      same_level(acc, &pts[i], "plaintext");
+      const ckks_operand cur{acc->data, acc->level, 2, sc};
+      sc = product_scale(&cur, cts[i].scale * pts[i].scale, "pt_mul_acc");
+      c[i] = cts[i].data;
+      p[i] = pts[i].data;
+    }
+    const ficgcn_status st = ckks_pt_mul_acc(ctx, acc->data, acc->level, c.data(), p.data(), k);
+    if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
+    acc->scale = sc;
+  });
+}
+
+ficgcn_status ckks_scalar_mul_acc_op(ckks_ctx* ctx, ckks_operand* acc, const ckks_operand* cts, const int64_t* consts,
+                                     double const_scale, size_t k) {
+  return guard([&] {
+    check_op(ctx, acc, 2, "accumulator");
+    REQUIRE(k == 0 || (cts && consts), EINVAL_, "null argument");
+    REQUIRE(const_scale > 0.0 && std::isfinite(const_scale), ESCALE_, "constant scale must be positive");
+    double sc = acc->scale;
+    std::vector<const uint64_t*> c(k);
+    for (size_t i = 0; i < k; ++i) {
+      check_op(ctx, &cts[i], 2, "ciphertext");
+      same_level(acc, &cts[i], "ciphertext");
+      const ckks_operand cur{acc->data, acc->level, 2, sc};
+      sc = product_scale(&cur, cts[i].scale * const_scale, "scalar_mul_acc");
+      c[i] = cts[i].data;
+    }
+    const ficgcn_status st = ckks_scalar_mul_acc(ctx, acc->data, acc->level, c.data(), consts, k);
+    if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
+    acc->scale = sc;
+  });
+}
+
+ficgcn_status ckks_add_op(ckks_ctx* ctx, ckks_operand* acc, const ckks_operand* in) {
+  return guard([&] {
+    check_op(ctx, acc, 2, "accumulator");
+    check_op(ctx, in, 2, "ciphertext");
+    same_level(acc, in, "ciphertext");
+    REQUIRE(scale_eq(acc->scale, in->scale), ESCALE_,
+            "add: scale " + std::to_string(in->scale) + " against " + std::to_string(acc->scale));
+    const ficgcn_status st = ckks_add(ctx, acc->data, in->data, acc->level);
+    if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
+  });
+}
+
+ficgcn_status ckks_rescale_op(ckks_ctx* ctx, ckks_operand* ct) {
+  return guard([&] {
+    check_op(ctx, ct, 2, "ciphertext");
+    REQUIRE(ct->level >= 1, ELEVEL_, "rescale at level 0");
+    const ficgcn_status st = ckks_rescale(ctx, ct->data, ct->level);
+    if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
+    ct->scale /= (double)ctx->mod[ct->level];
+    ct->level -= 1;
+  });
+}
+
+ficgcn_status ckks_mul_relin_op(ckks_ctx* ctx, const ckks_keys* eval_keys, const ckks_operand* x,
+                                const ckks_operand* y, ckks_operand* out) {
+  return guard([&] {
+    check_op(ctx, x, 2, "x");
+    check_op(ctx, y, 2, "y");
+    same_level(x, y, "y");
+    REQUIRE(out && out->data && out->n_poly == 2, EINVAL_, "output is not a ciphertext buffer");
+    REQUIRE(out->level == x->level, ELEVEL_, "output is at another level");
+    const ficgcn_status st = ckks_mul_relin(ctx, eval_keys, x->data, y->data, x->level, out->data);
+    if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
+    out->scale = x->scale * y->scale;
   });
 }
 

@@ -41,6 +41,11 @@ class PlanOpts(ctypes.Structure):
                 ("agg_c", ctypes.c_double), ("low_level", ctypes.c_int32)]
 
 
+class Operand(ctypes.Structure):
+    """ckks_operand: a device buffer with its level and scale (the library checks them)."""
+    _fields_ = [("data", c_vp), ("level", ctypes.c_uint32), ("n_poly", ctypes.c_uint32), ("scale", ctypes.c_double)]
+
+
 class SearchStats(ctypes.Structure):
     _fields_ = [("n_candidates", ctypes.c_uint32), ("n_built", ctypes.c_uint32), ("best_cost", ctypes.c_double),
                 ("build_seconds", ctypes.c_double)]
@@ -104,6 +109,14 @@ _SIGS = {
     "ckks_mul_relin": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.c_uint32, c_vp]),
     "ckks_mul_relin_noalloc": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.c_uint32, c_vp]),
     "ckks_mul_relin_noalloc_limit": (ctypes.c_size_t, []),
+    "ckks_encrypt_op": (ctypes.c_int, [c_vp, c_vp, ctypes.POINTER(Operand), ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(Operand)]),
+    "ckks_decrypt_op": (ctypes.c_int, [c_vp, c_vp, ctypes.POINTER(Operand), c_vp, c_vp, ctypes.c_size_t]),
+    "ckks_rotate_hoisted_op": (ctypes.c_int, [c_vp, c_vp, ctypes.POINTER(Operand), c_vp, ctypes.c_size_t, ctypes.POINTER(Operand)]),
+    "ckks_pt_mul_acc_op": (ctypes.c_int, [c_vp, ctypes.POINTER(Operand), ctypes.POINTER(Operand), ctypes.POINTER(Operand), ctypes.c_size_t]),
+    "ckks_scalar_mul_acc_op": (ctypes.c_int, [c_vp, ctypes.POINTER(Operand), ctypes.POINTER(Operand), c_vp, ctypes.c_double, ctypes.c_size_t]),
+    "ckks_add_op": (ctypes.c_int, [c_vp, ctypes.POINTER(Operand), ctypes.POINTER(Operand)]),
+    "ckks_rescale_op": (ctypes.c_int, [c_vp, ctypes.POINTER(Operand)]),
+    "ckks_mul_relin_op": (ctypes.c_int, [c_vp, c_vp, ctypes.POINTER(Operand), ctypes.POINTER(Operand), ctypes.POINTER(Operand)]),
     "ficgcn_plan_create": (ctypes.c_int, [c_vp, c_vp, c_vp, c_vp, ctypes.c_uint32, c_vp, ctypes.c_uint32, c_vp,
                                           ctypes.POINTER(PlanOpts), ctypes.POINTER(c_vp)]),
     "ficgcn_plan_destroy": (None, [c_vp]),
@@ -372,6 +385,51 @@ class Context:
     def ckks_mul_relin_noalloc(self, eval_keys: "Keys", x, y, level: int, out):
         _check(lib().ckks_mul_relin_noalloc(self.h, eval_keys.h, _ptr(x), _ptr(y), level, _ptr(out)))
         return out
+
+    # ---- the same operations on level/scale descriptors (Operand); the library
+    # checks levels and scales and updates the outputs' descriptors
+    @staticmethod
+    def operand(buf, level: int, scale: float, n_poly: int = 2) -> Operand:
+        return Operand(_ptr(buf), level, n_poly, scale)
+
+    @staticmethod
+    def _ops(xs) -> ctypes.Array:
+        arr = (Operand * max(1, len(xs)))()
+        for i, x in enumerate(xs):
+            arr[i] = x
+        return arr
+
+    def ckks_encrypt_op(self, client_keys: "Keys", pt: Operand, seed: int, ct_id: int, ct: Operand):
+        _check(lib().ckks_encrypt_op(self.h, client_keys.h, ctypes.byref(pt), seed, ct_id, ctypes.byref(ct)))
+
+    def ckks_decrypt_op(self, client_keys: "Keys", ct: Operand, n_slots: int) -> np.ndarray:
+        re = np.zeros(n_slots)
+        im = np.zeros(n_slots)
+        _check(lib().ckks_decrypt_op(self.h, client_keys.h, ctypes.byref(ct), _ptr(re), _ptr(im), n_slots))
+        return re + 1j * im
+
+    def ckks_rotate_hoisted_op(self, eval_keys: "Keys", ct: Operand, steps: Sequence[int], outs: List[Operand]):
+        steps = np.ascontiguousarray(np.array(list(steps), dtype=np.int64))
+        arr = self._ops(outs)
+        _check(lib().ckks_rotate_hoisted_op(self.h, eval_keys.h, ctypes.byref(ct), _ptr(steps), len(steps), arr))
+        for i in range(len(outs)):
+            outs[i].level, outs[i].scale = arr[i].level, arr[i].scale
+
+    def ckks_pt_mul_acc_op(self, acc: Operand, cts: List[Operand], pts: List[Operand]):
+        _check(lib().ckks_pt_mul_acc_op(self.h, ctypes.byref(acc), self._ops(cts), self._ops(pts), len(cts)))
+
+    def ckks_scalar_mul_acc_op(self, acc: Operand, cts: List[Operand], consts, const_scale: float):
+        c = np.ascontiguousarray(np.array(list(consts), dtype=np.int64))
+        _check(lib().ckks_scalar_mul_acc_op(self.h, ctypes.byref(acc), self._ops(cts), _ptr(c), const_scale, len(cts)))
+
+    def ckks_add_op(self, acc: Operand, x: Operand):
+        _check(lib().ckks_add_op(self.h, ctypes.byref(acc), ctypes.byref(x)))
+
+    def ckks_rescale_op(self, ct: Operand):
+        _check(lib().ckks_rescale_op(self.h, ctypes.byref(ct)))
+
+    def ckks_mul_relin_op(self, eval_keys: "Keys", x: Operand, y: Operand, out: Operand):
+        _check(lib().ckks_mul_relin_op(self.h, eval_keys.h, ctypes.byref(x), ctypes.byref(y), ctypes.byref(out)))
 
 
 class Keys:

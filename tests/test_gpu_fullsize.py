@@ -117,7 +117,7 @@ def test_first_layer_sparse_inputs_bit_exact(name):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("name", ["cora", "citeseer"])
+@pytest.mark.parametrize("name", NAMES)
 def test_second_layer_full_size_words(name):
     """Second layer at the full size: the digests of the GPU's output words (plain,
     batched, graph capture and replay) equal the oracle's."""

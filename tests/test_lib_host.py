@@ -370,3 +370,36 @@ def test_lowest_level_schedule_matches_oracle(fg, name, kw, fp):
     for d, st in zip(p.ficgcn_plan_info(), sched):
         assert (d["level_in"], d["level_out"]) == (st["level_in"], st["level_out"])
         assert d["scale_in"] == st["scale_in"] and d["scale_out"] == st["scale_out"] and d["sW"] == st["sW"]
+
+
+def test_operand_descriptors_checked_before_any_device_work(fg):
+    """Level and scale checks of the descriptor calls (no GPU: every case fails
+    its checks, so nothing reaches the device, and no descriptor changes)."""
+    ctx = fg.Context(13, 4, 50, 1, 60)
+    fake = 1 << 40                                   # never dereferenced
+    op = lambda lv, sc, n=2: fg.Operand(fake, lv, n, sc)
+
+    def status(f, *a):
+        with pytest.raises(fg.FicgcnError) as e:
+            f(*a)
+        return e.value.status
+
+    acc = op(3, 2.0 ** 80)
+    assert status(ctx.ckks_pt_mul_acc_op, acc, [op(2, 2.0 ** 40)], [op(2, 2.0 ** 40, 1)]) == -2    # ELEVEL
+    assert status(ctx.ckks_pt_mul_acc_op, acc, [op(3, 2.0 ** 40)], [op(3, 2.0 ** 40, 2)]) == -1    # not a plaintext
+    assert status(ctx.ckks_pt_mul_acc_op, acc, [op(3, 2.0 ** 40)], [op(3, 2.0 ** 41, 1)]) == -3    # ESCALE
+    assert (acc.level, acc.scale) == (3, 2.0 ** 80)
+    fresh = op(3, 0.0)                               # a fresh accumulator takes the first product's scale,
+    assert status(ctx.ckks_pt_mul_acc_op, fresh,     # every later product must carry it
+                  [op(3, 2.0 ** 40), op(3, 2.0 ** 40)], [op(3, 2.0 ** 40, 1), op(3, 2.0 ** 39, 1)]) == -3
+    assert status(ctx.ckks_scalar_mul_acc_op, acc, [op(3, 2.0 ** 40)], [5], 2.0 ** 39) == -3
+    assert status(ctx.ckks_scalar_mul_acc_op, acc, [op(3, 2.0 ** 40)], [5], -1.0) == -3
+    assert status(ctx.ckks_add_op, op(3, 2.0 ** 40), op(3, 2.0 ** 40 * (1 + 1e-6))) == -3
+    assert status(ctx.ckks_add_op, op(3, 2.0 ** 40), op(2, 2.0 ** 40)) == -2
+    assert status(ctx.ckks_rescale_op, op(0, 2.0 ** 40)) == -2
+    assert status(ctx.ckks_rescale_op, op(4, 2.0 ** 40)) == -2           # beyond the 4-prime chain
+    assert status(ctx.ckks_mul_relin_op, fg.Keys(ctx, None), op(3, 2.0 ** 40), op(2, 2.0 ** 40), op(3, 0.0)) == -2
+    outs = [op(3, 0.0), op(2, 0.0)]
+    assert status(ctx.ckks_rotate_hoisted_op, fg.Keys(ctx, None), op(3, 2.0 ** 40), [1, 2], outs) == -2
+    assert [(o.level, o.scale) for o in outs] == [(3, 0.0), (2, 0.0)]
+    assert status(ctx.ckks_decrypt_op, fg.Keys(ctx, None), op(3, 2.0 ** 40, 1), 4) == -1
