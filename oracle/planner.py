@@ -37,7 +37,7 @@ from __future__ import annotations
 import math
 from collections import deque
 from dataclasses import dataclass, field
-from typing import List, Optional, Sequence
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -211,8 +211,26 @@ def interleave_slots(sizes: Sequence[int], B: int) -> List[List[int]]:
     return slots
 
 
-def noo_place(rows, regions, slots, M: int, wrap: bool) -> np.ndarray:
-    """Stage 3 of Alg. 1 (conflict-least search): greedy placement minimising new shifts."""
+def demand_cells(s: int, delta: int, M: int) -> List[Tuple[int, int]]:
+    """The (round, slot) cells a radix-2 demand occupies (Sec. 3.3): it starts at slot s
+    and, in round r, moves by sign(delta) 2^r when bit r of |delta| is set; after each
+    round r below its highest bit it still travels and sits at
+    s - sign (|delta| mod 2^(r+1)) (mod M); in the round of its highest bit it arrives
+    and leaves the working ciphertext."""
+    mag, sg = abs(delta), (1 if delta > 0 else -1)
+    return [(r, (s - sg * (mag % (1 << (r + 1)))) % M) for r in range(max(0, mag.bit_length() - 1))]
+
+
+def noo_place(rows, regions, slots, M: int, wrap: bool, objective: str = "shifts") -> np.ndarray:
+    """Stage 3 of Alg. 1 (conflict-least search): nodes in BFS order, each at the free
+    slot of its region with the least cost (ties -> lowest slot).  objective "shifts"
+    (the diagonal and baby-step/giant-step forms, which pay per distinct shift): the
+    number of shifts the node's demands add to the plan.  objective "conflicts" (the
+    radix-2 form, whose extra working ciphertexts come from slot conflicts, Sec. 3.3):
+    the number of (round, slot) cells where the node's demands with already placed
+    nodes meet a placed demand of another source node (demand_cells)."""
+    if objective not in ("shifts", "conflicts"):
+        raise ValueError(objective)
     n = len(rows)
     out_nb = [[u for u, _ in row if u != v] for v, row in enumerate(rows)]   # v needs u
     in_nb = [[] for _ in range(n)]                                           # v needs x: x's in
@@ -221,14 +239,54 @@ def noo_place(rows, regions, slots, M: int, wrap: bool) -> np.ndarray:
             in_nb[u].append(v)
     pi = np.full(n, -1, dtype=np.int64)
     shiftset = set()
+    R = M.bit_length()
+    occ = np.full((R, M), -1, dtype=np.int64)       # source node per (round, slot); -2: several
+
+    def occupy(src, s_, delta):
+        for r, c in demand_cells(s_, delta, M):
+            cur = occ[r, c]
+            occ[r, c] = src if cur == -1 else (cur if cur == src else -2)
 
     def add_shifts(x):
         for u in out_nb[x]:
             if pi[u] >= 0:
-                shiftset.add(reduce_shift(int(pi[u] - pi[x]), M, wrap))
+                d = reduce_shift(int(pi[u] - pi[x]), M, wrap)
+                shiftset.add(d)
+                if objective == "conflicts":
+                    occupy(u, int(pi[u]), d)
         for v in in_nb[x]:
             if pi[v] >= 0:
-                shiftset.add(reduce_shift(int(pi[x] - pi[v]), M, wrap))
+                d = reduce_shift(int(pi[x] - pi[v]), M, wrap)
+                shiftset.add(d)
+                if objective == "conflicts":
+                    occupy(x, int(pi[x]), d)
+
+    def red(D):
+        if wrap:
+            D = D % M
+            D = np.where(D > M // 2, D - M, D)
+        return D
+
+    def conflict_cost(x, pos):
+        cost = np.zeros(len(pos), dtype=np.int64)
+
+        def walk(src, s_, D):
+            mag, sg = np.abs(D), np.where(D > 0, 1, -1)
+            for r in range(R):
+                live = (mag >> (r + 1)) > 0                  # still travelling after round r
+                if not live.any():
+                    break
+                c = (s_ - sg * (mag % (1 << (r + 1)))) % M
+                o = occ[r, c]
+                cost[:] += live & (o != -1) & (o != src)
+
+        for u in out_nb[x]:
+            if pi[u] >= 0:                                   # demand u -> x
+                walk(u, int(pi[u]), red(pi[u] - pos))
+        for v in in_nb[x]:
+            if pi[v] >= 0:                                   # demand x -> v
+                walk(x, pos, red(pos - pi[v]))
+        return cost
 
     for region, sl in zip(regions, slots):
         free = np.array(sl, dtype=np.int64)
@@ -240,36 +298,37 @@ def noo_place(rows, regions, slots, M: int, wrap: bool) -> np.ndarray:
         for x in region[1:]:
             cand = np.nonzero(~taken)[0]
             pos = free[cand]
-            rows_d = []
-            for u in out_nb[x]:
-                if pi[u] >= 0:
-                    rows_d.append(pi[u] - pos)
-            for v in in_nb[x]:
-                if pi[v] >= 0:
-                    rows_d.append(pos - pi[v])
-            if rows_d:
-                D = np.stack(rows_d)
-                if wrap:
-                    D = D % M
-                    D = np.where(D > M // 2, D - M, D)
-                D = np.sort(D, axis=0)
-                known = np.isin(D, np.fromiter(shiftset, dtype=np.int64, count=len(shiftset)))
-                first_of_run = np.ones_like(known)
-                first_of_run[1:] = D[1:] != D[:-1]
-                cost = np.sum(~known & first_of_run, axis=0)
-                k = int(np.argmin(cost))          # lowest slot among minima
+            if objective == "conflicts":
+                has = any(pi[u] >= 0 for u in out_nb[x]) or any(pi[v] >= 0 for v in in_nb[x])
+                k = int(np.argmin(conflict_cost(x, pos))) if has else 0
             else:
-                k = 0
+                rows_d = []
+                for u in out_nb[x]:
+                    if pi[u] >= 0:
+                        rows_d.append(pi[u] - pos)
+                for v in in_nb[x]:
+                    if pi[v] >= 0:
+                        rows_d.append(pos - pi[v])
+                if rows_d:
+                    D = red(np.stack(rows_d))
+                    D = np.sort(D, axis=0)
+                    known = np.isin(D, np.fromiter(shiftset, dtype=np.int64, count=len(shiftset)))
+                    first_of_run = np.ones_like(known)
+                    first_of_run[1:] = D[1:] != D[:-1]
+                    cost = np.sum(~known & first_of_run, axis=0)
+                    k = int(np.argmin(cost))          # lowest slot among minima
+                else:
+                    k = 0
             pi[x] = pos[k]
             taken[cand[k]] = True
             add_shifts(x)
     return pi
 
 
-def noo(rows, B: int, M: int, TH: int) -> tuple:
+def noo(rows, B: int, M: int, TH: int, objective: str = "shifts") -> tuple:
     regions = noo_regions(rows, TH)
     slots = interleave_slots([len(r) for r in regions], B)
-    pi = noo_place(rows, regions, slots, M, wrap=(B == M))
+    pi = noo_place(rows, regions, slots, M, wrap=(B == M), objective=objective)
     return pi, regions
 
 
@@ -423,7 +482,7 @@ def _build_rep_plan(n_v, rows, dims, activation, M, use_noo, TH, family, t1, cpo
     if TH is None:
         TH = 1024 if n_v < 10000 else 4096
     if use_noo:
-        pi, regions = noo(rows, Bc, M, TH)
+        pi, regions = noo(rows, Bc, M, TH, "conflicts" if family == 3 else "shifts")
     else:
         if n_v > Bc:
             raise ValueError("graph does not fit the column block")
@@ -508,7 +567,7 @@ def _build_plan(n_v: int, rows, dims: Sequence[int], activation: bool, M: int,
     if TH is None:
         TH = 1024 if n_v < 10000 else 4096
     if use_noo:
-        pi, regions = noo(rows, B, M, TH)
+        pi, regions = noo(rows, B, M, TH, "conflicts" if family == 3 else "shifts")
     else:
         pi, regions = np.arange(n_v, dtype=np.int64), [list(range(n_v))]
     layers = []

@@ -190,8 +190,15 @@ static std::vector<std::vector<int>> interleave(const std::vector<int>& sizes, i
   return slots;
 }
 
+// Stage 3: greedy placement in BFS order, each node at the free slot of its region with
+// the least cost (ties -> lowest slot).  conflicts = false: the shifts the node's demands
+// add to the plan (the diagonal and baby-step/giant-step forms pay per distinct shift);
+// conflicts = true (the radix-2 form): the (round, slot) cells where the node's demands
+// with placed nodes meet a placed demand of another source.  A radix-2 demand from slot s
+// with shift d sits, after each round r below the highest bit of |d|, at
+// s - sign(d) (|d| mod 2^(r+1)) (mod M); in its last round it arrives and leaves.
 static void place(ficgcn_plan* p, const std::vector<std::vector<int>>& regions,
-                  const std::vector<std::vector<int>>& slots, bool wrap) {
+                  const std::vector<std::vector<int>>& slots, bool wrap, bool conflicts) {
   const int n = p->n_v;
   const int64_t M = p->M;
   std::vector<std::vector<int>> out_nb(n), in_nb(n);
@@ -207,12 +214,44 @@ static void place(ficgcn_plan* p, const std::vector<std::vector<int>>& regions,
   // shifts lie in (-M, M): index d + M
   std::vector<char> used(2 * M + 1, 0);
   std::vector<int> stamp(2 * M + 1, -1);
+  int R = 0;
+  while ((M >> R) > 0) ++R;   // bit length of M
+  // source node per (round, slot); -1 free, -2 several sources
+  std::vector<int> occ(conflicts ? (size_t)R * M : 0, -1);
   auto red = [&](int64_t d) { return reduce_shift(d, M, wrap); };
+  auto cell = [&](int64_t s, int64_t d, int r) {
+    const int64_t mag = d < 0 ? -d : d, part = mag % ((int64_t)1 << (r + 1));
+    int64_t c = (s - (d > 0 ? part : -part)) % M;
+    return (size_t)r * M + (size_t)(c < 0 ? c + M : c);
+  };
+  auto travels = [](int64_t d, int r) { return ((d < 0 ? -d : d) >> (r + 1)) != 0; };
+  auto occupy = [&](int src, int64_t s, int64_t d) {
+    for (int r = 0; r < R && travels(d, r); ++r) {
+      int& o = occ[cell(s, d, r)];
+      o = o == -1 ? src : (o == src ? o : -2);
+    }
+  };
   auto add_shifts = [&](int x) {
     for (int u : out_nb[x])
-      if (p->pi[u] >= 0) used[red((int64_t)p->pi[u] - p->pi[x]) + M] = 1;
+      if (p->pi[u] >= 0) {
+        const int64_t d = red((int64_t)p->pi[u] - p->pi[x]);
+        used[d + M] = 1;
+        if (conflicts) occupy(u, p->pi[u], d);
+      }
     for (int v : in_nb[x])
-      if (p->pi[v] >= 0) used[red((int64_t)p->pi[x] - p->pi[v]) + M] = 1;
+      if (p->pi[v] >= 0) {
+        const int64_t d = red((int64_t)p->pi[x] - p->pi[v]);
+        used[d + M] = 1;
+        if (conflicts) occupy(x, p->pi[x], d);
+      }
+  };
+  auto walk_cost = [&](int src, int64_t s, int64_t d) {
+    long c = 0;
+    for (int r = 0; r < R && travels(d, r); ++r) {
+      const int o = occ[cell(s, d, r)];
+      c += (o != -1 && o != src) ? 1 : 0;
+    }
+    return c;
   };
   int stamp_id = 0;
   for (size_t r = 0; r < regions.size(); ++r) {
@@ -224,9 +263,12 @@ static void place(ficgcn_plan* p, const std::vector<std::vector<int>>& regions,
     add_shifts(reg[0]);
     for (size_t idx = 1; idx < reg.size(); ++idx) {
       int x = reg[idx];
-      std::vector<int> pu, pv;
+      std::vector<int> pu, pv, su;
       for (int u : out_nb[x])
-        if (p->pi[u] >= 0) pu.push_back(p->pi[u]);
+        if (p->pi[u] >= 0) {
+          pu.push_back(p->pi[u]);
+          su.push_back(u);
+        }
       for (int v : in_nb[x])
         if (p->pi[v] >= 0) pv.push_back(p->pi[v]);
       int best = -1;
@@ -235,7 +277,10 @@ static void place(ficgcn_plan* p, const std::vector<std::vector<int>>& regions,
         if (taken[k]) continue;
         int64_t pos = sl[k];
         long cost = 0;
-        if (!pu.empty() || !pv.empty()) {
+        if (conflicts) {
+          for (size_t a = 0; a < pu.size(); ++a) cost += walk_cost(su[a], pu[a], red(pu[a] - pos));
+          for (int b : pv) cost += walk_cost(x, pos, red(pos - b));
+        } else if (!pu.empty() || !pv.empty()) {
           ++stamp_id;
           for (int a : pu) {
             int64_t d = red(a - pos) + M;
@@ -637,7 +682,7 @@ static void node_order(ficgcn_plan* p, int B, const ficgcn_plan_opts& o) {
     std::vector<int> sizes;
     for (auto& r : p->regions) sizes.push_back((int)r.size());
     auto slots = interleave(sizes, B);
-    place(p, p->regions, slots, B == p->M);
+    place(p, p->regions, slots, B == p->M, o.family == 3);
   } else {
     if (n > B) FICGCN_THROW(EPLAN_, "graph does not fit the column block");
     p->pi.resize(n);

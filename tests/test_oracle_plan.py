@@ -118,6 +118,89 @@ def test_greedy_step_is_argmin_by_brute_force():
                 shifts.add(best - placed[v])
 
 
+def _walk(s, d, M):
+    """Cells of a radix-2 demand, simulated round by round: in round r the value
+    moves by sign(d) 2^r if bit r of |d| is set; while distance remains after the
+    round it occupies (r, slot)."""
+    cells, cur, mag, sg = [], s, abs(d), (1 if d > 0 else -1)
+    r = 0
+    while mag >> r:
+        if (mag >> r) & 1:
+            cur = (cur - sg * (1 << r)) % M
+        if mag >> (r + 1):
+            cells.append((r, cur))
+        r += 1
+    return cells
+
+
+@pytest.mark.parametrize("seed,n,B,M", [(1, 8, 8, 8), (2, 8, 16, 16), (3, 7, 8, 64), (4, 8, 32, 32),
+                                        (5, 6, 16, 128), (6, 8, 16, 16)])
+def test_conflict_objective_greedy_is_argmin_by_brute_force(seed, n, B, M):
+    """Stage 3 with the radix-2 objective: each placement is the brute-force
+    argmin (lowest slot on ties) of the number of (round, slot) cells where the
+    node's demands with placed nodes meet a placed demand of another source,
+    every demand's cells simulated round by round from its bits."""
+    rng = np.random.default_rng(seed)
+    adj = [set() for _ in range(n)]
+    for _ in range(2 * n):
+        a, b = (int(x) for x in rng.integers(0, n, 2))
+        if a != b:
+            adj[a].add(b)
+            adj[b].add(a)
+    rows = [[(v, 1.0)] + [(u, 1.0) for u in sorted(adj[v])] for v in range(n)]
+    wrap = B == M
+    red = lambda d: planner.reduce_shift(d, M, wrap)
+    regions = planner.noo_regions(rows, n)
+    slots = planner.interleave_slots([len(r) for r in regions], B)
+    pi = planner.noo_place(rows, regions, slots, M, wrap, objective="conflicts")
+    placed = {}
+    occupied = {}                                    # (round, slot) -> sources
+
+    def demands_of(x, pos):
+        out = []
+        for u, _ in rows[x]:
+            if u != x and u in placed:
+                out.append((u, placed[u], red(placed[u] - pos)))
+        for v, row in enumerate(rows):
+            if v != x and v in placed and any(u == x for u, _ in row):
+                out.append((x, pos, red(pos - placed[v])))
+        return out
+
+    for idx, x in enumerate(regions[0]):
+        free = [s_ for s_ in slots[0] if s_ not in placed.values()]
+        if idx == 0:
+            best = free[0]
+        else:
+            def cost(pos):
+                return sum(1 for src, s_, d in demands_of(x, pos) for c in _walk(s_, d, M)
+                           if occupied.get(c, set()) - {src})
+            best = min(free, key=lambda p_: (cost(p_), p_))
+        assert pi[x] == best, (seed, x)
+        for src, s_, d in demands_of(x, best):
+            for c in _walk(s_, d, M):
+                occupied.setdefault(c, set()).add(src)
+        placed[x] = best
+    assert planner.demand_cells(5, 6, 16) == _walk(5, 6, 16) == [(0, 5), (1, 3)]
+
+
+def test_conflict_objective_differs_from_shift_objective():
+    """On the small two-layer shape the radix-2 objective places nodes differently
+    from the distinct-shift objective, and the radix-2 program built on its order
+    needs no more working ciphertexts."""
+    from oracle import radix2
+    w, rows = _rows("tiny2")
+    regions = planner.noo_regions(rows, 1024)
+    slots = planner.interleave_slots([len(r) for r in regions], 512)
+    a = planner.noo_place(rows, regions, slots, 4096, False, objective="shifts")
+    b = planner.noo_place(rows, regions, slots, 4096, False, objective="conflicts")
+    assert not np.array_equal(a, b)
+    lanes = [radix2.build_program(pi, rows, 4096, 512, False, None).n_lanes for pi in (a, b)]
+    assert lanes[1] <= lanes[0], lanes           # 8 -> 7 working ciphertexts on this shape
+    o_a = planner.build_plan(w.graph.n, rows, w.meta["dims"], w.activation, 4096, family=3)
+    assert o_a.layers[1].family == 3
+    assert np.array_equal(o_a.pi, planner.noo(rows, o_a.layers[1].B, 4096, 1024, "conflicts")[0])
+
+
 def test_circulant_graph_routes_with_one_rotation():
     """A directed cycle v -> v+1 (identity order, one column): the only shifts
     are 0 and +1, i.e. one rotation (diagonal form)."""
