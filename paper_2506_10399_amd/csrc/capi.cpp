@@ -590,13 +590,16 @@ ficgcn_status ckks_mul_relin(ckks_ctx* ctx, const ckks_keys* eval_keys, const ui
 // ---------------------------------------------------------------- operands
 // Level and scale checks of the descriptor forms; nothing touches the device
 // before they pass.
-static void check_op(const ckks_ctx* c, const ckks_operand* op, uint32_t n_poly, const char* what) {
+static void check_op(const ckks_ctx* c, const ckks_operand* op, uint32_t n_poly, const char* what,
+                     bool fresh_ok = false) {
   REQUIRE(c != nullptr, EINVAL_, "null context");
   REQUIRE(op != nullptr && op->data != nullptr, EINVAL_, std::string("null ") + what);
   REQUIRE(op->n_poly == n_poly, EINVAL_,
           std::string(what) + (n_poly == 2 ? " is not a ciphertext (n_poly != 2)" : " is not a plaintext (n_poly != 1)"));
   check_level(c, op->level);
-  REQUIRE(op->scale > 0.0 && std::isfinite(op->scale), ESCALE_, std::string(what) + ": scale must be positive");
+  // an accumulator may be fresh (scale 0: it takes its first product's scale)
+  REQUIRE((op->scale > 0.0 || (fresh_ok && op->scale == 0.0)) && std::isfinite(op->scale), ESCALE_,
+          std::string(what) + ": scale must be positive");
 }
 
 static void same_level(const ckks_operand* a, const ckks_operand* b, const char* what) {
@@ -658,7 +661,7 @@ ficgcn_status ckks_rotate_hoisted_op(ckks_ctx* ctx, const ckks_keys* eval_keys, 
 ficgcn_status ckks_pt_mul_acc_op(ckks_ctx* ctx, ckks_operand* acc, const ckks_operand* cts, const ckks_operand* pts,
                                  size_t k) {
   return guard([&] {
-    check_op(ctx, acc, 2, "accumulator");
+    check_op(ctx, acc, 2, "accumulator", true);
     REQUIRE(k == 0 || (cts && pts), EINVAL_, "null argument");
     double sc = acc->scale;
     std::vector<const uint64_t*> c(k), p(k);
@@ -681,7 +684,7 @@ ficgcn_status ckks_pt_mul_acc_op(ckks_ctx* ctx, ckks_operand* acc, const ckks_op
 ficgcn_status ckks_scalar_mul_acc_op(ckks_ctx* ctx, ckks_operand* acc, const ckks_operand* cts, const int64_t* consts,
                                      double const_scale, size_t k) {
   return guard([&] {
-    check_op(ctx, acc, 2, "accumulator");
+    check_op(ctx, acc, 2, "accumulator", true);
     REQUIRE(k == 0 || (cts && consts), EINVAL_, "null argument");
     REQUIRE(const_scale > 0.0 && std::isfinite(const_scale), ESCALE_, "constant scale must be positive");
     double sc = acc->scale;

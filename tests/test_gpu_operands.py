@@ -98,7 +98,7 @@ def test_rejected_operand_call_leaves_output(env):
     for f, args, code in [
         (ctx.ckks_add_op, (A, ctx.operand(x, lv, 2 * S)), -3),
         (ctx.ckks_add_op, (A, ctx.operand(x, lv - 1, S)), -2),
-        (ctx.ckks_pt_mul_acc_op, (A, [X], [ctx.operand(e["pw"], lv, 1.0, 1)]), -3),
+        (ctx.ckks_pt_mul_acc_op, (A, [X], [ctx.operand(e["pw"], lv, 2.0, 1)]), -3),   # product scale 2 S, not S
         (ctx.ckks_mul_relin_op, (e["ev"], X, ctx.operand(x, lv - 1, S), A), -2),
     ]:
         with pytest.raises(fg.FicgcnError) as err:
