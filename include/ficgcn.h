@@ -535,15 +535,23 @@ ficgcn_status ficgcn_mlp_train_step(ficgcn_mlp* mlp, const float* x_dev, const f
                                     float* loss_out);
 
 /* ----------------------------------------------------------- serving [server]
- * Continuous batching of encrypted GCN inferences on one GPU.  The server
- * runs up to n_slots requests at once, each on its own context and stream
- * (so their kernels overlap on the device), admits waiting requests in FIFO
- * order as slots and device memory free up (a later request that fits may
- * pass the head until the head has been passed 16 times), and keeps every
- * client's evaluation keys resident (the caller's ckks_keys objects).  A
- * request's footprint = its input ciphertexts + every layer's outputs + its
- * encoded plan operands; it must fit under hbm_budget_bytes next to the
- * running requests (per-slot scratch is outside the budget). */
+ * Continuous batching of encrypted GCN inferences (the method's layer,
+ * Sec. 3, served to many clients under the threat model of Sec. 2.4) on one
+ * GPU.  The server runs up to n_slots requests at once, each on its own
+ * context and stream (so their kernels overlap on the device), admits waiting
+ * requests in FIFO order as slots and device memory free up (a later request
+ * that fits may pass the head until the head has been passed 16 times), and
+ * keeps every client's evaluation keys resident (the caller's ckks_keys
+ * objects, which must outlive the server).
+ * Device memory is accounted in full against hbm_budget_bytes: the resident
+ * key sets (each distinct set from its first request on), the plans' weight
+ * tables (each distinct plan once), and per slot an arena and a scratch
+ * share.  A request's arena holds its input ciphertexts, every layer's
+ * outputs and its plan's operands; its scratch share is bounded from the plan
+ * (key-switch chunks of at most 3 GiB plus one job, and 64 ciphertexts at the
+ * input level).  Arenas only grow, so in steady state a request allocates
+ * nothing; idle slots' arenas and scratch are released when a waiting request
+ * needs the room. */
 typedef struct ficgcn_server ficgcn_server;
 
 typedef struct {
@@ -554,20 +562,26 @@ typedef struct {
   size_t n_in;
   uint64_t* output_host;           /* the last layer's n_out ciphertexts [n_out][2][level_out+1][N] */
   size_t n_out;
+  const uint64_t* const* operands_host;  /* NULL: the slot encodes the plan's operands (ficgcn_plan_encode);
+                                      else per layer, every operand's coefficient-form residues in operand
+                                      order, as ficgcn_plan_load_operand takes them, concatenated */
 } ficgcn_request;
 
 typedef struct {
   int32_t status;                  /* the request's ficgcn_status */
   double queue_ms, run_ms, latency_ms;   /* submission to admission, admission to completion, total */
-  uint64_t footprint_bytes;
+  uint64_t footprint_bytes;        /* arena bytes plus the scratch bound */
 } ficgcn_request_result;
 
 typedef struct {
   uint32_t completed, failed;
   double p50_ms, p99_ms, mean_ms;  /* latency (submission to completion), nearest-rank percentiles */
   double throughput_per_s;         /* completed requests / (last completion - first submission) */
-  uint64_t peak_bytes;             /* largest admitted footprint sum */
+  uint64_t peak_bytes;             /* largest device memory held: resident keys and tables, arenas, scratch */
   uint32_t max_concurrent;         /* most requests running at once */
+  uint64_t resident_bytes;         /* key sets and plan tables */
+  uint64_t arena_allocs;           /* arena (re)allocations over the server's life */
+  uint64_t scratch_overruns;       /* requests whose measured scratch exceeded the bound (then counted) */
 } ficgcn_server_summary;
 
 /* Creates the slots (contexts for params on the current device, one stream

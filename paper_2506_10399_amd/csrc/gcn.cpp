@@ -42,7 +42,6 @@ void comb_mfma(ckks_ctx* c, const std::vector<uint64_t*>& outs, const uint64_t* 
                const uint64_t* pw, const char* prof_name);
 void build_plan(ckks_ctx* c, ficgcn_plan* p, const uint32_t* dims, uint32_t n_layers, const double* const* weights,
                 const ficgcn_plan_opts& o);
-std::vector<int64_t> layer_rotation_steps(const LayerPlan& lp);
 
 static int64_t fdiv(int64_t a, int64_t b) {
   int64_t q = a / b;

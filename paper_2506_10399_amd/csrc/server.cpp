@@ -1,27 +1,38 @@
 // Serving loop: continuous batching of encrypted GCN inferences on one GPU.
 //
 // The server owns n_slots execution slots, each with its own context (HIP
-// stream at the default priority and scratch memory) and worker thread, so
-// up to n_slots requests run at once and their kernels overlap on the
-// device.  A request names a plan (the graph's packing, node order,
-// operands to encode), the client's resident evaluation keys, the client's
-// ciphertexts in host memory and a host destination for the result.
-// Admission is by device-memory footprint: a request's inputs, every
-// layer's outputs and its encoded operands must fit under the budget next
-// to the requests already running.  The waiting queue is FIFO; a later
+// stream at the default priority and scratch memory), worker thread and device
+// arena, so up to n_slots requests run at once and their kernels overlap on the
+// device.  A request names a plan (the graph's packing, node order, operands),
+// the client's resident evaluation keys, the client's ciphertexts in host
+// memory and a host destination for the result.
+//
+// Device memory is accounted in full: held = the resident evaluation key sets
+// (each distinct set once, from its first request on) + the plans' weight
+// tables (each distinct plan once) + every slot's arena + every slot's scratch.
+// A request needs an arena of its inputs, every layer's outputs and its
+// operands, and scratch for its batched launches (bounded from the plan: the
+// key-switch chunk budget and a margin of ciphertext buffers); it is admitted
+// to an idle slot when held, grown by what that slot's arena and scratch must
+// grow, stays within the budget; arenas of other idle slots are released
+// first when that makes the difference.  An arena only grows, so in steady
+// state a request allocates nothing: its inputs, outputs and operands are
+// carved from the slot's arena (no hipMalloc / hipFree, which would
+// synchronise the device across slots).  The waiting queue is FIFO; a later
 // request that fits may pass a head that does not, until the head has been
-// passed 16 times (then the queue waits for it).  A slot's life for one
-// request: allocate, upload the inputs, encode the plan's operands, run
-// every layer in the batched form, download the last layer's ciphertexts,
-// free everything.  Latency = completion - submission on the server's
-// steady clock.
+// passed 16 times (then the queue waits for it).  A slot's work for one
+// request: upload the inputs, encode (or load) the plan's operands into the
+// arena, run every layer in the batched form, download the last layer's
+// ciphertexts.  Latency = completion - submission on the server's steady clock.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <mutex>
+#include <set>
 #include <thread>
 
 #include "../../include/ficgcn.h"
@@ -36,7 +47,8 @@ double now_ms() {
 
 struct Req {
   ficgcn_request r{};
-  size_t footprint = 0;
+  size_t footprint = 0;     // arena bytes: inputs, layer outputs, operands
+  size_t scratch = 0;       // scratch bound of its batched launches
   double t_submit = 0, t_start = 0, t_done = 0;
   int status = 0;
   std::string err;
@@ -44,16 +56,31 @@ struct Req {
   int passed = 0;
 };
 
+struct Slot {
+  ckks_ctx* c = nullptr;
+  uint8_t* arena = nullptr;
+  size_t cap = 0;           // arena bytes allocated
+  size_t cap_pending = 0;   // arena bytes the admitted request needs (counted in held at admission)
+  size_t scratch = 0;       // scratch bytes accounted (max of the bound admitted and the measured size)
+  bool busy = false;
+};
+
+constexpr size_t ALIGN = 256;
+size_t up(size_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
+
 }  // namespace
 
 struct ficgcn_server {
-  std::vector<ckks_ctx*> slots;
+  std::vector<Slot> slots;
   std::vector<std::thread> workers;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::map<uint64_t, Req> reqs;
   std::deque<uint64_t> waiting;
-  size_t budget = 0, in_use = 0, peak = 0;
+  std::set<const ckks_keys*> keys_seen;
+  std::set<const ficgcn_plan*> plans_seen;
+  size_t budget = 0, held = 0, peak = 0, resident = 0;
+  uint64_t allocs = 0, overruns = 0;
   int running = 0, max_running = 0;
   uint64_t next_id = 1;
   bool stop = false;
@@ -63,25 +90,108 @@ struct ficgcn_server {
 
 namespace ficgcn {
 
+// the chunk budget of batched key switching (ks_batch.hip)
+constexpr size_t KS_CHUNK = (size_t)3 << 30;
+
 static size_t ct_bytes(const ckks_ctx* c, int level) { return (size_t)2 * (level + 1) * c->N * 8; }
 
-static size_t request_footprint(const ficgcn_plan* p) {
+// arena layout of one request: inputs, then each layer's outputs, then each layer's operands
+static size_t request_arena(const ficgcn_plan* p, std::vector<size_t>* off = nullptr) {
   const ckks_ctx* c = p->ctx;
-  size_t b = plan_operand_bytes(p);
-  const LayerPlan& l0 = p->layers[0];
-  b += (size_t)l0.n_in_cts() * ct_bytes(c, l0.level_in);
-  for (const LayerPlan& lp : p->layers) b += (size_t)lp.n_packed() * ct_bytes(c, lp.level_in);
+  size_t b = 0;
+  auto take = [&](size_t n) {
+    if (off) off->push_back(b);
+    b += up(n);
+  };
+  take((size_t)p->layers[0].n_in_cts() * ct_bytes(c, p->layers[0].level_in));
+  for (const LayerPlan& lp : p->layers) take((size_t)lp.n_packed() * ct_bytes(c, lp.level_in));
+  for (const LayerPlan& lp : p->layers) take(std::max<size_t>(1, lp.op_words) * 8);
   return b;
 }
 
-// pick the next admissible request (FIFO with bounded passing); caller holds the lock
-static bool pick(ficgcn_server* s, uint64_t& id) {
-  for (size_t k = 0; k < s->waiting.size(); ++k) {
-    Req& q = s->reqs[s->waiting[k]];
-    if (s->in_use + q.footprint <= s->budget) {
-      id = s->waiting[k];
-      for (size_t m = 0; m < k; ++m) s->reqs[s->waiting[m]].passed += 1;
-      s->waiting.erase(s->waiting.begin() + k);
+// scratch of the batched launches: every layer's key switches (one job per rotation of each
+// packed ciphertext plus the relinearisations, a source per job at most), capped by the chunk
+// budget plus one job, and 64 ciphertext buffers at the input level for everything else
+static size_t scratch_bound(const ficgcn_plan* p) {
+  const ckks_ctx* c = p->ctx;
+  size_t ks = 0, extra = 0;
+  for (const LayerPlan& lp : p->layers) {
+    const size_t N = c->N, l1 = lp.level_in + 1, ext = l1 + c->alpha, nd = (l1 + c->alpha - 1) / c->alpha;
+    const size_t per_job = 2 * (ext + l1) * N * 8, per_src = (nd * ext + l1) * N * 8;
+    const size_t jobs = (layer_rotation_steps(lp).size() + (lp.act ? 1 : 0)) * (size_t)std::max(1, lp.n_packed()) +
+                        (size_t)lp.shifts.size() * std::max(1, lp.n_packed());
+    ks = std::max(ks, std::min(jobs * (per_job + per_src), KS_CHUNK + per_job + per_src));
+    extra = std::max(extra, 64 * ct_bytes(c, lp.level_in));
+  }
+  return ks + extra;
+}
+
+// device bytes of a plan's weight tables (per-operation residues, fused-pass weights): at most
+// 40 bytes per weight and limb, and 64 KiB of constants per layer
+static size_t plan_tables(const ficgcn_plan* p) {
+  size_t b = 0;
+  for (const LayerPlan& lp : p->layers) b += (size_t)40 * lp.f_in * lp.f_out * (lp.level_in + 1) + (64 << 10);
+  return b;
+}
+
+static size_t keys_bytes(const ckks_keys* k) {
+  const ckks_ctx* c = k->ctx;
+  const size_t nd = (size_t)(c->L + c->alpha - 1) / c->alpha;
+  return k->swk.size() * nd * 2 * (size_t)(c->L + c->alpha) * c->N * 8 + (k->s_ntt ? (size_t)(c->L + c->alpha) * c->N * 8 : 0);
+}
+
+static size_t slot_scratch_now(const ckks_ctx* c) {
+  size_t b = 0;
+  for (const auto& s : c->scratch) b += s.second;
+  return b;
+}
+
+// frees an idle slot's arena and scratch (its stream has no work left)
+static void release_slot(ficgcn_server* s, Slot& sl) {
+  if (sl.arena) (void)hipFree(sl.arena);
+  sl.arena = nullptr;
+  for (auto& b : sl.c->scratch) {
+    if (b.first) (void)hipFree(b.first);
+    b = {nullptr, 0};
+  }
+  s->held -= sl.cap + sl.scratch;
+  sl.cap = sl.scratch = 0;
+}
+
+// pick the next admissible request for slot k (FIFO with bounded passing); caller holds the lock.
+// Held memory after admission, by the first option that fits the budget: (a) as it is, the slot's
+// arena and scratch grown to the request's; (b) the other idle slots released first; (c) also the
+// slot's own arena and scratch released and taken anew at the request's size.
+static bool pick(ficgcn_server* s, int k, uint64_t& id) {
+  Slot& me = s->slots[k];
+  for (size_t w = 0; w < s->waiting.size(); ++w) {
+    Req& q = s->reqs[s->waiting[w]];
+    const size_t mine = me.cap + me.scratch;
+    const size_t others = s->held - s->resident - mine;
+    size_t idle = 0;
+    for (size_t o = 0; o < s->slots.size(); ++o)
+      if ((int)o != k && !s->slots[o].busy) idle += s->slots[o].cap + s->slots[o].scratch;
+    const size_t grown = std::max(me.cap, q.footprint) + std::max(me.scratch, q.scratch);
+    const size_t fresh = q.footprint + q.scratch;
+    int option = -1;
+    if (s->resident + others + grown <= s->budget) option = 0;
+    else if (s->resident + others - idle + grown <= s->budget) option = 1;
+    else if (s->resident + others - idle + fresh <= s->budget) option = 2;
+    if (option >= 0) {
+      if (option >= 1)
+        for (size_t o = 0; o < s->slots.size(); ++o)
+          if ((int)o != k && !s->slots[o].busy && s->slots[o].cap + s->slots[o].scratch) release_slot(s, s->slots[o]);
+      if (option == 2) release_slot(s, me);
+      id = s->waiting[w];
+      for (size_t m = 0; m < w; ++m) s->reqs[s->waiting[m]].passed += 1;
+      s->waiting.erase(s->waiting.begin() + w);
+      // the slot's share grows to what the request may use (the arena itself grows in run_request)
+      const size_t grow_a = q.footprint > me.cap ? q.footprint - me.cap : 0;
+      const size_t grow_s = q.scratch > me.scratch ? q.scratch - me.scratch : 0;
+      s->held += grow_a + grow_s;
+      me.scratch += grow_s;
+      me.cap_pending = std::max(me.cap, q.footprint);
+      s->peak = std::max(s->peak, s->held);
       return true;
     }
     if (q.passed >= 16) return false;   // the head has waited long enough
@@ -89,30 +199,62 @@ static bool pick(ficgcn_server* s, uint64_t& id) {
   return false;
 }
 
-static void run_request(ckks_ctx* c, Req& q) {
+static void load_operands(ckks_ctx* c, ficgcn_plan* p, const uint64_t* const* host) {
+  for (size_t li = 0; li < p->layers.size(); ++li) {
+    const LayerPlan& lp = p->layers[li];
+    const uint64_t* src = host[li];
+    if (!src) FICGCN_THROW(EINVAL_, "missing host operands of a layer");
+    for (size_t i = 0; i < lp.ops.size(); ++i) {
+      ficgcn_status st = ficgcn_plan_load_operand(c, p, (uint32_t)li, i, src);
+      if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
+      src += (size_t)(lp.op_lv[i] + 1 + (lp.op_x[i] ? c->alpha : 0)) * c->N;
+    }
+  }
+}
+
+static void run_request(ficgcn_server* s, Slot& sl, Req& q) {
+  ckks_ctx* c = sl.c;
   ficgcn_plan* p = const_cast<ficgcn_plan*>(q.r.plan);
   const LayerPlan& l0 = p->layers[0];
   const LayerPlan& ll = p->layers.back();
-  std::vector<void*> blocks;
   try {
     ensure_device(c);
+    if (sl.cap_pending > sl.cap) {   // the arena grows (never shrinks while the slot works)
+      if (sl.arena) {
+        HIPCHECK(hipStreamSynchronize(c->stream));
+        HIPCHECK(hipFree(sl.arena));
+      }
+      sl.arena = nullptr;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        sl.cap = sl.cap_pending;   // already counted in held at admission
+        s->allocs += 1;
+      }
+      HIPCHECK(hipMalloc(&sl.arena, sl.cap));
+    }
+    std::vector<size_t> off;
+    request_arena(p, &off);
+    const size_t nl = p->layers.size();
     // inputs
     const size_t in_ct = ct_bytes(c, l0.level_in);
-    uint8_t* din = nullptr;
-    HIPCHECK(hipMalloc(&din, std::max<size_t>(1, q.r.n_in * in_ct)));
-    blocks.push_back(din);
+    uint8_t* din = sl.arena + off[0];
     HIPCHECK(hipMemcpyAsync(din, q.r.inputs_host, q.r.n_in * in_ct, hipMemcpyHostToDevice, c->stream));
-    // operands of this graph's plan
-    ficgcn_status st = ficgcn_plan_encode(c, p);
-    if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
+    // operands of this graph's plan, in the arena
+    std::vector<uint64_t*> blocks(nl);
+    for (size_t li = 0; li < nl; ++li) blocks[li] = (uint64_t*)(sl.arena + off[1 + nl + li]);
+    lend_operand_blocks(p, blocks.data());
+    if (q.r.operands_host) {
+      load_operands(c, p, q.r.operands_host);
+    } else {
+      ficgcn_status st = ficgcn_plan_encode(c, p);
+      if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
+    }
     std::vector<const uint64_t*> cur(q.r.n_in);
     for (size_t i = 0; i < q.r.n_in; ++i) cur[i] = (const uint64_t*)(din + i * in_ct);
-    for (size_t li = 0; li < p->layers.size(); ++li) {
+    for (size_t li = 0; li < nl; ++li) {
       const LayerPlan& lp = p->layers[li];
       const size_t oc = ct_bytes(c, lp.level_in);
-      uint8_t* dout = nullptr;
-      HIPCHECK(hipMalloc(&dout, std::max<size_t>(1, lp.n_packed() * oc)));
-      blocks.push_back(dout);
+      uint8_t* dout = sl.arena + off[1 + li];
       std::vector<uint64_t*> outs(lp.n_packed());
       for (int i = 0; i < lp.n_packed(); ++i) outs[i] = (uint64_t*)(dout + i * oc);
       run_layer(c, q.r.eval_keys, p, (int)li, cur.data(), cur.size(), outs.data(), outs.size(), 1);
@@ -131,37 +273,39 @@ static void run_request(ckks_ctx* c, Req& q) {
     q.err = e.what();
   }
   (void)hipStreamSynchronize(c->stream);
-  for (void* b : blocks) (void)hipFree(b);
-  release_plan_device(p);
+  lend_operand_blocks(p, nullptr);   // the arena will hold another request's operands
 }
 
-static void worker(ficgcn_server* s, int slot) {
-  ckks_ctx* c = s->slots[slot];
-  (void)hipSetDevice(c->device);
+static void worker(ficgcn_server* s, int k) {
+  Slot& sl = s->slots[k];
+  (void)hipSetDevice(sl.c->device);
   for (;;) {
     uint64_t id;
-    {
-      std::unique_lock<std::mutex> lk(s->mu);
-      s->cv_work.wait(lk, [&] { return s->stop || pick(s, id); });
-      if (s->stop) return;
-      Req& q = s->reqs[id];
-      s->in_use += q.footprint;
-      s->peak = std::max(s->peak, s->in_use);
-      s->running += 1;
-      s->max_running = std::max(s->max_running, s->running);
-      q.t_start = now_ms();
-    }
     Req* qp;
     {
-      std::lock_guard<std::mutex> lk(s->mu);
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_work.wait(lk, [&] { return s->stop || pick(s, k, id); });
+      if (s->stop) return;
       qp = &s->reqs[id];   // map nodes are stable
+      sl.busy = true;
+      s->running += 1;
+      s->max_running = std::max(s->max_running, s->running);
+      qp->t_start = now_ms();
     }
-    run_request(c, *qp);
+    run_request(s, sl, *qp);
     {
       std::lock_guard<std::mutex> lk(s->mu);
       qp->t_done = now_ms();
       qp->done = true;
-      s->in_use -= qp->footprint;
+      // measured scratch: more than the bound admitted is counted (and reported as an overrun)
+      const size_t now = slot_scratch_now(sl.c);
+      if (now > sl.scratch) {
+        s->overruns += 1;
+        s->held += now - sl.scratch;
+        sl.scratch = now;
+        s->peak = std::max(s->peak, s->held);
+      }
+      sl.busy = false;
       s->running -= 1;
       s->t_last = std::max(s->t_last, qp->t_done);
     }
@@ -180,10 +324,12 @@ ficgcn_server::~ficgcn_server() {
   cv_work.notify_all();
   for (auto& t : workers)
     if (t.joinable()) t.join();
-  for (ckks_ctx* c : slots) {
-    if (c->stream) (void)hipStreamDestroy(c->stream);
-    c->stream = nullptr;
-    delete c;
+  for (Slot& sl : slots) {
+    if (sl.c->stream) (void)hipStreamSynchronize(sl.c->stream);
+    if (sl.arena) (void)hipFree(sl.arena);
+    if (sl.c->stream) (void)hipStreamDestroy(sl.c->stream);
+    sl.c->stream = nullptr;
+    delete sl.c;
   }
 }
 
@@ -218,7 +364,9 @@ ficgcn_status ficgcn_server_create(const ckks_params* params, uint32_t n_slots, 
     ckks_ctx* c = nullptr;
     ficgcn_status st = ckks_context_create(params, &c);
     if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
-    s->slots.push_back(c);
+    Slot sl;
+    sl.c = c;
+    s->slots.push_back(sl);
     c->device = dev;
     HIPCHECK(hipStreamCreate(&c->stream));
   }
@@ -235,19 +383,31 @@ ficgcn_status ficgcn_server_submit(ficgcn_server* server, const ficgcn_request* 
     FICGCN_THROW(EINVAL_, "null argument");
   const ficgcn_plan* p = req->plan;
   const ckks_ctx* pc = p->ctx;
-  const ckks_ctx* sc = server->slots[0];
+  const ckks_ctx* sc = server->slots[0].c;
   if (pc->N != sc->N || pc->L != sc->L || pc->alpha != sc->alpha || pc->mod != sc->mod)
     FICGCN_THROW(EINVAL_, "the plan was built for other CKKS parameters");
   if ((int)req->n_in != p->layers[0].n_in_cts()) FICGCN_THROW(EPLAN_, "wrong number of input ciphertexts");
   if ((int)req->n_out != p->layers.back().n_packed()) FICGCN_THROW(EPLAN_, "wrong number of output ciphertexts");
+  if (req->eval_keys->ctx && req->eval_keys->ctx->N != sc->N) FICGCN_THROW(EINVAL_, "keys of other parameters");
   Req q;
   q.r = *req;
-  q.footprint = request_footprint(p);
-  if (q.footprint > server->budget) FICGCN_THROW(ENOMEM_, "request larger than the server's device budget");
+  q.footprint = request_arena(p);
+  q.scratch = scratch_bound(p);
   std::lock_guard<std::mutex> lk(server->mu);
   for (const auto& kv : server->reqs)
     if (!kv.second.done && kv.second.r.plan == req->plan)
       FICGCN_THROW(EINVAL_, "a plan may serve one request at a time");
+  // resident memory this request brings: its key set and its plan's tables, once each
+  size_t add = 0;
+  if (!server->keys_seen.count(req->eval_keys)) add += keys_bytes(req->eval_keys);
+  if (!server->plans_seen.count(p)) add += plan_tables(p);
+  if (server->resident + add + q.footprint + q.scratch > server->budget)
+    FICGCN_THROW(ENOMEM_, "request larger than the server's device budget (with resident keys and plan tables)");
+  if (!server->keys_seen.count(req->eval_keys)) server->keys_seen.insert(req->eval_keys);
+  if (!server->plans_seen.count(p)) server->plans_seen.insert(p);
+  server->resident += add;
+  server->held += add;
+  server->peak = std::max(server->peak, server->held);
   q.t_submit = now_ms();
   if (server->t_first < 0) server->t_first = q.t_submit;
   const uint64_t id = server->next_id++;
@@ -270,7 +430,7 @@ ficgcn_status ficgcn_server_wait(ficgcn_server* server, uint64_t id, ficgcn_requ
   out->queue_ms = q.t_start - q.t_submit;
   out->run_ms = q.t_done - q.t_start;
   out->latency_ms = q.t_done - q.t_submit;
-  out->footprint_bytes = q.footprint;
+  out->footprint_bytes = q.footprint + q.scratch;
   if (q.status != 0) {
     set_error(q.err);
     return (ficgcn_status)q.status;
@@ -308,6 +468,9 @@ ficgcn_status ficgcn_server_stats(ficgcn_server* server, ficgcn_server_summary* 
   out->throughput_per_s = span > 0 ? lat.size() / (span * 1e-3) : 0.0;
   out->peak_bytes = server->peak;
   out->max_concurrent = (uint32_t)server->max_running;
+  out->resident_bytes = server->resident;
+  out->arena_allocs = server->allocs;
+  out->scratch_overruns = server->overruns;
   SV_END
 }
 

@@ -56,7 +56,7 @@ N_FEATURES = 24
 
 class Request(ctypes.Structure):
     _fields_ = [("plan", c_vp), ("eval_keys", c_vp), ("inputs_host", c_vp), ("n_in", ctypes.c_size_t),
-                ("output_host", c_vp), ("n_out", ctypes.c_size_t)]
+                ("output_host", c_vp), ("n_out", ctypes.c_size_t), ("operands_host", c_vp)]
 
 
 class RequestResult(ctypes.Structure):
@@ -67,7 +67,9 @@ class RequestResult(ctypes.Structure):
 class ServerSummary(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_uint32), ("failed", ctypes.c_uint32), ("p50_ms", ctypes.c_double),
                 ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double), ("throughput_per_s", ctypes.c_double),
-                ("peak_bytes", ctypes.c_uint64), ("max_concurrent", ctypes.c_uint32)]
+                ("peak_bytes", ctypes.c_uint64), ("max_concurrent", ctypes.c_uint32),
+                ("resident_bytes", ctypes.c_uint64), ("arena_allocs", ctypes.c_uint64),
+                ("scratch_overruns", ctypes.c_uint64)]
 
 # name -> (restype, argtypes); every status-returning call returns c_int
 _SIGS = {
@@ -701,11 +703,19 @@ class Server:
         self.close()
 
     def ficgcn_server_submit(self, plan: "Plan", eval_keys: "Keys", inputs_host, n_in: int, output_host,
-                             n_out: int) -> int:
-        r = Request(plan.h, eval_keys.h, _ptr(inputs_host), n_in, _ptr(output_host), n_out)
+                             n_out: int, operands_host=None) -> int:
+        """operands_host: None (the slot encodes the plan's operands) or, per layer, a uint64 array
+        of every operand's coefficient-form residues in operand order, concatenated."""
+        ops = None
+        if operands_host is not None:
+            operands_host = [np.ascontiguousarray(a, dtype=np.uint64) for a in operands_host]
+            ops = _ptr_array(operands_host)
+        r = Request(plan.h, eval_keys.h, _ptr(inputs_host), n_in, _ptr(output_host), n_out,
+                    ctypes.cast(ops, c_vp) if ops is not None else None)
         rid = ctypes.c_uint64()
         _check(lib().ficgcn_server_submit(self.h, ctypes.byref(r), ctypes.byref(rid)))
-        self._held[rid.value] = (plan, eval_keys, inputs_host, output_host)   # alive until waited for
+        # alive until waited for
+        self._held[rid.value] = (plan, eval_keys, inputs_host, output_host, operands_host, ops)
         return rid.value
 
     def ficgcn_server_wait(self, rid: int) -> dict:

@@ -48,18 +48,29 @@ def fp64_gcn(rp, col, val, x, weights):
 
 
 def make_requests(ctx: fg.Context, n_req: int, seed: int, n_range=(500, 4000), f_range=(64, 256), hidden: int = 16,
-                  classes=(2, 10), model: Optional[fg.Mlp] = None, keep: int = 4) -> List[ClientRequest]:
+                  classes=(2, 10), model: Optional[fg.Mlp] = None, keep: int = 4,
+                  corners: Sequence[tuple] = (), low_level: bool = False,
+                  max_input_bytes: Optional[float] = None, log=None) -> List[ClientRequest]:
     """Graphs of log-uniform size and feature width (power-law, average
     degree 3-5, sampled neighbours + self, mean aggregation), binary features
     at 1%, N(0, 0.1^2) weights; plans by the paper's rule or, with a model,
-    by the learned search."""
+    by the learned search.  corners: (n, F) shapes taken first (the range's
+    extremes); low_level: the client encrypts at the lowest level the layers
+    need; max_input_bytes: a drawn shape whose client ciphertexts would take the
+    pool's total beyond this is skipped and the next one drawn (host memory)."""
     from workload.graphs import chung_lu, sample_neighbors
     from workload.features import binary_features, gaussian_weights
     rng = np.random.default_rng(seed)
     out = []
-    for r in range(n_req):
-        n = int(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1]))))
-        F = int(np.exp(rng.uniform(np.log(f_range[0]), np.log(f_range[1]))))
+    total = 0.0
+    corners = list(corners)
+    r = 0
+    while len(out) < n_req:
+        if corners:
+            n, F = corners.pop(0)
+        else:
+            n = int(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1]))))
+            F = int(np.exp(rng.uniform(np.log(f_range[0]), np.log(f_range[1]))))
         c = int(rng.integers(classes[0], classes[1] + 1))
         deg = float(rng.uniform(3.0, 5.0))
         s = int(rng.integers(1 << 30))
@@ -70,14 +81,41 @@ def make_requests(ctx: fg.Context, n_req: int, seed: int, n_range=(500, 4000), f
         x = binary_features(n, F, 0.01, s + 2)
         ws = [gaussian_weights(dims[i], dims[i + 1], s + 3 + i) for i in range(2)]
         q = ClientRequest("req%d-n%d-F%d-c%d" % (r, n, F, c), n, dims, rp, col, val, x, ws)
+        r += 1
         if model is not None:
             base = fg.PlanOpts(0, 1, 0, 0, 1, 0)
+            base.low_level = int(low_level)
             opts, _ = fg.ficgcn_plan_search(ctx, rp, col, val, n, dims, ws, base, model=model, keep=keep)
             q.plan = fg.Plan(ctx, rp, col, val, n, dims, ws, opts=opts)
         else:
-            q.plan = fg.Plan(ctx, rp, col, val, n, dims, ws, activation=True)
+            q.plan = fg.Plan(ctx, rp, col, val, n, dims, ws, activation=True, low_level=low_level)
         q.info = q.plan.ficgcn_plan_info()
+        d0 = q.info[0]
+        nbytes = d0["n_in_cts"] * 2 * (d0["level_in"] + 1) * ctx.N * 8.0
+        if max_input_bytes is not None and out and total + nbytes > max_input_bytes:
+            continue
+        total += nbytes
         out.append(q)
+        if log:
+            log("planned %s: %d input ciphertexts, %.1f GB" % (q.name, d0["n_in_cts"], nbytes / 1e9))
+    return out
+
+
+def replicate(ctx: fg.Context, pool: Sequence[ClientRequest], n_req: int, seed: int) -> List[ClientRequest]:
+    """A stream of n_req requests on graphs drawn uniformly from the pool: each
+    request has its own plan object (built with the pool entry's options, so the
+    same node order and the client's same ciphertexts) and its own output buffer;
+    graph data and the encrypted inputs are shared with the pool entry."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in range(n_req):
+        q = pool[int(rng.integers(len(pool)))]
+        c = ClientRequest("%s#%d" % (q.name, r), q.n_v, q.dims, q.rowptr, q.col, q.val, q.x, q.weights)
+        c.plan = fg.Plan(ctx, q.rowptr, q.col, q.val, q.n_v, q.dims, q.weights, opts=q.plan.opts)
+        c.info = q.info
+        c.inputs_host = q.inputs_host
+        c.output_host = np.zeros_like(q.output_host)
+        out.append(c)
     return out
 
 
@@ -100,7 +138,10 @@ def encrypt_inputs(ctx: fg.Context, cl: fg.Keys, q: ClientRequest, seed: int):
     lv = d0["level_in"]
     K, F = d0["K"], d0["f_in"]
     N, M = ctx.N, ctx.M
-    host = torch.empty((K * F, 2, lv + 1, N), dtype=torch.int64, pin_memory=True)
+    try:
+        host = torch.empty((K * F, 2, lv + 1, N), dtype=torch.int64, pin_memory=True)
+    except RuntimeError:   # page-locked memory exhausted: a pageable buffer (the upload then blocks the slot)
+        host = torch.empty((K * F, 2, lv + 1, N), dtype=torch.int64)
     dev = torch.empty((min(256, F), 2, lv + 1, N), dtype=torch.int64, device="cuda")
     for k in range(K):
         have = src[k] >= 0

@@ -2,8 +2,11 @@
 
 Each request's returned ciphertext words are the same when it runs alone and
 when it runs in a mix with others on concurrent slots; decrypted, every
-result is within 1e-3 of the FP64 model.  Admission respects the device
-budget, and a request that can never fit is refused."""
+result is within 1e-3 of the FP64 model; a served request given the oracle's
+operands and ciphertexts returns the oracle's words.  Admission respects the
+device budget (resident keys and plan tables, slot arenas and scratch), a
+request that can never fit is refused, and in steady state requests allocate
+nothing (the slot arenas are reused)."""
 import numpy as np
 import pytest
 
@@ -26,6 +29,7 @@ def env():
 
 
 def _footprints(env):
+    """Each request's footprint (arena + scratch bound) and the resident bytes (keys, plan tables)."""
     fg = env["fg"]
     srv = fg.Server(PARAMS, 1, 1 << 40)
     out = []
@@ -33,8 +37,10 @@ def _footprints(env):
         rid = srv.ficgcn_server_submit(q.plan, env["ev"], q.inputs_host, len(q.inputs_host), q.output_host,
                                        len(q.output_host))
         out.append(srv.ficgcn_server_wait(rid)["footprint_bytes"])
+    st = srv.ficgcn_server_stats()
     srv.close()
-    return out
+    assert st["scratch_overruns"] == 0
+    return out, st["resident_bytes"]
 
 
 def test_alone_equals_mix(env):
@@ -61,18 +67,18 @@ def test_alone_equals_mix(env):
 
 def test_admission_by_footprint(env):
     fg, sv, reqs = env["fg"], env["sv"], env["reqs"]
-    fp = _footprints(env)
-    s = sorted(fp)
-    # below any two requests together (when the largest still fits alone): one at a time on three slots
-    one_at_a_time = s[-1] < s[0] + s[1]
-    budget = s[0] + s[1] - 1 if one_at_a_time else s[-1]
+    fp, resident = _footprints(env)
+    s_ = sorted(fp)
+    # room for the largest request alone (and, when any two exceed it, for one at a time)
+    budget = resident + s_[-1]
     srv = fg.Server(PARAMS, 3, budget)
     st = sv.run_stream(srv, reqs, env["ev"], 0.0, 3)
     srv.close()
-    assert st["completed"] == len(reqs)
+    assert st["completed"] == len(reqs) and st["failed"] == 0
     assert st["peak_bytes"] <= budget
-    if one_at_a_time:
+    if s_[0] + s_[1] > s_[-1]:
         assert st["max_concurrent"] == 1
+    assert st["scratch_overruns"] == 0
     # a request that can never fit is refused at submission
     srv = fg.Server(PARAMS, 2, min(fp) - 1)
     q = reqs[int(np.argmin(fp))]
@@ -81,6 +87,70 @@ def test_admission_by_footprint(env):
                                  len(q.output_host))
     assert e.value.status == -5
     srv.close()
+
+
+def test_arenas_reused_in_steady_state(env):
+    """The second pass over the same requests allocates no arena: every slot's
+    arena already fits them."""
+    fg, sv, reqs = env["fg"], env["sv"], env["reqs"]
+    srv = fg.Server(PARAMS, 2, 1 << 40)
+    sv.run_stream(srv, reqs, env["ev"], 0.0, 5)
+    first = srv.ficgcn_server_stats()["arena_allocs"]
+    assert 1 <= first <= 2 * len(reqs)
+    sv.run_stream(srv, reqs, env["ev"], 0.0, 6)
+    second = srv.ficgcn_server_stats()
+    srv.close()
+    assert second["arena_allocs"] == first
+    assert second["completed"] == 2 * len(reqs) and second["scratch_overruns"] == 0
+
+
+def test_served_request_returns_oracle_words():
+    """A two-layer request served beside another, with the oracle's encoded
+    operands and the oracle's ciphertexts, returns the oracle's output words."""
+    import torch
+    from oracle import ckks, gcn, planner, execute as ex
+    from oracle.params import Params
+    from workload import make_workload
+    from paper_2506_10399_amd import ficgcn as fg, graph, serving as sv
+    w = make_workload("tiny2")
+    prm = Params.from_dict(w.params)
+    rows = gcn.normalized_rows(w.graph.n, w.neighbors, w.norm)
+    o = planner.build_plan(w.graph.n, rows, w.meta["dims"], w.activation, prm.M)
+    okeys = ckks.keygen(prm, 41, o.rot_steps(prm.M), relin=True)
+    sched = ex.schedule(prm, o)
+    ops = ex.encode_operands(prm, o, w.weights, sched)
+    cts = ex.client_encrypt(prm, o, w.x, okeys, 42)
+    want = ex.run(prm, o, okeys, cts, ops, sched)[-1]
+    ctx = fg.Context.from_dict(w.params)
+    rp, col, val = graph.normalize(w.graph.n, w.neighbors, w.norm)
+    p = fg.Plan(ctx, rp, col, val, w.graph.n, w.meta["dims"], w.weights, activation=True)
+    assert np.array_equal(p.ficgcn_plan_node_order(), o.pi)
+    _, ev = ctx.ckks_keygen(41, p.ficgcn_plan_rot_steps(), with_relin=True)
+    info = p.ficgcn_plan_info()
+    lv0, lvo = info[0]["level_in"], info[-1]["level_out"]
+    host_in = torch.empty((len(cts), 2, lv0 + 1, ctx.N), dtype=torch.int64, pin_memory=True)
+    for i, c in enumerate(cts):
+        host_in[i].copy_(ctx.ckks_ct_load(np.stack([c.c0, c.c1]), lv0))
+    operands = []
+    for lp, d in zip(o.layers, ops):
+        flat = d["P"] if lp.kind == "inter" else [d["masks"][g][s] for g in range(len(d["masks"])) for s in lp.shifts]
+        operands.append(np.concatenate([pt.m.ravel() for pt in flat]))
+    out_host = np.zeros((len(want), 2, lvo + 1, ctx.N), dtype=np.uint64)
+    # another request on the same server at the same time (its own plan, the library's encoder)
+    other = sv.make_requests(ctx, 1, 9, n_range=(100, 200), f_range=(8, 16))[0]
+    cl2, ev2 = sv.client_keys(ctx, [other], 43)
+    sv.encrypt_inputs(ctx, cl2, other, 44)
+    srv = fg.Server(w.params, 2, 1 << 40)
+    r1 = srv.ficgcn_server_submit(p, ev, host_in, len(cts), out_host, len(want), operands_host=operands)
+    r2 = srv.ficgcn_server_submit(other.plan, ev2, other.inputs_host, len(other.inputs_host), other.output_host,
+                                  len(other.output_host))
+    srv.ficgcn_server_wait(r1)
+    srv.ficgcn_server_wait(r2)
+    srv.close()
+    for i, c in enumerate(want):
+        dev = torch.from_numpy(out_host[i].view(np.int64)).cuda()
+        got = ctx.ckks_poly_store(dev, lvo, 2)
+        assert np.array_equal(got, np.stack([c.c0, c.c1])), ("output", i)
 
 
 def test_poisson_stream_reports_latency(env):
