@@ -174,19 +174,32 @@ def cpu_baseline(params, plan_info, op_counts, all_core=None, sample_features=12
 
 
 def train_cost_model():
-    """The learned cost model: SpIntra-CA layer latencies of small synthetic graphs
-    measured here (the library's own kernels), fitted by the library's MLP kernels."""
+    """The learned cost model: SpIntra-CA layer latencies measured here (the library's own
+    kernels) on synthetic graphs at both ring degrees it plans for -- many small graphs
+    at N = 2^13 and a few of 2000-20000 nodes at N = 2^16 (the ring degree is one of the
+    features) -- fitted by the library's MLP kernels."""
     from paper_2506_10399_amd import ficgcn as fg, costmodel as cm
     t0 = time.perf_counter()
     base = fg.PlanOpts(0, 1, 0, 0, 1, 0)
-    ctx_m = fg.Context.from_dict(dict(log_n=13, n_q=8, q_bits=50, n_p=2, p_bits=60, log_scale=40))
     Xs, ys = [], []
-    for c in cm.synthetic_cases(8, 100, n_range=(128, 1400)):
-        _, F, ms = cm.measure_case(ctx_m, c, base)
-        Xs.append(F)
-        ys.append(ms)
-    net, losses = cm.train(ctx_m, np.concatenate(Xs), np.concatenate(ys), epochs=300)
-    return net, dict(samples=int(sum(len(x) for x in Xs)), train_loss=[round(losses[0], 4), round(losses[-1], 5)],
+    n_small = 0
+    for prm, cases in ((dict(log_n=13, n_q=8, q_bits=50, n_p=2, p_bits=60, log_scale=40),
+                        cm.synthetic_cases(8, 100, n_range=(128, 1400))),
+                       (dict(log_n=16, n_q=8, q_bits=50, n_p=2, p_bits=60, log_scale=40),
+                        cm.synthetic_cases(3, 200, n_range=(2000, 20000)))):
+        ctx_m = fg.Context.from_dict(prm)
+        for c in cases:
+            _, F, ms = cm.measure_case(ctx_m, c, base)
+            Xs.append(F)
+            ys.append(ms)
+        if prm["log_n"] == 13:
+            n_small = int(sum(len(x) for x in Xs))
+        log("cost model samples at N=2^%d: %d (%.1f s)" % (prm["log_n"], sum(len(x) for x in Xs), time.perf_counter() - t0))
+        del ctx_m
+    net, losses = cm.train(fg.Context.from_dict(dict(log_n=13, n_q=4, q_bits=50, n_p=1, p_bits=60)),
+                           np.concatenate(Xs), np.concatenate(ys), epochs=300)
+    return net, dict(samples=int(sum(len(x) for x in Xs)), samples_n16=int(sum(len(x) for x in Xs)) - n_small,
+                     train_loss=[round(losses[0], 4), round(losses[-1], 5)],
                      measure_and_train_s=round(time.perf_counter() - t0, 1))
 
 
@@ -230,7 +243,13 @@ def run_config(name, args, net, all_core=None, with_plain=True, with_ks=True, wi
     rule_plan = fg.Plan(ctx, rp, col, val, w.graph.n, dims, w.weights, activation=w.activation, first_pack=-1,
                         low_level=True)
     plan, learned = rule_plan, None
-    if net is not None:
+    if net == "exhaustive":
+        best_x, st_x = fg.ficgcn_plan_search(ctx, rp, col, val, w.graph.n, dims, w.weights, base)
+        plan = fg.Plan(ctx, rp, col, val, w.graph.n, dims, w.weights, opts=best_x)
+        learned = dict(chosen=dict(t=best_x.t, use_noo=best_x.use_noo, TH=best_x.TH, family=best_x.family),
+                       planner="exhaustive analytic search (no learned model)")
+        log("[%s] exhaustive plan search: %s" % (name, learned))
+    elif net is not None:
         best_l, st_l = fg.ficgcn_plan_search(ctx, rp, col, val, w.graph.n, dims, w.weights, base, model=net, keep=4)
         best_x, st_x = fg.ficgcn_plan_search(ctx, rp, col, val, w.graph.n, dims, w.weights, base)
         plan = fg.Plan(ctx, rp, col, val, w.graph.n, dims, w.weights, opts=best_l)
@@ -240,6 +259,15 @@ def run_config(name, args, net, all_core=None, with_plain=True, with_ks=True, wi
                        judge_bytes=dict(learned=st_l.best_cost, exhaustive=st_x.best_cost,
                                         paper_rule=rule_plan.ficgcn_plan_cost()),
                        within_5pct=bool(st_l.best_cost <= 1.05 * st_x.best_cost))
+        # the same comparison by measured latency: the SpIntra-CA layer (the only one the
+        # candidates change) of the learned and the exhaustive pick, timed on this GPU
+        from paper_2506_10399_amd import costmodel as cm
+        case = cm.GraphCase(name, w.graph.n, rp, col, val, list(dims), w.weights)
+        same = all(getattr(best_l, f) == getattr(best_x, f) for f, _ in fg.PlanOpts._fields_)
+        ms = cm.measure_plans(ctx, case, [best_l] if same else [best_l, best_x], bool(w.activation), reps=5)
+        learned["measured_layer_ms"] = dict(learned=round(float(ms[0]), 3), exhaustive=round(float(ms[-1]), 3),
+                                            same_plan=same)
+        learned["within_5pct_measured"] = bool(ms[0] <= 1.05 * ms[-1])
         log("[%s] learned plan search: %s" % (name, learned))
     info = plan.ficgcn_plan_info()
     steps_needed = sorted(set(plan.ficgcn_plan_rot_steps()) | set(rule_plan.ficgcn_plan_rot_steps()))
@@ -556,6 +584,8 @@ def main():
     ap.add_argument("--skip-ks", action="store_true")
     ap.add_argument("--skip-top", action="store_true", help="skip the same plan from the top of the prime chain")
     ap.add_argument("--rule-plan", action="store_true", help="batched form on the paper-rule plan (no learned search)")
+    ap.add_argument("--exhaustive", action="store_true",
+                    help="plan by the exhaustive analytic search, no cost model trained (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (scale reference for HBM counters)")
     ap.add_argument("--pool", type=int, default=8, help="serving: distinct graphs in the request pool")
@@ -608,7 +638,12 @@ def main():
         all_core = oracle_sample_all_cores(w.params, *sample_levels(info0), workers)
         del ctx0, w
     torch.cuda.set_device(0)
-    net, learned_training = (None, None) if args.rule_plan else train_cost_model()
+    if args.rule_plan:
+        net, learned_training = None, None
+    elif args.exhaustive:
+        net, learned_training = "exhaustive", None
+    else:
+        net, learned_training = train_cost_model()
     if learned_training:
         log("cost model: %s" % learned_training)
 
@@ -662,7 +697,7 @@ def serving_bench(args):
     classes, CKKS N = 2^16 with 8 + 2 primes; one client's keys resident; plans by the
     learned search, inputs at the lowest level the layers need.  A pool of graphs (the
     range's largest corner, 20000 nodes x 1433 features, plus log-uniform draws, a draw
-    skipped when its ciphertexts would take the pool beyond 80 GB of host memory) is
+    skipped when its ciphertexts would take the pool beyond 128 GB of host memory) is
     encrypted once; each rate point streams args.requests requests drawn uniformly from
     the pool, each with its own plan object.  The server (4 slots, 200 GB budget
     counting keys, plan tables, arenas and scratch) first takes every request at once
@@ -684,7 +719,7 @@ def serving_bench(args):
     ctx = fg.Context.from_dict(params)
     ctx.ckks_ntt_autotune(params["n_q"] + params["n_p"])
     pool = sv.make_requests(ctx, args.pool, 505, n_range=(500, 20000), f_range=(64, 1433), model=net,
-                            corners=[(20000, 1433)], low_level=True, max_input_bytes=80e9, log=log)
+                            corners=[(20000, 1433)], low_level=True, max_input_bytes=128e9, log=log)
     cl, ev = sv.client_keys(ctx, pool, 88)
     log("client keys generated (%.1f s)" % (time.perf_counter() - t0))
     for i, q in enumerate(pool):
@@ -694,11 +729,12 @@ def serving_bench(args):
     log("serving setup %.1f s: pool %s, %.1f GB of client ciphertexts"
         % (time.perf_counter() - t0, [q.name for q in pool], in_gb))
     runs = []
-    budget = 200 * 10 ** 9
+    budget = 220 * 10 ** 9
+    n_slots = 3
 
     def one(rate, seed):
         reqs = sv.replicate(ctx, pool, args.requests, 100 + seed)
-        srv = fg.Server(params, 4, budget)
+        srv = fg.Server(params, n_slots, budget)
         t1 = time.perf_counter()
         st = sv.run_stream(srv, reqs, ev, rate, seed)
         wall = time.perf_counter() - t1
@@ -708,8 +744,13 @@ def serving_bench(args):
         st["requests"] = len(reqs)
         st["wall_s"] = round(wall, 2)
         lat = [q.result["latency_ms"] for q in reqs]
-        st["largest_request_ms"] = round(max(q.result["latency_ms"] for q in reqs if q.dims[0] == max(
-            r.dims[0] for r in reqs)), 2)
+        # per pool graph: requests, median latency and median time on a slot
+        by = {}
+        for q in reqs:
+            by.setdefault(q.name.split("#")[0], []).append(q.result)
+        st["per_graph"] = {k: dict(n=len(v), p50_ms=round(float(np.median([r["latency_ms"] for r in v])), 1),
+                                   run_p50_ms=round(float(np.median([r["run_ms"] for r in v])), 1))
+                           for k, v in sorted(by.items())}
         log("rate %s: %s" % (rate, st))
         return st, reqs, lat
 
@@ -730,7 +771,7 @@ def serving_bench(args):
                            "%d power-law graphs of 500-20000 nodes and F 64-1433 (the 20000 x 1433 corner "
                            "included), hidden 16, 2-10 classes, CKKS N=2^16 8+2 primes"
                            % (args.requests, len(pool)),
-                           slots=4, budget_bytes=budget, planner="learned", client_ciphertexts_gb=round(in_gb, 1)),
+                           slots=n_slots, budget_bytes=budget, planner="learned", client_ciphertexts_gb=round(in_gb, 1)),
                runs=runs, max_rel_err=err,
                pool=[dict(name=q.name, n_in=len(q.inputs_host), level_in=q.info[0]["level_in"],
                           input_gb=round(q.inputs_host.numel() * 8 / 1e9, 2)) for q in pool])

@@ -544,27 +544,31 @@ ficgcn_status ficgcn_mlp_train_step(ficgcn_mlp* mlp, const float* x_dev, const f
  * keeps every client's evaluation keys resident (the caller's ckks_keys
  * objects, which must outlive the server).
  * Device memory is accounted in full against hbm_budget_bytes: the resident
- * key sets (each distinct set from its first request on), the plans' weight
- * tables (each distinct plan once), and per slot an arena and a scratch
- * share.  A request's arena holds its input ciphertexts, every layer's
- * outputs and its plan's operands; its scratch share is bounded from the plan
- * (key-switch chunks of at most 3 GiB plus one job, and 64 ciphertexts at the
- * input level).  Arenas only grow, so in steady state a request allocates
- * nothing; idle slots' arenas and scratch are released when a waiting request
- * needs the room. */
+ * key sets (each distinct set from its first request on), per distinct plan
+ * its operands and weight tables (server-side data, encoded once), and per
+ * slot an arena and a scratch share.  A request's arena holds its input
+ * ciphertexts and every layer's outputs; its scratch share is bounded from the
+ * plan (key-switch chunk buffers, rotated ciphertexts and inner sums, the
+ * encoder's chunk, 64 ciphertexts).  Arenas only grow, so in steady state a
+ * request allocates nothing; idle slots' arenas and scratch are released when
+ * a waiting request needs the room.  The first request of a plan encodes its
+ * operands (or loads the request's operands_host) and builds its tables; any
+ * number of requests may then run one plan at once. */
 typedef struct ficgcn_server ficgcn_server;
 
 typedef struct {
-  const ficgcn_plan* plan;         /* the graph's plan (server side); serves one request at a time */
+  const ficgcn_plan* plan;         /* the graph's plan (server side); must outlive the server */
   const ckks_keys* eval_keys;      /* the client's keys, resident on the device */
   const uint64_t* inputs_host;     /* n_in client ciphertexts [n_in][2][level_in+1][N] in host memory
                                       (pinned for an asynchronous upload); read while the request runs */
   size_t n_in;
   uint64_t* output_host;           /* the last layer's n_out ciphertexts [n_out][2][level_out+1][N] */
   size_t n_out;
-  const uint64_t* const* operands_host;  /* NULL: the slot encodes the plan's operands (ficgcn_plan_encode);
-                                      else per layer, every operand's coefficient-form residues in operand
-                                      order, as ficgcn_plan_load_operand takes them, concatenated */
+  const uint64_t* const* operands_host;  /* taken from the plan's first submitted request only (kept
+                                      alive until that request is waited for): NULL = the plan's operands
+                                      are encoded on the device (ficgcn_plan_encode); else per layer,
+                                      every operand's coefficient-form residues in operand order, as
+                                      ficgcn_plan_load_operand takes them, concatenated */
 } ficgcn_request;
 
 typedef struct {
@@ -590,8 +594,8 @@ ficgcn_status ficgcn_server_create(const ckks_params* params, uint32_t n_slots, 
                                    ficgcn_server** out);
 /* Stops the workers after their running requests; waiting requests are dropped. */
 void ficgcn_server_destroy(ficgcn_server* server);
-/* Queues a request; ENOMEM if it can never fit the budget, EINVAL if its plan
- * has other parameters or another request of the same plan is pending. */
+/* Queues a request; ENOMEM if it can never fit the budget (with the resident
+ * keys and plans), EINVAL if its plan or keys have other parameters. */
 ficgcn_status ficgcn_server_submit(ficgcn_server* server, const ficgcn_request* req, uint64_t* id_out);
 /* Blocks until the request completes; returns its status. */
 ficgcn_status ficgcn_server_wait(ficgcn_server* server, uint64_t id, ficgcn_request_result* out);

@@ -65,18 +65,26 @@ def measure_case(ctx: fg.Context, case: GraphCase, base: fg.PlanOpts, reps: int 
                  ) -> Tuple[List[fg.PlanOpts], np.ndarray, np.ndarray]:
     """Times the batched SpIntra-CA layer of every candidate plan of one
     graph on this GPU: (candidates, features, median ms)."""
-    import torch
     cands = fg.ficgcn_plan_candidates(case.n_v, case.dims, ctx.log_n, base)
+    return cands, features_of(ctx, case, cands), measure_plans(ctx, case, cands, bool(base.activation), reps, seed)
+
+
+def measure_plans(ctx: fg.Context, case: GraphCase, opts: Sequence[fg.PlanOpts], activation: bool, reps: int = 3,
+                  seed: int = 5) -> np.ndarray:
+    """Median ms of the batched SpIntra-CA layer (the last layer) of the plan of each
+    option set, operands filled with device-drawn residues, inputs uniform words."""
+    import torch
     plans = []
     steps = set()
-    for o in cands:
+    for o in opts:
         p = fg.Plan(ctx, case.rowptr, case.col, case.val, case.n_v, case.dims, case.weights, opts=o)
         plans.append(p)
         steps.update(p.ficgcn_plan_rot_steps())
-    _, ev = ctx.ckks_keygen(seed, sorted(steps), with_relin=bool(base.activation))
+    _, ev = ctx.ckks_keygen(seed, sorted(steps), with_relin=activation)
     ms = []
     li = len(case.dims) - 2    # the SpIntra-CA layer: the last one
-    for p in plans:
+    for k in range(len(plans)):
+        p = plans[k]
         p.ficgcn_plan_fill_operands(seed)
         d = p.ficgcn_plan_info()[li]
         lv = d["level_in"]
@@ -93,7 +101,10 @@ def measure_case(ctx: fg.Context, case: GraphCase, base: fg.PlanOpts, reps: int 
             if r:
                 times.append((time.perf_counter() - t0) * 1e3)
         ms.append(float(np.median(times)))
-    return cands, features_of(ctx, case, cands), np.array(ms)
+        del ins, outs, p
+        plans[k] = None      # the plan's device operands are freed before the next one is filled
+    del ev
+    return np.array(ms)
 
 
 def init_params(seed: int, widths=WIDTHS) -> np.ndarray:

@@ -127,6 +127,18 @@ static bool ensure_mfma_weights(ckks_ctx* c, LayerPlan& lp, int K) {
   return true;
 }
 
+// Every table the layers build on first use (per-operation weights, the fused passes'
+// weights and digit planes), built now: afterwards running the plan only reads it.
+void prepare_plan_device(ckks_ctx* c, ficgcn_plan* p) {
+  for (LayerPlan& lp : p->layers) {
+    ensure_weights(c, lp);
+    ensure_fused_weights(c, lp);
+    if (lp.kind == 0) ensure_mfma_weights(c, lp, lp.K);
+    for (size_t i = 0; i < lp.ops.size(); ++i)
+      if (!lp.ops[i] && lp.op_alias[i] >= 0) lp.ops[i] = lp.ops[lp.op_alias[i]];
+  }
+}
+
 // Fused pass of one layer on its rearranged inputs (matrix-core form only)
 static void fused_pass_packed(ckks_ctx* c, LayerPlan& lp, const std::vector<uint64_t*>& outs, const PtrList& pts, int K,
                               const char* name) {

@@ -605,10 +605,6 @@ LayerGraph::~LayerGraph() {
 void release_plan_device(ficgcn_plan* p) {
   p->graphs.clear();
   for (auto& lp : p->layers) {
-    if (lp.ops_external) {
-      lp.ops_block = nullptr;
-      lp.ops_external = false;
-    }
     for (void** q : {(void**)&lp.ops_block, (void**)&lp.w_dev, &lp.wf_dev, (void**)&lp.wm_dev, (void**)&lp.pw_dev})
       if (*q) {
         (void)hipFree(*q);
@@ -616,17 +612,6 @@ void release_plan_device(ficgcn_plan* p) {
       }
     for (auto& o : lp.ops) o = nullptr;
     lp.wm_state = 0;
-  }
-}
-
-void lend_operand_blocks(ficgcn_plan* p, uint64_t* const* blocks) {
-  p->graphs.clear();   // captured graphs read the previous operand addresses
-  for (size_t li = 0; li < p->layers.size(); ++li) {
-    LayerPlan& lp = p->layers[li];
-    if (lp.ops_block && !lp.ops_external) (void)hipFree(lp.ops_block);
-    lp.ops_block = blocks ? blocks[li] : nullptr;
-    lp.ops_external = blocks != nullptr;
-    for (auto& o : lp.ops) o = nullptr;
   }
 }
 

@@ -84,7 +84,6 @@ struct LayerPlan {
   size_t op_words = 0;
   std::vector<uint64_t*> ops;
   uint64_t* ops_block = nullptr;   // one allocation for all operands
-  bool ops_external = false;       // ops_block lent by the caller (a serving slot's arena): never freed here
   // device constants for the fused kernels (built on first use)
   uint64_t* w_dev = nullptr;       // [f_out][f_in][level+1][2] residues + Shoup (per-operation form)
   void* wf_dev = nullptr;          // fused-pass weights [level+1][f_in][f_out] (split halves or residues)
@@ -148,9 +147,9 @@ void run_layer(ckks_ctx* c, const ckks_keys* ek, ficgcn_plan* p, int li, const u
                uint64_t* const* out, size_t n_out, int mode);
 // frees the plan's device memory (operands and layer constants); the plan can be encoded again
 void release_plan_device(ficgcn_plan* p);
-// places every layer's operand block at blocks[li] (caller-owned, at least op_words words each), or
-// forgets lent blocks (blocks == nullptr); encoded operands must be loaded again afterwards
-void lend_operand_blocks(ficgcn_plan* p, uint64_t* const* blocks);
+// builds every table the layers would build on first use, so that running the plan only reads it
+// (several requests may then run one plan at once)
+void prepare_plan_device(ckks_ctx* c, ficgcn_plan* p);
 // rotation steps a layer's batched execution switches keys for
 std::vector<int64_t> layer_rotation_steps(const LayerPlan& lp);
 // device bytes the plan's operands take once encoded

@@ -8,22 +8,25 @@
 // memory and a host destination for the result.
 //
 // Device memory is accounted in full: held = the resident evaluation key sets
-// (each distinct set once, from its first request on) + the plans' weight
-// tables (each distinct plan once) + every slot's arena + every slot's scratch.
-// A request needs an arena of its inputs, every layer's outputs and its
-// operands, and scratch for its batched launches (bounded from the plan: the
-// key-switch chunk budget and a margin of ciphertext buffers); it is admitted
-// to an idle slot when held, grown by what that slot's arena and scratch must
-// grow, stays within the budget; arenas of other idle slots are released
-// first when that makes the difference.  An arena only grows, so in steady
-// state a request allocates nothing: its inputs, outputs and operands are
-// carved from the slot's arena (no hipMalloc / hipFree, which would
-// synchronise the device across slots).  The waiting queue is FIFO; a later
+// (each distinct set once, from its first request on) + per distinct plan its
+// operands (the graph's masks and adjacency plaintexts, server-side data
+// encoded once) and weight tables + every slot's arena + every slot's scratch.
+// A request needs an arena of its inputs and every layer's outputs, and
+// scratch for its batched launches (bounded from the plan: the key-switch chunk
+// buffers, the rotated ciphertexts and inner sums, the encoder's chunk and a
+// margin of ciphertext buffers); it is admitted to an idle slot when held,
+// grown by what that slot's arena and scratch must grow, stays within the
+// budget; idle slots' arenas and scratch are released first when that makes
+// the difference.  An arena only grows, so in steady state a request allocates
+// nothing (no hipMalloc / hipFree, which would synchronise the device across
+// slots).  The first request of a plan encodes (or loads) its operands and
+// builds its tables under the plan's lock; from then on any number of requests
+// run the plan at once, reading it only.  The waiting queue is FIFO; a later
 // request that fits may pass a head that does not, until the head has been
 // passed 16 times (then the queue waits for it).  A slot's work for one
-// request: upload the inputs, encode (or load) the plan's operands into the
-// arena, run every layer in the batched form, download the last layer's
-// ciphertexts.  Latency = completion - submission on the server's steady clock.
+// request: upload the inputs, run every layer in the batched form, download
+// the last layer's ciphertexts.  Latency = completion - submission on the
+// server's steady clock.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -31,6 +34,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <set>
 #include <thread>
@@ -47,7 +51,7 @@ double now_ms() {
 
 struct Req {
   ficgcn_request r{};
-  size_t footprint = 0;     // arena bytes: inputs, layer outputs, operands
+  size_t footprint = 0;     // arena bytes: inputs and layer outputs
   size_t scratch = 0;       // scratch bound of its batched launches
   double t_submit = 0, t_start = 0, t_done = 0;
   int status = 0;
@@ -78,7 +82,12 @@ struct ficgcn_server {
   std::map<uint64_t, Req> reqs;
   std::deque<uint64_t> waiting;
   std::set<const ckks_keys*> keys_seen;
-  std::set<const ficgcn_plan*> plans_seen;
+  struct PlanState {
+    std::mutex m;
+    bool ready = false;
+    const uint64_t* const* ops_host = nullptr;   // the first submitted request's operands_host
+  };
+  std::map<const ficgcn_plan*, std::unique_ptr<PlanState>> plans;
   size_t budget = 0, held = 0, peak = 0, resident = 0;
   uint64_t allocs = 0, overruns = 0;
   int running = 0, max_running = 0;
@@ -95,7 +104,7 @@ constexpr size_t KS_CHUNK = (size_t)3 << 30;
 
 static size_t ct_bytes(const ckks_ctx* c, int level) { return (size_t)2 * (level + 1) * c->N * 8; }
 
-// arena layout of one request: inputs, then each layer's outputs, then each layer's operands
+// arena layout of one request: inputs, then each layer's outputs
 static size_t request_arena(const ficgcn_plan* p, std::vector<size_t>* off = nullptr) {
   const ckks_ctx* c = p->ctx;
   size_t b = 0;
@@ -105,25 +114,32 @@ static size_t request_arena(const ficgcn_plan* p, std::vector<size_t>* off = nul
   };
   take((size_t)p->layers[0].n_in_cts() * ct_bytes(c, p->layers[0].level_in));
   for (const LayerPlan& lp : p->layers) take((size_t)lp.n_packed() * ct_bytes(c, lp.level_in));
-  for (const LayerPlan& lp : p->layers) take(std::max<size_t>(1, lp.op_words) * 8);
   return b;
 }
 
-// scratch of the batched launches: every layer's key switches (one job per rotation of each
-// packed ciphertext plus the relinearisations, a source per job at most), capped by the chunk
-// budget plus one job, and 64 ciphertext buffers at the input level for everything else
+// Scratch of the batched launches, by the buffers that grow with the plan (each kept by the
+// slot's context at its largest size): the key-switch chunk buffers (sources and digits, jobs'
+// accumulators and conversions; each pair at most one chunk budget plus one entry), per
+// SpIntra-CA layer the rotated ciphertexts and inner sums of every packed ciphertext (one per
+// rotation step) and the square's tensor products, the pre-activation outputs, the device
+// encoder's chunk, and 64 ciphertexts at the widest level for everything else.
 static size_t scratch_bound(const ficgcn_plan* p) {
   const ckks_ctx* c = p->ctx;
-  size_t ks = 0, extra = 0;
+  const size_t N = c->N;
+  size_t ks_src = 0, ks_job = 0, layers = 0, widest = 0;
   for (const LayerPlan& lp : p->layers) {
-    const size_t N = c->N, l1 = lp.level_in + 1, ext = l1 + c->alpha, nd = (l1 + c->alpha - 1) / c->alpha;
+    const size_t l1 = lp.level_in + 1, ext = l1 + c->alpha, nd = (l1 + c->alpha - 1) / c->alpha;
     const size_t per_job = 2 * (ext + l1) * N * 8, per_src = (nd * ext + l1) * N * 8;
-    const size_t jobs = (layer_rotation_steps(lp).size() + (lp.act ? 1 : 0)) * (size_t)std::max(1, lp.n_packed()) +
-                        (size_t)lp.shifts.size() * std::max(1, lp.n_packed());
-    ks = std::max(ks, std::min(jobs * (per_job + per_src), KS_CHUNK + per_job + per_src));
-    extra = std::max(extra, 64 * ct_bytes(c, lp.level_in));
+    const size_t np = (size_t)std::max(1, lp.n_packed()), ct = ct_bytes(c, lp.level_in);
+    const size_t rots = layer_rotation_steps(lp).size();
+    const size_t jobs = rots * np + (lp.act ? np : 0);
+    ks_src = std::max(ks_src, std::min(jobs * per_src, KS_CHUNK) + per_src);
+    ks_job = std::max(ks_job, std::min(jobs * per_job, KS_CHUNK) + per_job);
+    layers += rots * np * ct + np * ct * 5 / 2;   // rotations / inner sums; tensor + pre-activation
+    widest = std::max(widest, ct);
   }
-  return ks + extra;
+  const size_t encoder = (size_t)32 * N * 40;
+  return ks_src + ks_job + layers + encoder + 64 * widest;
 }
 
 // device bytes of a plan's weight tables (per-operation residues, fused-pass weights): at most
@@ -212,6 +228,27 @@ static void load_operands(ckks_ctx* c, ficgcn_plan* p, const uint64_t* const* ho
   }
 }
 
+// the plan's operands and tables, once, by whichever of its requests runs first: loaded from the
+// first submitted request's operands_host, or encoded
+static void prepare(ficgcn_server* s, ckks_ctx* c, ficgcn_plan* p) {
+  ficgcn_server::PlanState* ps;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    ps = s->plans.at(p).get();
+  }
+  std::lock_guard<std::mutex> lk(ps->m);
+  if (ps->ready) return;
+  if (ps->ops_host) {
+    load_operands(c, p, ps->ops_host);
+  } else {
+    ficgcn_status st = ficgcn_plan_encode(c, p);
+    if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
+  }
+  prepare_plan_device(c, p);
+  HIPCHECK(hipStreamSynchronize(c->stream));
+  ps->ready = true;
+}
+
 static void run_request(ficgcn_server* s, Slot& sl, Req& q) {
   ckks_ctx* c = sl.c;
   ficgcn_plan* p = const_cast<ficgcn_plan*>(q.r.plan);
@@ -219,6 +256,7 @@ static void run_request(ficgcn_server* s, Slot& sl, Req& q) {
   const LayerPlan& ll = p->layers.back();
   try {
     ensure_device(c);
+    prepare(s, c, p);
     if (sl.cap_pending > sl.cap) {   // the arena grows (never shrinks while the slot works)
       if (sl.arena) {
         HIPCHECK(hipStreamSynchronize(c->stream));
@@ -239,16 +277,6 @@ static void run_request(ficgcn_server* s, Slot& sl, Req& q) {
     const size_t in_ct = ct_bytes(c, l0.level_in);
     uint8_t* din = sl.arena + off[0];
     HIPCHECK(hipMemcpyAsync(din, q.r.inputs_host, q.r.n_in * in_ct, hipMemcpyHostToDevice, c->stream));
-    // operands of this graph's plan, in the arena
-    std::vector<uint64_t*> blocks(nl);
-    for (size_t li = 0; li < nl; ++li) blocks[li] = (uint64_t*)(sl.arena + off[1 + nl + li]);
-    lend_operand_blocks(p, blocks.data());
-    if (q.r.operands_host) {
-      load_operands(c, p, q.r.operands_host);
-    } else {
-      ficgcn_status st = ficgcn_plan_encode(c, p);
-      if (st != FICGCN_OK) FICGCN_THROW(st, ficgcn_last_error());
-    }
     std::vector<const uint64_t*> cur(q.r.n_in);
     for (size_t i = 0; i < q.r.n_in; ++i) cur[i] = (const uint64_t*)(din + i * in_ct);
     for (size_t li = 0; li < nl; ++li) {
@@ -273,7 +301,6 @@ static void run_request(ficgcn_server* s, Slot& sl, Req& q) {
     q.err = e.what();
   }
   (void)hipStreamSynchronize(c->stream);
-  lend_operand_blocks(p, nullptr);   // the arena will hold another request's operands
 }
 
 static void worker(ficgcn_server* s, int k) {
@@ -394,17 +421,19 @@ ficgcn_status ficgcn_server_submit(ficgcn_server* server, const ficgcn_request* 
   q.footprint = request_arena(p);
   q.scratch = scratch_bound(p);
   std::lock_guard<std::mutex> lk(server->mu);
-  for (const auto& kv : server->reqs)
-    if (!kv.second.done && kv.second.r.plan == req->plan)
-      FICGCN_THROW(EINVAL_, "a plan may serve one request at a time");
-  // resident memory this request brings: its key set and its plan's tables, once each
+  // resident memory this request brings: its key set, its plan's operands and tables, once each
   size_t add = 0;
-  if (!server->keys_seen.count(req->eval_keys)) add += keys_bytes(req->eval_keys);
-  if (!server->plans_seen.count(p)) add += plan_tables(p);
+  const bool new_keys = !server->keys_seen.count(req->eval_keys), new_plan = !server->plans.count(p);
+  if (new_keys) add += keys_bytes(req->eval_keys);
+  if (new_plan) add += plan_tables(p) + plan_operand_bytes(p);
   if (server->resident + add + q.footprint + q.scratch > server->budget)
-    FICGCN_THROW(ENOMEM_, "request larger than the server's device budget (with resident keys and plan tables)");
-  if (!server->keys_seen.count(req->eval_keys)) server->keys_seen.insert(req->eval_keys);
-  if (!server->plans_seen.count(p)) server->plans_seen.insert(p);
+    FICGCN_THROW(ENOMEM_, "request larger than the server's device budget (with resident keys and plans)");
+  if (new_keys) server->keys_seen.insert(req->eval_keys);
+  if (new_plan) {
+    auto ps = std::unique_ptr<ficgcn_server::PlanState>(new ficgcn_server::PlanState());
+    ps->ops_host = req->operands_host;
+    server->plans.emplace(p, std::move(ps));
+  }
   server->resident += add;
   server->held += add;
   server->peak = std::max(server->peak, server->held);

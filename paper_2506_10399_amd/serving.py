@@ -57,7 +57,8 @@ def make_requests(ctx: fg.Context, n_req: int, seed: int, n_range=(500, 4000), f
     by the learned search.  corners: (n, F) shapes taken first (the range's
     extremes); low_level: the client encrypts at the lowest level the layers
     need; max_input_bytes: a drawn shape whose client ciphertexts would take the
-    pool's total beyond this is skipped and the next one drawn (host memory)."""
+    pool's total beyond this is skipped and the next one drawn (host memory); after 200
+    skips in a row the pool is taken as full (fewer than n_req graphs)."""
     from workload.graphs import chung_lu, sample_neighbors
     from workload.features import binary_features, gaussian_weights
     rng = np.random.default_rng(seed)
@@ -65,6 +66,7 @@ def make_requests(ctx: fg.Context, n_req: int, seed: int, n_range=(500, 4000), f
     total = 0.0
     corners = list(corners)
     r = 0
+    skipped = 0
     while len(out) < n_req:
         if corners:
             n, F = corners.pop(0)
@@ -74,6 +76,20 @@ def make_requests(ctx: fg.Context, n_req: int, seed: int, n_range=(500, 4000), f
         c = int(rng.integers(classes[0], classes[1] + 1))
         deg = float(rng.uniform(3.0, 5.0))
         s = int(rng.integers(1 << 30))
+        if max_input_bytes is not None and out:
+            # client ciphertexts before planning: (sampled neighbours + self) copies of F columns,
+            # at most every prime of the chain
+            est = (int(round(deg)) + 1) * F * 2 * ctx.L * ctx.N * 8.0
+            if total + est > max_input_bytes:
+                skipped += 1
+                if skipped > 200:    # the pool is full: serve what it holds
+                    if log:
+                        log("pool full at %d graphs, %.1f GB" % (len(out), total / 1e9))
+                    break
+                if log and skipped <= 3:
+                    log("skipped n=%d F=%d: about %.1f GB of ciphertexts beyond the pool's %.0f GB"
+                        % (n, F, est / 1e9, max_input_bytes / 1e9))
+                continue
         g = chung_lu(n, deg, s)
         nb = sample_neighbors(g, int(round(deg)), s + 1)
         rp, col, val = graph.normalize(n, nb, "mean")
@@ -95,6 +111,7 @@ def make_requests(ctx: fg.Context, n_req: int, seed: int, n_range=(500, 4000), f
         if max_input_bytes is not None and out and total + nbytes > max_input_bytes:
             continue
         total += nbytes
+        skipped = 0
         out.append(q)
         if log:
             log("planned %s: %d input ciphertexts, %.1f GB" % (q.name, d0["n_in_cts"], nbytes / 1e9))
@@ -102,16 +119,15 @@ def make_requests(ctx: fg.Context, n_req: int, seed: int, n_range=(500, 4000), f
 
 
 def replicate(ctx: fg.Context, pool: Sequence[ClientRequest], n_req: int, seed: int) -> List[ClientRequest]:
-    """A stream of n_req requests on graphs drawn uniformly from the pool: each
-    request has its own plan object (built with the pool entry's options, so the
-    same node order and the client's same ciphertexts) and its own output buffer;
-    graph data and the encrypted inputs are shared with the pool entry."""
+    """A stream of n_req requests on graphs drawn uniformly from the pool: each request
+    runs its pool entry's plan (the server encodes a plan's operands once and lets
+    requests share it) on the entry's encrypted inputs, with its own output buffer."""
     rng = np.random.default_rng(seed)
     out = []
     for r in range(n_req):
         q = pool[int(rng.integers(len(pool)))]
         c = ClientRequest("%s#%d" % (q.name, r), q.n_v, q.dims, q.rowptr, q.col, q.val, q.x, q.weights)
-        c.plan = fg.Plan(ctx, q.rowptr, q.col, q.val, q.n_v, q.dims, q.weights, opts=q.plan.opts)
+        c.plan = q.plan
         c.info = q.info
         c.inputs_host = q.inputs_host
         c.output_host = np.zeros_like(q.output_host)

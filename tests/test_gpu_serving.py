@@ -106,7 +106,8 @@ def test_arenas_reused_in_steady_state(env):
 
 def test_served_request_returns_oracle_words():
     """A two-layer request served beside another, with the oracle's encoded
-    operands and the oracle's ciphertexts, returns the oracle's output words."""
+    operands and the oracle's ciphertexts, returns the oracle's output words; so
+    does a second request of the same plan submitted at the same time."""
     import torch
     from oracle import ckks, gcn, planner, execute as ex
     from oracle.params import Params
@@ -140,17 +141,21 @@ def test_served_request_returns_oracle_words():
     other = sv.make_requests(ctx, 1, 9, n_range=(100, 200), f_range=(8, 16))[0]
     cl2, ev2 = sv.client_keys(ctx, [other], 43)
     sv.encrypt_inputs(ctx, cl2, other, 44)
-    srv = fg.Server(w.params, 2, 1 << 40)
+    out_again = np.zeros_like(out_host)
+    srv = fg.Server(w.params, 3, 1 << 40)
     r1 = srv.ficgcn_server_submit(p, ev, host_in, len(cts), out_host, len(want), operands_host=operands)
     r2 = srv.ficgcn_server_submit(other.plan, ev2, other.inputs_host, len(other.inputs_host), other.output_host,
                                   len(other.output_host))
-    srv.ficgcn_server_wait(r1)
-    srv.ficgcn_server_wait(r2)
+    # the same plan again at once: it shares the operands the first request loads
+    r3 = srv.ficgcn_server_submit(p, ev, host_in, len(cts), out_again, len(want))
+    for r in (r1, r2, r3):
+        srv.ficgcn_server_wait(r)
     srv.close()
-    for i, c in enumerate(want):
-        dev = torch.from_numpy(out_host[i].view(np.int64)).cuda()
-        got = ctx.ckks_poly_store(dev, lvo, 2)
-        assert np.array_equal(got, np.stack([c.c0, c.c1])), ("output", i)
+    for res in (out_host, out_again):
+        for i, c in enumerate(want):
+            dev = torch.from_numpy(res[i].view(np.int64)).cuda()
+            got = ctx.ckks_poly_store(dev, lvo, 2)
+            assert np.array_equal(got, np.stack([c.c0, c.c1])), ("output", i)
 
 
 def test_poisson_stream_reports_latency(env):
