@@ -318,6 +318,8 @@ typedef struct {
   int32_t low_level;    /* 1: the first layer's inputs sit at the lowest level the layers need (their
                            rescales, Sec. 2.1, plus one spare prime for the output) instead of the top
                            of the chain; the client encrypts at plan info level_in of layer 0 */
+  double max_key_bytes; /* plan search only: a candidate whose rotation keys take more device memory
+                           than this is infeasible (0 = no limit) */
 } ficgcn_plan_opts;
 
 /* The server's plan of the method (Sec. 3.1's workflow): latency-aware

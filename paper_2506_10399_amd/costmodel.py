@@ -61,35 +61,56 @@ def features_of(ctx: fg.Context, case: GraphCase, cands: Sequence[fg.PlanOpts]) 
                      for o in cands])
 
 
-def measure_case(ctx: fg.Context, case: GraphCase, base: fg.PlanOpts, reps: int = 3, seed: int = 5
+def measure_case(ctx: fg.Context, case: GraphCase, base: fg.PlanOpts, reps: int = 3, seed: int = 5,
+                 max_keys: int = None, per_plan_keys: bool = False
                  ) -> Tuple[List[fg.PlanOpts], np.ndarray, np.ndarray]:
-    """Times the batched SpIntra-CA layer of every candidate plan of one
-    graph on this GPU: (candidates, features, median ms)."""
+    """Times the batched SpIntra-CA layer of every candidate plan of one graph on this
+    GPU: (candidates, features, median ms); a candidate needing more than max_keys
+    rotation keys is not timed (NaN)."""
     cands = fg.ficgcn_plan_candidates(case.n_v, case.dims, ctx.log_n, base)
-    return cands, features_of(ctx, case, cands), measure_plans(ctx, case, cands, bool(base.activation), reps, seed)
+    ms = measure_plans(ctx, case, cands, bool(base.activation), reps, seed, max_keys, per_plan_keys)
+    return cands, features_of(ctx, case, cands), ms
 
 
 def measure_plans(ctx: fg.Context, case: GraphCase, opts: Sequence[fg.PlanOpts], activation: bool, reps: int = 3,
-                  seed: int = 5) -> np.ndarray:
+                  seed: int = 5, max_keys: int = None, per_plan_keys: bool = False) -> np.ndarray:
     """Median ms of the batched SpIntra-CA layer (the last layer) of the plan of each
-    option set, operands filled with device-drawn residues, inputs uniform words."""
+    option set, operands filled with device-drawn residues, inputs uniform words.  Keys:
+    one set for the plans' steps (with max_keys: plans taken by ascending key count while
+    the set stays within max_keys keys), or (per_plan_keys) a set per plan freed after it;
+    a plan left out is not timed (NaN)."""
     import torch
-    plans = []
-    steps = set()
-    for o in opts:
-        p = fg.Plan(ctx, case.rowptr, case.col, case.val, case.n_v, case.dims, case.weights, opts=o)
-        plans.append(p)
-        steps.update(p.ficgcn_plan_rot_steps())
-    _, ev = ctx.ckks_keygen(seed, sorted(steps), with_relin=activation)
+    plans = [fg.Plan(ctx, case.rowptr, case.col, case.val, case.n_v, case.dims, case.weights, opts=o) for o in opts]
+    steps = [p.ficgcn_plan_rot_steps() for p in plans]
+    ok = [max_keys is None or len(s_) <= max_keys for s_ in steps]
+    ev = None
+    if not per_plan_keys:
+        union = set()
+        if max_keys is not None:
+            # one key set for the candidates in order of their key counts, up to max_keys keys in all
+            for k in sorted(range(len(plans)), key=lambda i: len(steps[i])):
+                if ok[k] and len(union | set(steps[k])) <= max_keys:
+                    union |= set(steps[k])
+                else:
+                    ok[k] = False
+        else:
+            union = {x for s_ in steps for x in s_}
+        _, ev = ctx.ckks_keygen(seed, sorted(union), with_relin=activation)
     ms = []
     li = len(case.dims) - 2    # the SpIntra-CA layer: the last one
     for k in range(len(plans)):
+        if not ok[k]:
+            ms.append(float("nan"))
+            plans[k] = None
+            continue
         p = plans[k]
+        if per_plan_keys:
+            _, ev = ctx.ckks_keygen(seed, steps[k], with_relin=activation)
         p.ficgcn_plan_fill_operands(seed)
         d = p.ficgcn_plan_info()[li]
         lv = d["level_in"]
         ins = [ctx.ct_buffer(lv) for _ in range(d["n_in_cts"])]
-        for i, x in enumerate(ins):
+        for x in ins:
             x.random_(0, 1 << 49)     # residues below every 50-bit prime of the chain
         outs = [ctx.ct_buffer(lv) for _ in range(d["n_out_cts"])]
         times = []
@@ -102,8 +123,9 @@ def measure_plans(ctx: fg.Context, case: GraphCase, opts: Sequence[fg.PlanOpts],
                 times.append((time.perf_counter() - t0) * 1e3)
         ms.append(float(np.median(times)))
         del ins, outs, p
-        plans[k] = None      # the plan's device operands are freed before the next one is filled
-    del ev
+        plans[k] = None            # the plan's device operands are freed before the next one is filled
+        if per_plan_keys:
+            ev = None
     return np.array(ms)
 
 

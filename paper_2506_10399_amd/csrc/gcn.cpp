@@ -687,10 +687,12 @@ static void aggregate_batched(ckks_ctx* c, const ckks_keys* ek, LayerPlan& lp, c
     uint64_t* bb = (uint64_t*)dev_scratch(c, 70, std::max<size_t>(1, (size_t)np * nb) * ct_words * 8);
     auto baby = [&](int g, int64_t b) { return bb + ((size_t)g * nb + bpos.at(b)) * ct_words; };
     {
+      // key-major: the rotations of every packed ciphertext by one baby step are adjacent, so the
+      // batch reads that step's key once for all of them
       std::vector<KSJob> jobs;
       std::vector<uint64_t*> bouts;
-      for (int g = 0; g < np; ++g)
-        for (int64_t b : babies) {
+      for (int64_t b : babies)
+        for (int g = 0; g < np; ++g) {
           uint64_t gal;
           const uint64_t* key = rot_key(c, ek, b, gal);
           if (!key) {

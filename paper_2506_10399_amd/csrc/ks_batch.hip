@@ -16,6 +16,7 @@
 // grouped final step replaces "write R switched ciphertexts, read them
 // back for a masked sum" by one read of acc and conv per switch.
 #include <algorithm>
+#include <numeric>
 
 #include "internal.h"
 #include "ks_batch.h"
@@ -114,6 +115,51 @@ __global__ void k_keymac_batch(uint64_t* __restrict__ acc, const uint64_t* __res
   acc[(((size_t)r * 2 + 1) * ext + i) * N + j] = reduce128(s1, md);
 }
 
+// The same inner products with jobs taken in runs that share one key (and Galois element):
+// a thread reads its key words once and applies them to every job of its run (the rotations
+// of several ciphertexts by one step), so the key streams from HBM once per run.
+constexpr int KR_MAXD = 8;   // digits held in registers (the kernels are instantiated per digit count)
+template <int ND>
+__global__ void k_keymac_runs(uint64_t* __restrict__ acc, const uint64_t* __restrict__ D,
+                              const KSJob* __restrict__ jobs, const int* __restrict__ run_start, int ext, int l1,
+                              int L, int n_mod, int log_n, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << log_n;
+  const uint32_t j = blockIdx.x * KB + threadIdx.x;
+  const int i = blockIdx.y;
+  const int r0 = run_start[blockIdx.z], r1 = run_start[blockIdx.z + 1];
+  const KSJob j0 = jobs[r0];
+  const int m = i < l1 ? i : i - l1 + L;
+  const uint32_t jj = j0.g == 1 ? j : auto_idx(j, j0.g, log_n);
+  uint64_t k0[ND], k1[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    k0[d] = gld(j0.key + (((size_t)d * 2 + 0) * n_mod + m) * N + j);
+    k1[d] = gld(j0.key + (((size_t)d * 2 + 1) * n_mod + m) * N + j);
+  }
+  const Mod md = mods[m];
+  for (int r = r0; r < r1; ++r) {
+    const uint64_t* Du = D + (size_t)jobs[r].src * ND * ext * N;
+    u128 s0 = 0, s1 = 0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      const u128 x = Du[((size_t)d * ext + i) * N + jj];
+      s0 += x * k0[d];
+      s1 += x * k1[d];
+    }
+    acc[(((size_t)r * 2 + 0) * ext + i) * N + j] = reduce128(s0, md);
+    acc[(((size_t)r * 2 + 1) * ext + i) * N + j] = reduce128(s1, md);
+  }
+}
+
+// runs of consecutive jobs with one key and Galois element; host side
+static std::vector<int> key_runs(const std::vector<KSJob>& jobs) {
+  std::vector<int> start;
+  for (size_t r = 0; r < jobs.size(); ++r)
+    if (r == 0 || jobs[r].key != jobs[r - 1].key || jobs[r].g != jobs[r - 1].g) start.push_back((int)r);
+  start.push_back((int)jobs.size());
+  return start;
+}
+
 struct MDK {
   uint64_t hP[8];                 // floor(P/2) mod p_t
   uint64_t hQ[64];                // floor(P/2) mod q_i
@@ -205,7 +251,7 @@ static MDK mdk(ckks_ctx* c, int level) {
 }
 
 enum { S_KB_TMP = 50, S_KB_D, S_KB_ACC, S_KB_CONV, S_KB_JOBS, S_KB_SRC, S_KB_GRP, S_TB_JOBS, S_RS_PTR, S_RS_LAST,
-       S_RS_D, S_GM_TERMS, S_GM_START, S_GM_OUT };
+       S_RS_D, S_GM_TERMS, S_GM_START, S_GM_OUT, S_KB_RUNS };
 
 template <typename T>
 static T* upload(ckks_ctx* c, int slot, const std::vector<T>& v) {
@@ -295,8 +341,29 @@ void keyswitch_batch(ckks_ctx* c, int level, const std::vector<const uint64_t*>&
     }
     {
       ProfScope pk(c, "keymac");
-      hipLaunchKernelGGL(k_keymac_batch, dim3(N / KB, ext, R), dim3(KB), 0, c->stream, acc, D, jd, nd, ext, l1, c->L,
-                         c->n_mod(), c->log_n, c->t.mods);
+      const std::vector<int> runs = key_runs(cj);
+      const int n_runs = (int)runs.size() - 1;
+      if (n_runs < R && nd <= KR_MAXD) {   // some jobs share a key: each key read once per run
+        const int* rd = upload(c, S_KB_RUNS, runs);
+        const dim3 grid(N / KB, ext, n_runs);
+#define KR_LAUNCH(NDV)                                                                                          \
+  hipLaunchKernelGGL(k_keymac_runs<NDV>, grid, dim3(KB), 0, c->stream, acc, D, jd, rd, ext, l1, c->L, c->n_mod(), \
+                     c->log_n, c->t.mods)
+        switch (nd) {
+          case 1: KR_LAUNCH(1); break;
+          case 2: KR_LAUNCH(2); break;
+          case 3: KR_LAUNCH(3); break;
+          case 4: KR_LAUNCH(4); break;
+          case 5: KR_LAUNCH(5); break;
+          case 6: KR_LAUNCH(6); break;
+          case 7: KR_LAUNCH(7); break;
+          default: KR_LAUNCH(8);
+        }
+#undef KR_LAUNCH
+      } else {
+        hipLaunchKernelGGL(k_keymac_batch, dim3(N / KB, ext, R), dim3(KB), 0, c->stream, acc, D, jd, nd, ext, l1,
+                           c->L, c->n_mod(), c->log_n, c->t.mods);
+      }
       HIPCHECK(hipGetLastError());
     }
     {
@@ -388,6 +455,96 @@ __global__ void k_keymac_masked(const uint64_t* __restrict__ D, const KSJob* __r
   gst(a1, add_mod(v1, reduce128(t1, md), md.q));
 }
 
+// The masked key inner products of a chunk with its jobs taken key by key (runs of jobs
+// sharing one key and Galois element, at most KM_MAXG output groups): a thread per (coefficient,
+// limb) reads each key word once for its run and adds every job's product, times its
+// plaintext, to its group's sum.  The runs are split in n_seg segments (blockIdx.z) whose sums
+// go to P[seg][group][component] and are added to the accumulators by k_masked_combine.
+constexpr int KM_MAXG = 4;
+template <int ND>
+__global__ void k_keymac_masked_runs(const uint64_t* __restrict__ D, const KSJob* __restrict__ jobs,
+                                     const int* __restrict__ run_start, int n_runs, int n_seg,
+                                     const int* __restrict__ job_gl, int n_gl, uint64_t* __restrict__ P, int ext,
+                                     int l1, int L, int n_mod, int log_n, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << log_n;
+  const uint32_t j = blockIdx.x * KB + threadIdx.x;
+  const int i = blockIdx.y, seg = blockIdx.z;
+  const int m = i < l1 ? i : i - l1 + L;
+  const Mod md = mods[m];
+  u128 t0[KM_MAXG], t1[KM_MAXG];
+  uint64_t v0[KM_MAXG], v1[KM_MAXG];
+  int cnt[KM_MAXG];
+#pragma unroll
+  for (int g = 0; g < KM_MAXG; ++g) {
+    t0[g] = t1[g] = 0;
+    v0[g] = v1[g] = 0;
+    cnt[g] = 0;
+  }
+  const int ra = (int)((int64_t)n_runs * seg / n_seg), rb = (int)((int64_t)n_runs * (seg + 1) / n_seg);
+  for (int run = ra; run < rb; ++run) {
+    const int r0 = run_start[run], r1 = run_start[run + 1];
+    const KSJob j0 = jobs[r0];
+    const uint32_t jj = j0.g == 1 ? j : auto_idx(j, j0.g, log_n);
+    uint64_t k0[ND], k1[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      k0[d] = gld(j0.key + (((size_t)d * 2 + 0) * n_mod + m) * N + j);
+      k1[d] = gld(j0.key + (((size_t)d * 2 + 1) * n_mod + m) * N + j);
+    }
+    for (int r = r0; r < r1; ++r) {
+      const KSJob jb = jobs[r];
+      const uint64_t* Du = D + (size_t)jb.src * ND * ext * N;
+      u128 s0 = 0, s1 = 0;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        const u128 x = Du[((size_t)d * ext + i) * N + jj];
+        s0 += x * k0[d];
+        s1 += x * k1[d];
+      }
+      const uint64_t x0 = reduce128(s0, md), x1 = reduce128(s1, md);
+      u128 y0 = x0, y1 = x1;
+      if (jb.pt) {   // one job per thread block step: no divergence
+        const uint64_t p = gld(jb.pt + (size_t)i * N + j);
+        y0 = (u128)x0 * p;
+        y1 = (u128)x1 * p;
+      }
+      const int gl = job_gl[r];
+#pragma unroll
+      for (int g = 0; g < KM_MAXG; ++g)
+        if (g == gl) {
+          t0[g] += y0;
+          t1[g] += y1;
+          if (++cnt[g] == 8) {
+            v0[g] = add_mod(v0[g], reduce128(t0[g], md), md.q);
+            v1[g] = add_mod(v1[g], reduce128(t1[g], md), md.q);
+            t0[g] = t1[g] = 0;
+            cnt[g] = 0;
+          }
+        }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < KM_MAXG; ++g)
+    if (g < n_gl) {
+      P[((((size_t)seg * n_gl + g) * 2 + 0) * ext + i) * N + j] = add_mod(v0[g], reduce128(t0[g], md), md.q);
+      P[((((size_t)seg * n_gl + g) * 2 + 1) * ext + i) * N + j] = add_mod(v1[g], reduce128(t1[g], md), md.q);
+    }
+}
+
+// A_group += sum over the segments of P[seg][group] (both components, every limb of the key basis)
+__global__ void k_masked_combine(const GroupDesc* __restrict__ groups, const uint64_t* __restrict__ P, int n_gl,
+                                 int n_seg, int ext, int l1, int L, int log_n, const Mod* __restrict__ mods) {
+  const size_t N = (size_t)1 << log_n;
+  const uint32_t j = blockIdx.x * KB + threadIdx.x;
+  const int i = blockIdx.y, g = blockIdx.z >> 1, comp = blockIdx.z & 1;
+  const int m = i < l1 ? i : i - l1 + L;
+  const uint64_t q = mods[m].q;
+  uint64_t* a = groups[g].out + ((size_t)comp * ext + i) * N + j;
+  uint64_t v = gld(a);
+  for (int sg = 0; sg < n_seg; ++sg) v = add_mod(v, P[((((size_t)sg * n_gl + g) * 2 + comp) * ext + i) * N + j], q);
+  gst(a, v);
+}
+
 // out_grp (+)= (A_Q - conv) P^-1  [+ sum_r sigma_g(add0_r) (.) pt_r on component 0]
 __global__ void k_masked_final(const uint64_t* __restrict__ A, const uint64_t* __restrict__ conv, int ext, int l1,
                                MDK k, const KSJob* __restrict__ jobs, const MaskGroup* __restrict__ groups,
@@ -423,7 +580,7 @@ __global__ void k_masked_final(const uint64_t* __restrict__ A, const uint64_t* _
   gst(out + o, accumulate ? add_mod(gld(out + o), v, q) : v);
 }
 
-enum { S_KM_A = 80, S_KM_CONV, S_KM_JOBS, S_KM_GRP, S_KM_OUT, S_KM_CGRP };
+enum { S_KM_A = 80, S_KM_CONV, S_KM_JOBS, S_KM_GRP, S_KM_OUT, S_KM_CGRP, S_KM_RUNS, S_KM_GL, S_KM_P };
 
 void keyswitch_masked_sum(ckks_ctx* c, int level, const std::vector<const uint64_t*>& sources,
                           const std::vector<KSJob>& jobs, const std::vector<uint64_t*>& outs, bool accumulate) {
@@ -441,6 +598,17 @@ void keyswitch_masked_sum(ckks_ctx* c, int level, const std::vector<const uint64
   }
   for (uint64_t* o : outs)
     if (!o) FICGCN_THROW(EINVAL_, "null output");
+  // at most KM_MAXG outputs: the jobs go key by key (before chunking, so a chunk holds every use
+  // of its keys) and every key is read once for all outputs that use it
+  const bool by_key = n_grp <= KM_MAXG && nd <= KR_MAXD;
+  std::vector<KSJob> sorted_jobs;
+  if (by_key) {
+    sorted_jobs = jobs;
+    std::stable_sort(sorted_jobs.begin(), sorted_jobs.end(), [](const KSJob& x, const KSJob& y) {
+      return x.key != y.key ? x.key < y.key : x.g < y.g;
+    });
+  }
+  const std::vector<KSJob>& jl = by_key ? sorted_jobs : jobs;
   ProfScope ps(c, "ks_masked");
   // one accumulator on the key basis per output, summed over every chunk
   uint64_t* A = (uint64_t*)dev_scratch(c, S_KM_A, (size_t)n_grp * 2 * ext * N * 8);
@@ -456,33 +624,39 @@ void keyswitch_masked_sum(ckks_ctx* c, int level, const std::vector<const uint64
     dt.n_dst[d] = bc.n_dst;
   }
   size_t a = 0;
-  while (a < jobs.size()) {
+  while (a < jl.size()) {
     std::vector<int> local(sources.size(), -1);
     std::vector<const uint64_t*> srcs;
     std::vector<KSJob> cj;
     size_t b = a, bytes = 0;
-    while (b < jobs.size()) {
-      const bool new_src = local[jobs[b].src] < 0;
+    while (b < jl.size()) {
+      const bool new_src = local[jl[b].src] < 0;
       const size_t add = per_job + (new_src ? per_src : 0);
-      if (b > a && bytes + add > KS_BUDGET) break;
+      // a chunk ends between runs of one key when the jobs go key by key
+      const bool run_start = !by_key || b == a || jl[b].key != jl[b - 1].key || jl[b].g != jl[b - 1].g;
+      if (b > a && run_start && bytes + add > KS_BUDGET) break;
       bytes += add;
       if (new_src) {
-        local[jobs[b].src] = (int)srcs.size();
-        srcs.push_back(sources[jobs[b].src]);
+        local[jl[b].src] = (int)srcs.size();
+        srcs.push_back(sources[jl[b].src]);
       }
-      KSJob jc = jobs[b];
+      KSJob jc = jl[b];
       jc.src = local[jc.src];
       cj.push_back(jc);
       ++b;
     }
     // this chunk's job ranges per output, each pointing at the output's accumulator
     std::vector<GroupDesc> gds;
-    for (size_t r = 0; r < cj.size(); ++r) {
-      const int g = cj[r].grp;
-      if (r == 0 || cj[r - 1].grp != g)
-        gds.push_back(GroupDesc{A + (size_t)g * 2 * ext * N, (int)r, (int)r + 1, 1, 0});
-      else
-        gds.back().end = (int)r + 1;
+    if (by_key) {
+      for (int g = 0; g < n_grp; ++g) gds.push_back(GroupDesc{A + (size_t)g * 2 * ext * N, 0, 0, 1, 0});
+    } else {
+      for (size_t r = 0; r < cj.size(); ++r) {
+        const int g = cj[r].grp;
+        if (r == 0 || cj[r - 1].grp != g)
+          gds.push_back(GroupDesc{A + (size_t)g * 2 * ext * N, (int)r, (int)r + 1, 1, 0});
+        else
+          gds.back().end = (int)r + 1;
+      }
     }
     const int U = (int)srcs.size();
     KSJob* jd = upload(c, S_KB_JOBS, cj);
@@ -504,10 +678,40 @@ void keyswitch_masked_sum(ckks_ctx* c, int level, const std::vector<const uint64
       ProfScope pk(c, "keymac");
       if (gds.size() > 65535) FICGCN_THROW(EINVAL_, "too many outputs in one launch");
       const int n_jb = (int)(N / KB), ng = (int)gds.size();
-      const bool xcd = n_jb % 8 == 0 && (size_t)n_jb * ng < ((size_t)1 << 31);
-      const dim3 grid = xcd ? dim3(n_jb * ng, ext, 1) : dim3(n_jb, ext, ng);
-      hipLaunchKernelGGL(k_keymac_masked, grid, dim3(KB), 0, c->stream, D, jd, gd, nd, ext, l1, c->L, c->n_mod(),
-                         c->log_n, ng, xcd ? 1 : 0, c->t.mods);
+      if (by_key) {
+        // each key read once for every output that uses it; runs split in segments for parallelism
+        const std::vector<int> runs = key_runs(cj);
+        const int n_runs = (int)runs.size() - 1;
+        const int n_seg = std::max(1, std::min(32, n_runs / 8));
+        std::vector<int> kgl(cj.size());
+        for (size_t r = 0; r < cj.size(); ++r) kgl[r] = cj[r].grp;
+        const int* rd = upload(c, S_KM_RUNS, runs);
+        const int* gld_ = upload(c, S_KM_GL, kgl);
+        uint64_t* P = (uint64_t*)dev_scratch(c, S_KM_P, (size_t)n_seg * ng * 2 * ext * N * 8);
+        const dim3 grid(n_jb, ext, n_seg);
+#define KM_LAUNCH(NDV)                                                                                         \
+  hipLaunchKernelGGL(k_keymac_masked_runs<NDV>, grid, dim3(KB), 0, c->stream, D, jd, rd, n_runs, n_seg, gld_, ng, P, \
+                     ext, l1, c->L, c->n_mod(), c->log_n, c->t.mods)
+        switch (nd) {
+          case 1: KM_LAUNCH(1); break;
+          case 2: KM_LAUNCH(2); break;
+          case 3: KM_LAUNCH(3); break;
+          case 4: KM_LAUNCH(4); break;
+          case 5: KM_LAUNCH(5); break;
+          case 6: KM_LAUNCH(6); break;
+          case 7: KM_LAUNCH(7); break;
+          default: KM_LAUNCH(8);
+        }
+#undef KM_LAUNCH
+        HIPCHECK(hipGetLastError());
+        hipLaunchKernelGGL(k_masked_combine, dim3(n_jb, ext, 2 * ng), dim3(KB), 0, c->stream, gd, P, ng, n_seg, ext,
+                           l1, c->L, c->log_n, c->t.mods);
+      } else {
+        const bool xcd = n_jb % 8 == 0 && (size_t)n_jb * ng < ((size_t)1 << 31);
+        const dim3 grid = xcd ? dim3(n_jb * ng, ext, 1) : dim3(n_jb, ext, ng);
+        hipLaunchKernelGGL(k_keymac_masked, grid, dim3(KB), 0, c->stream, D, jd, gd, nd, ext, l1, c->L, c->n_mod(),
+                           c->log_n, ng, xcd ? 1 : 0, c->t.mods);
+      }
       HIPCHECK(hipGetLastError());
     }
     stream_sync(c);

@@ -364,10 +364,14 @@ ficgcn_status ficgcn_plan_search(ckks_ctx* ctx, const int32_t* rowptr, const int
   }
   double best = 0;
   int best_i = -1;
-  uint32_t built = 0;
+  uint32_t built = 0, judged = 0;
   double secs = 0;
-  auto judge = [&](size_t lo, size_t hi) {
-    for (size_t k = lo; k < hi; ++k) {
+  // a key set of N words per limb, beta digits of 2 (L + alpha) limbs, per rotation step
+  const double key_bytes = (double)((ctx->L + ctx->alpha - 1) / ctx->alpha) * 2.0 * (ctx->L + ctx->alpha) * ctx->N * 8.0;
+  // candidates in order from lo, until `want` feasible ones are judged; a candidate that cannot be
+  // built, or whose rotation keys exceed base->max_key_bytes, is infeasible
+  auto judge = [&](size_t lo, size_t want) {
+    for (size_t k = lo; k < cand.size() && judged < want; ++k) {
       const ficgcn_plan_opts& o = cand[order[k]];
       ficgcn_plan* p = nullptr;
       auto t0 = std::chrono::steady_clock::now();
@@ -375,6 +379,13 @@ ficgcn_status ficgcn_plan_search(ckks_ctx* ctx, const int32_t* rowptr, const int
       secs += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
       if (st != FICGCN_OK) continue;   // infeasible candidate (e.g. the graph does not fit a block)
       ++built;
+      size_t n_steps = 0;
+      (void)ficgcn_plan_rot_steps(p, nullptr, 0, &n_steps);
+      if (base->max_key_bytes > 0 && (double)n_steps * key_bytes > base->max_key_bytes) {
+        ficgcn_plan_destroy(p);
+        continue;
+      }
+      ++judged;
       const double b = plan_bytes(p);
       ficgcn_plan_destroy(p);
       if (best_i < 0 || b < best) {
@@ -384,7 +395,6 @@ ficgcn_status ficgcn_plan_search(ckks_ctx* ctx, const int32_t* rowptr, const int
     }
   };
   judge(0, n_try);
-  if (best_i < 0 && n_try < cand.size()) judge(n_try, cand.size());   // fallback: everything
   if (best_i < 0) FICGCN_THROW(EPLAN_, "no candidate plan could be built");
   *best_out = cand[best_i];
   if (stats_out) {

@@ -38,7 +38,7 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("first_mode", ctypes.c_int32), ("use_noo", ctypes.c_int32), ("family", ctypes.c_int32),
                 ("TH", ctypes.c_int32), ("activation", ctypes.c_int32), ("t", ctypes.c_int32),
                 ("aoo_off", ctypes.c_int32), ("cpoo", ctypes.c_double), ("first_pack", ctypes.c_int32),
-                ("agg_c", ctypes.c_double), ("low_level", ctypes.c_int32)]
+                ("agg_c", ctypes.c_double), ("low_level", ctypes.c_int32), ("max_key_bytes", ctypes.c_double)]
 
 
 class Operand(ctypes.Structure):

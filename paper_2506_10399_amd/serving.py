@@ -101,6 +101,7 @@ def make_requests(ctx: fg.Context, n_req: int, seed: int, n_range=(500, 4000), f
         if model is not None:
             base = fg.PlanOpts(0, 1, 0, 0, 1, 0)
             base.low_level = int(low_level)
+            base.max_key_bytes = 32e9   # keys of a graph's plan within an eighth of the device memory
             opts, _ = fg.ficgcn_plan_search(ctx, rp, col, val, n, dims, ws, base, model=model, keep=keep)
             q.plan = fg.Plan(ctx, rp, col, val, n, dims, ws, opts=opts)
         else:
