@@ -461,7 +461,7 @@ __global__ void k_keymac_masked(const uint64_t* __restrict__ D, const KSJob* __r
 // plaintext, to its group's sum.  The runs are split in n_seg segments (blockIdx.z) whose sums
 // go to P[seg][group][component] and are added to the accumulators by k_masked_combine.
 constexpr int KM_MAXG = 4;
-template <int ND>
+template <int ND, int NG>
 __global__ void k_keymac_masked_runs(const uint64_t* __restrict__ D, const KSJob* __restrict__ jobs,
                                      const int* __restrict__ run_start, int n_runs, int n_seg,
                                      const int* __restrict__ job_gl, int n_gl, uint64_t* __restrict__ P, int ext,
@@ -471,11 +471,11 @@ __global__ void k_keymac_masked_runs(const uint64_t* __restrict__ D, const KSJob
   const int i = blockIdx.y, seg = blockIdx.z;
   const int m = i < l1 ? i : i - l1 + L;
   const Mod md = mods[m];
-  u128 t0[KM_MAXG], t1[KM_MAXG];
-  uint64_t v0[KM_MAXG], v1[KM_MAXG];
-  int cnt[KM_MAXG];
+  u128 t0[NG], t1[NG];
+  uint64_t v0[NG], v1[NG];
+  int cnt[NG];
 #pragma unroll
-  for (int g = 0; g < KM_MAXG; ++g) {
+  for (int g = 0; g < NG; ++g) {
     t0[g] = t1[g] = 0;
     v0[g] = v1[g] = 0;
     cnt[g] = 0;
@@ -510,7 +510,7 @@ __global__ void k_keymac_masked_runs(const uint64_t* __restrict__ D, const KSJob
       }
       const int gl = job_gl[r];
 #pragma unroll
-      for (int g = 0; g < KM_MAXG; ++g)
+      for (int g = 0; g < NG; ++g)
         if (g == gl) {
           t0[g] += y0;
           t1[g] += y1;
@@ -524,7 +524,7 @@ __global__ void k_keymac_masked_runs(const uint64_t* __restrict__ D, const KSJob
     }
   }
 #pragma unroll
-  for (int g = 0; g < KM_MAXG; ++g)
+  for (int g = 0; g < NG; ++g)
     if (g < n_gl) {
       P[((((size_t)seg * n_gl + g) * 2 + 0) * ext + i) * N + j] = add_mod(v0[g], reduce128(t0[g], md), md.q);
       P[((((size_t)seg * n_gl + g) * 2 + 1) * ext + i) * N + j] = add_mod(v1[g], reduce128(t1[g], md), md.q);
@@ -689,19 +689,27 @@ void keyswitch_masked_sum(ckks_ctx* c, int level, const std::vector<const uint64
         const int* gld_ = upload(c, S_KM_GL, kgl);
         uint64_t* P = (uint64_t*)dev_scratch(c, S_KM_P, (size_t)n_seg * ng * 2 * ext * N * 8);
         const dim3 grid(n_jb, ext, n_seg);
-#define KM_LAUNCH(NDV)                                                                                         \
-  hipLaunchKernelGGL(k_keymac_masked_runs<NDV>, grid, dim3(KB), 0, c->stream, D, jd, rd, n_runs, n_seg, gld_, ng, P, \
-                     ext, l1, c->L, c->n_mod(), c->log_n, c->t.mods)
+#define KM_LAUNCH(NDV, NGV)                                                                                \
+  hipLaunchKernelGGL((k_keymac_masked_runs<NDV, NGV>), grid, dim3(KB), 0, c->stream, D, jd, rd, n_runs, n_seg, gld_, \
+                     ng, P, ext, l1, c->L, c->n_mod(), c->log_n, c->t.mods)
+#define KM_BY_G(NDV)             \
+  switch (ng) {                  \
+    case 1: KM_LAUNCH(NDV, 1); break; \
+    case 2: KM_LAUNCH(NDV, 2); break; \
+    case 3: KM_LAUNCH(NDV, 3); break; \
+    default: KM_LAUNCH(NDV, 4);  \
+  }
         switch (nd) {
-          case 1: KM_LAUNCH(1); break;
-          case 2: KM_LAUNCH(2); break;
-          case 3: KM_LAUNCH(3); break;
-          case 4: KM_LAUNCH(4); break;
-          case 5: KM_LAUNCH(5); break;
-          case 6: KM_LAUNCH(6); break;
-          case 7: KM_LAUNCH(7); break;
-          default: KM_LAUNCH(8);
+          case 1: KM_BY_G(1); break;
+          case 2: KM_BY_G(2); break;
+          case 3: KM_BY_G(3); break;
+          case 4: KM_BY_G(4); break;
+          case 5: KM_BY_G(5); break;
+          case 6: KM_BY_G(6); break;
+          case 7: KM_BY_G(7); break;
+          default: KM_BY_G(8);
         }
+#undef KM_BY_G
 #undef KM_LAUNCH
         HIPCHECK(hipGetLastError());
         hipLaunchKernelGGL(k_masked_combine, dim3(n_jb, ext, 2 * ng), dim3(KB), 0, c->stream, gd, P, ng, n_seg, ext,
@@ -1107,8 +1115,10 @@ __global__ void __launch_bounds__(GM_TB) k_group_mac_np(const MacTermNP* __restr
     for (; t + 2 <= t_end; t += 2) {
       const MacTermNP ta = terms[t], tb = terms[t + 1];
       v2 pa = {1, 1}, pb = {1, 1};
-      if (ta.pt) pa = *(gv2*)(ta.pt + (size_t)i * N + j);
-      if (tb.pt) pb = *(gv2*)(tb.pt + (size_t)i * N + j);
+      // each mask word is read once: streamed past the cache so that the baby-step words,
+      // which every giant step of this coefficient block reads again, stay in L2
+      if (ta.pt) pa = __builtin_nontemporal_load((gv2*)(ta.pt + (size_t)i * N + j));
+      if (tb.pt) pb = __builtin_nontemporal_load((gv2*)(tb.pt + (size_t)i * N + j));
       v2 xa[NP], ya[NP], xb[NP], yb[NP];
 #pragma unroll
       for (int c = 0; c < NP; ++c) {
@@ -1123,7 +1133,7 @@ __global__ void __launch_bounds__(GM_TB) k_group_mac_np(const MacTermNP* __restr
     if (t < t_end) {
       const MacTermNP ta = terms[t];
       v2 pa = {1, 1};
-      if (ta.pt) pa = *(gv2*)(ta.pt + (size_t)i * N + j);
+      if (ta.pt) pa = __builtin_nontemporal_load((gv2*)(ta.pt + (size_t)i * N + j));
       v2 xa[NP], ya[NP];
 #pragma unroll
       for (int c = 0; c < NP; ++c) {
