@@ -182,10 +182,22 @@ def keygen(prm: Params, seed: int, rot_steps: Sequence[int] = (), relin: bool = 
 # ----------------------------------------------------------------------------
 # encryption
 # ----------------------------------------------------------------------------
-def encrypt(prm: Params, seed: int, ct_id: int, s: np.ndarray, pt: Plaintext) -> Ciphertext:
-    """Symmetric encryption (the client holds sk): (-a s + e + m, a) mod Q_level."""
+def seeded_uniform(prm: Params, a_seed: int, ct_id: int, level: int) -> np.ndarray:
+    """The uniform part a of ciphertext ct_id, as the server rebuilds it from a
+    public seed: residue i is the uniform stream (CT_A, ct_id, i) keyed by a_seed,
+    in coefficient form over Q_level.  A seeded ciphertext travels as (c0, a_seed,
+    ct_id); its second polynomial is this array."""
+    mods = prm.q_level(level)
+    return np.stack([sampler.uniform(a_seed, (sampler.CT_A, ct_id, i), prm.N, m) for i, m in enumerate(mods)])
+
+
+def encrypt(prm: Params, seed: int, ct_id: int, s: np.ndarray, pt: Plaintext, a_seed: int = None) -> Ciphertext:
+    """Symmetric encryption (the client holds sk): (-a s + e + m, a) mod Q_level,
+    e from the stream (CT_E, ct_id) of `seed`, a from seeded_uniform of a_seed
+    (default: seed).  A public a_seed lets the client send c0 alone; it must key
+    no other stream (the secret and the errors are drawn under their own seeds)."""
     mods = prm.q_level(pt.level)
-    a = np.stack([sampler.uniform(seed, (sampler.CT_A, ct_id, i), prm.N, m) for i, m in enumerate(mods)])
+    a = seeded_uniform(prm, seed if a_seed is None else a_seed, ct_id, pt.level)
     e = sampler.cbd21(seed, (sampler.CT_E, ct_id, 0), prm.N)
     c0 = poly_add(poly_sub(small_to_rns(e, mods), poly_mul(a, small_to_rns(s, mods), mods, prm), mods),
                   pt.m, mods)

@@ -211,3 +211,71 @@ def test_rotation_sum_one_moddown(small):
     assert max(abs(v) for v in d) < 2 ** 20
     with pytest.raises(ValueError):
         ckks.rotate_sum(prm, keys, [cts[0]], [0])
+
+
+def _negacyclic_mod(a, b, q):
+    """Brute-force negacyclic product mod q in Python integers."""
+    n = len(a)
+    out = [0] * n
+    for i in range(n):
+        ai = int(a[i])
+        if ai == 0:
+            continue
+        for j in range(n):
+            k = i + j
+            if k < n:
+                out[k] += ai * int(b[j])
+            else:
+                out[k - n] -= ai * int(b[j])
+    return [x % q for x in out]
+
+
+def test_seeded_ciphertext_rebuilt_from_its_seed_decrypts_to_small_error(small):
+    """A ciphertext whose uniform part comes from a public seed (Sec. 2.1's
+    (-a s + e + m, a) with a rebuilt by the server from (a_seed, ct_id) alone):
+    c0 + a s - m, the product taken by brute force, is one integer of magnitude
+    at most 21 (a centred binomial of 21 coin pairs) in every residue; the second
+    polynomial is exactly the rebuilt a; the error's seed changes c0 only by the
+    difference of two such errors."""
+    prm, keys = small
+    lv = prm.L - 1
+    z = rng.uniform(-1, 1, prm.M)
+    pt = enc.encode(prm, z, prm.scale, lv)
+    ct = ckks.encrypt(prm, 3, 17, keys.s, pt, a_seed=12345)
+    a = ckks.seeded_uniform(prm, 12345, 17, lv)
+    assert np.array_equal(ct.c1, a)
+    s = [int(v) for v in keys.s]
+    errs = []
+    for i, q in enumerate(prm.q_level(lv)):
+        As = _negacyclic_mod(a[i], s, q)
+        e = [(int(ct.c0[i][j]) + As[j] - int(pt.m[i][j])) % q for j in range(prm.N)]
+        errs.append([v - q if v > q // 2 else v for v in e])
+    assert all(r == errs[0] for r in errs[1:])
+    assert max(abs(v) for v in errs[0]) <= 21 and any(v != 0 for v in errs[0])
+    # another error seed, same public seed: same a, c0 moves by a difference of errors
+    ct2 = ckks.encrypt(prm, 4, 17, keys.s, pt, a_seed=12345)
+    assert np.array_equal(ct2.c1, a)
+    q0 = prm.q[0]
+    d = [(int(x) - int(y)) % q0 for x, y in zip(ct.c0[0], ct2.c0[0])]
+    assert max(min(v, q0 - v) for v in d) <= 42 and any(v != 0 for v in d)
+    # the unseeded form draws a from the error's seed
+    assert np.array_equal(ckks.encrypt(prm, 3, 17, keys.s, pt).c1, ckks.seeded_uniform(prm, 3, 17, lv))
+    assert np.array_equal(ckks.encrypt(prm, 3, 17, keys.s, pt).c0,
+                          ckks.encrypt(prm, 3, 17, keys.s, pt, a_seed=3).c0)
+
+
+def test_seeded_uniform_residues_are_uniform():
+    """Each residue of the rebuilt uniform part is a 128-bit word reduced mod q:
+    over the 2^13 coefficients of each of four primes its mean is q/2 within five
+    standard errors, and each of its ten low bits is set half the time within
+    five standard errors."""
+    prm = Params(log_n=13, n_q=4, q_bits=50, n_p=1, p_bits=60)
+    a = ckks.seeded_uniform(prm, 2024, 5, prm.L - 1)
+    for i, q in enumerate(prm.q_level(prm.L - 1)):
+        x = a[i].astype(np.float64) / q
+        n = x.size
+        assert (a[i] < q).all()
+        assert abs(x.mean() - 0.5) < 5 / np.sqrt(12 * n)
+        for b in range(10):
+            f = ((a[i] >> np.uint64(b)) & np.uint64(1)).mean()
+            assert abs(f - 0.5) < 5 * 0.5 / np.sqrt(n)
