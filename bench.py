@@ -600,6 +600,8 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="instead: a Poisson stream of encrypted GCN requests through the server (rate sweep)")
     ap.add_argument("--requests", type=int, default=50)
+    ap.add_argument("--whole-inputs", action="store_true",
+                    help="serving: clients send whole ciphertexts instead of seeded ones")
     ap.add_argument("--keyswitch", action="store_true",
                     help="instead: key switching alone at the citation-graph parameters (hoisted rotations of one "
                          "ciphertext, rotations of distinct ciphertexts, relinearisations)")
@@ -705,11 +707,13 @@ def serving_bench(args):
     classes, CKKS N = 2^16 with 8 + 2 primes; one client's keys resident; plans by the
     learned search, inputs at the lowest level the layers need.  A pool of graphs (the
     range's largest corner, 20000 nodes x 1433 features, plus log-uniform draws, a draw
-    skipped when its ciphertexts would take the pool beyond 128 GB of host memory) is
-    encrypted once; each rate point streams args.requests requests drawn uniformly from
-    the pool, each with its own plan object.  The server (4 slots, 200 GB budget
-    counting keys, plan tables, arenas and scratch) first takes every request at once
-    (its saturated throughput), then Poisson streams at 50% and 90% of that rate."""
+    skipped when its whole ciphertexts would take the pool beyond 128 GB of host memory)
+    is encrypted once, as seeded ciphertexts unless args.whole_inputs (the client then
+    uploads first polynomials only; the server rebuilds the uniform parts from the public
+    seed); each rate point streams args.requests requests drawn uniformly from the pool,
+    each with its own plan object.  The server (3 slots, 220 GB budget counting keys,
+    plan tables, arenas and scratch) first takes every request at once (its saturated
+    throughput), then Poisson streams at 50% and 90% of that rate."""
     import torch
     from paper_2506_10399_amd import ficgcn as fg, costmodel as cm, serving as sv
     torch.cuda.set_device(0)
@@ -723,12 +727,14 @@ def serving_bench(args):
                             corners=[(20000, 1433)], low_level=True, max_input_bytes=128e9, log=log)
     cl, ev = sv.client_keys(ctx, pool, 88)
     log("client keys generated (%.1f s)" % (time.perf_counter() - t0))
+    seeded = not args.whole_inputs
     for i, q in enumerate(pool):
-        sv.encrypt_inputs(ctx, cl, q, 2000 + i)
+        # seeded: each client's public seed (apart from its error seed 2000 + i and the key seed)
+        sv.encrypt_inputs(ctx, cl, q, 2000 + i, a_seed=(900000 + i) if seeded else None)
         log("encrypted %s (%.1f s)" % (q.name, time.perf_counter() - t0))
     in_gb = sum(q.inputs_host.numel() * 8 for q in pool) / 1e9
-    log("serving setup %.1f s: pool %s, %.1f GB of client ciphertexts"
-        % (time.perf_counter() - t0, [q.name for q in pool], in_gb))
+    log("serving setup %.1f s: pool %s, %.1f GB of client uploads (%s ciphertexts)"
+        % (time.perf_counter() - t0, [q.name for q in pool], in_gb, "seeded" if seeded else "whole"))
     runs = []
     budget = 220 * 10 ** 9
     n_slots = 3
@@ -772,10 +778,12 @@ def serving_bench(args):
                            "%d power-law graphs of 500-20000 nodes and F 64-1433 (the 20000 x 1433 corner "
                            "included), hidden 16, 2-10 classes, CKKS N=2^16 8+2 primes"
                            % (args.requests, len(pool)),
-                           slots=n_slots, budget_bytes=budget, planner="learned", client_ciphertexts_gb=round(in_gb, 1)),
+                           slots=n_slots, budget_bytes=budget, planner="learned",
+                           inputs="seeded (first polynomials + public seed)" if seeded else "whole ciphertexts",
+                           client_upload_gb=round(in_gb, 1)),
                runs=runs, max_rel_err=err,
                pool=[dict(name=q.name, n_in=len(q.inputs_host), level_in=q.info[0]["level_in"],
-                          input_gb=round(q.inputs_host.numel() * 8 / 1e9, 2)) for q in pool])
+                          upload_gb=round(q.inputs_host.numel() * 8 / 1e9, 2)) for q in pool])
     print(json.dumps(out), flush=True)
 
 

@@ -156,6 +156,24 @@ ficgcn_status ckks_pt_load(ckks_ctx* ctx, const uint64_t* host_coeffs, uint32_t 
  * streams of (seed, ct_id).  EINVAL without the secret. */
 ficgcn_status ckks_encrypt(ckks_ctx* ctx, const ckks_keys* client_keys, const uint64_t* pt_dev, uint32_t level,
                            uint64_t seed, uint32_t ct_id, uint64_t* ct_dev);
+/* [client] Symmetric CKKS encryption (Sec. 2.1) into a seeded ciphertext: as
+ * ckks_encrypt, with e from the streams of (e_seed, ct_id) and the uniform part
+ * a from those of a public seed, (a_seed, ct_id), so that the client may send
+ * the first polynomial alone with (a_seed, ct_id) and the server rebuilds a with
+ * ckks_expand_seeded.  The ciphertext words are ckks_encrypt's for e_seed with a
+ * drawn from a_seed.  EINVAL without the secret, or if a_seed equals e_seed or
+ * the key set's generation seed (a public seed must key no secret stream). */
+ficgcn_status ckks_encrypt_seeded(ckks_ctx* ctx, const ckks_keys* client_keys, const uint64_t* pt_dev, uint32_t level,
+                                  uint64_t e_seed, uint64_t a_seed, uint32_t ct_id, uint64_t* ct_dev);
+/* [server] Rebuilds the uniform parts of `count` seeded ciphertexts (Sec. 2.1's
+ * fresh encryption (-a s + e + m, a), a regenerated from its public seed):
+ * cts_dev[count][2][level+1][N] (device, caller-owned), ciphertext z's second
+ * polynomial is set to a of (a_seed, ct_id0 + z) in evaluation form, its first
+ * polynomial (the client's c0) is not touched.  count = 0 is a no-op; ELEVEL
+ * for a level outside the chain; EINVAL if the ids pass 2^32 - 1.  Asynchronous
+ * on the context's stream. */
+ficgcn_status ckks_expand_seeded(ckks_ctx* ctx, uint64_t a_seed, uint32_t ct_id0, size_t count, uint32_t level,
+                                 uint64_t* cts_dev);
 /* [client] Decryption and decoding (Sec. 2.1, Sec. 2.4): n_slots slots
  * (im may be NULL) at `scale` into host arrays.  Synchronous. */
 ficgcn_status ckks_decrypt(ckks_ctx* ctx, const ckks_keys* client_keys, const uint64_t* ct_dev, uint32_t level,
@@ -562,7 +580,8 @@ typedef struct {
   const ficgcn_plan* plan;         /* the graph's plan (server side); must outlive the server */
   const ckks_keys* eval_keys;      /* the client's keys, resident on the device */
   const uint64_t* inputs_host;     /* n_in client ciphertexts [n_in][2][level_in+1][N] in host memory
-                                      (pinned for an asynchronous upload); read while the request runs */
+                                      (pinned for an asynchronous upload; evaluation-form words as the
+                                      device holds them); read while the request runs; see `seeded` */
   size_t n_in;
   uint64_t* output_host;           /* the last layer's n_out ciphertexts [n_out][2][level_out+1][N] */
   size_t n_out;
@@ -571,6 +590,12 @@ typedef struct {
                                       are encoded on the device (ficgcn_plan_encode); else per layer,
                                       every operand's coefficient-form residues in operand order, as
                                       ficgcn_plan_load_operand takes them, concatenated */
+  uint32_t seeded;                 /* nonzero: the inputs are seeded ciphertexts (ckks_encrypt_seeded) and
+                                      inputs_host holds each one's first polynomial only,
+                                      [n_in][level_in+1][N]; input i's second polynomial is rebuilt on the
+                                      device from (a_seed, a_id0 + i), as ckks_expand_seeded does */
+  uint32_t a_id0;
+  uint64_t a_seed;
 } ficgcn_request;
 
 typedef struct {

@@ -176,6 +176,7 @@ ficgcn_status ckks_keygen(ckks_ctx* ctx, uint64_t seed, const int64_t* rot_steps
     std::unique_ptr<ckks_keys> cl(new ckks_keys()), ev(new ckks_keys());
     cl->ctx = ev->ctx = ctx;
     cl->has_secret = true;
+    cl->seed = seed;
     HIPCHECK(hipMalloc(&cl->s_ntt, (size_t)nm * N * 8));
     sample_small_rns(ctx, cl->s_ntt, seed, 1, 0, 0, 0, nm, lm_q(nm));
     ntt_fwd(ctx, cl->s_ntt, nm, lm_q(nm), 1, 0);
@@ -300,7 +301,32 @@ ficgcn_status ckks_encrypt(ckks_ctx* ctx, const ckks_keys* client_keys, const ui
     check_level(ctx, level);
     REQUIRE(client_keys && client_keys->has_secret, EINVAL_, "encryption needs the client key set");
     REQUIRE(pt_dev && ct_dev, EINVAL_, "null argument");
-    encrypt_sym(ctx, client_keys->s_ntt, pt_dev, level, seed, ct_id, ct_dev);
+    encrypt_sym(ctx, client_keys->s_ntt, pt_dev, level, seed, seed, ct_id, ct_dev);
+  });
+}
+
+ficgcn_status ckks_encrypt_seeded(ckks_ctx* ctx, const ckks_keys* client_keys, const uint64_t* pt_dev, uint32_t level,
+                                  uint64_t e_seed, uint64_t a_seed, uint32_t ct_id, uint64_t* ct_dev) {
+  return guard([&] {
+    check_level(ctx, level);
+    REQUIRE(client_keys && client_keys->has_secret, EINVAL_, "encryption needs the client key set");
+    REQUIRE(pt_dev && ct_dev, EINVAL_, "null argument");
+    REQUIRE(a_seed != e_seed && a_seed != client_keys->seed, EINVAL_,
+            "the public seed must differ from the error seed and the key generation seed");
+    ensure_device(ctx);
+    encrypt_sym(ctx, client_keys->s_ntt, pt_dev, level, e_seed, a_seed, ct_id, ct_dev);
+  });
+}
+
+ficgcn_status ckks_expand_seeded(ckks_ctx* ctx, uint64_t a_seed, uint32_t ct_id0, size_t count, uint32_t level,
+                                 uint64_t* cts_dev) {
+  return guard([&] {
+    check_level(ctx, level);
+    if (count == 0) return;
+    REQUIRE(cts_dev, EINVAL_, "null argument");
+    REQUIRE(count - 1 <= (size_t)(UINT32_MAX - ct_id0), EINVAL_, "ciphertext ids beyond 32 bits");
+    ensure_device(ctx);
+    expand_seeded(ctx, a_seed, ct_id0, count, (int)level, cts_dev);
   });
 }
 

@@ -114,6 +114,7 @@ struct ckks_ctx {
 struct ckks_keys {
   ckks_ctx* ctx = nullptr;
   bool has_secret = false;
+  uint64_t seed = 0;                         // key generation seed (client object only)
   uint64_t* s_ntt = nullptr;                 // [L+alpha][N] secret in NTT form (client object only)
   std::map<uint64_t, uint64_t*> swk;         // tag -> [beta][2][L+alpha][N] NTT form (tag 0 = relin)
   ~ckks_keys();
@@ -215,8 +216,14 @@ void sample_uniform(ckks_ctx* c, uint64_t* out, uint64_t seed, uint32_t kind, ui
 void sample_small_rns(ckks_ctx* c, uint64_t* out, uint64_t seed, uint32_t kind, uint32_t a, uint32_t b,
                       int dist, int n_limbs, LimbMap map);   // dist 0 = ternary, 1 = CBD(21)
 void keygen_swk(ckks_ctx* c, uint64_t seed, const uint64_t* s_ntt, const uint64_t* sp_ntt, uint64_t tag, uint64_t* key);
-void encrypt_sym(ckks_ctx* c, const uint64_t* s_ntt, const uint64_t* m_ntt, int level, uint64_t seed, uint32_t ct_id,
-                 uint64_t* ct);
+// ct = (-a s + e + m, a): e from the stream (5, ct_id) of seed, a from the
+// stream (4, ct_id, prime) of a_seed, both in coefficient form, then NTT
+void encrypt_sym(ckks_ctx* c, const uint64_t* s_ntt, const uint64_t* m_ntt, int level, uint64_t seed, uint64_t a_seed,
+                 uint32_t ct_id, uint64_t* ct);
+// the 'a' polynomials of `count` ciphertexts cts[count][2][level+1][N] (ct z
+// from the stream (4, ct_id0 + z, prime) of a_seed), written in evaluation form;
+// the first polynomials are not touched
+void expand_seeded(ckks_ctx* c, uint64_t a_seed, uint32_t ct_id0, size_t count, int level, uint64_t* cts);
 void ew_mul(ckks_ctx* c, uint64_t* out, const uint64_t* a, const uint64_t* b, int n_limbs, LimbMap map);
 void decrypt_core(ckks_ctx* c, const uint64_t* ct, const uint64_t* s_ntt, int level, uint64_t* m);
 

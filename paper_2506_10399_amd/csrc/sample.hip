@@ -8,8 +8,11 @@
 //   CBD(21)       : popcount(x & (2^21-1)) - popcount((x >> 21) & (2^21-1))
 // Streams: secret (1,0,0); key 'a' (2, tag, digit*65536 + prime index);
 // key 'e' (3, tag, digit); ciphertext 'a' (4, id, prime index); ciphertext
-// 'e' (5, id, 0).  A rotation key's tag is its Galois element, the
+// 'e' (5, id, 0).  A ciphertext's 'a' may be keyed by a public seed of its own
+// (a seeded ciphertext: the server regenerates 'a' from that seed and the id).  A rotation key's tag is its Galois element, the
 // relinearisation key's tag is 0.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace ficgcn {
@@ -40,16 +43,18 @@ __device__ void chacha_block(uint64_t seed, uint32_t n0, uint32_t n1, uint32_t n
   for (int i = 0; i < 16; ++i) out[i] = x[i] + s[i];
 }
 
-// one thread = one block = 4 coefficients of one limb
+// one thread = one block = 4 coefficients of one limb; blockIdx.z = polynomial
+// z at out + z * poly_stride, drawn from the stream with nonce word a + z
 __global__ void k_uniform(uint64_t* __restrict__ out, uint64_t seed, uint32_t kind, uint32_t a, uint32_t b0,
-                          LimbMap map, int log_n, const Mod* __restrict__ mods) {
+                          LimbMap map, int log_n, const Mod* __restrict__ mods, size_t poly_stride) {
   const size_t N = (size_t)1 << log_n;
   const uint32_t blk = blockIdx.x * SB + threadIdx.x;
   if ((size_t)blk * 4 >= N) return;
   const int i = blockIdx.y;
   const int mi = lm_mod(map, i);
+  out += blockIdx.z * poly_stride;
   uint32_t w[16];
-  chacha_block(seed, kind, a, b0 + (uint32_t)mi, blk, w);
+  chacha_block(seed, kind, a + blockIdx.z, b0 + (uint32_t)mi, blk, w);
   const Mod m = mods[mi];
   for (int u = 0; u < 4; ++u) {
     uint64_t lo = (uint64_t)w[4 * u] | ((uint64_t)w[4 * u + 1] << 32);
@@ -62,8 +67,24 @@ void sample_uniform(ckks_ctx* c, uint64_t* out, uint64_t seed, uint32_t kind, ui
                     LimbMap map, uint32_t) {
   int nb = (c->N / 4 + SB - 1) / SB;
   hipLaunchKernelGGL(k_uniform, dim3(nb, n_limbs), dim3(SB), 0, c->stream, out, seed, kind, a, b0, map, c->log_n,
-                     c->t.mods);
+                     c->t.mods, (size_t)0);
   HIPCHECK(hipGetLastError());
+}
+
+void expand_seeded(ckks_ctx* c, uint64_t a_seed, uint32_t ct_id0, size_t count, int level, uint64_t* cts) {
+  const size_t N = c->N;
+  const int l1 = level + 1;
+  const size_t ct_words = 2 * (size_t)l1 * N;
+  const int nb = (int)((N / 4 + SB - 1) / SB);
+  constexpr size_t CHUNK = 4096;   // polynomials per launch (grid z)
+  for (size_t z0 = 0; z0 < count; z0 += CHUNK) {
+    const size_t nz = std::min(CHUNK, count - z0);
+    uint64_t* c1 = cts + z0 * ct_words + (size_t)l1 * N;
+    hipLaunchKernelGGL(k_uniform, dim3(nb, l1, (uint32_t)nz), dim3(SB), 0, c->stream, c1, a_seed, 4u,
+                       ct_id0 + (uint32_t)z0, 0u, lm_q(l1), c->log_n, c->t.mods, ct_words);
+    HIPCHECK(hipGetLastError());
+    ntt_fwd(c, c1, l1, lm_q(l1), (int)nz, ct_words);
+  }
 }
 
 // one thread = one block = 8 coefficients, written as residues of every limb
@@ -154,14 +175,13 @@ __global__ void k_enc(uint64_t* __restrict__ c0, const uint64_t* __restrict__ a,
   c0[o] = add_mod(v, m[o], md.q);
 }
 
-void encrypt_sym(ckks_ctx* c, const uint64_t* s_ntt, const uint64_t* m_ntt, int level, uint64_t seed, uint32_t ct_id,
-                 uint64_t* ct) {
+void encrypt_sym(ckks_ctx* c, const uint64_t* s_ntt, const uint64_t* m_ntt, int level, uint64_t seed, uint64_t a_seed,
+                 uint32_t ct_id, uint64_t* ct) {
   const size_t N = c->N;
   const int l1 = level + 1;
   uint64_t* c0 = ct;
   uint64_t* c1 = ct + (size_t)l1 * N;
-  sample_uniform(c, c1, seed, 4, ct_id, 0, l1, lm_q(l1), 0);
-  ntt_fwd(c, c1, l1, lm_q(l1), 1, 0);
+  expand_seeded(c, a_seed, ct_id, 1, level, ct);
   sample_small_rns(c, c0, seed, 5, ct_id, 0, 1, l1, lm_q(l1));
   ntt_fwd(c, c0, l1, lm_q(l1), 1, 0);
   hipLaunchKernelGGL(k_enc, dim3(N / SB, l1), dim3(SB), 0, c->stream, c0, c1, s_ntt, m_ntt, c->log_n, c->t.mods);

@@ -276,7 +276,15 @@ static void run_request(ficgcn_server* s, Slot& sl, Req& q) {
     // inputs
     const size_t in_ct = ct_bytes(c, l0.level_in);
     uint8_t* din = sl.arena + off[0];
-    HIPCHECK(hipMemcpyAsync(din, q.r.inputs_host, q.r.n_in * in_ct, hipMemcpyHostToDevice, c->stream));
+    if (q.r.seeded) {   // first polynomials from the client, the uniform parts rebuilt from their seed
+      const size_t half = in_ct / 2;
+      const uint8_t* src = (const uint8_t*)q.r.inputs_host;
+      for (size_t i = 0; i < q.r.n_in; ++i)
+        HIPCHECK(hipMemcpyAsync(din + i * in_ct, src + i * half, half, hipMemcpyHostToDevice, c->stream));
+      expand_seeded(c, q.r.a_seed, q.r.a_id0, q.r.n_in, l0.level_in, (uint64_t*)din);
+    } else {
+      HIPCHECK(hipMemcpyAsync(din, q.r.inputs_host, q.r.n_in * in_ct, hipMemcpyHostToDevice, c->stream));
+    }
     std::vector<const uint64_t*> cur(q.r.n_in);
     for (size_t i = 0; i < q.r.n_in; ++i) cur[i] = (const uint64_t*)(din + i * in_ct);
     for (size_t li = 0; li < nl; ++li) {
@@ -415,6 +423,8 @@ ficgcn_status ficgcn_server_submit(ficgcn_server* server, const ficgcn_request* 
     FICGCN_THROW(EINVAL_, "the plan was built for other CKKS parameters");
   if ((int)req->n_in != p->layers[0].n_in_cts()) FICGCN_THROW(EPLAN_, "wrong number of input ciphertexts");
   if ((int)req->n_out != p->layers.back().n_packed()) FICGCN_THROW(EPLAN_, "wrong number of output ciphertexts");
+  if (req->seeded && req->n_in > 0 && req->n_in - 1 > (size_t)(UINT32_MAX - req->a_id0))
+    FICGCN_THROW(EINVAL_, "seeded input ids beyond 32 bits");
   if (req->eval_keys->ctx && req->eval_keys->ctx->N != sc->N) FICGCN_THROW(EINVAL_, "keys of other parameters");
   Req q;
   q.r = *req;

@@ -31,8 +31,9 @@ class ClientRequest:
     weights: List[np.ndarray]
     plan: "fg.Plan" = None
     info: list = None
-    inputs_host: object = None      # pinned torch tensor [n_in][2][L][N]
+    inputs_host: object = None      # pinned torch tensor [n_in][2][L][N], or [n_in][L][N] when seeded
     output_host: object = None      # numpy [n_out][2][l_out+1][N]
+    a_seed: Optional[int] = None    # public seed of seeded inputs (input i has ciphertext id i)
     result: dict = field(default_factory=dict)
 
 
@@ -131,6 +132,7 @@ def replicate(ctx: fg.Context, pool: Sequence[ClientRequest], n_req: int, seed: 
         c.plan = q.plan
         c.info = q.info
         c.inputs_host = q.inputs_host
+        c.a_seed = q.a_seed
         c.output_host = np.zeros_like(q.output_host)
         out.append(c)
     return out
@@ -144,10 +146,14 @@ def client_keys(ctx: fg.Context, reqs: Sequence[ClientRequest], seed: int):
     return ctx.ckks_keygen(seed, sorted(steps), with_relin=True)
 
 
-def encrypt_inputs(ctx: fg.Context, cl: fg.Keys, q: ClientRequest, seed: int):
+def encrypt_inputs(ctx: fg.Context, cl: fg.Keys, q: ClientRequest, seed: int, a_seed: Optional[int] = None,
+                   whole: bool = False):
     """The client's Inter-CA copies (copy k of column f at k*F + f, slots in
     the plan's node order), encrypted on the device, parked in pinned host
-    memory; and a host buffer for the returned ciphertexts."""
+    memory; and a host buffer for the returned ciphertexts.  With a_seed the
+    copies are seeded ciphertexts (uniform parts from the public a_seed, copy i
+    with id i) and only their first polynomials are parked, half the upload,
+    unless `whole` asks for both polynomials."""
     import torch
     pi = q.plan.ficgcn_plan_node_order()
     src = q.plan.ficgcn_plan_copy_sources(0)
@@ -155,10 +161,12 @@ def encrypt_inputs(ctx: fg.Context, cl: fg.Keys, q: ClientRequest, seed: int):
     lv = d0["level_in"]
     K, F = d0["K"], d0["f_in"]
     N, M = ctx.N, ctx.M
+    half = a_seed is not None and not whole
+    shape = (K * F, lv + 1, N) if half else (K * F, 2, lv + 1, N)
     try:
-        host = torch.empty((K * F, 2, lv + 1, N), dtype=torch.int64, pin_memory=True)
+        host = torch.empty(shape, dtype=torch.int64, pin_memory=True)
     except RuntimeError:   # page-locked memory exhausted: a pageable buffer (the upload then blocks the slot)
-        host = torch.empty((K * F, 2, lv + 1, N), dtype=torch.int64)
+        host = torch.empty(shape, dtype=torch.int64)
     dev = torch.empty((min(256, F), 2, lv + 1, N), dtype=torch.int64, device="cuda")
     for k in range(K):
         have = src[k] >= 0
@@ -168,10 +176,14 @@ def encrypt_inputs(ctx: fg.Context, cl: fg.Keys, q: ClientRequest, seed: int):
             rows[:, pi[have]] = q.x[src[k][have], f0:f0 + nf].T
             pts = ctx.ckks_encode_batch(rows, 2.0 ** ctx.log_scale, lv)
             for i in range(nf):
-                ctx.ckks_encrypt(cl, pts[i], lv, seed, k * F + f0 + i, out=dev[i])
+                if a_seed is None:
+                    ctx.ckks_encrypt(cl, pts[i], lv, seed, k * F + f0 + i, out=dev[i])
+                else:
+                    ctx.ckks_encrypt_seeded(cl, pts[i], lv, seed, a_seed, k * F + f0 + i, out=dev[i])
             torch.cuda.synchronize()
-            host[k * F + f0:k * F + f0 + nf].copy_(dev[:nf])
+            host[k * F + f0:k * F + f0 + nf].copy_(dev[:nf, 0] if half else dev[:nf])
     q.inputs_host = host
+    q.a_seed = a_seed if half else None
     q.output_host = np.zeros((dl["n_out_cts"], 2, dl["level_out"] + 1, N), dtype=np.uint64)
 
 
@@ -202,7 +214,7 @@ def run_stream(server: fg.Server, reqs: Sequence[ClientRequest], ev: fg.Keys, ra
         if dt > 0:
             time.sleep(dt)
         ids.append(server.ficgcn_server_submit(q.plan, ev, q.inputs_host, len(q.inputs_host), q.output_host,
-                                               len(q.output_host)))
+                                               len(q.output_host), a_seed=q.a_seed))
     for q, i in zip(reqs, ids):
         q.result = server.ficgcn_server_wait(i)
     return server.ficgcn_server_stats()

@@ -92,6 +92,42 @@ def test_encrypt_matches_oracle(env):
         assert np.abs(got - z).max() < 1e-6
 
 
+def test_seeded_encryption_and_rebuild_match_oracle(env):
+    """A seeded ciphertext (uniform part from a public seed) has the oracle's
+    words; rebuilding the uniform parts of a batch from (seed, ids) restores each
+    second polynomial, across the launch's chunk of 4096 ciphertexts at the tiny
+    parameters, and leaves the first polynomials alone."""
+    import torch
+    prm, ctx, fg = env["prm"], env["ctx"], env["fg"]
+    A_SEED = 0x5EED5EED
+    for lv in (prm.L - 1, 1):
+        z = env["rng"].uniform(-1, 1, prm.M)
+        pt = enc.encode(prm, z, prm.scale, lv)
+        want = ckks.encrypt(prm, SEED + 1, 30 + lv, env["okeys"].s, pt, a_seed=A_SEED)
+        dpt = ctx.ckks_pt_load(pt.m, lv)
+        ct = ctx.ckks_encrypt_seeded(env["cl"], dpt, lv, SEED + 1, A_SEED, 30 + lv)
+        assert np.array_equal(ctx.ckks_poly_store(ct, lv, 2), _ct(want))
+        assert np.abs(ctx.ckks_decrypt(env["cl"], ct, lv, prm.scale, prm.M) - z).max() < 1e-6
+    for bad in (SEED + 1, SEED):     # the error seed, the key generation seed
+        with pytest.raises(fg.FicgcnError) as ei:
+            ctx.ckks_encrypt_seeded(env["cl"], dpt, 1, SEED + 1, bad, 0)
+        assert ei.value.status == -1
+    lv = 0 if env["name"] == "tiny" else 1
+    count, id0 = (4100, 7) if env["name"] == "tiny" else (3, 7)
+    buf = torch.randint(0, 1 << 40, (count, 2, lv + 1, prm.N), dtype=torch.int64, device="cuda")
+    c0 = buf[:, 0].clone()
+    ctx.ckks_expand_seeded(A_SEED, id0, count, lv, buf)
+    torch.cuda.synchronize()
+    assert torch.equal(buf[:, 0], c0)
+    for z in sorted({0, 1, count // 2, count - 1} | ({4095, 4096} if count > 4096 else set())):
+        got = ctx.ckks_poly_store(buf[z].contiguous(), lv, 2)[1]
+        assert np.array_equal(got, ckks.seeded_uniform(prm, A_SEED, id0 + z, lv)), z
+    ctx.ckks_expand_seeded(A_SEED, 0, 0, lv, buf)     # no ciphertexts: nothing to do
+    with pytest.raises(fg.FicgcnError) as ei:
+        ctx.ckks_expand_seeded(A_SEED, 0, 1, prm.L, buf)
+    assert ei.value.status == -2
+
+
 def test_rotate_hoisted_matches_oracle(env):
     prm, ctx = env["prm"], env["ctx"]
     for lv in (prm.L - 1, 2):

@@ -169,3 +169,26 @@ def test_poisson_stream_reports_latency(env):
     assert st["throughput_per_s"] > 0
     for q in reqs:
         assert abs(q.result["latency_ms"] - q.result["queue_ms"] - q.result["run_ms"]) < 1e-6
+
+
+def test_seeded_inputs_return_the_words_of_whole_inputs(env):
+    """A request sent as seeded ciphertexts (each input's first polynomial and a
+    public seed; the server rebuilds the uniform parts) returns the words of the
+    same ciphertexts sent whole, beside an unseeded request; the upload is half."""
+    import dataclasses
+    fg, sv, ctx = env["fg"], env["sv"], env["ctx"]
+    base = env["reqs"][1]
+    whole = dataclasses.replace(base, result={})
+    seeded = dataclasses.replace(base, result={})
+    sv.encrypt_inputs(ctx, env["cl"], whole, 4001, a_seed=0xABCDEF, whole=True)
+    sv.encrypt_inputs(ctx, env["cl"], seeded, 4001, a_seed=0xABCDEF)
+    assert seeded.a_seed == 0xABCDEF and whole.a_seed is None
+    assert seeded.inputs_host.numel() * 2 == whole.inputs_host.numel()
+    assert bool((seeded.inputs_host == whole.inputs_host[:, 0]).all())
+    other = dataclasses.replace(env["reqs"][0], result={}, output_host=np.zeros_like(env["reqs"][0].output_host))
+    srv = fg.Server(PARAMS, 2, 1 << 40)
+    st = sv.run_stream(srv, [seeded, other, whole], env["ev"], 0.0, 9)
+    srv.close()
+    assert st["completed"] == 3 and st["failed"] == 0
+    assert np.array_equal(seeded.output_host, whole.output_host)
+    assert sv.decrypt_error(ctx, env["cl"], seeded) < 1e-3

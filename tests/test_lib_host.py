@@ -403,6 +403,10 @@ def test_operand_descriptors_checked_before_any_device_work(fg):
     assert status(ctx.ckks_rotate_hoisted_op, fg.Keys(ctx, None), op(3, 2.0 ** 40), [1, 2], outs) == -2
     assert [(o.level, o.scale) for o in outs] == [(3, 0.0), (2, 0.0)]
     assert status(ctx.ckks_decrypt_op, fg.Keys(ctx, None), op(3, 2.0 ** 40, 1), 4) == -1
+    # seeded ciphertexts: ids past 32 bits, a level beyond the chain, no secret
+    assert status(ctx.ckks_expand_seeded, 1, 2 ** 32 - 2, 3, 0, fake) == -1
+    assert status(ctx.ckks_expand_seeded, 1, 0, 1, 4, fake) == -2
+    assert status(ctx.ckks_encrypt_seeded, fg.Keys(ctx, None), fake, 0, 1, 2, 0, fake) == -1
 
 
 def test_search_rejects_plans_whose_keys_exceed_the_limit(fg):
