@@ -90,6 +90,7 @@ __global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void
   const size_t limb_off = ((size_t)comp * l1 + i) * N;
   const size_t off = limb_off + tile * 16 + r;
   const Mod m = mods[i];
+  const bool q50 = m.q > (1ull << 49) && m.q < (1ull << 50);
   const int KK = K > 0 ? K : 1;
   const int n_steps = KK * n_fb;   // (copy, block) steps, block-fastest
   // Strided inputs are read with buffer loads: one wave-uniform resource per
@@ -113,7 +114,7 @@ __global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 #pragma unroll
     for (int e = e0; e < e0 + n; ++e) {
       if (STRIDED) {
-        const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff[e], 0, 0);
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff[e], 0, 2);   // read once: nontemporal
         x[e] = ((uint64_t)w[1] << 32) | w[0];
       } else {
         const int f = fb * 64 + e + g * 16;
@@ -179,18 +180,52 @@ __global__ __launch_bounds__(MW) __attribute__((amdgpu_waves_per_eu(2, 2))) void
       }
       if (last) {
         // copy k done: fold the diagonals and add P_k (.) T
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          u128 sum = 0;
+        if (q50) {
+          // T = sum_d D_d [256^d]_q with the weights split as p0 + p1 2^25 (both below 2^25):
+          // s0 = sum_d D_d p0_d and s1 = sum_d D_d p1_d are exact in 64 bits (13 terms below
+          // 2^56 in magnitude), X = s0 + s1 2^25 lies in (-2^86, 2^86), and X + q 2^37 (a
+          // multiple of q, at least 2^86 for q > 2^49) is reduced once
+          uint32_t p0[13], p1[13];
 #pragma unroll
           for (int d = 0; d < 13; ++d) {
-            const int v = acc[d][rr];
-            const uint64_t res = v >= 0 ? (uint64_t)v : m.q - (uint64_t)(-(int64_t)v);
-            sum += (u128)res * pw[d];
+            const uint64_t w = pw[d];
+            p0[d] = (uint32_t)w & ((1u << 25) - 1);
+            p1[d] = (uint32_t)(w >> 25);
           }
-          uint64_t t = reduce128(sum, m);
-          if (K > 0) t = reduce128((u128)t * pk[rr], m);
-          h[rr] = add_mod(h[rr], t, m.q);
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            int64_t s0 = 0, s1 = 0;
+#pragma unroll
+            for (int d = 0; d < 13; ++d) {
+              const int64_t v = acc[d][rr];
+              s0 += v * (int64_t)p0[d];
+              s1 += v * (int64_t)p1[d];
+            }
+            uint64_t lo = (uint64_t)s1 << 25, hi = (uint64_t)(s1 >> 39);
+            const uint64_t l2 = lo + (uint64_t)s0;
+            hi += (uint64_t)(s0 >> 63) + (l2 < lo ? 1u : 0u);
+            lo = l2;
+            const uint64_t l3 = lo + (m.q << 37);
+            hi += (m.q >> 27) + (l3 < lo ? 1u : 0u);
+            lo = l3;
+            uint64_t t = reduce128(hi, lo, m);
+            if (K > 0) t = reduce128((u128)t * pk[rr], m);
+            h[rr] = add_mod(h[rr], t, m.q);
+          }
+        } else {
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            u128 sum = 0;
+#pragma unroll
+            for (int d = 0; d < 13; ++d) {
+              const int v = acc[d][rr];
+              const uint64_t res = v >= 0 ? (uint64_t)v : m.q - (uint64_t)(-(int64_t)v);
+              sum += (u128)res * pw[d];
+            }
+            uint64_t t = reduce128(sum, m);
+            if (K > 0) t = reduce128((u128)t * pk[rr], m);
+            h[rr] = add_mod(h[rr], t, m.q);
+          }
         }
 #pragma unroll
         for (int s = 0; s < 13; ++s) acc[s] = v4i{0, 0, 0, 0};

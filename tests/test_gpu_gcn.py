@@ -23,9 +23,11 @@ def _ct(c):
     return np.stack([c.c0, c.c1])
 
 
-def _setup(name, mode, family=None, cpoo=None, t=None, low_level=False, **kw):
+def _setup(name, mode, family=None, cpoo=None, t=None, low_level=False, params=None, **kw):
     from paper_2506_10399_amd import ficgcn as fg, graph
     w = make_workload(name, **kw)
+    if params:
+        w.params = dict(w.params, **params)
     prm = Params.from_dict(w.params)
     rows = gcn.normalized_rows(w.graph.n, w.neighbors, w.norm)
     ref = gcn.gcn_forward(rows, w.x, w.weights, w.activation)
@@ -283,6 +285,21 @@ def test_rearranged_inputs_refuse_primes_of_51_bits_or_more():
     out = torch.empty(words, dtype=torch.int64, device="cuda")
     st = fg.lib().ficgcn_plan_pack_inputs(ctx.h, p.h, 0, fg._ptr_array(ins), len(ins), fg._ptr(out), out.numel())
     assert st != 0
+
+
+def test_fused_pass_with_primes_of_52_bits_bit_exact():
+    """The fused Inter-CA + combination pass folds each output's digit diagonals through
+    two 64-bit sums of split weights when the prime lies in (2^49, 2^50), through 128-bit
+    sums otherwise: with 52-bit primes (the second way) the batched layer still gives
+    the oracle's words, and with the chain's 50-bit primes every other test covers the
+    first way."""
+    e = _setup("tiny", "inter", params=dict(q_bits=52))
+    assert min(e["ctx"].ckks_ctx_moduli()[:e["prm"].L]) >= 1 << 51
+    _load_operands(e)
+    for m in (0, 1):
+        for li, ((outs, lvo), want) in enumerate(zip(_run_gpu(e, m), e["outs"])):
+            for g, (a, b) in enumerate(zip(outs, want)):
+                assert np.array_equal(e["ctx"].ckks_poly_store(a, lvo, 2), _ct(b)), (m, li, g)
 
 
 @pytest.mark.parametrize("t,family", [(1, 2), (2, 2), (1, 1)])
