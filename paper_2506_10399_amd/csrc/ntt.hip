@@ -65,7 +65,11 @@ __device__ __forceinline__ void bf_inv(uint64_t& x, uint64_t& y, uint64_t w, uin
 //   * a sum or difference t in (-2q, 2q) is brought back by t - q*rint(t/q),
 //     which lands in [-q/2 - 1, q/2 + 1] (t/q is known to 2^-51);
 // three fp64 operations each, in place of a compare, an add and two selects.
-// The last pass maps the values to [0, q) once.
+// Sums are brought back on every other stage only (and on a pass's last stage):
+// a product with a in (-2q, 2q) still lands in (-3q/2, 3q/2) (the estimate
+// error grows to below 1/2 + 1/2, |lo| < q/2), so the next stage's sums stay
+// within (-4q, 4q), exact integers below 2^52, and t - q*rint(t/q) brings them
+// back as before.  The last pass maps the values to [0, q) once.
 __device__ __forceinline__ uint64_t f2b(double d) { return (uint64_t)__double_as_longlong(d); }
 __device__ __forceinline__ double b2f(uint64_t b) { return __longlong_as_double((long long)b); }
 // Exact conversions for integers below 2^52: the double 2^52 + v has v as its
@@ -98,11 +102,11 @@ __device__ __forceinline__ double canon(double r, double q) { return r < 0.0 ? r
 
 template <bool FP>
 __device__ __forceinline__ void bfly_fwd(uint64_t& x, uint64_t& y, uint64_t w, uint64_t ws, uint64_t q, double qd,
-                                         double qinv) {
+                                         double qinv, bool red = true) {
   if (FP) {
     const double xd = b2f(x), v = fmulmod_s(b2f(y), b2f(w), qd, qinv);
-    x = f2b(sred(xd + v, qd, qinv));
-    y = f2b(sred(xd - v, qd, qinv));
+    x = f2b(red ? sred(xd + v, qd, qinv) : xd + v);
+    y = f2b(red ? sred(xd - v, qd, qinv) : xd - v);
   } else {
     bf_fwd(x, y, w, ws, q);
   }
@@ -110,11 +114,11 @@ __device__ __forceinline__ void bfly_fwd(uint64_t& x, uint64_t& y, uint64_t w, u
 
 template <bool FP>
 __device__ __forceinline__ void bfly_inv(uint64_t& x, uint64_t& y, uint64_t w, uint64_t ws, uint64_t q, double qd,
-                                         double qinv) {
+                                         double qinv, bool red = true) {
   if (FP) {
     const double xd = b2f(x), yd = b2f(y);
-    x = f2b(sred(xd + yd, qd, qinv));
-    y = f2b(fmulmod_s(sred(xd - yd, qd, qinv), b2f(w), qd, qinv));
+    x = f2b(red ? sred(xd + yd, qd, qinv) : xd + yd);
+    y = f2b(fmulmod_s(red ? sred(xd - yd, qd, qinv) : xd - yd, b2f(w), qd, qinv));
   } else {
     bf_inv(x, y, w, ws, q);
   }
@@ -171,7 +175,8 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* s, uint64_t* a, const ui
         for (int u = 0; u < EPT; ++u)
           if ((u & tu) == 0) {
             const int i = u / (2 * tu);
-            bfly_fwd<FP>(x[u], x[u + tu], w[(1 << st) + i - 1], ws[(1 << st) + i - 1], q, qd, qinv);
+            bfly_fwd<FP>(x[u], x[u + tu], w[(1 << st) + i - 1], ws[(1 << st) + i - 1], q, qd, qinv,
+                         (st & 1) || st == LOGC - 1);
           }
       }
     }
@@ -207,7 +212,7 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* s, uint64_t* a, const ui
         for (int v = 0; v < EPT; ++v)
           if ((v & t) == 0) {
             const int gi = v / (2 * t);
-            bfly_fwd<FP>(x[v], x[v + t], w[pos + gi], ws[pos + gi], q, qd, qinv);
+            bfly_fwd<FP>(x[v], x[v + t], w[pos + gi], ws[pos + gi], q, qd, qinv, (st & 1) || st == LOGC - 1);
           }
         pos += ng;
       }
@@ -271,7 +276,7 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* s, uint64_t* a, const ui
         for (int v = 0; v < EPT; ++v)
           if ((v & t) == 0) {
             const int gi = v / (2 * t);
-            bfly_inv<FP>(x[v], x[v + t], w[pos + gi], ws[pos + gi], q, qd, qinv);
+            bfly_inv<FP>(x[v], x[v + t], w[pos + gi], ws[pos + gi], q, qd, qinv, ((LOGC - 1 - st) & 1) || st == 0);
           }
         pos += ng;
       }
@@ -300,7 +305,8 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* s, uint64_t* a, const ui
         for (int u = 0; u < EPT; ++u)
           if ((u & tu) == 0) {
             const int i = u / (2 * tu);
-            bfly_inv<FP>(x[u], x[u + tu], w[(1 << st) + i - 1], ws[(1 << st) + i - 1], q, qd, qinv);
+            bfly_inv<FP>(x[u], x[u + tu], w[(1 << st) + i - 1], ws[(1 << st) + i - 1], q, qd, qinv,
+                         ((LOGC - 1 - st) & 1) || st == 0);
           }
       }
     }
