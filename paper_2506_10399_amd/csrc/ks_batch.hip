@@ -19,6 +19,7 @@
 #include <numeric>
 
 #include "internal.h"
+#include "fpmod.h"
 #include "ks_batch.h"
 
 namespace ficgcn {
@@ -1052,17 +1053,21 @@ void group_mac(ckks_ctx* c, int level, const std::vector<std::vector<MacTerm>>& 
 // GM_TB threads per block: the baby-step ciphertexts of one block's 2 GM_TB coefficients
 // (every packed ciphertext, both components) stay in L2 while the masks stream past them.
 //
-// Products (L25 = every prime of the level below 2^50): a word w < 2^50 is split into
+// Products, by the level's primes: all in (2^49, 2^50) (AR = 2): fp64 residues, each
+// product an exact signed representative in (-q, q) from one fp64 product and its fma
+// error term (fpmod.h), summed in doubles and brought back every six terms; the 24
+// accumulators take a third of the registers of the integer forms, so five waves fit
+// per SIMD instead of three.  All below 2^50 (AR = 1): a word w < 2^50 is split into
 // w0 = w mod 2^25 and w1 = floor(w / 2^25), both below 2^25, and
 //   x p = x0 p0 + (x0 p1 + x1 p0) 2^25 + x1 p1 2^50;
 // the three partial sums are kept in 64-bit registers, each partial product added by one
 // 32 x 32 + 64 multiply-add (every partial below 2^51, so GM_MAX_TERMS terms fit), and the
-// group's sum is assembled to 128 bits and reduced once at the end.  Otherwise (wider
-// primes) products are summed in 128 bits and reduced every four terms.
+// group's sum is assembled to 128 bits and reduced once at the end.  Otherwise (AR = 0,
+// wider primes) products are summed in 128 bits and reduced every four terms.
 constexpr int GM_TB = 128;
 constexpr int GM_MAX_TERMS = 8191;   // 64-bit partial sums: 8191 * 2^51 < 2^64
 
-template <int NP, bool L25>
+template <int NP, int AR>
 __global__ void __launch_bounds__(GM_TB) k_group_mac_np(const MacTermNP* __restrict__ terms, const int* __restrict__ group_start,
                                uint64_t* const* __restrict__ outs, int l1, int accumulate, int log_n, int n_groups,
                                int xcd_order, const Mod* __restrict__ mods) {
@@ -1087,7 +1092,72 @@ __global__ void __launch_bounds__(GM_TB) k_group_mac_np(const MacTermNP* __restr
   int t = group_start[g];
   // per ciphertext, the four words of a thread: component 0 at j, j+1, component 1 at j, j+1
   uint64_t res[NP][4];
-  if (L25) {
+  if (AR == 2) {
+    // fp64 residues (every prime in (2^49, 2^50)): each product a signed representative in
+    // (-q, q), summed in a double; six terms at most between reductions keep every sum an
+    // exact integer below 2^53
+    const double qd = (double)m.q, qinv = 1.0 / qd;
+    double S[NP][4];
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) S[c][k] = 0.0;
+    auto cv = [](uint64_t v) { return b2f(to_fbits(v)); };
+    auto mac = [&](const v2& p, const v2 (&x)[NP], const v2 (&y)[NP]) {
+      const double p0 = cv(p.x), p1 = cv(p.y);
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+        S[c][0] += fmulmod_s(cv(x[c].x), p0, qd, qinv);
+        S[c][1] += fmulmod_s(cv(x[c].y), p1, qd, qinv);
+        S[c][2] += fmulmod_s(cv(y[c].x), p0, qd, qinv);
+        S[c][3] += fmulmod_s(cv(y[c].y), p1, qd, qinv);
+      }
+    };
+    auto fold = [&]() {
+#pragma unroll
+      for (int c = 0; c < NP; ++c)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) S[c][k] = sred(S[c][k], qd, qinv);
+    };
+    int cnt = 0;
+    for (; t + 2 <= t_end; t += 2) {
+      const MacTermNP ta = terms[t], tb = terms[t + 1];
+      v2 pa = {1, 1}, pb = {1, 1};
+      if (ta.pt) pa = __builtin_nontemporal_load((gv2*)(ta.pt + (size_t)i * N + j));
+      if (tb.pt) pb = __builtin_nontemporal_load((gv2*)(tb.pt + (size_t)i * N + j));
+      v2 xa[NP], ya[NP], xb[NP], yb[NP];
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+        xa[c] = *(gv2*)(ta.ct[c] + o0);
+        ya[c] = *(gv2*)(ta.ct[c] + o1);
+        xb[c] = *(gv2*)(tb.ct[c] + o0);
+        yb[c] = *(gv2*)(tb.ct[c] + o1);
+      }
+      mac(pa, xa, ya);
+      mac(pb, xb, yb);
+      if ((cnt += 2) == 6) {
+        fold();
+        cnt = 0;
+      }
+    }
+    if (t < t_end) {
+      const MacTermNP ta = terms[t];
+      v2 pa = {1, 1};
+      if (ta.pt) pa = __builtin_nontemporal_load((gv2*)(ta.pt + (size_t)i * N + j));
+      v2 xa[NP], ya[NP];
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+        xa[c] = *(gv2*)(ta.ct[c] + o0);
+        ya[c] = *(gv2*)(ta.ct[c] + o1);
+      }
+      mac(pa, xa, ya);
+    }
+    fold();
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) res[c][k] = from_fbits(f2b(canon(S[c][k], qd)));
+  } else if (AR == 1) {
     constexpr uint32_t M25 = (1u << 25) - 1;
     uint64_t A[NP][4], B[NP][4], C[NP][4];
 #pragma unroll
@@ -1252,23 +1322,30 @@ void group_mac_np(ckks_ctx* c, int level, int np, const std::vector<std::vector<
   const int acc = accumulate ? 1 : 0;
   // split-limb products need every prime of the level below 2^50 and at most GM_MAX_TERMS
   // terms per group
-  bool l25 = true;
-  for (int i = 0; i <= level; ++i) l25 = l25 && c->mod[i] < (1ull << 50);
-  for (size_t gi = 0; gi < groups.size(); ++gi) l25 = l25 && groups[gi].size() <= (size_t)GM_MAX_TERMS;
-  ProfScope ps(c, "bsgs_inner");   // the launch alone (its tables are uploaded above)
-#define GM_LAUNCH(NPV, LV)                                                                                     \
-  hipLaunchKernelGGL((k_group_mac_np<NPV, LV>), grid, dim3(GM_TB), 0, c->stream, td, sd, od, level + 1, acc, \
-                     c->log_n, ng, xcd ? 1 : 0, c->t.mods)
-  switch (np * 2 + (l25 ? 1 : 0)) {
-    case 2: GM_LAUNCH(1, false); break;
-    case 3: GM_LAUNCH(1, true); break;
-    case 4: GM_LAUNCH(2, false); break;
-    case 5: GM_LAUNCH(2, true); break;
-    case 6: GM_LAUNCH(3, false); break;
-    case 7: GM_LAUNCH(3, true); break;
-    case 8: GM_LAUNCH(4, false); break;
-    default: GM_LAUNCH(4, true);
+  bool l25 = true, f50 = true;
+  for (int i = 0; i <= level; ++i) {
+    l25 = l25 && c->mod[i] < (1ull << 50);
+    f50 = f50 && c->mod[i] > (1ull << 49) && c->mod[i] < (1ull << 50);
   }
+  for (size_t gi = 0; gi < groups.size(); ++gi) l25 = l25 && groups[gi].size() <= (size_t)GM_MAX_TERMS;
+  const int ar = f50 ? 2 : l25 ? 1 : 0;
+  ProfScope ps(c, "bsgs_inner");   // the launch alone (its tables are uploaded above)
+#define GM_LAUNCH(NPV, AV)                                                                                     \
+  hipLaunchKernelGGL((k_group_mac_np<NPV, AV>), grid, dim3(GM_TB), 0, c->stream, td, sd, od, level + 1, acc, \
+                     c->log_n, ng, xcd ? 1 : 0, c->t.mods)
+#define GM_BY_AR(NPV)          \
+  switch (ar) {                \
+    case 0: GM_LAUNCH(NPV, 0); break; \
+    case 1: GM_LAUNCH(NPV, 1); break; \
+    default: GM_LAUNCH(NPV, 2);       \
+  }
+  switch (np) {
+    case 1: GM_BY_AR(1); break;
+    case 2: GM_BY_AR(2); break;
+    case 3: GM_BY_AR(3); break;
+    default: GM_BY_AR(4);
+  }
+#undef GM_BY_AR
 #undef GM_LAUNCH
   HIPCHECK(hipGetLastError());
   ps.stop();

@@ -302,13 +302,15 @@ def test_fused_pass_with_primes_of_52_bits_bit_exact():
                 assert np.array_equal(e["ctx"].ckks_poly_store(a, lvo, 2), _ct(b)), (m, li, g)
 
 
-@pytest.mark.parametrize("t,family", [(1, 2), (2, 2), (1, 1)])
-def test_second_layer_packed_ciphertexts_share_masks(t, family):
+@pytest.mark.parametrize("t,family,q_bits", [(1, 2, 50), (2, 2, 50), (1, 1, 50), (1, 2, 45), (1, 2, 52)])
+def test_second_layer_packed_ciphertexts_share_masks(t, family, q_bits):
     """Seven output columns packed t per ciphertext: at t = 1 the seven packed ciphertexts
     share their masks (the baby-step/giant-step inner sums read each mask word once for
     four, then three, of them); at t = 2 the last one holds a single column, so its masks
-    differ and the general sum runs.  Words equal the oracle's in both forms."""
-    e = _setup("tiny2", "inter", family, t=t)
+    differ and the general sum runs.  Words equal the oracle's in both forms.  The shared
+    sums take fp64 residues for primes in (2^49, 2^50), split 25-bit products below 2^49
+    (45-bit primes) and 128-bit sums above 2^50 (52-bit primes)."""
+    e = _setup("tiny2", "inter", family, t=t, params=dict(q_bits=q_bits) if q_bits != 50 else None)
     _load_operands(e)
     assert e["p"].ficgcn_plan_info()[1]["n_out_cts"] == -(-7 // t)
     for m in (0, 1):
