@@ -461,17 +461,81 @@ __global__ void k_keymac_masked(const uint64_t* __restrict__ D, const KSJob* __r
 // limb) reads each key word once for its run and adds every job's product, times its
 // plaintext, to its group's sum.  The runs are split in n_seg segments (blockIdx.z) whose sums
 // go to P[seg][group][component] and are added to the accumulators by k_masked_combine.
+// Limbs of Q primes in (2^49, 2^50) (fq): the products in fp64 residues (fpmod.h), each an
+// exact signed representative in (-q, q); a job's digit sum is brought back before its mask
+// product, and the group sums every four jobs, so every double stays an exact integer below
+// 2^53.  The words equal those of the integer form, which the special primes' limbs take.
 constexpr int KM_MAXG = 4;
 template <int ND, int NG>
 __global__ void k_keymac_masked_runs(const uint64_t* __restrict__ D, const KSJob* __restrict__ jobs,
                                      const int* __restrict__ run_start, int n_runs, int n_seg,
                                      const int* __restrict__ job_gl, int n_gl, uint64_t* __restrict__ P, int ext,
-                                     int l1, int L, int n_mod, int log_n, const Mod* __restrict__ mods) {
+                                     int l1, int L, int n_mod, int log_n, int fq, const Mod* __restrict__ mods) {
   const size_t N = (size_t)1 << log_n;
   const uint32_t j = blockIdx.x * KB + threadIdx.x;
   const int i = blockIdx.y, seg = blockIdx.z;
   const int m = i < l1 ? i : i - l1 + L;
   const Mod md = mods[m];
+  const int ra = (int)((int64_t)n_runs * seg / n_seg), rb = (int)((int64_t)n_runs * (seg + 1) / n_seg);
+  if (fq && i < l1) {
+    const double qd = (double)md.q, qinv = 1.0 / qd;
+    auto cv = [](uint64_t v) { return b2f(to_fbits(v)); };
+    double T0[NG], T1[NG];
+    int cnt[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      T0[g] = T1[g] = 0.0;
+      cnt[g] = 0;
+    }
+    for (int run = ra; run < rb; ++run) {
+      const int r0 = run_start[run], r1 = run_start[run + 1];
+      const KSJob j0 = jobs[r0];
+      const uint32_t jj = j0.g == 1 ? j : auto_idx(j, j0.g, log_n);
+      double k0[ND], k1[ND];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        k0[d] = cv(gld(j0.key + (((size_t)d * 2 + 0) * n_mod + m) * N + j));
+        k1[d] = cv(gld(j0.key + (((size_t)d * 2 + 1) * n_mod + m) * N + j));
+      }
+      for (int r = r0; r < r1; ++r) {
+        const KSJob jb = jobs[r];
+        const uint64_t* Du = D + (size_t)jb.src * ND * ext * N;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          const double x = cv(Du[((size_t)d * ext + i) * N + jj]);
+          s0 += fmulmod_s(x, k0[d], qd, qinv);
+          s1 += fmulmod_s(x, k1[d], qd, qinv);
+        }
+        s0 = sred(s0, qd, qinv);
+        s1 = sred(s1, qd, qinv);
+        if (jb.pt) {   // one job per thread block step: no divergence
+          const double p = cv(gld(jb.pt + (size_t)i * N + j));
+          s0 = fmulmod_s(s0, p, qd, qinv);
+          s1 = fmulmod_s(s1, p, qd, qinv);
+        }
+        const int gl = job_gl[r];
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+          if (g == gl) {
+            T0[g] += s0;
+            T1[g] += s1;
+            if (++cnt[g] == 4) {
+              T0[g] = sred(T0[g], qd, qinv);
+              T1[g] = sred(T1[g], qd, qinv);
+              cnt[g] = 0;
+            }
+          }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+      if (g < n_gl) {
+        P[((((size_t)seg * n_gl + g) * 2 + 0) * ext + i) * N + j] = from_fbits(f2b(canon(sred(T0[g], qd, qinv), qd)));
+        P[((((size_t)seg * n_gl + g) * 2 + 1) * ext + i) * N + j] = from_fbits(f2b(canon(sred(T1[g], qd, qinv), qd)));
+      }
+    return;
+  }
   u128 t0[NG], t1[NG];
   uint64_t v0[NG], v1[NG];
   int cnt[NG];
@@ -481,7 +545,6 @@ __global__ void k_keymac_masked_runs(const uint64_t* __restrict__ D, const KSJob
     v0[g] = v1[g] = 0;
     cnt[g] = 0;
   }
-  const int ra = (int)((int64_t)n_runs * seg / n_seg), rb = (int)((int64_t)n_runs * (seg + 1) / n_seg);
   for (int run = ra; run < rb; ++run) {
     const int r0 = run_start[run], r1 = run_start[run + 1];
     const KSJob j0 = jobs[r0];
@@ -690,9 +753,11 @@ void keyswitch_masked_sum(ckks_ctx* c, int level, const std::vector<const uint64
         const int* gld_ = upload(c, S_KM_GL, kgl);
         uint64_t* P = (uint64_t*)dev_scratch(c, S_KM_P, (size_t)n_seg * ng * 2 * ext * N * 8);
         const dim3 grid(n_jb, ext, n_seg);
+        int fq = 1;   // the Q limbs in fp64 residues when every Q prime of the level lies in (2^49, 2^50)
+        for (int qi = 0; qi < l1; ++qi) fq = fq && c->mod[qi] > (1ull << 49) && c->mod[qi] < (1ull << 50);
 #define KM_LAUNCH(NDV, NGV)                                                                                \
   hipLaunchKernelGGL((k_keymac_masked_runs<NDV, NGV>), grid, dim3(KB), 0, c->stream, D, jd, rd, n_runs, n_seg, gld_, \
-                     ng, P, ext, l1, c->L, c->n_mod(), c->log_n, c->t.mods)
+                     ng, P, ext, l1, c->L, c->n_mod(), c->log_n, fq, c->t.mods)
 #define KM_BY_G(NDV)             \
   switch (ng) {                  \
     case 1: KM_LAUNCH(NDV, 1); break; \
@@ -1064,7 +1129,7 @@ void group_mac(ckks_ctx* c, int level, const std::vector<std::vector<MacTerm>>& 
 // 32 x 32 + 64 multiply-add (every partial below 2^51, so GM_MAX_TERMS terms fit), and the
 // group's sum is assembled to 128 bits and reduced once at the end.  Otherwise (AR = 0,
 // wider primes) products are summed in 128 bits and reduced every four terms.
-constexpr int GM_TB = 128;
+constexpr int GM_TB = 256;
 constexpr int GM_MAX_TERMS = 8191;   // 64-bit partial sums: 8191 * 2^51 < 2^64
 
 template <int NP, int AR>
