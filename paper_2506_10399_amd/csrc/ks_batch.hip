@@ -1129,7 +1129,7 @@ void group_mac(ckks_ctx* c, int level, const std::vector<std::vector<MacTerm>>& 
 // 32 x 32 + 64 multiply-add (every partial below 2^51, so GM_MAX_TERMS terms fit), and the
 // group's sum is assembled to 128 bits and reduced once at the end.  Otherwise (AR = 0,
 // wider primes) products are summed in 128 bits and reduced every four terms.
-constexpr int GM_TB = 256;
+constexpr int GM_TB = 128;
 constexpr int GM_MAX_TERMS = 8191;   // 64-bit partial sums: 8191 * 2^51 < 2^64
 
 template <int NP, int AR>
