@@ -35,16 +35,31 @@ __device__ __forceinline__ bool skip_limb(int limb, int poly, int skip_alpha, in
   return skip_alpha > 0 && limb < skip_q && limb / skip_alpha == poly % ((skip_q + skip_alpha - 1) / skip_alpha);
 }
 
-// forward CT butterfly / inverse GS butterfly on residues in [0, q)
+// Integer butterflies with lazy reduction (Harvey's, for q < 2^62): inside a forward
+// transform the values lie in [0, 4q), inside an inverse one in [0, 2q).  Shoup's
+// product without its correction lands in [0, 2q) for any 64-bit input, so
+//   forward CT: x <- x mod 2q (one conditional subtract), t = y w in [0, 2q),
+//               (x, y) <- (x + t, x - t + 2q), both in [0, 4q);
+//   inverse GS: (x, y) <- (x + y reduced to [0, 2q), (x - y + 2q) w in [0, 2q)).
+// The forward transform's last pass and the inverse's scaling by 1/N return [0, q).
 __device__ __forceinline__ void bf_fwd(uint64_t& x, uint64_t& y, uint64_t w, uint64_t ws, uint64_t q) {
-  uint64_t v = mul_shoup(y, w, ws, q);
-  y = sub_mod(x, v, q);
-  x = add_mod(x, v, q);
+  const uint64_t q2 = 2 * q;
+  const uint64_t a = x >= q2 ? x - q2 : x;
+  const uint64_t t = mul_shoup_lazy(y, w, ws, q);
+  x = a + t;
+  y = a - t + q2;
 }
 __device__ __forceinline__ void bf_inv(uint64_t& x, uint64_t& y, uint64_t w, uint64_t ws, uint64_t q) {
-  uint64_t d = sub_mod(x, y, q);
-  x = add_mod(x, y, q);
-  y = mul_shoup(d, w, ws, q);
+  const uint64_t q2 = 2 * q;
+  const uint64_t s = x + y;
+  const uint64_t d = x - y + q2;
+  x = s >= q2 ? s - q2 : s;
+  y = mul_shoup_lazy(d, w, ws, q);
+}
+// [0, 4q) -> [0, q)
+__device__ __forceinline__ uint64_t canon4(uint64_t x, uint64_t q) {
+  x = x >= 2 * q ? x - 2 * q : x;
+  return x >= q ? x - q : x;
 }
 
 
@@ -168,6 +183,10 @@ __device__ __forceinline__ void ntt_pass_body(uint64_t* s, uint64_t* a, const ui
     if (FP && ROW) {
 #pragma unroll
       for (int v = 0; v < EPT; ++v) x[v] = from_fbits(f2b(canon(b2f(x[v]), qd)));
+    }
+    if (!FP && ROW) {
+#pragma unroll
+      for (int v = 0; v < EPT; ++v) x[v] = canon4(x[v], q);
     }
     if (ROW) {
       // back to the strided layout for a coalesced store
