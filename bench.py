@@ -605,6 +605,8 @@ def main():
     ap.add_argument("--requests", type=int, default=50)
     ap.add_argument("--whole-inputs", action="store_true",
                     help="serving: clients send whole ciphertexts instead of seeded ones")
+    ap.add_argument("--no-pack", action="store_true",
+                    help="serving: seeded inputs as 64-bit words instead of packed at the primes' width")
     ap.add_argument("--keyswitch", action="store_true",
                     help="instead: key switching alone at the citation-graph parameters (hoisted rotations of one "
                          "ciphertext, rotations of distinct ciphertexts, relinearisations)")
@@ -712,8 +714,8 @@ def serving_bench(args):
     range's largest corner, 20000 nodes x 1433 features, plus log-uniform draws, a draw
     skipped when its whole ciphertexts would take the pool beyond 128 GB of host memory)
     is encrypted once, as seeded ciphertexts unless args.whole_inputs (the client then
-    uploads first polynomials only; the server rebuilds the uniform parts from the public
-    seed); each rate point streams args.requests requests drawn uniformly from the pool,
+    uploads first polynomials only, packed at the primes' bit length unless args.no_pack;
+    the server unpacks them and rebuilds the uniform parts from the public seed); each rate point streams args.requests requests drawn uniformly from the pool,
     each with its own plan object.  The server (3 slots, 220 GB budget counting keys,
     plan tables, arenas and scratch) first takes every request at once (its saturated
     throughput), then Poisson streams at 50% and 90% of that rate."""
@@ -731,13 +733,16 @@ def serving_bench(args):
     cl, ev = sv.client_keys(ctx, pool, 88)
     log("client keys generated (%.1f s)" % (time.perf_counter() - t0))
     seeded = not args.whole_inputs
+    # seeded first polynomials packed at the widest Q prime's bit length
+    pack = 0 if (args.no_pack or not seeded) else max(m.bit_length() for m in ctx.ckks_ctx_moduli()[:params["n_q"]])
     for i, q in enumerate(pool):
         # seeded: each client's public seed (apart from its error seed 2000 + i and the key seed)
-        sv.encrypt_inputs(ctx, cl, q, 2000 + i, a_seed=(900000 + i) if seeded else None)
+        sv.encrypt_inputs(ctx, cl, q, 2000 + i, a_seed=(900000 + i) if seeded else None, packed_bits=pack)
         log("encrypted %s (%.1f s)" % (q.name, time.perf_counter() - t0))
     in_gb = sum(q.inputs_host.numel() * 8 for q in pool) / 1e9
+    form = ("seeded, packed at %d bits" % pack if pack else "seeded") if seeded else "whole"
     log("serving setup %.1f s: pool %s, %.1f GB of client uploads (%s ciphertexts)"
-        % (time.perf_counter() - t0, [q.name for q in pool], in_gb, "seeded" if seeded else "whole"))
+        % (time.perf_counter() - t0, [q.name for q in pool], in_gb, form))
     runs = []
     budget = 220 * 10 ** 9
     n_slots = 3
@@ -782,7 +787,9 @@ def serving_bench(args):
                            "included), hidden 16, 2-10 classes, CKKS N=2^16 8+2 primes"
                            % (args.requests, len(pool)),
                            slots=n_slots, budget_bytes=budget, planner="learned",
-                           inputs="seeded (first polynomials + public seed)" if seeded else "whole ciphertexts",
+                           inputs=("seeded (first polynomials + public seed)%s" % (", packed at %d bits per residue"
+                                                                                      % pack if pack else ""))
+                           if seeded else "whole ciphertexts",
                            client_upload_gb=round(in_gb, 1)),
                runs=runs, max_rel_err=err,
                pool=[dict(name=q.name, n_in=len(q.inputs_host), level_in=q.info[0]["level_in"],

@@ -174,6 +174,21 @@ ficgcn_status ckks_encrypt_seeded(ckks_ctx* ctx, const ckks_keys* client_keys, c
  * on the context's stream. */
 ficgcn_status ckks_expand_seeded(ckks_ctx* ctx, uint64_t a_seed, uint32_t ct_id0, size_t count, uint32_t level,
                                  uint64_t* cts_dev);
+/* [either side] Transport form of residues (the RNS words of Sec. 2.1's
+ * ciphertexts, no operation of the paper): n_limbs limbs of N residues below
+ * 2^bits (in_dev, contiguous, device) become n_limbs * N * bits / 64 words
+ * (out_dev, device, caller-owned): residue r of a limb holds bits r*bits ..
+ * r*bits+bits-1 of the limb's little-endian bit stream; higher bits of a
+ * residue are dropped.  With bits = the widest prime's bit length a
+ * ciphertext's words shrink by that fraction of 64 (a 50-bit chain: 22%).
+ * EINVAL for bits outside 1..64 or more than 65535 limbs; asynchronous on the
+ * context's stream. */
+ficgcn_status ckks_pack_residues(ckks_ctx* ctx, const uint64_t* in_dev, size_t n_limbs, uint32_t bits,
+                                 uint64_t* out_dev);
+/* [either side] The inverse of ckks_pack_residues: n_limbs packed limbs of
+ * N * bits / 64 words (in_dev) to n_limbs limbs of N residues (out_dev). */
+ficgcn_status ckks_unpack_residues(ckks_ctx* ctx, const uint64_t* in_dev, size_t n_limbs, uint32_t bits,
+                                   uint64_t* out_dev);
 /* [client] Decryption and decoding (Sec. 2.1, Sec. 2.4): n_slots slots
  * (im may be NULL) at `scale` into host arrays.  Synchronous. */
 ficgcn_status ckks_decrypt(ckks_ctx* ctx, const ckks_keys* client_keys, const uint64_t* ct_dev, uint32_t level,
@@ -596,6 +611,10 @@ typedef struct {
                                       device from (a_seed, a_id0 + i), as ckks_expand_seeded does */
   uint32_t a_id0;
   uint64_t a_seed;
+  uint32_t packed_bits;            /* seeded inputs only: 0 = first polynomials as words; else each input's
+                                      first polynomial packed at packed_bits per residue
+                                      (ckks_pack_residues), [n_in][(level_in+1) N packed_bits / 64] words;
+                                      at least the bit length of every prime at level_in (else EINVAL) */
 } ficgcn_request;
 
 typedef struct {

@@ -330,6 +330,32 @@ ficgcn_status ckks_expand_seeded(ckks_ctx* ctx, uint64_t a_seed, uint32_t ct_id0
   });
 }
 
+ficgcn_status ckks_pack_residues(ckks_ctx* ctx, const uint64_t* in_dev, size_t n_limbs, uint32_t bits,
+                                 uint64_t* out_dev) {
+  return guard([&] {
+    REQUIRE(ctx, EINVAL_, "null context");
+    REQUIRE(bits >= 1 && bits <= 64, EINVAL_, "bits per residue must lie in 1..64");
+    REQUIRE(n_limbs <= 65535, EINVAL_, "at most 65535 limbs per call");
+    if (n_limbs == 0) return;
+    REQUIRE(in_dev && out_dev, EINVAL_, "null argument");
+    ensure_device(ctx);
+    pack_residues(ctx, in_dev, 0, out_dev, 0, (int)n_limbs, 1, (int)bits, false);
+  });
+}
+
+ficgcn_status ckks_unpack_residues(ckks_ctx* ctx, const uint64_t* in_dev, size_t n_limbs, uint32_t bits,
+                                   uint64_t* out_dev) {
+  return guard([&] {
+    REQUIRE(ctx, EINVAL_, "null context");
+    REQUIRE(bits >= 1 && bits <= 64, EINVAL_, "bits per residue must lie in 1..64");
+    REQUIRE(n_limbs <= 65535, EINVAL_, "at most 65535 limbs per call");
+    if (n_limbs == 0) return;
+    REQUIRE(in_dev && out_dev, EINVAL_, "null argument");
+    ensure_device(ctx);
+    pack_residues(ctx, in_dev, 0, out_dev, 0, (int)n_limbs, 1, (int)bits, true);
+  });
+}
+
 ficgcn_status ckks_decrypt(ckks_ctx* ctx, const ckks_keys* client_keys, const uint64_t* ct_dev, uint32_t level,
                            double scale, double* re, double* im, size_t n_slots) {
   return guard([&] {

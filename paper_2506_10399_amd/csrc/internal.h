@@ -224,6 +224,11 @@ void encrypt_sym(ckks_ctx* c, const uint64_t* s_ntt, const uint64_t* m_ntt, int 
 // from the stream (4, ct_id0 + z, prime) of a_seed), written in evaluation form;
 // the first polynomials are not touched
 void expand_seeded(ckks_ctx* c, uint64_t a_seed, uint32_t ct_id0, size_t count, int level, uint64_t* cts);
+// residues below 2^bits (1 <= bits <= 64) to and from a bit stream of N * bits / 64 words per
+// limb: count polynomials of n_limbs limbs, polynomial z at in + z * in_stride and
+// out + z * out_stride (words); unpack = false packs
+void pack_residues(ckks_ctx* c, const uint64_t* in, size_t in_stride, uint64_t* out, size_t out_stride,
+                   int n_limbs, size_t count, int bits, bool unpack);
 void ew_mul(ckks_ctx* c, uint64_t* out, const uint64_t* a, const uint64_t* b, int n_limbs, LimbMap map);
 void decrypt_core(ckks_ctx* c, const uint64_t* ct, const uint64_t* s_ntt, int level, uint64_t* m);
 

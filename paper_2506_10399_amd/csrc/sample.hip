@@ -87,6 +87,66 @@ void expand_seeded(ckks_ctx* c, uint64_t a_seed, uint32_t ct_id0, size_t count, 
   }
 }
 
+// ---- bit-packed residues (transport of client words) ----
+// A limb of N residues below 2^bits travels as N * bits / 64 words: residue r of the
+// limb holds bits r * bits .. r * bits + bits - 1 of the limb's little-endian bit stream.
+// count polynomials of n_limbs limbs: polynomial z's limbs at in + z * in_stride
+// (resp. out + z * out_stride), limbs N (packed: N * bits / 64) words apart.
+
+// one thread per packed word: the residues that overlap it, shifted into place
+__global__ void k_pack(const uint64_t* __restrict__ in, size_t in_stride, uint64_t* __restrict__ out,
+                       size_t out_stride, int bits, int log_n) {
+  const size_t N = (size_t)1 << log_n;
+  const size_t wpl = (N * (size_t)bits) >> 6;
+  const size_t w = blockIdx.x * (size_t)SB + threadIdx.x;
+  if (w >= wpl) return;
+  const uint64_t* src = in + blockIdx.z * in_stride + (size_t)blockIdx.y * N;
+  const uint64_t mask = bits == 64 ? ~0ull : (1ull << bits) - 1;
+  const size_t b0 = w * 64;
+  uint64_t v = 0;
+  for (size_t r = b0 / bits; r < N && r * bits < b0 + 64; ++r) {
+    const uint64_t x = src[r] & mask;
+    const long long off = (long long)(r * bits) - (long long)b0;   // in (-bits, 64)
+    v |= off >= 0 ? x << off : x >> (-off);
+  }
+  out[blockIdx.z * out_stride + (size_t)blockIdx.y * wpl + w] = v;
+}
+
+// one thread per residue: one or two packed words
+__global__ void k_unpack(const uint64_t* __restrict__ in, size_t in_stride, uint64_t* __restrict__ out,
+                         size_t out_stride, int bits, int log_n) {
+  const size_t N = (size_t)1 << log_n;
+  const size_t wpl = (N * (size_t)bits) >> 6;
+  const size_t r = blockIdx.x * (size_t)SB + threadIdx.x;
+  if (r >= N) return;
+  const uint64_t* src = in + blockIdx.z * in_stride + (size_t)blockIdx.y * wpl;
+  const size_t b = r * bits, w = b >> 6;
+  const int sh = (int)(b & 63);
+  uint64_t v = src[w] >> sh;
+  if (sh + bits > 64) v |= src[w + 1] << (64 - sh);   // the residue's last bit lies in the limb
+  const uint64_t mask = bits == 64 ? ~0ull : (1ull << bits) - 1;
+  out[blockIdx.z * out_stride + (size_t)blockIdx.y * N + r] = v & mask;
+}
+
+void pack_residues(ckks_ctx* c, const uint64_t* in, size_t in_stride, uint64_t* out, size_t out_stride,
+                   int n_limbs, size_t count, int bits, bool unpack) {
+  const size_t N = c->N;
+  const size_t wpl = (N * (size_t)bits) >> 6;
+  const size_t units = unpack ? N : wpl;
+  const int nb = (int)((units + SB - 1) / SB);
+  constexpr size_t CHUNK = 4096;   // polynomials per launch (grid z)
+  for (size_t z0 = 0; z0 < count; z0 += CHUNK) {
+    const size_t nz = std::min(CHUNK, count - z0);
+    if (unpack)
+      hipLaunchKernelGGL(k_unpack, dim3(nb, n_limbs, (uint32_t)nz), dim3(SB), 0, c->stream, in + z0 * in_stride,
+                         in_stride, out + z0 * out_stride, out_stride, bits, c->log_n);
+    else
+      hipLaunchKernelGGL(k_pack, dim3(nb, n_limbs, (uint32_t)nz), dim3(SB), 0, c->stream, in + z0 * in_stride,
+                         in_stride, out + z0 * out_stride, out_stride, bits, c->log_n);
+    HIPCHECK(hipGetLastError());
+  }
+}
+
 // one thread = one block = 8 coefficients, written as residues of every limb
 __global__ void k_small(uint64_t* __restrict__ out, uint64_t seed, uint32_t kind, uint32_t a, uint32_t b, int dist,
                         int n_limbs, LimbMap map, int log_n, const Mod* __restrict__ mods) {

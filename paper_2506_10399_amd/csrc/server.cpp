@@ -279,8 +279,18 @@ static void run_request(ficgcn_server* s, Slot& sl, Req& q) {
     if (q.r.seeded) {   // first polynomials from the client, the uniform parts rebuilt from their seed
       const size_t half = in_ct / 2;
       const uint8_t* src = (const uint8_t*)q.r.inputs_host;
-      for (size_t i = 0; i < q.r.n_in; ++i)
-        HIPCHECK(hipMemcpyAsync(din + i * in_ct, src + i * half, half, hipMemcpyHostToDevice, c->stream));
+      if (q.r.packed_bits) {
+        // packed first polynomials land in each input's second half (rebuilt next), then unpack
+        const int l1 = l0.level_in + 1;
+        const size_t pk = (size_t)l1 * ((c->N * (size_t)q.r.packed_bits) >> 6) * 8;
+        for (size_t i = 0; i < q.r.n_in; ++i)
+          HIPCHECK(hipMemcpyAsync(din + i * in_ct + half, src + i * pk, pk, hipMemcpyHostToDevice, c->stream));
+        pack_residues(c, (const uint64_t*)(din + half), in_ct / 8, (uint64_t*)din, in_ct / 8, l1, q.r.n_in,
+                      (int)q.r.packed_bits, true);
+      } else {
+        for (size_t i = 0; i < q.r.n_in; ++i)
+          HIPCHECK(hipMemcpyAsync(din + i * in_ct, src + i * half, half, hipMemcpyHostToDevice, c->stream));
+      }
       expand_seeded(c, q.r.a_seed, q.r.a_id0, q.r.n_in, l0.level_in, (uint64_t*)din);
     } else {
       HIPCHECK(hipMemcpyAsync(din, q.r.inputs_host, q.r.n_in * in_ct, hipMemcpyHostToDevice, c->stream));
@@ -425,6 +435,11 @@ ficgcn_status ficgcn_server_submit(ficgcn_server* server, const ficgcn_request* 
   if ((int)req->n_out != p->layers.back().n_packed()) FICGCN_THROW(EPLAN_, "wrong number of output ciphertexts");
   if (req->seeded && req->n_in > 0 && req->n_in - 1 > (size_t)(UINT32_MAX - req->a_id0))
     FICGCN_THROW(EINVAL_, "seeded input ids beyond 32 bits");
+  if (req->packed_bits) {
+    if (!req->seeded || req->packed_bits > 64) FICGCN_THROW(EINVAL_, "packed inputs must be seeded, at most 64 bits");
+    for (int i = 0; i <= p->layers[0].level_in; ++i)
+      if (req->packed_bits < 64 && (pc->mod[i] >> req->packed_bits)) FICGCN_THROW(EINVAL_, "packed width below a prime's bit length");
+  }
   if (req->eval_keys->ctx && req->eval_keys->ctx->N != sc->N) FICGCN_THROW(EINVAL_, "keys of other parameters");
   Req q;
   q.r = *req;

@@ -57,7 +57,8 @@ N_FEATURES = 24
 class Request(ctypes.Structure):
     _fields_ = [("plan", c_vp), ("eval_keys", c_vp), ("inputs_host", c_vp), ("n_in", ctypes.c_size_t),
                 ("output_host", c_vp), ("n_out", ctypes.c_size_t), ("operands_host", c_vp),
-                ("seeded", ctypes.c_uint32), ("a_id0", ctypes.c_uint32), ("a_seed", ctypes.c_uint64)]
+                ("seeded", ctypes.c_uint32), ("a_id0", ctypes.c_uint32), ("a_seed", ctypes.c_uint64),
+                ("packed_bits", ctypes.c_uint32)]
 
 
 class RequestResult(ctypes.Structure):
@@ -102,6 +103,8 @@ _SIGS = {
                                            ctypes.c_uint32, c_vp]),
     "ckks_expand_seeded": (ctypes.c_int, [c_vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_size_t, ctypes.c_uint32,
                                           c_vp]),
+    "ckks_pack_residues": (ctypes.c_int, [c_vp, c_vp, ctypes.c_size_t, ctypes.c_uint32, c_vp]),
+    "ckks_unpack_residues": (ctypes.c_int, [c_vp, c_vp, ctypes.c_size_t, ctypes.c_uint32, c_vp]),
     "ckks_decrypt": (ctypes.c_int, [c_vp, c_vp, c_vp, ctypes.c_uint32, ctypes.c_double, c_vp, c_vp,
                                     ctypes.c_size_t]),
     "ckks_ct_load": (ctypes.c_int, [c_vp, c_vp, ctypes.c_uint32, c_vp]),
@@ -343,6 +346,21 @@ class Context:
         """cts: device buffer [count][2][level+1][N]; rewrites every second polynomial."""
         _check(lib().ckks_expand_seeded(self.h, a_seed, ct_id0, count, level, _ptr(cts)))
         return cts
+
+    def ckks_pack_residues(self, src, n_limbs: int, bits: int, out=None):
+        """src: device words, n_limbs limbs of N residues -> n_limbs * N * bits / 64 packed words."""
+        import torch
+        if out is None:
+            out = torch.empty(n_limbs * self.N * bits // 64, dtype=torch.int64, device="cuda")
+        _check(lib().ckks_pack_residues(self.h, _ptr(src), n_limbs, bits, _ptr(out)))
+        return out
+
+    def ckks_unpack_residues(self, src, n_limbs: int, bits: int, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(n_limbs * self.N, dtype=torch.int64, device="cuda")
+        _check(lib().ckks_unpack_residues(self.h, _ptr(src), n_limbs, bits, _ptr(out)))
+        return out
 
     def ckks_decrypt(self, client_keys: "Keys", ct, level: int, scale: float, n_slots: int) -> np.ndarray:
         re = np.zeros(n_slots, dtype=np.float64)
@@ -719,18 +737,20 @@ class Server:
         self.close()
 
     def ficgcn_server_submit(self, plan: "Plan", eval_keys: "Keys", inputs_host, n_in: int, output_host,
-                             n_out: int, operands_host=None, a_seed=None, a_id0: int = 0) -> int:
+                             n_out: int, operands_host=None, a_seed=None, a_id0: int = 0,
+                             packed_bits: int = 0) -> int:
         """operands_host: None (the slot encodes the plan's operands) or, per layer, a uint64 array
         of every operand's coefficient-form residues in operand order, concatenated.
         a_seed: None (inputs_host holds whole ciphertexts) or the public seed of seeded inputs
-        (inputs_host holds their first polynomials; input i has id a_id0 + i)."""
+        (inputs_host holds their first polynomials; input i has id a_id0 + i); packed_bits: those
+        first polynomials packed at that many bits per residue (ckks_pack_residues)."""
         ops = None
         if operands_host is not None:
             operands_host = [np.ascontiguousarray(a, dtype=np.uint64) for a in operands_host]
             ops = _ptr_array(operands_host)
         r = Request(plan.h, eval_keys.h, _ptr(inputs_host), n_in, _ptr(output_host), n_out,
                     ctypes.cast(ops, c_vp) if ops is not None else None,
-                    0 if a_seed is None else 1, a_id0, 0 if a_seed is None else a_seed)
+                    0 if a_seed is None else 1, a_id0, 0 if a_seed is None else a_seed, packed_bits)
         rid = ctypes.c_uint64()
         _check(lib().ficgcn_server_submit(self.h, ctypes.byref(r), ctypes.byref(rid)))
         # alive until waited for

@@ -34,6 +34,7 @@ class ClientRequest:
     inputs_host: object = None      # pinned torch tensor [n_in][2][L][N], or [n_in][L][N] when seeded
     output_host: object = None      # numpy [n_out][2][l_out+1][N]
     a_seed: Optional[int] = None    # public seed of seeded inputs (input i has ciphertext id i)
+    packed_bits: int = 0            # seeded inputs' first polynomials packed at this many bits per residue
     result: dict = field(default_factory=dict)
 
 
@@ -133,6 +134,7 @@ def replicate(ctx: fg.Context, pool: Sequence[ClientRequest], n_req: int, seed: 
         c.info = q.info
         c.inputs_host = q.inputs_host
         c.a_seed = q.a_seed
+        c.packed_bits = q.packed_bits
         c.output_host = np.zeros_like(q.output_host)
         out.append(c)
     return out
@@ -147,13 +149,14 @@ def client_keys(ctx: fg.Context, reqs: Sequence[ClientRequest], seed: int):
 
 
 def encrypt_inputs(ctx: fg.Context, cl: fg.Keys, q: ClientRequest, seed: int, a_seed: Optional[int] = None,
-                   whole: bool = False):
+                   whole: bool = False, packed_bits: int = 0):
     """The client's Inter-CA copies (copy k of column f at k*F + f, slots in
     the plan's node order), encrypted on the device, parked in pinned host
     memory; and a host buffer for the returned ciphertexts.  With a_seed the
     copies are seeded ciphertexts (uniform parts from the public a_seed, copy i
     with id i) and only their first polynomials are parked, half the upload,
-    unless `whole` asks for both polynomials."""
+    unless `whole` asks for both polynomials; packed_bits (seeded only) packs
+    those residues at that many bits each (the widest prime's bit length)."""
     import torch
     pi = q.plan.ficgcn_plan_node_order()
     src = q.plan.ficgcn_plan_copy_sources(0)
@@ -162,12 +165,14 @@ def encrypt_inputs(ctx: fg.Context, cl: fg.Keys, q: ClientRequest, seed: int, a_
     K, F = d0["K"], d0["f_in"]
     N, M = ctx.N, ctx.M
     half = a_seed is not None and not whole
-    shape = (K * F, lv + 1, N) if half else (K * F, 2, lv + 1, N)
+    pk = packed_bits if half else 0
+    shape = ((K * F, (lv + 1) * N * pk // 64) if pk else (K * F, lv + 1, N)) if half else (K * F, 2, lv + 1, N)
     try:
         host = torch.empty(shape, dtype=torch.int64, pin_memory=True)
     except RuntimeError:   # page-locked memory exhausted: a pageable buffer (the upload then blocks the slot)
         host = torch.empty(shape, dtype=torch.int64)
     dev = torch.empty((min(256, F), 2, lv + 1, N), dtype=torch.int64, device="cuda")
+    packed = torch.empty((min(256, F),) + shape[1:], dtype=torch.int64, device="cuda") if pk else None
     for k in range(K):
         have = src[k] >= 0
         for f0 in range(0, F, dev.shape[0]):
@@ -180,10 +185,14 @@ def encrypt_inputs(ctx: fg.Context, cl: fg.Keys, q: ClientRequest, seed: int, a_
                     ctx.ckks_encrypt(cl, pts[i], lv, seed, k * F + f0 + i, out=dev[i])
                 else:
                     ctx.ckks_encrypt_seeded(cl, pts[i], lv, seed, a_seed, k * F + f0 + i, out=dev[i])
+            if pk:
+                for i in range(nf):
+                    ctx.ckks_pack_residues(dev[i, 0], lv + 1, pk, out=packed[i])
             torch.cuda.synchronize()
-            host[k * F + f0:k * F + f0 + nf].copy_(dev[:nf, 0] if half else dev[:nf])
+            host[k * F + f0:k * F + f0 + nf].copy_(packed[:nf] if pk else dev[:nf, 0] if half else dev[:nf])
     q.inputs_host = host
     q.a_seed = a_seed if half else None
+    q.packed_bits = pk
     q.output_host = np.zeros((dl["n_out_cts"], 2, dl["level_out"] + 1, N), dtype=np.uint64)
 
 
@@ -214,7 +223,7 @@ def run_stream(server: fg.Server, reqs: Sequence[ClientRequest], ev: fg.Keys, ra
         if dt > 0:
             time.sleep(dt)
         ids.append(server.ficgcn_server_submit(q.plan, ev, q.inputs_host, len(q.inputs_host), q.output_host,
-                                               len(q.output_host), a_seed=q.a_seed))
+                                               len(q.output_host), a_seed=q.a_seed, packed_bits=q.packed_bits))
     for q, i in zip(reqs, ids):
         q.result = server.ficgcn_server_wait(i)
     return server.ficgcn_server_stats()

@@ -128,6 +128,35 @@ def test_seeded_encryption_and_rebuild_match_oracle(env):
     assert ei.value.status == -2
 
 
+@pytest.mark.parametrize("bits", [50, 60, 64, 13])
+def test_packed_residues_layout_and_round_trip(env, bits):
+    """Residues packed at `bits` each form the limb's little-endian bit stream (checked
+    against Python integers), and unpacking restores them; higher bits are dropped."""
+    import torch
+    if env["name"] != "tiny":
+        pytest.skip("layout checked at the tiny ring degree")
+    ctx, N = env["ctx"], env["prm"].N
+    n_limbs = 3
+    rng = np.random.default_rng(bits)
+    hi = (1 << bits) if bits < 64 else (1 << 64)
+    x = np.stack([rng.integers(0, hi, N, dtype=np.uint64) if bits < 64 else
+                  rng.integers(0, 1 << 63, N, dtype=np.uint64) * np.uint64(2) + np.uint64(1) for _ in range(n_limbs)])
+    if bits < 64:
+        x[:, 5] |= np.uint64(1) << np.uint64(bits)     # a bit above the width: dropped
+    dev = torch.from_numpy(x.view(np.int64)).to("cuda")
+    packed = ctx.ckks_pack_residues(dev, n_limbs, bits)
+    got = packed.cpu().numpy().view(np.uint64).reshape(n_limbs, N * bits // 64)
+    mask = (1 << bits) - 1
+    for li in range(n_limbs):
+        stream = 0
+        for r in range(N):
+            stream |= (int(x[li, r]) & mask) << (r * bits)
+        want = [(stream >> (64 * w)) & ((1 << 64) - 1) for w in range(N * bits // 64)]
+        assert [int(v) for v in got[li]] == want, li
+    back = ctx.ckks_unpack_residues(packed, n_limbs, bits).cpu().numpy().view(np.uint64).reshape(n_limbs, N)
+    assert np.array_equal(back, x & np.uint64(mask) if bits < 64 else x)
+
+
 def test_rotate_hoisted_matches_oracle(env):
     prm, ctx = env["prm"], env["ctx"]
     for lv in (prm.L - 1, 2):

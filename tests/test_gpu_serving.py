@@ -174,7 +174,8 @@ def test_poisson_stream_reports_latency(env):
 def test_seeded_inputs_return_the_words_of_whole_inputs(env):
     """A request sent as seeded ciphertexts (each input's first polynomial and a
     public seed; the server rebuilds the uniform parts) returns the words of the
-    same ciphertexts sent whole, beside an unseeded request; the upload is half."""
+    same ciphertexts sent whole, beside an unseeded request; the upload is half,
+    and with the first polynomials packed at the primes' bit length smaller still."""
     import dataclasses
     fg, sv, ctx = env["fg"], env["sv"], env["ctx"]
     base = env["reqs"][1]
@@ -185,10 +186,19 @@ def test_seeded_inputs_return_the_words_of_whole_inputs(env):
     assert seeded.a_seed == 0xABCDEF and whole.a_seed is None
     assert seeded.inputs_host.numel() * 2 == whole.inputs_host.numel()
     assert bool((seeded.inputs_host == whole.inputs_host[:, 0]).all())
+    packed = dataclasses.replace(base, result={})
+    bits = max(m.bit_length() for m in ctx.ckks_ctx_moduli()[:PARAMS["n_q"]])
+    sv.encrypt_inputs(ctx, env["cl"], packed, 4001, a_seed=0xABCDEF, packed_bits=bits)
+    assert packed.packed_bits == bits and packed.inputs_host.numel() * 64 == seeded.inputs_host.numel() * bits
     other = dataclasses.replace(env["reqs"][0], result={}, output_host=np.zeros_like(env["reqs"][0].output_host))
     srv = fg.Server(PARAMS, 2, 1 << 40)
-    st = sv.run_stream(srv, [seeded, other, whole], env["ev"], 0.0, 9)
-    srv.close()
-    assert st["completed"] == 3 and st["failed"] == 0
+    st = sv.run_stream(srv, [seeded, other, whole, packed], env["ev"], 0.0, 9)
+    assert st["completed"] == 4 and st["failed"] == 0
     assert np.array_equal(seeded.output_host, whole.output_host)
+    assert np.array_equal(packed.output_host, whole.output_host)
     assert sv.decrypt_error(ctx, env["cl"], seeded) < 1e-3
+    # a packed width below a prime's bit length is refused at submission
+    with pytest.raises(fg.FicgcnError):
+        srv.ficgcn_server_submit(packed.plan, env["ev"], packed.inputs_host, len(packed.inputs_host),
+                                 packed.output_host, len(packed.output_host), a_seed=0xABCDEF, packed_bits=bits - 1)
+    srv.close()

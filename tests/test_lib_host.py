@@ -407,6 +407,10 @@ def test_operand_descriptors_checked_before_any_device_work(fg):
     assert status(ctx.ckks_expand_seeded, 1, 2 ** 32 - 2, 3, 0, fake) == -1
     assert status(ctx.ckks_expand_seeded, 1, 0, 1, 4, fake) == -2
     assert status(ctx.ckks_encrypt_seeded, fg.Keys(ctx, None), fake, 0, 1, 2, 0, fake) == -1
+    # packed residues: widths outside 1..64, too many limbs
+    assert status(ctx.ckks_pack_residues, fake, 3, 0, fake) == -1
+    assert status(ctx.ckks_unpack_residues, fake, 3, 65, fake) == -1
+    assert status(ctx.ckks_pack_residues, fake, 70000, 50, fake) == -1
 
 
 def test_search_rejects_plans_whose_keys_exceed_the_limit(fg):
