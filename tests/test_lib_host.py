@@ -42,6 +42,36 @@ def test_header_symbols_exported(fg):
     assert sorted(fg.exported_symbols()) == names
 
 
+def test_binding_structs_match_the_header_layout(fg, tmp_path):
+    """Every struct the binding mirrors has the header's size and each field's offset and
+    width (a C program built with gcc from include/ficgcn.h prints them)."""
+    import ctypes
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    pairs = [("ckks_params", fg.CkksParams), ("ficgcn_plan_opts", fg.PlanOpts), ("ckks_operand", fg.Operand),
+             ("ficgcn_search_stats", fg.SearchStats), ("ficgcn_request", fg.Request),
+             ("ficgcn_request_result", fg.RequestResult), ("ficgcn_server_summary", fg.ServerSummary)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ficgcn.h"', 'int main(void) {']
+    for cname, py in pairs:
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('  printf("%s %s %%zu %%zu\\n", offsetof(%s, %s), sizeof(((%s*)0)->%s));'
+                         % (cname, f, cname, f, cname, f))
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): [int(v) for v in l.split()[2:]] for l in out if l}
+    for cname, py in pairs:
+        assert got[(cname, "size")] == [ctypes.sizeof(py)], cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == [getattr(py, f).offset, getattr(py, f).size], (cname, f)
+
+
 @pytest.mark.parametrize("name", ["tiny", "tiny2", "cora", "pubmed"])
 def test_prime_chain_matches_oracle(fg, name):
     w = make_workload(name, n_nodes=16, dims=[2, 2])
